@@ -1,0 +1,192 @@
+"""FP64 CPU oracle of the fine-level DNN-MG step -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product path (the HIP library and its binding)
+never calls it.  numpy wrappers over the plain C implementation in
+dnnmg_oracle.c; every array is float64 and C-contiguous.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_U8 = ctypes.POINTER(ctypes.c_uint8)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        # DNNMG_ORACLE_LIB lets the mutation test load a deliberately broken
+        # build of this same source, to show that the pins catch it.
+        path = os.environ.get("DNNMG_ORACLE_LIB") or _build.build(force=False)
+        L = ctypes.CDLL(path)
+        i, d, u = ctypes.c_int, ctypes.c_double, ctypes.c_uint
+        L.orc_fine_coords.argtypes = [i, i, i, _D, _D]
+        L.orc_prolong.argtypes = [i, i, i, i, _D, _D]
+        L.orc_restrict.argtypes = [i, i, i, i, _D, _D]
+        L.orc_dirichlet_mask.argtypes = [i, i, i, u, _U8]
+        L.orc_defect.argtypes = [i, i, i, _D, _D, _D, _D, d, d, u, _D]
+        L.orc_mass_apply.argtypes = [i, i, i, _D, _D, _D]
+        L.orc_features.argtypes = [i, i, _D, _D]
+        L.orc_gather_input.argtypes = [i, i, i, _D, _D, _D, _D]
+        L.orc_gru.argtypes = [i, i, i, _D, _D, _D, _D, _D, _D, _D, _D, _D]
+        L.orc_mlp.argtypes = [i, i, i, i, _D, _D, _D, _D]
+        L.orc_average.argtypes = [i, i, i, _D, u, _D]
+        L.orc_rhs_restrict.argtypes = [i, i, i, _D, _D, _D, d, _D]
+        L.orc_step.argtypes = [i, i, i, i, i, d, d, u, _D, _D, _D, _D, _D, _D, i,
+                               _D, _D, _D, _D, _D, _D]
+        L.orc_step.restype = i
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous, (a.dtype, a.flags)
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def sizes(nx, ny, K):
+    n = 1 << K
+    return dict(n=n, nf=(n + 1) ** 2, Fn=(nx * n + 1) * (ny * n + 1),
+                Nc=(nx + 1) * (ny + 1), P=nx * ny, nin=4 * (n + 1) ** 2 + 4,
+                nout=2 * (n + 1) ** 2)
+
+
+def fine_coords(nx, ny, K, cxy):
+    s = sizes(nx, ny, K)
+    out = np.empty((s["Fn"], 2))
+    lib().orc_fine_coords(nx, ny, K, _p(_f64(cxy)), _p(out))
+    return out
+
+
+def prolong(nx, ny, K, coarse):
+    c = _f64(coarse)
+    ncomp = 1 if c.ndim == 1 else c.shape[-1]
+    s = sizes(nx, ny, K)
+    out = np.empty((s["Fn"], ncomp) if ncomp > 1 else (s["Fn"],))
+    lib().orc_prolong(nx, ny, K, ncomp, _p(c), _p(out))
+    return out
+
+
+def restrict(nx, ny, K, fine):
+    f = _f64(fine)
+    ncomp = 1 if f.ndim == 1 else f.shape[-1]
+    s = sizes(nx, ny, K)
+    out = np.empty((s["Nc"], ncomp) if ncomp > 1 else (s["Nc"],))
+    lib().orc_restrict(nx, ny, K, ncomp, _p(f), _p(out))
+    return out
+
+
+def dirichlet_mask(nx, ny, K, dirichlet):
+    s = sizes(nx, ny, K)
+    m = np.empty(s["Fn"], dtype=np.uint8)
+    lib().orc_dirichlet_mask(nx, ny, K, dirichlet, m.ctypes.data_as(_U8))
+    return m.astype(bool)
+
+
+def defect(nx, ny, K, cxy, pv, pp, uprev, dt, nu, dirichlet):
+    s = sizes(nx, ny, K)
+    D = np.empty((s["Fn"], 2))
+    lib().orc_defect(nx, ny, K, _p(_f64(cxy)), _p(_f64(pv)), _p(_f64(pp)), _p(_f64(uprev)),
+                     dt, nu, dirichlet, _p(D))
+    return D
+
+
+def mass_apply(nx, ny, K, cxy, u):
+    s = sizes(nx, ny, K)
+    out = np.empty((s["Fn"], 2))
+    lib().orc_mass_apply(nx, ny, K, _p(_f64(cxy)), _p(_f64(u)), _p(out))
+    return out
+
+
+def features(nx, ny, cxy):
+    out = np.empty((nx * ny, 4))
+    lib().orc_features(nx, ny, _p(_f64(cxy)), _p(out))
+    return out
+
+
+def gather_input(nx, ny, K, pv, D, feat):
+    s = sizes(nx, ny, K)
+    X = np.empty((s["P"], s["nin"]))
+    lib().orc_gather_input(nx, ny, K, _p(_f64(pv)), _p(_f64(D)), _p(_f64(feat)), _p(X))
+    return X
+
+
+def gru(X, h, Wz, Wr, Wh, Uz, Ur, Uh):
+    X, h = _f64(X), _f64(h)
+    P, nin = X.shape
+    H = h.shape[1]
+    out = np.empty((P, H))
+    lib().orc_gru(P, nin, H, *[_p(_f64(w)) for w in (Wz, Wr, Wh, Uz, Ur, Uh)],
+                  _p(X), _p(h), _p(out))
+    return out
+
+
+def mlp(h, M1, M2=None):
+    h = _f64(h)
+    P, H = h.shape
+    if M2 is None:
+        Hm, nout = 0, M1.shape[0]
+        m2 = None
+    else:
+        Hm, nout = M1.shape[0], M2.shape[0]
+        m2 = _f64(M2)
+    out = np.empty((P, nout))
+    lib().orc_mlp(P, H, Hm, nout, _p(_f64(M1)), _p(m2), _p(h), _p(out))
+    return out
+
+
+def average(nx, ny, K, dpatch, dirichlet):
+    s = sizes(nx, ny, K)
+    out = np.empty((s["Fn"], 2))
+    lib().orc_average(nx, ny, K, _p(_f64(dpatch)), dirichlet, _p(out))
+    return out
+
+
+def rhs_restrict(nx, ny, K, cxy, v, Dbar, dt):
+    s = sizes(nx, ny, K)
+    out = np.empty((s["Nc"], 2))
+    lib().orc_rhs_restrict(nx, ny, K, _p(_f64(cxy)), _p(_f64(v)), _p(_f64(Dbar)), dt, _p(out))
+    return out
+
+
+class OracleFlow:
+    """Stateful wrapper: h (P x H) and u_prev (Fn x 2) in float64."""
+
+    def __init__(self, nx, ny, K, H, Hm, dt, nu, dirichlet, cxy, weights):
+        self.nx, self.ny, self.K, self.H, self.Hm = nx, ny, K, H, Hm
+        self.dt, self.nu, self.dirichlet = dt, nu, dirichlet
+        self.cxy = _f64(cxy).reshape(-1, 2)
+        self.w = _f64(weights).reshape(-1)
+        s = sizes(nx, ny, K)
+        self.s = s
+        self.h = np.zeros((s["P"], H))
+        self.uprev = np.zeros((s["Fn"], 2))
+        self.nsteps = 0
+
+    def step(self, v, p, want=("Dbar", "bL")):
+        s = self.s
+        outs = {k: None for k in ("Pv", "D", "X", "dpatch", "Dbar", "bL")}
+        shapes = dict(Pv=(s["Fn"], 2), D=(s["Fn"], 2), X=(s["P"], s["nin"]),
+                      dpatch=(s["P"], s["nout"]), Dbar=(s["Fn"], 2), bL=(s["Nc"], 2))
+        for k in want:
+            outs[k] = np.empty(shapes[k])
+        rc = lib().orc_step(self.nx, self.ny, self.K, self.H, self.Hm, self.dt, self.nu,
+                            self.dirichlet, _p(self.cxy), _p(self.w),
+                            _p(_f64(v).reshape(-1, 2)), _p(_f64(p).reshape(-1)),
+                            _p(self.h), _p(self.uprev), 1 if self.nsteps == 0 else 0,
+                            *[_p(outs[k]) for k in ("Pv", "D", "X", "dpatch", "Dbar", "bL")])
+        if rc != 0:
+            raise MemoryError("oracle step failed: %d" % rc)
+        self.nsteps += 1
+        return {k: outs[k] for k in want}

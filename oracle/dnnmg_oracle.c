@@ -1,0 +1,503 @@
+/*
+ * FP64 CPU oracle of the fine-level DNN-MG step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant with the GPU library; both are fed from the
+ * seeded input generators.
+ *
+ * What it computes: one step of Algorithm 2 (lines 6-9) of the paper --
+ * prolongation of the coarse velocity, the fine Navier-Stokes defect, the
+ * per-patch GRU + MLP correction, duplicate averaging, the fine right-hand
+ * side and its restriction -- in the implicit-Euler, Q1/Q1 form used by the
+ * workloads (readings documented in the design notes: implicit Euler instead
+ * of Crank-Nicolson, Q1 instead of Q2, momentum rows only, no biases,
+ * reset gate applied before U_h as printed in Eq. (gru)).
+ *
+ * Everything is plain loops in double precision, in the order the
+ * definitions state; no blocking, fusion or reordering.
+ *
+ * Indexing (structured meshes):
+ *   coarse node (i,j), 0<=i<=nx, 0<=j<=ny : index j*(nx+1)+i
+ *   coarse element / patch (i,j)           : index j*nx+i
+ *   n = 2^K; fine node (I,J), 0<=I<=nx*n   : index J*(nx*n+1)+I
+ *   patch-local node (a,b), 0<=a,b<=n      : l = b*(n+1)+a  <-> fine (i*n+a, j*n+b)
+ * Vector fields are interleaved (x, y) per node.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- helpers */
+
+static int coarse_node(int nx, int i, int j) { return j * (nx + 1) + i; }
+static int fine_node(int nx, int n, int I, int J) { return J * (nx * n + 1) + I; }
+
+/* Bilinear shape functions on [0,1]^2 in the corner order 00, 10, 01, 11. */
+static void q1_shape(double s, double t, double N[4])
+{
+    N[0] = (1.0 - s) * (1.0 - t);
+    N[1] = s * (1.0 - t);
+    N[2] = (1.0 - s) * t;
+    N[3] = s * t;
+}
+
+static void q1_shape_ds(double s, double t, double dNs[4], double dNt[4])
+{
+    (void)s;
+    dNs[0] = -(1.0 - t); dNs[1] = (1.0 - t); dNs[2] = -t; dNs[3] = t;
+    dNt[0] = -(1.0 - s); dNt[1] = -s;        dNt[2] = (1.0 - s); dNt[3] = s;
+}
+
+/* The coarse element that holds fine node I along one axis, and the local
+ * offset a in [0, n] inside it.  Nodes on an element edge belong to both
+ * neighbours; the left/lower one is taken, except at the last node. */
+static void owner(int I, int n, int ne, int *e, int *a)
+{
+    int i = I / n;
+    if (i >= ne) i = ne - 1;
+    *e = i;
+    *a = I - i * n;
+}
+
+/* 2-point Gauss rule on [0,1] (exact for cubics). */
+static void gauss2(double g[2])
+{
+    double d = 0.5 / sqrt(3.0);
+    g[0] = 0.5 - d;
+    g[1] = 0.5 + d;
+}
+
+/* -------------------------------------------------- step 1: fine geometry */
+/* Fine node (i*n+a, j*n+b) sits at F_e(a/n, b/n), the bilinear
+ * (isoparametric) map of coarse element e; K uniform refinements of the
+ * coarse mesh (Sec. 3.4, nested mesh hierarchy). */
+void orc_fine_coords(int nx, int ny, int K, const double *cxy, double *fxy)
+{
+    int n = 1 << K;
+    for (int J = 0; J <= ny * n; ++J)
+        for (int I = 0; I <= nx * n; ++I) {
+            int i, a, j, b;
+            owner(I, n, nx, &i, &a);
+            owner(J, n, ny, &j, &b);
+            double N[4];
+            q1_shape((double)a / n, (double)b / n, N);
+            int c[4] = {coarse_node(nx, i, j), coarse_node(nx, i + 1, j),
+                        coarse_node(nx, i, j + 1), coarse_node(nx, i + 1, j + 1)};
+            int f = fine_node(nx, n, I, J);
+            for (int d = 0; d < 2; ++d) {
+                double x = 0.0;
+                for (int k = 0; k < 4; ++k) x += N[k] * cxy[2 * c[k] + d];
+                fxy[2 * f + d] = x;
+            }
+        }
+}
+
+/* ---------------------------------------------------- step 2: prolongation */
+/* P: interpolation of the coarse Q1 function at the fine nodes (Alg. 2,
+ * line 6; grid transfer of Sec. 3.4).  ncomp values per node. */
+void orc_prolong(int nx, int ny, int K, int ncomp, const double *coarse, double *fine)
+{
+    int n = 1 << K;
+    for (int J = 0; J <= ny * n; ++J)
+        for (int I = 0; I <= nx * n; ++I) {
+            int i, a, j, b;
+            owner(I, n, nx, &i, &a);
+            owner(J, n, ny, &j, &b);
+            double N[4];
+            q1_shape((double)a / n, (double)b / n, N);
+            int c[4] = {coarse_node(nx, i, j), coarse_node(nx, i + 1, j),
+                        coarse_node(nx, i, j + 1), coarse_node(nx, i + 1, j + 1)};
+            int f = fine_node(nx, n, I, J);
+            for (int d = 0; d < ncomp; ++d) {
+                double x = 0.0;
+                for (int k = 0; k < 4; ++k) x += N[k] * coarse[ncomp * c[k] + d];
+                fine[ncomp * f + d] = x;
+            }
+        }
+}
+
+/* --------------------------------------------------- step 10: restriction */
+/* R = P^T: the transpose of the prolongation above, applied to a dual
+ * (right-hand-side) vector (Alg. 2, line 9). */
+void orc_restrict(int nx, int ny, int K, int ncomp, const double *fine, double *coarse)
+{
+    int n = 1 << K;
+    memset(coarse, 0, sizeof(double) * (size_t)ncomp * (nx + 1) * (ny + 1));
+    for (int J = 0; J <= ny * n; ++J)
+        for (int I = 0; I <= nx * n; ++I) {
+            int i, a, j, b;
+            owner(I, n, nx, &i, &a);
+            owner(J, n, ny, &j, &b);
+            double N[4];
+            q1_shape((double)a / n, (double)b / n, N);
+            int c[4] = {coarse_node(nx, i, j), coarse_node(nx, i + 1, j),
+                        coarse_node(nx, i, j + 1), coarse_node(nx, i + 1, j + 1)};
+            int f = fine_node(nx, n, I, J);
+            for (int d = 0; d < ncomp; ++d)
+                for (int k = 0; k < 4; ++k) coarse[ncomp * c[k] + d] += N[k] * fine[ncomp * f + d];
+        }
+}
+
+/* ---------------------------------------------------------- Dirichlet mask */
+/* bit0 x=xmin, bit1 x=xmax, bit2 y=ymin, bit3 y=ymax (Eq. boundary: v=v^D
+ * on Gamma^D; the do-nothing sides are natural and left free). */
+void orc_dirichlet_mask(int nx, int ny, int K, unsigned dir, unsigned char *mask)
+{
+    int n = 1 << K, NX = nx * n, NY = ny * n;
+    for (int J = 0; J <= NY; ++J)
+        for (int I = 0; I <= NX; ++I) {
+            int m = ((dir & 1u) && I == 0) || ((dir & 2u) && I == NX) ||
+                    ((dir & 4u) && J == 0) || ((dir & 8u) && J == NY);
+            mask[fine_node(nx, n, I, J)] = (unsigned char)m;
+        }
+}
+
+/* ------------------------------------------------------ step 3: the defect */
+/* D = f - A(Pv, Pp): the momentum rows of the nonlinear residual of
+ * Eq. (nonlinearshort) for the prolongated coarse solution, with implicit
+ * Euler in place of Crank-Nicolson:
+ *   D_a,c = (1/dt)(u_prev - v, phi) - (v.grad v_c, phi) - nu (grad v_c, grad phi)
+ *           + (p, d_c phi)
+ * assembled element by element over the fine mesh with 2x2 Gauss points on
+ * each fine element's own bilinear map, then zeroed at Dirichlet nodes.
+ * v, p, u_prev are fine nodal values (2, 1, 2 per node). */
+void orc_defect(int nx, int ny, int K, const double *cxy, const double *v, const double *p,
+                const double *uprev, double dt, double nu, unsigned dir, double *D)
+{
+    int n = 1 << K, NX = nx * n, NY = ny * n;
+    size_t Fn = (size_t)(NX + 1) * (NY + 1);
+    double *fxy = (double *)malloc(sizeof(double) * 2 * Fn);
+    unsigned char *mask = (unsigned char *)malloc(Fn);
+    orc_fine_coords(nx, ny, K, cxy, fxy);
+    orc_dirichlet_mask(nx, ny, K, dir, mask);
+    memset(D, 0, sizeof(double) * 2 * Fn);
+    double g[2];
+    gauss2(g);
+    for (int J = 0; J < NY; ++J)
+        for (int I = 0; I < NX; ++I) {
+            int node[4] = {fine_node(nx, n, I, J), fine_node(nx, n, I + 1, J),
+                           fine_node(nx, n, I, J + 1), fine_node(nx, n, I + 1, J + 1)};
+            for (int qt = 0; qt < 2; ++qt)
+                for (int qs = 0; qs < 2; ++qs) {
+                    double s = g[qs], t = g[qt], w = 0.25;
+                    double N[4], dNs[4], dNt[4];
+                    q1_shape(s, t, N);
+                    q1_shape_ds(s, t, dNs, dNt);
+                    /* Jacobian of the element map x(s,t). */
+                    double xs = 0, xt = 0, ys = 0, yt = 0;
+                    for (int k = 0; k < 4; ++k) {
+                        xs += fxy[2 * node[k]] * dNs[k];
+                        xt += fxy[2 * node[k]] * dNt[k];
+                        ys += fxy[2 * node[k] + 1] * dNs[k];
+                        yt += fxy[2 * node[k] + 1] * dNt[k];
+                    }
+                    double det = xs * yt - xt * ys;
+                    /* Physical gradients: grad N = J^{-T} (dN/ds, dN/dt). */
+                    double dNx[4], dNy[4];
+                    for (int k = 0; k < 4; ++k) {
+                        dNx[k] = (yt * dNs[k] - ys * dNt[k]) / det;
+                        dNy[k] = (-xt * dNs[k] + xs * dNt[k]) / det;
+                    }
+                    double vq[2] = {0, 0}, uq[2] = {0, 0}, pq = 0;
+                    double gv[2][2] = {{0, 0}, {0, 0}}; /* gv[c][k] = d v_c / d x_k */
+                    for (int k = 0; k < 4; ++k) {
+                        for (int c = 0; c < 2; ++c) {
+                            vq[c] += N[k] * v[2 * node[k] + c];
+                            uq[c] += N[k] * uprev[2 * node[k] + c];
+                            gv[c][0] += v[2 * node[k] + c] * dNx[k];
+                            gv[c][1] += v[2 * node[k] + c] * dNy[k];
+                        }
+                        pq += N[k] * p[node[k]];
+                    }
+                    double conv[2];
+                    for (int c = 0; c < 2; ++c) conv[c] = vq[0] * gv[c][0] + vq[1] * gv[c][1];
+                    double wd = w * fabs(det);
+                    for (int a = 0; a < 4; ++a)
+                        for (int c = 0; c < 2; ++c) {
+                            double dphi_c = (c == 0) ? dNx[a] : dNy[a];
+                            double r = (1.0 / dt) * N[a] * (uq[c] - vq[c])
+                                     - N[a] * conv[c]
+                                     - nu * (dNx[a] * gv[c][0] + dNy[a] * gv[c][1])
+                                     + pq * dphi_c;
+                            D[2 * node[a] + c] += wd * r;
+                        }
+                }
+        }
+    for (size_t f = 0; f < Fn; ++f)
+        if (mask[f]) { D[2 * f] = 0.0; D[2 * f + 1] = 0.0; }
+    free(fxy);
+    free(mask);
+}
+
+/* ---------------------------------------------------- step 9: mass matrix */
+/* Mu = M_f u, the consistent fine-level mass matrix (same element loop and
+ * quadrature as the defect) applied to a 2-component nodal field. */
+void orc_mass_apply(int nx, int ny, int K, const double *cxy, const double *u, double *Mu)
+{
+    int n = 1 << K, NX = nx * n, NY = ny * n;
+    size_t Fn = (size_t)(NX + 1) * (NY + 1);
+    double *fxy = (double *)malloc(sizeof(double) * 2 * Fn);
+    orc_fine_coords(nx, ny, K, cxy, fxy);
+    memset(Mu, 0, sizeof(double) * 2 * Fn);
+    double g[2];
+    gauss2(g);
+    for (int J = 0; J < NY; ++J)
+        for (int I = 0; I < NX; ++I) {
+            int node[4] = {fine_node(nx, n, I, J), fine_node(nx, n, I + 1, J),
+                           fine_node(nx, n, I, J + 1), fine_node(nx, n, I + 1, J + 1)};
+            for (int qt = 0; qt < 2; ++qt)
+                for (int qs = 0; qs < 2; ++qs) {
+                    double s = g[qs], t = g[qt], w = 0.25;
+                    double N[4], dNs[4], dNt[4];
+                    q1_shape(s, t, N);
+                    q1_shape_ds(s, t, dNs, dNt);
+                    double xs = 0, xt = 0, ys = 0, yt = 0;
+                    for (int k = 0; k < 4; ++k) {
+                        xs += fxy[2 * node[k]] * dNs[k];
+                        xt += fxy[2 * node[k]] * dNt[k];
+                        ys += fxy[2 * node[k] + 1] * dNs[k];
+                        yt += fxy[2 * node[k] + 1] * dNt[k];
+                    }
+                    double wd = w * fabs(xs * yt - xt * ys);
+                    double uq[2] = {0, 0};
+                    for (int k = 0; k < 4; ++k)
+                        for (int c = 0; c < 2; ++c) uq[c] += N[k] * u[2 * node[k] + c];
+                    for (int a = 0; a < 4; ++a)
+                        for (int c = 0; c < 2; ++c) Mu[2 * node[a] + c] += wd * N[a] * uq[c];
+                }
+        }
+    free(fxy);
+}
+
+/* ------------------------------------------------ step 4: patch features */
+/* Geometry inputs per patch (Sec. 4.2 uses edge lengths, aspect ratios and
+ * angles; the workloads use hx, hy, aspect = hx/hy and the exact area). */
+void orc_features(int nx, int ny, const double *cxy, double *feat)
+{
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const double *c00 = cxy + 2 * coarse_node(nx, i, j);
+            const double *c10 = cxy + 2 * coarse_node(nx, i + 1, j);
+            const double *c01 = cxy + 2 * coarse_node(nx, i, j + 1);
+            const double *c11 = cxy + 2 * coarse_node(nx, i + 1, j + 1);
+            double hx = 0.5 * (hypot(c10[0] - c00[0], c10[1] - c00[1]) +
+                               hypot(c11[0] - c01[0], c11[1] - c01[1]));
+            double hy = 0.5 * (hypot(c01[0] - c00[0], c01[1] - c00[1]) +
+                               hypot(c11[0] - c10[0], c11[1] - c10[1]));
+            double d1x = c11[0] - c00[0], d1y = c11[1] - c00[1];
+            double d2x = c01[0] - c10[0], d2y = c01[1] - c10[1];
+            double area = 0.5 * fabs(d1x * d2y - d1y * d2x);
+            double *f = feat + 4 * (size_t)(j * nx + i);
+            f[0] = hx; f[1] = hy; f[2] = hx / hy; f[3] = area;
+        }
+}
+
+/* ------------------------------------------------ step 5: network inputs */
+/* x_e = [Pv at the patch nodes (x,y interleaved, patch-local lexicographic
+ * order, x fastest); D at the same nodes; hx, hy, aspect, area]. */
+void orc_gather_input(int nx, int ny, int K, const double *pv, const double *D,
+                      const double *feat, double *X)
+{
+    int n = 1 << K, nf = (n + 1) * (n + 1), nin = 4 * nf + 4;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t e = (size_t)j * nx + i;
+            double *x = X + e * nin;
+            for (int b = 0; b <= n; ++b)
+                for (int a = 0; a <= n; ++a) {
+                    int l = b * (n + 1) + a;
+                    int f = fine_node(nx, n, i * n + a, j * n + b);
+                    x[2 * l] = pv[2 * f];
+                    x[2 * l + 1] = pv[2 * f + 1];
+                    x[2 * nf + 2 * l] = D[2 * f];
+                    x[2 * nf + 2 * l + 1] = D[2 * f + 1];
+                }
+            for (int k = 0; k < 4; ++k) x[4 * nf + k] = feat[4 * e + k];
+        }
+}
+
+/* ---------------------------------------------------------- step 6: GRU */
+/* Eq. (gru) with no biases:
+ *   z = sigma(W_z x + U_z h), r = sigma(W_r x + U_r h),
+ *   h' = z*h + (1-z)*tanh(W_h x + U_h (r*h)),
+ * sigma the logistic function.  W: H x nin each, U: H x H each. */
+static double logistic(double t) { return 1.0 / (1.0 + exp(-t)); }
+
+void orc_gru(int P, int nin, int H, const double *Wz, const double *Wr, const double *Wh,
+             const double *Uz, const double *Ur, const double *Uh,
+             const double *X, const double *h, double *hout)
+{
+    double *z = (double *)malloc(sizeof(double) * H);
+    double *rh = (double *)malloc(sizeof(double) * H);
+    for (int e = 0; e < P; ++e) {
+        const double *x = X + (size_t)e * nin;
+        const double *he = h + (size_t)e * H;
+        for (int k = 0; k < H; ++k) {
+            double az = 0.0, ar = 0.0;
+            for (int i = 0; i < nin; ++i) {
+                az += Wz[(size_t)k * nin + i] * x[i];
+                ar += Wr[(size_t)k * nin + i] * x[i];
+            }
+            for (int m = 0; m < H; ++m) {
+                az += Uz[(size_t)k * H + m] * he[m];
+                ar += Ur[(size_t)k * H + m] * he[m];
+            }
+            z[k] = logistic(az);
+            rh[k] = logistic(ar) * he[k];
+        }
+        for (int k = 0; k < H; ++k) {
+            double ah = 0.0;
+            for (int i = 0; i < nin; ++i) ah += Wh[(size_t)k * nin + i] * x[i];
+            for (int m = 0; m < H; ++m) ah += Uh[(size_t)k * H + m] * rh[m];
+            hout[(size_t)e * H + k] = z[k] * he[k] + (1.0 - z[k]) * tanh(ah);
+        }
+    }
+    free(z);
+    free(rh);
+}
+
+/* ---------------------------------------------------------- step 7: MLP */
+/* d = M2 max(0, M1 h) (Hm > 0) or d = M h (Hm == 0); no biases. */
+void orc_mlp(int P, int H, int Hm, int nout, const double *M1, const double *M2,
+             const double *h, double *d)
+{
+    double *a = (double *)malloc(sizeof(double) * (Hm > 0 ? Hm : 1));
+    for (int e = 0; e < P; ++e) {
+        const double *he = h + (size_t)e * H;
+        double *de = d + (size_t)e * nout;
+        if (Hm > 0) {
+            for (int k = 0; k < Hm; ++k) {
+                double s = 0.0;
+                for (int m = 0; m < H; ++m) s += M1[(size_t)k * H + m] * he[m];
+                a[k] = s > 0.0 ? s : 0.0;
+            }
+            for (int o = 0; o < nout; ++o) {
+                double s = 0.0;
+                for (int k = 0; k < Hm; ++k) s += M2[(size_t)o * Hm + k] * a[k];
+                de[o] = s;
+            }
+        } else {
+            for (int o = 0; o < nout; ++o) {
+                double s = 0.0;
+                for (int m = 0; m < H; ++m) s += M1[(size_t)o * H + m] * he[m];
+                de[o] = s;
+            }
+        }
+    }
+    free(a);
+}
+
+/* ---------------------------------------------------- step 8: averaging */
+/* Duplicate predictions at fine nodes shared by adjacent patches are
+ * averaged (Sec. 4.2, patch-based network); the mean over the 1, 2 or 4
+ * patches that contain the node, then zero at Dirichlet nodes. */
+void orc_average(int nx, int ny, int K, const double *dpatch, unsigned dir, double *Dbar)
+{
+    int n = 1 << K, NX = nx * n, NY = ny * n, nf = (n + 1) * (n + 1);
+    size_t Fn = (size_t)(NX + 1) * (NY + 1);
+    unsigned char *mask = (unsigned char *)malloc(Fn);
+    orc_dirichlet_mask(nx, ny, K, dir, mask);
+    for (int J = 0; J <= NY; ++J)
+        for (int I = 0; I <= NX; ++I) {
+            double s[2] = {0, 0};
+            int cnt = 0;
+            /* only patches J/n-1 and J/n (resp. I/n-1, I/n) can contain the
+             * node; the containment test below decides. */
+            for (int pj = J / n - 1; pj <= J / n; ++pj) {
+                if (pj < 0 || pj >= ny || J < pj * n || J > pj * n + n) continue;
+                for (int pi = I / n - 1; pi <= I / n; ++pi) {
+                    if (pi < 0 || pi >= nx || I < pi * n || I > pi * n + n) continue;
+                    int l = (J - pj * n) * (n + 1) + (I - pi * n);
+                    const double *de = dpatch + ((size_t)pj * nx + pi) * 2 * nf;
+                    s[0] += de[2 * l];
+                    s[1] += de[2 * l + 1];
+                    ++cnt;
+                }
+            }
+            size_t f = (size_t)fine_node(nx, n, I, J);
+            Dbar[2 * f] = mask[f] ? 0.0 : s[0] / cnt;
+            Dbar[2 * f + 1] = mask[f] ? 0.0 : s[1] / cnt;
+        }
+    free(mask);
+}
+
+/* -------------------------------------------- steps 9-10 as one operation */
+/* b_L = R (1/dt) M_f u_corr with u_corr = P v + Dbar (Alg. 2, lines 8-9,
+ * implicit-Euler right-hand side, no body force).  v is the coarse
+ * velocity, Dbar the fine correction. */
+void orc_rhs_restrict(int nx, int ny, int K, const double *cxy, const double *v,
+                      const double *Dbar, double dt, double *bL)
+{
+    int n = 1 << K;
+    size_t Fn = (size_t)(nx * n + 1) * (ny * n + 1);
+    double *u = (double *)malloc(sizeof(double) * 2 * Fn);
+    double *bf = (double *)malloc(sizeof(double) * 2 * Fn);
+    orc_prolong(nx, ny, K, 2, v, u);
+    for (size_t f = 0; f < 2 * Fn; ++f) u[f] += Dbar[f];
+    orc_mass_apply(nx, ny, K, cxy, u, bf);
+    for (size_t f = 0; f < 2 * Fn; ++f) bf[f] *= 1.0 / dt;
+    orc_restrict(nx, ny, K, 2, bf, bL);
+    free(u);
+    free(bf);
+}
+
+/* ---------------------------------------------------------- the full step */
+/* One DNN-MG fine step (Alg. 2, lines 6-9) for given coarse v, p.
+ * weights: W_z, W_r, W_h (H x nin), U_z, U_r, U_h (H x H), then M1 (Hm x H)
+ * and M2 (nout x Hm), or M (nout x H) when Hm == 0.
+ * State in/out: h (P x H), uprev (Fn x 2).  When first != 0 the previous
+ * corrected velocity is taken as P v of this step (no right-hand side from
+ * an earlier step exists yet), so the mass term of the defect vanishes.
+ * Optional outputs (NULL to skip): Pv (Fn x 2), D (Fn x 2), X (P x nin),
+ * dpatch (P x nout), Dbar (Fn x 2), bL ((nx+1)(ny+1) x 2). */
+int orc_step(int nx, int ny, int K, int H, int Hm, double dt, double nu, unsigned dir,
+             const double *cxy, const double *weights, const double *v, const double *p,
+             double *h, double *uprev, int first,
+             double *Pv_out, double *D_out, double *X_out, double *dpatch_out,
+             double *Dbar_out, double *bL_out)
+{
+    int n = 1 << K, nf = (n + 1) * (n + 1), nout = 2 * nf, nin = 4 * nf + 4;
+    int P = nx * ny;
+    size_t Fn = (size_t)(nx * n + 1) * (ny * n + 1);
+    size_t Nc = (size_t)(nx + 1) * (ny + 1);
+    const double *Wz = weights, *Wr = Wz + (size_t)H * nin, *Wh = Wr + (size_t)H * nin;
+    const double *Uz = Wh + (size_t)H * nin, *Ur = Uz + (size_t)H * H, *Uh = Ur + (size_t)H * H;
+    const double *M1 = Uh + (size_t)H * H;
+    const double *M2 = Hm > 0 ? M1 + (size_t)Hm * H : NULL;
+
+    double *Pv = (double *)malloc(sizeof(double) * 2 * Fn);
+    double *Pp = (double *)malloc(sizeof(double) * Fn);
+    double *D = (double *)malloc(sizeof(double) * 2 * Fn);
+    double *feat = (double *)malloc(sizeof(double) * 4 * P);
+    double *X = (double *)malloc(sizeof(double) * (size_t)P * nin);
+    double *hn = (double *)malloc(sizeof(double) * (size_t)P * H);
+    double *dp = (double *)malloc(sizeof(double) * (size_t)P * nout);
+    double *Dbar = (double *)malloc(sizeof(double) * 2 * Fn);
+    double *bL = (double *)malloc(sizeof(double) * 2 * Nc);
+    if (!Pv || !Pp || !D || !feat || !X || !hn || !dp || !Dbar || !bL) return -2;
+
+    orc_prolong(nx, ny, K, 2, v, Pv);
+    orc_prolong(nx, ny, K, 1, p, Pp);
+    if (first) memcpy(uprev, Pv, sizeof(double) * 2 * Fn);
+    orc_defect(nx, ny, K, cxy, Pv, Pp, uprev, dt, nu, dir, D);
+    orc_features(nx, ny, cxy, feat);
+    orc_gather_input(nx, ny, K, Pv, D, feat, X);
+    orc_gru(P, nin, H, Wz, Wr, Wh, Uz, Ur, Uh, X, h, hn);
+    orc_mlp(P, H, Hm, nout, M1, M2, hn, dp);
+    orc_average(nx, ny, K, dp, dir, Dbar);
+    orc_rhs_restrict(nx, ny, K, cxy, v, Dbar, dt, bL);
+
+    /* state update: h <- h', u_prev <- u_corr = P v + Dbar */
+    memcpy(h, hn, sizeof(double) * (size_t)P * H);
+    for (size_t f = 0; f < 2 * Fn; ++f) uprev[f] = Pv[f] + Dbar[f];
+
+    if (Pv_out) memcpy(Pv_out, Pv, sizeof(double) * 2 * Fn);
+    if (D_out) memcpy(D_out, D, sizeof(double) * 2 * Fn);
+    if (X_out) memcpy(X_out, X, sizeof(double) * (size_t)P * nin);
+    if (dpatch_out) memcpy(dpatch_out, dp, sizeof(double) * (size_t)P * nout);
+    if (Dbar_out) memcpy(Dbar_out, Dbar, sizeof(double) * 2 * Fn);
+    if (bL_out) memcpy(bL_out, bL, sizeof(double) * 2 * Nc);
+    free(Pv); free(Pp); free(D); free(feat); free(X); free(hn); free(dp); free(Dbar); free(bL);
+    return 0;
+}

@@ -1,0 +1,316 @@
+"""Seeded synthetic inputs for the fine-level DNN-MG step.
+
+This module only *makes inputs*: coarse meshes, coarse velocity/pressure
+fields, network weights and serving arrivals.  It holds none of the method's
+arithmetic (no prolongation, defect, network or restriction), so both the
+GPU library and the FP64 oracle can be driven from it without sharing code.
+
+Random numbers come from SplitMix64 (Steele, Lea & Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014), written here from its
+published definition: the state advances by the golden-ratio increment and
+each output is the state passed through the two xor-shift-multiply rounds of
+Stafford's "Mix13" finaliser.  Uniform doubles take the top 53 bits.
+
+The paper's own flows (a Schaefer-Turek channel with an elliptic obstacle,
+Sec. 5.1) and its trained weights are not available; the generators below
+stand in for them with the channel's dimensions (2.2 x 0.41) and a parabolic
+inflow, smooth divergence-free Fourier fields, and Xavier-uniform weights.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+class SplitMix64:
+    """Counter-based SplitMix64 stream: output k is mix(seed + k*gamma)."""
+
+    def __init__(self, seed: int):
+        self.state = np.uint64(seed & 0xFFFFFFFFFFFFFFFF)
+
+    def next_u64(self, n: int) -> np.ndarray:
+        with np.errstate(over="ignore"):
+            k = np.arange(1, n + 1, dtype=np.uint64)
+            z = self.state + k * _GAMMA
+            self.state = self.state + np.uint64(n) * _GAMMA
+            z = (z ^ (z >> np.uint64(30))) * _M1
+            z = (z ^ (z >> np.uint64(27))) * _M2
+            z = z ^ (z >> np.uint64(31))
+        return z
+
+    def uniform(self, n: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+        u = (self.next_u64(n) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+        return lo + (hi - lo) * u
+
+    def integers(self, n: int, lo: int, hi: int) -> np.ndarray:
+        """Integers uniform in [lo, hi] (inclusive), by floor of a uniform draw."""
+        u = self.uniform(n)
+        return lo + np.minimum(np.floor(u * (hi - lo + 1)), hi - lo).astype(np.int64)
+
+
+# --------------------------------------------------------------------------
+# Meshes.  Coarse node (i, j) has index j*(nx+1)+i; arrays are (ny+1, nx+1, 2).
+# --------------------------------------------------------------------------
+
+def rect_mesh(nx: int, ny: int, lx: float = 1.0, ly: float = 1.0,
+              x0: float = 0.0, y0: float = 0.0) -> np.ndarray:
+    xs = x0 + lx * np.arange(nx + 1, dtype=np.float64) / nx
+    ys = y0 + ly * np.arange(ny + 1, dtype=np.float64) / ny
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    return np.stack([X, Y], axis=-1)
+
+
+def perturb_interior(cxy: np.ndarray, frac: float, seed: int) -> np.ndarray:
+    """Move every interior coarse node by U[-frac*h, frac*h] in each direction
+    (h = local spacing per direction); boundary nodes stay put."""
+    ny1, nx1, _ = cxy.shape
+    out = cxy.copy()
+    hx = (cxy[0, -1, 0] - cxy[0, 0, 0]) / (nx1 - 1)
+    hy = (cxy[-1, 0, 1] - cxy[0, 0, 1]) / (ny1 - 1)
+    rng = SplitMix64(seed)
+    n_int = max(nx1 - 2, 0) * max(ny1 - 2, 0)
+    d = rng.uniform(2 * n_int, -frac, frac).reshape(max(ny1 - 2, 0), max(nx1 - 2, 0), 2)
+    out[1:-1, 1:-1, 0] += d[..., 0] * hx
+    out[1:-1, 1:-1, 1] += d[..., 1] * hy
+    return out
+
+
+# Dirichlet side flags (bit0 x=xmin, bit1 x=xmax, bit2 y=ymin, bit3 y=ymax).
+DIR_XMIN, DIR_XMAX, DIR_YMIN, DIR_YMAX = 1, 2, 4, 8
+DIR_ALL = 15
+DIR_CHANNEL = DIR_XMIN | DIR_YMIN | DIR_YMAX   # inflow + walls; outflow is do-nothing
+
+
+# --------------------------------------------------------------------------
+# Fields.
+# --------------------------------------------------------------------------
+
+@dataclass
+class FourierField:
+    """Divergence-free velocity from a stream function of `nmodes` modes:
+    psi = sum_m |k_m|^-1 sin(2 pi (kx x/Lx + ky y/Ly) + phi_m + w_m t),
+    v = (d psi/dy, -d psi/dx), scaled so that max |v| over the coarse nodes
+    at t = 0 equals `amplitude`.  A scalar field of `pmodes` modes and
+    amplitude `p_amplitude` stands in for the coarse pressure."""
+    lx: float
+    ly: float
+    seed: int
+    nmodes: int = 8
+    pmodes: int = 4
+    amplitude: float = 1.0
+    p_amplitude: float = 0.1
+    k: np.ndarray = field(init=False)
+    phi: np.ndarray = field(init=False)
+    om: np.ndarray = field(init=False)
+    pk: np.ndarray = field(init=False)
+    pphi: np.ndarray = field(init=False)
+    pom: np.ndarray = field(init=False)
+    vscale: float = field(init=False, default=1.0)
+    pscale: float = field(init=False, default=1.0)
+
+    def __post_init__(self):
+        rng = SplitMix64(self.seed)
+
+        def draw_k(n):
+            ks = []
+            while len(ks) < n:
+                kk = rng.integers(2, -4, 4)
+                if kk[0] != 0 or kk[1] != 0:
+                    ks.append(kk)
+            return np.array(ks, dtype=np.float64)
+
+        self.k = draw_k(self.nmodes)
+        self.phi = rng.uniform(self.nmodes, 0.0, 2 * math.pi)
+        self.om = 2 * math.pi * rng.uniform(self.nmodes, 0.5, 2.0)
+        self.pk = draw_k(self.pmodes)
+        self.pphi = rng.uniform(self.pmodes, 0.0, 2 * math.pi)
+        self.pom = 2 * math.pi * rng.uniform(self.pmodes, 0.5, 2.0)
+
+    def _raw_v(self, x, y, t):
+        vx = np.zeros_like(x)
+        vy = np.zeros_like(x)
+        for m in range(self.nmodes):
+            kx, ky = self.k[m]
+            inv = 1.0 / math.hypot(kx, ky)
+            th = 2 * math.pi * (kx * x / self.lx + ky * y / self.ly) + self.phi[m] + self.om[m] * t
+            c = np.cos(th) * inv * 2 * math.pi
+            vx += c * ky / self.ly
+            vy -= c * kx / self.lx
+        return vx, vy
+
+    def _raw_p(self, x, y, t):
+        p = np.zeros_like(x)
+        for m in range(self.pmodes):
+            kx, ky = self.pk[m]
+            th = 2 * math.pi * (kx * x / self.lx + ky * y / self.ly) + self.pphi[m] + self.pom[m] * t
+            p += np.sin(th)
+        return p
+
+    def calibrate(self, cxy: np.ndarray) -> "FourierField":
+        x, y = cxy[..., 0], cxy[..., 1]
+        vx, vy = self._raw_v(x, y, 0.0)
+        m = float(np.sqrt(vx * vx + vy * vy).max())
+        self.vscale = self.amplitude / m if m > 0 else 1.0
+        pm = float(np.abs(self._raw_p(x, y, 0.0)).max())
+        self.pscale = self.p_amplitude / pm if pm > 0 else 1.0
+        return self
+
+    def velocity(self, cxy, t):
+        vx, vy = self._raw_v(cxy[..., 0], cxy[..., 1], t)
+        return np.stack([vx, vy], axis=-1) * self.vscale
+
+    def pressure(self, cxy, t):
+        return self._raw_p(cxy[..., 0], cxy[..., 1], t) * self.pscale
+
+
+CHANNEL_LX, CHANNEL_LY = 2.2, 0.41
+
+
+def channel_profile(y: np.ndarray, height: float = CHANNEL_LY) -> np.ndarray:
+    return 4.0 * y * (height - y) / (height * height)
+
+
+@dataclass
+class Flow:
+    """One synthetic flow: a coarse mesh plus the coarse fields per time step."""
+    nx: int
+    ny: int
+    cxy: np.ndarray           # (ny+1, nx+1, 2) float64
+    dirichlet: int
+    dt: float
+    fourier: FourierField
+    inflow_max: float = 0.0   # > 0: channel form v = inflow*e_x + fourier*profile
+
+    def fields(self, step: int):
+        """Coarse (v, p) at t_n = n*dt, float32, node-major (Nc, 2) and (Nc,)."""
+        t = step * self.dt
+        v = self.fourier.velocity(self.cxy, t)
+        if self.inflow_max > 0.0:
+            prof = channel_profile(self.cxy[..., 1])
+            v = v * prof[..., None]
+            v[..., 0] += self.inflow_max * prof
+        p = self.fourier.pressure(self.cxy, t)
+        nc = (self.nx + 1) * (self.ny + 1)
+        return (v.reshape(nc, 2).astype(np.float32),
+                p.reshape(nc).astype(np.float32))
+
+
+def unit_square_flow(nx=16, ny=16, field_seed=1, dt=0.01) -> Flow:
+    cxy = rect_mesh(nx, ny)
+    ff = FourierField(1.0, 1.0, field_seed).calibrate(cxy)
+    return Flow(nx, ny, cxy, DIR_ALL, dt, ff)
+
+
+def channel_flow(nx=256, ny=64, field_seed=1, dt=0.005, perturb_seed=None,
+                 perturb_frac=0.1, inflow_max=1.5) -> Flow:
+    cxy = rect_mesh(nx, ny, CHANNEL_LX, CHANNEL_LY)
+    if perturb_seed is not None:
+        cxy = perturb_interior(cxy, perturb_frac, perturb_seed)
+    ff = FourierField(CHANNEL_LX, CHANNEL_LY, field_seed).calibrate(cxy)
+    return Flow(nx, ny, cxy, DIR_CHANNEL, dt, ff, inflow_max=inflow_max)
+
+
+def stretched_flow(nx=128, ny=128, stretch=1.0, field_seed=1, dt=0.01) -> Flow:
+    cxy = rect_mesh(nx, ny, stretch, 1.0)
+    ff = FourierField(stretch, 1.0, field_seed).calibrate(cxy)
+    return Flow(nx, ny, cxy, DIR_ALL, dt, ff)
+
+
+def stretch_factors(nflows: int, seed: int = 5, lo: float = 1.0, hi: float = 8.0):
+    return SplitMix64(seed).uniform(nflows, lo, hi)
+
+
+# --------------------------------------------------------------------------
+# Network weights: W_z, W_r, W_h (H x Nin), U_z, U_r, U_h (H x H), then
+# M1 (Hm x H) and M2 (Nout x Hm), or M (Nout x H); row-major (out x in),
+# no biases.  Xavier-uniform bound sqrt(6 / (fan_in + fan_out)) per matrix.
+# --------------------------------------------------------------------------
+
+def net_shapes(K: int, H: int, Hm: int):
+    n = 1 << K
+    nf = (n + 1) * (n + 1)
+    nout = 2 * nf
+    nin = 2 * nf + 2 * nf + 4
+    shapes = [(H, nin)] * 3 + [(H, H)] * 3
+    shapes += [(Hm, H), (nout, Hm)] if Hm > 0 else [(nout, H)]
+    return nin, nout, shapes
+
+
+def xavier_weights(K: int, H: int, Hm: int, seed: int) -> np.ndarray:
+    _, _, shapes = net_shapes(K, H, Hm)
+    rng = SplitMix64(seed)
+    parts = []
+    for (o, i) in shapes:
+        a = math.sqrt(6.0 / (i + o))
+        parts.append(rng.uniform(o * i, -a, a))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def split_weights(w: np.ndarray, K: int, H: int, Hm: int):
+    """Views of the packed weight vector as the individual matrices."""
+    _, _, shapes = net_shapes(K, H, Hm)
+    out, off = [], 0
+    for (o, i) in shapes:
+        out.append(w[off:off + o * i].reshape(o, i))
+        off += o * i
+    assert off == w.size, (off, w.size)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Named workloads (sizes of the paper-derived configurations).
+# --------------------------------------------------------------------------
+
+@dataclass
+class Workload:
+    name: str
+    K: int
+    H: int
+    Hm: int
+    nu: float
+    steps: int
+    flows: list
+    weight_seed: int = 1234
+
+
+def workload(name: str) -> Workload:
+    if name == "unit16_k1":          # 16x16 unit square, K=1, H=32, linear 32->18
+        return Workload(name, 1, 32, 0, 1e-3, 10, [unit_square_flow(16, 16, 1, 0.01)])
+    if name == "channel256x64_k2":   # 256x64 channel, K=2, H=64, MLP 64->64->50
+        return Workload(name, 2, 64, 64, 1e-3, 100, [channel_flow(256, 64, 1, 0.005)])
+    if name == "channel1024x256_k2_perturbed":
+        return Workload(name, 2, 64, 64, 1e-3, 200,
+                        [channel_flow(1024, 256, 1, 0.005, perturb_seed=7)])
+    if name == "stretched64x128x128_k3":
+        s = stretch_factors(64, 5)
+        return Workload(name, 3, 128, 128, 1e-3, 100,
+                        [stretched_flow(128, 128, float(s[f]), 100 + f, 0.01) for f in range(64)])
+    raise KeyError(name)
+
+
+# --------------------------------------------------------------------------
+# Serving arrivals: Poisson process, mesh sizes and step counts per request.
+# --------------------------------------------------------------------------
+
+SERVE_MESHES = [(32, 8), (64, 16), (128, 32), (256, 64), (512, 128)]
+
+
+def serving_requests(n: int = 256, rate: float = 20.0, seed: int = 11,
+                     steps_lo: int = 50, steps_hi: int = 500):
+    rng = SplitMix64(seed)
+    gaps = -np.log1p(-rng.uniform(n)) / rate
+    arrivals = np.cumsum(gaps)
+    mesh_idx = rng.integers(n, 0, len(SERVE_MESHES) - 1)
+    steps = rng.integers(n, steps_lo, steps_hi)
+    reqs = []
+    for r in range(n):
+        nx, ny = SERVE_MESHES[int(mesh_idx[r])]
+        reqs.append(dict(id=r, arrival=float(arrivals[r]), nx=nx, ny=ny,
+                         steps=int(steps[r]), field_seed=1000 + r))
+    return reqs

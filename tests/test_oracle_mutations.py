@@ -1,0 +1,61 @@
+"""The oracle's pins have teeth: each plausible mistake planted in a copy of
+the oracle source (on the CPU) makes the pin suite fail.
+
+Each mutation is (original text, replacement, which occurrence).  The
+mutated copy is compiled into a temporary library and the pins are run
+against it in a subprocess through DNNMG_ORACLE_LIB.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "dnnmg_oracle.c")
+
+MUTATIONS = {
+    "mass_sign": ("(uq[c] - vq[c])", "(vq[c] - uq[c])", 0),
+    "drop_convection": ("- N[a] * conv[c]", "- 0.0 * conv[c]", 0),
+    "convection_transposed": ("vq[0] * gv[c][0] + vq[1] * gv[c][1]", "vq[0] * gv[0][c] + vq[1] * gv[1][c]", 0),
+    "diffusion_sign": ("- nu * (dNx[a]", "+ nu * (dNx[a]", 0),
+    "pressure_sign": ("+ pq * dphi_c", "- pq * dphi_c", 0),
+    "pressure_component": ("(c == 0) ? dNx[a] : dNy[a]", "(c == 0) ? dNy[a] : dNx[a]", 0),
+    "inverse_jacobian": ("(yt * dNs[k] - ys * dNt[k])", "(yt * dNs[k] - xt * dNt[k])", 0),
+    "gauss_points": ("0.5 / sqrt(3.0)", "0.5 / sqrt(2.0)", 0),
+    "gru_update_swapped": ("z[k] * he[k] + (1.0 - z[k]) * tanh(ah)", "(1.0 - z[k]) * he[k] + z[k] * tanh(ah)", 0),
+    "gru_no_reset": ("ah += Uh[(size_t)k * H + m] * rh[m]", "ah += Uh[(size_t)k * H + m] * he[m]", 0),
+    "gru_U_transposed": ("az += Uz[(size_t)k * H + m] * he[m]", "az += Uz[(size_t)m * H + k] * he[m]", 0),
+    "mlp_no_relu": ("a[k] = s > 0.0 ? s : 0.0;", "a[k] = s;", 0),
+    "prolong_axes_swapped": ("q1_shape((double)a / n, (double)b / n, N);", "q1_shape((double)b / n, (double)a / n, N);", 1),
+    "restrict_corner_order": ("coarse[ncomp * c[k] + d] += N[k]", "coarse[ncomp * c[3 - k] + d] += N[k]", 0),
+    "average_fixed_divisor": ("s[0] / cnt", "s[0] / 4", 0),
+    "input_component": ("x[2 * nf + 2 * l] = D[2 * f];", "x[2 * nf + 2 * l] = D[2 * f + 1];", 0),
+    "aspect_inverted": ("f[2] = hx / hy;", "f[2] = hy / hx;", 0),
+    "lumped_mass": ("Mu[2 * node[a] + c] += wd * N[a] * uq[c];", "Mu[2 * node[a] + c] += wd * 0.25 * uq[c];", 0),
+    "mask_wrong_axis": ("((dir & 4u) && J == 0)", "((dir & 4u) && I == 0)", 0),
+    "state_without_correction": ("uprev[f] = Pv[f] + Dbar[f];", "uprev[f] = Pv[f];", 0),
+}
+
+
+def _mutate(text, old, new, occ):
+    idx = -1
+    for _ in range(occ + 1):
+        idx = text.index(old, idx + 1)
+    return text[:idx] + new + text[idx + len(old):]
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new, occ = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) > occ, "mutation anchor missing: %s" % name
+    msrc = tmp_path / "mutant.c"
+    msrc.write_text(_mutate(src, old, new, occ))
+    mlib = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-o", str(mlib), str(msrc), "-lm"])
+    env = dict(os.environ, DNNMG_ORACLE_LIB=str(mlib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0, "pins did not catch mutation %s:\n%s" % (name, r.stdout[-2000:])
