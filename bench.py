@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the fine-level DNN-MG step on one MI355X.
+
+A step is one pass of the whole hot path over one flow's patches: prolongation,
+defect, network input, GRU + MLP, averaging, corrected velocity, FP64
+right-hand side and restriction (dnnmg_step + dnnmg_restrict_rhs).  Inputs
+(coarse v, p of every timed step) are resident in HBM before the timed region.
+
+Prints one JSON line: patch-steps/s for the BF16-operand form (value), the
+FP32-operand form beside it, the roofline of the dominant kernel measured
+with HIP events recorded by the library on the launch stream, and the FP64
+oracle timed on a bounded sample on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp8": 5000.0}
+STAGES = ["prolong_defect", "gru_mlp", "avg_rhs_fp64", "restrict_gather"]
+
+
+def per_patch_gemm_flop(K, H, Hm):
+    from paper_2008_11520_amd import synth
+    nin, nout, shapes = synth.net_shapes(K, H, Hm)
+    return 2 * sum(o * i for o, i in shapes)
+
+
+def per_patch_step_bytes(K, H):
+    """Minimum HBM bytes per patch-step the method must move (intermediates
+    excluded): coarse v (8) + p (4) + geometry (8) per coarse node, the
+    previous corrected velocity read and the new one written ((2^K)^2 fine
+    nodes x 8 B each way), h read + written (2 H x 4 B), b_L written (16 B)."""
+    n = 1 << K
+    return 8 + 4 + 8 + 2 * n * n * 8 + 2 * H * 4 + 16
+
+
+def run_gpu(wl, precision, steps, warmup):
+    import torch
+    import paper_2008_11520_amd as pam
+    from paper_2008_11520_amd import synth
+    flow = wl.flows[0]
+    w = synth.xavier_weights(wl.K, wl.H, wl.Hm, wl.weight_seed)
+    cfg = pam.make_config(flow.nx, flow.ny, wl.K, wl.H, wl.Hm, flow.dt, wl.nu, precision, flow.dirichlet)
+    g = pam.DnnMG(cfg, flow.cxy, w)
+    s = g.s
+    total = warmup + steps
+    # distinct coarse fields per step, resident on the device
+    nfield = min(total, 16)
+    vs, ps = [], []
+    for n in range(nfield):
+        v, p = flow.fields(n)
+        vs.append(torch.from_numpy(v.reshape(-1)).cuda())
+        ps.append(torch.from_numpy(p).cuda())
+    b = torch.empty(2 * s["Nc"], dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    for n in range(warmup):
+        g.step(vs[n % nfield], ps[n % nfield])
+        g.restrict_rhs(b)
+    torch.cuda.synchronize()
+    g.profile_enable(steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for n in range(steps):
+        k = (warmup + n) % nfield
+        g.step(vs[k], ps[k])
+        g.restrict_rhs(b)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    stage_ms, stage_n = g.profile_read()
+    g.profile_enable(0)
+    ok = bool(torch.isfinite(b).all().item())
+    g.close()
+    return dict(ms_total=ms, wall_s=wall, P=s["P"], stage_ms=stage_ms, stage_n=stage_n, finite=ok)
+
+
+def cpu_baseline(wl, sample_steps=2):
+    import oracle
+    from paper_2008_11520_amd import synth
+    flow = wl.flows[0]
+    w = synth.xavier_weights(wl.K, wl.H, wl.Hm, wl.weight_seed)
+    o = oracle.OracleFlow(flow.nx, flow.ny, wl.K, wl.H, wl.Hm, flow.dt, wl.nu, flow.dirichlet, flow.cxy, w)
+    fields = [flow.fields(n) for n in range(sample_steps)]
+    t0 = time.perf_counter()
+    for v, p in fields:
+        o.step(v, p, want=("bL",))
+    dt = time.perf_counter() - t0
+    P = flow.nx * flow.ny
+    return {"value": P * sample_steps / dt, "unit": "patch-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d full steps of the %dx%d mesh (%d patches), single-threaded FP64 C, %.1f s"
+                      % (sample_steps, flow.nx, flow.ny, P, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="channel1024x256_k2_perturbed")
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (each box has one MI355X); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2008_11520_amd import synth
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    wl = synth.workload(args.workload)
+    flow = wl.flows[0]
+    print("bench: workload %s, %d patches, precision %s, %d steps" % (wl.name, flow.nx * flow.ny, args.precision,
+                                                                     args.steps), file=sys.stderr, flush=True)
+
+    forms = {}
+    for prec in ([args.precision] + [p for p in ("bf16", "fp32") if p != args.precision]):
+        r = run_gpu(wl, prec, args.steps, args.warmup)
+        forms[prec] = r
+        print("bench: %s %.3f ms/step" % (prec, r["ms_total"] / args.steps), file=sys.stderr, flush=True)
+
+    main_r = forms[args.precision]
+    P = main_r["P"]
+    ms_step = main_r["ms_total"] / args.steps
+    value = P * args.steps / (main_r["ms_total"] / 1e3)
+
+    # dominant kernel and its roofline
+    avg = [main_r["stage_ms"][k] / max(main_r["stage_n"][k], 1) for k in range(4)]
+    dom = int(np.argmax(avg))
+    flop = per_patch_gemm_flop(wl.K, wl.H, wl.Hm)
+    if dom == 1:
+        achieved = flop * P / (avg[1] / 1e3) / 1e12
+        roof = {"kernel": STAGES[1], "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[args.precision],
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[args.precision], "traffic": None,
+                "avg_launch_us": avg[1] * 1e3, "algorithmic_per_patch": flop}
+    else:
+        bpp = per_patch_step_bytes(wl.K, wl.H)
+        achieved = bpp * P / (avg[dom] / 1e3) / 1e9
+        roof = {"kernel": STAGES[dom], "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "avg_launch_us": avg[dom] * 1e3,
+                "algorithmic_per_patch": bpp}
+    step_bytes = per_patch_step_bytes(wl.K, wl.H) * P
+    out = {
+        "metric": "patch-steps/s of the fine DNN-MG step",
+        "value": value,
+        "unit": "patch-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic (seeded channel mesh, Fourier-mode coarse fields, Xavier weights)",
+        "config": {"workload": wl.name, "patches": P, "K": wl.K, "H": wl.H, "Hm": wl.Hm,
+                   "gemm_operands": args.precision, "defect": "f32", "rhs_restriction": "f64"},
+        "forms": {p: {"patch_steps_per_s": P * args.steps / (r["ms_total"] / 1e3),
+                      "ms_per_step": r["ms_total"] / args.steps,
+                      "stage_us": {STAGES[k]: r["stage_ms"][k] / max(r["stage_n"][k], 1) * 1e3 for k in range(4)}}
+                  for p, r in forms.items()},
+        "step_hbm": {"algorithmic_bytes_per_patch": per_patch_step_bytes(wl.K, wl.H),
+                     "achieved_GBs": step_bytes / (ms_step / 1e3) / 1e9,
+                     "frac": step_bytes / (ms_step / 1e3) / 1e9 / PEAK_HBM_GBS},
+        "roofline": roof,
+        "finite": main_r["finite"],
+    }
+    if not args.no_cpu_baseline:
+        print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

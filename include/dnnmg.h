@@ -1,0 +1,198 @@
+/*
+ * dnnmg.h -- C ABI of the fine-level DNN-MG step on AMD Instinct MI355X (gfx950).
+ *
+ * The library performs, for one or many flows, the work that DNN-MG does in
+ * place of fine-level multigrid at every time step (Margenberg, Hartmann,
+ * Lessig, Richter, arXiv 2008.11520, Algorithm 2, lines 6-9; Sec. 4.1):
+ *   1. prolongation of the coarse (level L) velocity and pressure to level L+K,
+ *   2. element-wise assembly of the fine Navier-Stokes defect (momentum rows of
+ *      the nonlinear residual of Eq. (nonlinearshort), implicit-Euler form),
+ *   3. the per-patch GRU (Eq. (gru), no biases, Sec. 5.2) and MLP head that
+ *      predict a velocity correction, averaged where patches share fine nodes
+ *      (Sec. 4.2),
+ *   4. the fine right-hand side (1/dt) M_f (P v + d) and its restriction
+ *      R = P^T to level L, accumulated in FP64.
+ * A patch is one coarse element (Sec. 5.2); n = 2^K fine elements per coarse
+ * element and direction.
+ *
+ * Meshes are structured: coarse node (i,j), 0<=i<=nx, 0<=j<=ny has index
+ * j*(nx+1)+i; fine node (I,J), 0<=I<=nx*n has index J*(nx*n+1)+I.  Vector
+ * fields are interleaved (x,y) per node.  Coarse elements may be general
+ * (positively oriented) quadrilaterals; fine levels come from uniform
+ * bilinear refinement.
+ *
+ * Conventions for every entry point:
+ *  - Ownership: the caller owns every pointer it passes; device pointers must
+ *    stay valid until the work enqueued on the stream has completed.  The
+ *    library owns the per-flow state (GRU hidden state h, previous corrected
+ *    velocity), its workspace and the packed weights.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ *    stream).  Step calls only enqueue work: no host synchronisation and no
+ *    device allocation happen after dnnmg_create.
+ *  - Errors: arguments are validated on the host before anything is enqueued;
+ *    on failure nothing is enqueued, the context is unchanged and a negative
+ *    status is returned (the message is in dnnmg_last_error()).  Calls never
+ *    abort.  A device error raised by enqueued work is reported as
+ *    DNNMG_EDEVICE by the call that observes it.
+ *  - Threads: a context must not be used from two threads at once;
+ *    dnnmg_last_error() is per thread.
+ */
+#ifndef DNNMG_H
+#define DNNMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dnnmg_ctx dnnmg_ctx;     /* one flow: mesh, state, workspace   */
+typedef struct dnnmg_batch dnnmg_batch; /* descriptor table for batched steps */
+
+enum {
+    DNNMG_OK = 0,
+    DNNMG_EINVAL = -1,       /* bad argument (NULL, out of range, size mismatch) */
+    DNNMG_ENOMEM = -2,       /* device allocation failed (create only)           */
+    DNNMG_EDEVICE = -3,      /* HIP runtime or kernel error                      */
+    DNNMG_ESTATE = -4,       /* call out of order (e.g. restrict before a step)  */
+    DNNMG_EUNSUPPORTED = -5  /* valid but not built (e.g. an H without kernels)  */
+};
+
+/* Operand precision of the GRU/MLP products (accumulation is always FP32;
+ * prolongation and defect are FP32; rhs and restriction are FP64). */
+enum { DNNMG_FP32 = 0, DNNMG_BF16 = 1, DNNMG_FP8_E4M3 = 2 };
+
+/* Dirichlet sides (Eq. (boundary)); other sides are do-nothing outflow. */
+enum { DNNMG_DIR_XMIN = 1, DNNMG_DIR_XMAX = 2, DNNMG_DIR_YMIN = 4, DNNMG_DIR_YMAX = 8 };
+
+typedef struct {
+    int nx, ny;          /* coarse elements per direction, >= 1; patches = nx*ny    */
+    int K;               /* levels bridged, 1..3; n = 2^K                           */
+    int H;               /* GRU hidden size: 32, 64 or 128                          */
+    int Hm;              /* MLP hidden width: 0 (single linear H -> N_out), or a
+                            multiple of 16 up to 256                                 */
+    double dt;           /* time step (> 0)                                          */
+    double nu;           /* viscosity (>= 0)                                         */
+    int precision;       /* DNNMG_FP32 / DNNMG_BF16 / DNNMG_FP8_E4M3                 */
+    unsigned dirichlet;  /* DNNMG_DIR_* bits                                         */
+    unsigned flags;      /* reserved, must be 0                                      */
+} dnnmg_config;
+
+/* Network sizes: N_in = 4 (n+1)^2 + 4 (prolongated velocity and defect at the
+ * (n+1)^2 patch nodes, then hx, hy, hx/hy, area), N_out = 2 (n+1)^2.
+ * Weight count = 3 H N_in + 3 H H + (Hm > 0 ? Hm H + N_out Hm : N_out H). */
+size_t dnnmg_weight_count(const dnnmg_config *cfg);
+
+/* Device bytes one context of this configuration allocates (state, workspace
+ * and its own packed weights); 0 if cfg is invalid.  For admission control. */
+size_t dnnmg_workspace_bytes(const dnnmg_config *cfg);
+
+/* Create a flow.
+ * coarse_xy_host: host, (ny+1)(nx+1) x 2 doubles, node-major, coordinates of
+ *   the coarse nodes; every element must be positively oriented.
+ * weights_host: host FP32, dnnmg_weight_count(cfg) values in the order
+ *   W_z, W_r, W_h (H x N_in each), U_z, U_r, U_h (H x H each), then M1 (Hm x H)
+ *   and M2 (N_out x Hm), or M (N_out x H) when Hm == 0; row-major (out x in),
+ *   y = W x, no biases (Sec. 5.2).  Copied and packed (BF16, or FP8 E4M3 with
+ *   one FP32 scale per output row) at create.
+ * The GRU state starts at h = 0.  Allocates all device memory of the flow.
+ * Enqueues uploads on `stream` and synchronises it before returning. */
+int dnnmg_create(const dnnmg_config *cfg, const double *coarse_xy_host,
+                 const float *weights_host, size_t n_weights,
+                 void *stream, dnnmg_ctx **out);
+
+/* Create a flow that shares the packed weights of `model` (same K, H, Hm and
+ * precision required); flows created this way can be stepped together by
+ * dnnmg_step_batch.  The shared weights live until the last user is destroyed. */
+int dnnmg_create_shared(const dnnmg_config *cfg, const double *coarse_xy_host,
+                        const dnnmg_ctx *model, void *stream, dnnmg_ctx **out);
+
+/* One fine DNN-MG step (Alg. 2, lines 6-8).
+ * v_coarse_dev: device, (ny+1)(nx+1) x 2 FP32 coarse velocity v_n^L.
+ * p_coarse_dev: device, (ny+1)(nx+1) FP32 coarse pressure, or NULL (= 0).
+ * d_fine_dev:   device, optional (NULL to skip), Fn x 2 FP32: the averaged,
+ *   Dirichlet-masked correction d_n^{L+1} at the fine nodes.
+ * Updates h and the stored corrected velocity P v + d, and prepares the
+ * restricted right-hand side for dnnmg_restrict_rhs.  On the first step of a
+ * context the previous corrected velocity is taken as P v of this step. */
+int dnnmg_step(dnnmg_ctx *ctx, const float *v_coarse_dev, const float *p_coarse_dev,
+               float *d_fine_dev, void *stream);
+
+/* Restricted right-hand side of the most recent step (Alg. 2, line 9):
+ * b_coarse_dev: device, (ny+1)(nx+1) x 2 doubles,
+ *   b^L = P^T (1/dt) M_f (P v + d), accumulated in FP64.
+ * DNNMG_ESTATE before the first step.  May be called more than once. */
+int dnnmg_restrict_rhs(dnnmg_ctx *ctx, double *b_coarse_dev, void *stream);
+
+/* Batched steps (serving form): a descriptor table for up to max_flows flows.
+ * Allocates a small device table and pinned staging memory. */
+int dnnmg_batch_create(int max_flows, dnnmg_batch **out);
+int dnnmg_batch_destroy(dnnmg_batch *b);
+
+/* Step nflows flows (all sharing one weight set, see dnnmg_create_shared) with
+ * one launch per kernel stage; results equal dnnmg_step on each context, bit
+ * for bit.  v[f], p[f] (may be NULL), d_out[f] (may be NULL) as in dnnmg_step;
+ * d_out itself may be NULL.  Also produces each flow's restricted rhs, read
+ * with dnnmg_restrict_rhs.  The table upload is an async copy from pinned
+ * memory; the call waits for the batch's previous upload to finish before
+ * reusing its staging slot. */
+int dnnmg_step_batch(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int nflows,
+                     const float *const *v, const float *const *p, float *const *d_out,
+                     void *stream);
+
+int dnnmg_destroy(dnnmg_ctx *ctx);
+
+/* Last error message of the calling thread ("" if none). */
+const char *dnnmg_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Stage entry points: the same kernels as dnnmg_step, one stage at a time,
+ * for per-output verification.  None of them changes the flow's state.
+ * ------------------------------------------------------------------- */
+
+/* Prolongation (Alg. 2, line 6): pv_out Fn x 2 and pp_out Fn (either may be
+ * NULL) from the coarse v (and p, NULL = 0). */
+int dnnmg_prolong(dnnmg_ctx *ctx, const float *v_coarse_dev, const float *p_coarse_dev,
+                  float *pv_out_dev, float *pp_out_dev, void *stream);
+
+/* Fine defect of P(v, p) against the stored previous corrected velocity
+ * (P v itself before the first step), Dirichlet-masked: D_out Fn x 2 FP32. */
+int dnnmg_defect(dnnmg_ctx *ctx, const float *v_coarse_dev, const float *p_coarse_dev,
+                 float *D_out_dev, void *stream);
+
+/* Right-hand side and restriction alone (Alg. 2, lines 8-9) for a given fine
+ * correction: b_out = P^T (1/dt) M_f (P v + dbar), FP64.  dbar_dev Fn x 2. */
+int dnnmg_rhs_restrict(dnnmg_ctx *ctx, const float *v_coarse_dev, const float *dbar_dev,
+                       double *b_out_dev, void *stream);
+
+/* Copy the state out (h: P x H FP32, uprev: Fn x 2 FP32; either may be NULL)
+ * or in (then `steps` sets the step counter; 0 means "before the first step"). */
+int dnnmg_get_state(dnnmg_ctx *ctx, float *h_out_dev, float *uprev_out_dev, void *stream);
+int dnnmg_set_state(dnnmg_ctx *ctx, const float *h_in_dev, const float *uprev_in_dev,
+                    long long steps, void *stream);
+
+/* Per-patch network output of the most recent step, before averaging:
+ * d_out P x N_out FP32.  DNNMG_ESTATE before the first step. */
+int dnnmg_patch_output(dnnmg_ctx *ctx, float *d_out_dev, void *stream);
+
+long long dnnmg_step_count(const dnnmg_ctx *ctx);
+
+/* ---------------------------------------------------------------------
+ * Kernel timing for benchmarks.  While enabled, dnnmg_step and
+ * dnnmg_restrict_rhs record HIP events on their stream around each kernel
+ * stage: 0 = prolongation + defect + network input, 1 = GRU + MLP,
+ * 2 = averaging + FP64 rhs, 3 = restriction gather.  Up to max_steps steps
+ * are recorded (later ones are not timed).  Enabling creates the events (no
+ * device memory); max_steps = 0 disables and releases them.
+ * dnnmg_profile_read waits for the recorded events and returns, per stage,
+ * the summed milliseconds and the number of timed launches, then clears.
+ * ------------------------------------------------------------------- */
+enum { DNNMG_STAGES = 4 };
+int dnnmg_profile_enable(dnnmg_ctx *ctx, int max_steps);
+int dnnmg_profile_read(dnnmg_ctx *ctx, double *ms_per_stage, int *launches_per_stage);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DNNMG_H */

@@ -1,0 +1,728 @@
+// C ABI of the fine-level DNN-MG step (declared in include/dnnmg.h).
+//
+// Host side only: argument validation, device memory layout, weight packing
+// into MFMA fragments, exact moment tables for the FP64 right-hand side, and
+// kernel launches.  All per-step arithmetic runs in the kernels.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dnnmg.h"
+#include "internal.h"
+
+using namespace dnnmg;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OR_FAIL(expr)                                                                       \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return fail(DNNMG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char *dnnmg_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------- sizes
+namespace {
+
+struct Sizes {
+    int n, nf, nin, nout, P, Fn, Nc;
+};
+
+Sizes sizes_of(const dnnmg_config &c)
+{
+    Sizes s;
+    s.n = 1 << c.K;
+    s.nf = (s.n + 1) * (s.n + 1);
+    s.nin = 4 * s.nf + 4;
+    s.nout = 2 * s.nf;
+    s.P = c.nx * c.ny;
+    s.Fn = (c.nx * s.n + 1) * (c.ny * s.n + 1);
+    s.Nc = (c.nx + 1) * (c.ny + 1);
+    return s;
+}
+
+int kchunk(int prec) { return prec == DNNMG_FP32 ? 16 : 32; }
+int kquad(int prec) { return prec == DNNMG_FP32 ? 4 : 8; }
+int elem_bytes(int prec) { return prec == DNNMG_FP32 ? 4 : (prec == DNNMG_BF16 ? 2 : 1); }
+
+int check_config(const dnnmg_config *c)
+{
+    if (!c) return fail(DNNMG_EINVAL, "config is NULL");
+    if (c->nx < 1 || c->ny < 1) return fail(DNNMG_EINVAL, "nx, ny must be >= 1 (got %d, %d)", c->nx, c->ny);
+    if (c->K < 1 || c->K > 3) return fail(DNNMG_EINVAL, "K must be 1, 2 or 3 (got %d)", c->K);
+    if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return fail(DNNMG_EINVAL, "dt must be > 0");
+    if (!(c->nu >= 0.0) || !std::isfinite(c->nu)) return fail(DNNMG_EINVAL, "nu must be >= 0");
+    if (c->precision < DNNMG_FP32 || c->precision > DNNMG_FP8_E4M3)
+        return fail(DNNMG_EINVAL, "precision %d unknown", c->precision);
+    if (c->dirichlet > 15u) return fail(DNNMG_EINVAL, "dirichlet flags 0x%x out of range", c->dirichlet);
+    if (c->flags != 0u) return fail(DNNMG_EINVAL, "flags must be 0");
+    if (c->H <= 0 || c->Hm < 0) return fail(DNNMG_EINVAL, "H must be > 0 and Hm >= 0");
+    if (c->H != 32 && c->H != 64 && c->H != 128)
+        return fail(DNNMG_EUNSUPPORTED, "H = %d has no kernels (32, 64, 128)", c->H);
+    if (c->Hm != 0 && (c->Hm % 32 != 0 || c->Hm > 256))
+        return fail(DNNMG_EUNSUPPORTED, "Hm = %d unsupported (0 or a multiple of 32 up to 256)", c->Hm);
+    if (c->precision == DNNMG_FP8_E4M3) return fail(DNNMG_EUNSUPPORTED, "FP8 E4M3 form not built");
+    const double n = double(1 << c->K);
+    const double fn = (c->nx * n + 1.0) * (c->ny * n + 1.0);
+    if (fn > 2.0e9 || double(c->nx) * c->ny * (4.0 * (n + 1) * (n + 1) + 4) > 4.0e9)
+        return fail(DNNMG_EINVAL, "mesh too large for one context");
+    return DNNMG_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Device layout of one context's workspace.
+struct Layout {
+    size_t geo, geo64, feat, h, uprev, X, dpatch, part, G, M, cxy, flag, bad, total;
+};
+
+Layout layout_of(const dnnmg_config &c)
+{
+    Sizes s = sizes_of(c);
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
+    L.geo = take(sizeof(float) * 6 * s.P);
+    L.geo64 = take(sizeof(double) * 4 * s.P);
+    L.feat = take(sizeof(float) * 4 * s.P);
+    L.h = take(sizeof(float) * (size_t)s.P * c.H);
+    L.uprev = take(sizeof(float) * 2 * (size_t)s.Fn);
+    L.X = take(sizeof(float) * (size_t)s.P * s.nin);
+    L.dpatch = take(sizeof(float) * (size_t)s.P * s.nout);
+    L.part = take(sizeof(double) * 8 * (size_t)s.P);
+    L.G = take(sizeof(double) * 3 * 4 * s.nf);
+    L.M = take(sizeof(double) * 3 * 4 * 4);
+    L.cxy = take(sizeof(double) * 2 * (size_t)s.Nc);
+    L.flag = take(sizeof(int));
+    L.bad = take(sizeof(int));
+    L.total = o;
+    return L;
+}
+
+// -------------------------------------------------------- weight packing
+// Fragment layout: [tile ot][chunk kc][lane][e], value M[j][k] with
+// j = 16 ot + lane % 16, k = kc KC + (lane / 16) KQ + e (zero outside).
+uint16_t bf16_rne(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+void pack_matrix(std::vector<unsigned char> &out, const std::vector<float> &M, int rows, int cols, int tiles,
+                 int chunks, int prec)
+{
+    const int KC = kchunk(prec), KQ = kquad(prec), eb = elem_bytes(prec);
+    size_t base = out.size();
+    out.resize(base + (size_t)tiles * chunks * 64 * KQ * eb, 0);
+    for (int ot = 0; ot < tiles; ++ot)
+        for (int kc = 0; kc < chunks; ++kc)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < KQ; ++e) {
+                    int j = 16 * ot + lane % 16, k = kc * KC + (lane / 16) * KQ + e;
+                    float v = (j < rows && k < cols) ? M[(size_t)j * cols + k] : 0.0f;
+                    size_t idx = base + ((((size_t)ot * chunks + kc) * 64 + lane) * KQ + e) * eb;
+                    if (prec == DNNMG_FP32) std::memcpy(&out[idx], &v, 4);
+                    else { uint16_t b = bf16_rne(v); std::memcpy(&out[idx], &b, 2); }
+                }
+}
+
+}  // namespace
+
+// Shared, reference-counted packed weights.
+struct Weights {
+    std::atomic<int> refs{1};
+    void *dev = nullptr;
+    size_t bytes = 0;
+    int K = 0, H = 0, Hm = 0, prec = 0;
+    NetArgs net{};
+};
+
+// Event ring for per-stage kernel timing (benchmarks only).
+struct Profile {
+    int max_steps = 0;
+    std::vector<hipEvent_t> ev;        // per step: 4 events (defect start .. rhs end)
+    std::vector<hipEvent_t> evg;       // per restrict call: 2 events
+    int steps = 0, gathers = 0;
+};
+static void profile_release(Profile &pr);
+
+struct dnnmg_ctx {
+    dnnmg_config cfg;
+    Profile prof;
+    Sizes s;
+    Layout L;
+    unsigned char *ws = nullptr;
+    Weights *w = nullptr;
+    long long steps = 0;
+    int device = 0;
+
+    float *geo() const { return (float *)(ws + L.geo); }
+    double *geo64() const { return (double *)(ws + L.geo64); }
+    float *feat() const { return (float *)(ws + L.feat); }
+    float *h() const { return (float *)(ws + L.h); }
+    float *uprev() const { return (float *)(ws + L.uprev); }
+    float *X() const { return (float *)(ws + L.X); }
+    float *dpatch() const { return (float *)(ws + L.dpatch); }
+    double *part() const { return (double *)(ws + L.part); }
+    int *first_flag() const { return (int *)(ws + L.flag); }
+    RhsTables tables() const { return RhsTables{(const double *)(ws + L.G), (const double *)(ws + L.M)}; }
+};
+
+struct dnnmg_batch {
+    int max_flows = 0;
+    BatchTable *dev[2] = {nullptr, nullptr};
+    BatchTable *host[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int slot = 0;
+    bool used[2] = {false, false};
+};
+
+namespace {
+
+size_t weight_count(const dnnmg_config &c)
+{
+    Sizes s = sizes_of(c);
+    size_t n = 3 * (size_t)c.H * s.nin + 3 * (size_t)c.H * c.H;
+    n += c.Hm > 0 ? (size_t)c.Hm * c.H + (size_t)s.nout * c.Hm : (size_t)s.nout * c.H;
+    return n;
+}
+
+// Pack host FP32 weights into the four fragment arrays the network kernel reads.
+int build_weights(const dnnmg_config &c, const float *w, hipStream_t st, Weights **out)
+{
+    Sizes s = sizes_of(c);
+    const int H = c.H, Hm = c.Hm, prec = c.precision, KC = kchunk(prec);
+    const int nin = s.nin, nout = s.nout, HT = H / 16;
+    const int kc1 = (nin + H + KC - 1) / KC;
+    const float *Wg[3] = {w, w + (size_t)H * nin, w + 2 * (size_t)H * nin};
+    const float *Ug[3] = {w + 3 * (size_t)H * nin, w + 3 * (size_t)H * nin + (size_t)H * H,
+                          w + 3 * (size_t)H * nin + 2 * (size_t)H * H};
+    const float *M1 = w + 3 * (size_t)H * nin + 3 * (size_t)H * H;
+    const float *M2 = Hm > 0 ? M1 + (size_t)Hm * H : nullptr;
+
+    std::vector<unsigned char> buf;
+    size_t off[4];
+    off[0] = 0;
+    for (int g = 0; g < 3; ++g) {   // [W_g | U_g], the U_h block is applied in phase 2
+        std::vector<float> A((size_t)H * (nin + H), 0.0f);
+        for (int j = 0; j < H; ++j) {
+            for (int k = 0; k < nin; ++k) A[(size_t)j * (nin + H) + k] = Wg[g][(size_t)j * nin + k];
+            if (g < 2)
+                for (int k = 0; k < H; ++k) A[(size_t)j * (nin + H) + nin + k] = Ug[g][(size_t)j * H + k];
+        }
+        pack_matrix(buf, A, H, nin + H, HT, kc1, prec);
+    }
+    buf.resize(align256(buf.size()));
+    off[1] = buf.size();
+    pack_matrix(buf, std::vector<float>(Ug[2], Ug[2] + (size_t)H * H), H, H, HT, H / KC, prec);
+    buf.resize(align256(buf.size()));
+    off[2] = buf.size();
+    if (Hm > 0) {
+        pack_matrix(buf, std::vector<float>(M1, M1 + (size_t)Hm * H), Hm, H, Hm / 16, H / KC, prec);
+        buf.resize(align256(buf.size()));
+        off[3] = buf.size();
+        pack_matrix(buf, std::vector<float>(M2, M2 + (size_t)nout * Hm), nout, Hm, (nout + 15) / 16, Hm / KC, prec);
+    } else {
+        pack_matrix(buf, std::vector<float>(M1, M1 + (size_t)nout * H), nout, H, (nout + 15) / 16, H / KC, prec);
+        buf.resize(align256(buf.size()));
+        off[3] = buf.size();
+    }
+    buf.resize(align256(buf.size()) + 256);
+
+    Weights *W = new Weights();
+    W->bytes = buf.size();
+    if (hipMalloc(&W->dev, W->bytes) != hipSuccess) {
+        delete W;
+        (void)hipGetLastError();
+        return fail(DNNMG_ENOMEM, "hipMalloc of %zu weight bytes failed", buf.size());
+    }
+    hipError_t e = hipMemcpyAsync(W->dev, buf.data(), buf.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(W->dev);
+        delete W;
+        return fail(DNNMG_EDEVICE, "weight upload: %s", hipGetErrorString(e));
+    }
+    W->K = c.K; W->H = H; W->Hm = Hm; W->prec = prec;
+    unsigned char *d = (unsigned char *)W->dev;
+    W->net = NetArgs{c.K, H, Hm, nin, nout, prec, kc1, d + off[0], d + off[1], d + off[2], d + off[3],
+                     nullptr, nullptr, nullptr, nullptr};
+    *out = W;
+    return DNNMG_OK;
+}
+
+size_t weight_bytes_estimate(const dnnmg_config &c)
+{
+    Sizes s = sizes_of(c);
+    const int KC = kchunk(c.precision), KQ = kquad(c.precision), eb = elem_bytes(c.precision);
+    auto frag = [&](int rows, int cols) {
+        return align256((size_t)((rows + 15) / 16) * ((cols + KC - 1) / KC) * 64 * KQ * eb);
+    };
+    size_t b = 3 * (size_t)((c.H / 16) * ((s.nin + c.H + KC - 1) / KC) * 64 * KQ * eb);
+    b = align256(b) + frag(c.H, c.H);
+    b += c.Hm > 0 ? frag(c.Hm, c.H) + frag(s.nout, c.Hm) : frag(s.nout, c.H);
+    return align256(b) + 256;
+}
+
+void release_weights(Weights *w)
+{
+    if (w && --w->refs == 0) {
+        (void)hipFree(w->dev);
+        delete w;
+    }
+}
+
+// Exact moment tables on the reference square (see rhs.hip):
+//   G[k][c][l] = int N_c phi_l m_k,   M[k][c][c'] = int N_c N_c' m_k,  m = {1, xi, eta}.
+// Each factor is a 1D integral of a piecewise cubic, done with two Gauss points
+// per fine interval (exact).
+void moment_tables(int K, std::vector<double> &G, std::vector<double> &M)
+{
+    const int n = 1 << K, nf = (n + 1) * (n + 1);
+    const double gp[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+    auto L = [](int p, double x) { return p == 0 ? 1.0 - x : x; };
+    auto hat = [n](int a, double x) { double t = 1.0 - std::fabs(n * x - a); return t > 0.0 ? t : 0.0; };
+    // A[m][p][a] = int_0^1 L_p(x) hat_a(x) x^m dx ; C[m][p][q] = int_0^1 L_p L_q x^m dx
+    std::vector<double> A(2 * 2 * (n + 1), 0.0);
+    double C[2][2][2] = {};
+    for (int iv = 0; iv < n; ++iv)
+        for (int g = 0; g < 2; ++g) {
+            const double x = (iv + gp[g]) / n, w = 0.5 / n;
+            for (int m = 0; m < 2; ++m)
+                for (int p = 0; p < 2; ++p) {
+                    const double xm = m ? x : 1.0;
+                    for (int a = 0; a <= n; ++a) A[(m * 2 + p) * (n + 1) + a] += w * L(p, x) * hat(a, x) * xm;
+                    for (int q = 0; q < 2; ++q) C[m][p][q] += w * L(p, x) * L(q, x) * xm;
+                }
+        }
+    G.assign(3 * 4 * nf, 0.0);
+    M.assign(3 * 4 * 4, 0.0);
+    const int mx[3] = {0, 1, 0}, my[3] = {0, 0, 1};   // which direction carries xi / eta
+    for (int k = 0; k < 3; ++k)
+        for (int c = 0; c < 4; ++c) {
+            const int cx = c & 1, cy = c >> 1;
+            for (int b = 0; b <= n; ++b)
+                for (int a = 0; a <= n; ++a)
+                    G[(k * 4 + c) * nf + b * (n + 1) + a] =
+                        A[(mx[k] * 2 + cx) * (n + 1) + a] * A[(my[k] * 2 + cy) * (n + 1) + b];
+            for (int cc = 0; cc < 4; ++cc)
+                M[(k * 4 + c) * 4 + cc] = C[mx[k]][cx][cc & 1] * C[my[k]][cy][cc >> 1];
+        }
+}
+
+FlowArgs flow_args(const dnnmg_ctx *c, const float *v, const float *p)
+{
+    FlowArgs f{};
+    f.nx = c->cfg.nx;
+    f.ny = c->cfg.ny;
+    f.dirichlet = c->cfg.dirichlet;
+    f.first_flag = c->first_flag();
+    f.inv_dt = (float)(1.0 / c->cfg.dt);
+    f.nu = (float)c->cfg.nu;
+    f.inv_dt64 = 1.0 / c->cfg.dt;
+    f.v = v;
+    f.p = p;
+    f.geo = c->geo();
+    f.geo64 = c->geo64();
+    f.feat = c->feat();
+    f.h = c->h();
+    f.uprev = c->uprev();
+    f.X = c->X();
+    f.dpatch = c->dpatch();
+    f.part = c->part();
+    return f;
+}
+
+int create_common(const dnnmg_config *cfg, const double *cxy, const float *weights, size_t nw, Weights *shared,
+                  void *stream, dnnmg_ctx **out)
+{
+    if (!out) return fail(DNNMG_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    if (!cxy) return fail(DNNMG_EINVAL, "coarse_xy_host is NULL");
+    for (size_t i = 0; i < 2 * (size_t)(cfg->nx + 1) * (cfg->ny + 1); ++i)
+        if (!std::isfinite(cxy[i])) return fail(DNNMG_EINVAL, "coarse_xy_host[%zu] is not finite", i);
+    if (!shared) {
+        if (!weights) return fail(DNNMG_EINVAL, "weights_host is NULL");
+        if (nw != weight_count(*cfg))
+            return fail(DNNMG_EINVAL, "n_weights = %zu, expected %zu", nw, weight_count(*cfg));
+    } else if (shared->K != cfg->K || shared->H != cfg->H || shared->Hm != cfg->Hm || shared->prec != cfg->precision) {
+        return fail(DNNMG_EINVAL, "shared weights have another K/H/Hm/precision");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    dnnmg_ctx *c = new dnnmg_ctx();
+    c->cfg = *cfg;
+    c->s = sizes_of(*cfg);
+    c->L = layout_of(*cfg);
+    (void)hipGetDevice(&c->device);
+    if (hipMalloc((void **)&c->ws, c->L.total) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return fail(DNNMG_ENOMEM, "hipMalloc of %zu workspace bytes failed", c->L.total);
+    }
+    auto bail = [&](int code) {
+        (void)hipFree(c->ws);
+        if (c->w) release_weights(c->w);
+        delete c;
+        return code;
+    };
+    if (shared) {
+        ++shared->refs;
+        c->w = shared;
+    } else {
+        rc = build_weights(*cfg, weights, st, &c->w);
+        if (rc) { c->w = nullptr; return bail(rc); }
+    }
+    std::vector<double> G, M;
+    moment_tables(cfg->K, G, M);
+    const Sizes &s = c->s;
+    hipError_t e = hipMemcpyAsync(c->ws + c->L.cxy, cxy, sizeof(double) * 2 * s.Nc, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->ws + c->L.G, G.data(), sizeof(double) * G.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->ws + c->L.M, M.data(), sizeof(double) * M.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->h(), 0, sizeof(float) * (size_t)s.P * cfg->H, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->uprev(), 0, sizeof(float) * 2 * (size_t)s.Fn, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + c->L.bad, 0, sizeof(int), st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->first_flag(), 1, sizeof(int), st);
+    if (e == hipSuccess)
+        e = launch_geometry((const double *)(c->ws + c->L.cxy), cfg->nx, cfg->ny, c->geo(), c->geo64(), c->feat(),
+                            (int *)(c->ws + c->L.bad), st);
+    int bad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, c->ws + c->L.bad, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bail(fail(DNNMG_EDEVICE, "create: %s", hipGetErrorString(e)));
+    if (bad) return bail(fail(DNNMG_EINVAL, "coarse mesh has an element that is not positively oriented"));
+    *out = c;
+    return DNNMG_OK;
+}
+
+int check_ctx(const dnnmg_ctx *c)
+{
+    if (!c) return fail(DNNMG_EINVAL, "ctx is NULL");
+    return DNNMG_OK;
+}
+
+}  // namespace
+
+// ================================================================ ABI
+extern "C" size_t dnnmg_weight_count(const dnnmg_config *cfg)
+{
+    if (!cfg || cfg->K < 1 || cfg->K > 3 || cfg->H <= 0 || cfg->Hm < 0) return 0;
+    return weight_count(*cfg);
+}
+
+extern "C" size_t dnnmg_workspace_bytes(const dnnmg_config *cfg)
+{
+    if (check_config(cfg) != DNNMG_OK) return 0;
+    return layout_of(*cfg).total + weight_bytes_estimate(*cfg);
+}
+
+extern "C" int dnnmg_create(const dnnmg_config *cfg, const double *coarse_xy_host, const float *weights_host,
+                            size_t n_weights, void *stream, dnnmg_ctx **out)
+{
+    return create_common(cfg, coarse_xy_host, weights_host, n_weights, nullptr, stream, out);
+}
+
+extern "C" int dnnmg_create_shared(const dnnmg_config *cfg, const double *coarse_xy_host, const dnnmg_ctx *model,
+                                   void *stream, dnnmg_ctx **out)
+{
+    if (!model) return fail(DNNMG_EINVAL, "model is NULL");
+    return create_common(cfg, coarse_xy_host, nullptr, 0, model->w, stream, out);
+}
+
+extern "C" int dnnmg_destroy(dnnmg_ctx *ctx)
+{
+    if (!ctx) return fail(DNNMG_EINVAL, "ctx is NULL");
+    for (hipEvent_t e : ctx->prof.ev) (void)hipEventSynchronize(e);
+    for (hipEvent_t e : ctx->prof.evg) (void)hipEventSynchronize(e);
+    profile_release(ctx->prof);
+    (void)hipFree(ctx->ws);
+    release_weights(ctx->w);
+    delete ctx;
+    return DNNMG_OK;
+}
+
+extern "C" long long dnnmg_step_count(const dnnmg_ctx *ctx) { return ctx ? ctx->steps : -1; }
+
+static int enqueue_step(dnnmg_ctx *c, const FlowArgs &f, hipStream_t st)
+{
+    const dnnmg_config &g = c->cfg;
+    Profile &pr = c->prof;
+    hipEvent_t *ev = (pr.max_steps > 0 && pr.steps < pr.max_steps) ? &pr.ev[4 * pr.steps] : nullptr;
+    if (ev) HIP_OR_FAIL(hipEventRecord(ev[0], st));
+    HIP_OR_FAIL(launch_defect(f, nullptr, blocks_for(kKindDefect, g.nx, g.ny, g.K), g.K, 1, st));
+    if (ev) HIP_OR_FAIL(hipEventRecord(ev[1], st));
+    HIP_OR_FAIL(launch_net(f, nullptr, blocks_for(kKindNet, g.nx, g.ny, g.K), c->w->net, st));
+    if (ev) HIP_OR_FAIL(hipEventRecord(ev[2], st));
+    HIP_OR_FAIL(launch_rhs(f, nullptr, blocks_for(kKindRhs, g.nx, g.ny, g.K), g.K, c->tables(), 1, st));
+    if (ev) {
+        HIP_OR_FAIL(hipEventRecord(ev[3], st));
+        pr.steps++;
+    }
+    return DNNMG_OK;
+}
+
+static void profile_release(Profile &pr)
+{
+    for (hipEvent_t e : pr.ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : pr.evg) (void)hipEventDestroy(e);
+    pr.ev.clear();
+    pr.evg.clear();
+    pr.max_steps = pr.steps = pr.gathers = 0;
+}
+
+extern "C" int dnnmg_profile_enable(dnnmg_ctx *ctx, int max_steps)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (max_steps < 0 || max_steps > 100000) return fail(DNNMG_EINVAL, "max_steps must be in 0..100000");
+    for (hipEvent_t e : ctx->prof.ev) HIP_OR_FAIL(hipEventSynchronize(e));
+    profile_release(ctx->prof);
+    if (max_steps == 0) return DNNMG_OK;
+    Profile &pr = ctx->prof;
+    pr.ev.resize(4 * (size_t)max_steps);
+    pr.evg.resize(2 * (size_t)max_steps);
+    for (auto *v : {&pr.ev, &pr.evg})
+        for (hipEvent_t &e : *v)
+            if (hipEventCreate(&e) != hipSuccess) {
+                e = nullptr;
+                (void)hipGetLastError();
+                profile_release(pr);
+                return fail(DNNMG_EDEVICE, "hipEventCreate failed");
+            }
+    pr.max_steps = max_steps;
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_profile_read(dnnmg_ctx *ctx, double *ms, int *count)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!ms || !count) return fail(DNNMG_EINVAL, "ms_per_stage and launches_per_stage must not be NULL");
+    Profile &pr = ctx->prof;
+    for (int k = 0; k < DNNMG_STAGES; ++k) { ms[k] = 0.0; count[k] = 0; }
+    for (int s = 0; s < pr.steps; ++s)
+        for (int k = 0; k < 3; ++k) {
+            float t = 0.f;
+            HIP_OR_FAIL(hipEventSynchronize(pr.ev[4 * s + k + 1]));
+            HIP_OR_FAIL(hipEventElapsedTime(&t, pr.ev[4 * s + k], pr.ev[4 * s + k + 1]));
+            ms[k] += t;
+            count[k]++;
+        }
+    for (int s = 0; s < pr.gathers; ++s) {
+        float t = 0.f;
+        HIP_OR_FAIL(hipEventSynchronize(pr.evg[2 * s + 1]));
+        HIP_OR_FAIL(hipEventElapsedTime(&t, pr.evg[2 * s], pr.evg[2 * s + 1]));
+        ms[3] += t;
+        count[3]++;
+    }
+    pr.steps = pr.gathers = 0;
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_step(dnnmg_ctx *ctx, const float *v, const float *p, float *d_fine, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!v) return fail(DNNMG_EINVAL, "v_coarse_dev is NULL");
+    FlowArgs f = flow_args(ctx, v, p);
+    f.dbar_out = d_fine;
+    rc = enqueue_step(ctx, f, (hipStream_t)stream);
+    if (rc) return rc;
+    ctx->steps++;
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_restrict_rhs(dnnmg_ctx *ctx, double *b, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!b) return fail(DNNMG_EINVAL, "b_coarse_dev is NULL");
+    if (ctx->steps == 0) return fail(DNNMG_ESTATE, "no step has been taken yet");
+    FlowArgs f = flow_args(ctx, nullptr, nullptr);
+    f.bL = b;
+    Profile &pr = ctx->prof;
+    hipEvent_t *ev = (pr.max_steps > 0 && pr.gathers < pr.max_steps) ? &pr.evg[2 * pr.gathers] : nullptr;
+    if (ev) HIP_OR_FAIL(hipEventRecord(ev[0], (hipStream_t)stream));
+    HIP_OR_FAIL(launch_gather(f, nullptr, blocks_for(kKindGather, ctx->cfg.nx, ctx->cfg.ny, ctx->cfg.K),
+                              (hipStream_t)stream));
+    if (ev) {
+        HIP_OR_FAIL(hipEventRecord(ev[1], (hipStream_t)stream));
+        pr.gathers++;
+    }
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_prolong(dnnmg_ctx *ctx, const float *v, const float *p, float *pv, float *pp, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!v) return fail(DNNMG_EINVAL, "v_coarse_dev is NULL");
+    FlowArgs f = flow_args(ctx, v, p);
+    HIP_OR_FAIL(launch_prolong(f, ctx->cfg.K, pv, pp, (hipStream_t)stream));
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_defect(dnnmg_ctx *ctx, const float *v, const float *p, float *D, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!v || !D) return fail(DNNMG_EINVAL, "v_coarse_dev and D_out_dev must not be NULL");
+    FlowArgs f = flow_args(ctx, v, p);
+    f.D_out = D;
+    HIP_OR_FAIL(launch_defect(f, nullptr, blocks_for(kKindDefect, ctx->cfg.nx, ctx->cfg.ny, ctx->cfg.K), ctx->cfg.K,
+                              0, (hipStream_t)stream));
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_rhs_restrict(dnnmg_ctx *ctx, const float *v, const float *dbar, double *b, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!v || !dbar || !b) return fail(DNNMG_EINVAL, "v, dbar and b_out must not be NULL");
+    FlowArgs f = flow_args(ctx, v, nullptr);
+    f.dbar_in = dbar;
+    f.part = (double *)ctx->X();   // the network-input buffer is free between steps
+    f.bL = b;
+    const dnnmg_config &g = ctx->cfg;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_OR_FAIL(launch_rhs(f, nullptr, blocks_for(kKindRhs, g.nx, g.ny, g.K), g.K, ctx->tables(), 0, st));
+    HIP_OR_FAIL(launch_gather(f, nullptr, blocks_for(kKindGather, g.nx, g.ny, g.K), st));
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_get_state(dnnmg_ctx *ctx, float *h, float *u, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (h) HIP_OR_FAIL(hipMemcpyAsync(h, ctx->h(), sizeof(float) * (size_t)ctx->s.P * ctx->cfg.H,
+                                      hipMemcpyDeviceToDevice, st));
+    if (u) HIP_OR_FAIL(hipMemcpyAsync(u, ctx->uprev(), sizeof(float) * 2 * (size_t)ctx->s.Fn,
+                                      hipMemcpyDeviceToDevice, st));
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_set_state(dnnmg_ctx *ctx, const float *h, const float *u, long long steps, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (steps < 0) return fail(DNNMG_EINVAL, "steps must be >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    if (h) HIP_OR_FAIL(hipMemcpyAsync(ctx->h(), h, sizeof(float) * (size_t)ctx->s.P * ctx->cfg.H,
+                                      hipMemcpyDeviceToDevice, st));
+    if (u) HIP_OR_FAIL(hipMemcpyAsync(ctx->uprev(), u, sizeof(float) * 2 * (size_t)ctx->s.Fn,
+                                      hipMemcpyDeviceToDevice, st));
+    HIP_OR_FAIL(hipMemsetAsync(ctx->first_flag(), steps == 0 ? 1 : 0, sizeof(int), st));
+    ctx->steps = steps;
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_patch_output(dnnmg_ctx *ctx, float *d, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!d) return fail(DNNMG_EINVAL, "d_out_dev is NULL");
+    if (ctx->steps == 0) return fail(DNNMG_ESTATE, "no step has been taken yet");
+    HIP_OR_FAIL(hipMemcpyAsync(d, ctx->dpatch(), sizeof(float) * (size_t)ctx->s.P * ctx->s.nout,
+                               hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return DNNMG_OK;
+}
+
+// ------------------------------------------------------------- batches
+extern "C" int dnnmg_batch_create(int max_flows, dnnmg_batch **out)
+{
+    if (!out) return fail(DNNMG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_flows < 1 || max_flows > kMaxBatch)
+        return fail(DNNMG_EINVAL, "max_flows must be in 1..%d", kMaxBatch);
+    dnnmg_batch *b = new dnnmg_batch();
+    b->max_flows = max_flows;
+    for (int i = 0; i < 2; ++i) {
+        if (hipMalloc((void **)&b->dev[i], sizeof(BatchTable)) != hipSuccess ||
+            hipHostMalloc((void **)&b->host[i], sizeof(BatchTable), hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            dnnmg_batch_destroy(b);
+            return fail(DNNMG_ENOMEM, "batch table allocation failed");
+        }
+    }
+    *out = b;
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_batch_destroy(dnnmg_batch *b)
+{
+    if (!b) return fail(DNNMG_EINVAL, "batch is NULL");
+    for (int i = 0; i < 2; ++i) {
+        if (b->ev[i]) { (void)hipEventSynchronize(b->ev[i]); (void)hipEventDestroy(b->ev[i]); }
+        if (b->dev[i]) (void)hipFree(b->dev[i]);
+        if (b->host[i]) (void)hipHostFree(b->host[i]);
+    }
+    delete b;
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_step_batch(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int nflows, const float *const *v,
+                                const float *const *p, float *const *d_out, void *stream)
+{
+    if (!b || !ctxs || !v) return fail(DNNMG_EINVAL, "batch, ctxs and v must not be NULL");
+    if (nflows < 1 || nflows > b->max_flows) return fail(DNNMG_EINVAL, "nflows must be in 1..%d", b->max_flows);
+    Weights *w = ctxs[0] ? ctxs[0]->w : nullptr;
+    for (int i = 0; i < nflows; ++i) {
+        if (!ctxs[i]) return fail(DNNMG_EINVAL, "ctxs[%d] is NULL", i);
+        if (!v[i]) return fail(DNNMG_EINVAL, "v[%d] is NULL", i);
+        if (ctxs[i]->w != w) return fail(DNNMG_EINVAL, "ctxs[%d] does not share the weights of ctxs[0]", i);
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(DNNMG_EINVAL, "ctxs[%d] repeats ctxs[%d]", i, j);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int slot = b->slot;
+    if (b->used[slot]) HIP_OR_FAIL(hipEventSynchronize(b->ev[slot]));
+    BatchTable *t = b->host[slot];
+    t->nflows = nflows;
+    for (int k = 0; k < kKinds; ++k) t->prefix[k][0] = 0;
+    for (int i = 0; i < nflows; ++i) {
+        const dnnmg_config &g = ctxs[i]->cfg;
+        for (int k = 0; k < kKinds; ++k) t->prefix[k][i + 1] = t->prefix[k][i] + blocks_for(k, g.nx, g.ny, g.K);
+        FlowArgs f = flow_args(ctxs[i], v[i], p ? p[i] : nullptr);
+        f.dbar_out = d_out ? d_out[i] : nullptr;
+        f.bL = nullptr;
+        t->flows[i] = f;
+    }
+    const size_t bytes = offsetof(BatchTable, flows) + sizeof(FlowArgs) * nflows;
+    HIP_OR_FAIL(hipMemcpyAsync(b->dev[slot], t, bytes, hipMemcpyHostToDevice, st));
+    const int K = ctxs[0]->cfg.K;
+    RhsTables tab = ctxs[0]->tables();
+    FlowArgs dummy{};
+    HIP_OR_FAIL(launch_defect(dummy, b->dev[slot], t->prefix[kKindDefect][nflows], K, 1, st));
+    HIP_OR_FAIL(launch_net(dummy, b->dev[slot], t->prefix[kKindNet][nflows], w->net, st));
+    HIP_OR_FAIL(launch_rhs(dummy, b->dev[slot], t->prefix[kKindRhs][nflows], K, tab, 1, st));
+    HIP_OR_FAIL(hipEventRecord(b->ev[slot], st));
+    b->used[slot] = true;
+    b->slot ^= 1;
+    for (int i = 0; i < nflows; ++i) ctxs[i]->steps++;
+    return DNNMG_OK;
+}

@@ -1,0 +1,97 @@
+// Internal interfaces between the C ABI (api.cpp) and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dnnmg {
+
+constexpr int kThreads = 256;     // every kernel: 4 wave64s per workgroup
+constexpr int kTileFine = 16;     // defect tile: 16 x 16 fine elements
+constexpr int kNetRows = 64;      // GRU/MLP: patches per workgroup
+constexpr int kMaxBatch = 256;    // flows per batched launch
+
+// Per-flow arguments of one step.  Passed by value for a single flow, or read
+// from a device table for a batch.
+struct FlowArgs {
+    int nx, ny;
+    unsigned dirichlet;
+    int pad0;
+    float inv_dt, nu;
+    double inv_dt64;
+    const float *v;        // (ny+1)(nx+1) x 2
+    const float *p;        // (ny+1)(nx+1) or nullptr
+    const float *geo;      // per coarse element: ex, ey, exy (2 floats each)
+    const double *geo64;   // per coarse element: d0, d1, d2, (pad): det of the map
+    const float *feat;     // P x 4
+    int *first_flag;       // device: nonzero before the first step (then u_prev := P v)
+    float *h;              // P x H
+    float *uprev;          // Fn x 2
+    float *X;              // P x nin
+    float *dpatch;         // P x nout
+    double *part;          // P x 8: per-patch rhs contribution to its 4 corners
+    float *dbar_out;       // optional Fn x 2
+    float *D_out;          // optional Fn x 2 (stage)
+    const float *dbar_in;  // stage: given fine correction (rhs/restrict alone)
+    double *bL;            // restricted rhs output (gather)
+};
+
+// Shared network description.
+struct NetArgs {
+    int K, H, Hm, nin, nout, prec;
+    int kc1;               // k-chunks of phase 1 ([x | h])
+    const void *B1;        // phase 1 fragments: gates z, r, h over [x | h]
+    const void *B2;        // U_h fragments
+    const void *B3;        // M1 (or M when Hm == 0)
+    const void *B4;        // M2
+    const float *s1, *s2, *s3, *s4;  // FP8: per-output-row weight scales
+};
+
+// Moment tables for the FP64 right-hand side (exact integrals on the
+// reference square; see rhs.hip).
+struct RhsTables {
+    const double *G;       // 3 x 4 x nf : int N_c phi_l {1, xi, eta}
+    const double *M;       // 3 x 4 x 4  : int N_c N_c' {1, xi, eta}
+};
+
+// Device table for batched launches: per kernel kind, a block prefix over
+// flows, then the flows.
+enum { kKindDefect = 0, kKindNet = 1, kKindRhs = 2, kKindGather = 3, kKinds = 4 };
+struct BatchTable {
+    int nflows;
+    int pad[3];
+    int prefix[kKinds][kMaxBatch + 1];
+    FlowArgs flows[kMaxBatch];
+};
+
+// Blocks each kernel kind needs for one flow.
+int blocks_for(int kind, int nx, int ny, int K);
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_geometry(const double *cxy, int nx, int ny, float *geo, double *geo64,
+                           float *feat, int *bad, hipStream_t s);
+hipError_t launch_prolong(const FlowArgs &f, int K, float *pv, float *pp, hipStream_t s);
+hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K,
+                         int write_X, hipStream_t s);
+hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net,
+                      hipStream_t s);
+hipError_t net_set_attributes(int prec, int H);
+size_t net_lds_bytes(const NetArgs &net);
+hipError_t launch_rhs(const FlowArgs &f, const BatchTable *bt, int nblocks, int K,
+                      const RhsTables &tab, int from_patches, hipStream_t s);
+hipError_t launch_gather(const FlowArgs &f, const BatchTable *bt, int nblocks, hipStream_t s);
+
+// Find the flow and the flow-local block of a block of a batched launch.
+__device__ inline const FlowArgs *batch_flow(const BatchTable *bt, int kind, int &blk)
+{
+    int lo = 0, hi = bt->nflows - 1;
+    const int *pre = bt->prefix[kind];
+    while (lo < hi) {                      // last flow with prefix <= blk
+        int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= blk) lo = mid; else hi = mid - 1;
+    }
+    blk -= pre[lo];
+    return &bt->flows[lo];
+}
+
+}  // namespace dnnmg

@@ -1,0 +1,115 @@
+"""The C ABI library: it loads, exports every symbol include/dnnmg.h declares,
+and rejects bad arguments on the host before touching the device.  No compute
+call is made here (this suite runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dnnmg.h")
+
+pam = pytest.importorskip("paper_2008_11520_amd")
+if not os.path.exists(pam.LIB_PATH):
+    pytest.skip("libdnnmg.so not built", allow_module_level=True)
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dnnmg_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pam.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(pam.SYMBOLS) == names
+
+
+def cfg(**kw):
+    base = dict(nx=4, ny=3, K=2, H=64, Hm=64, dt=0.005, nu=1e-3, precision=0, dirichlet=13)
+    base.update(kw)
+    return pam.make_config(**base)
+
+
+def test_weight_count_formula():
+    c = cfg()
+    s = pam.sizes(4, 3, 2)
+    assert pam.weight_count(c) == 3 * 64 * s["nin"] + 3 * 64 * 64 + 64 * 64 + s["nout"] * 64
+    c = cfg(K=1, H=32, Hm=0)
+    assert pam.weight_count(c) == 3 * 32 * 40 + 3 * 32 * 32 + 18 * 32
+    from paper_2008_11520_amd import synth
+    for K, H, Hm in ((1, 32, 0), (2, 64, 64), (3, 128, 128)):
+        assert synth.xavier_weights(K, H, Hm, 1).size == pam.weight_count(cfg(K=K, H=H, Hm=Hm))
+
+
+def test_workspace_bytes():
+    assert pam.workspace_bytes(cfg()) > 0
+    big = pam.workspace_bytes(cfg(nx=1024, ny=256))
+    # state alone: h (P x H f32) and the corrected velocity (Fn x 2 f32)
+    assert big > 262144 * 64 * 4 + 4097 * 1025 * 8
+    assert pam.workspace_bytes(cfg(K=4)) == 0
+    assert pam.workspace_bytes(cfg(nx=0)) == 0
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(nx=0), pam.DNNMG_EINVAL), (dict(ny=-1), pam.DNNMG_EINVAL), (dict(K=0), pam.DNNMG_EINVAL),
+    (dict(K=4), pam.DNNMG_EINVAL), (dict(dt=0.0), pam.DNNMG_EINVAL), (dict(nu=-1.0), pam.DNNMG_EINVAL),
+    (dict(precision=7), pam.DNNMG_EINVAL), (dict(dirichlet=16), pam.DNNMG_EINVAL),
+    (dict(H=48), pam.DNNMG_EUNSUPPORTED), (dict(Hm=40), pam.DNNMG_EUNSUPPORTED),
+])
+def test_create_rejects_bad_config_on_host(bad, code):
+    L = pam.lib()
+    c = cfg(**bad)
+    cxy = np.zeros(2 * (max(c.nx, 1) + 1) * (max(c.ny, 1) + 1))
+    w = np.zeros(100000, dtype=np.float32)
+    out = ctypes.c_void_p(1)
+    rc = L.dnnmg_create(ctypes.byref(c), cxy.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p),
+                        w.size, None, ctypes.byref(out))
+    assert rc == code
+    assert out.value is None
+    assert len(L.dnnmg_last_error()) > 0
+
+
+def test_create_rejects_null_and_size_mismatch():
+    L = pam.lib()
+    c = cfg()
+    s = pam.sizes(4, 3, 2)
+    cxy = np.zeros(2 * s["Nc"])
+    w = np.zeros(pam.weight_count(c), dtype=np.float32)
+    out = ctypes.c_void_p()
+    vp = ctypes.c_void_p
+    assert L.dnnmg_create(ctypes.byref(c), None, w.ctypes.data_as(vp), w.size, None, ctypes.byref(out)) == pam.DNNMG_EINVAL
+    assert L.dnnmg_create(ctypes.byref(c), cxy.ctypes.data_as(vp), None, w.size, None, ctypes.byref(out)) == pam.DNNMG_EINVAL
+    assert L.dnnmg_create(ctypes.byref(c), cxy.ctypes.data_as(vp), w.ctypes.data_as(vp), w.size - 1, None,
+                          ctypes.byref(out)) == pam.DNNMG_EINVAL
+    assert b"n_weights" in L.dnnmg_last_error()
+    cxy[3] = np.nan
+    assert L.dnnmg_create(ctypes.byref(c), cxy.ctypes.data_as(vp), w.ctypes.data_as(vp), w.size, None,
+                          ctypes.byref(out)) == pam.DNNMG_EINVAL
+    assert L.dnnmg_create(None, cxy.ctypes.data_as(vp), w.ctypes.data_as(vp), w.size, None,
+                          ctypes.byref(out)) == pam.DNNMG_EINVAL
+    assert L.dnnmg_create(ctypes.byref(c), cxy.ctypes.data_as(vp), w.ctypes.data_as(vp), w.size, None,
+                          None) == pam.DNNMG_EINVAL
+
+
+def test_calls_on_null_context_fail_cleanly():
+    L = pam.lib()
+    assert L.dnnmg_step(None, None, None, None, None) == pam.DNNMG_EINVAL
+    assert L.dnnmg_restrict_rhs(None, None, None) == pam.DNNMG_EINVAL
+    assert L.dnnmg_defect(None, None, None, None, None) == pam.DNNMG_EINVAL
+    assert L.dnnmg_rhs_restrict(None, None, None, None, None) == pam.DNNMG_EINVAL
+    assert L.dnnmg_get_state(None, None, None, None) == pam.DNNMG_EINVAL
+    assert L.dnnmg_set_state(None, None, None, 0, None) == pam.DNNMG_EINVAL
+    assert L.dnnmg_patch_output(None, None, None) == pam.DNNMG_EINVAL
+    assert L.dnnmg_destroy(None) == pam.DNNMG_EINVAL
+    assert L.dnnmg_step_count(None) == -1
+    out = ctypes.c_void_p()
+    assert L.dnnmg_batch_create(0, ctypes.byref(out)) == pam.DNNMG_EINVAL
+    assert L.dnnmg_batch_create(100000, ctypes.byref(out)) == pam.DNNMG_EINVAL
+    assert L.dnnmg_step_batch(None, None, 1, None, None, None, None) == pam.DNNMG_EINVAL
