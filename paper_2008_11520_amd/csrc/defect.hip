@@ -114,10 +114,6 @@ hipError_t launch_prolong(const FlowArgs &f, int K, float *pv, float *pp, hipStr
 }
 
 // ------------------------------------------------------------------ defect
-// Two-point Gauss abscissae on [0,1]: 1/2 -+ 1/(2 sqrt 3).
-__device__ constexpr float kG0 = 0.21132486540518711775f;
-__device__ constexpr float kG1 = 0.78867513459481288225f;
-
 int blocks_for(int kind, int nx, int ny, int K)
 {
     int n = 1 << K;
@@ -127,170 +123,295 @@ int blocks_for(int kind, int nx, int ny, int K)
         return ((nx + tp - 1) / tp) * ((ny + tp - 1) / tp);
     }
     case kKindNet: return (nx * ny + kNetRows - 1) / kNetRows;
-    case kKindRhs: return (nx * ny + kThreads - 1) / kThreads;
+    case kKindRhs: {
+        int tp = kRhsFine / n;
+        return ((nx + tp - 1) / tp) * ((ny + tp - 1) / tp);
+    }
     case kKindGather: return ((nx + 1) * (ny + 1) + kThreads - 1) / kThreads;
+    case kKindGatherX: return (nx * ny + kGatherXPatches - 1) / kGatherXPatches;
     }
     return 0;
 }
 
+// Per coarse element, the coefficients the defect needs (LDS record):
+// prolongated velocity and pressure as bilinear polynomials in the coarse
+// reference coordinates, v = V0 + V1 xi + V2 eta + V3 xi eta, their fine-level
+// reference derivatives (scaled by 1/n), and the fine-level map derivatives
+// x_s = exn + exyn eta, x_t = eyn + exyn xi (also scaled by 1/n).
+struct CoarseRec {
+    float V0x, V1x, V2x, V3x, V0y, V1y, V2y, V3y;
+    float P0, P1, P2, P3;
+    float exnx, exny, eynx, eyny, exynx, exyny;
+};
+
+// Test-function sums of one component of the element residual: with the
+// Gauss abscissae g0, g1 and 1 - g0 = g1,
+//   R_a += 1/4 sum_q [ N_a(q) m(q) + dN_a/ds(q) Qs(q) + dN_a/dt(q) Qt(q) ]
+// for nodes a = 00, 10, 01, 11 (stride 2 in R: components interleaved).
+__device__ inline void element_sums(const float m[2][2], const float Qs[2][2], const float Qt[2][2], float *R)
+{
+    constexpr float g0 = 0.21132486540518711775f, g1 = 0.78867513459481288225f;
+    const float mb0 = g1 * m[0][0] + g0 * m[0][1], mb1 = g1 * m[1][0] + g0 * m[1][1];   // weight 1 - t
+    const float mt0 = g0 * m[0][0] + g1 * m[0][1], mt1 = g0 * m[1][0] + g1 * m[1][1];   // weight t
+    const float qs0 = Qs[0][0] + Qs[1][0], qs1 = Qs[0][1] + Qs[1][1];                   // sum over s
+    const float qt0 = Qt[0][0] + Qt[0][1], qt1 = Qt[1][0] + Qt[1][1];                   // sum over t
+    const float Sx0 = g1 * qs0 + g0 * qs1, Sx1 = g0 * qs0 + g1 * qs1;
+    const float Sy0 = g1 * qt0 + g0 * qt1, Sy1 = g0 * qt0 + g1 * qt1;
+    R[0] = 0.25f * (g1 * mb0 + g0 * mb1 - Sx0 - Sy0);
+    R[2] = 0.25f * (g0 * mb0 + g1 * mb1 + Sx0 - Sy1);
+    R[4] = 0.25f * (g1 * mt0 + g0 * mt1 - Sx1 + Sy0);
+    R[6] = 0.25f * (g0 * mt0 + g1 * mt1 + Sx1 + Sy1);
+}
+
 template <int K>
-__global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const BatchTable *bt, int write_X)
+__global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const BatchTable *bt)
 {
     constexpr int n = 1 << K;
+    constexpr float inv_n = 1.0f / n;
     constexpr int TP = kTileFine / n;           // patches per tile and direction
     constexpr int NE = kTileFine + 2;           // elements incl. one halo ring
     constexpr int NN = kTileFine + 3;           // nodes of those elements
-    constexpr int NO = kTileFine + 1;           // output nodes (tile nodes)
-    constexpr int nf = (n + 1) * (n + 1);
-    constexpr int nin = 4 * nf + 4;
+    constexpr int CE = TP + 2;                  // coarse elements incl. halo
+    constexpr int EPT = (NE * NE + kThreads - 1) / kThreads;   // elements per thread
 
-    __shared__ float s_vx[NN * NN], s_vy[NN * NN], s_p[NN * NN], s_dx[NN * NN], s_dy[NN * NN];
-    __shared__ float s_R[8][NE * NE];
-    __shared__ float2 s_D[NO * NO];
+    __shared__ CoarseRec s_c[CE * CE];
+    __shared__ float2 s_w[NN * NN];             // (u_prev - P v) / dt at nodes
+    __shared__ float2 s_acc[NN * NN];           // assembled residual at nodes
 
     int blk = blockIdx.x;
     const FlowArgs f = bt ? *batch_flow(bt, kKindDefect, blk) : single;
     const int nx = f.nx, ny = f.ny, NX = nx * n, NY = ny * n;
     const int tiles_x = (nx + TP - 1) / TP;
     const int tx = blk % tiles_x, ty = blk / tiles_x;
+    const int ci0 = tx * TP - 1, cj0 = ty * TP - 1;   // first (halo) coarse element
     const int I0 = tx * kTileFine, J0 = ty * kTileFine;
     const int tid = threadIdx.x;
     const int first = *f.first_flag;
-
-    // 1. nodal values of P v, P p and (u_prev - P v) on the tile's nodes + halo.
-    for (int t = tid; t < NN * NN; t += kThreads) {
-        int I = I0 - 1 + t % NN, J = J0 - 1 + t / NN;
-        float vx = 0.f, vy = 0.f, q = 0.f, dx = 0.f, dy = 0.f;
-        if (I >= 0 && I <= NX && J >= 0 && J <= NY) {
-            prolong_node<K>(f.v, f.p, nx, ny, I, J, vx, vy, q);
-            if (!first) {
-                float2 u = reinterpret_cast<const float2 *>(f.uprev)[(size_t)J * (NX + 1) + I];
-                dx = u.x - vx;
-                dy = u.y - vy;
-            }
-        }
-        s_vx[t] = vx; s_vy[t] = vy; s_p[t] = q; s_dx[t] = dx; s_dy[t] = dy;
-    }
-    __syncthreads();
-
-    // 2. element residuals (4 nodes x 2 components) on the tile + halo ring.
     const float inv_dt = f.inv_dt, nu = f.nu;
-    for (int t = tid; t < NE * NE; t += kThreads) {
-        int le = t % NE, me = t / NE;
-        int eI = I0 - 1 + le, eJ = J0 - 1 + me;
-        float R[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (eI >= 0 && eI < NX && eJ >= 0 && eJ < NY) {
-            int ci = eI >> K, a = eI & (n - 1), cj = eJ >> K, b = eJ & (n - 1);
-            const float *g = f.geo + 6 * ((size_t)cj * nx + ci);
-            float exx = g[0], exy = g[1], eyx = g[2], eyy = g[3], twx = g[4], twy = g[5];
-            int nd[4] = {me * NN + le, me * NN + le + 1, (me + 1) * NN + le, (me + 1) * NN + le + 1};
-            float vx[4], vy[4], pq[4], dx[4], dy[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                vx[k] = s_vx[nd[k]]; vy[k] = s_vy[nd[k]]; pq[k] = s_p[nd[k]];
-                dx[k] = s_dx[nd[k]]; dy[k] = s_dy[nd[k]];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float s = (q & 1) ? kG1 : kG0, tt = (q & 2) ? kG1 : kG0;
-                const float xi = (a + s) * (1.0f / n), eta = (b + tt) * (1.0f / n);
-                // columns of the fine-element Jacobian: d x / d s and d x / d t
-                const float xs = (exx + twx * eta) * (1.0f / n), ys = (exy + twy * eta) * (1.0f / n);
-                const float xt = (eyx + twx * xi) * (1.0f / n), yt = (eyy + twy * xi) * (1.0f / n);
-                const float det = xs * yt - xt * ys;
-                const float idet = 1.0f / det;
-                const float wd = 0.25f * fabsf(det);
-                const float N[4] = {(1.f - s) * (1.f - tt), s * (1.f - tt), (1.f - s) * tt, s * tt};
-                const float dNs[4] = {-(1.f - tt), 1.f - tt, -tt, tt};
-                const float dNt[4] = {-(1.f - s), -s, 1.f - s, s};
-                float dNx[4], dNy[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    dNx[k] = (yt * dNs[k] - ys * dNt[k]) * idet;
-                    dNy[k] = (-xt * dNs[k] + xs * dNt[k]) * idet;
-                }
-                float v0 = 0.f, v1 = 0.f, d0 = 0.f, d1 = 0.f, pp = 0.f;
-                float g00 = 0.f, g01 = 0.f, g10 = 0.f, g11 = 0.f;  // g[c][k] = d v_c / d x_k
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    v0 += N[k] * vx[k]; v1 += N[k] * vy[k];
-                    d0 += N[k] * dx[k]; d1 += N[k] * dy[k];
-                    pp += N[k] * pq[k];
-                    g00 += vx[k] * dNx[k]; g01 += vx[k] * dNy[k];
-                    g10 += vy[k] * dNx[k]; g11 += vy[k] * dNy[k];
-                }
-                const float m0 = inv_dt * d0 - (v0 * g00 + v1 * g01);   // mass - convection, c = x
-                const float m1 = inv_dt * d1 - (v0 * g10 + v1 * g11);   // c = y
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    R[2 * k] += wd * (N[k] * m0 - nu * (dNx[k] * g00 + dNy[k] * g01) + pp * dNx[k]);
-                    R[2 * k + 1] += wd * (N[k] * m1 - nu * (dNx[k] * g10 + dNy[k] * g11) + pp * dNy[k]);
-                }
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < 8; ++r) s_R[r][t] = R[r];
-    }
-    __syncthreads();
 
-    // 3. node sums over the (up to) four elements around each tile node, in
-    //    the order (I-1,J-1), (I,J-1), (I-1,J), (I,J); Dirichlet mask.
-    const unsigned dir = f.dirichlet;
-    for (int t = tid; t < NO * NO; t += kThreads) {
-        int li = t % NO, lj = t / NO;
-        int I = I0 + li, J = J0 + lj;
-        float2 d = make_float2(0.f, 0.f);
-        if (I <= NX && J <= NY) {
-            int e00 = lj * NE + li;                  // element (I-1, J-1) in tile-local numbering
-            d.x = s_R[6][e00] + s_R[4][e00 + 1] + s_R[2][e00 + NE] + s_R[0][e00 + NE + 1];
-            d.y = s_R[7][e00] + s_R[5][e00 + 1] + s_R[3][e00 + NE] + s_R[1][e00 + NE + 1];
-            bool m = ((dir & 1u) && I == 0) || ((dir & 2u) && I == NX) || ((dir & 4u) && J == 0) ||
-                     ((dir & 8u) && J == NY);
-            if (m) d = make_float2(0.f, 0.f);
-            if (f.D_out && (li < kTileFine || I == NX) && (lj < kTileFine || J == NY))
-                reinterpret_cast<float2 *>(f.D_out)[(size_t)J * (NX + 1) + I] = d;
-        }
-        s_D[t] = d;
-    }
-    if (!write_X) return;
-    __syncthreads();
-
-    // 4. network input rows of the tile's patches:
-    //    [P v at the (n+1)^2 patch nodes ; D at the same nodes ; features].
-    for (int t = tid; t < TP * TP * nin; t += kThreads) {
-        int pl = t / nin, fi = t - pl * nin;
-        int pi = tx * TP + pl % TP, pj = ty * TP + pl / TP;
-        if (pi >= nx || pj >= ny) continue;
-        size_t e = (size_t)pj * nx + pi;
-        float val;
-        if (fi < 4 * nf) {
-            int half = fi >= 2 * nf;
-            int r = fi - half * 2 * nf;
-            int l = r >> 1, c = r & 1;
-            int a = l % (n + 1), b = l / (n + 1);
-            int li = (pl % TP) * n + a, lj = (pl / TP) * n + b;   // output-node coordinates
-            if (!half) {
-                int nn = (lj + 1) * NN + (li + 1);
-                val = c ? s_vy[nn] : s_vx[nn];
+    // 1. coarse-element records
+    const float2 *v2 = reinterpret_cast<const float2 *>(f.v);
+    for (int t = tid; t < CE * CE; t += kThreads) {
+        const int ci = ci0 + t % CE, cj = cj0 + t / CE;
+        CoarseRec r;
+        if (ci >= 0 && ci < nx && cj >= 0 && cj < ny) {
+            const int c = cj * (nx + 1) + ci;
+            const float2 a = v2[c], b = v2[c + 1], cc = v2[c + nx + 1], d = v2[c + nx + 2];
+            r.V0x = a.x; r.V1x = b.x - a.x; r.V2x = cc.x - a.x; r.V3x = d.x - b.x - cc.x + a.x;
+            r.V0y = a.y; r.V1y = b.y - a.y; r.V2y = cc.y - a.y; r.V3y = d.y - b.y - cc.y + a.y;
+            if (f.p) {
+                const float pa = f.p[c], pb = f.p[c + 1], pc = f.p[c + nx + 1], pd = f.p[c + nx + 2];
+                r.P0 = pa; r.P1 = pb - pa; r.P2 = pc - pa; r.P3 = pd - pb - pc + pa;
             } else {
-                float2 d = s_D[lj * NO + li];
-                val = c ? d.y : d.x;
+                r.P0 = r.P1 = r.P2 = r.P3 = 0.f;
             }
+            const float *g = f.geo + 6 * ((size_t)cj * nx + ci);
+            r.exnx = g[0] * inv_n; r.exny = g[1] * inv_n;
+            r.eynx = g[2] * inv_n; r.eyny = g[3] * inv_n;
+            r.exynx = g[4] * inv_n; r.exyny = g[5] * inv_n;
         } else {
-            val = f.feat[4 * e + (fi - 4 * nf)];
+            r = CoarseRec{};
         }
-        f.X[e * nin + fi] = val;
+        s_c[t] = r;
+    }
+    __syncthreads();
+
+    // 2. (u_prev - P v) / dt on the tile's nodes + halo (zero before the first
+    //    step); clear the node accumulators
+    for (int t = tid; t < NN * NN; t += kThreads) {
+        const int I = I0 - 1 + t % NN, J = J0 - 1 + t / NN;
+        float2 w = make_float2(0.f, 0.f);
+        if (!first && I >= 0 && I <= NX && J >= 0 && J <= NY) {
+            const int ci = min(I >> K, nx - 1), cj = min(J >> K, ny - 1);
+            const float xi = (I - ci * n) * inv_n, eta = (J - cj * n) * inv_n;
+            const CoarseRec &r = s_c[(cj - cj0) * CE + (ci - ci0)];
+            const float pvx = (r.V0x + r.V1x * xi) + eta * (r.V2x + r.V3x * xi);
+            const float pvy = (r.V0y + r.V1y * xi) + eta * (r.V2y + r.V3y * xi);
+            const float2 u = reinterpret_cast<const float2 *>(f.uprev)[(size_t)J * (NX + 1) + I];
+            w = make_float2((u.x - pvx) * inv_dt, (u.y - pvy) * inv_dt);
+        }
+        s_w[t] = w;
+        s_acc[t] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+
+    // 3. element residuals on the tile + halo ring, kept in registers.  With
+    //    Cof = det J^{-T} (so det grad = Cof grad_ref) and G = Cof^T Cof, at
+    //    each Gauss point:
+    //      mass - convection:  m_c = det (u_prev - v)_c / dt - v . (Cof grad_ref v_c)
+    //      pressure - viscous: Q_c = p Cof^T e_c - (nu / det) G grad_ref v_c
+    //    R_a,c = sum_q w_q [ N_a m_c + grad_ref N_a . Q_c ]   (w_q = 1/4).
+    constexpr float g0 = 0.21132486540518711775f, g1 = 0.78867513459481288225f;
+    float R[EPT][8];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) R[k][q] = 0.f;
+        const int t = tid + k * kThreads;
+        const int le = t % NE, me = t / NE;
+        const int eI = I0 - 1 + le, eJ = J0 - 1 + me;
+        if (t < NE * NE && eI >= 0 && eI < NX && eJ >= 0 && eJ < NY) {
+            const int ci = eI >> K, a = eI & (n - 1), cj = eJ >> K, b = eJ & (n - 1);
+            const CoarseRec &r = s_c[(cj - cj0) * CE + (ci - ci0)];
+            const float xi[2] = {(a + g0) * inv_n, (a + g1) * inv_n};
+            const float eta[2] = {(b + g0) * inv_n, (b + g1) * inv_n};
+            float xsx[2], xsy[2], xtx[2], xty[2];          // x_s(eta_j), x_t(xi_i)
+            float vsx[2], vsy[2], vtx[2], vty[2];          // v_s(eta_j), v_t(xi_i) per component
+            float ax_[2], bx_[2], ay_[2], by_[2], ap[2], bp[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                xsx[j] = r.exnx + r.exynx * eta[j]; xsy[j] = r.exny + r.exyny * eta[j];
+                vsx[j] = (r.V1x + r.V3x * eta[j]) * inv_n; vsy[j] = (r.V1y + r.V3y * eta[j]) * inv_n;
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                xtx[i] = r.eynx + r.exynx * xi[i]; xty[i] = r.eyny + r.exyny * xi[i];
+                vtx[i] = (r.V2x + r.V3x * xi[i]) * inv_n; vty[i] = (r.V2y + r.V3y * xi[i]) * inv_n;
+                ax_[i] = r.V0x + r.V1x * xi[i]; bx_[i] = r.V2x + r.V3x * xi[i];
+                ay_[i] = r.V0y + r.V1y * xi[i]; by_[i] = r.V2y + r.V3y * xi[i];
+                ap[i] = r.P0 + r.P1 * xi[i]; bp[i] = r.P2 + r.P3 * xi[i];
+            }
+            // (u_prev - v)/dt at the Gauss points from the element's nodal values
+            const int n0 = me * NN + le;
+            const float2 w0 = s_w[n0], w1 = s_w[n0 + 1], w2 = s_w[n0 + NN], w3 = s_w[n0 + NN + 1];
+            float wx[2][2], wy[2][2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const float sg = i ? g1 : g0;
+                const float bxv = w0.x + (w1.x - w0.x) * sg, txv = w2.x + (w3.x - w2.x) * sg;
+                const float byv = w0.y + (w1.y - w0.y) * sg, tyv = w2.y + (w3.y - w2.y) * sg;
+                wx[i][0] = bxv + (txv - bxv) * g0; wx[i][1] = bxv + (txv - bxv) * g1;
+                wy[i][0] = byv + (tyv - byv) * g0; wy[i][1] = byv + (tyv - byv) * g1;
+            }
+            const float g11[2] = {xtx[0] * xtx[0] + xty[0] * xty[0], xtx[1] * xtx[1] + xty[1] * xty[1]};
+            const float g22[2] = {xsx[0] * xsx[0] + xsy[0] * xsy[0], xsx[1] * xsx[1] + xsy[1] * xsy[1]};
+            float mx[2][2], my[2][2], Qxs[2][2], Qxt[2][2], Qys[2][2], Qyt[2][2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const float xs = xsx[j], ys = xsy[j], xt = xtx[i], yt = xty[i];
+                    const float det = xs * yt - xt * ys;
+                    const float vxq = ax_[i] + bx_[i] * eta[j], vyq = ay_[i] + by_[i] * eta[j];
+                    const float pq = ap[i] + bp[i] * eta[j];
+                    // det grad v_c = Cof grad_ref v_c
+                    const float dxx = yt * vsx[j] - ys * vtx[i], dxy = -xt * vsx[j] + xs * vtx[i];
+                    const float dyx = yt * vsy[j] - ys * vty[i], dyy = -xt * vsy[j] + xs * vty[i];
+                    mx[i][j] = det * wx[i][j] - (vxq * dxx + vyq * dxy);
+                    my[i][j] = det * wy[i][j] - (vxq * dyx + vyq * dyy);
+                    const float g12 = -(xs * xt + ys * yt);
+                    const float inv = nu * __builtin_amdgcn_rcpf(det);
+                    Qxs[i][j] = pq * yt - inv * (g11[i] * vsx[j] + g12 * vtx[i]);
+                    Qxt[i][j] = -pq * ys - inv * (g12 * vsx[j] + g22[j] * vtx[i]);
+                    Qys[i][j] = -pq * xt - inv * (g11[i] * vsy[j] + g12 * vty[i]);
+                    Qyt[i][j] = pq * xs - inv * (g12 * vsy[j] + g22[j] * vty[i]);
+                }
+            element_sums(mx, Qxs, Qxt, R[k]);
+            element_sums(my, Qys, Qyt, R[k] + 1);
+        }
+    }
+
+    // 4. assembly in four colour rounds: elements of one colour (parity of
+    //    their indices) share no node, so each round adds without conflicts and
+    //    every node receives its four element contributions in a fixed order.
+#pragma unroll
+    for (int colour = 0; colour < 4; ++colour) {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int t = tid + k * kThreads;
+            const int le = t % NE, me = t / NE;
+            if (t < NE * NE && (((le + 1) & 1) | (((me + 1) & 1) << 1)) == colour) {
+                const int n0 = me * NN + le;
+                float2 *q0 = &s_acc[n0], *q1 = &s_acc[n0 + 1], *q2 = &s_acc[n0 + NN], *q3 = &s_acc[n0 + NN + 1];
+                q0->x += R[k][0]; q0->y += R[k][1];
+                q1->x += R[k][2]; q1->y += R[k][3];
+                q2->x += R[k][4]; q2->y += R[k][5];
+                q3->x += R[k][6]; q3->y += R[k][7];
+            }
+        }
+        __syncthreads();
+    }
+
+    // 5. Dirichlet mask; the tile writes the nodes it owns.
+    const unsigned dir = f.dirichlet;
+    constexpr int NO = kTileFine + 1;
+    for (int t = tid; t < NO * NO; t += kThreads) {
+        const int li = t % NO, lj = t / NO;
+        const int I = I0 + li, J = J0 + lj;
+        if (I > NX || J > NY || (li == kTileFine && I != NX) || (lj == kTileFine && J != NY)) continue;
+        float2 d = s_acc[(lj + 1) * NN + li + 1];
+        const bool m = ((dir & 1u) && I == 0) || ((dir & 2u) && I == NX) || ((dir & 4u) && J == 0) ||
+                       ((dir & 8u) && J == NY);
+        if (m) d = make_float2(0.f, 0.f);
+        reinterpret_cast<float2 *>(f.D)[(size_t)J * (NX + 1) + I] = d;
     }
 }
 
-hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, int write_X,
-                         hipStream_t s)
+// Network input rows X[e] = [P v at the (n+1)^2 patch nodes (x,y interleaved,
+// x fastest) ; D at the same nodes ; hx, hy, hx/hy, area], FP32 or BF16.
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_gather_x(FlowArgs single, const BatchTable *bt)
+{
+    constexpr int n = 1 << K, nf = (n + 1) * (n + 1), nin = 4 * nf + 4;
+    constexpr float inv_n = 1.0f / n;
+    int blk = blockIdx.x;
+    const FlowArgs f = bt ? *batch_flow(bt, kKindGatherX, blk) : single;
+    const int nx = f.nx, P = f.nx * f.ny, NX = nx * n;
+    const float2 *v2 = reinterpret_cast<const float2 *>(f.v);
+    const float2 *D2 = reinterpret_cast<const float2 *>(f.D);
+    for (int t = threadIdx.x; t < kGatherXPatches * (nf + 1); t += kThreads) {
+        const int pl = t / (nf + 1), l = t - pl * (nf + 1);
+        const int e = blk * kGatherXPatches + pl;
+        if (e >= P) continue;
+        const int pi = e % nx, pj = e / nx;
+        if (l == nf) {
+            const float4 ft = reinterpret_cast<const float4 *>(f.feat)[e];
+            if (f.x_bf16) {
+                __bf16 *o = reinterpret_cast<__bf16 *>(f.X) + (size_t)e * nin + 4 * nf;
+                o[0] = (__bf16)ft.x; o[1] = (__bf16)ft.y; o[2] = (__bf16)ft.z; o[3] = (__bf16)ft.w;
+            } else {
+                *reinterpret_cast<float4 *>(f.X + (size_t)e * nin + 4 * nf) = ft;
+            }
+            continue;
+        }
+        const int a = l % (n + 1), b = l / (n + 1);
+        const int c = pj * (nx + 1) + pi;
+        const float2 c00 = v2[c], c10 = v2[c + 1], c01 = v2[c + nx + 1], c11 = v2[c + nx + 2];
+        const float xi = a * inv_n, eta = b * inv_n;
+        const float pvx = (c00.x + (c10.x - c00.x) * xi) + eta * ((c01.x - c00.x) + (c11.x - c10.x - c01.x + c00.x) * xi);
+        const float pvy = (c00.y + (c10.y - c00.y) * xi) + eta * ((c01.y - c00.y) + (c11.y - c10.y - c01.y + c00.y) * xi);
+        const float2 d = D2[(size_t)(pj * n + b) * (NX + 1) + pi * n + a];
+        if (f.x_bf16) {
+            __bf16 *o = reinterpret_cast<__bf16 *>(f.X) + (size_t)e * nin;
+            o[2 * l] = (__bf16)pvx; o[2 * l + 1] = (__bf16)pvy;
+            o[2 * nf + 2 * l] = (__bf16)d.x; o[2 * nf + 2 * l + 1] = (__bf16)d.y;
+        } else {
+            float *o = f.X + (size_t)e * nin;
+            *reinterpret_cast<float2 *>(o + 2 * l) = make_float2(pvx, pvy);
+            *reinterpret_cast<float2 *>(o + 2 * nf + 2 * l) = d;
+        }
+    }
+}
+
+hipError_t launch_gather_x(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, hipStream_t s)
 {
     dim3 g(nblocks), b(kThreads);
     switch (K) {
-    case 1: hipLaunchKernelGGL(k_defect<1>, g, b, 0, s, f, bt, write_X); break;
-    case 2: hipLaunchKernelGGL(k_defect<2>, g, b, 0, s, f, bt, write_X); break;
-    case 3: hipLaunchKernelGGL(k_defect<3>, g, b, 0, s, f, bt, write_X); break;
+    case 1: hipLaunchKernelGGL(k_gather_x<1>, g, b, 0, s, f, bt); break;
+    case 2: hipLaunchKernelGGL(k_gather_x<2>, g, b, 0, s, f, bt); break;
+    case 3: hipLaunchKernelGGL(k_gather_x<3>, g, b, 0, s, f, bt); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, hipStream_t s)
+{
+    dim3 g(nblocks), b(kThreads);
+    switch (K) {
+    case 1: hipLaunchKernelGGL(k_defect<1>, g, b, 0, s, f, bt); break;
+    case 2: hipLaunchKernelGGL(k_defect<2>, g, b, 0, s, f, bt); break;
+    case 3: hipLaunchKernelGGL(k_defect<3>, g, b, 0, s, f, bt); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

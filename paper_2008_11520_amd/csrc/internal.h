@@ -7,7 +7,8 @@
 namespace dnnmg {
 
 constexpr int kThreads = 256;     // every kernel: 4 wave64s per workgroup
-constexpr int kTileFine = 16;     // defect tile: 16 x 16 fine elements
+constexpr int kTileFine = 32;     // defect tile: 32 x 32 fine elements
+constexpr int kRhsFine = 32;      // averaging / rhs tile: 32 x 32 fine elements
 constexpr int kNetRows = 64;      // GRU/MLP: patches per workgroup
 constexpr int kMaxBatch = 256;    // flows per batched launch
 
@@ -16,7 +17,7 @@ constexpr int kMaxBatch = 256;    // flows per batched launch
 struct FlowArgs {
     int nx, ny;
     unsigned dirichlet;
-    int pad0;
+    int x_bf16;            // network input stored as BF16 (BF16 operand form)
     float inv_dt, nu;
     double inv_dt64;
     const float *v;        // (ny+1)(nx+1) x 2
@@ -27,11 +28,11 @@ struct FlowArgs {
     int *first_flag;       // device: nonzero before the first step (then u_prev := P v)
     float *h;              // P x H
     float *uprev;          // Fn x 2
-    float *X;              // P x nin
+    float *X;              // P x nin (FP32, or BF16 when x_bf16)
     float *dpatch;         // P x nout
     double *part;          // P x 8: per-patch rhs contribution to its 4 corners
     float *dbar_out;       // optional Fn x 2
-    float *D_out;          // optional Fn x 2 (stage)
+    float *D;              // Fn x 2: defect at the fine nodes (written by the defect kernel)
     const float *dbar_in;  // stage: given fine correction (rhs/restrict alone)
     double *bL;            // restricted rhs output (gather)
 };
@@ -56,7 +57,8 @@ struct RhsTables {
 
 // Device table for batched launches: per kernel kind, a block prefix over
 // flows, then the flows.
-enum { kKindDefect = 0, kKindNet = 1, kKindRhs = 2, kKindGather = 3, kKinds = 4 };
+enum { kKindDefect = 0, kKindNet = 1, kKindRhs = 2, kKindGather = 3, kKindGatherX = 4, kKinds = 5 };
+constexpr int kGatherXPatches = 16;  // patches per block of the network-input gather
 struct BatchTable {
     int nflows;
     int pad[3];
@@ -71,10 +73,15 @@ int blocks_for(int kind, int nx, int ny, int K);
 hipError_t launch_geometry(const double *cxy, int nx, int ny, float *geo, double *geo64,
                            float *feat, int *bad, hipStream_t s);
 hipError_t launch_prolong(const FlowArgs &f, int K, float *pv, float *pp, hipStream_t s);
-hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K,
-                         int write_X, hipStream_t s);
+hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, hipStream_t s);
+hipError_t launch_gather_x(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, hipStream_t s);
+// Whether the network kernel for this shape reads a materialised input X
+// (otherwise it assembles its input from D itself).
+bool net_needs_x(int prec, int K, int H, int Hm);
 hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net,
                       hipStream_t s);
+// Blocks of the network launch (persistent kernels use fewer than row tiles).
+int net_blocks(const NetArgs &net, int row_tiles);
 hipError_t net_set_attributes(int prec, int H);
 size_t net_lds_bytes(const NetArgs &net);
 hipError_t launch_rhs(const FlowArgs &f, const BatchTable *bt, int nblocks, int K,

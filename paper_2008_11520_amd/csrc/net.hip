@@ -44,6 +44,11 @@ template <> struct Op<0> {
     __device__ static inline T cvt(float x) { return x; }
     // A fragment from FP32 global memory (4 contiguous values).
     __device__ static inline Frag load_f32(const float *p) { return *reinterpret_cast<const f4 *>(p); }
+    // A fragment of the network input (stored FP32 in this form).
+    __device__ static inline Frag load_x(const void *X, size_t off)
+    {
+        return *reinterpret_cast<const f4 *>(reinterpret_cast<const float *>(X) + off);
+    }
 };
 
 // BF16 operands: one 16x16x32 MFMA per 32-wide k-chunk.
@@ -64,9 +69,18 @@ template <> struct Op<1> {
         r[4] = (__bf16)w.x; r[5] = (__bf16)w.y; r[6] = (__bf16)w.z; r[7] = (__bf16)w.w;
         return r;
     }
+    // A fragment of the network input (stored BF16 in this form).
+    __device__ static inline Frag load_x(const void *X, size_t off)
+    {
+        return *reinterpret_cast<const bf8 *>(reinterpret_cast<const __bf16 *>(X) + off);
+    }
 };
 
-__device__ inline float sigmoid(float t) { return 1.0f / (1.0f + expf(-t)); }
+// Logistic function and tanh from the hardware exponential and reciprocal
+// (tanh x = 1 - 2 / (1 + e^{2x})); absolute error ~1e-7, which is what the
+// state update h' = z h + (1 - z) tanh(.) needs.
+__device__ inline float sigmoid(float t) { return __builtin_amdgcn_rcpf(1.0f + __expf(-t)); }
+__device__ inline float fast_tanh(float t) { return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * t)); }
 
 template <int PREC, int H>
 __global__ __launch_bounds__(kThreads) void k_net(FlowArgs single, const BatchTable *bt, NetArgs net)
@@ -109,7 +123,7 @@ __global__ __launch_bounds__(kThreads) void k_net(FlowArgs single, const BatchTa
     for (int kc = 0; kc < kc1; ++kc) {
         const int k0 = kc * KC + lq * KQ;
         Frag a;
-        if (aok && k0 < nin) a = O::load_f32(f.X + (size_t)arow * nin + k0);
+        if (aok && k0 < nin) a = O::load_x(f.X, (size_t)arow * nin + k0);
         else if (aok && k0 < nin + H) a = O::load_f32(f.h + (size_t)arow * H + (k0 - nin));
         else {
 #pragma unroll
@@ -154,7 +168,7 @@ __global__ __launch_bounds__(kThreads) void k_net(FlowArgs single, const BatchTa
         for (int e = 0; e < 4; ++e) {
             const int row = rbase + 4 * lq + e, k = 16 * t + li;
             const float z = az[t][e];
-            const float hh = tanhf(ah[t][e] + au[t][e]);
+            const float hh = fast_tanh(ah[t][e] + au[t][e]);
             const float hn = z * hold[t][e] + (1.0f - z) * hh;
             if (row < P) f.h[(size_t)row * H + k] = hn;
             sHp[wave][(4 * lq + e) * LDH + k] = O::cvt(hn);
@@ -205,6 +219,215 @@ __global__ __launch_bounds__(kThreads) void k_net(FlowArgs single, const BatchTa
     }
 }
 
+
+// Persistent BF16 kernel for H = 64 (and Hm 0 or 64).  Eight waves: wave w
+// owns hidden tile w % 4 for row tiles 2 (w / 4) and 2 (w / 4) + 1 of each
+// 64-patch tile, and keeps that hidden tile's weight fragments (three gates,
+// U_h, M1 and M2 / M) in registers for the whole launch.  The workgroup loops
+// over 64-patch row tiles staged through LDS, so each weight fragment is read
+// from memory once per workgroup.
+constexpr int kNetH64Threads = 512;
+
+template <int K>
+__global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, const BatchTable *bt, NetArgs net,
+                                                               int ntiles)
+{
+    typedef Op<1> O;
+    constexpr int H = 64, KC = 32, KQ = 8, HT = 4, RTW = 2;
+    constexpr int n = 1 << K, nf = (n + 1) * (n + 1), nin = 4 * nf + 4, nout = 2 * nf;
+    constexpr int KC1 = (nin + H + KC - 1) / KC;
+    constexpr int LDA = KC1 * KC + 8;          // +16 bytes per row
+    constexpr int LDH = H + 8;
+    constexpr int OT = (nout + 15) / 16;       // output tiles (<= 4 here)
+    constexpr int PADK = KC1 * KC - nin - H;
+    static_assert(OT <= 4, "one output tile per hidden-tile slot");
+
+    __shared__ __align__(16) __bf16 sA[64 * LDA];
+    constexpr int LDS32 = H + 4;              // FP32 state rows, padded against bank conflicts
+    __shared__ __align__(16) float sH[64 * LDS32];
+    __shared__ __align__(16) __bf16 sR[64 * LDH];
+    __shared__ __align__(16) __bf16 sHp[64 * LDH];
+    __shared__ __align__(16) __bf16 sAm[64 * LDH];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lq = lane >> 4;
+    const int ht = wave & 3, rt0 = RTW * (wave >> 2);
+    const int Hm = net.Hm;
+    const bf8 *B1 = reinterpret_cast<const bf8 *>(net.B1);
+    const bf8 *B2 = reinterpret_cast<const bf8 *>(net.B2);
+    const bf8 *B3 = reinterpret_cast<const bf8 *>(net.B3);
+    const bf8 *B4 = reinterpret_cast<const bf8 *>(net.B4);
+
+    bf8 w1[3][KC1], w2[H / KC], w3[H / KC], w4[H / KC];
+#pragma unroll
+    for (int g = 0; g < 3; ++g)
+#pragma unroll
+        for (int kc = 0; kc < KC1; ++kc) w1[g][kc] = B1[((g * HT + ht) * KC1 + kc) * 64 + lane];
+#pragma unroll
+    for (int kc = 0; kc < H / KC; ++kc) {
+        w2[kc] = B2[(ht * (H / KC) + kc) * 64 + lane];
+        w3[kc] = (Hm > 0 || ht < OT) ? B3[(ht * (H / KC) + kc) * 64 + lane] : bf8{};
+        w4[kc] = (Hm > 0 && ht < OT) ? B4[(ht * (H / KC) + kc) * 64 + lane] : bf8{};
+    }
+    const int col = 16 * ht + li;              // hidden unit / output column of this lane
+
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        int blk = tile;
+        const FlowArgs ff = bt ? *batch_flow(bt, kKindNet, blk) : single;
+        const int P = ff.nx * ff.ny;
+        const int row0 = blk * 64;
+        const int nrows = min(64, P - row0);
+        float *hg = ff.h + (size_t)row0 * H;
+        float *dp = ff.dpatch + (size_t)row0 * nout;
+        const int nx = ff.nx, NX = nx * n;
+        const float2 *v2 = reinterpret_cast<const float2 *>(ff.v);
+        const float2 *D2 = reinterpret_cast<const float2 *>(ff.D);
+
+        __syncthreads();   // the previous tile's readers of LDS are done
+        // ---- stage the network input [P v ; D ; features] (BF16) ...
+        for (int t = tid; t < 64 * (nf + 1); t += kNetH64Threads) {
+            const int r = t / (nf + 1), l = t - r * (nf + 1);
+            __bf16 *o = &sA[r * LDA];
+            if (r >= nrows) {
+                if (l < nf) {
+                    o[2 * l] = o[2 * l + 1] = o[2 * nf + 2 * l] = o[2 * nf + 2 * l + 1] = (__bf16)0.f;
+                } else {
+                    o[4 * nf] = o[4 * nf + 1] = o[4 * nf + 2] = o[4 * nf + 3] = (__bf16)0.f;
+                }
+                continue;
+            }
+            const int e = row0 + r, pi = e % nx, pj = e / nx;
+            if (l == nf) {
+                const f4 ft = reinterpret_cast<const f4 *>(ff.feat)[e];
+                o[4 * nf] = (__bf16)ft.x; o[4 * nf + 1] = (__bf16)ft.y;
+                o[4 * nf + 2] = (__bf16)ft.z; o[4 * nf + 3] = (__bf16)ft.w;
+                continue;
+            }
+            const int a = l % (n + 1), b = l / (n + 1);
+            const int c = pj * (nx + 1) + pi;
+            const float2 c00 = v2[c], c10 = v2[c + 1], c01 = v2[c + nx + 1], c11 = v2[c + nx + 2];
+            const float xi = a * (1.0f / n), eta = b * (1.0f / n);
+            const float pvx = (c00.x + (c10.x - c00.x) * xi) + eta * ((c01.x - c00.x) + (c11.x - c10.x - c01.x + c00.x) * xi);
+            const float pvy = (c00.y + (c10.y - c00.y) * xi) + eta * ((c01.y - c00.y) + (c11.y - c10.y - c01.y + c00.y) * xi);
+            const float2 d = D2[(size_t)(pj * n + b) * (NX + 1) + pi * n + a];
+            o[2 * l] = (__bf16)pvx; o[2 * l + 1] = (__bf16)pvy;
+            o[2 * nf + 2 * l] = (__bf16)d.x; o[2 * nf + 2 * l + 1] = (__bf16)d.y;
+        }
+        // ... and the state h (FP32 copy for the update, BF16 operand copy)
+        for (int t = tid; t < 64 * (H / 4); t += kNetH64Threads) {
+            const int r = t / (H / 4), k = (t - r * (H / 4)) * 4;
+            f4 v = r < nrows ? *reinterpret_cast<const f4 *>(hg + (size_t)r * H + k) : f4{0.f, 0.f, 0.f, 0.f};
+            *reinterpret_cast<f4 *>(&sH[r * LDS32 + k]) = v;
+            __bf16 *a = &sA[r * LDA + nin + k];
+            a[0] = (__bf16)v.x; a[1] = (__bf16)v.y; a[2] = (__bf16)v.z; a[3] = (__bf16)v.w;
+        }
+        if (PADK > 0)
+            for (int t = tid; t < 64 * PADK; t += kNetH64Threads) sA[(t / PADK) * LDA + nin + H + t % PADK] = (__bf16)0.f;
+        __syncthreads();
+
+        // ---- phase 1: the three gates of this wave's hidden tile
+        f4 az[RTW], ar[RTW], ah[RTW];
+#pragma unroll
+        for (int q = 0; q < RTW; ++q) az[q] = ar[q] = ah[q] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < KC1; ++kc)
+#pragma unroll
+            for (int q = 0; q < RTW; ++q) {
+                const bf8 a = *reinterpret_cast<const bf8 *>(&sA[(16 * (rt0 + q) + li) * LDA + kc * KC + lq * KQ]);
+                az[q] = O::mma(az[q], a, w1[0][kc]);
+                ar[q] = O::mma(ar[q], a, w1[1][kc]);
+                ah[q] = O::mma(ah[q], a, w1[2][kc]);
+            }
+        float hold[RTW][4];
+#pragma unroll
+        for (int q = 0; q < RTW; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = 16 * (rt0 + q) + 4 * lq + e;
+                hold[q][e] = sH[r * LDS32 + col];
+                az[q][e] = sigmoid(az[q][e]);
+                sR[r * LDH + col] = (__bf16)(sigmoid(ar[q][e]) * hold[q][e]);
+            }
+        __syncthreads();
+
+        // ---- phase 2: U_h (r*h); new state
+#pragma unroll
+        for (int q = 0; q < RTW; ++q) {
+            f4 au = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < H / KC; ++kc) {
+                const bf8 a = *reinterpret_cast<const bf8 *>(&sR[(16 * (rt0 + q) + li) * LDH + kc * KC + lq * KQ]);
+                au = O::mma(au, a, w2[kc]);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = 16 * (rt0 + q) + 4 * lq + e;
+                const float z = az[q][e];
+                const float hn = z * hold[q][e] + (1.0f - z) * fast_tanh(ah[q][e] + au[e]);
+                if (r < nrows) hg[(size_t)r * H + col] = hn;
+                sHp[r * LDH + col] = (__bf16)hn;
+            }
+        }
+        __syncthreads();
+
+        // ---- MLP head
+        const __bf16 *src = sHp;
+        if (Hm > 0) {
+#pragma unroll
+            for (int q = 0; q < RTW; ++q) {
+                f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kc = 0; kc < H / KC; ++kc) {
+                    const bf8 a = *reinterpret_cast<const bf8 *>(&sHp[(16 * (rt0 + q) + li) * LDH + kc * KC + lq * KQ]);
+                    acc = O::mma(acc, a, w3[kc]);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    sAm[(16 * (rt0 + q) + 4 * lq + e) * LDH + col] = (__bf16)fmaxf(acc[e], 0.f);
+            }
+            __syncthreads();
+            src = sAm;
+        }
+        if (ht < OT) {
+#pragma unroll
+            for (int q = 0; q < RTW; ++q) {
+                f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kc = 0; kc < H / KC; ++kc) {
+                    const bf8 a = *reinterpret_cast<const bf8 *>(&src[(16 * (rt0 + q) + li) * LDH + kc * KC + lq * KQ]);
+                    acc = O::mma(acc, a, Hm > 0 ? w4[kc] : w3[kc]);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = 16 * (rt0 + q) + 4 * lq + e;
+                    if (r < nrows && col < nout) dp[(size_t)r * nout + col] = acc[e];
+                }
+            }
+        }
+    }
+}
+
+static int g_num_cus = 0;
+
+static bool use_h64(int prec, int K, int H, int Hm) { return prec == 1 && H == 64 && K <= 2 && (Hm == 0 || Hm == 64); }
+static bool use_h64(const NetArgs &net) { return use_h64(net.prec, net.K, net.H, net.Hm); }
+
+bool net_needs_x(int prec, int K, int H, int Hm) { return !use_h64(prec, K, H, Hm); }
+
+int net_blocks(const NetArgs &net, int row_tiles)
+{
+    if (use_h64(net)) {
+        if (g_num_cus == 0) {
+            int dev = 0;
+            (void)hipGetDevice(&dev);
+            if (hipDeviceGetAttribute(&g_num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+                g_num_cus = 256;
+        }
+        return row_tiles < g_num_cus ? row_tiles : g_num_cus;
+    }
+    return row_tiles;
+}
+
 template <int PREC, int H>
 static hipError_t launch_net_t(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net,
                                hipStream_t s)
@@ -213,8 +436,14 @@ static hipError_t launch_net_t(const FlowArgs &f, const BatchTable *bt, int nblo
     return hipGetLastError();
 }
 
-hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net, hipStream_t s)
+hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int ntiles, const NetArgs &net, hipStream_t s)
 {
+    const int nblocks = net_blocks(net, ntiles);
+    if (use_h64(net)) {
+        if (net.K == 1) hipLaunchKernelGGL(k_net_h64<1>, dim3(nblocks), dim3(kNetH64Threads), 0, s, f, bt, net, ntiles);
+        else hipLaunchKernelGGL(k_net_h64<2>, dim3(nblocks), dim3(kNetH64Threads), 0, s, f, bt, net, ntiles);
+        return hipGetLastError();
+    }
     if (net.prec == 0) {
         if (net.H == 32) return launch_net_t<0, 32>(f, bt, nblocks, net, s);
         if (net.H == 64) return launch_net_t<0, 64>(f, bt, nblocks, net, s);

@@ -29,92 +29,158 @@ __device__ inline bool dirichlet_node(unsigned dir, int I, int J, int NX, int NY
     return ((dir & 1u) && I == 0) || ((dir & 2u) && I == NX) || ((dir & 4u) && J == 0) || ((dir & 8u) && J == NY);
 }
 
-// from_patches = 1: average f.dpatch (the step); 0: take f.dbar_in (stage).
+// One workgroup per tile of kRhsFine x kRhsFine fine elements (TP x TP patches).
+// from_patches = 1: average f.dpatch and store the corrected velocity (the
+// step); 0: take the correction from f.dbar_in (stage, state untouched).
 template <int K, int FROM_PATCHES>
 __global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTable *bt, RhsTables tab)
 {
     constexpr int n = 1 << K;
     constexpr int nf = (n + 1) * (n + 1);
     constexpr int nout = 2 * nf;
+    constexpr int TP = kRhsFine / n;          // patches per tile and direction
+    constexpr int HP = TP + 2;                // with a ring of neighbour patches
+    constexpr int NO = kRhsFine + 1;          // tile nodes per direction
+    constexpr int NCH = (kThreads / (TP * TP * 4)) > 0 ? kThreads / (TP * TP * 4) : 1;  // node chunks per corner
+
+    __shared__ float s_d[FROM_PATCHES ? HP * HP * nout : 1];
+    __shared__ float2 s_dbar[NO * NO];
+    __shared__ float2 s_v[(TP + 1) * (TP + 1)];
+    __shared__ double s_G[3 * 4 * nf];
+    __shared__ double s_red[NCH > 1 ? kThreads * 2 : 1];
+
     int blk = blockIdx.x;
     const FlowArgs f = bt ? *batch_flow(bt, kKindRhs, blk) : single;
     const int nx = f.nx, ny = f.ny, NX = nx * n, NY = ny * n;
-    const int e = blk * kThreads + threadIdx.x;
+    const int tiles_x = (nx + TP - 1) / TP;
+    const int tx = blk % tiles_x, ty = blk / tiles_x;
+    const int pi0 = tx * TP, pj0 = ty * TP;    // first patch of the tile
+    const int I0 = pi0 * n, J0 = pj0 * n;      // first fine node
+    const int tid = threadIdx.x;
     // The step's defect has already read the first-step flag (stream order).
-    if (FROM_PATCHES && e == 0) *f.first_flag = 0;
-    if (e >= nx * ny) return;
-    const int pi = e % nx, pj = e / nx;
-    const double d0 = f.geo64[4 * (size_t)e], d1 = f.geo64[4 * (size_t)e + 1], d2 = f.geo64[4 * (size_t)e + 2];
+    if (FROM_PATCHES && blk == 0 && tid == 0) *f.first_flag = 0;
+
+    // ---- stage: moment table, coarse corner velocities, per-patch outputs
+    for (int t = tid; t < 3 * 4 * nf; t += kThreads) s_G[t] = tab.G[t];
     const float2 *v2 = reinterpret_cast<const float2 *>(f.v);
-    const int c00 = pj * (nx + 1) + pi;
-    const float2 vc[4] = {v2[c00], v2[c00 + 1], v2[c00 + nx + 1], v2[c00 + nx + 2]};
-
-    double acc[4][2];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c][0] = acc[c][1] = 0.0;
-
-    for (int b = 0; b <= n; ++b) {
-        for (int a = 0; a <= n; ++a) {
-            const int l = b * (n + 1) + a;
-            const int I = pi * n + a, J = pj * n + b;
-            float dx, dy;
-            if (FROM_PATCHES) {
-                // containing patches in (row, column) order, as the mean is defined
-                const int qj0 = (b == 0 && pj > 0) ? pj - 1 : pj, qj1 = (b == n && pj < ny - 1) ? pj + 1 : pj;
-                const int qi0 = (a == 0 && pi > 0) ? pi - 1 : pi, qi1 = (a == n && pi < nx - 1) ? pi + 1 : pi;
-                float sx = 0.f, sy = 0.f;
-                int cnt = 0;
-                for (int qj = qj0; qj <= qj1; ++qj)
-                    for (int qi = qi0; qi <= qi1; ++qi) {
-                        const int ll = (b - (qj - pj) * n) * (n + 1) + (a - (qi - pi) * n);
-                        const float *dq = f.dpatch + ((size_t)qj * nx + qi) * nout + 2 * ll;
-                        sx += dq[0];
-                        sy += dq[1];
-                        ++cnt;
-                    }
-                const float inv = cnt == 1 ? 1.0f : (cnt == 2 ? 0.5f : 0.25f);
-                dx = sx * inv;
-                dy = sy * inv;
-                if (dirichlet_node<K>(f.dirichlet, I, J, NX, NY)) dx = dy = 0.f;
-                const bool owned = (a < n || pi == nx - 1) && (b < n || pj == ny - 1);
-                if (owned) {
-                    const size_t fi = (size_t)J * (NX + 1) + I;
-                    const float xi = a * (1.0f / n), eta = b * (1.0f / n);
-                    const float n00 = (1.f - xi) * (1.f - eta), n10 = xi * (1.f - eta), n01 = (1.f - xi) * eta,
-                                n11 = xi * eta;
-                    const float pvx = n00 * vc[0].x + n10 * vc[1].x + n01 * vc[2].x + n11 * vc[3].x;
-                    const float pvy = n00 * vc[0].y + n10 * vc[1].y + n01 * vc[2].y + n11 * vc[3].y;
-                    reinterpret_cast<float2 *>(f.uprev)[fi] = make_float2(pvx + dx, pvy + dy);
-                    if (f.dbar_out) reinterpret_cast<float2 *>(f.dbar_out)[fi] = make_float2(dx, dy);
-                }
-            } else {
-                const float2 d = reinterpret_cast<const float2 *>(f.dbar_in)[(size_t)J * (NX + 1) + I];
-                dx = d.x;
-                dy = d.y;
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const double w = d0 * tab.G[(0 * 4 + c) * nf + l] + d1 * tab.G[(1 * 4 + c) * nf + l] +
-                                 d2 * tab.G[(2 * 4 + c) * nf + l];
-                acc[c][0] += w * (double)dx;
-                acc[c][1] += w * (double)dy;
-            }
+    for (int t = tid; t < (TP + 1) * (TP + 1); t += kThreads) {
+        int ci = pi0 + t % (TP + 1), cj = pj0 + t / (TP + 1);
+        s_v[t] = (ci <= nx && cj <= ny) ? v2[(size_t)cj * (nx + 1) + ci] : make_float2(0.f, 0.f);
+    }
+    if (FROM_PATCHES) {
+        // per-patch outputs of the tile and its ring of neighbours, 8 bytes at a time
+        float2 *sd2 = reinterpret_cast<float2 *>(s_d);
+        for (int t = tid; t < HP * HP * nf; t += kThreads) {
+            const int hp = t / nf, o = t - hp * nf;
+            const int qi = pi0 - 1 + hp % HP, qj = pj0 - 1 + hp / HP;
+            sd2[t] = (qi >= 0 && qi < nx && qj >= 0 && qj < ny)
+                         ? reinterpret_cast<const float2 *>(f.dpatch)[((size_t)qj * nx + qi) * nf + o]
+                         : make_float2(0.f, 0.f);
         }
     }
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc) {
-            const double w = d0 * tab.M[(0 * 4 + c) * 4 + cc] + d1 * tab.M[(1 * 4 + c) * 4 + cc] +
-                             d2 * tab.M[(2 * 4 + c) * 4 + cc];
-            acc[c][0] += w * (double)vc[cc].x;
-            acc[c][1] += w * (double)vc[cc].y;
+    __syncthreads();
+
+    // ---- node pass: mean over the containing patches (row-major order, as
+    //      the mean is defined), Dirichlet mask, corrected velocity.
+    for (int t = tid; t < NO * NO; t += kThreads) {
+        const int li = t % NO, lj = t / NO;
+        const int I = I0 + li, J = J0 + lj;
+        float2 d = make_float2(0.f, 0.f);
+        if (I <= NX && J <= NY) {
+            if (FROM_PATCHES) {
+                // the node's own (left/lower-owner) patch, plus the patches to the
+                // left, below and diagonal when the node lies on their edges;
+                // summed in row-major patch order
+                const int pI = min(I >> K, nx - 1), pJ = min(J >> K, ny - 1);
+                const int a = I - pI * n, b = J - pJ * n;
+                const bool lft = a == 0 && pI > 0, low = b == 0 && pJ > 0;
+                const float2 *sd2 = reinterpret_cast<const float2 *>(s_d);
+                const int hb = (pJ - pj0 + 1) * HP + (pI - pi0 + 1);   // own patch in the staged ring
+                float2 acc = make_float2(0.f, 0.f);
+                if (lft && low) { const float2 q = sd2[(hb - HP - 1) * nf + n * (n + 1) + n]; acc.x += q.x; acc.y += q.y; }
+                if (low) { const float2 q = sd2[(hb - HP) * nf + n * (n + 1) + a]; acc.x += q.x; acc.y += q.y; }
+                if (lft) { const float2 q = sd2[(hb - 1) * nf + b * (n + 1) + n]; acc.x += q.x; acc.y += q.y; }
+                { const float2 q = sd2[hb * nf + b * (n + 1) + a]; acc.x += q.x; acc.y += q.y; }
+                const float inv = (lft && low) ? 0.25f : ((lft || low) ? 0.5f : 1.0f);
+                d = make_float2(acc.x * inv, acc.y * inv);
+                if (dirichlet_node<K>(f.dirichlet, I, J, NX, NY)) d = make_float2(0.f, 0.f);
+                const bool owned = (li < kRhsFine || I == NX) && (lj < kRhsFine || J == NY);
+                if (owned) {
+                    // P v at the node from the corners of its (left/lower) patch
+                    const float xi = a * (1.0f / n), eta = b * (1.0f / n);
+                    const int c = (pJ - pj0) * (TP + 1) + (pI - pi0);
+                    const float2 v00 = s_v[c], v10 = s_v[c + 1], v01 = s_v[c + TP + 1], v11 = s_v[c + TP + 2];
+                    const float n00 = (1.f - xi) * (1.f - eta), n10 = xi * (1.f - eta), n01 = (1.f - xi) * eta,
+                                n11 = xi * eta;
+                    const float pvx = n00 * v00.x + n10 * v10.x + n01 * v01.x + n11 * v11.x;
+                    const float pvy = n00 * v00.y + n10 * v10.y + n01 * v01.y + n11 * v11.y;
+                    const size_t fi = (size_t)J * (NX + 1) + I;
+                    reinterpret_cast<float2 *>(f.uprev)[fi] = make_float2(pvx + d.x, pvy + d.y);
+                    if (f.dbar_out) reinterpret_cast<float2 *>(f.dbar_out)[fi] = d;
+                }
+            } else {
+                d = reinterpret_cast<const float2 *>(f.dbar_in)[(size_t)J * (NX + 1) + I];
+            }
         }
-    double *out = f.part + 8 * (size_t)e;
+        s_dbar[t] = d;
+    }
+    __syncthreads();
+
+    // ---- FP64 share of each patch at each of its 4 corners:
+    //      [d0 G0 + d1 G1 + d2 G2] Dbar + [d0 M0 + d1 M1 + d2 M2] v, times 1/dt.
+    constexpr int ITEMS = TP * TP * 4 * NCH;
+    for (int it = tid; it < ITEMS; it += kThreads) {
+        const int ch = it % NCH, c = (it / NCH) & 3, pl = it / (NCH * 4);
+        const int pi = pi0 + pl % TP, pj = pj0 + pl / TP;
+        double ax = 0.0, ay = 0.0;
+        if (pi < nx && pj < ny) {
+            const size_t e = (size_t)pj * nx + pi;
+            const double d0 = f.geo64[4 * e], d1 = f.geo64[4 * e + 1], d2 = f.geo64[4 * e + 2];
+            const int bi = (pl % TP) * n, bj = (pl / TP) * n;
+            for (int l = ch; l < nf; l += NCH) {
+                const int a = l % (n + 1), b = l / (n + 1);
+                const double w = d0 * s_G[(0 * 4 + c) * nf + l] + d1 * s_G[(1 * 4 + c) * nf + l] +
+                                 d2 * s_G[(2 * 4 + c) * nf + l];
+                const float2 d = s_dbar[(bj + b) * NO + bi + a];
+                ax += w * (double)d.x;
+                ay += w * (double)d.y;
+            }
+            if (ch == 0) {
+                const int cb = (pl / TP) * (TP + 1) + (pl % TP);
+                const float2 vc[4] = {s_v[cb], s_v[cb + 1], s_v[cb + TP + 1], s_v[cb + TP + 2]};
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        out[2 * c] = f.inv_dt64 * acc[c][0];
-        out[2 * c + 1] = f.inv_dt64 * acc[c][1];
+                for (int cc = 0; cc < 4; ++cc) {
+                    const double w = d0 * tab.M[(0 * 4 + c) * 4 + cc] + d1 * tab.M[(1 * 4 + c) * 4 + cc] +
+                                     d2 * tab.M[(2 * 4 + c) * 4 + cc];
+                    ax += w * (double)vc[cc].x;
+                    ay += w * (double)vc[cc].y;
+                }
+            }
+        }
+        if (NCH > 1) {
+            s_red[2 * it] = ax;
+            s_red[2 * it + 1] = ay;
+        } else if (pi < nx && pj < ny) {
+            double *out = f.part + 8 * ((size_t)pj * nx + pi) + 2 * c;
+            out[0] = f.inv_dt64 * ax;
+            out[1] = f.inv_dt64 * ay;
+        }
+    }
+    if (NCH > 1) {
+        __syncthreads();
+        for (int q = tid; q < TP * TP * 4; q += kThreads) {
+            const int c = q & 3, pl = q >> 2;
+            const int pi = pi0 + pl % TP, pj = pj0 + pl / TP;
+            if (pi >= nx || pj >= ny) continue;
+            double ax = 0.0, ay = 0.0;
+            for (int ch = 0; ch < NCH; ++ch) {
+                ax += s_red[2 * (q * NCH + ch)];
+                ay += s_red[2 * (q * NCH + ch) + 1];
+            }
+            double *out = f.part + 8 * ((size_t)pj * nx + pi) + 2 * c;
+            out[0] = f.inv_dt64 * ax;
+            out[1] = f.inv_dt64 * ay;
+        }
     }
 }
 
