@@ -24,7 +24,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp8": 5000.0}
+PEAK_FP32_VECTOR_TFLOPS = 157.3
 STAGES = ["prolong_defect", "gru_mlp", "avg_rhs_fp64", "restrict_gather"]
+# kernel source files per stage (their hash guards the stored traffic counters)
+STAGE_SOURCES = {0: ["defect.hip"], 1: ["net.hip"], 2: ["rhs.hip"], 3: ["rhs.hip"]}
+STAGE_KERNELS = {0: "k_defect", 1: "k_net", 2: "k_rhs", 3: "k_gather"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def per_patch_gemm_flop(K, H, Hm):
@@ -40,6 +45,58 @@ def per_patch_step_bytes(K, H):
     nodes x 8 B each way), h read + written (2 H x 4 B), b_L written (16 B)."""
     n = 1 << K
     return 8 + 4 + 8 + 2 * n * n * 8 + 2 * H * 4 + 16
+
+
+def stencil_flop_per_patch(K):
+    """Defect FLOP per patch with general bilinear geometry: about 760 per fine
+    element (the figure the measurement plan uses), n^2 fine elements per patch."""
+    n = 1 << K
+    return 760 * n * n
+
+
+def rhs_bytes_per_patch(K):
+    """Averaging/rhs kernel interface bytes per patch: per-patch outputs read
+    (2 (n+1)^2 FP32), corrected velocity written (n^2 fine nodes x 8 B), corner
+    partials written (4 x 16 B), coarse v read (8 B)."""
+    n = 1 << K
+    return 2 * (n + 1) ** 2 * 4 + n * n * 8 + 64 + 8
+
+
+def source_hash(stage):
+    import hashlib
+    h = hashlib.sha256()
+    for name in STAGE_SOURCES[stage] + ["internal.h"]:
+        with open(os.path.join(ROOT, "paper_2008_11520_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(stage, workload, precision):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs in
+    profiles/traffic.json, scaled by the copy-kernel factor; None if absent or
+    if the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+        e = t["kernels"][workload][precision][STAGE_KERNELS[stage]]
+    except (OSError, KeyError, ValueError):
+        return None
+    if e.get("source_hash") != source_hash(stage):
+        return None
+    return (e["fetch_kib"] * t["copy_factor_fetch"] + e["write_kib"] * t["copy_factor_write"]) * 1024.0
+
+
+def calibrate_copy(mib):
+    """Plain device-to-device copy of a known size (for scaling the HBM
+    counters): three copies of `mib` MiB."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 3}))
 
 
 def run_gpu(wl, precision, steps, warmup):
@@ -111,7 +168,12 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each box has one MI355X); "
               "run with --gpus 1", file=sys.stderr)
@@ -136,21 +198,29 @@ def main():
     ms_step = main_r["ms_total"] / args.steps
     value = P * args.steps / (main_r["ms_total"] / 1e3)
 
-    # dominant kernel and its roofline
+    # dominant kernel and its roofline (per-launch algorithmic work / average
+    # launch time from the library's HIP events on the launch stream)
     avg = [main_r["stage_ms"][k] / max(main_r["stage_n"][k], 1) for k in range(4)]
     dom = int(np.argmax(avg))
-    flop = per_patch_gemm_flop(wl.K, wl.H, wl.Hm)
-    if dom == 1:
-        achieved = flop * P / (avg[1] / 1e3) / 1e12
-        roof = {"kernel": STAGES[1], "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[args.precision],
-                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[args.precision], "traffic": None,
-                "avg_launch_us": avg[1] * 1e3, "algorithmic_per_patch": flop}
+    t_s = avg[dom] / 1e3
+    if dom == 0:
+        unit_work = stencil_flop_per_patch(wl.K)
+        achieved = unit_work * P / t_s / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS}
+    elif dom == 1:
+        unit_work = per_patch_gemm_flop(wl.K, wl.H, wl.Hm)
+        peak = PEAK_TFLOPS[args.precision]
+        achieved = unit_work * P / t_s / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}
     else:
-        bpp = per_patch_step_bytes(wl.K, wl.H)
-        achieved = bpp * P / (avg[dom] / 1e3) / 1e9
-        roof = {"kernel": STAGES[dom], "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "avg_launch_us": avg[dom] * 1e3,
-                "algorithmic_per_patch": bpp}
+        unit_work = rhs_bytes_per_patch(wl.K) if dom == 2 else 5 * 16 * (flow.nx + 1) * (flow.ny + 1) / P
+        achieved = unit_work * P / t_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS}
+    roof.update({"traffic": stored_traffic(dom, wl.name, args.precision), "kernel": STAGES[dom],
+                 "avg_launch_us": avg[dom] * 1e3, "algorithmic_per_patch": unit_work,
+                 "units_per_launch": P})
     step_bytes = per_patch_step_bytes(wl.K, wl.H) * P
     out = {
         "metric": "patch-steps/s of the fine DNN-MG step",

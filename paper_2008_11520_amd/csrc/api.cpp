@@ -92,7 +92,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Device layout of one context's workspace.
 struct Layout {
-    size_t geo, geo64, feat, h, uprev, D, X, dpatch, part, part2, G, M, cxy, flag, bad, total;
+    size_t geo, geo64, feat, h, uprev, X, dpatch, part, part2, G, M, cxy, flag, bad, total;
 };
 
 Layout layout_of(const dnnmg_config &c)
@@ -106,9 +106,7 @@ Layout layout_of(const dnnmg_config &c)
     L.feat = take(sizeof(float) * 4 * s.P);
     L.h = take(sizeof(float) * (size_t)s.P * c.H);
     L.uprev = take(sizeof(float) * 2 * (size_t)s.Fn);
-    L.D = take(sizeof(float) * 2 * (size_t)s.Fn);
-    // the materialised network input is only read by the generic network kernel
-    L.X = net_needs_x(c.precision, c.K, c.H, c.Hm) ? take(sizeof(float) * (size_t)s.P * s.nin) : 0;
+    L.X = take((c.precision == DNNMG_BF16 ? 2 : 4) * (size_t)s.P * s.nin);
     L.dpatch = take(sizeof(float) * (size_t)s.P * s.nout);
     L.part = take(sizeof(double) * 8 * (size_t)s.P);
     L.part2 = take(sizeof(double) * 8 * (size_t)s.P);
@@ -186,9 +184,7 @@ struct dnnmg_ctx {
     float *feat() const { return (float *)(ws + L.feat); }
     float *h() const { return (float *)(ws + L.h); }
     float *uprev() const { return (float *)(ws + L.uprev); }
-    float *D() const { return (float *)(ws + L.D); }
-    float *X() const { return L.X ? (float *)(ws + L.X) : nullptr; }
-    bool needs_x() const { return L.X != 0; }
+    float *X() const { return (float *)(ws + L.X); }
     float *dpatch() const { return (float *)(ws + L.dpatch); }
     double *part() const { return (double *)(ws + L.part); }
     int *first_flag() const { return (int *)(ws + L.flag); }
@@ -354,7 +350,6 @@ FlowArgs flow_args(const dnnmg_ctx *c, const float *v, const float *p)
     f.feat = c->feat();
     f.h = c->h();
     f.uprev = c->uprev();
-    f.D = c->D();
     f.X = c->X();
     f.x_bf16 = c->cfg.precision == DNNMG_BF16;
     f.dpatch = c->dpatch();
@@ -480,7 +475,6 @@ static int enqueue_step(dnnmg_ctx *c, const FlowArgs &f, hipStream_t st)
     hipEvent_t *ev = (pr.max_steps > 0 && pr.steps < pr.max_steps) ? &pr.ev[4 * pr.steps] : nullptr;
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[0], st));
     HIP_OR_FAIL(launch_defect(f, nullptr, blocks_for(kKindDefect, g.nx, g.ny, g.K), g.K, st));
-    if (c->needs_x()) HIP_OR_FAIL(launch_gather_x(f, nullptr, blocks_for(kKindGatherX, g.nx, g.ny, g.K), g.K, st));
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[1], st));
     HIP_OR_FAIL(launch_net(f, nullptr, blocks_for(kKindNet, g.nx, g.ny, g.K), c->w->net, st));
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[2], st));
@@ -600,6 +594,7 @@ extern "C" int dnnmg_defect(dnnmg_ctx *ctx, const float *v, const float *p, floa
     if (!v || !D) return fail(DNNMG_EINVAL, "v_coarse_dev and D_out_dev must not be NULL");
     FlowArgs f = flow_args(ctx, v, p);
     f.D = D;
+    f.X = nullptr;   // the stage leaves the network input alone
     HIP_OR_FAIL(launch_defect(f, nullptr, blocks_for(kKindDefect, ctx->cfg.nx, ctx->cfg.ny, ctx->cfg.K), ctx->cfg.K,
                               (hipStream_t)stream));
     return DNNMG_OK;
@@ -726,7 +721,6 @@ extern "C" int dnnmg_step_batch(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int nflo
     RhsTables tab = ctxs[0]->tables();
     FlowArgs dummy{};
     HIP_OR_FAIL(launch_defect(dummy, b->dev[slot], t->prefix[kKindDefect][nflows], K, st));
-    if (ctxs[0]->needs_x()) HIP_OR_FAIL(launch_gather_x(dummy, b->dev[slot], t->prefix[kKindGatherX][nflows], K, st));
     HIP_OR_FAIL(launch_net(dummy, b->dev[slot], t->prefix[kKindNet][nflows], w->net, st));
     HIP_OR_FAIL(launch_rhs(dummy, b->dev[slot], t->prefix[kKindRhs][nflows], K, tab, 1, st));
     HIP_OR_FAIL(hipEventRecord(b->ev[slot], st));

@@ -128,7 +128,6 @@ int blocks_for(int kind, int nx, int ny, int K)
         return ((nx + tp - 1) / tp) * ((ny + tp - 1) / tp);
     }
     case kKindGather: return ((nx + 1) * (ny + 1) + kThreads - 1) / kThreads;
-    case kKindGatherX: return (nx * ny + kGatherXPatches - 1) / kGatherXPatches;
     }
     return 0;
 }
@@ -332,77 +331,60 @@ __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const Batc
         __syncthreads();
     }
 
-    // 5. Dirichlet mask; the tile writes the nodes it owns.
+    // 5. Dirichlet mask on the tile's nodes (in place)
     const unsigned dir = f.dirichlet;
     constexpr int NO = kTileFine + 1;
     for (int t = tid; t < NO * NO; t += kThreads) {
         const int li = t % NO, lj = t / NO;
         const int I = I0 + li, J = J0 + lj;
-        if (I > NX || J > NY || (li == kTileFine && I != NX) || (lj == kTileFine && J != NY)) continue;
-        float2 d = s_acc[(lj + 1) * NN + li + 1];
+        if (I > NX || J > NY) continue;
         const bool m = ((dir & 1u) && I == 0) || ((dir & 2u) && I == NX) || ((dir & 4u) && J == 0) ||
                        ((dir & 8u) && J == NY);
+        float2 &d = s_acc[(lj + 1) * NN + li + 1];
         if (m) d = make_float2(0.f, 0.f);
-        reinterpret_cast<float2 *>(f.D)[(size_t)J * (NX + 1) + I] = d;
+        // stage entry: the defect itself, written by the tile that owns the node
+        if (f.D && (li < kTileFine || I == NX) && (lj < kTileFine || J == NY))
+            reinterpret_cast<float2 *>(f.D)[(size_t)J * (NX + 1) + I] = d;
     }
-}
+    if (!f.X) return;
+    __syncthreads();
 
-// Network input rows X[e] = [P v at the (n+1)^2 patch nodes (x,y interleaved,
-// x fastest) ; D at the same nodes ; hx, hy, hx/hy, area], FP32 or BF16.
-template <int K>
-__global__ __launch_bounds__(kThreads) void k_gather_x(FlowArgs single, const BatchTable *bt)
-{
-    constexpr int n = 1 << K, nf = (n + 1) * (n + 1), nin = 4 * nf + 4;
-    constexpr float inv_n = 1.0f / n;
-    int blk = blockIdx.x;
-    const FlowArgs f = bt ? *batch_flow(bt, kKindGatherX, blk) : single;
-    const int nx = f.nx, P = f.nx * f.ny, NX = nx * n;
-    const float2 *v2 = reinterpret_cast<const float2 *>(f.v);
-    const float2 *D2 = reinterpret_cast<const float2 *>(f.D);
-    for (int t = threadIdx.x; t < kGatherXPatches * (nf + 1); t += kThreads) {
+    // 6. network input rows of the tile's patches, one patch node per item:
+    //    X[e] = [P v at the (n+1)^2 patch nodes (x,y interleaved, x fastest) ;
+    //            D at the same nodes ; hx, hy, hx/hy, area]
+    constexpr int nf = (n + 1) * (n + 1), nin = 4 * nf + 4;
+    for (int t = tid; t < TP * TP * (nf + 1); t += kThreads) {
         const int pl = t / (nf + 1), l = t - pl * (nf + 1);
-        const int e = blk * kGatherXPatches + pl;
-        if (e >= P) continue;
-        const int pi = e % nx, pj = e / nx;
+        const int pa = pl % TP, pb = pl / TP;
+        const int pi = tx * TP + pa, pj = ty * TP + pb;
+        if (pi >= nx || pj >= ny) continue;
+        const size_t e = (size_t)pj * nx + pi;
         if (l == nf) {
             const float4 ft = reinterpret_cast<const float4 *>(f.feat)[e];
             if (f.x_bf16) {
-                __bf16 *o = reinterpret_cast<__bf16 *>(f.X) + (size_t)e * nin + 4 * nf;
+                __bf16 *o = reinterpret_cast<__bf16 *>(f.X) + e * nin + 4 * nf;
                 o[0] = (__bf16)ft.x; o[1] = (__bf16)ft.y; o[2] = (__bf16)ft.z; o[3] = (__bf16)ft.w;
             } else {
-                *reinterpret_cast<float4 *>(f.X + (size_t)e * nin + 4 * nf) = ft;
+                *reinterpret_cast<float4 *>(f.X + e * nin + 4 * nf) = ft;
             }
             continue;
         }
         const int a = l % (n + 1), b = l / (n + 1);
-        const int c = pj * (nx + 1) + pi;
-        const float2 c00 = v2[c], c10 = v2[c + 1], c01 = v2[c + nx + 1], c11 = v2[c + nx + 2];
+        const CoarseRec &r = s_c[(pb + 1) * CE + (pa + 1)];
         const float xi = a * inv_n, eta = b * inv_n;
-        const float pvx = (c00.x + (c10.x - c00.x) * xi) + eta * ((c01.x - c00.x) + (c11.x - c10.x - c01.x + c00.x) * xi);
-        const float pvy = (c00.y + (c10.y - c00.y) * xi) + eta * ((c01.y - c00.y) + (c11.y - c10.y - c01.y + c00.y) * xi);
-        const float2 d = D2[(size_t)(pj * n + b) * (NX + 1) + pi * n + a];
+        const float pvx = (r.V0x + r.V1x * xi) + eta * (r.V2x + r.V3x * xi);
+        const float pvy = (r.V0y + r.V1y * xi) + eta * (r.V2y + r.V3y * xi);
+        const float2 d = s_acc[(pb * n + b + 1) * NN + pa * n + a + 1];
         if (f.x_bf16) {
-            __bf16 *o = reinterpret_cast<__bf16 *>(f.X) + (size_t)e * nin;
+            __bf16 *o = reinterpret_cast<__bf16 *>(f.X) + e * nin;
             o[2 * l] = (__bf16)pvx; o[2 * l + 1] = (__bf16)pvy;
             o[2 * nf + 2 * l] = (__bf16)d.x; o[2 * nf + 2 * l + 1] = (__bf16)d.y;
         } else {
-            float *o = f.X + (size_t)e * nin;
+            float *o = f.X + e * nin;
             *reinterpret_cast<float2 *>(o + 2 * l) = make_float2(pvx, pvy);
             *reinterpret_cast<float2 *>(o + 2 * nf + 2 * l) = d;
         }
     }
-}
-
-hipError_t launch_gather_x(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, hipStream_t s)
-{
-    dim3 g(nblocks), b(kThreads);
-    switch (K) {
-    case 1: hipLaunchKernelGGL(k_gather_x<1>, g, b, 0, s, f, bt); break;
-    case 2: hipLaunchKernelGGL(k_gather_x<2>, g, b, 0, s, f, bt); break;
-    case 3: hipLaunchKernelGGL(k_gather_x<3>, g, b, 0, s, f, bt); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
 }
 
 hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, hipStream_t s)

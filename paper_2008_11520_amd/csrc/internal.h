@@ -28,11 +28,11 @@ struct FlowArgs {
     int *first_flag;       // device: nonzero before the first step (then u_prev := P v)
     float *h;              // P x H
     float *uprev;          // Fn x 2
-    float *X;              // P x nin (FP32, or BF16 when x_bf16)
+    float *X;              // P x nin network input (FP32, or BF16 when x_bf16); the step writes it
     float *dpatch;         // P x nout
-    double *part;          // P x 8: per-patch rhs contribution to its 4 corners
+    double *part;          // 4 x P x 2: per-patch rhs contribution, one plane per corner
     float *dbar_out;       // optional Fn x 2
-    float *D;              // Fn x 2: defect at the fine nodes (written by the defect kernel)
+    float *D;              // stage only: Fn x 2 defect at the fine nodes
     const float *dbar_in;  // stage: given fine correction (rhs/restrict alone)
     double *bL;            // restricted rhs output (gather)
 };
@@ -57,8 +57,7 @@ struct RhsTables {
 
 // Device table for batched launches: per kernel kind, a block prefix over
 // flows, then the flows.
-enum { kKindDefect = 0, kKindNet = 1, kKindRhs = 2, kKindGather = 3, kKindGatherX = 4, kKinds = 5 };
-constexpr int kGatherXPatches = 16;  // patches per block of the network-input gather
+enum { kKindDefect = 0, kKindNet = 1, kKindRhs = 2, kKindGather = 3, kKinds = 4 };
 struct BatchTable {
     int nflows;
     int pad[3];
@@ -74,10 +73,6 @@ hipError_t launch_geometry(const double *cxy, int nx, int ny, float *geo, double
                            float *feat, int *bad, hipStream_t s);
 hipError_t launch_prolong(const FlowArgs &f, int K, float *pv, float *pp, hipStream_t s);
 hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, hipStream_t s);
-hipError_t launch_gather_x(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, hipStream_t s);
-// Whether the network kernel for this shape reads a materialised input X
-// (otherwise it assembles its input from D itself).
-bool net_needs_x(int prec, int K, int H, int Hm);
 hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net,
                       hipStream_t s);
 // Blocks of the network launch (persistent kernels use fewer than row tiles).

@@ -258,18 +258,52 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
     const bf8 *B3 = reinterpret_cast<const bf8 *>(net.B3);
     const bf8 *B4 = reinterpret_cast<const bf8 *>(net.B4);
 
-    bf8 w1[3][KC1], w2[H / KC], w3[H / KC], w4[H / KC];
+    // gate and U_h fragments in registers; the MLP fragments in LDS
+    __shared__ __align__(16) bf8 sW3[4 * (H / KC) * 64];
+    __shared__ __align__(16) bf8 sW4[4 * (H / KC) * 64];
+    bf8 w1[3][KC1], w2[H / KC];
 #pragma unroll
     for (int g = 0; g < 3; ++g)
 #pragma unroll
         for (int kc = 0; kc < KC1; ++kc) w1[g][kc] = B1[((g * HT + ht) * KC1 + kc) * 64 + lane];
 #pragma unroll
-    for (int kc = 0; kc < H / KC; ++kc) {
-        w2[kc] = B2[(ht * (H / KC) + kc) * 64 + lane];
-        w3[kc] = (Hm > 0 || ht < OT) ? B3[(ht * (H / KC) + kc) * 64 + lane] : bf8{};
-        w4[kc] = (Hm > 0 && ht < OT) ? B4[(ht * (H / KC) + kc) * 64 + lane] : bf8{};
+    for (int kc = 0; kc < H / KC; ++kc) w2[kc] = B2[(ht * (H / KC) + kc) * 64 + lane];
+    for (int t = tid; t < 4 * (H / KC) * 64; t += kNetH64Threads) {
+        const int tile_m = t / ((H / KC) * 64);
+        sW3[t] = (Hm > 0 || tile_m < OT) ? B3[t] : bf8{};
+        sW4[t] = (Hm > 0 && tile_m < OT) ? B4[t] : bf8{};
     }
     const int col = 16 * ht + li;              // hidden unit / output column of this lane
+
+    // Tiles are contiguous in memory: the network input (BF16, 64 x nin) and
+    // the state (FP32, 64 x H).  Each thread prefetches its 16-byte pieces of
+    // the next tile into registers while the current one is computed.
+    constexpr int XCH = 64 * nin / 8, HCH = 64 * H / 4;            // 16-byte pieces per tile
+    constexpr int XPT = (XCH + kNetH64Threads - 1) / kNetH64Threads;
+    constexpr int HPT = (HCH + kNetH64Threads - 1) / kNetH64Threads;
+    bf8 xr[XPT];
+    f4 hr[HPT];
+    auto load_tile = [&](int tile) {
+        int blk = tile;
+        const FlowArgs *fq = bt ? batch_flow(bt, kKindNet, blk) : &single;
+        const int P = fq->nx * fq->ny, row0 = blk * 64, nrows = min(64, P - row0);
+        const bf8 *xg = reinterpret_cast<const bf8 *>(reinterpret_cast<const __bf16 *>(fq->X) + (size_t)row0 * nin);
+        const f4 *hgv = reinterpret_cast<const f4 *>(fq->h + (size_t)row0 * H);
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) {
+            const int c = tid + i * kNetH64Threads;
+            xr[i] = (c < XCH && c / (nin / 8) < nrows) ? xg[c] : bf8{};
+        }
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
+            const int c = tid + i * kNetH64Threads;
+            hr[i] = (c < HCH && c / (H / 4) < nrows) ? hgv[c] : f4{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    // the k-padding columns of [x | h] stay zero for the whole launch
+    if (PADK > 0)
+        for (int t = tid; t < 64 * PADK; t += kNetH64Threads) sA[(t / PADK) * LDA + nin + H + t % PADK] = (__bf16)0.f;
+    if (blockIdx.x < ntiles) load_tile(blockIdx.x);
 
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         int blk = tile;
@@ -279,50 +313,24 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
         const int nrows = min(64, P - row0);
         float *hg = ff.h + (size_t)row0 * H;
         float *dp = ff.dpatch + (size_t)row0 * nout;
-        const int nx = ff.nx, NX = nx * n;
-        const float2 *v2 = reinterpret_cast<const float2 *>(ff.v);
-        const float2 *D2 = reinterpret_cast<const float2 *>(ff.D);
 
         __syncthreads();   // the previous tile's readers of LDS are done
-        // ---- stage the network input [P v ; D ; features] (BF16) ...
-        for (int t = tid; t < 64 * (nf + 1); t += kNetH64Threads) {
-            const int r = t / (nf + 1), l = t - r * (nf + 1);
-            __bf16 *o = &sA[r * LDA];
-            if (r >= nrows) {
-                if (l < nf) {
-                    o[2 * l] = o[2 * l + 1] = o[2 * nf + 2 * l] = o[2 * nf + 2 * l + 1] = (__bf16)0.f;
-                } else {
-                    o[4 * nf] = o[4 * nf + 1] = o[4 * nf + 2] = o[4 * nf + 3] = (__bf16)0.f;
-                }
-                continue;
-            }
-            const int e = row0 + r, pi = e % nx, pj = e / nx;
-            if (l == nf) {
-                const f4 ft = reinterpret_cast<const f4 *>(ff.feat)[e];
-                o[4 * nf] = (__bf16)ft.x; o[4 * nf + 1] = (__bf16)ft.y;
-                o[4 * nf + 2] = (__bf16)ft.z; o[4 * nf + 3] = (__bf16)ft.w;
-                continue;
-            }
-            const int a = l % (n + 1), b = l / (n + 1);
-            const int c = pj * (nx + 1) + pi;
-            const float2 c00 = v2[c], c10 = v2[c + 1], c01 = v2[c + nx + 1], c11 = v2[c + nx + 2];
-            const float xi = a * (1.0f / n), eta = b * (1.0f / n);
-            const float pvx = (c00.x + (c10.x - c00.x) * xi) + eta * ((c01.x - c00.x) + (c11.x - c10.x - c01.x + c00.x) * xi);
-            const float pvy = (c00.y + (c10.y - c00.y) * xi) + eta * ((c01.y - c00.y) + (c11.y - c10.y - c01.y + c00.y) * xi);
-            const float2 d = D2[(size_t)(pj * n + b) * (NX + 1) + pi * n + a];
-            o[2 * l] = (__bf16)pvx; o[2 * l + 1] = (__bf16)pvy;
-            o[2 * nf + 2 * l] = (__bf16)d.x; o[2 * nf + 2 * l + 1] = (__bf16)d.y;
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) {
+            const int c = tid + i * kNetH64Threads;
+            if (c < XCH) *reinterpret_cast<bf8 *>(&sA[(c / (nin / 8)) * LDA + 8 * (c % (nin / 8))]) = xr[i];
         }
-        // ... and the state h (FP32 copy for the update, BF16 operand copy)
-        for (int t = tid; t < 64 * (H / 4); t += kNetH64Threads) {
-            const int r = t / (H / 4), k = (t - r * (H / 4)) * 4;
-            f4 v = r < nrows ? *reinterpret_cast<const f4 *>(hg + (size_t)r * H + k) : f4{0.f, 0.f, 0.f, 0.f};
-            *reinterpret_cast<f4 *>(&sH[r * LDS32 + k]) = v;
-            __bf16 *a = &sA[r * LDA + nin + k];
-            a[0] = (__bf16)v.x; a[1] = (__bf16)v.y; a[2] = (__bf16)v.z; a[3] = (__bf16)v.w;
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
+            const int c = tid + i * kNetH64Threads;
+            if (c < HCH) {
+                const int r = c / (H / 4), k = 4 * (c % (H / 4));
+                *reinterpret_cast<f4 *>(&sH[r * LDS32 + k]) = hr[i];
+                __bf16 *o = &sA[r * LDA + nin + k];
+                o[0] = (__bf16)hr[i].x; o[1] = (__bf16)hr[i].y; o[2] = (__bf16)hr[i].z; o[3] = (__bf16)hr[i].w;
+            }
         }
-        if (PADK > 0)
-            for (int t = tid; t < 64 * PADK; t += kNetH64Threads) sA[(t / PADK) * LDA + nin + H + t % PADK] = (__bf16)0.f;
+        if (tile + (int)gridDim.x < ntiles) load_tile(tile + gridDim.x);
         __syncthreads();
 
         // ---- phase 1: the three gates of this wave's hidden tile
@@ -379,7 +387,7 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
 #pragma unroll
                 for (int kc = 0; kc < H / KC; ++kc) {
                     const bf8 a = *reinterpret_cast<const bf8 *>(&sHp[(16 * (rt0 + q) + li) * LDH + kc * KC + lq * KQ]);
-                    acc = O::mma(acc, a, w3[kc]);
+                    acc = O::mma(acc, a, sW3[(ht * (H / KC) + kc) * 64 + lane]);
                 }
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
@@ -395,7 +403,7 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
 #pragma unroll
                 for (int kc = 0; kc < H / KC; ++kc) {
                     const bf8 a = *reinterpret_cast<const bf8 *>(&src[(16 * (rt0 + q) + li) * LDH + kc * KC + lq * KQ]);
-                    acc = O::mma(acc, a, Hm > 0 ? w4[kc] : w3[kc]);
+                    acc = O::mma(acc, a, Hm > 0 ? sW4[(ht * (H / KC) + kc) * 64 + lane] : sW3[(ht * (H / KC) + kc) * 64 + lane]);
                 }
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {

@@ -161,9 +161,8 @@ __global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTa
             s_red[2 * it] = ax;
             s_red[2 * it + 1] = ay;
         } else if (pi < nx && pj < ny) {
-            double *out = f.part + 8 * ((size_t)pj * nx + pi) + 2 * c;
-            out[0] = f.inv_dt64 * ax;
-            out[1] = f.inv_dt64 * ay;
+            reinterpret_cast<double2 *>(f.part)[(size_t)c * nx * ny + (size_t)pj * nx + pi] =
+                make_double2(f.inv_dt64 * ax, f.inv_dt64 * ay);
         }
     }
     if (NCH > 1) {
@@ -177,9 +176,8 @@ __global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTa
                 ax += s_red[2 * (q * NCH + ch)];
                 ay += s_red[2 * (q * NCH + ch) + 1];
             }
-            double *out = f.part + 8 * ((size_t)pj * nx + pi) + 2 * c;
-            out[0] = f.inv_dt64 * ax;
-            out[1] = f.inv_dt64 * ay;
+            reinterpret_cast<double2 *>(f.part)[(size_t)c * nx * ny + (size_t)pj * nx + pi] =
+                make_double2(f.inv_dt64 * ax, f.inv_dt64 * ay);
         }
     }
 }
@@ -194,13 +192,15 @@ __global__ __launch_bounds__(kThreads) void k_gather(FlowArgs single, const Batc
     const int t = blk * kThreads + threadIdx.x;
     if (t >= (nx + 1) * (ny + 1)) return;
     const int i = t % (nx + 1), j = t / (nx + 1);
+    // partials are stored as four corner planes of P (x, y) pairs
+    const double2 *pl = reinterpret_cast<const double2 *>(f.part);
+    const size_t P = (size_t)nx * ny;
     double bx = 0.0, by = 0.0;
-    if (i > 0 && j > 0) { const double *q = f.part + 8 * ((size_t)(j - 1) * nx + i - 1) + 6; bx += q[0]; by += q[1]; }
-    if (i < nx && j > 0) { const double *q = f.part + 8 * ((size_t)(j - 1) * nx + i) + 4; bx += q[0]; by += q[1]; }
-    if (i > 0 && j < ny) { const double *q = f.part + 8 * ((size_t)j * nx + i - 1) + 2; bx += q[0]; by += q[1]; }
-    if (i < nx && j < ny) { const double *q = f.part + 8 * ((size_t)j * nx + i); bx += q[0]; by += q[1]; }
-    f.bL[2 * (size_t)t] = bx;
-    f.bL[2 * (size_t)t + 1] = by;
+    if (i > 0 && j > 0) { const double2 q = pl[3 * P + (size_t)(j - 1) * nx + i - 1]; bx += q.x; by += q.y; }
+    if (i < nx && j > 0) { const double2 q = pl[2 * P + (size_t)(j - 1) * nx + i]; bx += q.x; by += q.y; }
+    if (i > 0 && j < ny) { const double2 q = pl[1 * P + (size_t)j * nx + i - 1]; bx += q.x; by += q.y; }
+    if (i < nx && j < ny) { const double2 q = pl[(size_t)j * nx + i]; bx += q.x; by += q.y; }
+    reinterpret_cast<double2 *>(f.bL)[t] = make_double2(bx, by);
 }
 
 hipError_t launch_rhs(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, const RhsTables &tab,
