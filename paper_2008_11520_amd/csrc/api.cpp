@@ -110,7 +110,7 @@ Layout layout_of(const dnnmg_config &c)
     L.dpatch = take(sizeof(float) * (size_t)s.P * s.nout);
     L.part = take(sizeof(double) * 8 * (size_t)s.P);
     L.part2 = take(sizeof(double) * 8 * (size_t)s.P);
-    L.G = take(sizeof(double) * 3 * 4 * s.nf);
+    L.G = take(sizeof(double) * 4 * (s.n + 1));
     L.M = take(sizeof(double) * 3 * 4 * 4);
     L.cxy = take(sizeof(double) * 2 * (size_t)s.Nc);
     L.flag = take(sizeof(int));
@@ -188,7 +188,7 @@ struct dnnmg_ctx {
     float *dpatch() const { return (float *)(ws + L.dpatch); }
     double *part() const { return (double *)(ws + L.part); }
     int *first_flag() const { return (int *)(ws + L.flag); }
-    RhsTables tables() const { return RhsTables{(const double *)(ws + L.G), (const double *)(ws + L.M)}; }
+    RhsTables tables() const { return RhsTables{(const double *)(ws + L.G), (const double *)(ws + L.M)}; }  // A, M
 };
 
 struct dnnmg_batch {
@@ -296,10 +296,11 @@ void release_weights(Weights *w)
 }
 
 // Exact moment tables on the reference square (see rhs.hip):
-//   G[k][c][l] = int N_c phi_l m_k,   M[k][c][c'] = int N_c N_c' m_k,  m = {1, xi, eta}.
+//   int N_c phi_l m_k = A[mx_k][cx][a] A[my_k][cy][b]  (l = (a,b), c = (cx,cy)),
+//   M[k][c][c'] = int N_c N_c' m_k,  m = {1, xi, eta}.
 // Each factor is a 1D integral of a piecewise cubic, done with two Gauss points
 // per fine interval (exact).
-void moment_tables(int K, std::vector<double> &G, std::vector<double> &M)
+void moment_tables(int K, std::vector<double> &A1, std::vector<double> &M)
 {
     const int n = 1 << K, nf = (n + 1) * (n + 1);
     const double gp[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
@@ -318,16 +319,14 @@ void moment_tables(int K, std::vector<double> &G, std::vector<double> &M)
                     for (int q = 0; q < 2; ++q) C[m][p][q] += w * L(p, x) * L(q, x) * xm;
                 }
         }
-    G.assign(3 * 4 * nf, 0.0);
+    // G_k[c][l] = A[mx_k][cx][a] A[my_k][cy][b] factorises; the kernel uses A directly
+    (void)nf;
+    A1 = A;
     M.assign(3 * 4 * 4, 0.0);
     const int mx[3] = {0, 1, 0}, my[3] = {0, 0, 1};   // which direction carries xi / eta
     for (int k = 0; k < 3; ++k)
         for (int c = 0; c < 4; ++c) {
             const int cx = c & 1, cy = c >> 1;
-            for (int b = 0; b <= n; ++b)
-                for (int a = 0; a <= n; ++a)
-                    G[(k * 4 + c) * nf + b * (n + 1) + a] =
-                        A[(mx[k] * 2 + cx) * (n + 1) + a] * A[(my[k] * 2 + cy) * (n + 1) + b];
             for (int cc = 0; cc < 4; ++cc)
                 M[(k * 4 + c) * 4 + cc] = C[mx[k]][cx][cc & 1] * C[my[k]][cy][cc >> 1];
         }
@@ -474,7 +473,7 @@ static int enqueue_step(dnnmg_ctx *c, const FlowArgs &f, hipStream_t st)
     Profile &pr = c->prof;
     hipEvent_t *ev = (pr.max_steps > 0 && pr.steps < pr.max_steps) ? &pr.ev[4 * pr.steps] : nullptr;
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[0], st));
-    HIP_OR_FAIL(launch_defect(f, nullptr, blocks_for(kKindDefect, g.nx, g.ny, g.K), g.K, st));
+    HIP_OR_FAIL(launch_defect(f, nullptr, blocks_for(kKindDefect, g.nx, g.ny, g.K), g.K, f.x_bf16, st));
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[1], st));
     HIP_OR_FAIL(launch_net(f, nullptr, blocks_for(kKindNet, g.nx, g.ny, g.K), c->w->net, st));
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[2], st));
@@ -596,7 +595,7 @@ extern "C" int dnnmg_defect(dnnmg_ctx *ctx, const float *v, const float *p, floa
     f.D = D;
     f.X = nullptr;   // the stage leaves the network input alone
     HIP_OR_FAIL(launch_defect(f, nullptr, blocks_for(kKindDefect, ctx->cfg.nx, ctx->cfg.ny, ctx->cfg.K), ctx->cfg.K,
-                              (hipStream_t)stream));
+                              f.x_bf16, (hipStream_t)stream));
     return DNNMG_OK;
 }
 
@@ -720,7 +719,8 @@ extern "C" int dnnmg_step_batch(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int nflo
     const int K = ctxs[0]->cfg.K;
     RhsTables tab = ctxs[0]->tables();
     FlowArgs dummy{};
-    HIP_OR_FAIL(launch_defect(dummy, b->dev[slot], t->prefix[kKindDefect][nflows], K, st));
+    HIP_OR_FAIL(launch_defect(dummy, b->dev[slot], t->prefix[kKindDefect][nflows], K,
+                              ctxs[0]->cfg.precision == DNNMG_BF16, st));
     HIP_OR_FAIL(launch_net(dummy, b->dev[slot], t->prefix[kKindNet][nflows], w->net, st));
     HIP_OR_FAIL(launch_rhs(dummy, b->dev[slot], t->prefix[kKindRhs][nflows], K, tab, 1, st));
     HIP_OR_FAIL(hipEventRecord(b->ev[slot], st));

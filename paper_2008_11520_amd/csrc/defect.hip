@@ -162,7 +162,7 @@ __device__ inline void element_sums(const float m[2][2], const float Qs[2][2], c
     R[6] = 0.25f * (g0 * mt0 + g1 * mt1 + Sx1 + Sy1);
 }
 
-template <int K>
+template <int K, typename XT>
 __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const BatchTable *bt)
 {
     constexpr int n = 1 << K;
@@ -173,8 +173,14 @@ __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const Batc
     constexpr int CE = TP + 2;                  // coarse elements incl. halo
     constexpr int EPT = (NE * NE + kThreads - 1) / kThreads;   // elements per thread
 
+    constexpr int nf = (n + 1) * (n + 1), nin = 4 * nf + 4;
+    constexpr size_t kWBytes = sizeof(float2) * NN * NN, kXBytes = sizeof(XT) * TP * TP * nin;
     __shared__ CoarseRec s_c[CE * CE];
-    __shared__ float2 s_w[NN * NN];             // (u_prev - P v) / dt at nodes
+    // (u_prev - P v) / dt at nodes; once the element residuals are formed the
+    // same bytes hold the tile's network-input rows
+    __shared__ __align__(16) unsigned char s_wx[kWBytes > kXBytes ? kWBytes : kXBytes];
+    float2 *s_w = reinterpret_cast<float2 *>(s_wx);
+    XT *s_x = reinterpret_cast<XT *>(s_wx);
     __shared__ float2 s_acc[NN * NN];           // assembled residual at nodes
 
     int blk = blockIdx.x;
@@ -187,6 +193,18 @@ __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const Batc
     const int tid = threadIdx.x;
     const int first = *f.first_flag;
     const float inv_dt = f.inv_dt, nu = f.nu;
+
+    // 0. the previous corrected velocity on the tile's nodes + halo: issue the
+    //    loads now, use them after the coarse records are in LDS
+    constexpr int NIT = (NN * NN + kThreads - 1) / kThreads;
+    float2 uq[NIT];
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {            // issue every load first
+        const int t = tid + i * kThreads;
+        const int I = I0 - 1 + t % NN, J = J0 - 1 + t / NN;
+        const bool in = t < NN * NN && !first && I >= 0 && I <= NX && J >= 0 && J <= NY;
+        uq[i] = in ? reinterpret_cast<const float2 *>(f.uprev)[(size_t)J * (NX + 1) + I] : make_float2(0.f, 0.f);
+    }
 
     // 1. coarse-element records
     const float2 *v2 = reinterpret_cast<const float2 *>(f.v);
@@ -217,7 +235,10 @@ __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const Batc
 
     // 2. (u_prev - P v) / dt on the tile's nodes + halo (zero before the first
     //    step); clear the node accumulators
-    for (int t = tid; t < NN * NN; t += kThreads) {
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        const int t = tid + i * kThreads;
+        if (t >= NN * NN) break;
         const int I = I0 - 1 + t % NN, J = J0 - 1 + t / NN;
         float2 w = make_float2(0.f, 0.f);
         if (!first && I >= 0 && I <= NX && J >= 0 && J <= NY) {
@@ -226,8 +247,7 @@ __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const Batc
             const CoarseRec &r = s_c[(cj - cj0) * CE + (ci - ci0)];
             const float pvx = (r.V0x + r.V1x * xi) + eta * (r.V2x + r.V3x * xi);
             const float pvy = (r.V0y + r.V1y * xi) + eta * (r.V2y + r.V3y * xi);
-            const float2 u = reinterpret_cast<const float2 *>(f.uprev)[(size_t)J * (NX + 1) + I];
-            w = make_float2((u.x - pvx) * inv_dt, (u.y - pvy) * inv_dt);
+            w = make_float2((uq[i].x - pvx) * inv_dt, (uq[i].y - pvy) * inv_dt);
         }
         s_w[t] = w;
         s_acc[t] = make_float2(0.f, 0.f);
@@ -242,12 +262,20 @@ __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const Batc
     //    R_a,c = sum_q w_q [ N_a m_c + grad_ref N_a . Q_c ]   (w_q = 1/4).
     constexpr float g0 = 0.21132486540518711775f, g1 = 0.78867513459481288225f;
     float R[EPT][8];
+    // Elements are numbered colour by colour: colour c = (parity of eI) + 2
+    // (parity of eJ) holds the (NE/2)^2 elements 2*lx + ((c & 1) ^ 1),
+    // 2*ly + ((c >> 1) ^ 1) of the tile-local grid.
+    static_assert(NE % 2 == 0, "colour classes of equal size");
+    constexpr int CS = (NE / 2) * (NE / 2);
+    int ecol[EPT];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) R[k][q] = 0.f;
         const int t = tid + k * kThreads;
-        const int le = t % NE, me = t / NE;
+        const int c = t / CS, rr = t - c * CS;
+        const int le = 2 * (rr % (NE / 2)) + ((c & 1) ^ 1), me = 2 * (rr / (NE / 2)) + ((c >> 1) ^ 1);
+        ecol[k] = t < NE * NE ? c : -1;
         const int eI = I0 - 1 + le, eJ = J0 - 1 + me;
         if (t < NE * NE && eI >= 0 && eI < NX && eJ >= 0 && eJ < NY) {
             const int ci = eI >> K, a = eI & (n - 1), cj = eJ >> K, b = eJ & (n - 1);
@@ -310,23 +338,23 @@ __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const Batc
         }
     }
 
-    // 4. assembly in four colour rounds: elements of one colour (parity of
-    //    their indices) share no node, so each round adds without conflicts and
-    //    every node receives its four element contributions in a fixed order.
+    // 4. assembly in four colour rounds: elements of one colour share no node,
+    //    so each round adds without conflicts and every node receives its four
+    //    element contributions in a fixed order.
 #pragma unroll
     for (int colour = 0; colour < 4; ++colour) {
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
+            if (ecol[k] != colour) continue;
             const int t = tid + k * kThreads;
-            const int le = t % NE, me = t / NE;
-            if (t < NE * NE && (((le + 1) & 1) | (((me + 1) & 1) << 1)) == colour) {
-                const int n0 = me * NN + le;
-                float2 *q0 = &s_acc[n0], *q1 = &s_acc[n0 + 1], *q2 = &s_acc[n0 + NN], *q3 = &s_acc[n0 + NN + 1];
-                q0->x += R[k][0]; q0->y += R[k][1];
-                q1->x += R[k][2]; q1->y += R[k][3];
-                q2->x += R[k][4]; q2->y += R[k][5];
-                q3->x += R[k][6]; q3->y += R[k][7];
-            }
+            const int rr = t - colour * CS;
+            const int le = 2 * (rr % (NE / 2)) + ((colour & 1) ^ 1), me = 2 * (rr / (NE / 2)) + ((colour >> 1) ^ 1);
+            const int n0 = me * NN + le;
+            float2 *q0 = &s_acc[n0], *q1 = &s_acc[n0 + 1], *q2 = &s_acc[n0 + NN], *q3 = &s_acc[n0 + NN + 1];
+            q0->x += R[k][0]; q0->y += R[k][1];
+            q1->x += R[k][2]; q1->y += R[k][3];
+            q2->x += R[k][4]; q2->y += R[k][5];
+            q3->x += R[k][6]; q3->y += R[k][7];
         }
         __syncthreads();
     }
@@ -349,24 +377,20 @@ __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const Batc
     if (!f.X) return;
     __syncthreads();
 
-    // 6. network input rows of the tile's patches, one patch node per item:
+    // 6. network input rows of the tile's patches, assembled in LDS one patch
+    //    node per item, then written with full 16-byte stores (each row of TP
+    //    patches is contiguous in X):
     //    X[e] = [P v at the (n+1)^2 patch nodes (x,y interleaved, x fastest) ;
     //            D at the same nodes ; hx, hy, hx/hy, area]
-    constexpr int nf = (n + 1) * (n + 1), nin = 4 * nf + 4;
     for (int t = tid; t < TP * TP * (nf + 1); t += kThreads) {
         const int pl = t / (nf + 1), l = t - pl * (nf + 1);
         const int pa = pl % TP, pb = pl / TP;
         const int pi = tx * TP + pa, pj = ty * TP + pb;
+        XT *o = s_x + pl * nin;
         if (pi >= nx || pj >= ny) continue;
-        const size_t e = (size_t)pj * nx + pi;
         if (l == nf) {
-            const float4 ft = reinterpret_cast<const float4 *>(f.feat)[e];
-            if (f.x_bf16) {
-                __bf16 *o = reinterpret_cast<__bf16 *>(f.X) + e * nin + 4 * nf;
-                o[0] = (__bf16)ft.x; o[1] = (__bf16)ft.y; o[2] = (__bf16)ft.z; o[3] = (__bf16)ft.w;
-            } else {
-                *reinterpret_cast<float4 *>(f.X + e * nin + 4 * nf) = ft;
-            }
+            const float4 ft = reinterpret_cast<const float4 *>(f.feat)[(size_t)pj * nx + pi];
+            o[4 * nf] = (XT)ft.x; o[4 * nf + 1] = (XT)ft.y; o[4 * nf + 2] = (XT)ft.z; o[4 * nf + 3] = (XT)ft.w;
             continue;
         }
         const int a = l % (n + 1), b = l / (n + 1);
@@ -375,27 +399,37 @@ __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const Batc
         const float pvx = (r.V0x + r.V1x * xi) + eta * (r.V2x + r.V3x * xi);
         const float pvy = (r.V0y + r.V1y * xi) + eta * (r.V2y + r.V3y * xi);
         const float2 d = s_acc[(pb * n + b + 1) * NN + pa * n + a + 1];
-        if (f.x_bf16) {
-            __bf16 *o = reinterpret_cast<__bf16 *>(f.X) + e * nin;
-            o[2 * l] = (__bf16)pvx; o[2 * l + 1] = (__bf16)pvy;
-            o[2 * nf + 2 * l] = (__bf16)d.x; o[2 * nf + 2 * l + 1] = (__bf16)d.y;
-        } else {
-            float *o = f.X + e * nin;
-            *reinterpret_cast<float2 *>(o + 2 * l) = make_float2(pvx, pvy);
-            *reinterpret_cast<float2 *>(o + 2 * nf + 2 * l) = d;
-        }
+        o[2 * l] = (XT)pvx; o[2 * l + 1] = (XT)pvy;
+        o[2 * nf + 2 * l] = (XT)d.x; o[2 * nf + 2 * l + 1] = (XT)d.y;
+    }
+    __syncthreads();
+    constexpr int CPR = TP * nin * sizeof(XT) / 16;   // 16-byte pieces per tile row of patches
+    for (int t = tid; t < TP * CPR; t += kThreads) {
+        const int pb = t / CPR, c = t - pb * CPR;
+        const int pj = ty * TP + pb;
+        const int npr = min(TP, nx - tx * TP);        // patches of this tile row inside the mesh
+        if (pj >= ny || c * 16 >= npr * nin * (int)sizeof(XT)) continue;
+        const uint4 v = reinterpret_cast<const uint4 *>(s_x + pb * TP * nin)[c];
+        XT *dst = reinterpret_cast<XT *>(f.X) + ((size_t)pj * nx + tx * TP) * nin;
+        reinterpret_cast<uint4 *>(dst)[c] = v;
     }
 }
 
-hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, hipStream_t s)
+hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, int x_bf16, hipStream_t s)
 {
     dim3 g(nblocks), b(kThreads);
+#define DNNMG_DEFECT_CASE(KK)                                                                 \
+    case KK:                                                                                  \
+        if (x_bf16) hipLaunchKernelGGL((k_defect<KK, __bf16>), g, b, 0, s, f, bt);           \
+        else hipLaunchKernelGGL((k_defect<KK, float>), g, b, 0, s, f, bt);                   \
+        break;
     switch (K) {
-    case 1: hipLaunchKernelGGL(k_defect<1>, g, b, 0, s, f, bt); break;
-    case 2: hipLaunchKernelGGL(k_defect<2>, g, b, 0, s, f, bt); break;
-    case 3: hipLaunchKernelGGL(k_defect<3>, g, b, 0, s, f, bt); break;
+        DNNMG_DEFECT_CASE(1)
+        DNNMG_DEFECT_CASE(2)
+        DNNMG_DEFECT_CASE(3)
     default: return hipErrorInvalidValue;
     }
+#undef DNNMG_DEFECT_CASE
     return hipGetLastError();
 }
 

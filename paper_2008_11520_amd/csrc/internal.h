@@ -51,8 +51,8 @@ struct NetArgs {
 // Moment tables for the FP64 right-hand side (exact integrals on the
 // reference square; see rhs.hip).
 struct RhsTables {
-    const double *G;       // 3 x 4 x nf : int N_c phi_l {1, xi, eta}
-    const double *M;       // 3 x 4 x 4  : int N_c N_c' {1, xi, eta}
+    const double *A;       // 2 x 2 x (n+1): A[m][p][a] = int_0^1 L_p(x) hat_a(x) x^m dx
+    const double *M;       // 3 x 4 x 4    : int N_c N_c' {1, xi, eta} on the reference square
 };
 
 // Device table for batched launches: per kernel kind, a block prefix over
@@ -72,7 +72,7 @@ int blocks_for(int kind, int nx, int ny, int K);
 hipError_t launch_geometry(const double *cxy, int nx, int ny, float *geo, double *geo64,
                            float *feat, int *bad, hipStream_t s);
 hipError_t launch_prolong(const FlowArgs &f, int K, float *pv, float *pp, hipStream_t s);
-hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, hipStream_t s);
+hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, int x_bf16, hipStream_t s);
 hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net,
                       hipStream_t s);
 // Blocks of the network launch (persistent kernels use fewer than row tiles).

@@ -24,6 +24,7 @@ namespace dnnmg {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 
 template <int PREC> struct Op;
 
@@ -273,7 +274,6 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
         sW3[t] = (Hm > 0 || tile_m < OT) ? B3[t] : bf8{};
         sW4[t] = (Hm > 0 && tile_m < OT) ? B4[t] : bf8{};
     }
-    const int col = 16 * ht + li;              // hidden unit / output column of this lane
 
     // Tiles are contiguous in memory: the network input (BF16, 64 x nin) and
     // the state (FP32, 64 x H).  Each thread prefetches its 16-byte pieces of
@@ -326,13 +326,19 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
             if (c < HCH) {
                 const int r = c / (H / 4), k = 4 * (c % (H / 4));
                 *reinterpret_cast<f4 *>(&sH[r * LDS32 + k]) = hr[i];
-                __bf16 *o = &sA[r * LDA + nin + k];
-                o[0] = (__bf16)hr[i].x; o[1] = (__bf16)hr[i].y; o[2] = (__bf16)hr[i].z; o[3] = (__bf16)hr[i].w;
+                bf4 hb;
+                hb[0] = (__bf16)hr[i].x; hb[1] = (__bf16)hr[i].y; hb[2] = (__bf16)hr[i].z; hb[3] = (__bf16)hr[i].w;
+                *reinterpret_cast<bf4 *>(&sA[r * LDA + nin + k]) = hb;
             }
         }
         if (tile + (int)gridDim.x < ntiles) load_tile(tile + gridDim.x);
         __syncthreads();
 
+        // The products are formed transposed (weights x activations^T), so the
+        // 16 x 16 result tile gives lane (li, lq) patch row 16 rt + li and the
+        // four consecutive hidden units 16 ht + 4 lq + e: gate inputs, r*h, h'
+        // and the MLP activations move as 8- and 16-byte vectors.
+        const int ucol = 16 * ht + 4 * lq;       // first of this lane's four units
         // ---- phase 1: the three gates of this wave's hidden tile
         f4 az[RTW], ar[RTW], ah[RTW];
 #pragma unroll
@@ -342,39 +348,45 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
 #pragma unroll
             for (int q = 0; q < RTW; ++q) {
                 const bf8 a = *reinterpret_cast<const bf8 *>(&sA[(16 * (rt0 + q) + li) * LDA + kc * KC + lq * KQ]);
-                az[q] = O::mma(az[q], a, w1[0][kc]);
-                ar[q] = O::mma(ar[q], a, w1[1][kc]);
-                ah[q] = O::mma(ah[q], a, w1[2][kc]);
+                az[q] = O::mma(az[q], w1[0][kc], a);
+                ar[q] = O::mma(ar[q], w1[1][kc], a);
+                ah[q] = O::mma(ah[q], w1[2][kc], a);
             }
-        float hold[RTW][4];
+        f4 hold[RTW];
 #pragma unroll
-        for (int q = 0; q < RTW; ++q)
+        for (int q = 0; q < RTW; ++q) {
+            const int r = 16 * (rt0 + q) + li;
+            hold[q] = *reinterpret_cast<const f4 *>(&sH[r * LDS32 + ucol]);
+            bf4 rh;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int r = 16 * (rt0 + q) + 4 * lq + e;
-                hold[q][e] = sH[r * LDS32 + col];
                 az[q][e] = sigmoid(az[q][e]);
-                sR[r * LDH + col] = (__bf16)(sigmoid(ar[q][e]) * hold[q][e]);
+                rh[e] = (__bf16)(sigmoid(ar[q][e]) * hold[q][e]);
             }
+            *reinterpret_cast<bf4 *>(&sR[r * LDH + ucol]) = rh;
+        }
         __syncthreads();
 
         // ---- phase 2: U_h (r*h); new state
 #pragma unroll
         for (int q = 0; q < RTW; ++q) {
+            const int r = 16 * (rt0 + q) + li;
             f4 au = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kc = 0; kc < H / KC; ++kc) {
-                const bf8 a = *reinterpret_cast<const bf8 *>(&sR[(16 * (rt0 + q) + li) * LDH + kc * KC + lq * KQ]);
-                au = O::mma(au, a, w2[kc]);
+                const bf8 a = *reinterpret_cast<const bf8 *>(&sR[r * LDH + kc * KC + lq * KQ]);
+                au = O::mma(au, w2[kc], a);
             }
+            f4 hn;
+            bf4 hb;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int r = 16 * (rt0 + q) + 4 * lq + e;
                 const float z = az[q][e];
-                const float hn = z * hold[q][e] + (1.0f - z) * fast_tanh(ah[q][e] + au[e]);
-                if (r < nrows) hg[(size_t)r * H + col] = hn;
-                sHp[r * LDH + col] = (__bf16)hn;
+                hn[e] = z * hold[q][e] + (1.0f - z) * fast_tanh(ah[q][e] + au[e]);
+                hb[e] = (__bf16)hn[e];
             }
+            if (r < nrows) *reinterpret_cast<f4 *>(hg + (size_t)r * H + ucol) = hn;
+            *reinterpret_cast<bf4 *>(&sHp[r * LDH + ucol]) = hb;
         }
         __syncthreads();
 
@@ -383,15 +395,17 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
         if (Hm > 0) {
 #pragma unroll
             for (int q = 0; q < RTW; ++q) {
+                const int r = 16 * (rt0 + q) + li;
                 f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int kc = 0; kc < H / KC; ++kc) {
-                    const bf8 a = *reinterpret_cast<const bf8 *>(&sHp[(16 * (rt0 + q) + li) * LDH + kc * KC + lq * KQ]);
-                    acc = O::mma(acc, a, sW3[(ht * (H / KC) + kc) * 64 + lane]);
+                    const bf8 a = *reinterpret_cast<const bf8 *>(&sHp[r * LDH + kc * KC + lq * KQ]);
+                    acc = O::mma(acc, sW3[(ht * (H / KC) + kc) * 64 + lane], a);
                 }
+                bf4 m;
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    sAm[(16 * (rt0 + q) + 4 * lq + e) * LDH + col] = (__bf16)fmaxf(acc[e], 0.f);
+                for (int e = 0; e < 4; ++e) m[e] = (__bf16)fmaxf(acc[e], 0.f);
+                *reinterpret_cast<bf4 *>(&sAm[r * LDH + ucol]) = m;
             }
             __syncthreads();
             src = sAm;
@@ -399,16 +413,18 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
         if (ht < OT) {
 #pragma unroll
             for (int q = 0; q < RTW; ++q) {
+                const int r = 16 * (rt0 + q) + li;
                 f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int kc = 0; kc < H / KC; ++kc) {
-                    const bf8 a = *reinterpret_cast<const bf8 *>(&src[(16 * (rt0 + q) + li) * LDH + kc * KC + lq * KQ]);
-                    acc = O::mma(acc, a, Hm > 0 ? sW4[(ht * (H / KC) + kc) * 64 + lane] : sW3[(ht * (H / KC) + kc) * 64 + lane]);
+                    const bf8 a = *reinterpret_cast<const bf8 *>(&src[r * LDH + kc * KC + lq * KQ]);
+                    acc = O::mma(acc, Hm > 0 ? sW4[(ht * (H / KC) + kc) * 64 + lane] : sW3[(ht * (H / KC) + kc) * 64 + lane], a);
                 }
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int r = 16 * (rt0 + q) + 4 * lq + e;
-                    if (r < nrows && col < nout) dp[(size_t)r * nout + col] = acc[e];
+                // nout is even: the pairs (ucol, ucol+1), (ucol+2, ucol+3) are inside or outside together
+                if (r < nrows) {
+                    float *o = dp + (size_t)r * nout + ucol;
+                    if (ucol < nout) *reinterpret_cast<float2 *>(o) = make_float2(acc[0], acc[1]);
+                    if (ucol + 2 < nout) *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[2], acc[3]);
                 }
             }
         }

@@ -13,7 +13,9 @@
 //   int_E N_c (P v) dx = sum_c' v_c' [d0 M0 + d1 M1 + d2 M2]_{c c'}
 //   int_E N_c d     dx = sum_l  d_l  [d0 G0 + d1 G1 + d2 G2]_{c l}
 // where M_k, G_k integrate N_c N_c' {1, xi, eta} and N_c phi_l {1, xi, eta} on the
-// reference square (phi_l the fine Q1 hat of patch node l).  These are the
+// reference square (phi_l the fine Q1 hat of patch node l).  G_k is a tensor
+// product of 1D integrals A[m][p][a] = int_0^1 L_p hat_a x^m, so the sums over
+// the (n+1)^2 nodes are done as a pass along x then a pass along y.  These are the
 // same integrals the fine-level 2 x 2 Gauss rule computes exactly (the
 // integrands are polynomials of degree <= 3 per variable on every fine cell),
 // and P^T is the evaluation of N_c at fine nodes, so the result equals the
@@ -41,13 +43,11 @@ __global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTa
     constexpr int TP = kRhsFine / n;          // patches per tile and direction
     constexpr int HP = TP + 2;                // with a ring of neighbour patches
     constexpr int NO = kRhsFine + 1;          // tile nodes per direction
-    constexpr int NCH = (kThreads / (TP * TP * 4)) > 0 ? kThreads / (TP * TP * 4) : 1;  // node chunks per corner
 
     __shared__ float s_d[FROM_PATCHES ? HP * HP * nout : 1];
     __shared__ float2 s_dbar[NO * NO];
     __shared__ float2 s_v[(TP + 1) * (TP + 1)];
-    __shared__ double s_G[3 * 4 * nf];
-    __shared__ double s_red[NCH > 1 ? kThreads * 2 : 1];
+    __shared__ double s_A[4 * (n + 1)];
 
     int blk = blockIdx.x;
     const FlowArgs f = bt ? *batch_flow(bt, kKindRhs, blk) : single;
@@ -61,21 +61,31 @@ __global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTa
     if (FROM_PATCHES && blk == 0 && tid == 0) *f.first_flag = 0;
 
     // ---- stage: moment table, coarse corner velocities, per-patch outputs
-    for (int t = tid; t < 3 * 4 * nf; t += kThreads) s_G[t] = tab.G[t];
+    for (int t = tid; t < 4 * (n + 1); t += kThreads) s_A[t] = tab.A[t];
     const float2 *v2 = reinterpret_cast<const float2 *>(f.v);
     for (int t = tid; t < (TP + 1) * (TP + 1); t += kThreads) {
         int ci = pi0 + t % (TP + 1), cj = pj0 + t / (TP + 1);
         s_v[t] = (ci <= nx && cj <= ny) ? v2[(size_t)cj * (nx + 1) + ci] : make_float2(0.f, 0.f);
     }
     if (FROM_PATCHES) {
-        // per-patch outputs of the tile and its ring of neighbours, 8 bytes at a time
+        // per-patch outputs of the tile and its ring of neighbours, 8 bytes at a
+        // time; all of a thread's loads are issued before any LDS store
+        constexpr int NS = HP * HP * nf, IT = (NS + kThreads - 1) / kThreads;
         float2 *sd2 = reinterpret_cast<float2 *>(s_d);
-        for (int t = tid; t < HP * HP * nf; t += kThreads) {
+        const float2 *dp2 = reinterpret_cast<const float2 *>(f.dpatch);
+        float2 tmp[IT];
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int t = tid + i * kThreads;
             const int hp = t / nf, o = t - hp * nf;
             const int qi = pi0 - 1 + hp % HP, qj = pj0 - 1 + hp / HP;
-            sd2[t] = (qi >= 0 && qi < nx && qj >= 0 && qj < ny)
-                         ? reinterpret_cast<const float2 *>(f.dpatch)[((size_t)qj * nx + qi) * nf + o]
-                         : make_float2(0.f, 0.f);
+            tmp[i] = (t < NS && qi >= 0 && qi < nx && qj >= 0 && qj < ny) ? dp2[((size_t)qj * nx + qi) * nf + o]
+                                                                          : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int t = tid + i * kThreads;
+            if (t < NS) sd2[t] = tmp[i];
         }
     }
     __syncthreads();
@@ -126,58 +136,55 @@ __global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTa
     }
     __syncthreads();
 
-    // ---- FP64 share of each patch at each of its 4 corners:
-    //      [d0 G0 + d1 G1 + d2 G2] Dbar + [d0 M0 + d1 M1 + d2 M2] v, times 1/dt.
-    constexpr int ITEMS = TP * TP * 4 * NCH;
-    for (int it = tid; it < ITEMS; it += kThreads) {
-        const int ch = it % NCH, c = (it / NCH) & 3, pl = it / (NCH * 4);
+    // ---- FP64 share of each patch at each of its 4 corners c = (cx, cy):
+    //      (1/dt) [ sum_k d_k sum_{a,b} A[mx_k][cx][a] A[my_k][cy][b] Dbar(a,b)
+    //             + sum_c' (d0 M0 + d1 M1 + d2 M2)[c][c'] v_c' ].
+    //      One item per (patch, component, cx): the x pass T_m(b) = sum_a A[m][cx][a] Dbar(a,b),
+    //      then the y pass for both cy.
+    for (int it = tid; it < TP * TP * 4; it += kThreads) {
+        const int cx = it & 1, comp = (it >> 1) & 1, pl = it >> 2;
         const int pi = pi0 + pl % TP, pj = pj0 + pl / TP;
-        double ax = 0.0, ay = 0.0;
-        if (pi < nx && pj < ny) {
-            const size_t e = (size_t)pj * nx + pi;
-            const double d0 = f.geo64[4 * e], d1 = f.geo64[4 * e + 1], d2 = f.geo64[4 * e + 2];
-            const int bi = (pl % TP) * n, bj = (pl / TP) * n;
-            for (int l = ch; l < nf; l += NCH) {
-                const int a = l % (n + 1), b = l / (n + 1);
-                const double w = d0 * s_G[(0 * 4 + c) * nf + l] + d1 * s_G[(1 * 4 + c) * nf + l] +
-                                 d2 * s_G[(2 * 4 + c) * nf + l];
-                const float2 d = s_dbar[(bj + b) * NO + bi + a];
-                ax += w * (double)d.x;
-                ay += w * (double)d.y;
-            }
-            if (ch == 0) {
-                const int cb = (pl / TP) * (TP + 1) + (pl % TP);
-                const float2 vc[4] = {s_v[cb], s_v[cb + 1], s_v[cb + TP + 1], s_v[cb + TP + 2]};
+        if (pi >= nx || pj >= ny) continue;
+        const size_t e = (size_t)pj * nx + pi;
+        const double d0 = f.geo64[4 * e], d1 = f.geo64[4 * e + 1], d2 = f.geo64[4 * e + 2];
+        const int bi = (pl % TP) * n, bj = (pl / TP) * n;
+        double T0[n + 1], T1[n + 1];
 #pragma unroll
-                for (int cc = 0; cc < 4; ++cc) {
-                    const double w = d0 * tab.M[(0 * 4 + c) * 4 + cc] + d1 * tab.M[(1 * 4 + c) * 4 + cc] +
-                                     d2 * tab.M[(2 * 4 + c) * 4 + cc];
-                    ax += w * (double)vc[cc].x;
-                    ay += w * (double)vc[cc].y;
-                }
+        for (int b = 0; b <= n; ++b) {
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int a = 0; a <= n; ++a) {
+                const float2 dd = s_dbar[(bj + b) * NO + bi + a];
+                const double dv = (double)(comp ? dd.y : dd.x);
+                s0 += s_A[(0 * 2 + cx) * (n + 1) + a] * dv;
+                s1 += s_A[(1 * 2 + cx) * (n + 1) + a] * dv;
             }
+            T0[b] = s0;
+            T1[b] = s1;
         }
-        if (NCH > 1) {
-            s_red[2 * it] = ax;
-            s_red[2 * it + 1] = ay;
-        } else if (pi < nx && pj < ny) {
-            reinterpret_cast<double2 *>(f.part)[(size_t)c * nx * ny + (size_t)pj * nx + pi] =
-                make_double2(f.inv_dt64 * ax, f.inv_dt64 * ay);
-        }
-    }
-    if (NCH > 1) {
-        __syncthreads();
-        for (int q = tid; q < TP * TP * 4; q += kThreads) {
-            const int c = q & 3, pl = q >> 2;
-            const int pi = pi0 + pl % TP, pj = pj0 + pl / TP;
-            if (pi >= nx || pj >= ny) continue;
-            double ax = 0.0, ay = 0.0;
-            for (int ch = 0; ch < NCH; ++ch) {
-                ax += s_red[2 * (q * NCH + ch)];
-                ay += s_red[2 * (q * NCH + ch) + 1];
+        const int cb = (pl / TP) * (TP + 1) + (pl % TP);
+        const float2 v00 = s_v[cb], v10 = s_v[cb + 1], v01 = s_v[cb + TP + 1], v11 = s_v[cb + TP + 2];
+        const double vq[4] = {(double)(comp ? v00.y : v00.x), (double)(comp ? v10.y : v10.x),
+                              (double)(comp ? v01.y : v01.x), (double)(comp ? v11.y : v11.x)};
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy) {
+            double S0 = 0.0, S1 = 0.0, S2 = 0.0;
+#pragma unroll
+            for (int b = 0; b <= n; ++b) {
+                const double ay0 = s_A[(0 * 2 + cy) * (n + 1) + b], ay1 = s_A[(1 * 2 + cy) * (n + 1) + b];
+                S0 += ay0 * T0[b];
+                S1 += ay0 * T1[b];
+                S2 += ay1 * T0[b];
             }
-            reinterpret_cast<double2 *>(f.part)[(size_t)c * nx * ny + (size_t)pj * nx + pi] =
-                make_double2(f.inv_dt64 * ax, f.inv_dt64 * ay);
+            const int c = cx + 2 * cy;
+            double acc = d0 * S0 + d1 * S1 + d2 * S2;
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                const double w = d0 * tab.M[(0 * 4 + c) * 4 + cc] + d1 * tab.M[(1 * 4 + c) * 4 + cc] +
+                                 d2 * tab.M[(2 * 4 + c) * 4 + cc];
+                acc += w * vq[cc];
+            }
+            f.part[2 * ((size_t)c * nx * ny + e) + comp] = f.inv_dt64 * acc;
         }
     }
 }
