@@ -159,6 +159,26 @@ def cpu_baseline(wl, sample_steps=2):
                       % (sample_steps, flow.nx, flow.ny, P, dt)}
 
 
+def run_serving(time_scales, n_requests=256, rate=20.0, hbm_budget=None, use_graph=True):
+    """The serving mix: seeded Poisson arrivals of channel requests of mixed
+    mesh sizes, continuous batching with HBM-budget admission (see serve.py).
+    time_scale 1 is the offered rate; 1e9 puts every arrival at t = 0."""
+    from paper_2008_11520_amd import synth
+    from paper_2008_11520_amd.serve import Server
+    reqs = synth.serving_requests(n_requests, rate, 11)
+    out = []
+    for scale in time_scales:
+        srv = Server(max_flows=256, ring=8, use_graph=use_graph, hbm_budget=hbm_budget)
+        st = srv.run(reqs, time_scale=scale)
+        srv.close()
+        st["offered_rate_per_s"] = rate * scale if scale < 1e6 else "all at t=0"
+        out.append(st)
+        print("bench: serving x%g: %.3g patch-steps/s, p50 %.3f ms, p99 %.3f ms, mean concurrency %.2f"
+              % (scale, st["patch_steps_per_s"], st["p50_step_latency_ms"], st["p99_step_latency_ms"],
+                 st["mean_concurrency"]), file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +188,10 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
+    ap.add_argument("--serving", default="offered,all", metavar="LIST",
+                    help="serving runs after the throughput legs: comma list of offered (20/s), x10, x100, "
+                         "all (every arrival at t=0), or none")
+    ap.add_argument("--serve-budget-mib", type=int, default=0, help="HBM budget of the serving runs (0: 80%% free)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -223,7 +247,7 @@ def main():
                  "units_per_launch": P})
     step_bytes = per_patch_step_bytes(wl.K, wl.H) * P
     out = {
-        "metric": "patch-steps/s of the fine DNN-MG step",
+        "metric": "patch-steps/sec of fine DNN-MG step (BF16 vs FP32); serving p50/p99 step latency",
         "value": value,
         "unit": "patch-steps/s",
         "n_gpus": 1,
@@ -247,6 +271,14 @@ def main():
         "roofline": roof,
         "finite": main_r["finite"],
     }
+    scales = {"offered": 1.0, "x10": 10.0, "x100": 100.0, "all": 1e9}
+    runs = [r for r in args.serving.split(",") if r and r != "none"]
+    if runs:
+        budget = args.serve_budget_mib << 20 if args.serve_budget_mib else None
+        res = run_serving([scales[r] for r in runs], hbm_budget=budget)
+        out["serving"] = {"workload": "256 requests, Poisson 20/s, channel meshes 32x8..512x128, 50-500 steps, "
+                                      "K=2 H=64 bf16, hipGraph",
+                          "runs": dict(zip(runs, res))}
     if not args.no_cpu_baseline:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)

@@ -124,18 +124,38 @@ int dnnmg_step(dnnmg_ctx *ctx, const float *v_coarse_dev, const float *p_coarse_
  * DNNMG_ESTATE before the first step.  May be called more than once. */
 int dnnmg_restrict_rhs(dnnmg_ctx *ctx, double *b_coarse_dev, void *stream);
 
-/* Batched steps (serving form): a descriptor table for up to max_flows flows.
- * Allocates a small device table and pinned staging memory. */
+/* Batched steps (serving form).  A batch object owns one device table of up to
+ * max_flows flow descriptors and double-buffered pinned staging for it.  Use a
+ * batch object from one stream only: table uploads and launches are ordered
+ * on that stream. */
 int dnnmg_batch_create(int max_flows, dnnmg_batch **out);
 int dnnmg_batch_destroy(dnnmg_batch *b);
 
-/* Step nflows flows (all sharing one weight set, see dnnmg_create_shared) with
- * one launch per kernel stage; results equal dnnmg_step on each context, bit
- * for bit.  v[f], p[f] (may be NULL), d_out[f] (may be NULL) as in dnnmg_step;
- * d_out itself may be NULL.  Also produces each flow's restricted rhs, read
- * with dnnmg_restrict_rhs.  The table upload is an async copy from pinned
- * memory; the call waits for the batch's previous upload to finish before
- * reusing its staging slot. */
+/* Describe the next step of nflows flows (all sharing one weight set, see
+ * dnnmg_create_shared): v[f], p[f] (may be NULL) and d_out[f] (may be NULL) as
+ * in dnnmg_step; d_out itself may be NULL.  b_out (may be NULL) gives each
+ * flow's restricted rhs output, (ny+1)(nx+1) x 2 doubles, so that the batched
+ * launch also performs the restriction.  Uploads the table with an async copy
+ * from pinned memory (waiting, if needed, for the upload two calls back to
+ * finish) and advances each context's step counter. */
+int dnnmg_batch_prepare(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int nflows,
+                        const float *const *v, const float *const *p, float *const *d_out,
+                        double *const *b_out, void *stream);
+
+/* Launch the prepared step: one launch per kernel stage over all flows.  With
+ * use_graph != 0 the launch sequence is captured into a hipGraph and replayed.
+ * Its kernels run a fixed grid that strides over the tiles listed in the
+ * device table, reading every per-flow argument and the tile counts at run
+ * time, so one capture serves every membership: the graph is captured again
+ * only when K, the precision, whether b_out is given, or the weight set
+ * changes.  stream must then be a non-default stream.  Results equal dnnmg_step on each
+ * context, bit for bit.  DNNMG_ESTATE if nothing was prepared. */
+int dnnmg_batch_launch(dnnmg_batch *b, int use_graph, void *stream);
+
+/* Number of graph captures this batch object has made (-1 for NULL). */
+int dnnmg_batch_captures(const dnnmg_batch *b);
+
+/* dnnmg_batch_prepare (without b_out) followed by an eager dnnmg_batch_launch. */
 int dnnmg_step_batch(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int nflows,
                      const float *const *v, const float *const *p, float *const *d_out,
                      void *stream);

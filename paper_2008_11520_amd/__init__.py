@@ -24,7 +24,7 @@ PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
 SYMBOLS = [
     "dnnmg_weight_count", "dnnmg_workspace_bytes", "dnnmg_create", "dnnmg_create_shared",
     "dnnmg_step", "dnnmg_restrict_rhs", "dnnmg_batch_create", "dnnmg_batch_destroy",
-    "dnnmg_step_batch", "dnnmg_destroy", "dnnmg_last_error", "dnnmg_prolong", "dnnmg_defect",
+    "dnnmg_batch_prepare", "dnnmg_batch_launch", "dnnmg_batch_captures", "dnnmg_step_batch", "dnnmg_destroy", "dnnmg_last_error", "dnnmg_prolong", "dnnmg_defect",
     "dnnmg_rhs_restrict", "dnnmg_get_state", "dnnmg_set_state", "dnnmg_patch_output",
     "dnnmg_step_count", "dnnmg_profile_enable", "dnnmg_profile_read",
 ]
@@ -65,6 +65,9 @@ def lib():
     L.dnnmg_batch_create.argtypes = [i, ctypes.POINTER(vp)]
     L.dnnmg_batch_destroy.argtypes = [vp]
     L.dnnmg_step_batch.argtypes = [vp, vp, i, vp, vp, vp, vp]
+    L.dnnmg_batch_prepare.argtypes = [vp, vp, i, vp, vp, vp, vp, vp]
+    L.dnnmg_batch_launch.argtypes = [vp, i, vp]
+    L.dnnmg_batch_captures.argtypes = [vp]
     L.dnnmg_destroy.argtypes = [vp]
     L.dnnmg_last_error.restype = ctypes.c_char_p
     L.dnnmg_prolong.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -239,20 +242,39 @@ class Batch:
         self.handle = h
         self.max_flows = max_flows
 
-    def step(self, flows, vs, ps=None, d_outs=None, stream=None):
+    @staticmethod
+    def _arrays(flows, vs, ps, d_outs, b_outs):
         import torch
         nf = len(flows)
         arr = (ctypes.c_void_p * nf)(*[f.handle.value for f in flows])
         va = (ctypes.c_void_p * nf)(*[_ptr(v, torch.float32, 2 * f.s["Nc"], "v").value for f, v in zip(flows, vs)])
-        pa = None
+        pa = da = ba = None
         if ps is not None:
             pa = (ctypes.c_void_p * nf)(*[(_ptr(p, torch.float32, f.s["Nc"], "p").value if p is not None else None)
                                           for f, p in zip(flows, ps)])
-        da = None
         if d_outs is not None:
             da = (ctypes.c_void_p * nf)(*[(_ptr(d, torch.float32, 2 * f.s["Fn"], "d").value if d is not None else None)
                                           for f, d in zip(flows, d_outs)])
+        if b_outs is not None:
+            ba = (ctypes.c_void_p * nf)(*[_ptr(b, torch.float64, 2 * f.s["Nc"], "b").value
+                                          for f, b in zip(flows, b_outs)])
+        return nf, arr, va, pa, da, ba
+
+    def step(self, flows, vs, ps=None, d_outs=None, stream=None):
+        """dnnmg_step_batch: prepare + eager launch."""
+        nf, arr, va, pa, da, _ = self._arrays(flows, vs, ps, d_outs, None)
         _check(lib().dnnmg_step_batch(self.handle, arr, nf, va, pa, da, _stream(stream)))
+
+    def prepare(self, flows, vs, ps=None, d_outs=None, b_outs=None, stream=None):
+        nf, arr, va, pa, da, ba = self._arrays(flows, vs, ps, d_outs, b_outs)
+        _check(lib().dnnmg_batch_prepare(self.handle, arr, nf, va, pa, da, ba, _stream(stream)))
+
+    def launch(self, graph=False, stream=None):
+        _check(lib().dnnmg_batch_launch(self.handle, 1 if graph else 0, _stream(stream)))
+
+    @property
+    def captures(self) -> int:
+        return int(lib().dnnmg_batch_captures(self.handle))
 
     def close(self):
         if getattr(self, "handle", None):

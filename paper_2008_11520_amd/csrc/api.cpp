@@ -5,6 +5,7 @@
 // kernel launches.  All per-step arithmetic runs in the kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -92,7 +93,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Device layout of one context's workspace.
 struct Layout {
-    size_t geo, geo64, feat, h, uprev, X, dpatch, part, part2, G, M, cxy, flag, bad, total;
+    size_t geo, geo64, feat, h, uprev, X, dpatch, part, part2, cxy, flag, bad, total;
 };
 
 Layout layout_of(const dnnmg_config &c)
@@ -110,8 +111,6 @@ Layout layout_of(const dnnmg_config &c)
     L.dpatch = take(sizeof(float) * (size_t)s.P * s.nout);
     L.part = take(sizeof(double) * 8 * (size_t)s.P);
     L.part2 = take(sizeof(double) * 8 * (size_t)s.P);
-    L.G = take(sizeof(double) * 4 * (s.n + 1));
-    L.M = take(sizeof(double) * 3 * 4 * 4);
     L.cxy = take(sizeof(double) * 2 * (size_t)s.Nc);
     L.flag = take(sizeof(int));
     L.bad = take(sizeof(int));
@@ -158,6 +157,7 @@ struct Weights {
     size_t bytes = 0;
     int K = 0, H = 0, Hm = 0, prec = 0;
     NetArgs net{};
+    RhsTables tab{};       // moment tables (depend on K only), inside dev
 };
 
 // Event ring for per-stage kernel timing (benchmarks only).
@@ -188,16 +188,33 @@ struct dnnmg_ctx {
     float *dpatch() const { return (float *)(ws + L.dpatch); }
     double *part() const { return (double *)(ws + L.part); }
     int *first_flag() const { return (int *)(ws + L.flag); }
-    RhsTables tables() const { return RhsTables{(const double *)(ws + L.G), (const double *)(ws + L.M)}; }  // A, M
+    RhsTables tables() const { return w->tab; }
 };
 
 struct dnnmg_batch {
     int max_flows = 0;
-    BatchTable *dev[2] = {nullptr, nullptr};
-    BatchTable *host[2] = {nullptr, nullptr};
+    BatchTable *dev = nullptr;                  // the one device table every launch reads
+    BatchTable *host[2] = {nullptr, nullptr};   // pinned staging, double-buffered
     hipEvent_t ev[2] = {nullptr, nullptr};
-    int slot = 0;
     bool used[2] = {false, false};
+    int slot = 0;
+    // what the last prepare uploaded
+    bool prepared = false;
+    int nflows = 0, K = 0, x_bf16 = 0, gather = 0;
+    int totals[kKinds] = {0, 0, 0, 0};
+    NetArgs net{};
+    RhsTables tab{};
+    int cap = 0;                                // grid of every batched launch in a graph
+    // captured launch sequence.  Every per-flow argument and the tile counts
+    // are read from `dev` at run time, so a graph stays valid while K, the X
+    // type, the gather and the shared weight set are unchanged, whichever
+    // flows fill the table.
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_K = -1, graph_x_bf16 = -1, graph_gather = -1;
+    NetArgs graph_net{};
+    RhsTables graph_tab{};
+    int captures = 0;
 };
 
 namespace {
@@ -209,6 +226,8 @@ size_t weight_count(const dnnmg_config &c)
     n += c.Hm > 0 ? (size_t)c.Hm * c.H + (size_t)s.nout * c.Hm : (size_t)s.nout * c.H;
     return n;
 }
+
+void moment_tables(int K, std::vector<double> &A1, std::vector<double> &M);
 
 // Pack host FP32 weights into the four fragment arrays the network kernel reads.
 int build_weights(const dnnmg_config &c, const float *w, hipStream_t st, Weights **out)
@@ -250,6 +269,16 @@ int build_weights(const dnnmg_config &c, const float *w, hipStream_t st, Weights
         buf.resize(align256(buf.size()));
         off[3] = buf.size();
     }
+    // moment tables of the FP64 right-hand side, shared by every flow of the model
+    std::vector<double> A1, Mt;
+    moment_tables(c.K, A1, Mt);
+    buf.resize(align256(buf.size()));
+    const size_t offA = buf.size();
+    buf.resize(offA + align256(sizeof(double) * A1.size()));
+    std::memcpy(&buf[offA], A1.data(), sizeof(double) * A1.size());
+    const size_t offM = buf.size();
+    buf.resize(offM + align256(sizeof(double) * Mt.size()));
+    std::memcpy(&buf[offM], Mt.data(), sizeof(double) * Mt.size());
     buf.resize(align256(buf.size()) + 256);
 
     Weights *W = new Weights();
@@ -270,6 +299,7 @@ int build_weights(const dnnmg_config &c, const float *w, hipStream_t st, Weights
     unsigned char *d = (unsigned char *)W->dev;
     W->net = NetArgs{c.K, H, Hm, nin, nout, prec, kc1, d + off[0], d + off[1], d + off[2], d + off[3],
                      nullptr, nullptr, nullptr, nullptr};
+    W->tab = RhsTables{(const double *)(d + offA), (const double *)(d + offM)};
     *out = W;
     return DNNMG_OK;
 }
@@ -284,7 +314,8 @@ size_t weight_bytes_estimate(const dnnmg_config &c)
     size_t b = 3 * (size_t)((c.H / 16) * ((s.nin + c.H + KC - 1) / KC) * 64 * KQ * eb);
     b = align256(b) + frag(c.H, c.H);
     b += c.Hm > 0 ? frag(c.Hm, c.H) + frag(s.nout, c.Hm) : frag(s.nout, c.H);
-    return align256(b) + 256;
+    b = align256(b) + align256(sizeof(double) * 4 * (s.n + 1)) + align256(sizeof(double) * 48);
+    return b + 256;
 }
 
 void release_weights(Weights *w)
@@ -397,12 +428,8 @@ int create_common(const dnnmg_config *cfg, const double *cxy, const float *weigh
         rc = build_weights(*cfg, weights, st, &c->w);
         if (rc) { c->w = nullptr; return bail(rc); }
     }
-    std::vector<double> G, M;
-    moment_tables(cfg->K, G, M);
     const Sizes &s = c->s;
     hipError_t e = hipMemcpyAsync(c->ws + c->L.cxy, cxy, sizeof(double) * 2 * s.Nc, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->ws + c->L.G, G.data(), sizeof(double) * G.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->ws + c->L.M, M.data(), sizeof(double) * M.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemsetAsync(c->h(), 0, sizeof(float) * (size_t)s.P * cfg->H, st);
     if (e == hipSuccess) e = hipMemsetAsync(c->uprev(), 0, sizeof(float) * 2 * (size_t)s.Fn, st);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + c->L.bad, 0, sizeof(int), st);
@@ -662,33 +689,57 @@ extern "C" int dnnmg_batch_create(int max_flows, dnnmg_batch **out)
         return fail(DNNMG_EINVAL, "max_flows must be in 1..%d", kMaxBatch);
     dnnmg_batch *b = new dnnmg_batch();
     b->max_flows = max_flows;
-    for (int i = 0; i < 2; ++i) {
-        if (hipMalloc((void **)&b->dev[i], sizeof(BatchTable)) != hipSuccess ||
-            hipHostMalloc((void **)&b->host[i], sizeof(BatchTable), hipHostMallocDefault) != hipSuccess ||
-            hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) != hipSuccess) {
-            (void)hipGetLastError();
-            dnnmg_batch_destroy(b);
-            return fail(DNNMG_ENOMEM, "batch table allocation failed");
-        }
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) {
+        (void)hipGetLastError();
+        delete b;
+        return fail(DNNMG_EDEVICE, "cannot query the device's compute units");
+    }
+    b->cap = 4 * ncu;
+    bool ok = hipMalloc((void **)&b->dev, sizeof(BatchTable)) == hipSuccess;
+    for (int i = 0; ok && i < 2; ++i)
+        ok = hipHostMalloc((void **)&b->host[i], sizeof(BatchTable), hipHostMallocDefault) == hipSuccess &&
+             hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        dnnmg_batch_destroy(b);
+        return fail(DNNMG_ENOMEM, "batch table allocation failed");
     }
     *out = b;
     return DNNMG_OK;
 }
 
+static bool same_net(const NetArgs &a, const NetArgs &b)
+{
+    return a.K == b.K && a.H == b.H && a.Hm == b.Hm && a.nin == b.nin && a.nout == b.nout && a.prec == b.prec &&
+           a.kc1 == b.kc1 && a.B1 == b.B1 && a.B2 == b.B2 && a.B3 == b.B3 && a.B4 == b.B4;
+}
+
+static void batch_drop_graph(dnnmg_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_gather = -1;
+}
+
 extern "C" int dnnmg_batch_destroy(dnnmg_batch *b)
 {
     if (!b) return fail(DNNMG_EINVAL, "batch is NULL");
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 2; ++i)
         if (b->ev[i]) { (void)hipEventSynchronize(b->ev[i]); (void)hipEventDestroy(b->ev[i]); }
-        if (b->dev[i]) (void)hipFree(b->dev[i]);
+    batch_drop_graph(b);
+    if (b->dev) (void)hipFree(b->dev);
+    for (int i = 0; i < 2; ++i)
         if (b->host[i]) (void)hipHostFree(b->host[i]);
-    }
     delete b;
     return DNNMG_OK;
 }
 
-extern "C" int dnnmg_step_batch(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int nflows, const float *const *v,
-                                const float *const *p, float *const *d_out, void *stream)
+extern "C" int dnnmg_batch_prepare(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int nflows, const float *const *v,
+                                   const float *const *p, float *const *d_out, double *const *b_out, void *stream)
 {
     if (!b || !ctxs || !v) return fail(DNNMG_EINVAL, "batch, ctxs and v must not be NULL");
     if (nflows < 1 || nflows > b->max_flows) return fail(DNNMG_EINVAL, "nflows must be in 1..%d", b->max_flows);
@@ -696,6 +747,7 @@ extern "C" int dnnmg_step_batch(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int nflo
     for (int i = 0; i < nflows; ++i) {
         if (!ctxs[i]) return fail(DNNMG_EINVAL, "ctxs[%d] is NULL", i);
         if (!v[i]) return fail(DNNMG_EINVAL, "v[%d] is NULL", i);
+        if (b_out && !b_out[i]) return fail(DNNMG_EINVAL, "b_out[%d] is NULL", i);
         if (ctxs[i]->w != w) return fail(DNNMG_EINVAL, "ctxs[%d] does not share the weights of ctxs[0]", i);
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(DNNMG_EINVAL, "ctxs[%d] repeats ctxs[%d]", i, j);
@@ -711,21 +763,82 @@ extern "C" int dnnmg_step_batch(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int nflo
         for (int k = 0; k < kKinds; ++k) t->prefix[k][i + 1] = t->prefix[k][i] + blocks_for(k, g.nx, g.ny, g.K);
         FlowArgs f = flow_args(ctxs[i], v[i], p ? p[i] : nullptr);
         f.dbar_out = d_out ? d_out[i] : nullptr;
-        f.bL = nullptr;
+        f.bL = b_out ? b_out[i] : nullptr;
         t->flows[i] = f;
     }
     const size_t bytes = offsetof(BatchTable, flows) + sizeof(FlowArgs) * nflows;
-    HIP_OR_FAIL(hipMemcpyAsync(b->dev[slot], t, bytes, hipMemcpyHostToDevice, st));
-    const int K = ctxs[0]->cfg.K;
-    RhsTables tab = ctxs[0]->tables();
-    FlowArgs dummy{};
-    HIP_OR_FAIL(launch_defect(dummy, b->dev[slot], t->prefix[kKindDefect][nflows], K,
-                              ctxs[0]->cfg.precision == DNNMG_BF16, st));
-    HIP_OR_FAIL(launch_net(dummy, b->dev[slot], t->prefix[kKindNet][nflows], w->net, st));
-    HIP_OR_FAIL(launch_rhs(dummy, b->dev[slot], t->prefix[kKindRhs][nflows], K, tab, 1, st));
+    HIP_OR_FAIL(hipMemcpyAsync(b->dev, t, bytes, hipMemcpyHostToDevice, st));
     HIP_OR_FAIL(hipEventRecord(b->ev[slot], st));
     b->used[slot] = true;
     b->slot ^= 1;
+    b->prepared = true;
+    b->nflows = nflows;
+    b->K = ctxs[0]->cfg.K;
+    b->x_bf16 = ctxs[0]->cfg.precision == DNNMG_BF16;
+    b->gather = b_out != nullptr;
+    b->net = w->net;
+    b->tab = ctxs[0]->tables();
+    for (int k = 0; k < kKinds; ++k) b->totals[k] = t->prefix[k][nflows];
     for (int i = 0; i < nflows; ++i) ctxs[i]->steps++;
     return DNNMG_OK;
+}
+
+// Grids of the batched launches.  The kernels stride over the table's tiles,
+// so any grid is correct; a graph uses the fixed cap so that one capture
+// serves every membership, an eager launch trims the grid to the work.
+static int batch_enqueue(dnnmg_batch *b, bool graph, hipStream_t st)
+{
+    FlowArgs dummy{};
+    int grid[kKinds];
+    for (int k = 0; k < kKinds; ++k) grid[k] = graph ? b->cap : std::min(b->totals[k], b->cap);
+    HIP_OR_FAIL(launch_defect(dummy, b->dev, grid[kKindDefect], b->K, b->x_bf16, st));
+    HIP_OR_FAIL(launch_net(dummy, b->dev, grid[kKindNet], b->net, st));
+    HIP_OR_FAIL(launch_rhs(dummy, b->dev, grid[kKindRhs], b->K, b->tab, 1, st));
+    if (b->gather) HIP_OR_FAIL(launch_gather(dummy, b->dev, grid[kKindGather], st));
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_batch_launch(dnnmg_batch *b, int use_graph, void *stream)
+{
+    if (!b) return fail(DNNMG_EINVAL, "batch is NULL");
+    if (!b->prepared) return fail(DNNMG_ESTATE, "dnnmg_batch_prepare has not been called");
+    hipStream_t st = (hipStream_t)stream;
+    if (!use_graph) return batch_enqueue(b, false, st);
+    if (!st) return fail(DNNMG_EINVAL, "graph launches need a non-default stream");
+    const bool same = b->exec && b->graph_K == b->K && b->graph_x_bf16 == b->x_bf16 &&
+                      b->graph_gather == b->gather && same_net(b->graph_net, b->net) &&
+                      b->graph_tab.A == b->tab.A && b->graph_tab.M == b->tab.M;
+    if (!same) {
+        batch_drop_graph(b);
+        HIP_OR_FAIL(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        int rc = batch_enqueue(b, true, st);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+        if (e != hipSuccess) return fail(DNNMG_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        b->graph = g;
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) { batch_drop_graph(b); return fail(DNNMG_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e)); }
+        b->graph_K = b->K;
+        b->graph_x_bf16 = b->x_bf16;
+        b->graph_gather = b->gather;
+        b->graph_net = b->net;
+        b->graph_tab = b->tab;
+        b->captures++;
+    }
+    HIP_OR_FAIL(hipGraphLaunch(b->exec, st));
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_batch_captures(const dnnmg_batch *b)
+{
+    return b ? b->captures : -1;
+}
+
+extern "C" int dnnmg_step_batch(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int nflows, const float *const *v,
+                                const float *const *p, float *const *d_out, void *stream)
+{
+    int rc = dnnmg_batch_prepare(b, ctxs, nflows, v, p, d_out, nullptr, stream);
+    if (rc) return rc;
+    return dnnmg_batch_launch(b, 0, stream);
 }

@@ -163,7 +163,7 @@ __device__ inline void element_sums(const float m[2][2], const float Qs[2][2], c
 }
 
 template <int K, typename XT>
-__global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const BatchTable *bt)
+__device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
 {
     constexpr int n = 1 << K;
     constexpr float inv_n = 1.0f / n;
@@ -183,8 +183,6 @@ __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const Batc
     XT *s_x = reinterpret_cast<XT *>(s_wx);
     __shared__ float2 s_acc[NN * NN];           // assembled residual at nodes
 
-    int blk = blockIdx.x;
-    const FlowArgs f = bt ? *batch_flow(bt, kKindDefect, blk) : single;
     const int nx = f.nx, ny = f.ny, NX = nx * n, NY = ny * n;
     const int tiles_x = (nx + TP - 1) / TP;
     const int tx = blk % tiles_x, ty = blk / tiles_x;
@@ -415,13 +413,36 @@ __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const Batc
     }
 }
 
+// Single flow: one tile per block.  Batched: the blocks stride over the
+// table's tiles of all flows, so the grid need not match the batch.
+template <int K, typename XT, bool BATCHED>
+__global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const BatchTable *bt)
+{
+    if (!BATCHED) {
+        defect_tile<K, XT>(single, blockIdx.x);
+        return;
+    }
+    const int total = bt->prefix[kKindDefect][bt->nflows];
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        int blk = g;
+        const FlowArgs f = *batch_flow(bt, kKindDefect, blk);
+        defect_tile<K, XT>(f, blk);
+        __syncthreads();   // LDS is reused by the next tile
+    }
+}
+
 hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, int x_bf16, hipStream_t s)
 {
     dim3 g(nblocks), b(kThreads);
 #define DNNMG_DEFECT_CASE(KK)                                                                 \
     case KK:                                                                                  \
-        if (x_bf16) hipLaunchKernelGGL((k_defect<KK, __bf16>), g, b, 0, s, f, bt);           \
-        else hipLaunchKernelGGL((k_defect<KK, float>), g, b, 0, s, f, bt);                   \
+        if (bt) {                                                                             \
+            if (x_bf16) hipLaunchKernelGGL((k_defect<KK, __bf16, true>), g, b, 0, s, f, bt);  \
+            else hipLaunchKernelGGL((k_defect<KK, float, true>), g, b, 0, s, f, bt);          \
+        } else {                                                                              \
+            if (x_bf16) hipLaunchKernelGGL((k_defect<KK, __bf16, false>), g, b, 0, s, f, bt); \
+            else hipLaunchKernelGGL((k_defect<KK, float, false>), g, b, 0, s, f, bt);         \
+        }                                                                                     \
         break;
     switch (K) {
         DNNMG_DEFECT_CASE(1)

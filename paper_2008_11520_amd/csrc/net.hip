@@ -84,7 +84,7 @@ __device__ inline float sigmoid(float t) { return __builtin_amdgcn_rcpf(1.0f + _
 __device__ inline float fast_tanh(float t) { return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * t)); }
 
 template <int PREC, int H>
-__global__ __launch_bounds__(kThreads) void k_net(FlowArgs single, const BatchTable *bt, NetArgs net)
+__device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net)
 {
     typedef Op<PREC> O;
     typedef typename O::T T;
@@ -102,8 +102,6 @@ __global__ __launch_bounds__(kThreads) void k_net(FlowArgs single, const BatchTa
     __shared__ __align__(16) T sHp[4][16 * LDH];
     T *sR = sBuf[0], *sAm = sBuf[0];
 
-    int blk = blockIdx.x;
-    const FlowArgs f = bt ? *batch_flow(bt, kKindNet, blk) : single;
     const int P = f.nx * f.ny;
     const int nin = net.nin, nout = net.nout, Hm = net.Hm, kc1 = net.kc1;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -220,6 +218,24 @@ __global__ __launch_bounds__(kThreads) void k_net(FlowArgs single, const BatchTa
     }
 }
 
+// Single flow: one tile per block.  Batched: the blocks stride over the
+// table's tiles of all flows, so the grid need not match the batch.
+template <int PREC, int H, bool BATCHED>
+__global__ __launch_bounds__(kThreads) void k_net(FlowArgs single, const BatchTable *bt, NetArgs net)
+{
+    if (!BATCHED) {
+        net_tile<PREC, H>(single, blockIdx.x, net);
+        return;
+    }
+    const int total = bt->prefix[kKindNet][bt->nflows];
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        int blk = g;
+        const FlowArgs f = *batch_flow(bt, kKindNet, blk);
+        net_tile<PREC, H>(f, blk, net);
+        __syncthreads();   // LDS is reused by the next tile
+    }
+}
+
 
 // Persistent BF16 kernel for H = 64 (and Hm 0 or 64).  Eight waves: wave w
 // owns hidden tile w % 4 for row tiles 2 (w / 4) and 2 (w / 4) + 1 of each
@@ -236,6 +252,7 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
     typedef Op<1> O;
     constexpr int H = 64, KC = 32, KQ = 8, HT = 4, RTW = 2;
     constexpr int n = 1 << K, nf = (n + 1) * (n + 1), nin = 4 * nf + 4, nout = 2 * nf;
+    if (bt) ntiles = bt->prefix[kKindNet][bt->nflows];   // batched: the table's row tiles
     constexpr int KC1 = (nin + H + KC - 1) / KC;
     constexpr int LDA = KC1 * KC + 8;          // +16 bytes per row
     constexpr int LDH = H + 8;
@@ -456,7 +473,8 @@ template <int PREC, int H>
 static hipError_t launch_net_t(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net,
                                hipStream_t s)
 {
-    hipLaunchKernelGGL((k_net<PREC, H>), dim3(nblocks), dim3(kThreads), 0, s, f, bt, net);
+    if (bt) hipLaunchKernelGGL((k_net<PREC, H, true>), dim3(nblocks), dim3(kThreads), 0, s, f, bt, net);
+    else hipLaunchKernelGGL((k_net<PREC, H, false>), dim3(nblocks), dim3(kThreads), 0, s, f, bt, net);
     return hipGetLastError();
 }
 

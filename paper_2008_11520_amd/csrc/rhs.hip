@@ -35,7 +35,7 @@ __device__ inline bool dirichlet_node(unsigned dir, int I, int J, int NX, int NY
 // from_patches = 1: average f.dpatch and store the corrected velocity (the
 // step); 0: take the correction from f.dbar_in (stage, state untouched).
 template <int K, int FROM_PATCHES>
-__global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTable *bt, RhsTables tab)
+__device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables tab)
 {
     constexpr int n = 1 << K;
     constexpr int nf = (n + 1) * (n + 1);
@@ -49,8 +49,6 @@ __global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTa
     __shared__ float2 s_v[(TP + 1) * (TP + 1)];
     __shared__ double s_A[4 * (n + 1)];
 
-    int blk = blockIdx.x;
-    const FlowArgs f = bt ? *batch_flow(bt, kKindRhs, blk) : single;
     const int nx = f.nx, ny = f.ny, NX = nx * n, NY = ny * n;
     const int tiles_x = (nx + TP - 1) / TP;
     const int tx = blk % tiles_x, ty = blk / tiles_x;
@@ -189,12 +187,28 @@ __global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTa
     }
 }
 
+// Single flow: one tile per block.  Batched: the blocks stride over the
+// table's tiles of all flows, so the grid need not match the batch.
+template <int K, int FROM_PATCHES, bool BATCHED>
+__global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTable *bt, RhsTables tab)
+{
+    if (!BATCHED) {
+        rhs_tile<K, FROM_PATCHES>(single, blockIdx.x, tab);
+        return;
+    }
+    const int total = bt->prefix[kKindRhs][bt->nflows];
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        int blk = g;
+        const FlowArgs f = *batch_flow(bt, kKindRhs, blk);
+        rhs_tile<K, FROM_PATCHES>(f, blk, tab);
+        __syncthreads();   // LDS is reused by the next tile
+    }
+}
+
 // b_L at coarse node (i,j): the node is corner 11 of patch (i-1,j-1), corner 01
 // of (i,j-1), corner 10 of (i-1,j) and corner 00 of (i,j); summed in that order.
-__global__ __launch_bounds__(kThreads) void k_gather(FlowArgs single, const BatchTable *bt)
+__device__ __forceinline__ void gather_tile(const FlowArgs &f, int blk)
 {
-    int blk = blockIdx.x;
-    const FlowArgs f = bt ? *batch_flow(bt, kKindGather, blk) : single;
     const int nx = f.nx, ny = f.ny;
     const int t = blk * kThreads + threadIdx.x;
     if (t >= (nx + 1) * (ny + 1)) return;
@@ -210,14 +224,32 @@ __global__ __launch_bounds__(kThreads) void k_gather(FlowArgs single, const Batc
     reinterpret_cast<double2 *>(f.bL)[t] = make_double2(bx, by);
 }
 
+// Single flow: one tile per block.  Batched: the blocks stride over the
+template <bool BATCHED>
+__global__ __launch_bounds__(kThreads) void k_gather(FlowArgs single, const BatchTable *bt)
+{
+    if (!BATCHED) {
+        gather_tile(single, blockIdx.x);
+        return;
+    }
+    const int total = bt->prefix[kKindGather][bt->nflows];
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        int blk = g;
+        const FlowArgs f = *batch_flow(bt, kKindGather, blk);
+        gather_tile(f, blk);
+    }
+}
+
 hipError_t launch_rhs(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, const RhsTables &tab,
                       int from_patches, hipStream_t s)
 {
+    if (bt && !from_patches) return hipErrorInvalidValue;   // batched launches are whole steps
     dim3 g(nblocks), b(kThreads);
 #define DNNMG_RHS_CASE(KK)                                                                \
     case KK:                                                                              \
-        if (from_patches) hipLaunchKernelGGL((k_rhs<KK, 1>), g, b, 0, s, f, bt, tab);     \
-        else hipLaunchKernelGGL((k_rhs<KK, 0>), g, b, 0, s, f, bt, tab);                  \
+        if (bt) hipLaunchKernelGGL((k_rhs<KK, 1, true>), g, b, 0, s, f, bt, tab);         \
+        else if (from_patches) hipLaunchKernelGGL((k_rhs<KK, 1, false>), g, b, 0, s, f, bt, tab); \
+        else hipLaunchKernelGGL((k_rhs<KK, 0, false>), g, b, 0, s, f, bt, tab);           \
         break;
     switch (K) {
         DNNMG_RHS_CASE(1)
@@ -231,7 +263,8 @@ hipError_t launch_rhs(const FlowArgs &f, const BatchTable *bt, int nblocks, int 
 
 hipError_t launch_gather(const FlowArgs &f, const BatchTable *bt, int nblocks, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather, dim3(nblocks), dim3(kThreads), 0, s, f, bt);
+    if (bt) hipLaunchKernelGGL(k_gather<true>, dim3(nblocks), dim3(kThreads), 0, s, f, bt);
+    else hipLaunchKernelGGL(k_gather<false>, dim3(nblocks), dim3(kThreads), 0, s, f, bt);
     return hipGetLastError();
 }
 

@@ -1,0 +1,210 @@
+"""Serving loop: continuous batching of many fine DNN-MG flows on one GPU.
+
+Requests (a channel mesh size, a step count, a field seed and an arrival
+time) are admitted while a slot is free and their device memory fits the HBM
+budget; every tick steps all active flows together with one batched,
+graph-captured launch (dnnmg_batch_prepare + dnnmg_batch_launch), so requests
+that arrive while others run join at the next tick boundary and finished ones
+leave.  Each flow keeps its GRU state and corrected velocity resident on the
+device between ticks.
+
+The coarse solve is not part of this build: each admitted request gets a ring
+of `ring` coarse (v, p) time levels evaluated on the device from its seeded
+Fourier field, and step n reads level n mod ring.
+
+Per-step latency is the time from the moment a flow's step becomes eligible
+(its admission, or the completion of its previous step) to the completion of
+the tick that carries it.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import DnnMG, Batch, make_config, workspace_bytes, synth
+
+
+class Scheduler:
+    """Admission policy (host logic only): requests wait in arrival order and
+    are admitted first come, first served while fewer than max_flows run and
+    their bytes fit the remaining budget.  A request larger than the whole
+    budget is refused."""
+
+    def __init__(self, budget: int, max_flows: int, cost):
+        self.budget, self.max_flows, self.cost = int(budget), int(max_flows), cost
+        self.used, self.running, self.queue = 0, 0, []
+
+    def arrive(self, req):
+        if self.cost(req) > self.budget:
+            raise ValueError("request %s needs %d bytes, more than the whole budget of %d"
+                             % (req.get("id"), self.cost(req), self.budget))
+        self.queue.append(req)
+
+    def admissible(self):
+        """Pop and return the requests that can start now."""
+        out = []
+        while self.queue and self.running < self.max_flows and self.used + self.cost(self.queue[0]) <= self.budget:
+            r = self.queue.pop(0)
+            self.used += self.cost(r)
+            self.running += 1
+            out.append(r)
+        return out
+
+    def release(self, req):
+        self.used -= self.cost(req)
+        self.running -= 1
+
+
+@dataclass
+class Active:
+    req: dict
+    ctx: DnnMG
+    vring: object           # (ring, Nc*2) float32 device tensor
+    pring: object           # (ring, Nc) float32 device tensor
+    b_out: object           # (Nc*2,) float64 device tensor: restricted rhs of the last step
+    bytes: int
+    step: int = 0
+    eligible: float = 0.0
+    admitted: float = 0.0
+    latencies: list = field(default_factory=list)
+
+
+class Server:
+    def __init__(self, K=2, H=64, Hm=64, precision="bf16", weight_seed=1234, nu=1e-3, dt=0.005,
+                 hbm_budget=None, max_flows=64, ring=8, use_graph=True, stream=None):
+        import torch
+        self.K, self.H, self.Hm, self.precision = K, H, Hm, precision
+        self.nu, self.dt, self.ring, self.use_graph = nu, dt, ring, use_graph
+        self.max_flows = max_flows
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        w = synth.xavier_weights(K, H, Hm, weight_seed)
+        with torch.cuda.stream(self.stream):
+            # a one-patch context that owns the shared weights
+            self.model = DnnMG(make_config(1, 1, K, H, Hm, dt, nu, precision, 15),
+                               synth.rect_mesh(1, 1), w, stream=self.stream)
+        free, total = torch.cuda.mem_get_info()
+        self.hbm_budget = int(hbm_budget if hbm_budget is not None else 0.8 * free)
+        self.batch = Batch(max_flows)
+
+    def flow_bytes(self, nx, ny):
+        cfg = make_config(nx, ny, self.K, self.H, self.Hm, self.dt, self.nu, self.precision, synth.DIR_CHANNEL)
+        nc = (nx + 1) * (ny + 1)
+        return workspace_bytes(cfg) + self.ring * nc * 12 + nc * 16
+
+    def admit(self, req, now):
+        import torch
+        nx, ny = req["nx"], req["ny"]
+        flow = synth.Flow(nx, ny, synth.rect_mesh(nx, ny, synth.CHANNEL_LX, synth.CHANNEL_LY), synth.DIR_CHANNEL,
+                          self.dt, synth.FourierField(synth.CHANNEL_LX, synth.CHANNEL_LY, req["field_seed"]),
+                          inflow_max=1.5)
+        cfg = make_config(nx, ny, self.K, self.H, self.Hm, self.dt, self.nu, self.precision, synth.DIR_CHANNEL)
+        with torch.cuda.stream(self.stream):
+            ctx = DnnMG(cfg, flow.cxy, share=self.model, stream=self.stream)
+            xy = torch.from_numpy(flow.cxy.reshape(-1, 2)).cuda()
+            flow.fourier.calibrate_torch(xy)
+            v, p = flow.fourier.fields_torch(xy, [n * self.dt for n in range(self.ring)], inflow_max=1.5)
+            vring = v.reshape(self.ring, -1).float().contiguous()
+            pring = p.float().contiguous()
+            b_out = torch.empty(2 * ctx.s["Nc"], dtype=torch.float64, device="cuda")
+        return Active(req, ctx, vring, pring, b_out, self.flow_bytes(nx, ny), eligible=now, admitted=now)
+
+    def retire(self, a, results=None):
+        import torch
+        if results is not None:
+            h = torch.empty(a.ctx.s["P"] * self.H, dtype=torch.float32, device="cuda")
+            u = torch.empty(2 * a.ctx.s["Fn"], dtype=torch.float32, device="cuda")
+            with torch.cuda.stream(self.stream):
+                a.ctx.get_state(h, u, stream=self.stream)
+            self.stream.synchronize()
+            results[a.req["id"]] = dict(h=h.cpu().numpy(), u=u.cpu().numpy(), bL=a.b_out.cpu().numpy(),
+                                        steps=a.step, queue_delay=a.req["admitted_at"] - a.req["queued_at"])
+        a.ctx.close()
+
+    def run(self, requests, time_scale=1.0, log_every=0.0, results=None):
+        """Serve `requests` (dicts with id, arrival [s], nx, ny, steps,
+        field_seed).  Arrival times are divided by time_scale (10 = ten times
+        the offered rate).  Returns pooled statistics; with a dict `results`,
+        also each request's final state (h, corrected velocity) and last b_L."""
+        import torch
+        pending = sorted((dict(r) for r in requests), key=lambda r: r["arrival"])
+        sched = Scheduler(self.hbm_budget, self.max_flows, lambda r: self.flow_bytes(r["nx"], r["ny"]))
+        active, done = [], []
+        max_conc = 0
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        ticks, conc_sum, patch_steps, gpu_busy = 0, 0, 0, 0.0
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        last_log = 0.0
+        while pending or sched.queue or active:
+            t = now()
+            while pending and pending[0]["arrival"] / time_scale <= t:
+                r = pending.pop(0)
+                r["queued_at"] = r["arrival"] / time_scale
+                sched.arrive(r)
+            for r in sched.admissible():
+                a = self.admit(r, now())
+                r["admitted_at"] = a.admitted
+                active.append(a)
+            max_conc = max(max_conc, len(active))
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, min(pending[0]["arrival"] / time_scale - now(), 0.01)))
+                continue
+            # one tick: every active flow advances one step
+            flows = [a.ctx for a in active]
+            vs = [a.vring[a.step % self.ring] for a in active]
+            ps = [a.pring[a.step % self.ring] for a in active]
+            with torch.cuda.stream(self.stream):
+                self.batch.prepare(flows, vs, ps, None, [a.b_out for a in active], stream=self.stream)
+                ev0.record(self.stream)
+                self.batch.launch(graph=self.use_graph, stream=self.stream)
+                ev1.record(self.stream)
+            ev1.synchronize()
+            t_done = now()
+            gpu_busy += ev0.elapsed_time(ev1) / 1e3
+            ticks += 1
+            conc_sum += len(active)
+            still = []
+            for a in active:
+                a.latencies.append(t_done - a.eligible)
+                a.eligible = t_done
+                a.step += 1
+                patch_steps += a.req["nx"] * a.req["ny"]
+                if a.step >= a.req["steps"]:
+                    a.req["finished_at"] = t_done
+                    done.append(a)
+                    self.retire(a, results)
+                    sched.release(a.req)
+                else:
+                    still.append(a)
+            active = still
+            if log_every and t_done - last_log > log_every:
+                last_log = t_done
+                print("serve: t=%.1fs active=%d queued=%d done=%d" % (t_done, len(active), len(sched.queue),
+                                                                       len(done)), flush=True)
+        wall = now()
+        lat = np.concatenate([np.asarray(a.latencies) for a in done]) if done else np.zeros(0)
+        qdelay = np.array([a.req["admitted_at"] - a.req["queued_at"] for a in done])
+        return {
+            "requests": len(done),
+            "steps": int(lat.size),
+            "ticks": ticks,
+            "wall_s": wall,
+            "gpu_busy_s": gpu_busy,
+            "patch_steps": patch_steps,
+            "patch_steps_per_s": patch_steps / wall if wall > 0 else 0.0,
+            "mean_concurrency": conc_sum / ticks if ticks else 0.0,
+            "max_concurrency": max_conc,
+            "p50_step_latency_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+            "p99_step_latency_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+            "max_step_latency_ms": float(lat.max() * 1e3) if lat.size else None,
+            "p50_queue_delay_ms": float(np.percentile(qdelay, 50) * 1e3) if qdelay.size else None,
+            "p99_queue_delay_ms": float(np.percentile(qdelay, 99) * 1e3) if qdelay.size else None,
+            "graph": self.use_graph,
+        }
+
+    def close(self):
+        self.batch.close()
+        self.model.close()

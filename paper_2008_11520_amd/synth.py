@@ -168,6 +168,50 @@ class FourierField:
     def pressure(self, cxy, t):
         return self._raw_p(cxy[..., 0], cxy[..., 1], t) * self.pscale
 
+    # The same fields evaluated with torch on a device tensor of node
+    # coordinates (N x 2, float64), for inputs made on the GPU.
+    def _raw_torch(self, xy, times):
+        import torch
+        x, y = xy[:, 0][None, :], xy[:, 1][None, :]
+        t = torch.as_tensor(times, dtype=xy.dtype, device=xy.device)[:, None]
+        vx = torch.zeros(t.shape[0], xy.shape[0], dtype=xy.dtype, device=xy.device)
+        vy = torch.zeros_like(vx)
+        p = torch.zeros_like(vx)
+        for m in range(self.nmodes):
+            kx, ky = self.k[m]
+            inv = 1.0 / math.hypot(kx, ky)
+            c = torch.cos(2 * math.pi * (kx * x / self.lx + ky * y / self.ly) + self.phi[m] + self.om[m] * t)
+            c = c * (inv * 2 * math.pi)
+            vx += c * (ky / self.ly)
+            vy -= c * (kx / self.lx)
+        for m in range(self.pmodes):
+            kx, ky = self.pk[m]
+            p += torch.sin(2 * math.pi * (kx * x / self.lx + ky * y / self.ly) + self.pphi[m] + self.pom[m] * t)
+        return vx, vy, p
+
+    def calibrate_torch(self, xy) -> "FourierField":
+        vx, vy, p = self._raw_torch(xy, [0.0])
+        m = float(torch_hypot_max(vx, vy))
+        self.vscale = self.amplitude / m if m > 0 else 1.0
+        pm = float(p.abs().max())
+        self.pscale = self.p_amplitude / pm if pm > 0 else 1.0
+        return self
+
+    def fields_torch(self, xy, times, inflow_max=0.0, height=0.41):
+        """(v, p) at the given times: (T x N x 2, T x N) on xy's device."""
+        import torch
+        vx, vy, p = self._raw_torch(xy, times)
+        vx, vy, p = vx * self.vscale, vy * self.vscale, p * self.pscale
+        if inflow_max > 0.0:
+            y = xy[:, 1][None, :]
+            prof = 4.0 * y * (height - y) / (height * height)
+            vx, vy = vx * prof + inflow_max * prof, vy * prof
+        return torch.stack([vx, vy], dim=-1), p
+
+
+def torch_hypot_max(vx, vy):
+    return (vx * vx + vy * vy).sqrt().max()
+
 
 CHANNEL_LX, CHANNEL_LY = 2.2, 0.41
 
