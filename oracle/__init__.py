@@ -40,6 +40,17 @@ def lib():
         L.orc_step.argtypes = [i, i, i, i, i, d, d, u, _D, _D, _D, _D, _D, _D, i,
                                _D, _D, _D, _D, _D, _D]
         L.orc_step.restype = i
+        L.orc_step_prec.argtypes = [i, i, i, i, i, d, d, u, _D, _D, _D, _D, _D, _D, i, i,
+                                    _D, _D, _D, _D, _D, _D]
+        L.orc_step_prec.restype = i
+        L.orc_e4m3_decode.argtypes = [u]
+        L.orc_e4m3_decode.restype = d
+        L.orc_e4m3_encode.argtypes = [ctypes.c_float]
+        L.orc_e4m3_encode.restype = u
+        L.orc_quantize_rows.argtypes = [i, i, ctypes.POINTER(ctypes.c_float), _U8, ctypes.POINTER(ctypes.c_float)]
+        L.orc_qgemm.argtypes = [i, i, i, _D, _D, _D]
+        L.orc_gru_fp8.argtypes = [i, i, i, _D, _D, _D, _D, _D, _D, _D, _D, _D]
+        L.orc_mlp_fp8.argtypes = [i, i, i, i, _D, _D, _D, _D]
         _lib = L
     return _lib
 
@@ -146,6 +157,56 @@ def mlp(h, M1, M2=None):
     return out
 
 
+# ---- FP8 E4M3 operand form
+def e4m3_decode(code):
+    return lib().orc_e4m3_decode(int(code))
+
+
+def e4m3_encode(x):
+    return lib().orc_e4m3_encode(float(x))
+
+
+def quantize_rows(a):
+    """Per-row E4M3 quantisation of an FP32 matrix: (codes uint8, scales float32)."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    rows, cols = a.shape
+    q = np.empty((rows, cols), dtype=np.uint8)
+    sc = np.empty(rows, dtype=np.float32)
+    F = ctypes.POINTER(ctypes.c_float)
+    lib().orc_quantize_rows(rows, cols, a.ctypes.data_as(F), q.ctypes.data_as(_U8), sc.ctypes.data_as(F))
+    return q, sc
+
+
+def qgemm(A, B):
+    """A (M x K) times B (N x K)^T with per-row FP8 operands, exact accumulation."""
+    A, B = _f64(A), _f64(B)
+    out = np.empty((A.shape[0], B.shape[0]))
+    lib().orc_qgemm(A.shape[0], B.shape[0], A.shape[1], _p(A), _p(B), _p(out))
+    return out
+
+
+def gru_fp8(X, h, Wz, Wr, Wh, Uz, Ur, Uh):
+    X, h = _f64(X), _f64(h)
+    P, nin = X.shape
+    H = h.shape[1]
+    out = np.empty((P, H))
+    lib().orc_gru_fp8(P, nin, H, *[_p(_f64(w)) for w in (Wz, Wr, Wh, Uz, Ur, Uh)],
+                      _p(X), _p(h), _p(out))
+    return out
+
+
+def mlp_fp8(h, M1, M2=None):
+    h = _f64(h)
+    P, H = h.shape
+    if M2 is None:
+        Hm, nout, m2 = 0, M1.shape[0], None
+    else:
+        Hm, nout, m2 = M1.shape[0], M2.shape[0], _f64(M2)
+    out = np.empty((P, nout))
+    lib().orc_mlp_fp8(P, H, Hm, nout, _p(_f64(M1)), _p(m2), _p(h), _p(out))
+    return out
+
+
 def average(nx, ny, K, dpatch, dirichlet):
     s = sizes(nx, ny, K)
     out = np.empty((s["Fn"], 2))
@@ -163,8 +224,9 @@ def rhs_restrict(nx, ny, K, cxy, v, Dbar, dt):
 class OracleFlow:
     """Stateful wrapper: h (P x H) and u_prev (Fn x 2) in float64."""
 
-    def __init__(self, nx, ny, K, H, Hm, dt, nu, dirichlet, cxy, weights):
+    def __init__(self, nx, ny, K, H, Hm, dt, nu, dirichlet, cxy, weights, fp8=False):
         self.nx, self.ny, self.K, self.H, self.Hm = nx, ny, K, H, Hm
+        self.fp8 = bool(fp8)
         self.dt, self.nu, self.dirichlet = dt, nu, dirichlet
         self.cxy = _f64(cxy).reshape(-1, 2)
         self.w = _f64(weights).reshape(-1)
@@ -181,11 +243,11 @@ class OracleFlow:
                       dpatch=(s["P"], s["nout"]), Dbar=(s["Fn"], 2), bL=(s["Nc"], 2))
         for k in want:
             outs[k] = np.empty(shapes[k])
-        rc = lib().orc_step(self.nx, self.ny, self.K, self.H, self.Hm, self.dt, self.nu,
-                            self.dirichlet, _p(self.cxy), _p(self.w),
-                            _p(_f64(v).reshape(-1, 2)), _p(_f64(p).reshape(-1)),
-                            _p(self.h), _p(self.uprev), 1 if self.nsteps == 0 else 0,
-                            *[_p(outs[k]) for k in ("Pv", "D", "X", "dpatch", "Dbar", "bL")])
+        rc = lib().orc_step_prec(self.nx, self.ny, self.K, self.H, self.Hm, self.dt, self.nu,
+                                 self.dirichlet, _p(self.cxy), _p(self.w),
+                                 _p(_f64(v).reshape(-1, 2)), _p(_f64(p).reshape(-1)),
+                                 _p(self.h), _p(self.uprev), 1 if self.nsteps == 0 else 0, int(self.fp8),
+                                 *[_p(outs[k]) for k in ("Pv", "D", "X", "dpatch", "Dbar", "bL")])
         if rc != 0:
             raise MemoryError("oracle step failed: %d" % rc)
         self.nsteps += 1

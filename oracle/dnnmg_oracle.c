@@ -388,6 +388,185 @@ void orc_mlp(int P, int H, int Hm, int nout, const double *M1, const double *M2,
     free(a);
 }
 
+/* ------------------------------------- steps 6-7 with FP8 E4M3 operands */
+/* The precision form with 8-bit operands (not part of the paper, which runs
+ * its network in FP32): every product of the GRU and the MLP takes both
+ * operands as OCP FP8 E4M3 codes with one FP32 scale per row, and
+ * accumulates exactly; everything else is as in orc_gru / orc_mlp.
+ *
+ * E4M3 (OCP 8-bit floating point, "E4M3FN"): sign, 4 exponent bits with
+ * bias 7, 3 mantissa bits; exponent field 0 holds subnormals m/8 * 2^-6;
+ * there are no infinities, S.1111.111 is NaN, so the largest finite value
+ * is 1.75 * 2^8 = 448. */
+double orc_e4m3_decode(unsigned code)
+{
+    const unsigned e = (code >> 3) & 15u, m = code & 7u;
+    const double sign = (code & 0x80u) ? -1.0 : 1.0;
+    if (e == 15u && m == 7u) return NAN;
+    if (e == 0u) return sign * ldexp((double)m / 8.0, -6);
+    return sign * ldexp(1.0 + (double)m / 8.0, (int)e - 7);
+}
+
+/* Nearest E4M3 value of x, ties to the even code; magnitudes above 448
+ * saturate to 448 (the scaled operands never exceed it by more than an FP32
+ * rounding); NaN gives the NaN code. */
+unsigned orc_e4m3_encode(float x)
+{
+    if (isnan(x)) return 0x7Fu;
+    const unsigned sign = signbit(x) ? 0x80u : 0u;
+    const double a = fabs((double)x);
+    if (a >= 448.0) return sign | 0x7Eu;
+    if (a < ldexp(1.0, -6)) {                       /* subnormal range: steps of 2^-9 */
+        const double m = rint(a * 512.0);           /* rint: nearest, ties to even */
+        return sign | (unsigned)m;                   /* m == 8 is the smallest normal */
+    }
+    int e;
+    (void)frexp(a, &e);                             /* a = f 2^e, f in [0.5, 1) */
+    e -= 1;                                         /* a = (1 + t) 2^e, t in [0, 1) */
+    double m = rint((ldexp(a, -e) - 1.0) * 8.0);
+    if (m == 8.0) { m = 0.0; e += 1; }
+    const unsigned code = ((unsigned)(e + 7) << 3) | (unsigned)m;
+    return sign | (code > 0x7Eu ? 0x7Eu : code);
+}
+
+/* Per-row quantisation of a rows x cols matrix of FP32 values, in FP32:
+ *   m = max(max_k |a_k|, 448 * 2^-64), r = 448 / m, s = m / 448,
+ *   q_k = e4m3(a_k * r);  a_k ~ s * dec(q_k).
+ * The floor keeps 1/s finite for an all-zero row. */
+void orc_quantize_rows(int rows, int cols, const float *a, unsigned char *q, float *s)
+{
+    const float floor_m = 448.0f * 0x1p-64f;
+    for (int i = 0; i < rows; ++i) {
+        const float *ai = a + (size_t)i * cols;
+        float m = floor_m;
+        for (int k = 0; k < cols; ++k) {
+            const float v = fabsf(ai[k]);
+            if (v > m) m = v;
+        }
+        const float r = 448.0f / m;
+        s[i] = m / 448.0f;
+        for (int k = 0; k < cols; ++k) q[(size_t)i * cols + k] = (unsigned char)orc_e4m3_encode(ai[k] * r);
+    }
+}
+
+/* One quantised operand row: codes and scale of x (rounded to FP32 first). */
+static void quant_row(int n, const double *x, unsigned char *q, float *s)
+{
+    float *xf = (float *)malloc(sizeof(float) * (n > 0 ? n : 1));
+    for (int k = 0; k < n; ++k) xf[k] = (float)x[k];
+    orc_quantize_rows(1, n, xf, q, s);
+    free(xf);
+}
+
+/* Weights, one scale per output row of the product that uses them. */
+static void quant_matrix(int rows, int cols, const double *w, unsigned char *q, float *s)
+{
+    for (int i = 0; i < rows; ++i) quant_row(cols, w + (size_t)i * cols, q + (size_t)i * cols, s + i);
+}
+
+static double qdot(int n, const unsigned char *a, const unsigned char *b)
+{
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc += orc_e4m3_decode(a[k]) * orc_e4m3_decode(b[k]);
+    return acc;
+}
+
+/* Quantised product: out[i][j] = s_a[i] s_b[j] sum_k dec(qa[i][k]) dec(qb[j][k]),
+ * each row of A and of B quantised with its own scale (orc_quantize_rows). */
+void orc_qgemm(int M, int N, int Kd, const double *A, const double *B, double *out)
+{
+    unsigned char *qa = (unsigned char *)malloc((size_t)M * Kd + 1), *qb = (unsigned char *)malloc((size_t)N * Kd + 1);
+    float *sa = (float *)malloc(sizeof(float) * (M + 1)), *sb = (float *)malloc(sizeof(float) * (N + 1));
+    quant_matrix(M, Kd, A, qa, sa);
+    quant_matrix(N, Kd, B, qb, sb);
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < N; ++j)
+            out[(size_t)i * N + j] = (double)sa[i] * (double)sb[j] * qdot(Kd, qa + (size_t)i * Kd, qb + (size_t)j * Kd);
+    free(qa); free(qb); free(sa); free(sb);
+}
+
+/* GRU with FP8 operands.  The products and their operands:
+ *   gates z, r: [W_g | U_g] (one scale per row over both blocks) times x and
+ *     h, which are quantised separately (the network input x with its own
+ *     per-patch scale, the state h with another);
+ *   candidate:  W_h x (row scales of W_h) and U_h (r*h) (row scales of U_h,
+ *     per-patch scale of r*h). */
+void orc_gru_fp8(int P, int nin, int H, const double *Wz, const double *Wr, const double *Wh,
+                 const double *Uz, const double *Ur, const double *Uh,
+                 const double *X, const double *h, double *hout)
+{
+    const int nb = nin + H;
+    unsigned char *qB[3], *qUh = (unsigned char *)malloc((size_t)H * H);
+    float *sB[3], *sUh = (float *)malloc(sizeof(float) * H);
+    const double *Wg[3] = {Wz, Wr, Wh}, *Ug[3] = {Uz, Ur, NULL};
+    double *row = (double *)malloc(sizeof(double) * nb);
+    for (int g = 0; g < 3; ++g) {
+        qB[g] = (unsigned char *)malloc((size_t)H * nb);
+        sB[g] = (float *)malloc(sizeof(float) * H);
+        for (int k = 0; k < H; ++k) {
+            for (int i = 0; i < nin; ++i) row[i] = Wg[g][(size_t)k * nin + i];
+            for (int m = 0; m < H; ++m) row[nin + m] = Ug[g] ? Ug[g][(size_t)k * H + m] : 0.0;
+            quant_row(nb, row, qB[g] + (size_t)k * nb, sB[g] + k);
+        }
+    }
+    quant_matrix(H, H, Uh, qUh, sUh);
+    unsigned char *qx = (unsigned char *)malloc(nin), *qh = (unsigned char *)malloc(H), *qrh = (unsigned char *)malloc(H);
+    double *z = (double *)malloc(sizeof(double) * H), *rh = (double *)malloc(sizeof(double) * H);
+    for (int e = 0; e < P; ++e) {
+        const double *he = h + (size_t)e * H;
+        float sx, sh, srh;
+        quant_row(nin, X + (size_t)e * nin, qx, &sx);
+        quant_row(H, he, qh, &sh);
+        for (int k = 0; k < H; ++k) {
+            double a[2];
+            for (int g = 0; g < 2; ++g) {
+                const unsigned char *b = qB[g] + (size_t)k * nb;
+                a[g] = (double)sB[g][k] * ((double)sx * qdot(nin, qx, b) + (double)sh * qdot(H, qh, b + nin));
+            }
+            z[k] = logistic(a[0]);
+            rh[k] = logistic(a[1]) * he[k];
+        }
+        quant_row(H, rh, qrh, &srh);
+        for (int k = 0; k < H; ++k) {
+            const double ah = (double)sB[2][k] * (double)sx * qdot(nin, qx, qB[2] + (size_t)k * nb) +
+                              (double)sUh[k] * (double)srh * qdot(H, qrh, qUh + (size_t)k * H);
+            hout[(size_t)e * H + k] = z[k] * he[k] + (1.0 - z[k]) * tanh(ah);
+        }
+    }
+    for (int g = 0; g < 3; ++g) { free(qB[g]); free(sB[g]); }
+    free(qUh); free(sUh); free(row); free(qx); free(qh); free(qrh); free(z); free(rh);
+}
+
+/* MLP with FP8 operands: each layer quantises its input per patch and its
+ * weights per output row. */
+void orc_mlp_fp8(int P, int H, int Hm, int nout, const double *M1, const double *M2,
+                 const double *h, double *d)
+{
+    const int n1 = Hm > 0 ? Hm : nout;
+    unsigned char *q1 = (unsigned char *)malloc((size_t)n1 * H), *q2 = (unsigned char *)malloc((size_t)nout * (Hm > 0 ? Hm : 1));
+    float *s1 = (float *)malloc(sizeof(float) * n1), *s2 = (float *)malloc(sizeof(float) * nout);
+    quant_matrix(n1, H, M1, q1, s1);
+    if (Hm > 0) quant_matrix(nout, Hm, M2, q2, s2);
+    unsigned char *qh = (unsigned char *)malloc(H), *qa = (unsigned char *)malloc(Hm > 0 ? Hm : 1);
+    double *a = (double *)malloc(sizeof(double) * (Hm > 0 ? Hm : 1));
+    for (int e = 0; e < P; ++e) {
+        float sh, sa;
+        double *de = d + (size_t)e * nout;
+        quant_row(H, h + (size_t)e * H, qh, &sh);
+        if (Hm > 0) {
+            for (int k = 0; k < Hm; ++k) {
+                const double t = (double)s1[k] * (double)sh * qdot(H, qh, q1 + (size_t)k * H);
+                a[k] = t > 0.0 ? t : 0.0;
+            }
+            quant_row(Hm, a, qa, &sa);
+            for (int o = 0; o < nout; ++o) de[o] = (double)s2[o] * (double)sa * qdot(Hm, qa, q2 + (size_t)o * Hm);
+        } else {
+            for (int o = 0; o < nout; ++o) de[o] = (double)s1[o] * (double)sh * qdot(H, qh, q1 + (size_t)o * H);
+        }
+    }
+    free(q1); free(q2); free(s1); free(s2); free(qh); free(qa); free(a);
+}
+
 /* ---------------------------------------------------- step 8: averaging */
 /* Duplicate predictions at fine nodes shared by adjacent patches are
  * averaged (Sec. 4.2, patch-based network); the mean over the 1, 2 or 4
@@ -446,16 +625,18 @@ void orc_rhs_restrict(int nx, int ny, int K, const double *cxy, const double *v,
 /* One DNN-MG fine step (Alg. 2, lines 6-9) for given coarse v, p.
  * weights: W_z, W_r, W_h (H x nin), U_z, U_r, U_h (H x H), then M1 (Hm x H)
  * and M2 (nout x Hm), or M (nout x H) when Hm == 0.
+ * fp8 != 0 takes the network products with FP8 E4M3 operands
+ * (orc_gru_fp8, orc_mlp_fp8).
  * State in/out: h (P x H), uprev (Fn x 2).  When first != 0 the previous
  * corrected velocity is taken as P v of this step (no right-hand side from
  * an earlier step exists yet), so the mass term of the defect vanishes.
  * Optional outputs (NULL to skip): Pv (Fn x 2), D (Fn x 2), X (P x nin),
  * dpatch (P x nout), Dbar (Fn x 2), bL ((nx+1)(ny+1) x 2). */
-int orc_step(int nx, int ny, int K, int H, int Hm, double dt, double nu, unsigned dir,
-             const double *cxy, const double *weights, const double *v, const double *p,
-             double *h, double *uprev, int first,
-             double *Pv_out, double *D_out, double *X_out, double *dpatch_out,
-             double *Dbar_out, double *bL_out)
+int orc_step_prec(int nx, int ny, int K, int H, int Hm, double dt, double nu, unsigned dir,
+                  const double *cxy, const double *weights, const double *v, const double *p,
+                  double *h, double *uprev, int first, int fp8,
+                  double *Pv_out, double *D_out, double *X_out, double *dpatch_out,
+                  double *Dbar_out, double *bL_out)
 {
     int n = 1 << K, nf = (n + 1) * (n + 1), nout = 2 * nf, nin = 4 * nf + 4;
     int P = nx * ny;
@@ -483,8 +664,13 @@ int orc_step(int nx, int ny, int K, int H, int Hm, double dt, double nu, unsigne
     orc_defect(nx, ny, K, cxy, Pv, Pp, uprev, dt, nu, dir, D);
     orc_features(nx, ny, cxy, feat);
     orc_gather_input(nx, ny, K, Pv, D, feat, X);
-    orc_gru(P, nin, H, Wz, Wr, Wh, Uz, Ur, Uh, X, h, hn);
-    orc_mlp(P, H, Hm, nout, M1, M2, hn, dp);
+    if (fp8) {
+        orc_gru_fp8(P, nin, H, Wz, Wr, Wh, Uz, Ur, Uh, X, h, hn);
+        orc_mlp_fp8(P, H, Hm, nout, M1, M2, hn, dp);
+    } else {
+        orc_gru(P, nin, H, Wz, Wr, Wh, Uz, Ur, Uh, X, h, hn);
+        orc_mlp(P, H, Hm, nout, M1, M2, hn, dp);
+    }
     orc_average(nx, ny, K, dp, dir, Dbar);
     orc_rhs_restrict(nx, ny, K, cxy, v, Dbar, dt, bL);
 
@@ -500,4 +686,15 @@ int orc_step(int nx, int ny, int K, int H, int Hm, double dt, double nu, unsigne
     if (bL_out) memcpy(bL_out, bL, sizeof(double) * 2 * Nc);
     free(Pv); free(Pp); free(D); free(feat); free(X); free(hn); free(dp); free(Dbar); free(bL);
     return 0;
+}
+
+/* orc_step_prec with FP64 network products. */
+int orc_step(int nx, int ny, int K, int H, int Hm, double dt, double nu, unsigned dir,
+             const double *cxy, const double *weights, const double *v, const double *p,
+             double *h, double *uprev, int first,
+             double *Pv_out, double *D_out, double *X_out, double *dpatch_out,
+             double *Dbar_out, double *bL_out)
+{
+    return orc_step_prec(nx, ny, K, H, Hm, dt, nu, dir, cxy, weights, v, p, h, uprev, first, 0,
+                         Pv_out, D_out, X_out, dpatch_out, Dbar_out, bL_out);
 }

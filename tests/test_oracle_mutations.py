@@ -35,6 +35,16 @@ MUTATIONS = {
     "lumped_mass": ("Mu[2 * node[a] + c] += wd * N[a] * uq[c];", "Mu[2 * node[a] + c] += wd * 0.25 * uq[c];", 0),
     "mask_wrong_axis": ("((dir & 4u) && J == 0)", "((dir & 4u) && I == 0)", 0),
     "state_without_correction": ("uprev[f] = Pv[f] + Dbar[f];", "uprev[f] = Pv[f];", 0),
+    # FP8 E4M3 operand form
+    "e4m3_ties_away": ("rint((ldexp(a, -e) - 1.0) * 8.0)", "round((ldexp(a, -e) - 1.0) * 8.0)", 0),
+    "e4m3_truncate": ("rint((ldexp(a, -e) - 1.0) * 8.0)", "floor((ldexp(a, -e) - 1.0) * 8.0)", 0),
+    "e4m3_bias8": ("((unsigned)(e + 7) << 3)", "((unsigned)(e + 8) << 3)", 0),
+    "e4m3_subnormal_exponent": ("ldexp((double)m / 8.0, -6)", "ldexp((double)m / 8.0, -7)", 0),
+    "fp8_scale_240": ("const float r = 448.0f / m;", "const float r = 240.0f / m;", 0),
+    "gru_fp8_state_unscaled": ("(double)sh * qdot(H, qh, b + nin)", "qdot(H, qh, b + nin)", 0),
+    "gru_fp8_scales_swapped": ("(double)sx * qdot(nin, qx, b) + (double)sh", "(double)sh * qdot(nin, qx, b) + (double)sx", 0),
+    "gru_fp8_reset_on_state": ("(double)sUh[k] * (double)srh * qdot(H, qrh, qUh", "(double)sUh[k] * (double)sh * qdot(H, qh, qUh", 0),
+    "mlp_fp8_no_relu": ("a[k] = t > 0.0 ? t : 0.0;", "a[k] = t;", 0),
 }
 
 
@@ -56,6 +66,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     subprocess.check_call(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-o", str(mlib), str(msrc), "-lm"])
     env = dict(os.environ, DNNMG_ORACLE_LIB=str(mlib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_fp8_pins.py")],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, "pins did not catch mutation %s:\n%s" % (name, r.stdout[-2000:])
