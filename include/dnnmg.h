@@ -59,7 +59,13 @@ enum {
 };
 
 /* Operand precision of the GRU/MLP products (accumulation is always FP32;
- * prolongation and defect are FP32; rhs and restriction are FP64). */
+ * prolongation and defect are FP32; rhs and restriction are FP64).
+ * BF16: operands rounded to nearest even.  FP8_E4M3: OCP E4M3 operands, each
+ * with one FP32 scale per row: weights per output row (at create), the
+ * network input, the state h, r*h, h' and the MLP hidden layer per patch
+ * (scale m / 448 with m the row's largest magnitude, floored at 448 * 2^-64;
+ * codes round x * 448 / m to nearest even).  The network input and the state
+ * carry separate scales in the gate products. */
 enum { DNNMG_FP32 = 0, DNNMG_BF16 = 1, DNNMG_FP8_E4M3 = 2 };
 
 /* Dirichlet sides (Eq. (boundary)); other sides are do-nothing outflow. */
@@ -70,7 +76,7 @@ typedef struct {
     int K;               /* levels bridged, 1..3; n = 2^K                           */
     int H;               /* GRU hidden size: 32, 64 or 128                          */
     int Hm;              /* MLP hidden width: 0 (single linear H -> N_out), or a
-                            multiple of 16 up to 256                                 */
+                            multiple of 32 up to 256                                 */
     double dt;           /* time step (> 0)                                          */
     double nu;           /* viscosity (>= 0)                                         */
     int precision;       /* DNNMG_FP32 / DNNMG_BF16 / DNNMG_FP8_E4M3                 */
@@ -196,6 +202,14 @@ int dnnmg_set_state(dnnmg_ctx *ctx, const float *h_in_dev, const float *uprev_in
 int dnnmg_patch_output(dnnmg_ctx *ctx, float *d_out_dev, void *stream);
 
 long long dnnmg_step_count(const dnnmg_ctx *ctx);
+
+/* The FP8 form's activation quantiser alone (the rule under DNNMG_FP8_E4M3
+ * above): a_dev rows x cols FP32, row-major, finite values -> q_dev rows x
+ * cols E4M3 codes and scale_dev rows FP32 scales, so a ~ scale * value(q).
+ * Device pointers, caller-owned.  DNNMG_EINVAL for NULL pointers or
+ * rows, cols < 1. */
+int dnnmg_quantize_e4m3(const float *a_dev, int rows, int cols, unsigned char *q_dev, float *scale_dev,
+                        void *stream);
 
 /* ---------------------------------------------------------------------
  * Kernel timing for benchmarks.  While enabled, dnnmg_step and

@@ -26,7 +26,7 @@ SYMBOLS = [
     "dnnmg_step", "dnnmg_restrict_rhs", "dnnmg_batch_create", "dnnmg_batch_destroy",
     "dnnmg_batch_prepare", "dnnmg_batch_launch", "dnnmg_batch_captures", "dnnmg_step_batch", "dnnmg_destroy", "dnnmg_last_error", "dnnmg_prolong", "dnnmg_defect",
     "dnnmg_rhs_restrict", "dnnmg_get_state", "dnnmg_set_state", "dnnmg_patch_output",
-    "dnnmg_step_count", "dnnmg_profile_enable", "dnnmg_profile_read",
+    "dnnmg_step_count", "dnnmg_profile_enable", "dnnmg_profile_read", "dnnmg_quantize_e4m3",
 ]
 
 
@@ -78,6 +78,7 @@ def lib():
     L.dnnmg_patch_output.argtypes = [vp, vp, vp]
     L.dnnmg_step_count.argtypes = [vp]; L.dnnmg_step_count.restype = ctypes.c_longlong
     L.dnnmg_profile_enable.argtypes = [vp, i]
+    L.dnnmg_quantize_e4m3.argtypes = [vp, i, i, vp, vp, vp]
     L.dnnmg_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     for name in SYMBOLS:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
@@ -231,6 +232,16 @@ class DnnMG:
             self.close()
         except Exception:
             pass
+
+
+def quantize_e4m3(a, q_out, scale_out, stream=None):
+    """dnnmg_quantize_e4m3 on device tensors: a (rows, cols) float32 ->
+    q_out (rows, cols) uint8 codes, scale_out (rows,) float32."""
+    import torch
+    rows, cols = a.shape
+    _check(lib().dnnmg_quantize_e4m3(_ptr(a, torch.float32, rows * cols, "a"), rows, cols,
+                                     _ptr(q_out, torch.uint8, rows * cols, "q_out"),
+                                     _ptr(scale_out, torch.float32, rows, "scale_out"), _stream(stream)))
 
 
 class Batch:

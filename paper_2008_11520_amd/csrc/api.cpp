@@ -81,7 +81,6 @@ int check_config(const dnnmg_config *c)
         return fail(DNNMG_EUNSUPPORTED, "H = %d has no kernels (32, 64, 128)", c->H);
     if (c->Hm != 0 && (c->Hm % 32 != 0 || c->Hm > 256))
         return fail(DNNMG_EUNSUPPORTED, "Hm = %d unsupported (0 or a multiple of 32 up to 256)", c->Hm);
-    if (c->precision == DNNMG_FP8_E4M3) return fail(DNNMG_EUNSUPPORTED, "FP8 E4M3 form not built");
     const double n = double(1 << c->K);
     const double fn = (c->nx * n + 1.0) * (c->ny * n + 1.0);
     if (fn > 2.0e9 || double(c->nx) * c->ny * (4.0 * (n + 1) * (n + 1) + 4) > 4.0e9)
@@ -93,7 +92,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Device layout of one context's workspace.
 struct Layout {
-    size_t geo, geo64, feat, h, uprev, X, dpatch, part, part2, cxy, flag, bad, total;
+    size_t geo, geo64, feat, h, uprev, X, sx, dpatch, part, part2, cxy, flag, bad, total;
 };
 
 Layout layout_of(const dnnmg_config &c)
@@ -107,7 +106,13 @@ Layout layout_of(const dnnmg_config &c)
     L.feat = take(sizeof(float) * 4 * s.P);
     L.h = take(sizeof(float) * (size_t)s.P * c.H);
     L.uprev = take(sizeof(float) * 2 * (size_t)s.Fn);
-    L.X = take((c.precision == DNNMG_BF16 ? 2 : 4) * (size_t)s.P * s.nin);
+    if (c.precision == DNNMG_FP8_E4M3) {
+        L.X = take((size_t)s.P * xstride_fp8(s.nin));
+        L.sx = take(sizeof(float) * (size_t)s.P);
+    } else {
+        L.X = take((c.precision == DNNMG_BF16 ? 2 : 4) * (size_t)s.P * s.nin);
+        L.sx = L.X;
+    }
     L.dpatch = take(sizeof(float) * (size_t)s.P * s.nout);
     L.part = take(sizeof(double) * 8 * (size_t)s.P);
     L.part2 = take(sizeof(double) * 8 * (size_t)s.P);
@@ -130,6 +135,43 @@ uint16_t bf16_rne(float x)
     return (uint16_t)(u >> 16);
 }
 
+// OCP FP8 E4M3 code of x, round to nearest even on the bit pattern;
+// magnitudes above 448 saturate.
+uint8_t e4m3_rne(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    const uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
+    const uint32_t a = u & 0x7fffffffu;
+    if (a > 0x7f800000u) return sign | 0x7f;              // NaN
+    if (a >= 0x43e00000u) return sign | 0x7e;             // >= 448
+    int e = (int)(a >> 23) - 127;
+    if (e < -6) {                                         // E4M3 subnormal: multiples of 2^-9
+        const float t = std::fabs(x) * 512.0f;            // exact
+        return sign | (uint8_t)std::nearbyint(t);         // ties to even (default rounding mode)
+    }
+    uint32_t keep = (a >> 20) & 7u;
+    const uint32_t rest = a & 0xfffffu;
+    if (rest > 0x80000u || (rest == 0x80000u && (keep & 1u))) ++keep;
+    if (keep == 8u) { keep = 0; ++e; }
+    if (e > 8 || (e == 8 && keep > 6u)) return sign | 0x7e;
+    return sign | (uint8_t)(((e + 7) << 3) | (int)keep);
+}
+
+// Per-row FP8 scale of a weight row: m = max(max |w|, floor), codes of
+// w * (448 / m), scale m / 448 (all in FP32, as for the activations).
+void fp8_rows(std::vector<float> &M, int rows, int cols, std::vector<float> &scale)
+{
+    scale.assign(rows, 1.0f);
+    for (int j = 0; j < rows; ++j) {
+        float m = kFp8MinMax;
+        for (int k = 0; k < cols; ++k) m = std::max(m, std::fabs(M[(size_t)j * cols + k]));
+        const float r = 448.0f / m;
+        scale[j] = m / 448.0f;
+        for (int k = 0; k < cols; ++k) M[(size_t)j * cols + k] *= r;
+    }
+}
+
 void pack_matrix(std::vector<unsigned char> &out, const std::vector<float> &M, int rows, int cols, int tiles,
                  int chunks, int prec)
 {
@@ -144,6 +186,7 @@ void pack_matrix(std::vector<unsigned char> &out, const std::vector<float> &M, i
                     float v = (j < rows && k < cols) ? M[(size_t)j * cols + k] : 0.0f;
                     size_t idx = base + ((((size_t)ot * chunks + kc) * 64 + lane) * KQ + e) * eb;
                     if (prec == DNNMG_FP32) std::memcpy(&out[idx], &v, 4);
+                    else if (prec == DNNMG_FP8_E4M3) out[idx] = e4m3_rne(v);   // v already scaled
                     else { uint16_t b = bf16_rne(v); std::memcpy(&out[idx], &b, 2); }
                 }
 }
@@ -185,6 +228,7 @@ struct dnnmg_ctx {
     float *h() const { return (float *)(ws + L.h); }
     float *uprev() const { return (float *)(ws + L.uprev); }
     float *X() const { return (float *)(ws + L.X); }
+    float *sx() const { return cfg.precision == DNNMG_FP8_E4M3 ? (float *)(ws + L.sx) : nullptr; }
     float *dpatch() const { return (float *)(ws + L.dpatch); }
     double *part() const { return (double *)(ws + L.part); }
     int *first_flag() const { return (int *)(ws + L.flag); }
@@ -200,7 +244,7 @@ struct dnnmg_batch {
     int slot = 0;
     // what the last prepare uploaded
     bool prepared = false;
-    int nflows = 0, K = 0, x_bf16 = 0, gather = 0;
+    int nflows = 0, K = 0, xfmt = 0, gather = 0;
     int totals[kKinds] = {0, 0, 0, 0};
     NetArgs net{};
     RhsTables tab{};
@@ -211,7 +255,7 @@ struct dnnmg_batch {
     // flows fill the table.
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int graph_K = -1, graph_x_bf16 = -1, graph_gather = -1;
+    int graph_K = -1, graph_xfmt = -1, graph_gather = -1;
     NetArgs graph_net{};
     RhsTables graph_tab{};
     int captures = 0;
@@ -235,7 +279,11 @@ int build_weights(const dnnmg_config &c, const float *w, hipStream_t st, Weights
     Sizes s = sizes_of(c);
     const int H = c.H, Hm = c.Hm, prec = c.precision, KC = kchunk(prec);
     const int nin = s.nin, nout = s.nout, HT = H / 16;
-    const int kc1 = (nin + H + KC - 1) / KC;
+    const bool fp8 = prec == DNNMG_FP8_E4M3;
+    // phase-1 columns: [x | h]; FP8 pads the input to whole k-chunks so that
+    // the input and the state (separately scaled) never share a chunk
+    const int xw = fp8 ? xstride_fp8(nin) : nin;
+    const int kc1 = (xw + H + KC - 1) / KC;
     const float *Wg[3] = {w, w + (size_t)H * nin, w + 2 * (size_t)H * nin};
     const float *Ug[3] = {w + 3 * (size_t)H * nin, w + 3 * (size_t)H * nin + (size_t)H * H,
                           w + 3 * (size_t)H * nin + 2 * (size_t)H * H};
@@ -243,31 +291,47 @@ int build_weights(const dnnmg_config &c, const float *w, hipStream_t st, Weights
     const float *M2 = Hm > 0 ? M1 + (size_t)Hm * H : nullptr;
 
     std::vector<unsigned char> buf;
+    std::vector<float> scales[4], sc;          // FP8: per-output-row weight scales
+    // FP8 matrices are scaled per row before packing
+    auto pack = [&](std::vector<float> A, int rows, int cols, int tiles, int chunks, int which) {
+        if (fp8) {
+            fp8_rows(A, rows, cols, sc);
+            scales[which].insert(scales[which].end(), sc.begin(), sc.end());
+        }
+        pack_matrix(buf, A, rows, cols, tiles, chunks, prec);
+    };
     size_t off[4];
     off[0] = 0;
     for (int g = 0; g < 3; ++g) {   // [W_g | U_g], the U_h block is applied in phase 2
-        std::vector<float> A((size_t)H * (nin + H), 0.0f);
+        std::vector<float> A((size_t)H * (xw + H), 0.0f);
         for (int j = 0; j < H; ++j) {
-            for (int k = 0; k < nin; ++k) A[(size_t)j * (nin + H) + k] = Wg[g][(size_t)j * nin + k];
+            for (int k = 0; k < nin; ++k) A[(size_t)j * (xw + H) + k] = Wg[g][(size_t)j * nin + k];
             if (g < 2)
-                for (int k = 0; k < H; ++k) A[(size_t)j * (nin + H) + nin + k] = Ug[g][(size_t)j * H + k];
+                for (int k = 0; k < H; ++k) A[(size_t)j * (xw + H) + xw + k] = Ug[g][(size_t)j * H + k];
         }
-        pack_matrix(buf, A, H, nin + H, HT, kc1, prec);
+        pack(A, H, xw + H, HT, kc1, 0);
     }
     buf.resize(align256(buf.size()));
     off[1] = buf.size();
-    pack_matrix(buf, std::vector<float>(Ug[2], Ug[2] + (size_t)H * H), H, H, HT, H / KC, prec);
+    pack(std::vector<float>(Ug[2], Ug[2] + (size_t)H * H), H, H, HT, H / KC, 1);
     buf.resize(align256(buf.size()));
     off[2] = buf.size();
     if (Hm > 0) {
-        pack_matrix(buf, std::vector<float>(M1, M1 + (size_t)Hm * H), Hm, H, Hm / 16, H / KC, prec);
+        pack(std::vector<float>(M1, M1 + (size_t)Hm * H), Hm, H, Hm / 16, H / KC, 2);
         buf.resize(align256(buf.size()));
         off[3] = buf.size();
-        pack_matrix(buf, std::vector<float>(M2, M2 + (size_t)nout * Hm), nout, Hm, (nout + 15) / 16, Hm / KC, prec);
+        pack(std::vector<float>(M2, M2 + (size_t)nout * Hm), nout, Hm, (nout + 15) / 16, Hm / KC, 3);
     } else {
-        pack_matrix(buf, std::vector<float>(M1, M1 + (size_t)nout * H), nout, H, (nout + 15) / 16, H / KC, prec);
+        pack(std::vector<float>(M1, M1 + (size_t)nout * H), nout, H, (nout + 15) / 16, H / KC, 2);
         buf.resize(align256(buf.size()));
         off[3] = buf.size();
+    }
+    size_t offS[4] = {0, 0, 0, 0};
+    for (int i = 0; i < 4 && fp8; ++i) {
+        buf.resize(align256(buf.size()));
+        offS[i] = buf.size();
+        buf.resize(offS[i] + align256(sizeof(float) * std::max<size_t>(scales[i].size(), 1)));
+        if (!scales[i].empty()) std::memcpy(&buf[offS[i]], scales[i].data(), sizeof(float) * scales[i].size());
     }
     // moment tables of the FP64 right-hand side, shared by every flow of the model
     std::vector<double> A1, Mt;
@@ -299,6 +363,12 @@ int build_weights(const dnnmg_config &c, const float *w, hipStream_t st, Weights
     unsigned char *d = (unsigned char *)W->dev;
     W->net = NetArgs{c.K, H, Hm, nin, nout, prec, kc1, d + off[0], d + off[1], d + off[2], d + off[3],
                      nullptr, nullptr, nullptr, nullptr};
+    if (fp8) {
+        W->net.s1 = (const float *)(d + offS[0]);
+        W->net.s2 = (const float *)(d + offS[1]);
+        W->net.s3 = (const float *)(d + offS[2]);
+        W->net.s4 = (const float *)(d + offS[3]);
+    }
     W->tab = RhsTables{(const double *)(d + offA), (const double *)(d + offM)};
     *out = W;
     return DNNMG_OK;
@@ -311,9 +381,14 @@ size_t weight_bytes_estimate(const dnnmg_config &c)
     auto frag = [&](int rows, int cols) {
         return align256((size_t)((rows + 15) / 16) * ((cols + KC - 1) / KC) * 64 * KQ * eb);
     };
-    size_t b = 3 * (size_t)((c.H / 16) * ((s.nin + c.H + KC - 1) / KC) * 64 * KQ * eb);
+    const bool fp8 = c.precision == DNNMG_FP8_E4M3;
+    const int xw = fp8 ? xstride_fp8(s.nin) : s.nin;
+    size_t b = 3 * (size_t)((c.H / 16) * ((xw + c.H + KC - 1) / KC) * 64 * KQ * eb);
     b = align256(b) + frag(c.H, c.H);
     b += c.Hm > 0 ? frag(c.Hm, c.H) + frag(s.nout, c.Hm) : frag(s.nout, c.H);
+    if (fp8)
+        b += align256(sizeof(float) * 3 * c.H) + align256(sizeof(float) * c.H) +
+             align256(sizeof(float) * (c.Hm > 0 ? c.Hm : s.nout)) + align256(sizeof(float) * (c.Hm > 0 ? s.nout : 1));
     b = align256(b) + align256(sizeof(double) * 4 * (s.n + 1)) + align256(sizeof(double) * 48);
     return b + 256;
 }
@@ -381,7 +456,8 @@ FlowArgs flow_args(const dnnmg_ctx *c, const float *v, const float *p)
     f.h = c->h();
     f.uprev = c->uprev();
     f.X = c->X();
-    f.x_bf16 = c->cfg.precision == DNNMG_BF16;
+    f.xfmt = c->cfg.precision;
+    f.sx = c->sx();
     f.dpatch = c->dpatch();
     f.part = c->part();
     return f;
@@ -500,7 +576,7 @@ static int enqueue_step(dnnmg_ctx *c, const FlowArgs &f, hipStream_t st)
     Profile &pr = c->prof;
     hipEvent_t *ev = (pr.max_steps > 0 && pr.steps < pr.max_steps) ? &pr.ev[4 * pr.steps] : nullptr;
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[0], st));
-    HIP_OR_FAIL(launch_defect(f, nullptr, blocks_for(kKindDefect, g.nx, g.ny, g.K), g.K, f.x_bf16, st));
+    HIP_OR_FAIL(launch_defect(f, nullptr, blocks_for(kKindDefect, g.nx, g.ny, g.K), g.K, f.xfmt, st));
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[1], st));
     HIP_OR_FAIL(launch_net(f, nullptr, blocks_for(kKindNet, g.nx, g.ny, g.K), c->w->net, st));
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[2], st));
@@ -622,7 +698,7 @@ extern "C" int dnnmg_defect(dnnmg_ctx *ctx, const float *v, const float *p, floa
     f.D = D;
     f.X = nullptr;   // the stage leaves the network input alone
     HIP_OR_FAIL(launch_defect(f, nullptr, blocks_for(kKindDefect, ctx->cfg.nx, ctx->cfg.ny, ctx->cfg.K), ctx->cfg.K,
-                              f.x_bf16, (hipStream_t)stream));
+                              f.xfmt, (hipStream_t)stream));
     return DNNMG_OK;
 }
 
@@ -774,7 +850,7 @@ extern "C" int dnnmg_batch_prepare(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int n
     b->prepared = true;
     b->nflows = nflows;
     b->K = ctxs[0]->cfg.K;
-    b->x_bf16 = ctxs[0]->cfg.precision == DNNMG_BF16;
+    b->xfmt = ctxs[0]->cfg.precision;
     b->gather = b_out != nullptr;
     b->net = w->net;
     b->tab = ctxs[0]->tables();
@@ -791,7 +867,7 @@ static int batch_enqueue(dnnmg_batch *b, bool graph, hipStream_t st)
     FlowArgs dummy{};
     int grid[kKinds];
     for (int k = 0; k < kKinds; ++k) grid[k] = graph ? b->cap : std::min(b->totals[k], b->cap);
-    HIP_OR_FAIL(launch_defect(dummy, b->dev, grid[kKindDefect], b->K, b->x_bf16, st));
+    HIP_OR_FAIL(launch_defect(dummy, b->dev, grid[kKindDefect], b->K, b->xfmt, st));
     HIP_OR_FAIL(launch_net(dummy, b->dev, grid[kKindNet], b->net, st));
     HIP_OR_FAIL(launch_rhs(dummy, b->dev, grid[kKindRhs], b->K, b->tab, 1, st));
     if (b->gather) HIP_OR_FAIL(launch_gather(dummy, b->dev, grid[kKindGather], st));
@@ -805,7 +881,7 @@ extern "C" int dnnmg_batch_launch(dnnmg_batch *b, int use_graph, void *stream)
     hipStream_t st = (hipStream_t)stream;
     if (!use_graph) return batch_enqueue(b, false, st);
     if (!st) return fail(DNNMG_EINVAL, "graph launches need a non-default stream");
-    const bool same = b->exec && b->graph_K == b->K && b->graph_x_bf16 == b->x_bf16 &&
+    const bool same = b->exec && b->graph_K == b->K && b->graph_xfmt == b->xfmt &&
                       b->graph_gather == b->gather && same_net(b->graph_net, b->net) &&
                       b->graph_tab.A == b->tab.A && b->graph_tab.M == b->tab.M;
     if (!same) {
@@ -820,13 +896,22 @@ extern "C" int dnnmg_batch_launch(dnnmg_batch *b, int use_graph, void *stream)
         e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
         if (e != hipSuccess) { batch_drop_graph(b); return fail(DNNMG_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e)); }
         b->graph_K = b->K;
-        b->graph_x_bf16 = b->x_bf16;
+        b->graph_xfmt = b->xfmt;
         b->graph_gather = b->gather;
         b->graph_net = b->net;
         b->graph_tab = b->tab;
         b->captures++;
     }
     HIP_OR_FAIL(hipGraphLaunch(b->exec, st));
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_quantize_e4m3(const float *a_dev, int rows, int cols, unsigned char *q_dev, float *scale_dev,
+                                   void *stream)
+{
+    if (!a_dev || !q_dev || !scale_dev) return fail(DNNMG_EINVAL, "a, q and scale must not be NULL");
+    if (rows < 1 || cols < 1) return fail(DNNMG_EINVAL, "rows and cols must be >= 1 (got %d, %d)", rows, cols);
+    HIP_OR_FAIL(launch_quantize(a_dev, rows, cols, q_dev, scale_dev, (hipStream_t)stream));
     return DNNMG_OK;
 }
 

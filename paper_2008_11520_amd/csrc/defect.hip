@@ -5,7 +5,7 @@
 //   D_a,c = sum_e sum_q w_q |det J_q| [ (1/dt) phi_a (u_prev - v)_c - phi_a (v.grad v_c)
 //                                       - nu grad phi_a . grad v_c + p d_c phi_a ]
 // evaluated on the prolongated coarse fields v = P v_L, p = P p_L (Alg. 2,
-// line 6) and zeroed at Dirichlet nodes.  One workgroup owns a 16 x 16 tile of
+// line 6) and zeroed at Dirichlet nodes.  One workgroup owns a 32 x 32 tile of
 // fine elements plus a ring of one halo element, so that the nodes on the tile
 // border get every element contribution without global atomics; element
 // residuals go to LDS and are summed per node in a fixed order (bitwise
@@ -15,6 +15,9 @@
 // F(xi,eta) = c00 + ex xi + ey eta + exy xi eta (edge vectors formed in FP64 at
 // create time), so Jacobians keep full FP32 relative precision even when the
 // absolute coordinates are large compared with the fine mesh width.
+#include <type_traits>
+
+#include "fp8.h"
 #include "internal.h"
 
 namespace dnnmg {
@@ -174,13 +177,16 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
     constexpr int EPT = (NE * NE + kThreads - 1) / kThreads;   // elements per thread
 
     constexpr int nf = (n + 1) * (n + 1), nin = 4 * nf + 4;
-    constexpr size_t kWBytes = sizeof(float2) * NN * NN, kXBytes = sizeof(XT) * TP * TP * nin;
+    // XT = uint8_t: FP8 network input, assembled in FP32 and quantised per patch
+    constexpr bool FP8 = std::is_same<XT, uint8_t>::value;
+    typedef typename std::conditional<FP8, float, XT>::type ST;
+    constexpr size_t kWBytes = sizeof(float2) * NN * NN, kXBytes = sizeof(ST) * TP * TP * nin;
     __shared__ CoarseRec s_c[CE * CE];
     // (u_prev - P v) / dt at nodes; once the element residuals are formed the
     // same bytes hold the tile's network-input rows
     __shared__ __align__(16) unsigned char s_wx[kWBytes > kXBytes ? kWBytes : kXBytes];
     float2 *s_w = reinterpret_cast<float2 *>(s_wx);
-    XT *s_x = reinterpret_cast<XT *>(s_wx);
+    ST *s_x = reinterpret_cast<ST *>(s_wx);
     __shared__ float2 s_acc[NN * NN];           // assembled residual at nodes
 
     const int nx = f.nx, ny = f.ny, NX = nx * n, NY = ny * n;
@@ -384,11 +390,11 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
         const int pl = t / (nf + 1), l = t - pl * (nf + 1);
         const int pa = pl % TP, pb = pl / TP;
         const int pi = tx * TP + pa, pj = ty * TP + pb;
-        XT *o = s_x + pl * nin;
+        ST *o = s_x + pl * nin;
         if (pi >= nx || pj >= ny) continue;
         if (l == nf) {
             const float4 ft = reinterpret_cast<const float4 *>(f.feat)[(size_t)pj * nx + pi];
-            o[4 * nf] = (XT)ft.x; o[4 * nf + 1] = (XT)ft.y; o[4 * nf + 2] = (XT)ft.z; o[4 * nf + 3] = (XT)ft.w;
+            o[4 * nf] = (ST)ft.x; o[4 * nf + 1] = (ST)ft.y; o[4 * nf + 2] = (ST)ft.z; o[4 * nf + 3] = (ST)ft.w;
             continue;
         }
         const int a = l % (n + 1), b = l / (n + 1);
@@ -397,52 +403,95 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
         const float pvx = (r.V0x + r.V1x * xi) + eta * (r.V2x + r.V3x * xi);
         const float pvy = (r.V0y + r.V1y * xi) + eta * (r.V2y + r.V3y * xi);
         const float2 d = s_acc[(pb * n + b + 1) * NN + pa * n + a + 1];
-        o[2 * l] = (XT)pvx; o[2 * l + 1] = (XT)pvy;
-        o[2 * nf + 2 * l] = (XT)d.x; o[2 * nf + 2 * l + 1] = (XT)d.y;
+        o[2 * l] = (ST)pvx; o[2 * l + 1] = (ST)pvy;
+        o[2 * nf + 2 * l] = (ST)d.x; o[2 * nf + 2 * l + 1] = (ST)d.y;
     }
     __syncthreads();
-    constexpr int CPR = TP * nin * sizeof(XT) / 16;   // 16-byte pieces per tile row of patches
-    for (int t = tid; t < TP * CPR; t += kThreads) {
-        const int pb = t / CPR, c = t - pb * CPR;
-        const int pj = ty * TP + pb;
-        const int npr = min(TP, nx - tx * TP);        // patches of this tile row inside the mesh
-        if (pj >= ny || c * 16 >= npr * nin * (int)sizeof(XT)) continue;
-        const uint4 v = reinterpret_cast<const uint4 *>(s_x + pb * TP * nin)[c];
-        XT *dst = reinterpret_cast<XT *>(f.X) + ((size_t)pj * nx + tx * TP) * nin;
-        reinterpret_cast<uint4 *>(dst)[c] = v;
+    const int npr = min(TP, nx - tx * TP);            // patches of this tile row inside the mesh
+    if constexpr (FP8) {
+        // per-patch scale: m = max(max |x|, floor), codes e4m3(x * 448/m),
+        // scale m/448; TPR threads per patch row reduce the maximum
+        constexpr int ROWS = TP * TP, TPR = kThreads / ROWS;
+        static_assert(TPR >= 1 && 64 % TPR == 0, "patch rows per wave");
+        __shared__ float s_r[ROWS];
+        {
+            const int pl = tid / TPR, sub = tid - pl * TPR;
+            float m = 0.0f;
+            for (int k = sub; k < nin; k += TPR) m = fmaxf(m, fabsf(s_x[pl * nin + k]));
+#pragma unroll
+            for (int o = TPR / 2; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+            m = fmaxf(m, kFp8MinMax);
+            const int pa = pl % TP, pb = pl / TP, pi = tx * TP + pa, pj = ty * TP + pb;
+            if (sub == 0) {
+                s_r[pl] = 448.0f / m;
+                if (pi < nx && pj < ny) f.sx[(size_t)pj * nx + pi] = m / 448.0f;
+            }
+        }
+        __syncthreads();
+        // rows of xstride bytes (zero beyond nin), 16 codes per item
+        constexpr int XS = xstride_fp8(nin), CPR = TP * XS / 16;
+        for (int t = tid; t < TP * CPR; t += kThreads) {
+            const int pb = t / CPR, c = t - pb * CPR;
+            const int pj = ty * TP + pb;
+            if (pj >= ny || c * 16 >= npr * XS) continue;
+            const int pa = c * 16 / XS, k0 = c * 16 - pa * XS;
+            const int pl = pb * TP + pa;
+            const float r = s_r[pl];
+            const ST *row = s_x + pl * nin;
+            float v[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = (k0 + i < nin) ? row[k0 + i] * r : 0.0f;
+            uint4 w;
+            w.x = pack4_e4m3(v[0], v[1], v[2], v[3]);
+            w.y = pack4_e4m3(v[4], v[5], v[6], v[7]);
+            w.z = pack4_e4m3(v[8], v[9], v[10], v[11]);
+            w.w = pack4_e4m3(v[12], v[13], v[14], v[15]);
+            uint8_t *dst = reinterpret_cast<uint8_t *>(f.X) + ((size_t)pj * nx + tx * TP) * XS;
+            reinterpret_cast<uint4 *>(dst)[c] = w;
+        }
+    } else {
+        constexpr int CPR = TP * nin * sizeof(XT) / 16;   // 16-byte pieces per tile row of patches
+        for (int t = tid; t < TP * CPR; t += kThreads) {
+            const int pb = t / CPR, c = t - pb * CPR;
+            const int pj = ty * TP + pb;
+            if (pj >= ny || c * 16 >= npr * nin * (int)sizeof(XT)) continue;
+            const uint4 v = reinterpret_cast<const uint4 *>(s_x + pb * TP * nin)[c];
+            XT *dst = reinterpret_cast<XT *>(f.X) + ((size_t)pj * nx + tx * TP) * nin;
+            reinterpret_cast<uint4 *>(dst)[c] = v;
+        }
     }
 }
 
 // Single flow: one tile per block.  Batched: the blocks stride over the
 // table's tiles of all flows, so the grid need not match the batch.
 template <int K, typename XT, bool BATCHED>
-__global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const BatchTable *bt)
+__global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const BatchTable *__restrict__ bt)
 {
     if (!BATCHED) {
         defect_tile<K, XT>(single, blockIdx.x);
         return;
     }
     const int total = bt->prefix[kKindDefect][bt->nflows];
+#pragma unroll 1
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         int blk = g;
-        const FlowArgs f = *batch_flow(bt, kKindDefect, blk);
+        const FlowArgs &f = *batch_flow(bt, kKindDefect, blk);
         defect_tile<K, XT>(f, blk);
         __syncthreads();   // LDS is reused by the next tile
     }
 }
 
-hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, int x_bf16, hipStream_t s)
+hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, int xfmt, hipStream_t s)
 {
     dim3 g(nblocks), b(kThreads);
+#define DNNMG_DEFECT_LAUNCH(KK, XT)                                                           \
+    if (bt) hipLaunchKernelGGL((k_defect<KK, XT, true>), g, b, 0, s, f, bt);                   \
+    else hipLaunchKernelGGL((k_defect<KK, XT, false>), g, b, 0, s, f, bt);
 #define DNNMG_DEFECT_CASE(KK)                                                                 \
     case KK:                                                                                  \
-        if (bt) {                                                                             \
-            if (x_bf16) hipLaunchKernelGGL((k_defect<KK, __bf16, true>), g, b, 0, s, f, bt);  \
-            else hipLaunchKernelGGL((k_defect<KK, float, true>), g, b, 0, s, f, bt);          \
-        } else {                                                                              \
-            if (x_bf16) hipLaunchKernelGGL((k_defect<KK, __bf16, false>), g, b, 0, s, f, bt); \
-            else hipLaunchKernelGGL((k_defect<KK, float, false>), g, b, 0, s, f, bt);         \
-        }                                                                                     \
+        if (xfmt == 1) { DNNMG_DEFECT_LAUNCH(KK, __bf16) }                                    \
+        else if (xfmt == 2) { DNNMG_DEFECT_LAUNCH(KK, uint8_t) }                              \
+        else { DNNMG_DEFECT_LAUNCH(KK, float) }                                               \
         break;
     switch (K) {
         DNNMG_DEFECT_CASE(1)
@@ -451,6 +500,7 @@ hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, i
     default: return hipErrorInvalidValue;
     }
 #undef DNNMG_DEFECT_CASE
+#undef DNNMG_DEFECT_LAUNCH
     return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ constexpr int kMaxBatch = 256;    // flows per batched launch
 struct FlowArgs {
     int nx, ny;
     unsigned dirichlet;
-    int x_bf16;            // network input stored as BF16 (BF16 operand form)
+    int xfmt;              // network input storage: 0 FP32, 1 BF16, 2 FP8 E4M3 with per-patch scales
     float inv_dt, nu;
     double inv_dt64;
     const float *v;        // (ny+1)(nx+1) x 2
@@ -28,7 +28,9 @@ struct FlowArgs {
     int *first_flag;       // device: nonzero before the first step (then u_prev := P v)
     float *h;              // P x H
     float *uprev;          // Fn x 2
-    float *X;              // P x nin network input (FP32, or BF16 when x_bf16); the step writes it
+    float *X;              // network input, the step writes it: P x nin FP32 or BF16, or for FP8
+                           // P rows of xstride(nin) E4M3 codes (zero beyond nin)
+    float *sx;             // FP8: per-patch scale of X
     float *dpatch;         // P x nout
     double *part;          // 4 x P x 2: per-patch rhs contribution, one plane per corner
     float *dbar_out;       // optional Fn x 2
@@ -65,6 +67,14 @@ struct BatchTable {
     FlowArgs flows[kMaxBatch];
 };
 
+// FP8 E4M3 operands.  Row stride (bytes) of the FP8 network input: nin
+// rounded up to the 32-wide k-chunk, so the input and the state occupy
+// separate chunks (they carry separate scales).
+__host__ __device__ constexpr int xstride_fp8(int nin) { return (nin + 31) / 32 * 32; }
+// Smallest row maximum a scale is computed from (keeps 448 / m finite).
+constexpr float kFp8MinMax = 448.0f * 0x1p-64f;
+
+
 // Blocks each kernel kind needs for one flow.
 int blocks_for(int kind, int nx, int ny, int K);
 
@@ -72,7 +82,9 @@ int blocks_for(int kind, int nx, int ny, int K);
 hipError_t launch_geometry(const double *cxy, int nx, int ny, float *geo, double *geo64,
                            float *feat, int *bad, hipStream_t s);
 hipError_t launch_prolong(const FlowArgs &f, int K, float *pv, float *pp, hipStream_t s);
-hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, int x_bf16, hipStream_t s);
+hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, int xfmt, hipStream_t s);
+// FP8 activation quantiser (stage entry point): rows x cols FP32 -> codes, scales.
+hipError_t launch_quantize(const float *a, int rows, int cols, uint8_t *q, float *s, hipStream_t st);
 hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net,
                       hipStream_t s);
 // Blocks of the network launch (persistent kernels use fewer than row tiles).

@@ -18,6 +18,7 @@
 // Fragment convention (both forms): in k-chunk kc, lane l = i + 16 q holds
 // operand values at k = kc*KC + q*KQ + e, e < KQ (A: row i; B: column i).
 // The 16 x 16 f32 result tile gives lane l rows 4 q + e (e < 4) of column i.
+#include "fp8.h"
 #include "internal.h"
 
 namespace dnnmg {
@@ -221,21 +222,292 @@ __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net
 // Single flow: one tile per block.  Batched: the blocks stride over the
 // table's tiles of all flows, so the grid need not match the batch.
 template <int PREC, int H, bool BATCHED>
-__global__ __launch_bounds__(kThreads) void k_net(FlowArgs single, const BatchTable *bt, NetArgs net)
+__global__ __launch_bounds__(kThreads) void k_net(FlowArgs single, const BatchTable *__restrict__ bt, NetArgs net)
 {
     if (!BATCHED) {
         net_tile<PREC, H>(single, blockIdx.x, net);
         return;
     }
     const int total = bt->prefix[kKindNet][bt->nflows];
+#pragma unroll 1
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         int blk = g;
-        const FlowArgs f = *batch_flow(bt, kKindNet, blk);
+        const FlowArgs &f = *batch_flow(bt, kKindNet, blk);
         net_tile<PREC, H>(f, blk, net);
         __syncthreads();   // LDS is reused by the next tile
     }
 }
 
+
+// ---------------------------------------------------------------- FP8 E4M3
+// Every product takes E4M3 operands with one FP32 scale per row and
+// accumulates in FP32: weights per output row (packed at create), the
+// network input per patch (quantised by the defect kernel), and the state h,
+// r*h, h' and the MLP hidden layer per patch, quantised here.  The input and
+// the state of the gate products carry separate scales, so their k-chunks are
+// accumulated separately: the input part is rescaled by s_x / s_h before the
+// state part is added, and the sum by s_h s_w at the end.
+typedef long f8x8;   // 8 E4M3 codes: one MFMA operand fragment
+
+__device__ inline f8x8 mma_fp8_operand(const uint8_t *p) { return *reinterpret_cast<const f8x8 *>(p); }
+
+__device__ inline f4 mma_fp8(f4 acc, f8x8 a, f8x8 b)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, acc, 0, 0, 0);
+}
+
+// Row maximum over the 16 lanes that share lq (the 16 columns of a tile).
+__device__ inline float max16(float m)
+{
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
+    return m;
+}
+
+template <int H>
+__device__ __forceinline__ void net_tile_fp8(const FlowArgs &f, int blk, NetArgs net)
+{
+    constexpr int KC = 32, KQ = 8, HT = H / 16, HC = H / 32;
+    constexpr int LDH = H + 16;                // bytes per staged row (16-byte padding)
+    constexpr int LDM = 256 + 16;
+    constexpr int MT_MAX = 256 / 16;           // MLP hidden tiles (Hm <= 256)
+    __shared__ __align__(16) uint8_t sR[4][16 * LDH];
+    __shared__ __align__(16) uint8_t sHp[4][16 * LDH];
+    __shared__ __align__(16) uint8_t sAm[4][16 * LDM];
+
+    const int P = f.nx * f.ny;
+    const int nin = net.nin, nout = net.nout, Hm = net.Hm, kc1 = net.kc1;
+    const int XS = xstride_fp8(nin), kcx = XS / KC;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = lane & 15, lq = lane >> 4;
+    const int rbase = blk * kNetRows + wave * 16;   // first patch row of this wave
+    const int arow = rbase + li;                    // row this lane supplies A values for
+    const bool aok = arow < P;
+    const uint8_t *X8 = reinterpret_cast<const uint8_t *>(f.X);
+    const f8x8 *B1 = reinterpret_cast<const f8x8 *>(net.B1);
+    const f8x8 *B2 = reinterpret_cast<const f8x8 *>(net.B2);
+    const f8x8 *B3 = reinterpret_cast<const f8x8 *>(net.B3);
+    const f8x8 *B4 = reinterpret_cast<const f8x8 *>(net.B4);
+
+    // ---- the state row of this lane's A row: scale and codes
+    float hv[HC][KQ];
+    float mh = 0.0f;
+#pragma unroll
+    for (int kh = 0; kh < HC; ++kh)
+#pragma unroll
+        for (int e = 0; e < KQ; ++e) {
+            hv[kh][e] = aok ? f.h[(size_t)arow * H + kh * KC + lq * KQ + e] : 0.0f;
+            mh = fmaxf(mh, fabsf(hv[kh][e]));
+        }
+    mh = fmaxf(mh, __shfl_xor(mh, 16));
+    mh = fmaxf(mh, __shfl_xor(mh, 32));
+    mh = fmaxf(mh, kFp8MinMax);
+    const float rh_li = 448.0f / mh, sh_li = mh / 448.0f;
+    f8x8 qh[HC];
+#pragma unroll
+    for (int kh = 0; kh < HC; ++kh) {
+        const uint32_t lo = pack4_e4m3(hv[kh][0] * rh_li, hv[kh][1] * rh_li, hv[kh][2] * rh_li, hv[kh][3] * rh_li);
+        const uint32_t hi = pack4_e4m3(hv[kh][4] * rh_li, hv[kh][5] * rh_li, hv[kh][6] * rh_li, hv[kh][7] * rh_li);
+        qh[kh] = (f8x8)(((unsigned long)hi << 32) | lo);
+    }
+
+    // ---- phase 1, input chunks: x . [W_z W_r W_h]
+    f4 az[HT], ar[HT], ah[HT];
+#pragma unroll
+    for (int t = 0; t < HT; ++t) az[t] = ar[t] = ah[t] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < kcx; ++kc) {
+        const f8x8 a = aok ? mma_fp8_operand(X8 + (size_t)arow * XS + kc * KC + lq * KQ) : 0;
+#pragma unroll
+        for (int t = 0; t < HT; ++t) {
+            az[t] = mma_fp8(az[t], a, B1[((0 * HT + t) * kc1 + kc) * 64 + lane]);
+            ar[t] = mma_fp8(ar[t], a, B1[((1 * HT + t) * kc1 + kc) * 64 + lane]);
+            ah[t] = mma_fp8(ah[t], a, B1[((2 * HT + t) * kc1 + kc) * 64 + lane]);
+        }
+    }
+    // accumulator element e is patch row rbase + 4 lq + e
+    float sx[4], sh[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int row = rbase + 4 * lq + e;
+        sx[e] = row < P ? f.sx[row] : 1.0f;
+        sh[e] = __shfl(sh_li, 4 * lq + e);
+        const float ratio = sx[e] / sh[e];
+#pragma unroll
+        for (int t = 0; t < HT; ++t) { az[t][e] *= ratio; ar[t][e] *= ratio; }
+    }
+    // ---- phase 1, state chunks: h . [U_z U_r] (the candidate has no U block here)
+#pragma unroll
+    for (int kh = 0; kh < HC; ++kh)
+#pragma unroll
+        for (int t = 0; t < HT; ++t) {
+            az[t] = mma_fp8(az[t], qh[kh], B1[((0 * HT + t) * kc1 + kcx + kh) * 64 + lane]);
+            ar[t] = mma_fp8(ar[t], qh[kh], B1[((1 * HT + t) * kc1 + kcx + kh) * 64 + lane]);
+        }
+
+    // ---- gates; r*h.  Lane holds rows rbase + 4 lq + e, column 16 t + li.
+    float hold[HT][4];
+    float mr[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < HT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = rbase + 4 * lq + e, k = 16 * t + li;
+            const float h0 = row < P ? f.h[(size_t)row * H + k] : 0.f;
+            hold[t][e] = h0;
+            az[t][e] = sigmoid(az[t][e] * sh[e] * net.s1[k]);
+            const float rh = sigmoid(ar[t][e] * sh[e] * net.s1[H + k]) * h0;
+            ar[t][e] = rh;
+            mr[e] = fmaxf(mr[e], fabsf(rh));
+            ah[t][e] *= sx[e] * net.s1[2 * H + k];
+        }
+    float srh[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float m = fmaxf(max16(mr[e]), kFp8MinMax);
+        const float r = 448.0f / m;
+        srh[e] = m / 448.0f;
+#pragma unroll
+        for (int t = 0; t < HT; ++t) sR[wave][(4 * lq + e) * LDH + 16 * t + li] = to_e4m3(ar[t][e] * r);
+    }
+    __syncthreads();
+
+    // ---- phase 2: (r*h) . U_h^T; new state
+    f4 au[HT];
+#pragma unroll
+    for (int t = 0; t < HT; ++t) au[t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < HC; ++kc) {
+        const f8x8 a = mma_fp8_operand(&sR[wave][li * LDH + kc * KC + lq * KQ]);
+#pragma unroll
+        for (int t = 0; t < HT; ++t) au[t] = mma_fp8(au[t], a, B2[(t * HC + kc) * 64 + lane]);
+    }
+    float mp[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < HT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = rbase + 4 * lq + e, k = 16 * t + li;
+            const float z = az[t][e];
+            const float hh = fast_tanh(ah[t][e] + au[t][e] * srh[e] * net.s2[k]);
+            const float hn = z * hold[t][e] + (1.0f - z) * hh;
+            if (row < P) f.h[(size_t)row * H + k] = hn;
+            au[t][e] = hn;
+            mp[e] = fmaxf(mp[e], fabsf(hn));
+        }
+    float shp[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float m = fmaxf(max16(mp[e]), kFp8MinMax);
+        const float r = 448.0f / m;
+        shp[e] = m / 448.0f;
+#pragma unroll
+        for (int t = 0; t < HT; ++t) sHp[wave][(4 * lq + e) * LDH + 16 * t + li] = to_e4m3(au[t][e] * r);
+    }
+    __syncthreads();
+
+    // ---- MLP head
+    const int ot_n = (nout + 15) / 16;
+    const uint8_t *src = sHp[wave];
+    int lds = LDH, kcs = HC;
+    const f8x8 *Bo = B3;
+    const float *so = net.s3;
+    float sin_[4] = {shp[0], shp[1], shp[2], shp[3]};
+    if (Hm > 0) {
+        float am[MT_MAX][4];
+        float ma[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int mt = 0; mt < MT_MAX; ++mt) {
+            if (mt < Hm / 16) {
+                f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kc = 0; kc < HC; ++kc) {
+                    const f8x8 a = mma_fp8_operand(&sHp[wave][li * LDH + kc * KC + lq * KQ]);
+                    acc = mma_fp8(acc, a, B3[(mt * HC + kc) * 64 + lane]);
+                }
+                const float sw = net.s3[16 * mt + li];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    am[mt][e] = fmaxf(acc[e] * shp[e] * sw, 0.f);
+                    ma[e] = fmaxf(ma[e], am[mt][e]);
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float m = fmaxf(max16(ma[e]), kFp8MinMax);
+            const float r = 448.0f / m;
+            sin_[e] = m / 448.0f;
+#pragma unroll
+            for (int mt = 0; mt < MT_MAX; ++mt)
+                if (mt < Hm / 16) sAm[wave][(4 * lq + e) * LDM + 16 * mt + li] = to_e4m3(am[mt][e] * r);
+        }
+        __syncthreads();
+        src = sAm[wave];
+        lds = LDM;
+        kcs = Hm / KC;
+        Bo = B4;
+        so = net.s4;
+    }
+    for (int ot = 0; ot < ot_n; ++ot) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int kc = 0; kc < kcs; ++kc) {
+            const f8x8 a = mma_fp8_operand(&src[li * lds + kc * KC + lq * KQ]);
+            acc = mma_fp8(acc, a, Bo[(ot * kcs + kc) * 64 + lane]);
+        }
+        const int o = 16 * ot + li;
+        if (o < nout) {
+            const float sw = so[o];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = rbase + 4 * lq + e;
+                if (row < P) f.dpatch[(size_t)row * nout + o] = acc[e] * sin_[e] * sw;
+            }
+        }
+    }
+}
+
+// Stage entry point: the per-row activation quantiser of the FP8 form on its
+// own, one workgroup per row.
+__global__ __launch_bounds__(kThreads) void k_quantize(const float *a, int rows, int cols, uint8_t *q, float *s)
+{
+    __shared__ float sm[kThreads / 64];
+    const int row = blockIdx.x;
+    const float *ar = a + (size_t)row * cols;
+    float m = 0.0f;
+    for (int k = threadIdx.x; k < cols; k += kThreads) m = fmaxf(m, fabsf(ar[k]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = fmaxf(fmaxf(sm[0], sm[1]), fmaxf(sm[2], sm[3]));
+    m = fmaxf(m, kFp8MinMax);
+    const float r = 448.0f / m;
+    if (threadIdx.x == 0) s[row] = m / 448.0f;
+    for (int k = threadIdx.x; k < cols; k += kThreads) q[(size_t)row * cols + k] = to_e4m3(ar[k] * r);
+}
+
+hipError_t launch_quantize(const float *a, int rows, int cols, uint8_t *q, float *s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_quantize, dim3(rows), dim3(kThreads), 0, st, a, rows, cols, q, s);
+    return hipGetLastError();
+}
+
+template <int H, bool BATCHED>
+__global__ __launch_bounds__(kThreads) void k_net_fp8(FlowArgs single, const BatchTable *__restrict__ bt, NetArgs net)
+{
+    if (!BATCHED) {
+        net_tile_fp8<H>(single, blockIdx.x, net);
+        return;
+    }
+    const int total = bt->prefix[kKindNet][bt->nflows];
+#pragma unroll 1
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        int blk = g;
+        const FlowArgs &f = *batch_flow(bt, kKindNet, blk);
+        net_tile_fp8<H>(f, blk, net);
+        __syncthreads();   // LDS is reused by the next tile
+    }
+}
 
 // Persistent BF16 kernel for H = 64 (and Hm 0 or 64).  Eight waves: wave w
 // owns hidden tile w % 4 for row tiles 2 (w / 4) and 2 (w / 4) + 1 of each
@@ -246,7 +518,7 @@ __global__ __launch_bounds__(kThreads) void k_net(FlowArgs single, const BatchTa
 constexpr int kNetH64Threads = 512;
 
 template <int K>
-__global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, const BatchTable *bt, NetArgs net,
+__global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, const BatchTable *__restrict__ bt, NetArgs net,
                                                                int ntiles)
 {
     typedef Op<1> O;
@@ -485,6 +757,20 @@ hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int ntiles, const
         if (net.K == 1) hipLaunchKernelGGL(k_net_h64<1>, dim3(nblocks), dim3(kNetH64Threads), 0, s, f, bt, net, ntiles);
         else hipLaunchKernelGGL(k_net_h64<2>, dim3(nblocks), dim3(kNetH64Threads), 0, s, f, bt, net, ntiles);
         return hipGetLastError();
+    }
+    if (net.prec == 2) {
+        dim3 g(nblocks), b(kThreads);
+#define DNNMG_FP8_CASE(HH)                                                                  \
+        if (net.H == HH) {                                                                  \
+            if (bt) hipLaunchKernelGGL((k_net_fp8<HH, true>), g, b, 0, s, f, bt, net);      \
+            else hipLaunchKernelGGL((k_net_fp8<HH, false>), g, b, 0, s, f, bt, net);        \
+            return hipGetLastError();                                                       \
+        }
+        DNNMG_FP8_CASE(32)
+        DNNMG_FP8_CASE(64)
+        DNNMG_FP8_CASE(128)
+#undef DNNMG_FP8_CASE
+        return hipErrorInvalidValue;
     }
     if (net.prec == 0) {
         if (net.H == 32) return launch_net_t<0, 32>(f, bt, nblocks, net, s);

@@ -190,16 +190,17 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
 // Single flow: one tile per block.  Batched: the blocks stride over the
 // table's tiles of all flows, so the grid need not match the batch.
 template <int K, int FROM_PATCHES, bool BATCHED>
-__global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTable *bt, RhsTables tab)
+__global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTable *__restrict__ bt, RhsTables tab)
 {
     if (!BATCHED) {
         rhs_tile<K, FROM_PATCHES>(single, blockIdx.x, tab);
         return;
     }
     const int total = bt->prefix[kKindRhs][bt->nflows];
+#pragma unroll 1
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         int blk = g;
-        const FlowArgs f = *batch_flow(bt, kKindRhs, blk);
+        const FlowArgs &f = *batch_flow(bt, kKindRhs, blk);
         rhs_tile<K, FROM_PATCHES>(f, blk, tab);
         __syncthreads();   // LDS is reused by the next tile
     }
@@ -226,16 +227,17 @@ __device__ __forceinline__ void gather_tile(const FlowArgs &f, int blk)
 
 // Single flow: one tile per block.  Batched: the blocks stride over the
 template <bool BATCHED>
-__global__ __launch_bounds__(kThreads) void k_gather(FlowArgs single, const BatchTable *bt)
+__global__ __launch_bounds__(kThreads) void k_gather(FlowArgs single, const BatchTable *__restrict__ bt)
 {
     if (!BATCHED) {
         gather_tile(single, blockIdx.x);
         return;
     }
     const int total = bt->prefix[kKindGather][bt->nflows];
+#pragma unroll 1
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         int blk = g;
-        const FlowArgs f = *batch_flow(bt, kKindGather, blk);
+        const FlowArgs &f = *batch_flow(bt, kKindGather, blk);
         gather_tile(f, blk);
     }
 }

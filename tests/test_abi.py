@@ -19,7 +19,7 @@ if not os.path.exists(pam.LIB_PATH):
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(dnnmg_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(dnnmg_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -113,3 +113,15 @@ def test_calls_on_null_context_fail_cleanly():
     assert L.dnnmg_batch_create(0, ctypes.byref(out)) == pam.DNNMG_EINVAL
     assert L.dnnmg_batch_create(100000, ctypes.byref(out)) == pam.DNNMG_EINVAL
     assert L.dnnmg_step_batch(None, None, 1, None, None, None, None) == pam.DNNMG_EINVAL
+
+
+def test_fp8_config_sizes_and_quantiser_validation():
+    c8, c16 = cfg(nx=64, ny=32, precision=2), cfg(nx=64, ny=32, precision=1)
+    assert pam.workspace_bytes(c8) > 0
+    # FP8 network input: 128 bytes + a 4-byte scale per patch instead of 208 BF16 bytes
+    assert pam.workspace_bytes(c8) < pam.workspace_bytes(c16)
+    L = pam.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.dnnmg_quantize_e4m3(None, 1, 1, fake, fake, None) == pam.DNNMG_EINVAL
+    assert L.dnnmg_quantize_e4m3(fake, 0, 4, fake, fake, None) == pam.DNNMG_EINVAL
+    assert L.dnnmg_quantize_e4m3(fake, 4, 0, fake, fake, None) == pam.DNNMG_EINVAL
