@@ -142,6 +142,48 @@ def run_gpu(wl, precision, steps, warmup):
     return dict(ms_total=ms, wall_s=wall, P=s["P"], stage_ms=stage_ms, stage_n=stage_n, finite=ok)
 
 
+def run_gpu_batch(wl, precision, steps, warmup):
+    """A multi-flow workload: every flow stepped together by one batched,
+    graph-captured launch per step (with the restriction)."""
+    import torch
+    import paper_2008_11520_amd as pam
+    from paper_2008_11520_amd import synth
+    w = synth.xavier_weights(wl.K, wl.H, wl.Hm, wl.weight_seed)
+    cfg0 = lambda f: pam.make_config(f.nx, f.ny, wl.K, wl.H, wl.Hm, f.dt, wl.nu, precision, f.dirichlet)
+    model = pam.DnnMG(cfg0(wl.flows[0]), wl.flows[0].cxy, w)
+    ctxs = [pam.DnnMG(cfg0(f), f.cxy, share=model) for f in wl.flows]
+    nfield = min(warmup + steps, 4)
+    vs = [[torch.from_numpy(f.fields(n)[0].reshape(-1)).cuda() for f in wl.flows] for n in range(nfield)]
+    ps = [[torch.from_numpy(f.fields(n)[1]).cuda() for f in wl.flows] for n in range(nfield)]
+    bs = [torch.empty(2 * c.s["Nc"], dtype=torch.float64, device="cuda") for c in ctxs]
+    batch = pam.Batch(len(ctxs))
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for n in range(warmup):
+            batch.prepare(ctxs, vs[n % nfield], ps[n % nfield], None, bs, stream=st)
+            batch.launch(graph=True, stream=st)
+    st.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(st):
+        e0.record(st)
+        for n in range(steps):
+            k = (warmup + n) % nfield
+            batch.prepare(ctxs, vs[k], ps[k], None, bs, stream=st)
+            batch.launch(graph=True, stream=st)
+        e1.record(st)
+    st.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ok = all(bool(torch.isfinite(b).all().item()) for b in bs)
+    P = sum(c.s["P"] for c in ctxs)
+    batch.close()
+    for c in ctxs:
+        c.close()
+    model.close()
+    return dict(ms_total=ms, wall_s=wall, P=P, stage_ms=None, stage_n=None, finite=ok)
+
+
 def cpu_baseline(wl, sample_steps=2):
     import oracle
     from paper_2008_11520_amd import synth
@@ -179,13 +221,41 @@ def run_serving(time_scales, n_requests=256, rate=20.0, hbm_budget=None, use_gra
     return out
 
 
+def roofline(wl, flow, P, main_r, precision):
+    """Roofline of the dominant stage: per-launch algorithmic work over the
+    stage's average launch time from the library's HIP events on the launch
+    stream."""
+    avg = [main_r["stage_ms"][k] / max(main_r["stage_n"][k], 1) for k in range(4)]
+    dom = int(np.argmax(avg))
+    t_s = avg[dom] / 1e3
+    if dom == 0:
+        unit_work = stencil_flop_per_patch(wl.K)
+        achieved = unit_work * P / t_s / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS}
+    elif dom == 1:
+        unit_work = per_patch_gemm_flop(wl.K, wl.H, wl.Hm)
+        peak = PEAK_TFLOPS[precision]
+        achieved = unit_work * P / t_s / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}
+    else:
+        unit_work = rhs_bytes_per_patch(wl.K) if dom == 2 else 5 * 16 * (flow.nx + 1) * (flow.ny + 1) / P
+        achieved = unit_work * P / t_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS}
+    roof.update({"traffic": stored_traffic(dom, wl.name, precision), "kernel": STAGES[dom],
+                 "avg_launch_us": avg[dom] * 1e3, "algorithmic_per_patch": unit_work,
+                 "units_per_launch": P})
+    return roof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="channel1024x256_k2_perturbed")
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
     ap.add_argument("--serving", default="offered,all", metavar="LIST",
@@ -212,8 +282,9 @@ def main():
                                                                      args.steps), file=sys.stderr, flush=True)
 
     forms = {}
-    for prec in ([args.precision] + [p for p in ("bf16", "fp32") if p != args.precision]):
-        r = run_gpu(wl, prec, args.steps, args.warmup)
+    batched = len(wl.flows) > 1
+    for prec in ([args.precision] + [p for p in ("bf16", "fp32", "fp8") if p != args.precision]):
+        r = (run_gpu_batch if batched else run_gpu)(wl, prec, args.steps, args.warmup)
         forms[prec] = r
         print("bench: %s %.3f ms/step" % (prec, r["ms_total"] / args.steps), file=sys.stderr, flush=True)
 
@@ -224,27 +295,9 @@ def main():
 
     # dominant kernel and its roofline (per-launch algorithmic work / average
     # launch time from the library's HIP events on the launch stream)
-    avg = [main_r["stage_ms"][k] / max(main_r["stage_n"][k], 1) for k in range(4)]
-    dom = int(np.argmax(avg))
-    t_s = avg[dom] / 1e3
-    if dom == 0:
-        unit_work = stencil_flop_per_patch(wl.K)
-        achieved = unit_work * P / t_s / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS}
-    elif dom == 1:
-        unit_work = per_patch_gemm_flop(wl.K, wl.H, wl.Hm)
-        peak = PEAK_TFLOPS[args.precision]
-        achieved = unit_work * P / t_s / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}
-    else:
-        unit_work = rhs_bytes_per_patch(wl.K) if dom == 2 else 5 * 16 * (flow.nx + 1) * (flow.ny + 1) / P
-        achieved = unit_work * P / t_s / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS}
-    roof.update({"traffic": stored_traffic(dom, wl.name, args.precision), "kernel": STAGES[dom],
-                 "avg_launch_us": avg[dom] * 1e3, "algorithmic_per_patch": unit_work,
-                 "units_per_launch": P})
+    roof = None
+    if main_r["stage_ms"] is not None:
+        roof = roofline(wl, flow, P, main_r, args.precision)
     step_bytes = per_patch_step_bytes(wl.K, wl.H) * P
     out = {
         "metric": "patch-steps/sec of fine DNN-MG step (BF16 vs FP32); serving p50/p99 step latency",
@@ -258,12 +311,13 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.precision,
-        "data": "synthetic (seeded channel mesh, Fourier-mode coarse fields, Xavier weights)",
+        "data": "synthetic (seeded meshes, Fourier-mode coarse fields, Xavier weights)",
         "config": {"workload": wl.name, "patches": P, "K": wl.K, "H": wl.H, "Hm": wl.Hm,
                    "gemm_operands": args.precision, "defect": "f32", "rhs_restriction": "f64"},
         "forms": {p: {"patch_steps_per_s": P * args.steps / (r["ms_total"] / 1e3),
                       "ms_per_step": r["ms_total"] / args.steps,
-                      "stage_us": {STAGES[k]: r["stage_ms"][k] / max(r["stage_n"][k], 1) * 1e3 for k in range(4)}}
+                      "stage_us": ({STAGES[k]: r["stage_ms"][k] / max(r["stage_n"][k], 1) * 1e3 for k in range(4)}
+                                   if r["stage_ms"] is not None else None)}
                   for p, r in forms.items()},
         "step_hbm": {"algorithmic_bytes_per_patch": per_patch_step_bytes(wl.K, wl.H),
                      "achieved_GBs": step_bytes / (ms_step / 1e3) / 1e9,

@@ -1,0 +1,74 @@
+"""The stretched-mesh workload at full size: 64 concurrent flows of 128 x 128
+coarse elements on [0, s_f] x [0, 1] (s_f ~ U[1, 8], all-Dirichlet), K = 3,
+H = 128, MLP 128-128-162, stepped together through one batched, graph-
+captured launch in BF16 and in FP8 E4M3.  Sampled flows are checked on
+windows the oracle computes in seconds (outputs more than 3 patches from a
+window edge depend on window data only): BF16 against the FP64 step (2e-2),
+FP8 against the oracle's FP8 form (2e-2, see test_gpu_fp8)."""
+import numpy as np
+import pytest
+
+from paper_2008_11520_amd import synth
+
+from gpu_common import make_gpu_flow, make_oracle_flow, rel_l2, to_dev, window, window_fields
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2008_11520_amd as pam
+    pam.lib()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_stretched_64_flows_k3_batched_sampled_windows(prec):
+    import torch
+    import paper_2008_11520_amd as pam
+    wl = synth.workload("stretched64x128x128_k3")
+    K, H, Hm = wl.K, wl.H, wl.Hm
+    w = synth.xavier_weights(K, H, Hm, wl.weight_seed)
+    n = 1 << K
+    model = make_gpu_flow(wl.flows[0], K, H, Hm, wl.nu, w, prec)
+    ctxs = [make_gpu_flow(f, K, H, Hm, wl.nu, w, prec, share=model) for f in wl.flows]
+    s = ctxs[0].s
+    dbar = [torch.empty(2 * s["Fn"], dtype=torch.float32, device="cuda") for _ in ctxs]
+    bL = [torch.empty(2 * s["Nc"], dtype=torch.float64, device="cuda") for _ in ctxs]
+    batch = pam.Batch(64)
+    st = torch.cuda.Stream()
+    fields = [f.fields(0) for f in wl.flows]
+    with torch.cuda.stream(st):
+        vs = [to_dev(v.reshape(-1)) for v, _ in fields]
+        ps = [to_dev(p) for _, p in fields]
+        batch.prepare(ctxs, vs, ps, dbar, bL, stream=st)
+        batch.launch(graph=True, stream=st)
+    st.synchronize()
+    m = 3
+    for fi, (i0, j0) in ((0, (0, 0)), (17, (60, 50)), (63, (116, 116)), (40, (0, 100))):
+        flow = wl.flows[fi]
+        i1, j1 = min(i0 + 12, flow.nx), min(j0 + 12, flow.ny)
+        sub = window(flow, i0, i1, j0, j1)
+        o = oracle.OracleFlow(sub.nx, sub.ny, K, H, Hm, sub.dt, wl.nu, sub.dirichlet, sub.cxy,
+                              w.astype(np.float64), fp8=(prec == "fp8"))
+        ref = o.step(*window_fields(flow, 0, i0, i1, j0, j1), want=("Dbar", "bL"))
+        Dg = dbar[fi].cpu().numpy().reshape(flow.ny * n + 1, flow.nx * n + 1, 2)
+        bg = bL[fi].cpu().numpy().reshape(flow.ny + 1, flow.nx + 1, 2)
+        Dr = ref["Dbar"].reshape(sub.ny * n + 1, sub.nx * n + 1, 2)
+        br = ref["bL"].reshape(sub.ny + 1, sub.nx + 1, 2)
+        a0 = 0 if i0 == 0 else m
+        a1 = sub.nx if i1 == flow.nx else sub.nx - m
+        c0 = 0 if j0 == 0 else m
+        c1 = sub.ny if j1 == flow.ny else sub.ny - m
+        eD = rel_l2(Dg[(j0 + c0) * n:(j0 + c1) * n + 1, (i0 + a0) * n:(i0 + a1) * n + 1],
+                    Dr[c0 * n:c1 * n + 1, a0 * n:a1 * n + 1])
+        eb = rel_l2(bg[j0 + c0 + 1:j0 + c1, i0 + a0 + 1:i0 + a1], br[c0 + 1:c1, a0 + 1:a1])
+        print("stretched", prec, fi, (i0, j0), "Dbar %.2e bL %.2e" % (eD, eb))
+        assert eD < 2e-2 and eb < 2e-2
+    batch.close()
+    for c in ctxs:
+        c.close()
+    model.close()
