@@ -17,6 +17,7 @@
 // absolute coordinates are large compared with the fine mesh width.
 #include <type_traits>
 
+#include "device.h"
 #include "fp8.h"
 #include "internal.h"
 
@@ -165,9 +166,10 @@ __device__ inline void element_sums(const float m[2][2], const float Qs[2][2], c
     R[6] = 0.25f * (g0 * mt0 + g1 * mt1 + Sx1 + Sy1);
 }
 
-template <int K, typename XT>
+template <int K, typename XT, bool OPAQUE_TID>
 __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
 {
+    const int tid = OPAQUE_TID ? tile_thread() : (int)threadIdx.x;
     constexpr int n = 1 << K;
     constexpr float inv_n = 1.0f / n;
     constexpr int TP = kTileFine / n;           // patches per tile and direction
@@ -180,7 +182,9 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
     // XT = uint8_t: FP8 network input, assembled in FP32 and quantised per patch
     constexpr bool FP8 = std::is_same<XT, uint8_t>::value;
     typedef typename std::conditional<FP8, float, XT>::type ST;
-    constexpr size_t kWBytes = sizeof(float2) * NN * NN, kXBytes = sizeof(ST) * TP * TP * nin;
+    constexpr int XS8 = xstride_fp8(nin);        // FP8 row stride (bytes)
+    constexpr size_t kWBytes = sizeof(float2) * NN * NN;
+    constexpr size_t kXBytes = FP8 ? (size_t)TP * TP * XS8 : sizeof(ST) * TP * TP * nin;
     __shared__ CoarseRec s_c[CE * CE];
     // (u_prev - P v) / dt at nodes; once the element residuals are formed the
     // same bytes hold the tile's network-input rows
@@ -194,7 +198,6 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
     const int tx = blk % tiles_x, ty = blk / tiles_x;
     const int ci0 = tx * TP - 1, cj0 = ty * TP - 1;   // first (halo) coarse element
     const int I0 = tx * kTileFine, J0 = ty * kTileFine;
-    const int tid = threadIdx.x;
     const int first = *f.first_flag;
     const float inv_dt = f.inv_dt, nu = f.nu;
 
@@ -381,75 +384,98 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
     if (!f.X) return;
     __syncthreads();
 
-    // 6. network input rows of the tile's patches, assembled in LDS one patch
-    //    node per item, then written with full 16-byte stores (each row of TP
-    //    patches is contiguous in X):
-    //    X[e] = [P v at the (n+1)^2 patch nodes (x,y interleaved, x fastest) ;
-    //            D at the same nodes ; hx, hy, hx/hy, area]
-    for (int t = tid; t < TP * TP * (nf + 1); t += kThreads) {
-        const int pl = t / (nf + 1), l = t - pl * (nf + 1);
-        const int pa = pl % TP, pb = pl / TP;
-        const int pi = tx * TP + pa, pj = ty * TP + pb;
-        ST *o = s_x + pl * nin;
-        if (pi >= nx || pj >= ny) continue;
-        if (l == nf) {
-            const float4 ft = reinterpret_cast<const float4 *>(f.feat)[(size_t)pj * nx + pi];
-            o[4 * nf] = (ST)ft.x; o[4 * nf + 1] = (ST)ft.y; o[4 * nf + 2] = (ST)ft.z; o[4 * nf + 3] = (ST)ft.w;
-            continue;
-        }
-        const int a = l % (n + 1), b = l / (n + 1);
-        const CoarseRec &r = s_c[(pb + 1) * CE + (pa + 1)];
-        const float xi = a * inv_n, eta = b * inv_n;
-        const float pvx = (r.V0x + r.V1x * xi) + eta * (r.V2x + r.V3x * xi);
-        const float pvy = (r.V0y + r.V1y * xi) + eta * (r.V2y + r.V3y * xi);
-        const float2 d = s_acc[(pb * n + b + 1) * NN + pa * n + a + 1];
-        o[2 * l] = (ST)pvx; o[2 * l + 1] = (ST)pvy;
-        o[2 * nf + 2 * l] = (ST)d.x; o[2 * nf + 2 * l + 1] = (ST)d.y;
-    }
-    __syncthreads();
     const int npr = min(TP, nx - tx * TP);            // patches of this tile row inside the mesh
     if constexpr (FP8) {
-        // per-patch scale: m = max(max |x|, floor), codes e4m3(x * 448/m),
-        // scale m/448; TPR threads per patch row reduce the maximum
-        constexpr int ROWS = TP * TP, TPR = kThreads / ROWS;
-        static_assert(TPR >= 1 && 64 % TPR == 0, "patch rows per wave");
-        __shared__ float s_r[ROWS];
-        {
-            const int pl = tid / TPR, sub = tid - pl * TPR;
-            float m = 0.0f;
-            for (int k = sub; k < nin; k += TPR) m = fmaxf(m, fabsf(s_x[pl * nin + k]));
-#pragma unroll
-            for (int o = TPR / 2; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-            m = fmaxf(m, kFp8MinMax);
-            const int pa = pl % TP, pb = pl / TP, pi = tx * TP + pa, pj = ty * TP + pb;
-            if (sub == 0) {
-                s_r[pl] = 448.0f / m;
-                if (pi < nx && pj < ny) f.sx[(size_t)pj * nx + pi] = m / 448.0f;
+        // FP8: per-patch maximum first (LDS atomic max on the bit patterns of
+        // non-negative floats), then the values are formed again, scaled and
+        // converted into byte rows of xstride bytes (zero beyond nin).
+        uint8_t *s_q = reinterpret_cast<uint8_t *>(s_wx);
+        __shared__ unsigned s_m[TP * TP];
+        for (int t = tid; t < TP * TP; t += kThreads) s_m[t] = 0u;
+        for (int t = tid; t < TP * TP * XS8 / 16; t += kThreads) reinterpret_cast<uint4 *>(s_q)[t] = make_uint4(0u, 0u, 0u, 0u);
+        __syncthreads();
+        // item (patch pl, node l < nf): P v and D at the node; l == nf: the features
+        auto node_values = [&](int pl, int l, float4 &o) {
+            const int pa = pl % TP, pb = pl / TP;
+            if (l == nf) {
+                o = reinterpret_cast<const float4 *>(f.feat)[(size_t)(ty * TP + pb) * nx + tx * TP + pa];
+                return;
+            }
+            const int a = l % (n + 1), b = l / (n + 1);
+            const CoarseRec &r = s_c[(pb + 1) * CE + (pa + 1)];
+            const float xi = a * inv_n, eta = b * inv_n;
+            const float2 d = s_acc[(pb * n + b + 1) * NN + pa * n + a + 1];
+            o.x = (r.V0x + r.V1x * xi) + eta * (r.V2x + r.V3x * xi);
+            o.y = (r.V0y + r.V1y * xi) + eta * (r.V2y + r.V3y * xi);
+            o.z = d.x;
+            o.w = d.y;
+        };
+        for (int t = tid; t < TP * TP * (nf + 1); t += kThreads) {
+            const int pl = t / (nf + 1), l = t - pl * (nf + 1);
+            if (tx * TP + pl % TP >= nx || ty * TP + pl / TP >= ny) continue;
+            float4 o;
+            node_values(pl, l, o);
+            const float m = fmaxf(fmaxf(fabsf(o.x), fabsf(o.y)), fmaxf(fabsf(o.z), fabsf(o.w)));
+            atomicMax(&s_m[pl], __float_as_uint(m));
+        }
+        __syncthreads();
+        for (int t = tid; t < TP * TP * (nf + 1); t += kThreads) {
+            const int pl = t / (nf + 1), l = t - pl * (nf + 1);
+            const int pi = tx * TP + pl % TP, pj = ty * TP + pl / TP;
+            if (pi >= nx || pj >= ny) continue;
+            const float m = fmaxf(__uint_as_float(s_m[pl]), kFp8MinMax);
+            const float r = 448.0f / m;
+            if (l == 0) f.sx[(size_t)pj * nx + pi] = m / 448.0f;
+            float4 o;
+            node_values(pl, l, o);
+            uint8_t *row = s_q + pl * XS8;
+            const uint32_t c = pack4_e4m3(o.x * r, o.y * r, o.z * r, o.w * r);
+            if (l == nf) {
+                *reinterpret_cast<uint32_t *>(row + 4 * nf) = c;      // 4 nf is a multiple of 4
+            } else {
+                row[2 * l] = (uint8_t)c;
+                row[2 * l + 1] = (uint8_t)(c >> 8);
+                row[2 * nf + 2 * l] = (uint8_t)(c >> 16);
+                row[2 * nf + 2 * l + 1] = (uint8_t)(c >> 24);
             }
         }
         __syncthreads();
-        // rows of xstride bytes (zero beyond nin), 16 codes per item
-        constexpr int XS = xstride_fp8(nin), CPR = TP * XS / 16;
+        constexpr int CPR = TP * XS8 / 16;                 // 16-byte pieces per tile row of patches
         for (int t = tid; t < TP * CPR; t += kThreads) {
             const int pb = t / CPR, c = t - pb * CPR;
             const int pj = ty * TP + pb;
-            if (pj >= ny || c * 16 >= npr * XS) continue;
-            const int pa = c * 16 / XS, k0 = c * 16 - pa * XS;
-            const int pl = pb * TP + pa;
-            const float r = s_r[pl];
-            const ST *row = s_x + pl * nin;
-            float v[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) v[i] = (k0 + i < nin) ? row[k0 + i] * r : 0.0f;
-            uint4 w;
-            w.x = pack4_e4m3(v[0], v[1], v[2], v[3]);
-            w.y = pack4_e4m3(v[4], v[5], v[6], v[7]);
-            w.z = pack4_e4m3(v[8], v[9], v[10], v[11]);
-            w.w = pack4_e4m3(v[12], v[13], v[14], v[15]);
-            uint8_t *dst = reinterpret_cast<uint8_t *>(f.X) + ((size_t)pj * nx + tx * TP) * XS;
-            reinterpret_cast<uint4 *>(dst)[c] = w;
+            if (pj >= ny || c * 16 >= npr * XS8) continue;
+            const uint4 v = reinterpret_cast<const uint4 *>(s_q + pb * TP * XS8)[c];
+            uint8_t *dst = reinterpret_cast<uint8_t *>(f.X) + ((size_t)pj * nx + tx * TP) * XS8;
+            reinterpret_cast<uint4 *>(dst)[c] = v;
         }
     } else {
+        // 6. network input rows of the tile's patches, assembled in LDS one patch
+        //    node per item, then written with full 16-byte stores (each row of TP
+        //    patches is contiguous in X):
+        //    X[e] = [P v at the (n+1)^2 patch nodes (x,y interleaved, x fastest) ;
+        //            D at the same nodes ; hx, hy, hx/hy, area]
+        for (int t = tid; t < TP * TP * (nf + 1); t += kThreads) {
+            const int pl = t / (nf + 1), l = t - pl * (nf + 1);
+            const int pa = pl % TP, pb = pl / TP;
+            const int pi = tx * TP + pa, pj = ty * TP + pb;
+            ST *o = s_x + pl * nin;
+            if (pi >= nx || pj >= ny) continue;
+            if (l == nf) {
+                const float4 ft = reinterpret_cast<const float4 *>(f.feat)[(size_t)pj * nx + pi];
+                o[4 * nf] = (ST)ft.x; o[4 * nf + 1] = (ST)ft.y; o[4 * nf + 2] = (ST)ft.z; o[4 * nf + 3] = (ST)ft.w;
+                continue;
+            }
+            const int a = l % (n + 1), b = l / (n + 1);
+            const CoarseRec &r = s_c[(pb + 1) * CE + (pa + 1)];
+            const float xi = a * inv_n, eta = b * inv_n;
+            const float pvx = (r.V0x + r.V1x * xi) + eta * (r.V2x + r.V3x * xi);
+            const float pvy = (r.V0y + r.V1y * xi) + eta * (r.V2y + r.V3y * xi);
+            const float2 d = s_acc[(pb * n + b + 1) * NN + pa * n + a + 1];
+            o[2 * l] = (ST)pvx; o[2 * l + 1] = (ST)pvy;
+            o[2 * nf + 2 * l] = (ST)d.x; o[2 * nf + 2 * l + 1] = (ST)d.y;
+        }
+        __syncthreads();
         constexpr int CPR = TP * nin * sizeof(XT) / 16;   // 16-byte pieces per tile row of patches
         for (int t = tid; t < TP * CPR; t += kThreads) {
             const int pb = t / CPR, c = t - pb * CPR;
@@ -468,7 +494,7 @@ template <int K, typename XT, bool BATCHED>
 __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const BatchTable *__restrict__ bt)
 {
     if (!BATCHED) {
-        defect_tile<K, XT>(single, blockIdx.x);
+        defect_tile<K, XT, false>(single, blockIdx.x);
         return;
     }
     const int total = bt->prefix[kKindDefect][bt->nflows];
@@ -476,7 +502,7 @@ __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const Batc
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         int blk = g;
         const FlowArgs &f = *batch_flow(bt, kKindDefect, blk);
-        defect_tile<K, XT>(f, blk);
+        defect_tile<K, XT, true>(f, blk);
         __syncthreads();   // LDS is reused by the next tile
     }
 }

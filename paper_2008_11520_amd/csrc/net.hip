@@ -18,6 +18,7 @@
 // Fragment convention (both forms): in k-chunk kc, lane l = i + 16 q holds
 // operand values at k = kc*KC + q*KQ + e, e < KQ (A: row i; B: column i).
 // The 16 x 16 f32 result tile gives lane l rows 4 q + e (e < 4) of column i.
+#include "device.h"
 #include "fp8.h"
 #include "internal.h"
 
@@ -720,16 +721,314 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
     }
 }
 
+// Persistent FP8 kernel (H = 64 or 128, Hm = 0 or H, K <= 3).  Eight waves:
+// wave w owns hidden tile w % HT for 4 / (8 / HT) row tiles of each 64-patch
+// tile and keeps that hidden tile's gate and U_h fragments in registers for
+// the whole launch (90 VGPRs at K = 3, H = 128: the FP8 weights that BF16
+// could not keep resident); the MLP fragments live in LDS.  Products are
+// formed transposed (weights x activations^T) as in k_net_h64, so a lane
+// holds one patch row and four consecutive units; the per-patch row maxima
+// of the quantised activations are reduced over lanes and then over the
+// waves of the row through LDS.
+template <int K, int H, int HM>
+__global__ __launch_bounds__(kNetH64Threads, 2) void k_net_q8p(FlowArgs single, const BatchTable *__restrict__ bt,
+                                                               NetArgs net, int ntiles)
+{
+    constexpr int n = 1 << K, nf = (n + 1) * (n + 1), nin = 4 * nf + 4, nout = 2 * nf;
+    constexpr int KC = 32, KQ = 8;
+    constexpr int XS = xstride_fp8(nin), KCX = XS / KC, HC = H / KC, KC1 = KCX + HC;
+    // wave w: hidden tile w % HT, row tiles RTW (w / HT) .. + RTW - 1 of a pass;
+    // a 64-patch tile takes PASSES passes (2 at H = 128, to bound registers)
+    constexpr int HT = H / 16, WPH = 8 / HT, RTW = 2, PASSES = 4 / (WPH * RTW);
+    constexpr int OT = (nout + 15) / 16;
+    constexpr int MC = HM / KC;
+    constexpr int LDX = XS + 16, LDQ = H + 16, LDS32 = H + 4;
+    constexpr int W3N = (HM > 0 ? HM / 16 : OT) * HC * 64, W4N = HM > 0 ? OT * MC * 64 : 1;
+    static_assert(HM == 0 || HM == H, "MLP hidden tiles follow the hidden tiles");
+    if (bt) ntiles = bt->prefix[kKindNet][bt->nflows];   // batched: the table's row tiles
+
+    __shared__ __align__(16) uint8_t sX[64 * LDX];       // network input codes of the tile
+    __shared__ __align__(16) float sH[64 * LDS32];       // FP32 state of the tile
+    __shared__ __align__(16) uint8_t sQ[64 * LDQ];       // state codes, then r*h codes
+    __shared__ __align__(16) uint8_t sHp[64 * LDQ];      // h' codes
+    __shared__ __align__(16) uint8_t sAm[64 * LDQ];      // MLP hidden codes
+    __shared__ __align__(16) f8x8 sW3[W3N];
+    __shared__ __align__(16) f8x8 sW4[W4N];
+    __shared__ float sMax[HT * 64];                     // per-wave partial row maxima
+    __shared__ float sSx[64], sSh[64];                  // row scales of x and h
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lq = lane >> 4;
+    const int ht = wave % HT, rt0 = RTW * (wave / HT);   // row-tile offset within a pass
+    const int ucol = 16 * ht + 4 * lq;                  // first of this lane's four units
+    const f8x8 *B1 = reinterpret_cast<const f8x8 *>(net.B1);
+    const f8x8 *B2 = reinterpret_cast<const f8x8 *>(net.B2);
+    const f8x8 *B3 = reinterpret_cast<const f8x8 *>(net.B3);
+    const f8x8 *B4 = reinterpret_cast<const f8x8 *>(net.B4);
+
+    f8x8 wz[KC1], wr[KC1], wh[KCX], w2[HC];
+#pragma unroll
+    for (int kc = 0; kc < KC1; ++kc) {
+        wz[kc] = B1[((0 * HT + ht) * KC1 + kc) * 64 + lane];
+        wr[kc] = B1[((1 * HT + ht) * KC1 + kc) * 64 + lane];
+    }
+#pragma unroll
+    for (int kc = 0; kc < KCX; ++kc) wh[kc] = B1[((2 * HT + ht) * KC1 + kc) * 64 + lane];
+#pragma unroll
+    for (int kc = 0; kc < HC; ++kc) w2[kc] = B2[(ht * HC + kc) * 64 + lane];
+    for (int t = tid; t < W3N; t += kNetH64Threads) sW3[t] = B3[t];
+    for (int t = tid; t < W4N; t += kNetH64Threads) sW4[t] = HM > 0 ? B4[t] : 0;
+    float s1z[4], s1r[4], s1h[4], s2u[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        s1z[e] = net.s1[ucol + e];
+        s1r[e] = net.s1[H + ucol + e];
+        s1h[e] = net.s1[2 * H + ucol + e];
+        s2u[e] = net.s2[ucol + e];
+    }
+
+    // next-tile prefetch into registers: network input codes, FP32 state, x scales
+    constexpr int XCH = 64 * XS / 16, HCH = 64 * H / 4;
+    constexpr int XPT = (XCH + kNetH64Threads - 1) / kNetH64Threads;
+    constexpr int HPT = (HCH + kNetH64Threads - 1) / kNetH64Threads;
+    uint4 xr[XPT];
+    f4 hr[HPT];
+    float sxr = 1.0f;
+    auto load_tile = [&](int tile) {
+        int blk = tile;
+        const FlowArgs *fq = bt ? batch_flow(bt, kKindNet, blk) : &single;
+        const int P = fq->nx * fq->ny, row0 = blk * 64, nrows = min(64, P - row0);
+        const uint4 *xg = reinterpret_cast<const uint4 *>(reinterpret_cast<const uint8_t *>(fq->X) + (size_t)row0 * XS);
+        const f4 *hgv = reinterpret_cast<const f4 *>(fq->h + (size_t)row0 * H);
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) {
+            const int c = tid + i * kNetH64Threads;
+            xr[i] = (c < XCH && c / (XS / 16) < nrows) ? xg[c] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
+            const int c = tid + i * kNetH64Threads;
+            hr[i] = (c < HCH && c / (H / 4) < nrows) ? hgv[c] : f4{0.f, 0.f, 0.f, 0.f};
+        }
+        sxr = tid < nrows ? fq->sx[row0 + tid] : 1.0f;
+    };
+    if (blockIdx.x < ntiles) load_tile(blockIdx.x);
+
+    // row maximum of |v| over the 16 units a wave holds for its row, then over
+    // the HT waves of the row (the caller brackets this with barriers)
+    auto wave_max = [&](float m, int row) {
+        m = fmaxf(m, __shfl_xor(m, 16));
+        m = fmaxf(m, __shfl_xor(m, 32));
+        if (lq == 0) sMax[ht * 64 + row] = m;
+    };
+    auto row_max = [&](int row) {
+        float m = kFp8MinMax;
+#pragma unroll
+        for (int t = 0; t < HT; ++t) m = fmaxf(m, sMax[t * 64 + row]);
+        return m;
+    };
+
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        int blk = tile;
+        const FlowArgs &ff = bt ? *batch_flow(bt, kKindNet, blk) : single;
+        const int P = ff.nx * ff.ny;
+        const int row0 = blk * 64;
+        const int nrows = min(64, P - row0);
+        float *hg = ff.h + (size_t)row0 * H;
+        float *dp = ff.dpatch + (size_t)row0 * nout;
+
+        __syncthreads();   // the previous tile's readers of LDS are done
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) {
+            const int c = tid + i * kNetH64Threads;
+            if (c < XCH) *reinterpret_cast<uint4 *>(&sX[(c / (XS / 16)) * LDX + 16 * (c % (XS / 16))]) = xr[i];
+        }
+        // the state: FP32 rows and their codes; the H / 4 consecutive threads
+        // that hold one row's pieces reduce its maximum by shuffles
+        static_assert(HCH % kNetH64Threads == 0 && (H / 4) <= 64, "whole rows per pass");
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
+            const int c = tid + i * kNetH64Threads;
+            const int row = c / (H / 4), k = 4 * (c % (H / 4));
+            *reinterpret_cast<f4 *>(&sH[row * LDS32 + k]) = hr[i];
+            float m = fmaxf(fmaxf(fabsf(hr[i].x), fabsf(hr[i].y)), fmaxf(fabsf(hr[i].z), fabsf(hr[i].w)));
+#pragma unroll
+            for (int o = 1; o < H / 4; o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
+            m = fmaxf(m, kFp8MinMax);
+            const float r = 448.0f / m;
+            if (k == 0) sSh[row] = m / 448.0f;
+            *reinterpret_cast<uint32_t *>(&sQ[row * LDQ + k]) =
+                pack4_e4m3(hr[i].x * r, hr[i].y * r, hr[i].z * r, hr[i].w * r);
+        }
+        if (tid < 64) sSx[tid] = sxr;
+        if (tile + (int)gridDim.x < ntiles) load_tile(tile + gridDim.x);
+        __syncthreads();
+
+        for (int pass = 0; pass < PASSES; ++pass) {
+            const int rtb = pass * WPH * RTW + rt0;      // first row tile of this wave in the pass
+            // ---- phase 1: the three gates of this wave's hidden tile
+            f4 az[RTW], ar[RTW], ah[RTW];
+            float sx[RTW], sh[RTW];
+#pragma unroll
+            for (int q = 0; q < RTW; ++q) {
+                const int row = 16 * (rtb + q) + li;
+                az[q] = ar[q] = ah[q] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kc = 0; kc < KCX; ++kc) {
+                    const f8x8 a = mma_fp8_operand(&sX[row * LDX + kc * KC + lq * KQ]);
+                    az[q] = mma_fp8(az[q], wz[kc], a);
+                    ar[q] = mma_fp8(ar[q], wr[kc], a);
+                    ah[q] = mma_fp8(ah[q], wh[kc], a);
+                }
+                sx[q] = sSx[row];
+                sh[q] = sSh[row];
+                const float ratio = sx[q] / sh[q];
+                az[q] *= ratio;
+                ar[q] *= ratio;
+#pragma unroll
+                for (int kh = 0; kh < HC; ++kh) {
+                    const f8x8 a = mma_fp8_operand(&sQ[row * LDQ + kh * KC + lq * KQ]);
+                    az[q] = mma_fp8(az[q], wz[KCX + kh], a);
+                    ar[q] = mma_fp8(ar[q], wr[KCX + kh], a);
+                }
+            }
+            f4 hold[RTW];
+#pragma unroll
+            for (int q = 0; q < RTW; ++q) {
+                const int row = 16 * (rtb + q) + li;
+                hold[q] = *reinterpret_cast<const f4 *>(&sH[row * LDS32 + ucol]);
+                float m = 0.0f;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    az[q][e] = sigmoid(az[q][e] * sh[q] * s1z[e]);
+                    ar[q][e] = sigmoid(ar[q][e] * sh[q] * s1r[e]) * hold[q][e];   // r*h
+                    ah[q][e] *= sx[q] * s1h[e];
+                    m = fmaxf(m, fabsf(ar[q][e]));
+                }
+                wave_max(m, row);
+            }
+            __syncthreads();
+            float srh[RTW];
+#pragma unroll
+            for (int q = 0; q < RTW; ++q) {
+                const int row = 16 * (rtb + q) + li;
+                const float m = row_max(row), r = 448.0f / m;
+                srh[q] = m / 448.0f;
+                *reinterpret_cast<uint32_t *>(&sQ[row * LDQ + ucol]) =
+                    pack4_e4m3(ar[q][0] * r, ar[q][1] * r, ar[q][2] * r, ar[q][3] * r);
+            }
+            __syncthreads();
+
+            // ---- phase 2: U_h (r*h); new state
+#pragma unroll
+            for (int q = 0; q < RTW; ++q) {
+                const int row = 16 * (rtb + q) + li;
+                f4 au = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kc = 0; kc < HC; ++kc) au = mma_fp8(au, w2[kc], mma_fp8_operand(&sQ[row * LDQ + kc * KC + lq * KQ]));
+                float m = 0.0f;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float z = az[q][e];
+                    const float hn = z * hold[q][e] + (1.0f - z) * fast_tanh(ah[q][e] + au[e] * srh[q] * s2u[e]);
+                    az[q][e] = hn;
+                    m = fmaxf(m, fabsf(hn));
+                }
+                if (row < nrows) *reinterpret_cast<f4 *>(hg + (size_t)row * H + ucol) = az[q];
+                wave_max(m, row);
+            }
+            __syncthreads();
+            float shp[RTW];
+#pragma unroll
+            for (int q = 0; q < RTW; ++q) {
+                const int row = 16 * (rtb + q) + li;
+                const float m = row_max(row), r = 448.0f / m;
+                shp[q] = m / 448.0f;
+                *reinterpret_cast<uint32_t *>(&sHp[row * LDQ + ucol]) =
+                    pack4_e4m3(az[q][0] * r, az[q][1] * r, az[q][2] * r, az[q][3] * r);
+            }
+            __syncthreads();
+
+            // ---- MLP head
+            const uint8_t *src = sHp;
+            const f8x8 *Wo = sW3;
+            const float *so = net.s3;
+            constexpr int CO = HM > 0 ? MC : HC;             // k-chunks of the output layer
+            float sin_[RTW];
+#pragma unroll
+            for (int q = 0; q < RTW; ++q) sin_[q] = shp[q];
+            if constexpr (HM > 0) {
+                float s3u[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s3u[e] = net.s3[ucol + e];
+#pragma unroll
+                for (int q = 0; q < RTW; ++q) {
+                    const int row = 16 * (rtb + q) + li;
+                    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kc = 0; kc < HC; ++kc)
+                        acc = mma_fp8(acc, sW3[(ht * HC + kc) * 64 + lane], mma_fp8_operand(&sHp[row * LDQ + kc * KC + lq * KQ]));
+                    float m = 0.0f;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        ar[q][e] = fmaxf(acc[e] * shp[q] * s3u[e], 0.f);
+                        m = fmaxf(m, ar[q][e]);
+                    }
+                    wave_max(m, row);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < RTW; ++q) {
+                    const int row = 16 * (rtb + q) + li;
+                    const float m = row_max(row), r = 448.0f / m;
+                    sin_[q] = m / 448.0f;
+                    *reinterpret_cast<uint32_t *>(&sAm[row * LDQ + ucol]) =
+                        pack4_e4m3(ar[q][0] * r, ar[q][1] * r, ar[q][2] * r, ar[q][3] * r);
+                }
+                __syncthreads();
+                src = sAm;
+                Wo = sW4;
+                so = net.s4;
+            }
+            for (int ot = ht; ot < OT; ot += HT) {
+                const int oc = 16 * ot + 4 * lq;
+                float so4[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) so4[e] = oc + e < nout ? so[oc + e] : 0.0f;
+#pragma unroll
+                for (int q = 0; q < RTW; ++q) {
+                    const int row = 16 * (rtb + q) + li;
+                    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kc = 0; kc < CO; ++kc)
+                        acc = mma_fp8(acc, Wo[(ot * CO + kc) * 64 + lane], mma_fp8_operand(&src[row * LDQ + kc * KC + lq * KQ]));
+                    // nout is even: the pairs (oc, oc+1), (oc+2, oc+3) are inside or outside together
+                    if (row < nrows) {
+                        float *o = dp + (size_t)row * nout + oc;
+                        if (oc < nout) *reinterpret_cast<float2 *>(o) = make_float2(acc[0] * sin_[q] * so4[0], acc[1] * sin_[q] * so4[1]);
+                        if (oc + 2 < nout) *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[2] * sin_[q] * so4[2], acc[3] * sin_[q] * so4[3]);
+                    }
+                }
+            }
+        }
+    }
+}
+
 static int g_num_cus = 0;
 
 static bool use_h64(int prec, int K, int H, int Hm) { return prec == 1 && H == 64 && K <= 2 && (Hm == 0 || Hm == 64); }
 static bool use_h64(const NetArgs &net) { return use_h64(net.prec, net.K, net.H, net.Hm); }
+static bool use_q8p(const NetArgs &net)
+{
+    return net.prec == 2 && (net.H == 64 || net.H == 128) && (net.Hm == 0 || net.Hm == net.H);
+}
+static bool persistent(const NetArgs &net) { return use_h64(net) || use_q8p(net); }
 
 bool net_needs_x(int prec, int K, int H, int Hm) { return !use_h64(prec, K, H, Hm); }
 
 int net_blocks(const NetArgs &net, int row_tiles)
 {
-    if (use_h64(net)) {
+    if (persistent(net)) {
         if (g_num_cus == 0) {
             int dev = 0;
             (void)hipGetDevice(&dev);
@@ -756,6 +1055,22 @@ hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int ntiles, const
     if (use_h64(net)) {
         if (net.K == 1) hipLaunchKernelGGL(k_net_h64<1>, dim3(nblocks), dim3(kNetH64Threads), 0, s, f, bt, net, ntiles);
         else hipLaunchKernelGGL(k_net_h64<2>, dim3(nblocks), dim3(kNetH64Threads), 0, s, f, bt, net, ntiles);
+        return hipGetLastError();
+    }
+    if (use_q8p(net)) {
+        dim3 g(nblocks), b(kNetH64Threads);
+#define DNNMG_Q8P(KK, HH, MM) hipLaunchKernelGGL((k_net_q8p<KK, HH, MM>), g, b, 0, s, f, bt, net, ntiles)
+#define DNNMG_Q8P_H(KK)                                                                            \
+        if (net.H == 64) { if (net.Hm == 64) DNNMG_Q8P(KK, 64, 64); else DNNMG_Q8P(KK, 64, 0); }    \
+        else { if (net.Hm == 128) DNNMG_Q8P(KK, 128, 128); else DNNMG_Q8P(KK, 128, 0); }
+        switch (net.K) {
+        case 1: DNNMG_Q8P_H(1) break;
+        case 2: DNNMG_Q8P_H(2) break;
+        case 3: DNNMG_Q8P_H(3) break;
+        default: return hipErrorInvalidValue;
+        }
+#undef DNNMG_Q8P_H
+#undef DNNMG_Q8P
         return hipGetLastError();
     }
     if (net.prec == 2) {

@@ -21,6 +21,7 @@
 // and P^T is the evaluation of N_c at fine nodes, so the result equals the
 // definition up to FP64 rounding.  A second kernel sums the four patch
 // contributions at each coarse node in a fixed order (no atomics).
+#include "device.h"
 #include "internal.h"
 
 namespace dnnmg {
@@ -34,9 +35,10 @@ __device__ inline bool dirichlet_node(unsigned dir, int I, int J, int NX, int NY
 // One workgroup per tile of kRhsFine x kRhsFine fine elements (TP x TP patches).
 // from_patches = 1: average f.dpatch and store the corrected velocity (the
 // step); 0: take the correction from f.dbar_in (stage, state untouched).
-template <int K, int FROM_PATCHES>
+template <int K, int FROM_PATCHES, bool OPAQUE_TID>
 __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables tab)
 {
+    const int tid = OPAQUE_TID ? tile_thread() : (int)threadIdx.x;
     constexpr int n = 1 << K;
     constexpr int nf = (n + 1) * (n + 1);
     constexpr int nout = 2 * nf;
@@ -54,7 +56,6 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
     const int tx = blk % tiles_x, ty = blk / tiles_x;
     const int pi0 = tx * TP, pj0 = ty * TP;    // first patch of the tile
     const int I0 = pi0 * n, J0 = pj0 * n;      // first fine node
-    const int tid = threadIdx.x;
     // The step's defect has already read the first-step flag (stream order).
     if (FROM_PATCHES && blk == 0 && tid == 0) *f.first_flag = 0;
 
@@ -193,7 +194,7 @@ template <int K, int FROM_PATCHES, bool BATCHED>
 __global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTable *__restrict__ bt, RhsTables tab)
 {
     if (!BATCHED) {
-        rhs_tile<K, FROM_PATCHES>(single, blockIdx.x, tab);
+        rhs_tile<K, FROM_PATCHES, false>(single, blockIdx.x, tab);
         return;
     }
     const int total = bt->prefix[kKindRhs][bt->nflows];
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTa
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         int blk = g;
         const FlowArgs &f = *batch_flow(bt, kKindRhs, blk);
-        rhs_tile<K, FROM_PATCHES>(f, blk, tab);
+        rhs_tile<K, FROM_PATCHES, true>(f, blk, tab);
         __syncthreads();   // LDS is reused by the next tile
     }
 }
