@@ -567,13 +567,14 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
 
     // Tiles are contiguous in memory: the network input (BF16, 64 x nin) and
     // the state (FP32, 64 x H).  Each thread prefetches its 16-byte pieces of
-    // the next tile into registers while the current one is computed.
+    // the next two tiles into two register buffers while the current one is
+    // computed, so two tiles' loads are in flight per workgroup.
     constexpr int XCH = 64 * nin / 8, HCH = 64 * H / 4;            // 16-byte pieces per tile
     constexpr int XPT = (XCH + kNetH64Threads - 1) / kNetH64Threads;
     constexpr int HPT = (HCH + kNetH64Threads - 1) / kNetH64Threads;
-    bf8 xr[XPT];
-    f4 hr[HPT];
-    auto load_tile = [&](int tile) {
+    bf8 xrA[XPT], xrB[XPT];
+    f4 hrA[HPT], hrB[HPT];
+    auto load_tile = [&](int tile, bf8 (&xr)[XPT], f4 (&hr)[HPT]) {
         int blk = tile;
         const FlowArgs *fq = bt ? batch_flow(bt, kKindNet, blk) : &single;
         const int P = fq->nx * fq->ny, row0 = blk * 64, nrows = min(64, P - row0);
@@ -593,9 +594,13 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
     // the k-padding columns of [x | h] stay zero for the whole launch
     if (PADK > 0)
         for (int t = tid; t < 64 * PADK; t += kNetH64Threads) sA[(t / PADK) * LDA + nin + H + t % PADK] = (__bf16)0.f;
-    if (blockIdx.x < ntiles) load_tile(blockIdx.x);
+    const int G = gridDim.x;
+    if (blockIdx.x < ntiles) load_tile(blockIdx.x, xrA, hrA);
+    if (blockIdx.x + G < ntiles) load_tile(blockIdx.x + G, xrB, hrB);
 
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // one 64-patch tile: stage the prefetched registers, refill them with
+    // tile `next`, compute
+    auto process = [&](int tile, bf8 (&xr)[XPT], f4 (&hr)[HPT], int next) {
         int blk = tile;
         const FlowArgs ff = bt ? *batch_flow(bt, kKindNet, blk) : single;
         const int P = ff.nx * ff.ny;
@@ -621,7 +626,7 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
                 *reinterpret_cast<bf4 *>(&sA[r * LDA + nin + k]) = hb;
             }
         }
-        if (tile + (int)gridDim.x < ntiles) load_tile(tile + gridDim.x);
+        if (next < ntiles) load_tile(next, xr, hr);
         __syncthreads();
 
         // The products are formed transposed (weights x activations^T), so the
@@ -718,6 +723,10 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
                 }
             }
         }
+    };
+    for (int tile = blockIdx.x; tile < ntiles; tile += 2 * G) {
+        process(tile, xrA, hrA, tile + 2 * G);
+        if (tile + G < ntiles) process(tile + G, xrB, hrB, tile + 3 * G);
     }
 }
 
