@@ -138,32 +138,40 @@ int blocks_for(int kind, int nx, int ny, int K)
 
 // Per coarse element, the coefficients the defect needs (LDS record):
 // prolongated velocity and pressure as bilinear polynomials in the coarse
-// reference coordinates, v = V0 + V1 xi + V2 eta + V3 xi eta, their fine-level
-// reference derivatives (scaled by 1/n), and the fine-level map derivatives
-// x_s = exn + exyn eta, x_t = eyn + exyn xi (also scaled by 1/n).
+// reference coordinates, v = V0 + V1 xi + V2 eta + V3 xi eta, and the map
+// vectors of F(xi, eta) = c00 + ex xi + ey eta + exy xi eta, so that
+// x_xi = ex + exy eta, x_eta = ey + exy xi.  Derivatives are taken in the
+// coarse reference coordinates; the fine element's own reference derivatives
+// are these times 1/n, a factor the element sums apply at the end.
 struct CoarseRec {
     float V0x, V1x, V2x, V3x, V0y, V1y, V2y, V3y;
     float P0, P1, P2, P3;
-    float exnx, exny, eynx, eyny, exynx, exyny;
+    float exx, exy, eyx, eyy, exyx, exyy;
 };
 
 // Test-function sums of one component of the element residual: with the
 // Gauss abscissae g0, g1 and 1 - g0 = g1,
 //   R_a += 1/4 sum_q [ N_a(q) m(q) + dN_a/ds(q) Qs(q) + dN_a/dt(q) Qt(q) ]
 // for nodes a = 00, 10, 01, 11 (stride 2 in R: components interleaved).
+// m and Q come from coarse-reference derivatives: m carries n^2 and Q carries
+// n relative to the fine element's, so those factors and the weight 1/4 go
+// into the outer constants.
+template <int n>
 __device__ inline void element_sums(const float m[2][2], const float Qs[2][2], const float Qt[2][2], float *R)
 {
     constexpr float g0 = 0.21132486540518711775f, g1 = 0.78867513459481288225f;
+    constexpr float hm0 = 0.25f * g0 / (n * n), hm1 = 0.25f * g1 / (n * n);
+    constexpr float h0 = 0.25f * g0 / n, h1 = 0.25f * g1 / n;
     const float mb0 = g1 * m[0][0] + g0 * m[0][1], mb1 = g1 * m[1][0] + g0 * m[1][1];   // weight 1 - t
     const float mt0 = g0 * m[0][0] + g1 * m[0][1], mt1 = g0 * m[1][0] + g1 * m[1][1];   // weight t
     const float qs0 = Qs[0][0] + Qs[1][0], qs1 = Qs[0][1] + Qs[1][1];                   // sum over s
     const float qt0 = Qt[0][0] + Qt[0][1], qt1 = Qt[1][0] + Qt[1][1];                   // sum over t
-    const float Sx0 = g1 * qs0 + g0 * qs1, Sx1 = g0 * qs0 + g1 * qs1;
-    const float Sy0 = g1 * qt0 + g0 * qt1, Sy1 = g0 * qt0 + g1 * qt1;
-    R[0] = 0.25f * (g1 * mb0 + g0 * mb1 - Sx0 - Sy0);
-    R[2] = 0.25f * (g0 * mb0 + g1 * mb1 + Sx0 - Sy1);
-    R[4] = 0.25f * (g1 * mt0 + g0 * mt1 - Sx1 + Sy0);
-    R[6] = 0.25f * (g0 * mt0 + g1 * mt1 + Sx1 + Sy1);
+    const float Sx0 = h1 * qs0 + h0 * qs1, Sx1 = h0 * qs0 + h1 * qs1;
+    const float Sy0 = h1 * qt0 + h0 * qt1, Sy1 = h0 * qt0 + h1 * qt1;
+    R[0] = hm1 * mb0 + hm0 * mb1 - Sx0 - Sy0;
+    R[2] = hm0 * mb0 + hm1 * mb1 + Sx0 - Sy1;
+    R[4] = hm1 * mt0 + hm0 * mt1 - Sx1 + Sy0;
+    R[6] = hm0 * mt0 + hm1 * mt1 + Sx1 + Sy1;
 }
 
 template <int K, typename XT, bool OPAQUE_TID>
@@ -230,9 +238,9 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
                 r.P0 = r.P1 = r.P2 = r.P3 = 0.f;
             }
             const float *g = f.geo + 6 * ((size_t)cj * nx + ci);
-            r.exnx = g[0] * inv_n; r.exny = g[1] * inv_n;
-            r.eynx = g[2] * inv_n; r.eyny = g[3] * inv_n;
-            r.exynx = g[4] * inv_n; r.exyny = g[5] * inv_n;
+            r.exx = g[0]; r.exy = g[1];
+            r.eyx = g[2]; r.eyy = g[3];
+            r.exyx = g[4]; r.exyy = g[5];
         } else {
             r = CoarseRec{};
         }
@@ -266,7 +274,9 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
     //    each Gauss point:
     //      mass - convection:  m_c = det (u_prev - v)_c / dt - v . (Cof grad_ref v_c)
     //      pressure - viscous: Q_c = p Cof^T e_c - (nu / det) G grad_ref v_c
-    //    R_a,c = sum_q w_q [ N_a m_c + grad_ref N_a . Q_c ]   (w_q = 1/4).
+    //    R_a,c = sum_q w_q [ N_a m_c + grad_ref N_a . Q_c ]   (w_q = 1/4),
+    //    with J and grad_ref in the coarse reference coordinates (element_sums
+    //    applies the 1/n^2 and 1/n that turn them into the fine element's).
     constexpr float g0 = 0.21132486540518711775f, g1 = 0.78867513459481288225f;
     float R[EPT][8];
     // Elements are numbered colour by colour: colour c = (parity of eI) + 2
@@ -290,19 +300,19 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
             const float xi[2] = {(a + g0) * inv_n, (a + g1) * inv_n};
             const float eta[2] = {(b + g0) * inv_n, (b + g1) * inv_n};
             float xsx[2], xsy[2], xtx[2], xty[2];          // x_s(eta_j), x_t(xi_i)
-            float vsx[2], vsy[2], vtx[2], vty[2];          // v_s(eta_j), v_t(xi_i) per component
-            float ax_[2], bx_[2], ay_[2], by_[2], ap[2], bp[2];
+            float vsx[2], vsy[2], vtx[2], vty[2];          // v_xi(eta_j), v_eta(xi_i) per component
+            float ax_[2], ay_[2], ap[2], bp[2];                // v = ax_ + vtx eta along xi_i
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                xsx[j] = r.exnx + r.exynx * eta[j]; xsy[j] = r.exny + r.exyny * eta[j];
-                vsx[j] = (r.V1x + r.V3x * eta[j]) * inv_n; vsy[j] = (r.V1y + r.V3y * eta[j]) * inv_n;
+                xsx[j] = r.exx + r.exyx * eta[j]; xsy[j] = r.exy + r.exyy * eta[j];
+                vsx[j] = r.V1x + r.V3x * eta[j]; vsy[j] = r.V1y + r.V3y * eta[j];
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                xtx[i] = r.eynx + r.exynx * xi[i]; xty[i] = r.eyny + r.exyny * xi[i];
-                vtx[i] = (r.V2x + r.V3x * xi[i]) * inv_n; vty[i] = (r.V2y + r.V3y * xi[i]) * inv_n;
-                ax_[i] = r.V0x + r.V1x * xi[i]; bx_[i] = r.V2x + r.V3x * xi[i];
-                ay_[i] = r.V0y + r.V1y * xi[i]; by_[i] = r.V2y + r.V3y * xi[i];
+                xtx[i] = r.eyx + r.exyx * xi[i]; xty[i] = r.eyy + r.exyy * xi[i];
+                vtx[i] = r.V2x + r.V3x * xi[i]; vty[i] = r.V2y + r.V3y * xi[i];
+                ax_[i] = r.V0x + r.V1x * xi[i];
+                ay_[i] = r.V0y + r.V1y * xi[i];
                 ap[i] = r.P0 + r.P1 * xi[i]; bp[i] = r.P2 + r.P3 * xi[i];
             }
             // (u_prev - v)/dt at the Gauss points from the element's nodal values
@@ -326,7 +336,7 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
                 for (int j = 0; j < 2; ++j) {
                     const float xs = xsx[j], ys = xsy[j], xt = xtx[i], yt = xty[i];
                     const float det = xs * yt - xt * ys;
-                    const float vxq = ax_[i] + bx_[i] * eta[j], vyq = ay_[i] + by_[i] * eta[j];
+                    const float vxq = ax_[i] + vtx[i] * eta[j], vyq = ay_[i] + vty[i] * eta[j];
                     const float pq = ap[i] + bp[i] * eta[j];
                     // det grad v_c = Cof grad_ref v_c
                     const float dxx = yt * vsx[j] - ys * vtx[i], dxy = -xt * vsx[j] + xs * vtx[i];
@@ -340,8 +350,8 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
                     Qys[i][j] = -pq * xt - inv * (g11[i] * vsy[j] + g12 * vty[i]);
                     Qyt[i][j] = pq * xs - inv * (g12 * vsy[j] + g22[j] * vty[i]);
                 }
-            element_sums(mx, Qxs, Qxt, R[k]);
-            element_sums(my, Qys, Qyt, R[k] + 1);
+            element_sums<n>(mx, Qxs, Qxt, R[k]);
+            element_sums<n>(my, Qys, Qyt, R[k] + 1);
         }
     }
 
