@@ -54,6 +54,20 @@ def stencil_flop_per_patch(K):
     return 760 * n * n
 
 
+def fused_bytes_per_patch(K, H):
+    """Interface bytes per patch of the one-launch defect + GRU + MLP: coarse
+    v, p and geometry (20 B), the previous corrected velocity read (n^2 fine
+    nodes x 8 B), h read and written (2 H x 4 B), per-patch outputs written
+    (2 (n+1)^2 x 4 B).  The network input stays on chip."""
+    n = 1 << K
+    return 20 + n * n * 8 + 2 * H * 4 + 2 * (n + 1) ** 2 * 4
+
+
+def is_fused(wl, precision, flags=0):
+    """The library runs defect + GRU + MLP as one launch for these shapes."""
+    return precision == "bf16" and wl.K == 2 and wl.H == 64 and wl.Hm in (0, 64) and not flags
+
+
 def rhs_bytes_per_patch(K):
     """Averaging/rhs kernel interface bytes per patch: per-patch outputs read
     (2 (n+1)^2 FP32), corrected velocity written (n^2 fine nodes x 8 B), corner
@@ -65,20 +79,20 @@ def rhs_bytes_per_patch(K):
 def source_hash(stage):
     import hashlib
     h = hashlib.sha256()
-    for name in STAGE_SOURCES[stage] + ["internal.h"]:
+    for name in STAGE_SOURCES[stage] + ["internal.h", "device.h", "fp8.h"]:
         with open(os.path.join(ROOT, "paper_2008_11520_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(stage, workload, precision):
+def stored_traffic(stage, workload, precision, fused=False):
     """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs in
     profiles/traffic.json, scaled by the copy-kernel factor; None if absent or
     if the kernel source changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
-        e = t["kernels"][workload][precision][STAGE_KERNELS[stage]]
+        e = t["kernels"][workload][precision]["k_defect_net" if fused else STAGE_KERNELS[stage]]
     except (OSError, KeyError, ValueError):
         return None
     if e.get("source_hash") != source_hash(stage):
@@ -99,13 +113,13 @@ def calibrate_copy(mib):
     print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 3}))
 
 
-def run_gpu(wl, precision, steps, warmup):
+def run_gpu(wl, precision, steps, warmup, flags=0):
     import torch
     import paper_2008_11520_amd as pam
     from paper_2008_11520_amd import synth
     flow = wl.flows[0]
     w = synth.xavier_weights(wl.K, wl.H, wl.Hm, wl.weight_seed)
-    cfg = pam.make_config(flow.nx, flow.ny, wl.K, wl.H, wl.Hm, flow.dt, wl.nu, precision, flow.dirichlet)
+    cfg = pam.make_config(flow.nx, flow.ny, wl.K, wl.H, wl.Hm, flow.dt, wl.nu, precision, flow.dirichlet, flags)
     g = pam.DnnMG(cfg, flow.cxy, w)
     s = g.s
     total = warmup + steps
@@ -122,9 +136,9 @@ def run_gpu(wl, precision, steps, warmup):
         g.step(vs[n % nfield], ps[n % nfield])
         g.restrict_rhs(b)
     torch.cuda.synchronize()
-    g.profile_enable(steps)
+    # the timed steps: no events between the kernels (each event record puts a
+    # few microseconds of idle time on the stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
     for n in range(steps):
@@ -135,11 +149,21 @@ def run_gpu(wl, precision, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
+    # the same loop again with the library's per-stage HIP events on the launch
+    # stream: the kernels' own durations (roofline, stage breakdown)
+    nprof = min(steps, 50)
+    g.profile_enable(nprof)
+    for n in range(nprof):
+        k = (warmup + steps + n) % nfield
+        g.step(vs[k], ps[k])
+        g.restrict_rhs(b)
+    torch.cuda.synchronize()
     stage_ms, stage_n = g.profile_read()
     g.profile_enable(0)
     ok = bool(torch.isfinite(b).all().item())
     g.close()
-    return dict(ms_total=ms, wall_s=wall, P=s["P"], stage_ms=stage_ms, stage_n=stage_n, finite=ok)
+    return dict(ms_total=ms, wall_s=wall, P=s["P"], stage_ms=stage_ms, stage_n=stage_n, finite=ok,
+                fused=is_fused(wl, precision, flags))
 
 
 def run_gpu_batch(wl, precision, steps, warmup):
@@ -228,6 +252,23 @@ def roofline(wl, flow, P, main_r, precision):
     avg = [main_r["stage_ms"][k] / max(main_r["stage_n"][k], 1) for k in range(4)]
     dom = int(np.argmax(avg))
     t_s = avg[dom] / 1e3
+    if dom == 0 and main_r.get("fused"):
+        # one launch with vector work (defect), matrix-core work (GRU, MLP) and
+        # HBM traffic: the roofline is the largest of the three lower bounds
+        vflop, mflop = stencil_flop_per_patch(wl.K), per_patch_gemm_flop(wl.K, wl.H, wl.Hm)
+        unit_work = fused_bytes_per_patch(wl.K, wl.H)
+        bounds = {"alu": vflop * P / (PEAK_FP32_VECTOR_TFLOPS * 1e12), "mfma": mflop * P / (PEAK_TFLOPS[precision] * 1e12),
+                  "hbm": unit_work * P / (PEAK_HBM_GBS * 1e9)}
+        bound = max(bounds, key=bounds.get)
+        achieved = unit_work * P / t_s / 1e9
+        roof = {"bound": bound, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": bounds[bound] / t_s,
+                "lower_bounds_us": {k: v * 1e6 for k, v in bounds.items()},
+                "vector_tflops": vflop * P / t_s / 1e12, "mfma_tflops": mflop * P / t_s / 1e12}
+        roof.update({"traffic": stored_traffic(dom, wl.name, precision, fused=True),
+                     "kernel": "defect_gru_mlp (one launch)", "avg_launch_us": avg[dom] * 1e3,
+                     "algorithmic_per_patch": unit_work, "units_per_launch": P})
+        return roof
     if dom == 0:
         unit_work = stencil_flop_per_patch(wl.K)
         achieved = unit_work * P / t_s / 1e12
@@ -287,6 +328,12 @@ def main():
         r = (run_gpu_batch if batched else run_gpu)(wl, prec, args.steps, args.warmup)
         forms[prec] = r
         print("bench: %s %.3f ms/step" % (prec, r["ms_total"] / args.steps), file=sys.stderr, flush=True)
+    if not batched and args.precision == "bf16":
+        # the same BF16 step with defect and network as separate launches
+        import paper_2008_11520_amd as pam
+        r = run_gpu(wl, "bf16", args.steps, args.warmup, flags=pam.DNNMG_F_UNFUSED)
+        forms["bf16_unfused"] = r
+        print("bench: bf16 unfused %.3f ms/step" % (r["ms_total"] / args.steps), file=sys.stderr, flush=True)
 
     main_r = forms[args.precision]
     P = main_r["P"]

@@ -68,6 +68,13 @@ enum {
  * carry separate scales in the gate products. */
 enum { DNNMG_FP32 = 0, DNNMG_BF16 = 1, DNNMG_FP8_E4M3 = 2 };
 
+/* Configuration flags.  DNNMG_F_UNFUSED: where the library would run the
+ * defect, the network input, the GRU and the MLP as one launch (K = 2, BF16
+ * operands, H = 64, Hm 0 or 64; the network input then stays on chip), run
+ * them as separate launches through an HBM buffer instead.  Both forms do
+ * the same arithmetic in the same order, so their results are bitwise equal. */
+enum { DNNMG_F_UNFUSED = 1 };
+
 /* Dirichlet sides (Eq. (boundary)); other sides are do-nothing outflow. */
 enum { DNNMG_DIR_XMIN = 1, DNNMG_DIR_XMAX = 2, DNNMG_DIR_YMIN = 4, DNNMG_DIR_YMAX = 8 };
 
@@ -81,7 +88,7 @@ typedef struct {
     double nu;           /* viscosity (>= 0)                                         */
     int precision;       /* DNNMG_FP32 / DNNMG_BF16 / DNNMG_FP8_E4M3                 */
     unsigned dirichlet;  /* DNNMG_DIR_* bits                                         */
-    unsigned flags;      /* reserved, must be 0                                      */
+    unsigned flags;      /* 0, or DNNMG_F_UNFUSED                                    */
 } dnnmg_config;
 
 /* Network sizes: N_in = 4 (n+1)^2 + 4 (prolongated velocity and defect at the

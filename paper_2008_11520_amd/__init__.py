@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libdnnmg.so")
 
 DNNMG_OK, DNNMG_EINVAL, DNNMG_ENOMEM, DNNMG_EDEVICE, DNNMG_ESTATE, DNNMG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 FP32, BF16, FP8_E4M3 = 0, 1, 2
+DNNMG_F_UNFUSED = 1
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
 
 SYMBOLS = [
@@ -99,10 +100,10 @@ def sizes(nx, ny, K):
                 Fn=(nx * n + 1) * (ny * n + 1), Nc=(nx + 1) * (ny + 1))
 
 
-def make_config(nx, ny, K, H, Hm, dt, nu, precision=FP32, dirichlet=15):
+def make_config(nx, ny, K, H, Hm, dt, nu, precision=FP32, dirichlet=15, flags=0):
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
-    return Config(nx, ny, K, H, Hm, dt, nu, precision, dirichlet, 0)
+    return Config(nx, ny, K, H, Hm, dt, nu, precision, dirichlet, flags)
 
 
 def weight_count(cfg: Config) -> int:

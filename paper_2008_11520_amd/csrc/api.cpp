@@ -75,7 +75,7 @@ int check_config(const dnnmg_config *c)
     if (c->precision < DNNMG_FP32 || c->precision > DNNMG_FP8_E4M3)
         return fail(DNNMG_EINVAL, "precision %d unknown", c->precision);
     if (c->dirichlet > 15u) return fail(DNNMG_EINVAL, "dirichlet flags 0x%x out of range", c->dirichlet);
-    if (c->flags != 0u) return fail(DNNMG_EINVAL, "flags must be 0");
+    if ((c->flags & ~(unsigned)DNNMG_F_UNFUSED) != 0u) return fail(DNNMG_EINVAL, "unknown flags 0x%x", c->flags);
     if (c->H <= 0 || c->Hm < 0) return fail(DNNMG_EINVAL, "H must be > 0 and Hm >= 0");
     if (c->H != 32 && c->H != 64 && c->H != 128)
         return fail(DNNMG_EUNSUPPORTED, "H = %d has no kernels (32, 64, 128)", c->H);
@@ -576,9 +576,15 @@ static int enqueue_step(dnnmg_ctx *c, const FlowArgs &f, hipStream_t st)
     Profile &pr = c->prof;
     hipEvent_t *ev = (pr.max_steps > 0 && pr.steps < pr.max_steps) ? &pr.ev[4 * pr.steps] : nullptr;
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[0], st));
-    HIP_OR_FAIL(launch_defect(f, nullptr, blocks_for(kKindDefect, g.nx, g.ny, g.K), g.K, f.xfmt, st));
-    if (ev) HIP_OR_FAIL(hipEventRecord(ev[1], st));
-    HIP_OR_FAIL(launch_net(f, nullptr, blocks_for(kKindNet, g.nx, g.ny, g.K), c->w->net, st));
+    if (fused_step(c->w->net) && !(g.flags & DNNMG_F_UNFUSED)) {
+        // defect, network input, GRU and MLP in one launch (stage 1 then times nothing)
+        HIP_OR_FAIL(launch_defect_net(f, nullptr, blocks_for(kKindDefect, g.nx, g.ny, g.K), c->w->net, st));
+        if (ev) HIP_OR_FAIL(hipEventRecord(ev[1], st));
+    } else {
+        HIP_OR_FAIL(launch_defect(f, nullptr, blocks_for(kKindDefect, g.nx, g.ny, g.K), g.K, f.xfmt, st));
+        if (ev) HIP_OR_FAIL(hipEventRecord(ev[1], st));
+        HIP_OR_FAIL(launch_net(f, nullptr, blocks_for(kKindNet, g.nx, g.ny, g.K), c->w->net, st));
+    }
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[2], st));
     HIP_OR_FAIL(launch_rhs(f, nullptr, blocks_for(kKindRhs, g.nx, g.ny, g.K), g.K, c->tables(), 1, st));
     if (ev) {
@@ -867,8 +873,12 @@ static int batch_enqueue(dnnmg_batch *b, bool graph, hipStream_t st)
     FlowArgs dummy{};
     int grid[kKinds];
     for (int k = 0; k < kKinds; ++k) grid[k] = graph ? b->cap : std::min(b->totals[k], b->cap);
-    HIP_OR_FAIL(launch_defect(dummy, b->dev, grid[kKindDefect], b->K, b->xfmt, st));
-    HIP_OR_FAIL(launch_net(dummy, b->dev, grid[kKindNet], b->net, st));
+    if (fused_step(b->net)) {
+        HIP_OR_FAIL(launch_defect_net(dummy, b->dev, grid[kKindDefect], b->net, st));
+    } else {
+        HIP_OR_FAIL(launch_defect(dummy, b->dev, grid[kKindDefect], b->K, b->xfmt, st));
+        HIP_OR_FAIL(launch_net(dummy, b->dev, grid[kKindNet], b->net, st));
+    }
     HIP_OR_FAIL(launch_rhs(dummy, b->dev, grid[kKindRhs], b->K, b->tab, 1, st));
     if (b->gather) HIP_OR_FAIL(launch_gather(dummy, b->dev, grid[kKindGather], st));
     return DNNMG_OK;

@@ -174,8 +174,145 @@ __device__ inline void element_sums(const float m[2][2], const float Qs[2][2], c
     R[6] = hm0 * mt0 + hm1 * mt1 + Sx1 + Sy1;
 }
 
-template <int K, typename XT, bool OPAQUE_TID>
-__device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
+// ------------------------------------------------- defect + network fusion
+// For K = 2 a defect tile covers 8 x 8 = 64 patches, one network tile: the
+// fused step keeps the network input in LDS and runs the GRU and MLP of the
+// tile right after its defect (BF16 operands, H = 64).  Layout and MFMA use
+// follow the persistent network kernel (products formed transposed, so a lane
+// holds one patch row and four consecutive units); wave w owns hidden tile w
+// for all four row tiles and loads that tile's weight fragments itself.
+constexpr int kFusedLDA = 6 * 32 + 8;          // [x | h | 0] rows, 16-byte padding
+constexpr int kFusedLDH = 64 + 8;
+
+template <int HM>
+__device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int tid, const NetArgs &net,
+                                          __bf16 *sA, __bf16 *sR, __bf16 *sHp, __bf16 *sAm, const f4 (&hp)[4])
+{
+    constexpr int nin = 104, nout = 50, H = 64, KC = 32, KQ = 8, KC1 = 6, TP = 8, RT = 4, HT = 4;
+    constexpr int LDA = kFusedLDA, LDH = kFusedLDH, PADK = KC1 * KC - nin - H;
+    const int nx = f.nx, ny = f.ny;
+    const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lq = lane >> 4;
+    const int ht = wave, ucol = 16 * ht + 4 * lq;
+    auto patch = [&](int r) { return (size_t)(ty * TP + r / TP) * nx + tx * TP + r % TP; };
+    auto valid = [&](int r) { return tx * TP + r % TP < nx && ty * TP + r / TP < ny; };
+    const bf8 *B1 = pinned<bf8>(net.B1);
+    const bf8 *B2 = pinned<bf8>(net.B2);
+    const bf8 *B3 = pinned<bf8>(net.B3);
+    const bf8 *B4 = pinned<bf8>(net.B4);
+    // the state (prefetched at the start of the tile) next to the network input
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        bf4 hb;
+        hb[0] = (__bf16)hp[q].x; hb[1] = (__bf16)hp[q].y; hb[2] = (__bf16)hp[q].z; hb[3] = (__bf16)hp[q].w;
+        *reinterpret_cast<bf4 *>(&sA[(16 * q + li) * LDA + nin + ucol]) = hb;
+    }
+    for (int t = tid; t < 64 * PADK; t += kThreads) sA[(t / PADK) * LDA + nin + H + t % PADK] = (__bf16)0.f;
+    __syncthreads();
+
+    // ---- phase 1: the three gates of this wave's hidden tile, four row tiles
+    f4 az[RT], ar[RT], ah[RT];
+#pragma unroll
+    for (int q = 0; q < RT; ++q) az[q] = ar[q] = ah[q] = f4{0.f, 0.f, 0.f, 0.f};
+    // weight fragments chunk by chunk (L2-resident; other waves cover the latency)
+#pragma unroll
+    for (int kc = 0; kc < KC1; ++kc) {
+        const bf8 wz = B1[((0 * HT + ht) * KC1 + kc) * 64 + lane];
+        const bf8 wr = B1[((1 * HT + ht) * KC1 + kc) * 64 + lane];
+        const bf8 wh = B1[((2 * HT + ht) * KC1 + kc) * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            const bf8 a = *reinterpret_cast<const bf8 *>(&sA[(16 * q + li) * LDA + kc * KC + lq * KQ]);
+            az[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wz, a, az[q], 0, 0, 0);
+            ar[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr, a, ar[q], 0, 0, 0);
+            ah[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, a, ah[q], 0, 0, 0);
+        }
+    }
+    bf8 w2[2];
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) w2[kc] = B2[(ht * 2 + kc) * 64 + lane];
+    const f4 (&hold)[RT] = hp;
+    __syncthreads();   // every wave is done with the input rows (r*h reuses them)
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        const int r = 16 * q + li;
+        bf4 rh;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            az[q][e] = sigmoid(az[q][e]);
+            rh[e] = (__bf16)(sigmoid(ar[q][e]) * hold[q][e]);
+        }
+        *reinterpret_cast<bf4 *>(&sR[r * LDH + ucol]) = rh;
+    }
+    __syncthreads();
+
+    // ---- phase 2: U_h (r*h); new state
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        const int r = 16 * q + li;
+        f4 au = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc)
+            au = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[kc], *reinterpret_cast<const bf8 *>(&sR[r * LDH + kc * KC + lq * KQ]), au, 0, 0, 0);
+        f4 hn;
+        bf4 hb;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float z = az[q][e];
+            hn[e] = z * hold[q][e] + (1.0f - z) * fast_tanh(ah[q][e] + au[e]);
+            hb[e] = (__bf16)hn[e];
+        }
+        if (valid(r)) *reinterpret_cast<f4 *>(f.h + patch(r) * H + ucol) = hn;
+        *reinterpret_cast<bf4 *>(&sHp[r * LDH + ucol]) = hb;
+    }
+    __syncthreads();
+
+    // ---- MLP head: M2 relu(M1 h') (HM = 64) or M h' (HM = 0); wave w makes output tile w
+    const __bf16 *src = sHp;
+    bf8 wo[2];
+    if constexpr (HM > 0) {
+        bf8 w3[2];
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc) w3[kc] = B3[(ht * 2 + kc) * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            const int r = 16 * q + li;
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3[kc], *reinterpret_cast<const bf8 *>(&sHp[r * LDH + kc * KC + lq * KQ]), acc, 0, 0, 0);
+            bf4 m;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) m[e] = (__bf16)fmaxf(acc[e], 0.f);
+            *reinterpret_cast<bf4 *>(&sAm[r * LDH + ucol]) = m;
+        }
+        __syncthreads();
+        src = sAm;
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc) wo[kc] = B4[(ht * 2 + kc) * 64 + lane];
+    } else {
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc) wo[kc] = B3[(ht * 2 + kc) * 64 + lane];
+    }
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        const int r = 16 * q + li;
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wo[kc], *reinterpret_cast<const bf8 *>(&src[r * LDH + kc * KC + lq * KQ]), acc, 0, 0, 0);
+        // nout is even: the pairs (ucol, ucol+1), (ucol+2, ucol+3) are inside or outside together
+        if (valid(r)) {
+            float *o = f.dpatch + patch(r) * nout + ucol;
+            if (ucol < nout) *reinterpret_cast<float2 *>(o) = make_float2(acc[0], acc[1]);
+            if (ucol + 2 < nout) *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[2], acc[3]);
+        }
+    }
+}
+
+// FUSED (K = 2, BF16 input): the network input stays in LDS and the tile's
+// GRU and MLP run right after (gru_fused); HM is the MLP hidden width.
+template <int K, typename XT, bool OPAQUE_TID, bool FUSED = false, int HM = 0>
+__device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const NetArgs *net = nullptr)
 {
     const int tid = OPAQUE_TID ? tile_thread() : (int)threadIdx.x;
     constexpr int n = 1 << K;
@@ -192,14 +329,16 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
     typedef typename std::conditional<FP8, float, XT>::type ST;
     constexpr int XS8 = xstride_fp8(nin);        // FP8 row stride (bytes)
     constexpr size_t kWBytes = sizeof(float2) * NN * NN;
-    constexpr size_t kXBytes = FP8 ? (size_t)TP * TP * XS8 : sizeof(ST) * TP * TP * nin;
+    static_assert(!FUSED || (K == 2 && std::is_same<XT, __bf16>::value), "fused step: K = 2, BF16");
+    constexpr size_t kXBytes = FUSED ? sizeof(__bf16) * 64 * kFusedLDA
+                                     : (FP8 ? (size_t)TP * TP * XS8 : sizeof(ST) * TP * TP * nin);
     __shared__ CoarseRec s_c[CE * CE];
     // (u_prev - P v) / dt at nodes; once the element residuals are formed the
     // same bytes hold the tile's network-input rows
     __shared__ __align__(16) unsigned char s_wx[kWBytes > kXBytes ? kWBytes : kXBytes];
     float2 *s_w = reinterpret_cast<float2 *>(s_wx);
     ST *s_x = reinterpret_cast<ST *>(s_wx);
-    __shared__ float2 s_acc[NN * NN];           // assembled residual at nodes
+    __shared__ __align__(16) float2 s_acc[NN * NN];   // assembled residual at nodes
 
     const int nx = f.nx, ny = f.ny, NX = nx * n, NY = ny * n;
     const int tiles_x = (nx + TP - 1) / TP;
@@ -219,6 +358,20 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
         const int I = I0 - 1 + t % NN, J = J0 - 1 + t / NN;
         const bool in = t < NN * NN && !first && I >= 0 && I <= NX && J >= 0 && J <= NY;
         uq[i] = in ? reinterpret_cast<const float2 *>(f.uprev)[(size_t)J * (NX + 1) + I] : make_float2(0.f, 0.f);
+    }
+
+    // fused: the tile's GRU state, loaded early in the layout the network
+    // phase uses (wave w, lane (li, lq): rows 16 q + li, units 16 w + 4 lq)
+    f4 hp[4];
+    if constexpr (FUSED) {
+        const int li = tid & 15, col = 16 * (tid >> 6) + 4 * ((tid >> 4) & 3);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 16 * q + li;
+            const int pi = tx * TP + r % TP, pj = ty * TP + r / TP;
+            hp[q] = (pi < nx && pj < ny) ? *reinterpret_cast<const f4 *>(f.h + ((size_t)pj * nx + pi) * 64 + col)
+                                         : f4{0.f, 0.f, 0.f, 0.f};
+        }
     }
 
     // 1. coarse-element records
@@ -391,7 +544,7 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
         if (f.D && (li < kTileFine || I == NX) && (lj < kTileFine || J == NY))
             reinterpret_cast<float2 *>(f.D)[(size_t)J * (NX + 1) + I] = d;
     }
-    if (!f.X) return;
+    if (!FUSED && !f.X) return;
     __syncthreads();
 
     const int npr = min(TP, nx - tx * TP);            // patches of this tile row inside the mesh
@@ -469,7 +622,7 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
             const int pl = t / (nf + 1), l = t - pl * (nf + 1);
             const int pa = pl % TP, pb = pl / TP;
             const int pi = tx * TP + pa, pj = ty * TP + pb;
-            ST *o = s_x + pl * nin;
+            ST *o = FUSED ? s_x + pl * kFusedLDA : s_x + pl * nin;
             if (pi >= nx || pj >= ny) continue;
             if (l == nf) {
                 const float4 ft = reinterpret_cast<const float4 *>(f.feat)[(size_t)pj * nx + pi];
@@ -486,6 +639,13 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk)
             o[2 * nf + 2 * l] = (ST)d.x; o[2 * nf + 2 * l + 1] = (ST)d.y;
         }
         __syncthreads();
+        if constexpr (FUSED) {
+            // the network input rows stay in LDS; r*h, h' reuse them after phase
+            // 1 and the MLP hidden layer reuses the node accumulators
+            __bf16 *sA = reinterpret_cast<__bf16 *>(s_wx);
+            gru_fused<HM>(f, tx, ty, tid, *net, sA, sA, sA + 64 * kFusedLDH, reinterpret_cast<__bf16 *>(s_acc), hp);
+            return;
+        }
         constexpr int CPR = TP * nin * sizeof(XT) / 16;   // 16-byte pieces per tile row of patches
         for (int t = tid; t < TP * CPR; t += kThreads) {
             const int pb = t / CPR, c = t - pb * CPR;
@@ -515,6 +675,39 @@ __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const Batc
         defect_tile<K, XT, true>(f, blk);
         __syncthreads();   // LDS is reused by the next tile
     }
+}
+
+template <bool BATCHED, int HM>
+__global__ __launch_bounds__(kThreads, 3) void k_defect_net(FlowArgs single, const BatchTable *__restrict__ bt, NetArgs net)
+{
+    if (!BATCHED) {
+        defect_tile<2, __bf16, false, true, HM>(single, blockIdx.x, &net);
+        return;
+    }
+    const int total = bt->prefix[kKindDefect][bt->nflows];
+#pragma unroll 1
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        int blk = g;
+        const FlowArgs &f = *batch_flow(bt, kKindDefect, blk);
+        defect_tile<2, __bf16, true, true, HM>(f, blk, &net);
+        __syncthreads();   // LDS is reused by the next tile
+    }
+}
+
+bool fused_step(const NetArgs &net) { return net.prec == 1 && net.K == 2 && net.H == 64 && (net.Hm == 0 || net.Hm == 64); }
+
+hipError_t launch_defect_net(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net, hipStream_t s)
+{
+    if (!fused_step(net)) return hipErrorInvalidValue;
+    dim3 g(nblocks), b(kThreads);
+    if (net.Hm == 64) {
+        if (bt) hipLaunchKernelGGL((k_defect_net<true, 64>), g, b, 0, s, f, bt, net);
+        else hipLaunchKernelGGL((k_defect_net<false, 64>), g, b, 0, s, f, bt, net);
+    } else {
+        if (bt) hipLaunchKernelGGL((k_defect_net<true, 0>), g, b, 0, s, f, bt, net);
+        else hipLaunchKernelGGL((k_defect_net<false, 0>), g, b, 0, s, f, bt, net);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, int xfmt, hipStream_t s)

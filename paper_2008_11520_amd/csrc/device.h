@@ -5,6 +5,16 @@
 
 namespace dnnmg {
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+
+// Logistic function and tanh from the hardware exponential and reciprocal
+// (tanh x = 1 - 2 / (1 + e^{2x})); absolute error ~1e-7, which is what the
+// state update h' = z h + (1 - z) tanh(.) needs.
+__device__ inline float sigmoid(float t) { return __builtin_amdgcn_rcpf(1.0f + __expf(-t)); }
+__device__ inline float fast_tanh(float t) { return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * t)); }
+
 // The thread's index in its workgroup, opaque to the optimiser.  The batched
 // kernels loop over tiles; with the plain index the compiler hoists every
 // index-derived address and mask out of that loop and keeps them live across
@@ -15,6 +25,16 @@ __device__ inline int tile_thread()
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
     return t;
+}
+
+// A pointer the optimiser cannot move loads through from before this point:
+// keeps weight loads where they are written instead of hoisted to the top of
+// a kernel, where they would hold registers through unrelated phases.
+template <typename T>
+__device__ inline const T *pinned(const void *p)
+{
+    asm volatile("" : "+s"(p));
+    return reinterpret_cast<const T *>(p);
 }
 
 }  // namespace dnnmg

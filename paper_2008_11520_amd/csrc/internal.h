@@ -83,6 +83,10 @@ hipError_t launch_geometry(const double *cxy, int nx, int ny, float *geo, double
                            float *feat, int *bad, hipStream_t s);
 hipError_t launch_prolong(const FlowArgs &f, int K, float *pv, float *pp, hipStream_t s);
 hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, int xfmt, hipStream_t s);
+// Defect + GRU + MLP in one launch (K = 2, BF16 operands, H = 64, Hm 0 or 64):
+// the network input never leaves LDS.  fused_step tells whether it applies.
+bool fused_step(const NetArgs &net);
+hipError_t launch_defect_net(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net, hipStream_t s);
 // FP8 activation quantiser (stage entry point): rows x cols FP32 -> codes, scales.
 hipError_t launch_quantize(const float *a, int rows, int cols, uint8_t *q, float *s, hipStream_t st);
 hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net,

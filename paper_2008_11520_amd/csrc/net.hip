@@ -24,9 +24,6 @@
 
 namespace dnnmg {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 
 template <int PREC> struct Op;
 
@@ -79,11 +76,6 @@ template <> struct Op<1> {
     }
 };
 
-// Logistic function and tanh from the hardware exponential and reciprocal
-// (tanh x = 1 - 2 / (1 + e^{2x})); absolute error ~1e-7, which is what the
-// state update h' = z h + (1 - z) tanh(.) needs.
-__device__ inline float sigmoid(float t) { return __builtin_amdgcn_rcpf(1.0f + __expf(-t)); }
-__device__ inline float fast_tanh(float t) { return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * t)); }
 
 template <int PREC, int H>
 __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net)

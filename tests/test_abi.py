@@ -125,3 +125,15 @@ def test_fp8_config_sizes_and_quantiser_validation():
     assert L.dnnmg_quantize_e4m3(None, 1, 1, fake, fake, None) == pam.DNNMG_EINVAL
     assert L.dnnmg_quantize_e4m3(fake, 0, 4, fake, fake, None) == pam.DNNMG_EINVAL
     assert L.dnnmg_quantize_e4m3(fake, 4, 0, fake, fake, None) == pam.DNNMG_EINVAL
+
+
+def test_unknown_flags_rejected_on_host():
+    L = pam.lib()
+    c = cfg(flags=2)
+    s = pam.sizes(4, 3, 2)
+    cxy = np.zeros(2 * s["Nc"])
+    w = np.zeros(pam.weight_count(c), dtype=np.float32)
+    out = ctypes.c_void_p()
+    rc = L.dnnmg_create(ctypes.byref(c), cxy.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p),
+                        w.size, None, ctypes.byref(out))
+    assert rc == pam.DNNMG_EINVAL and b"flags" in L.dnnmg_last_error()

@@ -209,6 +209,24 @@ def test_bitwise_determinism():
             assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("Hm", [64, 0])
+def test_fused_step_equals_unfused_bitwise(Hm):
+    """K=2, H=64, BF16: the one-launch defect + GRU + MLP and the separate
+    launches do the same arithmetic in the same order."""
+    import paper_2008_11520_amd as pam
+    flow = synth.channel_flow(13, 7, 3, 0.005, perturb_seed=5)
+    K, H = 2, 64
+    w = synth.xavier_weights(K, H, Hm, 1234)
+    runs = []
+    for flags in (0, pam.DNNMG_F_UNFUSED):
+        cfg = pam.make_config(flow.nx, flow.ny, K, H, Hm, flow.dt, 1e-3, "bf16", flow.dirichlet, flags)
+        g = GpuRunner(pam.DnnMG(cfg, flow.cxy, w))
+        runs.append([g.step(*flow.fields(n)) for n in range(4)])
+    for a, b in zip(*runs):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+
+
 def test_batched_step_equals_single_steps_bitwise():
     import torch
     import paper_2008_11520_amd as pam
