@@ -1015,6 +1015,197 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_q8p(FlowArgs single, 
     }
 }
 
+// Persistent BF16 kernel for the shapes k_net_h64 does not cover (H = 128,
+// or K = 3), Hm = 0 or H.  Eight waves; wave w owns hidden tile w % HT for
+// 4 / (8 / HT) row tiles of each 64-patch tile, as in k_net_q8p.  The weights
+// (368 KB at K = 3, H = 128) do not fit in registers or LDS, so each wave
+// streams its hidden tile's fragments from L2 once per 64-patch tile; the
+// input and state rows are staged through LDS and prefetched one tile ahead.
+template <int K, int H, int HM>
+__global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16p(FlowArgs single, const BatchTable *__restrict__ bt,
+                                                                NetArgs net, int ntiles)
+{
+    typedef Op<1> O;
+    constexpr int n = 1 << K, nf = (n + 1) * (n + 1), nin = 4 * nf + 4, nout = 2 * nf;
+    constexpr int KC = 32, KQ = 8, KC1 = (nin + H + KC - 1) / KC, HC = H / KC;
+    constexpr int HT = H / 16, WPH = 8 / HT, RTW = 4 / WPH;
+    constexpr int OT = (nout + 15) / 16;
+    constexpr int LDA = KC1 * KC + 8, LDH = H + 8, LDS32 = H + 4;
+    constexpr int PADK = KC1 * KC - nin - H;
+    static_assert(HM == 0 || HM == H, "MLP hidden tiles follow the hidden tiles");
+    static_assert(nin % 8 == 0, "input rows in 16-byte pieces");
+    if (bt) ntiles = bt->prefix[kKindNet][bt->nflows];
+
+    __shared__ __align__(16) __bf16 sA[64 * LDA];        // [x | h | 0] rows (BF16)
+    __shared__ __align__(16) float sH[64 * LDS32];       // FP32 state rows
+    __shared__ __align__(16) __bf16 sR[64 * LDH];        // r*h
+    __shared__ __align__(16) __bf16 sHp[64 * LDH];       // h'
+    __shared__ __align__(16) __bf16 sAm[64 * LDH];       // MLP hidden layer
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lq = lane >> 4;
+    const int ht = wave % HT, rt0 = RTW * (wave / HT);
+    const int ucol = 16 * ht + 4 * lq;
+    const bf8 *B1 = reinterpret_cast<const bf8 *>(net.B1);
+    const bf8 *B2 = reinterpret_cast<const bf8 *>(net.B2);
+    const bf8 *B3 = reinterpret_cast<const bf8 *>(net.B3);
+    const bf8 *B4 = reinterpret_cast<const bf8 *>(net.B4);
+
+    constexpr int XCH = 64 * nin / 8, HCH = 64 * H / 4;
+    constexpr int XPT = (XCH + kNetH64Threads - 1) / kNetH64Threads;
+    constexpr int HPT = (HCH + kNetH64Threads - 1) / kNetH64Threads;
+    bf8 xr[XPT];
+    f4 hr[HPT];
+    auto load_tile = [&](int tile) {
+        int blk = tile;
+        const FlowArgs *fq = bt ? batch_flow(bt, kKindNet, blk) : &single;
+        const int P = fq->nx * fq->ny, row0 = blk * 64, nrows = min(64, P - row0);
+        const bf8 *xg = reinterpret_cast<const bf8 *>(reinterpret_cast<const __bf16 *>(fq->X) + (size_t)row0 * nin);
+        const f4 *hgv = reinterpret_cast<const f4 *>(fq->h + (size_t)row0 * H);
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) {
+            const int c = tid + i * kNetH64Threads;
+            xr[i] = (c < XCH && c / (nin / 8) < nrows) ? xg[c] : bf8{};
+        }
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
+            const int c = tid + i * kNetH64Threads;
+            hr[i] = (c < HCH && c / (H / 4) < nrows) ? hgv[c] : f4{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    if (PADK > 0)
+        for (int t = tid; t < 64 * PADK; t += kNetH64Threads) sA[(t / PADK) * LDA + nin + H + t % PADK] = (__bf16)0.f;
+    if (blockIdx.x < ntiles) load_tile(blockIdx.x);
+
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        int blk = tile;
+        const FlowArgs &ff = bt ? *batch_flow(bt, kKindNet, blk) : single;
+        const int P = ff.nx * ff.ny;
+        const int row0 = blk * 64;
+        const int nrows = min(64, P - row0);
+        float *hg = ff.h + (size_t)row0 * H;
+        float *dp = ff.dpatch + (size_t)row0 * nout;
+
+        __syncthreads();   // the previous tile's readers of LDS are done
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) {
+            const int c = tid + i * kNetH64Threads;
+            if (c < XCH) *reinterpret_cast<bf8 *>(&sA[(c / (nin / 8)) * LDA + 8 * (c % (nin / 8))]) = xr[i];
+        }
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
+            const int c = tid + i * kNetH64Threads;
+            if (c < HCH) {
+                const int r = c / (H / 4), k = 4 * (c % (H / 4));
+                *reinterpret_cast<f4 *>(&sH[r * LDS32 + k]) = hr[i];
+                bf4 hb;
+                hb[0] = (__bf16)hr[i].x; hb[1] = (__bf16)hr[i].y; hb[2] = (__bf16)hr[i].z; hb[3] = (__bf16)hr[i].w;
+                *reinterpret_cast<bf4 *>(&sA[r * LDA + nin + k]) = hb;
+            }
+        }
+        if (tile + (int)gridDim.x < ntiles) load_tile(tile + gridDim.x);
+        __syncthreads();
+
+        // ---- phase 1: weight fragments streamed chunk by chunk
+        f4 az[RTW], ar[RTW], ah[RTW];
+#pragma unroll
+        for (int q = 0; q < RTW; ++q) az[q] = ar[q] = ah[q] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 3
+        for (int kc = 0; kc < KC1; ++kc) {
+            const bf8 wz = B1[((0 * HT + ht) * KC1 + kc) * 64 + lane];
+            const bf8 wr = B1[((1 * HT + ht) * KC1 + kc) * 64 + lane];
+            const bf8 wh = B1[((2 * HT + ht) * KC1 + kc) * 64 + lane];
+#pragma unroll
+            for (int q = 0; q < RTW; ++q) {
+                const bf8 a = *reinterpret_cast<const bf8 *>(&sA[(16 * (rt0 + q) + li) * LDA + kc * KC + lq * KQ]);
+                az[q] = O::mma(az[q], wz, a);
+                ar[q] = O::mma(ar[q], wr, a);
+                ah[q] = O::mma(ah[q], wh, a);
+            }
+        }
+        f4 hold[RTW];
+#pragma unroll
+        for (int q = 0; q < RTW; ++q) {
+            const int r = 16 * (rt0 + q) + li;
+            hold[q] = *reinterpret_cast<const f4 *>(&sH[r * LDS32 + ucol]);
+            bf4 rh;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                az[q][e] = sigmoid(az[q][e]);
+                rh[e] = (__bf16)(sigmoid(ar[q][e]) * hold[q][e]);
+            }
+            *reinterpret_cast<bf4 *>(&sR[r * LDH + ucol]) = rh;
+        }
+        __syncthreads();
+
+        // ---- phase 2: U_h (r*h); new state
+        bf8 w2[HC];
+#pragma unroll
+        for (int kc = 0; kc < HC; ++kc) w2[kc] = B2[(ht * HC + kc) * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < RTW; ++q) {
+            const int r = 16 * (rt0 + q) + li;
+            f4 au = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < HC; ++kc)
+                au = O::mma(au, w2[kc], *reinterpret_cast<const bf8 *>(&sR[r * LDH + kc * KC + lq * KQ]));
+            f4 hn;
+            bf4 hb;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float z = az[q][e];
+                hn[e] = z * hold[q][e] + (1.0f - z) * fast_tanh(ah[q][e] + au[e]);
+                hb[e] = (__bf16)hn[e];
+            }
+            if (r < nrows) *reinterpret_cast<f4 *>(hg + (size_t)r * H + ucol) = hn;
+            *reinterpret_cast<bf4 *>(&sHp[r * LDH + ucol]) = hb;
+        }
+        __syncthreads();
+
+        // ---- MLP head
+        const __bf16 *src = sHp;
+        const bf8 *Wo = B3;
+        constexpr int CO = HC;          // HM == H or 0: both layers have H-wide inputs
+        if constexpr (HM > 0) {
+#pragma unroll
+            for (int q = 0; q < RTW; ++q) {
+                const int r = 16 * (rt0 + q) + li;
+                f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kc = 0; kc < HC; ++kc)
+                    acc = O::mma(acc, B3[(ht * HC + kc) * 64 + lane], *reinterpret_cast<const bf8 *>(&sHp[r * LDH + kc * KC + lq * KQ]));
+                bf4 m;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) m[e] = (__bf16)fmaxf(acc[e], 0.f);
+                *reinterpret_cast<bf4 *>(&sAm[r * LDH + ucol]) = m;
+            }
+            __syncthreads();
+            src = sAm;
+            Wo = B4;
+        }
+        for (int ot = ht; ot < OT; ot += HT) {
+            const int oc = 16 * ot + 4 * lq;
+            bf8 wo[CO];
+#pragma unroll
+            for (int kc = 0; kc < CO; ++kc) wo[kc] = Wo[(ot * CO + kc) * 64 + lane];
+#pragma unroll
+            for (int q = 0; q < RTW; ++q) {
+                const int r = 16 * (rt0 + q) + li;
+                f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kc = 0; kc < CO; ++kc)
+                    acc = O::mma(acc, wo[kc], *reinterpret_cast<const bf8 *>(&src[r * LDH + kc * KC + lq * KQ]));
+                // nout is even: the pairs (oc, oc+1), (oc+2, oc+3) are inside or outside together
+                if (r < nrows) {
+                    float *o = dp + (size_t)r * nout + oc;
+                    if (oc < nout) *reinterpret_cast<float2 *>(o) = make_float2(acc[0], acc[1]);
+                    if (oc + 2 < nout) *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[2], acc[3]);
+                }
+            }
+        }
+    }
+}
+
 static int g_num_cus = 0;
 
 static bool use_h64(int prec, int K, int H, int Hm) { return prec == 1 && H == 64 && K <= 2 && (Hm == 0 || Hm == 64); }
@@ -1023,7 +1214,11 @@ static bool use_q8p(const NetArgs &net)
 {
     return net.prec == 2 && (net.H == 64 || net.H == 128) && (net.Hm == 0 || net.Hm == net.H);
 }
-static bool persistent(const NetArgs &net) { return use_h64(net) || use_q8p(net); }
+static bool use_b16p(const NetArgs &net)
+{
+    return net.prec == 1 && !use_h64(net) && (net.H == 64 || net.H == 128) && (net.Hm == 0 || net.Hm == net.H);
+}
+static bool persistent(const NetArgs &net) { return use_h64(net) || use_q8p(net) || use_b16p(net); }
 
 bool net_needs_x(int prec, int K, int H, int Hm) { return !use_h64(prec, K, H, Hm); }
 
@@ -1056,6 +1251,22 @@ hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int ntiles, const
     if (use_h64(net)) {
         if (net.K == 1) hipLaunchKernelGGL(k_net_h64<1>, dim3(nblocks), dim3(kNetH64Threads), 0, s, f, bt, net, ntiles);
         else hipLaunchKernelGGL(k_net_h64<2>, dim3(nblocks), dim3(kNetH64Threads), 0, s, f, bt, net, ntiles);
+        return hipGetLastError();
+    }
+    if (use_b16p(net)) {
+        dim3 g(nblocks), b(kNetH64Threads);
+#define DNNMG_B16P(KK, HH, MM) hipLaunchKernelGGL((k_net_b16p<KK, HH, MM>), g, b, 0, s, f, bt, net, ntiles)
+#define DNNMG_B16P_H(KK)                                                                             \
+        if (net.H == 64) { if (net.Hm == 64) DNNMG_B16P(KK, 64, 64); else DNNMG_B16P(KK, 64, 0); }    \
+        else { if (net.Hm == 128) DNNMG_B16P(KK, 128, 128); else DNNMG_B16P(KK, 128, 0); }
+        switch (net.K) {
+        case 1: DNNMG_B16P_H(1) break;
+        case 2: DNNMG_B16P_H(2) break;
+        case 3: DNNMG_B16P_H(3) break;
+        default: return hipErrorInvalidValue;
+        }
+#undef DNNMG_B16P_H
+#undef DNNMG_B16P
         return hipGetLastError();
     }
     if (use_q8p(net)) {

@@ -14,7 +14,9 @@ Fourier field, and step n reads level n mod ring.
 
 Per-step latency is the time from the moment a flow's step becomes eligible
 (its admission, or the completion of its previous step) to the completion of
-the tick that carries it.
+the tick that carries it.  Ticks are pipelined: while the GPU runs one, the
+host admits arrivals and issues the next, and a flow's buffers are released
+only after the tick with its last step has finished.
 """
 from __future__ import annotations
 
@@ -65,7 +67,8 @@ class Active:
     pring: object           # (ring, Nc) float32 device tensor
     b_out: object           # (Nc*2,) float64 device tensor: restricted rhs of the last step
     bytes: int
-    step: int = 0
+    step: int = 0            # steps issued
+    completed: int = 0       # steps whose tick has finished
     eligible: float = 0.0
     admitted: float = 0.0
     latencies: list = field(default_factory=list)
@@ -122,22 +125,45 @@ class Server:
                                         steps=a.step, queue_delay=a.req["admitted_at"] - a.req["queued_at"])
         a.ctx.close()
 
-    def run(self, requests, time_scale=1.0, log_every=0.0, results=None):
+    def run(self, requests, time_scale=1.0, log_every=0.0, results=None, depth=2):
         """Serve `requests` (dicts with id, arrival [s], nx, ny, steps,
         field_seed).  Arrival times are divided by time_scale (10 = ten times
-        the offered rate).  Returns pooled statistics; with a dict `results`,
+        the offered rate).  Up to `depth` ticks are in flight: the host admits
+        requests and prepares tick n+1 while the GPU runs tick n (stream order
+        keeps them apart).  Returns pooled statistics; with a dict `results`,
         also each request's final state (h, corrected velocity) and last b_L."""
+        import collections
         import torch
         pending = sorted((dict(r) for r in requests), key=lambda r: r["arrival"])
         sched = Scheduler(self.hbm_budget, self.max_flows, lambda r: self.flow_bytes(r["nx"], r["ny"]))
-        active, done = [], []
-        max_conc = 0
+        active, done = [], []            # flows still issuing steps; finished flows
+        inflight = collections.deque()   # ticks on the GPU: (start event, end event, members)
+        spare = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                 for _ in range(depth + 1)]
+        stats = dict(ticks=0, conc=0, patch_steps=0, busy=0.0, max_conc=0)
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
-        ticks, conc_sum, patch_steps, gpu_busy = 0, 0, 0, 0.0
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         last_log = 0.0
-        while pending or sched.queue or active:
+
+        def complete_oldest():
+            e0, e1, members = inflight.popleft()
+            e1.synchronize()
+            t_done = now()
+            stats["busy"] += e0.elapsed_time(e1) / 1e3
+            spare.append((e0, e1))
+            for a in members:
+                a.latencies.append(t_done - a.eligible)
+                a.eligible = t_done
+                a.completed += 1
+                stats["patch_steps"] += a.req["nx"] * a.req["ny"]
+                if a.completed >= a.req["steps"]:
+                    a.req["finished_at"] = t_done
+                    done.append(a)
+                    self.retire(a, results)
+                    sched.release(a.req)
+            return t_done
+
+        while pending or sched.queue or active or inflight:
             t = now()
             while pending and pending[0]["arrival"] / time_scale <= t:
                 r = pending.pop(0)
@@ -147,56 +173,48 @@ class Server:
                 a = self.admit(r, now())
                 r["admitted_at"] = a.admitted
                 active.append(a)
-            max_conc = max(max_conc, len(active))
-            if not active:
-                if pending:
-                    time.sleep(max(0.0, min(pending[0]["arrival"] / time_scale - now(), 0.01)))
+            stats["max_conc"] = max(stats["max_conc"], len(active))
+            if active and len(inflight) < depth:
+                # issue one tick: every active flow advances one step
+                flows = [a.ctx for a in active]
+                vs = [a.vring[a.step % self.ring] for a in active]
+                ps = [a.pring[a.step % self.ring] for a in active]
+                e0, e1 = spare.pop()
+                with torch.cuda.stream(self.stream):
+                    self.batch.prepare(flows, vs, ps, None, [a.b_out for a in active], stream=self.stream)
+                    e0.record(self.stream)
+                    self.batch.launch(graph=self.use_graph, stream=self.stream)
+                    e1.record(self.stream)
+                inflight.append((e0, e1, list(active)))
+                stats["ticks"] += 1
+                stats["conc"] += len(active)
+                for a in active:
+                    a.step += 1
+                active = [a for a in active if a.step < a.req["steps"]]
                 continue
-            # one tick: every active flow advances one step
-            flows = [a.ctx for a in active]
-            vs = [a.vring[a.step % self.ring] for a in active]
-            ps = [a.pring[a.step % self.ring] for a in active]
-            with torch.cuda.stream(self.stream):
-                self.batch.prepare(flows, vs, ps, None, [a.b_out for a in active], stream=self.stream)
-                ev0.record(self.stream)
-                self.batch.launch(graph=self.use_graph, stream=self.stream)
-                ev1.record(self.stream)
-            ev1.synchronize()
-            t_done = now()
-            gpu_busy += ev0.elapsed_time(ev1) / 1e3
-            ticks += 1
-            conc_sum += len(active)
-            still = []
-            for a in active:
-                a.latencies.append(t_done - a.eligible)
-                a.eligible = t_done
-                a.step += 1
-                patch_steps += a.req["nx"] * a.req["ny"]
-                if a.step >= a.req["steps"]:
-                    a.req["finished_at"] = t_done
-                    done.append(a)
-                    self.retire(a, results)
-                    sched.release(a.req)
-                else:
-                    still.append(a)
-            active = still
-            if log_every and t_done - last_log > log_every:
-                last_log = t_done
-                print("serve: t=%.1fs active=%d queued=%d done=%d" % (t_done, len(active), len(sched.queue),
-                                                                       len(done)), flush=True)
+            if inflight:
+                t_done = complete_oldest()
+                if log_every and t_done - last_log > log_every:
+                    last_log = t_done
+                    print("serve: t=%.1fs active=%d queued=%d done=%d" % (t_done, len(active), len(sched.queue),
+                                                                           len(done)), flush=True)
+            elif pending:
+                time.sleep(max(0.0, min(pending[0]["arrival"] / time_scale - now(), 0.01)))
         wall = now()
         lat = np.concatenate([np.asarray(a.latencies) for a in done]) if done else np.zeros(0)
         qdelay = np.array([a.req["admitted_at"] - a.req["queued_at"] for a in done])
+        ticks = stats["ticks"]
         return {
             "requests": len(done),
             "steps": int(lat.size),
             "ticks": ticks,
+            "depth": depth,
             "wall_s": wall,
-            "gpu_busy_s": gpu_busy,
-            "patch_steps": patch_steps,
-            "patch_steps_per_s": patch_steps / wall if wall > 0 else 0.0,
-            "mean_concurrency": conc_sum / ticks if ticks else 0.0,
-            "max_concurrency": max_conc,
+            "gpu_busy_s": stats["busy"],
+            "patch_steps": stats["patch_steps"],
+            "patch_steps_per_s": stats["patch_steps"] / wall if wall > 0 else 0.0,
+            "mean_concurrency": stats["conc"] / ticks if ticks else 0.0,
+            "max_concurrency": stats["max_conc"],
             "p50_step_latency_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
             "p99_step_latency_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
             "max_step_latency_ms": float(lat.max() * 1e3) if lat.size else None,
