@@ -181,15 +181,16 @@ __device__ inline void element_sums(const float m[2][2], const float Qs[2][2], c
 // follow the persistent network kernel (products formed transposed, so a lane
 // holds one patch row and four consecutive units); wave w owns hidden tile w
 // for all four row tiles and loads that tile's weight fragments itself.
-constexpr int kFusedLDA = 6 * 32 + 8;          // [x | h | 0] rows, 16-byte padding
+constexpr int kFusedLDA = 104 + 64 + 8;        // [x | h] rows (168 values), 16-byte padding
 constexpr int kFusedLDH = 64 + 8;
 
 template <int HM>
 __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int tid, const NetArgs &net,
-                                          __bf16 *sA, __bf16 *sR, __bf16 *sHp, __bf16 *sAm, const f4 (&hp)[4])
+                                          __bf16 *sA, __bf16 *sR, __bf16 *sHp, __bf16 *sAm)
 {
     constexpr int nin = 104, nout = 50, H = 64, KC = 32, KQ = 8, KC1 = 6, TP = 8, RT = 4, HT = 4;
-    constexpr int LDA = kFusedLDA, LDH = kFusedLDH, PADK = KC1 * KC - nin - H;
+    constexpr int LDA = kFusedLDA, LDH = kFusedLDH;
+    static_assert((nin + H) % KQ == 0 && nin + H > (KC1 - 1) * KC, "k-padding only in the last chunk");
     const int nx = f.nx, ny = f.ny;
     const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lq = lane >> 4;
     const int ht = wave, ucol = 16 * ht + 4 * lq;
@@ -199,14 +200,21 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
     const bf8 *B2 = pinned<bf8>(net.B2);
     const bf8 *B3 = pinned<bf8>(net.B3);
     const bf8 *B4 = pinned<bf8>(net.B4);
-    // the state (prefetched at the start of the tile) next to the network input
+    // the tile's state in this lane's layout (rows 16 q + li, units ucol..+3):
+    // one HBM read serves the MFMA operand (BF16, next to the network input)
+    // and the update
+    f4 hp[RT];
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        const int r = 16 * q + li;
+        hp[q] = valid(r) ? *reinterpret_cast<const f4 *>(f.h + patch(r) * H + ucol) : f4{0.f, 0.f, 0.f, 0.f};
+    }
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
         bf4 hb;
         hb[0] = (__bf16)hp[q].x; hb[1] = (__bf16)hp[q].y; hb[2] = (__bf16)hp[q].z; hb[3] = (__bf16)hp[q].w;
         *reinterpret_cast<bf4 *>(&sA[(16 * q + li) * LDA + nin + ucol]) = hb;
     }
-    for (int t = tid; t < 64 * PADK; t += kThreads) sA[(t / PADK) * LDA + nin + H + t % PADK] = (__bf16)0.f;
     __syncthreads();
 
     // ---- phase 1: the three gates of this wave's hidden tile, four row tiles
@@ -214,14 +222,16 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
 #pragma unroll
     for (int q = 0; q < RT; ++q) az[q] = ar[q] = ah[q] = f4{0.f, 0.f, 0.f, 0.f};
     // weight fragments chunk by chunk (L2-resident; other waves cover the latency)
-#pragma unroll
+#pragma unroll 2
     for (int kc = 0; kc < KC1; ++kc) {
         const bf8 wz = B1[((0 * HT + ht) * KC1 + kc) * 64 + lane];
         const bf8 wr = B1[((1 * HT + ht) * KC1 + kc) * 64 + lane];
         const bf8 wh = B1[((2 * HT + ht) * KC1 + kc) * 64 + lane];
 #pragma unroll
         for (int q = 0; q < RT; ++q) {
-            const bf8 a = *reinterpret_cast<const bf8 *>(&sA[(16 * q + li) * LDA + kc * KC + lq * KQ]);
+            // lanes whose 8 values lie beyond [x | h] (last chunk) supply zeros
+            const int k0 = kc * KC + lq * KQ;
+            const bf8 a = k0 < nin + H ? *reinterpret_cast<const bf8 *>(&sA[(16 * q + li) * LDA + k0]) : bf8{};
             az[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wz, a, az[q], 0, 0, 0);
             ar[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr, a, ar[q], 0, 0, 0);
             ah[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, a, ah[q], 0, 0, 0);
@@ -358,20 +368,6 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
         const int I = I0 - 1 + t % NN, J = J0 - 1 + t / NN;
         const bool in = t < NN * NN && !first && I >= 0 && I <= NX && J >= 0 && J <= NY;
         uq[i] = in ? reinterpret_cast<const float2 *>(f.uprev)[(size_t)J * (NX + 1) + I] : make_float2(0.f, 0.f);
-    }
-
-    // fused: the tile's GRU state, loaded early in the layout the network
-    // phase uses (wave w, lane (li, lq): rows 16 q + li, units 16 w + 4 lq)
-    f4 hp[4];
-    if constexpr (FUSED) {
-        const int li = tid & 15, col = 16 * (tid >> 6) + 4 * ((tid >> 4) & 3);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = 16 * q + li;
-            const int pi = tx * TP + r % TP, pj = ty * TP + r / TP;
-            hp[q] = (pi < nx && pj < ny) ? *reinterpret_cast<const f4 *>(f.h + ((size_t)pj * nx + pi) * 64 + col)
-                                         : f4{0.f, 0.f, 0.f, 0.f};
-        }
     }
 
     // 1. coarse-element records
@@ -643,7 +639,7 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
             // the network input rows stay in LDS; r*h, h' reuse them after phase
             // 1 and the MLP hidden layer reuses the node accumulators
             __bf16 *sA = reinterpret_cast<__bf16 *>(s_wx);
-            gru_fused<HM>(f, tx, ty, tid, *net, sA, sA, sA + 64 * kFusedLDH, reinterpret_cast<__bf16 *>(s_acc), hp);
+            gru_fused<HM>(f, tx, ty, tid, *net, sA, sA, sA + 64 * kFusedLDH, reinterpret_cast<__bf16 *>(s_acc));
             return;
         }
         constexpr int CPR = TP * nin * sizeof(XT) / 16;   // 16-byte pieces per tile row of patches
@@ -678,7 +674,7 @@ __global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const Batc
 }
 
 template <bool BATCHED, int HM>
-__global__ __launch_bounds__(kThreads, 3) void k_defect_net(FlowArgs single, const BatchTable *__restrict__ bt, NetArgs net)
+__global__ __launch_bounds__(kThreads, 4) void k_defect_net(FlowArgs single, const BatchTable *__restrict__ bt, NetArgs net)
 {
     if (!BATCHED) {
         defect_tile<2, __bf16, false, true, HM>(single, blockIdx.x, &net);
