@@ -433,7 +433,8 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
     // 2*ly + ((c >> 1) ^ 1) of the tile-local grid.
     static_assert(NE % 2 == 0, "colour classes of equal size");
     constexpr int CS = (NE / 2) * (NE / 2);
-    int ecol[EPT];
+    // per slot: colour << 16 | first node of the element (-1: no element)
+    int slot[EPT];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
 #pragma unroll
@@ -441,7 +442,7 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
         const int t = tid + k * kThreads;
         const int c = t / CS, rr = t - c * CS;
         const int le = 2 * (rr % (NE / 2)) + ((c & 1) ^ 1), me = 2 * (rr / (NE / 2)) + ((c >> 1) ^ 1);
-        ecol[k] = t < NE * NE ? c : -1;
+        slot[k] = t < NE * NE ? (c << 16) | (me * NN + le) : -1;
         const int eI = I0 - 1 + le, eJ = J0 - 1 + me;
         if (t < NE * NE && eI >= 0 && eI < NX && eJ >= 0 && eJ < NY) {
             const int ci = eI >> K, a = eI & (n - 1), cj = eJ >> K, b = eJ & (n - 1);
@@ -511,11 +512,8 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
     for (int colour = 0; colour < 4; ++colour) {
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
-            if (ecol[k] != colour) continue;
-            const int t = tid + k * kThreads;
-            const int rr = t - colour * CS;
-            const int le = 2 * (rr % (NE / 2)) + ((colour & 1) ^ 1), me = 2 * (rr / (NE / 2)) + ((colour >> 1) ^ 1);
-            const int n0 = me * NN + le;
+            if ((slot[k] >> 16) != colour) continue;
+            const int n0 = slot[k] & 0xffff;
             float2 *q0 = &s_acc[n0], *q1 = &s_acc[n0 + 1], *q2 = &s_acc[n0 + NN], *q3 = &s_acc[n0 + NN + 1];
             q0->x += R[k][0]; q0->y += R[k][1];
             q1->x += R[k][2]; q1->y += R[k][3];
