@@ -59,8 +59,11 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
     // The step's defect has already read the first-step flag (stream order).
     if (FROM_PATCHES && blk == 0 && tid == 0) *f.first_flag = 0;
 
-    // ---- stage: moment table, coarse corner velocities, per-patch outputs
-    for (int t = tid; t < 4 * (n + 1); t += kThreads) s_A[t] = tab.A[t];
+    // ---- stage: moment table, coarse corner velocities, per-patch outputs.
+    //      The tables are read through pinned pointers: in the batched tile
+    //      loop their loads would otherwise be hoisted and held in registers.
+    const double *tabA = pinned<double>(tab.A), *tabM = pinned<double>(tab.M);
+    for (int t = tid; t < 4 * (n + 1); t += kThreads) s_A[t] = tabA[t];
     const float2 *v2 = reinterpret_cast<const float2 *>(f.v);
     for (int t = tid; t < (TP + 1) * (TP + 1); t += kThreads) {
         int ci = pi0 + t % (TP + 1), cj = pj0 + t / (TP + 1);
@@ -179,8 +182,8 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
             double acc = d0 * S0 + d1 * S1 + d2 * S2;
 #pragma unroll
             for (int cc = 0; cc < 4; ++cc) {
-                const double w = d0 * tab.M[(0 * 4 + c) * 4 + cc] + d1 * tab.M[(1 * 4 + c) * 4 + cc] +
-                                 d2 * tab.M[(2 * 4 + c) * 4 + cc];
+                const double w = d0 * tabM[(0 * 4 + c) * 4 + cc] + d1 * tabM[(1 * 4 + c) * 4 + cc] +
+                                 d2 * tabM[(2 * 4 + c) * 4 + cc];
                 acc += w * vq[cc];
             }
             f.part[2 * ((size_t)c * nx * ny + e) + comp] = f.inv_dt64 * acc;
