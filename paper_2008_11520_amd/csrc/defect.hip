@@ -191,15 +191,16 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
     constexpr int nin = 104, nout = 50, H = 64, KC = 32, KQ = 8, KC1 = 6, TP = 8, RT = 4, HT = 4;
     constexpr int LDA = kFusedLDA, LDH = kFusedLDH;
     static_assert((nin + H) % KQ == 0 && nin + H > (KC1 - 1) * KC, "k-padding only in the last chunk");
+    static_assert(LDA >= nin + H + KQ, "room for the zeros after [x | h]");
     const int nx = f.nx, ny = f.ny;
     const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lq = lane >> 4;
     const int ht = wave, ucol = 16 * ht + 4 * lq;
     auto patch = [&](int r) { return (size_t)(ty * TP + r / TP) * nx + tx * TP + r % TP; };
     auto valid = [&](int r) { return tx * TP + r % TP < nx && ty * TP + r / TP < ny; };
-    const bf8 *B1 = pinned<bf8>(net.B1);
-    const bf8 *B2 = pinned<bf8>(net.B2);
-    const bf8 *B3 = pinned<bf8>(net.B3);
-    const bf8 *B4 = pinned<bf8>(net.B4);
+    const gptr<bf8> B1 = pinned<bf8>(net.B1);
+    const gptr<bf8> B2 = pinned<bf8>(net.B2);
+    const gptr<bf8> B3 = pinned<bf8>(net.B3);
+    const gptr<bf8> B4 = pinned<bf8>(net.B4);
     // the tile's state in this lane's layout (rows 16 q + li, units ucol..+3):
     // one HBM read serves the MFMA operand (BF16, next to the network input)
     // and the update
@@ -215,28 +216,33 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
         hb[0] = (__bf16)hp[q].x; hb[1] = (__bf16)hp[q].y; hb[2] = (__bf16)hp[q].z; hb[3] = (__bf16)hp[q].w;
         *reinterpret_cast<bf4 *>(&sA[(16 * q + li) * LDA + nin + ucol]) = hb;
     }
+    // zeros after [x | h]: the lanes of the last k-chunk that lie beyond it read these
+    if (tid < 64) *reinterpret_cast<uint4 *>(&sA[tid * LDA + nin + H]) = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
 
-    // ---- phase 1: the three gates of this wave's hidden tile, four row tiles
+    // ---- phase 1: the three gates of this wave's hidden tile, four row tiles.
+    //      Weight fragments are read chunk by chunk (L2-resident; other waves
+    //      cover the latency); the first chunk starts the accumulators.
     f4 az[RT], ar[RT], ah[RT];
-#pragma unroll
-    for (int q = 0; q < RT; ++q) az[q] = ar[q] = ah[q] = f4{0.f, 0.f, 0.f, 0.f};
-    // weight fragments chunk by chunk (L2-resident; other waves cover the latency)
-#pragma unroll 2
-    for (int kc = 0; kc < KC1; ++kc) {
+    auto chunk = [&](int kc, bool first, bool last) {
         const bf8 wz = B1[((0 * HT + ht) * KC1 + kc) * 64 + lane];
         const bf8 wr = B1[((1 * HT + ht) * KC1 + kc) * 64 + lane];
         const bf8 wh = B1[((2 * HT + ht) * KC1 + kc) * 64 + lane];
+        const int k0 = kc * KC + lq * KQ;
+        const int kk = last && k0 >= nin + H ? nin + H : k0;
 #pragma unroll
         for (int q = 0; q < RT; ++q) {
-            // lanes whose 8 values lie beyond [x | h] (last chunk) supply zeros
-            const int k0 = kc * KC + lq * KQ;
-            const bf8 a = k0 < nin + H ? *reinterpret_cast<const bf8 *>(&sA[(16 * q + li) * LDA + k0]) : bf8{};
-            az[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wz, a, az[q], 0, 0, 0);
-            ar[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr, a, ar[q], 0, 0, 0);
-            ah[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, a, ah[q], 0, 0, 0);
+            const bf8 a = *reinterpret_cast<const bf8 *>(&sA[(16 * q + li) * LDA + kk]);
+            const f4 z0 = {0.f, 0.f, 0.f, 0.f};
+            az[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wz, a, first ? z0 : az[q], 0, 0, 0);
+            ar[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr, a, first ? z0 : ar[q], 0, 0, 0);
+            ah[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, a, first ? z0 : ah[q], 0, 0, 0);
         }
-    }
+    };
+    chunk(0, true, false);
+#pragma unroll 2
+    for (int kc = 1; kc < KC1 - 1; ++kc) chunk(kc, false, false);
+    chunk(KC1 - 1, false, true);
     bf8 w2[2];
 #pragma unroll
     for (int kc = 0; kc < 2; ++kc) w2[kc] = B2[(ht * 2 + kc) * 64 + lane];
@@ -523,9 +529,13 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
         __syncthreads();
     }
 
-    // 5. Dirichlet mask on the tile's nodes (in place)
+    // 5. Dirichlet mask on the tile's nodes (in place); a tile away from the
+    //    masked sides has nothing to mask
     const unsigned dir = f.dirichlet;
     constexpr int NO = kTileFine + 1;
+    const bool masked = ((dir & 1u) && I0 == 0) || ((dir & 2u) && I0 + kTileFine >= NX) ||
+                        ((dir & 4u) && J0 == 0) || ((dir & 8u) && J0 + kTileFine >= NY);
+    if (masked || f.D)
     for (int t = tid; t < NO * NO; t += kThreads) {
         const int li = t % NO, lj = t / NO;
         const int I = I0 + li, J = J0 + lj;
@@ -607,30 +617,47 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
             reinterpret_cast<uint4 *>(dst)[c] = v;
         }
     } else {
-        // 6. network input rows of the tile's patches, assembled in LDS one patch
-        //    node per item, then written with full 16-byte stores (each row of TP
-        //    patches is contiguous in X):
+        // 6. network input rows of the tile's patches, assembled in LDS, then
+        //    written with full 16-byte stores (each row of TP patches is
+        //    contiguous in X):
         //    X[e] = [P v at the (n+1)^2 patch nodes (x,y interleaved, x fastest) ;
         //            D at the same nodes ; hx, hy, hx/hy, area]
-        for (int t = tid; t < TP * TP * (nf + 1); t += kThreads) {
-            const int pl = t / (nf + 1), l = t - pl * (nf + 1);
+        //    One item is one node row b of one patch (P v along the row is
+        //    linear in the node index) or, for b = n + 1, the patch features.
+        constexpr int PP = TP * TP, LDX = FUSED ? kFusedLDA : nin;
+        auto store2 = [](ST *o, float x, float y) {
+            if constexpr (std::is_same<ST, float>::value) {
+                *reinterpret_cast<float2 *>(o) = make_float2(x, y);
+            } else {
+                typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+                b2 v;
+                v[0] = (__bf16)x; v[1] = (__bf16)y;
+                *reinterpret_cast<b2 *>(o) = v;
+            }
+        };
+        for (int t = tid; t < PP * (n + 2); t += kThreads) {
+            const int b = t / PP, pl = t % PP;
             const int pa = pl % TP, pb = pl / TP;
-            const int pi = tx * TP + pa, pj = ty * TP + pb;
-            ST *o = FUSED ? s_x + pl * kFusedLDA : s_x + pl * nin;
-            if (pi >= nx || pj >= ny) continue;
-            if (l == nf) {
-                const float4 ft = reinterpret_cast<const float4 *>(f.feat)[(size_t)pj * nx + pi];
-                o[4 * nf] = (ST)ft.x; o[4 * nf + 1] = (ST)ft.y; o[4 * nf + 2] = (ST)ft.z; o[4 * nf + 3] = (ST)ft.w;
+            if (tx * TP + pa >= nx || ty * TP + pb >= ny) continue;
+            ST *o = s_x + pl * LDX;
+            if (b == n + 1) {
+                const float4 ft = reinterpret_cast<const float4 *>(f.feat)[(size_t)(ty * TP + pb) * nx + tx * TP + pa];
+                store2(o + 4 * nf, ft.x, ft.y);
+                store2(o + 4 * nf + 2, ft.z, ft.w);
                 continue;
             }
-            const int a = l % (n + 1), b = l / (n + 1);
             const CoarseRec &r = s_c[(pb + 1) * CE + (pa + 1)];
-            const float xi = a * inv_n, eta = b * inv_n;
-            const float pvx = (r.V0x + r.V1x * xi) + eta * (r.V2x + r.V3x * xi);
-            const float pvy = (r.V0y + r.V1y * xi) + eta * (r.V2y + r.V3y * xi);
-            const float2 d = s_acc[(pb * n + b + 1) * NN + pa * n + a + 1];
-            o[2 * l] = (ST)pvx; o[2 * l + 1] = (ST)pvy;
-            o[2 * nf + 2 * l] = (ST)d.x; o[2 * nf + 2 * l + 1] = (ST)d.y;
+            const float eta = b * inv_n;
+            const float ax = r.V0x + r.V2x * eta, bx = (r.V1x + r.V3x * eta) * inv_n;
+            const float ay = r.V0y + r.V2y * eta, by = (r.V1y + r.V3y * eta) * inv_n;
+            const float2 *d = &s_acc[(pb * n + b + 1) * NN + pa * n + 1];
+#pragma unroll
+            for (int a = 0; a <= n; ++a) {
+                const int l = b * (n + 1) + a;
+                store2(o + 2 * l, ax + bx * a, ay + by * a);
+                const float2 dd = d[a];
+                store2(o + 2 * nf + 2 * l, dd.x, dd.y);
+            }
         }
         __syncthreads();
         if constexpr (FUSED) {

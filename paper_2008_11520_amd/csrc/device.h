@@ -27,14 +27,21 @@ __device__ inline int tile_thread()
     return t;
 }
 
+// Pointer into global memory (address space 1): loads through it are global
+// loads with a scalar base and a 32-bit lane offset, not flat loads, which
+// would also count against the LDS wait counter.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+
 // A pointer the optimiser cannot move loads through from before this point:
 // keeps weight loads where they are written instead of hoisted to the top of
-// a kernel, where they would hold registers through unrelated phases.
+// a kernel, where they would hold registers through unrelated phases.  The
+// pointee must be device (global) memory.
 template <typename T>
-__device__ inline const T *pinned(const void *p)
+__device__ inline gptr<T> pinned(const void *p)
 {
     asm volatile("" : "+s"(p));
-    return reinterpret_cast<const T *>(p);
+    return (gptr<T>)(p);
 }
 
 }  // namespace dnnmg

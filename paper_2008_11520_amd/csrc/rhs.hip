@@ -62,7 +62,7 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
     // ---- stage: moment table, coarse corner velocities, per-patch outputs.
     //      The tables are read through pinned pointers: in the batched tile
     //      loop their loads would otherwise be hoisted and held in registers.
-    const double *tabA = pinned<double>(tab.A), *tabM = pinned<double>(tab.M);
+    const gptr<double> tabA = pinned<double>(tab.A), tabM = pinned<double>(tab.M);
     for (int t = tid; t < 4 * (n + 1); t += kThreads) s_A[t] = tabA[t];
     const float2 *v2 = reinterpret_cast<const float2 *>(f.v);
     for (int t = tid; t < (TP + 1) * (TP + 1); t += kThreads) {
