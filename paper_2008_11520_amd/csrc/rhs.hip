@@ -70,32 +70,64 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
         s_v[t] = (ci <= nx && cj <= ny) ? v2[(size_t)cj * (nx + 1) + ci] : make_float2(0.f, 0.f);
     }
     if (FROM_PATCHES) {
-        // per-patch outputs of the tile and its ring of neighbours, 8 bytes at a
-        // time; all of a thread's loads are issued before any LDS store
-        constexpr int NS = HP * HP * nf, IT = (NS + kThreads - 1) / kThreads;
+        // per-patch outputs, 8 bytes at a time, into the staged (TP+2)^2-patch
+        // layout: the tile's own patches whole (each tile row of TP patches is
+        // one contiguous run of TP nf nodes), and of the ring of neighbours only
+        // the nodes on the edges the tile touches (right edges of the left
+        // column, left edges of the right column, top edges of the row below,
+        // bottom edges of the row above, one node of each diagonal patch); the
+        // rest of the ring is never read.  All of a thread's loads are issued
+        // before any LDS store.
+        constexpr int RW = TP * nf, NS = TP * RW, IT = (NS + kThreads - 1) / kThreads;
+        constexpr int NR = 4 * TP * (n + 1) + 4;
+        static_assert(NR <= kThreads, "one ring node per thread");
         float2 *sd2 = reinterpret_cast<float2 *>(s_d);
         const float2 *dp2 = reinterpret_cast<const float2 *>(f.dpatch);
+        const int npr = min(TP, nx - pi0), nrows = min(TP, ny - pj0);
         float2 tmp[IT];
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
             const int t = tid + i * kThreads;
-            const int hp = t / nf, o = t - hp * nf;
-            const int qi = pi0 - 1 + hp % HP, qj = pj0 - 1 + hp / HP;
-            tmp[i] = (t < NS && qi >= 0 && qi < nx && qj >= 0 && qj < ny) ? dp2[((size_t)qj * nx + qi) * nf + o]
-                                                                          : make_float2(0.f, 0.f);
+            const int r = t / RW, k = t - r * RW;
+            tmp[i] = (t < NS && r < nrows && k < npr * nf) ? dp2[((size_t)(pj0 + r) * nx + pi0) * nf + k]
+                                                          : make_float2(0.f, 0.f);
+        }
+        float2 ring = make_float2(0.f, 0.f);
+        int rdst = -1;
+        if (tid < NR) {
+            const int side = tid / (TP * (n + 1)), sidx = tid - side * (TP * (n + 1));
+            const int r = sidx / (n + 1), m = sidx - r * (n + 1);
+            int qi, qj, a, b;
+            switch (side) {
+            case 0: qi = -1; qj = r; a = n; b = m; break;         // left column: right edges
+            case 1: qi = TP; qj = r; a = 0; b = m; break;         // right column: left edges
+            case 2: qi = r; qj = -1; a = m; b = n; break;         // row below: top edges
+            case 3: qi = r; qj = TP; a = m; b = 0; break;         // row above: bottom edges
+            default:                                              // diagonal patches: one corner each
+                qi = (sidx & 1) ? TP : -1; qj = (sidx & 2) ? TP : -1;
+                a = (sidx & 1) ? 0 : n; b = (sidx & 2) ? 0 : n;
+            }
+            const int gi = pi0 + qi, gj = pj0 + qj;
+            if (gi >= 0 && gi < nx && gj >= 0 && gj < ny) {
+                ring = dp2[((size_t)gj * nx + gi) * nf + b * (n + 1) + a];
+                rdst = ((qj + 1) * HP + qi + 1) * nf + b * (n + 1) + a;
+            }
         }
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
             const int t = tid + i * kThreads;
-            if (t < NS) sd2[t] = tmp[i];
+            const int r = t / RW, k = t - r * RW;
+            if (t < NS) sd2[((r + 1) * HP + 1) * nf + k] = tmp[i];
         }
+        if (rdst >= 0) sd2[rdst] = ring;
     }
     __syncthreads();
 
     // ---- node pass: mean over the containing patches (row-major order, as
     //      the mean is defined), Dirichlet mask, corrected velocity.
-    for (int t = tid; t < NO * NO; t += kThreads) {
-        const int li = t % NO, lj = t / NO;
+    const float2 *sd2 = reinterpret_cast<const float2 *>(s_d);
+    // Any tile node (li, lj); the patch offsets are those of the staged ring.
+    auto node = [&](int li, int lj) {
         const int I = I0 + li, J = J0 + lj;
         float2 d = make_float2(0.f, 0.f);
         if (I <= NX && J <= NY) {
@@ -106,7 +138,6 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                 const int pI = min(I >> K, nx - 1), pJ = min(J >> K, ny - 1);
                 const int a = I - pI * n, b = J - pJ * n;
                 const bool lft = a == 0 && pI > 0, low = b == 0 && pJ > 0;
-                const float2 *sd2 = reinterpret_cast<const float2 *>(s_d);
                 const int hb = (pJ - pj0 + 1) * HP + (pI - pi0 + 1);   // own patch in the staged ring
                 float2 acc = make_float2(0.f, 0.f);
                 if (lft && low) { const float2 q = sd2[(hb - HP - 1) * nf + n * (n + 1) + n]; acc.x += q.x; acc.y += q.y; }
@@ -134,7 +165,55 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                 d = reinterpret_cast<const float2 *>(f.dbar_in)[(size_t)J * (NX + 1) + I];
             }
         }
-        s_dbar[t] = d;
+        s_dbar[lj * NO + li] = d;
+    };
+    if (!FROM_PATCHES) {
+        for (int t = tid; t < NO * NO; t += kThreads) node(t % NO, t / NO);
+    } else {
+        // the nodes (a, b), a, b < n, of the tile's own patches, one node row of
+        // one patch per item: the same sums as node() with the patch known
+        // (a node with I < NX, J < NY is masked only on the sides I = 0, J = 0)
+        const unsigned dir = f.dirichlet;
+        for (int it = tid; it < TP * TP * n; it += kThreads) {
+            const int pl = it % (TP * TP), b = it / (TP * TP);
+            const int pa = pl % TP, pb = pl / TP, pi = pi0 + pa, pj = pj0 + pb;
+            if (pi >= nx || pj >= ny) continue;
+            const int hb = (pb + 1) * HP + pa + 1;
+            const bool low = b == 0 && pj > 0;
+            const int J = pj * n + b;
+            const float eta = b * (1.0f / n);
+            const int c = pb * (TP + 1) + pa;
+            const float2 v00 = s_v[c], v10 = s_v[c + 1], v01 = s_v[c + TP + 1], v11 = s_v[c + TP + 2];
+#pragma unroll
+            for (int a = 0; a < n; ++a) {
+                const bool lft = a == 0 && pi > 0;
+                float2 acc = make_float2(0.f, 0.f);
+                if (lft && low) { const float2 q = sd2[(hb - HP - 1) * nf + n * (n + 1) + n]; acc.x += q.x; acc.y += q.y; }
+                if (low) { const float2 q = sd2[(hb - HP) * nf + n * (n + 1) + a]; acc.x += q.x; acc.y += q.y; }
+                if (lft) { const float2 q = sd2[(hb - 1) * nf + b * (n + 1) + n]; acc.x += q.x; acc.y += q.y; }
+                { const float2 q = sd2[hb * nf + b * (n + 1) + a]; acc.x += q.x; acc.y += q.y; }
+                const float inv = (lft && low) ? 0.25f : ((lft || low) ? 0.5f : 1.0f);
+                float2 d = make_float2(acc.x * inv, acc.y * inv);
+                const int I = pi * n + a;
+                if (((dir & 1u) && I == 0) || ((dir & 4u) && J == 0)) d = make_float2(0.f, 0.f);
+                const float xi = a * (1.0f / n);
+                const float n00 = (1.f - xi) * (1.f - eta), n10 = xi * (1.f - eta), n01 = (1.f - xi) * eta,
+                            n11 = xi * eta;
+                const float pvx = n00 * v00.x + n10 * v10.x + n01 * v01.x + n11 * v11.x;
+                const float pvy = n00 * v00.y + n10 * v10.y + n01 * v01.y + n11 * v11.y;
+                const size_t fi = (size_t)J * (NX + 1) + I;
+                reinterpret_cast<float2 *>(f.uprev)[fi] = make_float2(pvx + d.x, pvy + d.y);
+                if (f.dbar_out) reinterpret_cast<float2 *>(f.dbar_out)[fi] = d;
+                s_dbar[(pb * n + b) * NO + pa * n + a] = d;
+            }
+        }
+        // the rest: the last node column and row of the tile's patches (the
+        // tile's own last column and row, or the mesh end inside the tile)
+        const int le = min(TP, nx - pi0) * n, me = min(TP, ny - pj0) * n;
+        for (int t = tid; t < le + me + 1; t += kThreads) {
+            if (t <= me) node(le, t);
+            else node(t - me - 1, me);
+        }
     }
     __syncthreads();
 
