@@ -79,7 +79,7 @@ def rhs_bytes_per_patch(K):
 def source_hash(stage):
     import hashlib
     h = hashlib.sha256()
-    for name in STAGE_SOURCES[stage] + ["internal.h", "device.h", "fp8.h"]:
+    for name in STAGE_SOURCES[stage] + ["internal.h", "device.h", "element.h", "fp8.h"]:
         with open(os.path.join(ROOT, "paper_2008_11520_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -18,6 +18,7 @@
 #include <type_traits>
 
 #include "device.h"
+#include "element.h"
 #include "fp8.h"
 #include "internal.h"
 
@@ -134,44 +135,6 @@ int blocks_for(int kind, int nx, int ny, int K)
     case kKindGather: return ((nx + 1) * (ny + 1) + kThreads - 1) / kThreads;
     }
     return 0;
-}
-
-// Per coarse element, the coefficients the defect needs (LDS record):
-// prolongated velocity and pressure as bilinear polynomials in the coarse
-// reference coordinates, v = V0 + V1 xi + V2 eta + V3 xi eta, and the map
-// vectors of F(xi, eta) = c00 + ex xi + ey eta + exy xi eta, so that
-// x_xi = ex + exy eta, x_eta = ey + exy xi.  Derivatives are taken in the
-// coarse reference coordinates; the fine element's own reference derivatives
-// are these times 1/n, a factor the element sums apply at the end.
-struct CoarseRec {
-    float V0x, V1x, V2x, V3x, V0y, V1y, V2y, V3y;
-    float P0, P1, P2, P3;
-    float exx, exy, eyx, eyy, exyx, exyy;
-};
-
-// Test-function sums of one component of the element residual: with the
-// Gauss abscissae g0, g1 and 1 - g0 = g1,
-//   R_a += 1/4 sum_q [ N_a(q) m(q) + dN_a/ds(q) Qs(q) + dN_a/dt(q) Qt(q) ]
-// for nodes a = 00, 10, 01, 11 (stride 2 in R: components interleaved).
-// m and Q come from coarse-reference derivatives: m carries n^2 and Q carries
-// n relative to the fine element's, so those factors and the weight 1/4 go
-// into the outer constants.
-template <int n>
-__device__ inline void element_sums(const float m[2][2], const float Qs[2][2], const float Qt[2][2], float *R)
-{
-    constexpr float g0 = 0.21132486540518711775f, g1 = 0.78867513459481288225f;
-    constexpr float hm0 = 0.25f * g0 / (n * n), hm1 = 0.25f * g1 / (n * n);
-    constexpr float h0 = 0.25f * g0 / n, h1 = 0.25f * g1 / n;
-    const float mb0 = g1 * m[0][0] + g0 * m[0][1], mb1 = g1 * m[1][0] + g0 * m[1][1];   // weight 1 - t
-    const float mt0 = g0 * m[0][0] + g1 * m[0][1], mt1 = g0 * m[1][0] + g1 * m[1][1];   // weight t
-    const float qs0 = Qs[0][0] + Qs[1][0], qs1 = Qs[0][1] + Qs[1][1];                   // sum over s
-    const float qt0 = Qt[0][0] + Qt[0][1], qt1 = Qt[1][0] + Qt[1][1];                   // sum over t
-    const float Sx0 = h1 * qs0 + h0 * qs1, Sx1 = h0 * qs0 + h1 * qs1;
-    const float Sy0 = h1 * qt0 + h0 * qt1, Sy1 = h0 * qt0 + h1 * qt1;
-    R[0] = hm1 * mb0 + hm0 * mb1 - Sx0 - Sy0;
-    R[2] = hm0 * mb0 + hm1 * mb1 + Sx0 - Sy1;
-    R[4] = hm1 * mt0 + hm0 * mt1 - Sx1 + Sy0;
-    R[6] = hm0 * mt0 + hm1 * mt1 + Sx1 + Sy1;
 }
 
 // ------------------------------------------------- defect + network fusion
@@ -334,10 +297,8 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
     constexpr int n = 1 << K;
     constexpr float inv_n = 1.0f / n;
     constexpr int TP = kTileFine / n;           // patches per tile and direction
-    constexpr int NE = kTileFine + 2;           // elements incl. one halo ring
     constexpr int NN = kTileFine + 3;           // nodes of those elements
     constexpr int CE = TP + 2;                  // coarse elements incl. halo
-    constexpr int EPT = (NE * NE + kThreads - 1) / kThreads;   // elements per thread
 
     constexpr int nf = (n + 1) * (n + 1), nin = 4 * nf + 4;
     // XT = uint8_t: FP8 network input, assembled in FP32 and quantised per patch
@@ -424,107 +385,86 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
     }
     __syncthreads();
 
-    // 3. element residuals on the tile + halo ring, kept in registers.  With
-    //    Cof = det J^{-T} (so det grad = Cof grad_ref) and G = Cof^T Cof, at
-    //    each Gauss point:
-    //      mass - convection:  m_c = det (u_prev - v)_c / dt - v . (Cof grad_ref v_c)
-    //      pressure - viscous: Q_c = p Cof^T e_c - (nu / det) G grad_ref v_c
-    //    R_a,c = sum_q w_q [ N_a m_c + grad_ref N_a . Q_c ]   (w_q = 1/4),
-    //    with J and grad_ref in the coarse reference coordinates (element_sums
-    //    applies the 1/n^2 and 1/n that turn them into the fine element's).
-    constexpr float g0 = 0.21132486540518711775f, g1 = 0.78867513459481288225f;
-    float R[EPT][8];
-    // Elements are numbered colour by colour: colour c = (parity of eI) + 2
-    // (parity of eJ) holds the (NE/2)^2 elements 2*lx + ((c & 1) ^ 1),
-    // 2*ly + ((c >> 1) ^ 1) of the tile-local grid.
-    static_assert(NE % 2 == 0, "colour classes of equal size");
-    constexpr int CS = (NE / 2) * (NE / 2);
-    // per slot: colour << 16 | first node of the element (-1: no element)
-    int slot[EPT];
+    // 3. element residuals, kept in registers (the formulas are in
+    //    element.h).  The tile's own elements are taken as vertical strips of
+    //    SH elements inside one coarse element; wave w holds the strips of
+    //    colour w (column parity w & 1, strip-row parity w >> 1), so that the
+    //    strips of one wave share no node.  The ring of halo elements around
+    //    the tile, one per thread, is computed element by element.
+    constexpr int SH = n < 4 ? n : 4;                      // strip height
+    constexpr int NSR = kTileFine / SH;                    // strip rows per tile
+    constexpr int SPL = kTileFine * NSR / kThreads;        // strips per thread
+    static_assert(kTileFine == 32 && kThreads == 256 && NSR == 8 * SPL, "strip mapping: 16 columns x 4 strip rows per wave and strip");
+    const int wave = tid >> 6, lane = tid & 63;
+    float S[SPL][SH + 1][4];
+    int sn0[SPL];                                          // lower-left node of the strip (-1: outside the mesh)
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) {
+    for (int s = 0; s < SPL; ++s) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) R[k][q] = 0.f;
-        const int t = tid + k * kThreads;
-        const int c = t / CS, rr = t - c * CS;
-        const int le = 2 * (rr % (NE / 2)) + ((c & 1) ^ 1), me = 2 * (rr / (NE / 2)) + ((c >> 1) ^ 1);
-        slot[k] = t < NE * NE ? (c << 16) | (me * NN + le) : -1;
-        const int eI = I0 - 1 + le, eJ = J0 - 1 + me;
-        if (t < NE * NE && eI >= 0 && eI < NX && eJ >= 0 && eJ < NY) {
-            const int ci = eI >> K, a = eI & (n - 1), cj = eJ >> K, b = eJ & (n - 1);
-            const CoarseRec &r = s_c[(cj - cj0) * CE + (ci - ci0)];
-            const float xi[2] = {(a + g0) * inv_n, (a + g1) * inv_n};
-            const float eta[2] = {(b + g0) * inv_n, (b + g1) * inv_n};
-            float xsx[2], xsy[2], xtx[2], xty[2];          // x_s(eta_j), x_t(xi_i)
-            float vsx[2], vsy[2], vtx[2], vty[2];          // v_xi(eta_j), v_eta(xi_i) per component
-            float ax_[2], ay_[2], ap[2], bp[2];                // v = ax_ + vtx eta along xi_i
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                xsx[j] = r.exx + r.exyx * eta[j]; xsy[j] = r.exy + r.exyy * eta[j];
-                vsx[j] = r.V1x + r.V3x * eta[j]; vsy[j] = r.V1y + r.V3y * eta[j];
-            }
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                xtx[i] = r.eyx + r.exyx * xi[i]; xty[i] = r.eyy + r.exyy * xi[i];
-                vtx[i] = r.V2x + r.V3x * xi[i]; vty[i] = r.V2y + r.V3y * xi[i];
-                ax_[i] = r.V0x + r.V1x * xi[i];
-                ay_[i] = r.V0y + r.V1y * xi[i];
-                ap[i] = r.P0 + r.P1 * xi[i]; bp[i] = r.P2 + r.P3 * xi[i];
-            }
-            // (u_prev - v)/dt at the Gauss points from the element's nodal values
-            const int n0 = me * NN + le;
-            const float2 w0 = s_w[n0], w1 = s_w[n0 + 1], w2 = s_w[n0 + NN], w3 = s_w[n0 + NN + 1];
-            float wx[2][2], wy[2][2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const float sg = i ? g1 : g0;
-                const float bxv = w0.x + (w1.x - w0.x) * sg, txv = w2.x + (w3.x - w2.x) * sg;
-                const float byv = w0.y + (w1.y - w0.y) * sg, tyv = w2.y + (w3.y - w2.y) * sg;
-                wx[i][0] = bxv + (txv - bxv) * g0; wx[i][1] = bxv + (txv - bxv) * g1;
-                wy[i][0] = byv + (tyv - byv) * g0; wy[i][1] = byv + (tyv - byv) * g1;
-            }
-            const float g11[2] = {xtx[0] * xtx[0] + xty[0] * xty[0], xtx[1] * xtx[1] + xty[1] * xty[1]};
-            const float g22[2] = {xsx[0] * xsx[0] + xsy[0] * xsy[0], xsx[1] * xsx[1] + xsy[1] * xsy[1]};
-            float mx[2][2], my[2][2], Qxs[2][2], Qxt[2][2], Qys[2][2], Qyt[2][2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const float xs = xsx[j], ys = xsy[j], xt = xtx[i], yt = xty[i];
-                    const float det = xs * yt - xt * ys;
-                    const float vxq = ax_[i] + vtx[i] * eta[j], vyq = ay_[i] + vty[i] * eta[j];
-                    const float pq = ap[i] + bp[i] * eta[j];
-                    // det grad v_c = Cof grad_ref v_c
-                    const float dxx = yt * vsx[j] - ys * vtx[i], dxy = -xt * vsx[j] + xs * vtx[i];
-                    const float dyx = yt * vsy[j] - ys * vty[i], dyy = -xt * vsy[j] + xs * vty[i];
-                    mx[i][j] = det * wx[i][j] - (vxq * dxx + vyq * dxy);
-                    my[i][j] = det * wy[i][j] - (vxq * dyx + vyq * dyy);
-                    const float g12 = -(xs * xt + ys * yt);
-                    const float inv = nu * __builtin_amdgcn_rcpf(det);
-                    Qxs[i][j] = pq * yt - inv * (g11[i] * vsx[j] + g12 * vtx[i]);
-                    Qxt[i][j] = -pq * ys - inv * (g12 * vsx[j] + g22[j] * vtx[i]);
-                    Qys[i][j] = -pq * xt - inv * (g11[i] * vsy[j] + g12 * vty[i]);
-                    Qyt[i][j] = pq * xs - inv * (g12 * vsy[j] + g22[j] * vty[i]);
-                }
-            element_sums<n>(mx, Qxs, Qxt, R[k]);
-            element_sums<n>(my, Qys, Qyt, R[k] + 1);
+        for (int k = 0; k <= SH; ++k) S[s][k][0] = S[s][k][1] = S[s][k][2] = S[s][k][3] = 0.f;
+        const int ec = 2 * (lane & 15) + (wave & 1);
+        const int sr = 2 * ((lane >> 4) + 4 * s) + (wave >> 1);
+        const int eI = I0 + ec, eJ = J0 + sr * SH;
+        sn0[s] = -1;
+        if (eI < NX && eJ < NY) {
+            const int n0 = (sr * SH + 1) * NN + ec + 1;
+            sn0[s] = n0;
+            const CoarseRec &r = s_c[((eJ >> K) - cj0) * CE + ((eI >> K) - ci0)];
+            strip_residual<K, SH, HwRcp>(r, eI & (n - 1), eJ & (n - 1), nu, s_w + n0, NN, S[s]);
+        }
+    }
+    // halo: left and right columns (with the corners), then the rows below
+    // and above; each gets the colour of the one round in which it shares no
+    // node with that round's strips or with the other halo elements of it
+    constexpr int NH = 4 * (kTileFine + 1);
+    float Rh[8];
+    int hn0 = -1, hcol = -1;
+    if (tid < NH) {
+        int le, me;                                        // tile-local element (-1 .. kTileFine)
+        if (tid < 2 * (kTileFine + 2)) {
+            const int side = tid / (kTileFine + 2);
+            le = side ? kTileFine : -1;
+            me = tid - side * (kTileFine + 2) - 1;
+            hcol = side ? ((me & 1) ? 2 : 0) : ((me & 1) ? 3 : 1);
+        } else {
+            const int u = tid - 2 * (kTileFine + 2), side = u / kTileFine;
+            le = u - side * kTileFine;
+            me = side ? kTileFine : -1;
+            hcol = side ? ((le & 1) ? 1 : 0) : ((le & 1) ? 3 : 2);
+        }
+        const int eI = I0 + le, eJ = J0 + me;
+        if (eI >= 0 && eI < NX && eJ >= 0 && eJ < NY) {
+            const int n0 = (me + 1) * NN + le + 1;
+            hn0 = n0;
+            const CoarseRec &r = s_c[((eJ >> K) - cj0) * CE + ((eI >> K) - ci0)];
+            element_residual<K, HwRcp>(r, eI & (n - 1), eJ & (n - 1), nu, s_w[n0], s_w[n0 + 1], s_w[n0 + NN],
+                                       s_w[n0 + NN + 1], Rh);
         }
     }
 
-    // 4. assembly in four colour rounds: elements of one colour share no node,
-    //    so each round adds without conflicts and every node receives its four
-    //    element contributions in a fixed order.
+    // 4. assembly in four colour rounds: round c adds the strips of wave c and
+    //    the halo elements of colour c, which share no node, so every node
+    //    receives its contributions without conflicts and in a fixed order.
 #pragma unroll
     for (int colour = 0; colour < 4; ++colour) {
+        if (wave == colour) {
 #pragma unroll
-        for (int k = 0; k < EPT; ++k) {
-            if ((slot[k] >> 16) != colour) continue;
-            const int n0 = slot[k] & 0xffff;
-            float2 *q0 = &s_acc[n0], *q1 = &s_acc[n0 + 1], *q2 = &s_acc[n0 + NN], *q3 = &s_acc[n0 + NN + 1];
-            q0->x += R[k][0]; q0->y += R[k][1];
-            q1->x += R[k][2]; q1->y += R[k][3];
-            q2->x += R[k][4]; q2->y += R[k][5];
-            q3->x += R[k][6]; q3->y += R[k][7];
+            for (int s = 0; s < SPL; ++s) {
+                if (sn0[s] < 0) continue;
+#pragma unroll
+                for (int k = 0; k <= SH; ++k) {
+                    float2 *q = &s_acc[sn0[s] + k * NN];
+                    q[0].x += S[s][k][0]; q[0].y += S[s][k][1];
+                    q[1].x += S[s][k][2]; q[1].y += S[s][k][3];
+                }
+            }
+        }
+        if (hcol == colour && hn0 >= 0) {
+            float2 *q0 = &s_acc[hn0], *q1 = &s_acc[hn0 + 1], *q2 = &s_acc[hn0 + NN], *q3 = &s_acc[hn0 + NN + 1];
+            q0->x += Rh[0]; q0->y += Rh[1];
+            q1->x += Rh[2]; q1->y += Rh[3];
+            q2->x += Rh[4]; q2->y += Rh[5];
+            q3->x += Rh[6]; q3->y += Rh[7];
         }
         __syncthreads();
     }
@@ -682,7 +622,7 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
 // Single flow: one tile per block.  Batched: the blocks stride over the
 // table's tiles of all flows, so the grid need not match the batch.
 template <int K, typename XT, bool BATCHED>
-__global__ __launch_bounds__(kThreads) void k_defect(FlowArgs single, const BatchTable *__restrict__ bt)
+__global__ __launch_bounds__(kThreads, 4) void k_defect(FlowArgs single, const BatchTable *__restrict__ bt)
 {
     if (!BATCHED) {
         defect_tile<K, XT, false>(single, blockIdx.x);

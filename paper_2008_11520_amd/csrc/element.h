@@ -1,0 +1,238 @@
+// Fine-element residuals of the momentum defect on a coarse Q1 element
+// (implicit-Euler Navier-Stokes, Q1/Q1, 2 x 2 Gauss rule): one element at a
+// time, or a vertical strip of elements that share their abscissae.  Host and
+// device code; the reciprocal is a parameter (the device passes the hardware
+// one).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dnnmg {
+
+// Per coarse element, the coefficients the defect needs (LDS record):
+// prolongated velocity and pressure as bilinear polynomials in the coarse
+// reference coordinates, v = V0 + V1 xi + V2 eta + V3 xi eta, and the map
+// vectors of F(xi, eta) = c00 + ex xi + ey eta + exy xi eta, so that
+// x_xi = ex + exy eta, x_eta = ey + exy xi.  Derivatives are taken in the
+// coarse reference coordinates; the fine element's own reference derivatives
+// are these times 1/n, a factor the element sums apply at the end.
+struct CoarseRec {
+    float V0x, V1x, V2x, V3x, V0y, V1y, V2y, V3y;
+    float P0, P1, P2, P3;
+    float exx, exy, eyx, eyy, exyx, exyy;
+};
+
+// Device operations of the element code: the hardware reciprocal, and a
+// scheduling fence that keeps the compiler from interleaving the two
+// abscissa passes of a strip (which would hold both passes' coefficients in
+// registers at once).
+struct HwRcp {
+    __device__ static float f(float x) { return __builtin_amdgcn_rcpf(x); }
+    __device__ static void fence() { __builtin_amdgcn_sched_barrier(0); }
+};
+
+constexpr float kGauss0 = 0.21132486540518711775f, kGauss1 = 0.78867513459481288225f;
+
+// At each Gauss point, with Cof = det J^{-T} (so det grad = Cof grad_ref) and
+// G = Cof^T Cof:
+//   mass - convection:  m_c = det (u_prev - v)_c / dt - v . (Cof grad_ref v_c)
+//   pressure - viscous: Q_c = p Cof^T e_c - (nu / det) G grad_ref v_c
+// and R_a,c = sum_q w_q [ N_a m_c + grad_ref N_a . Q_c ] (w_q = 1/4), with J
+// and grad_ref in the coarse reference coordinates.
+
+// Test-function sums of one component of the element residual: with the
+// Gauss abscissae g0, g1 and 1 - g0 = g1,
+//   R_a += 1/4 sum_q [ N_a(q) m(q) + dN_a/ds(q) Qs(q) + dN_a/dt(q) Qt(q) ]
+// for nodes a = 00, 10, 01, 11 (stride 2 in R: components interleaved).
+// m and Q come from coarse-reference derivatives: m carries n^2 and Q carries
+// n relative to the fine element's, so those factors and the weight 1/4 go
+// into the outer constants.
+template <int n>
+__host__ __device__ inline void element_sums(const float m[2][2], const float Qs[2][2], const float Qt[2][2], float *R)
+{
+    constexpr float g0 = kGauss0, g1 = kGauss1;
+    constexpr float hm0 = 0.25f * g0 / (n * n), hm1 = 0.25f * g1 / (n * n);
+    constexpr float h0 = 0.25f * g0 / n, h1 = 0.25f * g1 / n;
+    const float mb0 = g1 * m[0][0] + g0 * m[0][1], mb1 = g1 * m[1][0] + g0 * m[1][1];   // weight 1 - t
+    const float mt0 = g0 * m[0][0] + g1 * m[0][1], mt1 = g0 * m[1][0] + g1 * m[1][1];   // weight t
+    const float qs0 = Qs[0][0] + Qs[1][0], qs1 = Qs[0][1] + Qs[1][1];                   // sum over s
+    const float qt0 = Qt[0][0] + Qt[0][1], qt1 = Qt[1][0] + Qt[1][1];                   // sum over t
+    const float Sx0 = h1 * qs0 + h0 * qs1, Sx1 = h0 * qs0 + h1 * qs1;
+    const float Sy0 = h1 * qt0 + h0 * qt1, Sy1 = h0 * qt0 + h1 * qt1;
+    R[0] = hm1 * mb0 + hm0 * mb1 - Sx0 - Sy0;
+    R[2] = hm0 * mb0 + hm1 * mb1 + Sx0 - Sy1;
+    R[4] = hm1 * mt0 + hm0 * mt1 - Sx1 + Sy0;
+    R[6] = hm0 * mt0 + hm1 * mt1 + Sx1 + Sy1;
+}
+
+// One fine element: column a, row b (0 .. n-1) of coarse element r; w0..w3
+// the nodal (u_prev - P v)/dt at its corners 00, 10, 01, 11.  R[2 a + c] is
+// the residual of component c at corner a.
+template <int K, typename Rcp>
+__host__ __device__ inline void element_residual(const CoarseRec &r, int a, int b, float nu, float2 w0, float2 w1,
+                                                 float2 w2, float2 w3, float (&R)[8])
+{
+    constexpr int n = 1 << K;
+    constexpr float inv_n = 1.0f / n, g0 = kGauss0, g1 = kGauss1;
+    const float xi[2] = {(a + g0) * inv_n, (a + g1) * inv_n};
+    const float eta[2] = {(b + g0) * inv_n, (b + g1) * inv_n};
+    float xsx[2], xsy[2], xtx[2], xty[2];          // x_s(eta_j), x_t(xi_i)
+    float vsx[2], vsy[2], vtx[2], vty[2];          // v_xi(eta_j), v_eta(xi_i) per component
+    float ax_[2], ay_[2], ap[2], bp[2];            // v = ax_ + vtx eta along xi_i
+    for (int j = 0; j < 2; ++j) {
+        xsx[j] = r.exx + r.exyx * eta[j]; xsy[j] = r.exy + r.exyy * eta[j];
+        vsx[j] = r.V1x + r.V3x * eta[j]; vsy[j] = r.V1y + r.V3y * eta[j];
+    }
+    for (int i = 0; i < 2; ++i) {
+        xtx[i] = r.eyx + r.exyx * xi[i]; xty[i] = r.eyy + r.exyy * xi[i];
+        vtx[i] = r.V2x + r.V3x * xi[i]; vty[i] = r.V2y + r.V3y * xi[i];
+        ax_[i] = r.V0x + r.V1x * xi[i];
+        ay_[i] = r.V0y + r.V1y * xi[i];
+        ap[i] = r.P0 + r.P1 * xi[i]; bp[i] = r.P2 + r.P3 * xi[i];
+    }
+    // (u_prev - v)/dt at the Gauss points from the element's nodal values
+    float wx[2][2], wy[2][2];
+    for (int i = 0; i < 2; ++i) {
+        const float sg = i ? g1 : g0;
+        const float bxv = w0.x + (w1.x - w0.x) * sg, txv = w2.x + (w3.x - w2.x) * sg;
+        const float byv = w0.y + (w1.y - w0.y) * sg, tyv = w2.y + (w3.y - w2.y) * sg;
+        wx[i][0] = bxv + (txv - bxv) * g0; wx[i][1] = bxv + (txv - bxv) * g1;
+        wy[i][0] = byv + (tyv - byv) * g0; wy[i][1] = byv + (tyv - byv) * g1;
+    }
+    const float g11[2] = {xtx[0] * xtx[0] + xty[0] * xty[0], xtx[1] * xtx[1] + xty[1] * xty[1]};
+    const float g22[2] = {xsx[0] * xsx[0] + xsy[0] * xsy[0], xsx[1] * xsx[1] + xsy[1] * xsy[1]};
+    float mx[2][2], my[2][2], Qxs[2][2], Qxt[2][2], Qys[2][2], Qyt[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const float xs = xsx[j], ys = xsy[j], xt = xtx[i], yt = xty[i];
+            const float det = xs * yt - xt * ys;
+            const float vxq = ax_[i] + vtx[i] * eta[j], vyq = ay_[i] + vty[i] * eta[j];
+            const float pq = ap[i] + bp[i] * eta[j];
+            // det grad v_c = Cof grad_ref v_c
+            const float dxx = yt * vsx[j] - ys * vtx[i], dxy = -xt * vsx[j] + xs * vtx[i];
+            const float dyx = yt * vsy[j] - ys * vty[i], dyy = -xt * vsy[j] + xs * vty[i];
+            mx[i][j] = det * wx[i][j] - (vxq * dxx + vyq * dxy);
+            my[i][j] = det * wy[i][j] - (vxq * dyx + vyq * dyy);
+            const float g12 = -(xs * xt + ys * yt);
+            const float inv = nu * Rcp::f(det);
+            Qxs[i][j] = pq * yt - inv * (g11[i] * vsx[j] + g12 * vtx[i]);
+            Qxt[i][j] = -pq * ys - inv * (g12 * vsx[j] + g22[j] * vtx[i]);
+            Qys[i][j] = -pq * xt - inv * (g11[i] * vsy[j] + g12 * vty[i]);
+            Qyt[i][j] = pq * xs - inv * (g12 * vsy[j] + g22[j] * vty[i]);
+        }
+    element_sums<n>(mx, Qxs, Qxt, R);
+    element_sums<n>(my, Qys, Qyt, R + 1);
+}
+
+// A vertical strip of SH fine elements of coarse element r: column a, rows
+// b0 .. b0 + SH - 1.  The same sums as element_residual, arranged so that the
+// work per Gauss point shrinks: on the coarse element
+//   det          = d0 + d1 xi + d2 eta                 (no xi eta term)
+//   det grad v_c = B_c(xi) + C_c eta                   (no xi eta term)
+//   nu g12       = G0(xi) + G1(xi) eta,  nu g22 = k0 + k1 eta + k2 eta^2
+// so at a fixed abscissa xi the viscous numerators are polynomials in eta,
+//   nu (g11 v_c,xi + g12 v_c,eta) = E0 + E1 eta,
+//   nu (g12 v_c,xi + g22 v_c,eta) = F0 + F1 eta + F2 eta^2,
+// whose coefficients are formed once per abscissa and serve the 2 SH Gauss
+// points of the strip on it.  The element sums are taken one abscissa at a
+// time and added straight into the strip's nodes: S[k] is node row k (0 ..
+// SH) as left x, left y, right x, right y (added to, not cleared).  w points
+// at the nodal (u_prev - P v)/dt of the strip's lower-left node; rows are ldw
+// apart.
+template <int K, int SH, typename Rcp>
+__host__ __device__ inline void strip_residual(const CoarseRec &r, int a, int b0, float nu, const float2 *w, int ldw,
+                                               float (&S)[SH + 1][4])
+{
+    constexpr int n = 1 << K;
+    constexpr float inv_n = 1.0f / n, g0 = kGauss0, g1 = kGauss1;
+    constexpr float hm0 = 0.25f * g0 / (n * n), hm1 = 0.25f * g1 / (n * n);
+    constexpr float h0 = 0.25f * g0 / n, h1 = 0.25f * g1 / n;
+    // strip constants
+    const float d0 = r.exx * r.eyy - r.eyx * r.exy;
+    const float d1 = r.exx * r.exyy - r.exyx * r.exy;
+    const float d2 = r.exyx * r.eyy - r.eyx * r.exyy;
+    // det d(v_c)/dx = Bx_c + Cx_c eta, det d(v_c)/dy = By_c + Cy_c eta, Bx_c = Bx0_c + Bx1_c xi, ...
+    const float Bx0x = r.eyy * r.V1x - r.exy * r.V2x, Bx1x = r.exyy * r.V1x - r.exy * r.V3x;
+    const float Cxx = r.eyy * r.V3x - r.exyy * r.V2x;
+    const float By0x = r.exx * r.V2x - r.eyx * r.V1x, By1x = r.exx * r.V3x - r.exyx * r.V1x;
+    const float Cyx = r.exyx * r.V2x - r.eyx * r.V3x;
+    const float Bx0y = r.eyy * r.V1y - r.exy * r.V2y, Bx1y = r.exyy * r.V1y - r.exy * r.V3y;
+    const float Cxy = r.eyy * r.V3y - r.exyy * r.V2y;
+    const float By0y = r.exx * r.V2y - r.eyx * r.V1y, By1y = r.exx * r.V3y - r.exyx * r.V1y;
+    const float Cyy = r.exyx * r.V2y - r.eyx * r.V3y;
+    const float nexx = nu * r.exx, nexy = nu * r.exy, nexyx = nu * r.exyx, nexyy = nu * r.exyy;
+    const float k0 = nexx * r.exx + nexy * r.exy;
+    const float k1 = 2.0f * (nexx * r.exyx + nexy * r.exyy);
+    const float k2 = nexyx * r.exyx + nexyy * r.exyy;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float gi = i ? g1 : g0;
+        const float xi = (a + gi) * inv_n;
+        const float xt = r.eyx + r.exyx * xi, yt = r.eyy + r.exyy * xi;
+        const float vtx = r.V2x + r.V3x * xi, vty = r.V2y + r.V3y * xi;
+        const float ax = r.V0x + r.V1x * xi, ay = r.V0y + r.V1y * xi;
+        const float ap = r.P0 + r.P1 * xi, bp = r.P2 + r.P3 * xi;
+        const float A = d0 + d1 * xi;
+        const float Bxx = Bx0x + Bx1x * xi, Byx = By0x + By1x * xi;
+        const float Bxy = Bx0y + Bx1y * xi, Byy = By0y + By1y * xi;
+        const float g11 = nu * (xt * xt + yt * yt);
+        const float G0 = -(nexx * xt + nexy * yt), G1 = -(nexyx * xt + nexyy * yt);
+        const float E0x = g11 * r.V1x + G0 * vtx, E1x = g11 * r.V3x + G1 * vtx;
+        const float E0y = g11 * r.V1y + G0 * vty, E1y = g11 * r.V3y + G1 * vty;
+        const float F0x = G0 * r.V1x + k0 * vtx, F1x = G0 * r.V3x + G1 * r.V1x + k1 * vtx, F2x = G1 * r.V3x + k2 * vtx;
+        const float F0y = G0 * r.V1y + k0 * vty, F1y = G0 * r.V3y + G1 * r.V1y + k1 * vty, F2y = G1 * r.V3y + k2 * vty;
+        const float hmA = i ? hm0 : hm1, hmB = i ? hm1 : hm0, hA = i ? h0 : h1, hB = i ? h1 : h0;
+        // nodal values interpolated to this abscissa along the element's lower
+        // and upper node rows (the upper row carries over to the next element)
+        float wxl, wyl;
+        {
+            const float2 wl = w[0], wr = w[1];
+            wxl = wl.x + (wr.x - wl.x) * gi;
+            wyl = wl.y + (wr.y - wl.y) * gi;
+        }
+#pragma unroll
+        for (int k = 0; k < SH; ++k) {
+            const float2 wl = w[(k + 1) * ldw], wr = w[(k + 1) * ldw + 1];
+            const float wxu = wl.x + (wr.x - wl.x) * gi, wyu = wl.y + (wr.y - wl.y) * gi;
+            float m[2][2], Qs[2][2], Qt[2][2];     // [component][eta point]
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const float gj = j ? g1 : g0;
+                const float eta = (b0 + k + gj) * inv_n;
+                const float xs = r.exx + r.exyx * eta, ys = r.exy + r.exyy * eta;
+                const float det = A + d2 * eta;
+                const float inv = Rcp::f(det);
+                const float pq = ap + bp * eta;
+                const float vxq = ax + vtx * eta, vyq = ay + vty * eta;
+                const float dxx = Bxx + Cxx * eta, dxy = Byx + Cyx * eta;
+                const float dyx = Bxy + Cxy * eta, dyy = Byy + Cyy * eta;
+                const float wxq = wxl + (wxu - wxl) * gj;
+                const float wyq = wyl + (wyu - wyl) * gj;
+                m[0][j] = det * wxq - (vxq * dxx + vyq * dxy);
+                m[1][j] = det * wyq - (vxq * dyx + vyq * dyy);
+                const float T1x = E0x + E1x * eta, T1y = E0y + E1y * eta;
+                const float T2x = F0x + (F1x + F2x * eta) * eta, T2y = F0y + (F1y + F2y * eta) * eta;
+                Qs[0][j] = pq * yt - inv * T1x;
+                Qt[0][j] = -pq * ys - inv * T2x;
+                Qs[1][j] = -pq * xt - inv * T1y;
+                Qt[1][j] = pq * xs - inv * T2y;
+            }
+            wxl = wxu;
+            wyl = wyu;
+            // this abscissa's share of element k's sums (element_sums split by xi)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const float mb = g1 * m[c][0] + g0 * m[c][1], mt = g0 * m[c][0] + g1 * m[c][1];
+                const float sx0 = h1 * Qs[c][0] + h0 * Qs[c][1], sx1 = h0 * Qs[c][0] + h1 * Qs[c][1];
+                const float qt = Qt[c][0] + Qt[c][1];
+                S[k][c] += hmA * mb - sx0 - hA * qt;
+                S[k][2 + c] += hmB * mb + sx0 - hB * qt;
+                S[k + 1][c] += hmA * mt - sx1 + hA * qt;
+                S[k + 1][2 + c] += hmB * mt + sx1 + hB * qt;
+            }
+            Rcp::fence();
+        }
+    }
+}
+
+}  // namespace dnnmg
