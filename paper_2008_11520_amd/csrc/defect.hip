@@ -326,7 +326,7 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
     const float inv_dt = f.inv_dt, nu = f.nu;
 
     // 0. the previous corrected velocity on the tile's nodes + halo: issue the
-    //    loads now, use them after the coarse records are in LDS
+    //    loads now, use them after the coarse records are formed
     constexpr int NIT = (NN * NN + kThreads - 1) / kThreads;
     float2 uq[NIT];
 #pragma unroll
@@ -362,25 +362,16 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
         }
         s_c[t] = r;
     }
-    __syncthreads();
 
-    // 2. (u_prev - P v) / dt on the tile's nodes + halo (zero before the first
-    //    step); clear the node accumulators
+    // 2. u_prev / dt on the tile's nodes + halo (zero before the first step:
+    //    u_prev is then P v, so the element code, which subtracts v / dt at
+    //    each Gauss point, takes 1/dt as 0); clear the node accumulators
+    const float idt = first ? 0.0f : inv_dt;
 #pragma unroll
     for (int i = 0; i < NIT; ++i) {
         const int t = tid + i * kThreads;
         if (t >= NN * NN) break;
-        const int I = I0 - 1 + t % NN, J = J0 - 1 + t / NN;
-        float2 w = make_float2(0.f, 0.f);
-        if (!first && I >= 0 && I <= NX && J >= 0 && J <= NY) {
-            const int ci = min(I >> K, nx - 1), cj = min(J >> K, ny - 1);
-            const float xi = (I - ci * n) * inv_n, eta = (J - cj * n) * inv_n;
-            const CoarseRec &r = s_c[(cj - cj0) * CE + (ci - ci0)];
-            const float pvx = (r.V0x + r.V1x * xi) + eta * (r.V2x + r.V3x * xi);
-            const float pvy = (r.V0y + r.V1y * xi) + eta * (r.V2y + r.V3y * xi);
-            w = make_float2((uq[i].x - pvx) * inv_dt, (uq[i].y - pvy) * inv_dt);
-        }
-        s_w[t] = w;
+        s_w[t] = make_float2(uq[i].x * idt, uq[i].y * idt);
         s_acc[t] = make_float2(0.f, 0.f);
     }
     __syncthreads();
@@ -410,7 +401,7 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
             const int n0 = (sr * SH + 1) * NN + ec + 1;
             sn0[s] = n0;
             const CoarseRec &r = s_c[((eJ >> K) - cj0) * CE + ((eI >> K) - ci0)];
-            strip_residual<K, SH, HwRcp>(r, eI & (n - 1), eJ & (n - 1), nu, s_w + n0, NN, S[s]);
+            strip_residual<K, SH, HwRcp>(r, eI & (n - 1), eJ & (n - 1), nu, idt, s_w + n0, NN, S[s]);
         }
     }
     // halo: left and right columns (with the corners), then the rows below
@@ -437,7 +428,7 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
             const int n0 = (me + 1) * NN + le + 1;
             hn0 = n0;
             const CoarseRec &r = s_c[((eJ >> K) - cj0) * CE + ((eI >> K) - ci0)];
-            element_residual<K, HwRcp>(r, eI & (n - 1), eJ & (n - 1), nu, s_w[n0], s_w[n0 + 1], s_w[n0 + NN],
+            element_residual<K, HwRcp>(r, eI & (n - 1), eJ & (n - 1), nu, idt, s_w[n0], s_w[n0 + 1], s_w[n0 + NN],
                                        s_w[n0 + NN + 1], Rh);
         }
     }
@@ -575,8 +566,11 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
                 *reinterpret_cast<b2 *>(o) = v;
             }
         };
+        // (items of one patch on consecutive lanes: their LDS rows interleave
+        // across the banks, where one row per lane would stride LDX apart)
         for (int t = tid; t < PP * (n + 2); t += kThreads) {
-            const int b = t / PP, pl = t % PP;
+            const bool feat = t >= PP * (n + 1);
+            const int pl = feat ? t - PP * (n + 1) : t / (n + 1), b = feat ? n + 1 : t - pl * (n + 1);
             const int pa = pl % TP, pb = pl / TP;
             if (tx * TP + pa >= nx || ty * TP + pb >= ny) continue;
             ST *o = s_x + pl * LDX;
@@ -621,8 +615,16 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
 
 // Single flow: one tile per block.  Batched: the blocks stride over the
 // table's tiles of all flows, so the grid need not match the batch.
+// Waves per SIMD the defect aims at (register budget 512 / waves): 4, or
+// what its LDS allows (K = 1 tiles hold more patches; FP32 input rows).
+template <int K, typename XT>
+constexpr int defect_waves()
+{
+    return K == 1 ? (std::is_same<XT, float>::value ? 2 : 3) : (K == 2 && std::is_same<XT, float>::value ? 3 : 4);
+}
+
 template <int K, typename XT, bool BATCHED>
-__global__ __launch_bounds__(kThreads, 4) void k_defect(FlowArgs single, const BatchTable *__restrict__ bt)
+__global__ __launch_bounds__(kThreads, (defect_waves<K, XT>())) void k_defect(FlowArgs single, const BatchTable *__restrict__ bt)
 {
     if (!BATCHED) {
         defect_tile<K, XT, false>(single, blockIdx.x);

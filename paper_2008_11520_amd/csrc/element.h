@@ -66,11 +66,12 @@ __host__ __device__ inline void element_sums(const float m[2][2], const float Qs
 }
 
 // One fine element: column a, row b (0 .. n-1) of coarse element r; w0..w3
-// the nodal (u_prev - P v)/dt at its corners 00, 10, 01, 11.  R[2 a + c] is
-// the residual of component c at corner a.
+// the nodal u_prev / dt at its corners 00, 10, 01, 11, idt = 1/dt (the Gauss
+// point value of (u_prev - v)/dt is the interpolated nodal u_prev / dt minus
+// idt times v there).  R[2 a + c] is the residual of component c at corner a.
 template <int K, typename Rcp>
-__host__ __device__ inline void element_residual(const CoarseRec &r, int a, int b, float nu, float2 w0, float2 w1,
-                                                 float2 w2, float2 w3, float (&R)[8])
+__host__ __device__ inline void element_residual(const CoarseRec &r, int a, int b, float nu, float idt, float2 w0,
+                                                 float2 w1, float2 w2, float2 w3, float (&R)[8])
 {
     constexpr int n = 1 << K;
     constexpr float inv_n = 1.0f / n, g0 = kGauss0, g1 = kGauss1;
@@ -90,7 +91,7 @@ __host__ __device__ inline void element_residual(const CoarseRec &r, int a, int 
         ay_[i] = r.V0y + r.V1y * xi[i];
         ap[i] = r.P0 + r.P1 * xi[i]; bp[i] = r.P2 + r.P3 * xi[i];
     }
-    // (u_prev - v)/dt at the Gauss points from the element's nodal values
+    // u_prev / dt at the Gauss points from the element's nodal values
     float wx[2][2], wy[2][2];
     for (int i = 0; i < 2; ++i) {
         const float sg = i ? g1 : g0;
@@ -111,8 +112,8 @@ __host__ __device__ inline void element_residual(const CoarseRec &r, int a, int 
             // det grad v_c = Cof grad_ref v_c
             const float dxx = yt * vsx[j] - ys * vtx[i], dxy = -xt * vsx[j] + xs * vtx[i];
             const float dyx = yt * vsy[j] - ys * vty[i], dyy = -xt * vsy[j] + xs * vty[i];
-            mx[i][j] = det * wx[i][j] - (vxq * dxx + vyq * dxy);
-            my[i][j] = det * wy[i][j] - (vxq * dyx + vyq * dyy);
+            mx[i][j] = det * (wx[i][j] - idt * vxq) - (vxq * dxx + vyq * dxy);
+            my[i][j] = det * (wy[i][j] - idt * vyq) - (vxq * dyx + vyq * dyy);
             const float g12 = -(xs * xt + ys * yt);
             const float inv = nu * Rcp::f(det);
             Qxs[i][j] = pq * yt - inv * (g11[i] * vsx[j] + g12 * vtx[i]);
@@ -137,11 +138,11 @@ __host__ __device__ inline void element_residual(const CoarseRec &r, int a, int 
 // points of the strip on it.  The element sums are taken one abscissa at a
 // time and added straight into the strip's nodes: S[k] is node row k (0 ..
 // SH) as left x, left y, right x, right y (added to, not cleared).  w points
-// at the nodal (u_prev - P v)/dt of the strip's lower-left node; rows are ldw
-// apart.
+// at the nodal u_prev / dt of the strip's lower-left node; rows are ldw apart;
+// idt = 1/dt as in element_residual.
 template <int K, int SH, typename Rcp>
-__host__ __device__ inline void strip_residual(const CoarseRec &r, int a, int b0, float nu, const float2 *w, int ldw,
-                                               float (&S)[SH + 1][4])
+__host__ __device__ inline void strip_residual(const CoarseRec &r, int a, int b0, float nu, float idt, const float2 *w,
+                                               int ldw, float (&S)[SH + 1][4])
 {
     constexpr int n = 1 << K;
     constexpr float inv_n = 1.0f / n, g0 = kGauss0, g1 = kGauss1;
@@ -208,8 +209,8 @@ __host__ __device__ inline void strip_residual(const CoarseRec &r, int a, int b0
                 const float dyx = Bxy + Cxy * eta, dyy = Byy + Cyy * eta;
                 const float wxq = wxl + (wxu - wxl) * gj;
                 const float wyq = wyl + (wyu - wyl) * gj;
-                m[0][j] = det * wxq - (vxq * dxx + vyq * dxy);
-                m[1][j] = det * wyq - (vxq * dyx + vyq * dyy);
+                m[0][j] = det * (wxq - idt * vxq) - (vxq * dxx + vyq * dxy);
+                m[1][j] = det * (wyq - idt * vyq) - (vxq * dyx + vyq * dyy);
                 const float T1x = E0x + E1x * eta, T1y = E0y + E1y * eta;
                 const float T2x = F0x + (F1x + F2x * eta) * eta, T2y = F0y + (F1y + F2y * eta) * eta;
                 Qs[0][j] = pq * yt - inv * T1x;

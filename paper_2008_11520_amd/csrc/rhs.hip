@@ -84,13 +84,30 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
         float2 *sd2 = reinterpret_cast<float2 *>(s_d);
         const float2 *dp2 = reinterpret_cast<const float2 *>(f.dpatch);
         const int npr = min(TP, nx - pi0), nrows = min(TP, ny - pj0);
+        // With nx even and the tile full in x, every row starts on a 16-byte
+        // boundary and holds an even number of nodes: 16 bytes per load.
+        const bool wide = (nx & 1) == 0 && npr == TP;
+        constexpr int RW4 = RW / 2, NS4 = TP * RW4, IT4 = (NS4 + kThreads - 1) / kThreads;
+        static_assert(RW % 2 == 0, "whole 16-byte pieces per tile row");
         float2 tmp[IT];
+        float4 tmp4[IT4];
+        if (wide) {
+            const float4 *dp4 = reinterpret_cast<const float4 *>(f.dpatch);
 #pragma unroll
-        for (int i = 0; i < IT; ++i) {
-            const int t = tid + i * kThreads;
-            const int r = t / RW, k = t - r * RW;
-            tmp[i] = (t < NS && r < nrows && k < npr * nf) ? dp2[((size_t)(pj0 + r) * nx + pi0) * nf + k]
-                                                          : make_float2(0.f, 0.f);
+            for (int i = 0; i < IT4; ++i) {
+                const int t = tid + i * kThreads;
+                const int r = t / RW4, k = t - r * RW4;
+                tmp4[i] = (t < NS4 && r < nrows) ? dp4[((size_t)(pj0 + r) * nx + pi0) * nf / 2 + k]
+                                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                const int t = tid + i * kThreads;
+                const int r = t / RW, k = t - r * RW;
+                tmp[i] = (t < NS && r < nrows && k < npr * nf) ? dp2[((size_t)(pj0 + r) * nx + pi0) * nf + k]
+                                                              : make_float2(0.f, 0.f);
+            }
         }
         float2 ring = make_float2(0.f, 0.f);
         int rdst = -1;
@@ -113,11 +130,24 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                 rdst = ((qj + 1) * HP + qi + 1) * nf + b * (n + 1) + a;
             }
         }
+        if (wide) {
 #pragma unroll
-        for (int i = 0; i < IT; ++i) {
-            const int t = tid + i * kThreads;
-            const int r = t / RW, k = t - r * RW;
-            if (t < NS) sd2[((r + 1) * HP + 1) * nf + k] = tmp[i];
+            for (int i = 0; i < IT4; ++i) {
+                const int t = tid + i * kThreads;
+                const int r = t / RW4, k = t - r * RW4;
+                if (t < NS4) {
+                    float2 *d = sd2 + ((r + 1) * HP + 1) * nf + 2 * k;
+                    d[0] = make_float2(tmp4[i].x, tmp4[i].y);
+                    d[1] = make_float2(tmp4[i].z, tmp4[i].w);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                const int t = tid + i * kThreads;
+                const int r = t / RW, k = t - r * RW;
+                if (t < NS) sd2[((r + 1) * HP + 1) * nf + k] = tmp[i];
+            }
         }
         if (rdst >= 0) sd2[rdst] = ring;
     }
