@@ -391,8 +391,6 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
     int sn0[SPL];                                          // lower-left node of the strip (-1: outside the mesh)
 #pragma unroll
     for (int s = 0; s < SPL; ++s) {
-#pragma unroll
-        for (int k = 0; k <= SH; ++k) S[s][k][0] = S[s][k][1] = S[s][k][2] = S[s][k][3] = 0.f;
         const int ec = 2 * (lane & 15) + (wave & 1);
         const int sr = 2 * ((lane >> 4) + 4 * s) + (wave >> 1);
         const int eI = I0 + ec, eJ = J0 + sr * SH;

@@ -137,7 +137,7 @@ __host__ __device__ inline void element_residual(const CoarseRec &r, int a, int 
 // whose coefficients are formed once per abscissa and serve the 2 SH Gauss
 // points of the strip on it.  The element sums are taken one abscissa at a
 // time and added straight into the strip's nodes: S[k] is node row k (0 ..
-// SH) as left x, left y, right x, right y (added to, not cleared).  w points
+// SH) as left x, left y, right x, right y (overwritten).  w points
 // at the nodal u_prev / dt of the strip's lower-left node; rows are ldw apart;
 // idt = 1/dt as in element_residual.
 template <int K, int SH, typename Rcp>
@@ -161,6 +161,7 @@ __host__ __device__ inline void strip_residual(const CoarseRec &r, int a, int b0
     const float Cxy = r.eyy * r.V3y - r.exyy * r.V2y;
     const float By0y = r.exx * r.V2y - r.eyx * r.V1y, By1y = r.exx * r.V3y - r.exyx * r.V1y;
     const float Cyy = r.exyx * r.V2y - r.eyx * r.V3y;
+    const float Cxx2 = Cxx + idt * d2, Cyy2 = Cyy + idt * d2;
     const float nexx = nu * r.exx, nexy = nu * r.exy, nexyx = nu * r.exyx, nexyy = nu * r.exyy;
     const float k0 = nexx * r.exx + nexy * r.exy;
     const float k1 = 2.0f * (nexx * r.exyx + nexy * r.exyy);
@@ -174,8 +175,11 @@ __host__ __device__ inline void strip_residual(const CoarseRec &r, int a, int b0
         const float ax = r.V0x + r.V1x * xi, ay = r.V0y + r.V1y * xi;
         const float ap = r.P0 + r.P1 * xi, bp = r.P2 + r.P3 * xi;
         const float A = d0 + d1 * xi;
-        const float Bxx = Bx0x + Bx1x * xi, Byx = By0x + By1x * xi;
-        const float Bxy = Bx0y + Bx1y * xi, Byy = By0y + By1y * xi;
+        // the mass term's -v_c det / dt joins the diagonal gradient terms:
+        // det (w_c - v_c / dt) - v . det grad v_c
+        //   = det w_c - v_x (det dv_c/dx + [c = x] det / dt) - v_y (det dv_c/dy + [c = y] det / dt)
+        const float Bxx = Bx0x + Bx1x * xi + idt * A, Byx = By0x + By1x * xi;
+        const float Bxy = Bx0y + Bx1y * xi, Byy = By0y + By1y * xi + idt * A;
         const float g11 = nu * (xt * xt + yt * yt);
         const float G0 = -(nexx * xt + nexy * yt), G1 = -(nexyx * xt + nexyy * yt);
         const float E0x = g11 * r.V1x + G0 * vtx, E1x = g11 * r.V3x + G1 * vtx;
@@ -205,12 +209,12 @@ __host__ __device__ inline void strip_residual(const CoarseRec &r, int a, int b0
                 const float inv = Rcp::f(det);
                 const float pq = ap + bp * eta;
                 const float vxq = ax + vtx * eta, vyq = ay + vty * eta;
-                const float dxx = Bxx + Cxx * eta, dxy = Byx + Cyx * eta;
-                const float dyx = Bxy + Cxy * eta, dyy = Byy + Cyy * eta;
+                const float dxx = Bxx + Cxx2 * eta, dxy = Byx + Cyx * eta;
+                const float dyx = Bxy + Cxy * eta, dyy = Byy + Cyy2 * eta;
                 const float wxq = wxl + (wxu - wxl) * gj;
                 const float wyq = wyl + (wyu - wyl) * gj;
-                m[0][j] = det * (wxq - idt * vxq) - (vxq * dxx + vyq * dxy);
-                m[1][j] = det * (wyq - idt * vyq) - (vxq * dyx + vyq * dyy);
+                m[0][j] = det * wxq - (vxq * dxx + vyq * dxy);
+                m[1][j] = det * wyq - (vxq * dyx + vyq * dyy);
                 const float T1x = E0x + E1x * eta, T1y = E0y + E1y * eta;
                 const float T2x = F0x + (F1x + F2x * eta) * eta, T2y = F0y + (F1y + F2y * eta) * eta;
                 Qs[0][j] = pq * yt - inv * T1x;
@@ -226,10 +230,23 @@ __host__ __device__ inline void strip_residual(const CoarseRec &r, int a, int b0
                 const float mb = g1 * m[c][0] + g0 * m[c][1], mt = g0 * m[c][0] + g1 * m[c][1];
                 const float sx0 = h1 * Qs[c][0] + h0 * Qs[c][1], sx1 = h0 * Qs[c][0] + h1 * Qs[c][1];
                 const float qt = Qt[c][0] + Qt[c][1];
-                S[k][c] += hmA * mb - sx0 - hA * qt;
-                S[k][2 + c] += hmB * mb + sx0 - hB * qt;
-                S[k + 1][c] += hmA * mt - sx1 + hA * qt;
-                S[k + 1][2 + c] += hmB * mt + sx1 + hB * qt;
+                const float r0 = hmA * mb - sx0 - hA * qt, r2 = hmB * mb + sx0 - hB * qt;
+                const float r4 = hmA * mt - sx1 + hA * qt, r6 = hmB * mt + sx1 + hB * qt;
+                // the first pass writes each node once before adding to it
+                if (i == 0 && k == 0) {
+                    S[k][c] = r0;
+                    S[k][2 + c] = r2;
+                } else {
+                    S[k][c] += r0;
+                    S[k][2 + c] += r2;
+                }
+                if (i == 0) {
+                    S[k + 1][c] = r4;
+                    S[k + 1][2 + c] = r6;
+                } else {
+                    S[k + 1][c] += r4;
+                    S[k + 1][2 + c] += r6;
+                }
             }
             Rcp::fence();
         }

@@ -41,13 +41,15 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
     const int tid = OPAQUE_TID ? tile_thread() : (int)threadIdx.x;
     constexpr int n = 1 << K;
     constexpr int nf = (n + 1) * (n + 1);
-    constexpr int nout = 2 * nf;
     constexpr int TP = kRhsFine / n;          // patches per tile and direction
     constexpr int HP = TP + 2;                // with a ring of neighbour patches
     constexpr int NO = kRhsFine + 1;          // tile nodes per direction
 
-    __shared__ float s_d[FROM_PATCHES ? HP * HP * nout : 1];
-    __shared__ float2 s_dbar[NO * NO];
+    // the staged per-patch outputs (step) and, once the node pass has read
+    // them, the averaged correction at the tile's nodes share one buffer
+    constexpr int kStaged = FROM_PATCHES ? HP * HP * nf : 0;
+    __shared__ float2 s_buf[kStaged > NO * NO ? kStaged : NO * NO];
+    float2 *const s_dbar = s_buf;
     __shared__ float2 s_v[(TP + 1) * (TP + 1)];
     __shared__ double s_A[4 * (n + 1)];
 
@@ -81,7 +83,7 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
         constexpr int RW = TP * nf, NS = TP * RW, IT = (NS + kThreads - 1) / kThreads;
         constexpr int NR = 4 * TP * (n + 1) + 4;
         static_assert(NR <= kThreads, "one ring node per thread");
-        float2 *sd2 = reinterpret_cast<float2 *>(s_d);
+        float2 *sd2 = s_buf;
         const float2 *dp2 = reinterpret_cast<const float2 *>(f.dpatch);
         const int npr = min(TP, nx - pi0), nrows = min(TP, ny - pj0);
         // With nx even and the tile full in x, every row starts on a 16-byte
@@ -155,9 +157,10 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
 
     // ---- node pass: mean over the containing patches (row-major order, as
     //      the mean is defined), Dirichlet mask, corrected velocity.
-    const float2 *sd2 = reinterpret_cast<const float2 *>(s_d);
+    const float2 *sd2 = s_buf;
     // Any tile node (li, lj); the patch offsets are those of the staged ring.
-    auto node = [&](int li, int lj) {
+    // Returns the node's averaged correction.
+    auto node = [&](int li, int lj) -> float2 {
         const int I = I0 + li, J = J0 + lj;
         float2 d = make_float2(0.f, 0.f);
         if (I <= NX && J <= NY) {
@@ -195,19 +198,30 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                 d = reinterpret_cast<const float2 *>(f.dbar_in)[(size_t)J * (NX + 1) + I];
             }
         }
-        s_dbar[lj * NO + li] = d;
+        return d;
     };
     if (!FROM_PATCHES) {
-        for (int t = tid; t < NO * NO; t += kThreads) node(t % NO, t / NO);
+        for (int t = tid; t < NO * NO; t += kThreads) s_dbar[t] = node(t % NO, t / NO);
     } else {
+        // the corrections are kept in registers until every thread is done
+        // reading the staged outputs, then written over them
+        constexpr int OIT = (TP * TP * n + kThreads - 1) / kThreads;
+        float2 dreg[OIT][n];
+        int dpos[OIT];
+        float2 dlast = make_float2(0.f, 0.f);
+        int lpos = -1;
         // the nodes (a, b), a, b < n, of the tile's own patches, one node row of
         // one patch per item: the same sums as node() with the patch known
         // (a node with I < NX, J < NY is masked only on the sides I = 0, J = 0)
         const unsigned dir = f.dirichlet;
-        for (int it = tid; it < TP * TP * n; it += kThreads) {
+#pragma unroll
+        for (int o = 0; o < OIT; ++o) {
+            const int it = tid + o * kThreads;
+            dpos[o] = -1;
             const int pl = it % (TP * TP), b = it / (TP * TP);
             const int pa = pl % TP, pb = pl / TP, pi = pi0 + pa, pj = pj0 + pb;
-            if (pi >= nx || pj >= ny) continue;
+            if (it >= TP * TP * n || pi >= nx || pj >= ny) continue;
+            dpos[o] = (pb * n + b) * NO + pa * n;
             const int hb = (pb + 1) * HP + pa + 1;
             const bool low = b == 0 && pj > 0;
             const int J = pj * n + b;
@@ -234,16 +248,26 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                 const size_t fi = (size_t)J * (NX + 1) + I;
                 reinterpret_cast<float2 *>(f.uprev)[fi] = make_float2(pvx + d.x, pvy + d.y);
                 if (f.dbar_out) reinterpret_cast<float2 *>(f.dbar_out)[fi] = d;
-                s_dbar[(pb * n + b) * NO + pa * n + a] = d;
+                dreg[o][a] = d;
             }
         }
         // the rest: the last node column and row of the tile's patches (the
         // tile's own last column and row, or the mesh end inside the tile)
         const int le = min(TP, nx - pi0) * n, me = min(TP, ny - pj0) * n;
-        for (int t = tid; t < le + me + 1; t += kThreads) {
-            if (t <= me) node(le, t);
-            else node(t - me - 1, me);
+        static_assert(2 * kRhsFine + 1 <= kThreads, "one last-row/column node per thread");
+        if (tid < le + me + 1) {
+            const int li = tid <= me ? le : tid - me - 1, lj = tid <= me ? tid : me;
+            dlast = node(li, lj);
+            lpos = lj * NO + li;
         }
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < OIT; ++o)
+            if (dpos[o] >= 0) {
+#pragma unroll
+                for (int a = 0; a < n; ++a) s_dbar[dpos[o] + a] = dreg[o][a];
+            }
+        if (lpos >= 0) s_dbar[lpos] = dlast;
     }
     __syncthreads();
 
@@ -251,7 +275,9 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
     //      (1/dt) [ sum_k d_k sum_{a,b} A[mx_k][cx][a] A[my_k][cy][b] Dbar(a,b)
     //             + sum_c' (d0 M0 + d1 M1 + d2 M2)[c][c'] v_c' ].
     //      One item per (patch, component, cx): the x pass T_m(b) = sum_a A[m][cx][a] Dbar(a,b),
-    //      then the y pass for both cy.
+    //      then the y pass for both cy (the four items of a patch on
+    //      neighbouring lanes read neighbouring LDS words).
+    const float *dbar1 = reinterpret_cast<const float *>(s_dbar);
     for (int it = tid; it < TP * TP * 4; it += kThreads) {
         const int cx = it & 1, comp = (it >> 1) & 1, pl = it >> 2;
         const int pi = pi0 + pl % TP, pj = pj0 + pl / TP;
@@ -265,8 +291,7 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
             double s0 = 0.0, s1 = 0.0;
 #pragma unroll
             for (int a = 0; a <= n; ++a) {
-                const float2 dd = s_dbar[(bj + b) * NO + bi + a];
-                const double dv = (double)(comp ? dd.y : dd.x);
+                const double dv = (double)dbar1[2 * ((bj + b) * NO + bi + a) + comp];
                 s0 += s_A[(0 * 2 + cx) * (n + 1) + a] * dv;
                 s1 += s_A[(1 * 2 + cx) * (n + 1) + a] * dv;
             }
@@ -274,9 +299,9 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
             T1[b] = s1;
         }
         const int cb = (pl / TP) * (TP + 1) + (pl % TP);
-        const float2 v00 = s_v[cb], v10 = s_v[cb + 1], v01 = s_v[cb + TP + 1], v11 = s_v[cb + TP + 2];
-        const double vq[4] = {(double)(comp ? v00.y : v00.x), (double)(comp ? v10.y : v10.x),
-                              (double)(comp ? v01.y : v01.x), (double)(comp ? v11.y : v11.x)};
+        const float *v1 = reinterpret_cast<const float *>(s_v);
+        const double vq[4] = {(double)v1[2 * cb + comp], (double)v1[2 * (cb + 1) + comp],
+                              (double)v1[2 * (cb + TP + 1) + comp], (double)v1[2 * (cb + TP + 2) + comp]};
 #pragma unroll
         for (int cy = 0; cy < 2; ++cy) {
             double S0 = 0.0, S1 = 0.0, S2 = 0.0;
@@ -302,8 +327,12 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
 
 // Single flow: one tile per block.  Batched: the blocks stride over the
 // table's tiles of all flows, so the grid need not match the batch.
+// Waves per SIMD the rhs aims at (what its LDS allows; register budget 512 / waves).
+template <int K>
+constexpr int rhs_waves() { return K == 2 ? 6 : 4; }
+
 template <int K, int FROM_PATCHES, bool BATCHED>
-__global__ __launch_bounds__(kThreads) void k_rhs(FlowArgs single, const BatchTable *__restrict__ bt, RhsTables tab)
+__global__ __launch_bounds__(kThreads, rhs_waves<K>()) void k_rhs(FlowArgs single, const BatchTable *__restrict__ bt, RhsTables tab)
 {
     if (!BATCHED) {
         rhs_tile<K, FROM_PATCHES, false>(single, blockIdx.x, tab);
