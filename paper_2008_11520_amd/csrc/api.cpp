@@ -616,7 +616,9 @@ extern "C" int dnnmg_profile_enable(dnnmg_ctx *ctx, int max_steps)
     pr.evg.resize(2 * (size_t)max_steps);
     for (auto *v : {&pr.ev, &pr.evg})
         for (hipEvent_t &e : *v)
-            if (hipEventCreate(&e) != hipSuccess) {
+            // no system-scope release at each record: a record then costs about
+            // 2 us of stream time instead of 3.6 us, and the timings stay exact
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
                 e = nullptr;
                 (void)hipGetLastError();
                 profile_release(pr);
