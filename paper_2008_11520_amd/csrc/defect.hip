@@ -144,7 +144,7 @@ int blocks_for(int kind, int nx, int ny, int K)
 // follow the persistent network kernel (products formed transposed, so a lane
 // holds one patch row and four consecutive units); wave w owns hidden tile w
 // for all four row tiles and loads that tile's weight fragments itself.
-constexpr int kFusedLDA = 104 + 64 + 8;        // [x | h] rows (168 values), 16-byte padding
+constexpr int kFusedLDA = 104 + 64 + 16;       // [x | h | 8 zeros] rows (168 + 8 values), padded so that 16 rows of a fragment read fall in distinct LDS banks
 constexpr int kFusedLDH = 64 + 8;
 
 template <int HM>
