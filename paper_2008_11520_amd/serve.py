@@ -91,6 +91,20 @@ class Server:
         self.hbm_budget = int(hbm_budget if hbm_budget is not None else 0.8 * free)
         self.batch = Batch(max_flows)
 
+    def warmup(self):
+        """One tick of the model's own one-patch context: captures the batch
+        graph (and loads the kernels) before any request is timed.  The shared
+        weights are not changed by a step."""
+        import torch
+        nc = self.model.s["Nc"]
+        with torch.cuda.stream(self.stream):
+            v = torch.zeros(2 * nc, dtype=torch.float32, device="cuda")
+            p = torch.zeros(nc, dtype=torch.float32, device="cuda")
+            b = torch.empty(2 * nc, dtype=torch.float64, device="cuda")
+            self.batch.prepare([self.model], [v], [p], None, [b], stream=self.stream)
+            self.batch.launch(graph=self.use_graph, stream=self.stream)
+        self.stream.synchronize()
+
     def flow_bytes(self, nx, ny):
         cfg = make_config(nx, ny, self.K, self.H, self.Hm, self.dt, self.nu, self.precision, synth.DIR_CHANNEL)
         nc = (nx + 1) * (ny + 1)
@@ -134,6 +148,7 @@ class Server:
         also each request's final state (h, corrected velocity) and last b_L."""
         import collections
         import torch
+        self.warmup()
         pending = sorted((dict(r) for r in requests), key=lambda r: r["arrival"])
         sched = Scheduler(self.hbm_budget, self.max_flows, lambda r: self.flow_bytes(r["nx"], r["ny"]))
         active, done = [], []            # flows still issuing steps; finished flows
