@@ -385,14 +385,15 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
     constexpr int SH = n < 4 ? n : 4;                      // strip height
     constexpr int NSR = kTileFine / SH;                    // strip rows per tile
     constexpr int SPL = kTileFine * NSR / kThreads;        // strips per thread
-    static_assert(kTileFine == 32 && kThreads == 256 && NSR == 8 * SPL, "strip mapping: 16 columns x 4 strip rows per wave and strip");
+    static_assert(kTileFine == kTileElems && kThreads == 256 && NSR == 8 * SPL,
+                  "strip mapping: 16 columns x 4 strip rows per wave and strip");
     const int wave = tid >> 6, lane = tid & 63;
     float S[SPL][SH + 1][4];
     int sn0[SPL];                                          // lower-left node of the strip (-1: outside the mesh)
 #pragma unroll
     for (int s = 0; s < SPL; ++s) {
-        const int ec = 2 * (lane & 15) + (wave & 1);
-        const int sr = 2 * ((lane >> 4) + 4 * s) + (wave >> 1);
+        int ec, sr;
+        strip_of(wave, lane, s, ec, sr);
         const int eI = I0 + ec, eJ = J0 + sr * SH;
         sn0[s] = -1;
         if (eI < NX && eJ < NY) {
@@ -402,25 +403,13 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
             strip_residual<K, SH, HwRcp>(r, eI & (n - 1), eJ & (n - 1), nu, idt, s_w + n0, NN, S[s]);
         }
     }
-    // halo: left and right columns (with the corners), then the rows below
-    // and above; each gets the colour of the one round in which it shares no
-    // node with that round's strips or with the other halo elements of it
+    // halo ring, one element per thread (halo_of)
     constexpr int NH = 4 * (kTileFine + 1);
     float Rh[8];
     int hn0 = -1, hcol = -1;
     if (tid < NH) {
         int le, me;                                        // tile-local element (-1 .. kTileFine)
-        if (tid < 2 * (kTileFine + 2)) {
-            const int side = tid / (kTileFine + 2);
-            le = side ? kTileFine : -1;
-            me = tid - side * (kTileFine + 2) - 1;
-            hcol = side ? ((me & 1) ? 2 : 0) : ((me & 1) ? 3 : 1);
-        } else {
-            const int u = tid - 2 * (kTileFine + 2), side = u / kTileFine;
-            le = u - side * kTileFine;
-            me = side ? kTileFine : -1;
-            hcol = side ? ((le & 1) ? 1 : 0) : ((le & 1) ? 3 : 2);
-        }
+        halo_of(tid, le, me, hcol);
         const int eI = I0 + le, eJ = J0 + me;
         if (eI >= 0 && eI < NX && eJ >= 0 && eJ < NY) {
             const int n0 = (me + 1) * NN + le + 1;

@@ -253,4 +253,39 @@ __host__ __device__ inline void strip_residual(const CoarseRec &r, int a, int b0
     }
 }
 
+// ---------------------------------------------------------------- tile partition
+// A defect tile owns kT x kT fine elements (kT = 32) and computes the ring of
+// halo elements around them as well (tile-local element coordinates -1 .. kT).
+// The own elements are vertical strips of SH elements inside one coarse
+// element; thread (wave, lane) holds strip s of its SPL strips at element
+// column ec and strip row sr.  Wave w holds the strips of colour w (column
+// parity w & 1, strip-row parity w >> 1), so one wave's strips share no node.
+constexpr int kTileElems = 32;
+
+__host__ __device__ inline void strip_of(int wave, int lane, int s, int &ec, int &sr)
+{
+    ec = 2 * (lane & 15) + (wave & 1);
+    sr = 2 * ((lane >> 4) + 4 * s) + (wave >> 1);
+}
+
+// Halo element of thread t (t < 4 (kT + 1)): the left and right columns with the
+// corners, then the rows below and above.  colour is the one assembly round in
+// which the element shares no node with that round's strips or with the other
+// halo elements of that round.
+__host__ __device__ inline void halo_of(int t, int &le, int &me, int &colour)
+{
+    constexpr int T = kTileElems;
+    if (t < 2 * (T + 2)) {
+        const int side = t / (T + 2);
+        le = side ? T : -1;
+        me = t - side * (T + 2) - 1;
+        colour = side ? ((me & 1) ? 2 : 0) : ((me & 1) ? 3 : 1);
+    } else {
+        const int u = t - 2 * (T + 2), side = u / T;
+        le = u - side * T;
+        me = side ? T : -1;
+        colour = side ? ((le & 1) ? 1 : 0) : ((le & 1) ? 3 : 2);
+    }
+}
+
 }  // namespace dnnmg
