@@ -471,14 +471,16 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
 
     const int npr = min(TP, nx - tx * TP);            // patches of this tile row inside the mesh
     if constexpr (FP8) {
-        // FP8: per-patch maximum first (LDS atomic max on the bit patterns of
-        // non-negative floats), then the values are formed again, scaled and
-        // converted into byte rows of xstride bytes (zero beyond nin).
+        // FP8: each patch is taken by G consecutive lanes; they form the
+        // patch's values (kept in registers when few enough, else formed
+        // again), reduce the row maximum with lane shuffles, then scale,
+        // convert and write byte pairs into rows of xstride bytes (zero
+        // beyond nin).
         uint8_t *s_q = reinterpret_cast<uint8_t *>(s_wx);
-        __shared__ unsigned s_m[TP * TP];
-        for (int t = tid; t < TP * TP; t += kThreads) s_m[t] = 0u;
-        for (int t = tid; t < TP * TP * XS8 / 16; t += kThreads) reinterpret_cast<uint4 *>(s_q)[t] = make_uint4(0u, 0u, 0u, 0u);
-        __syncthreads();
+        constexpr int G = kThreads / (TP * TP);            // lanes per patch: 1, 4 or 16
+        constexpr int NI = (nf + 1 + G - 1) / G;           // items (node or features) per lane
+        constexpr bool KEEP = NI <= 8;
+        static_assert(G * TP * TP == kThreads && (G & (G - 1)) == 0 && G <= 64, "patch lane groups");
         // item (patch pl, node l < nf): P v and D at the node; l == nf: the features
         auto node_values = [&](int pl, int l, float4 &o) {
             const int pa = pl % TP, pb = pl / TP;
@@ -495,33 +497,42 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
             o.z = d.x;
             o.w = d.y;
         };
-        for (int t = tid; t < TP * TP * (nf + 1); t += kThreads) {
-            const int pl = t / (nf + 1), l = t - pl * (nf + 1);
-            if (tx * TP + pl % TP >= nx || ty * TP + pl / TP >= ny) continue;
-            float4 o;
-            node_values(pl, l, o);
-            const float m = fmaxf(fmaxf(fabsf(o.x), fabsf(o.y)), fmaxf(fabsf(o.z), fabsf(o.w)));
-            atomicMax(&s_m[pl], __float_as_uint(m));
+        const int pl = tid / G, j = tid % G;
+        const int pi = tx * TP + pl % TP, pj = ty * TP + pl / TP;
+        const bool pin = pi < nx && pj < ny;
+        uint8_t *row = s_q + pl * XS8;
+        // the bytes beyond nin (the others are all written below)
+        for (int b = nin + j; b < XS8; b += G) row[b] = 0;
+        float4 o[KEEP ? NI : 1];
+        float m = 0.0f;
+#pragma unroll
+        for (int q = 0; q < NI; ++q) {
+            const int l = j + q * G;
+            if (l <= nf && pin) {
+                float4 v;
+                node_values(pl, l, v);
+                if constexpr (KEEP) o[q] = v;
+                m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+            }
         }
-        __syncthreads();
-        for (int t = tid; t < TP * TP * (nf + 1); t += kThreads) {
-            const int pl = t / (nf + 1), l = t - pl * (nf + 1);
-            const int pi = tx * TP + pl % TP, pj = ty * TP + pl / TP;
-            if (pi >= nx || pj >= ny) continue;
-            const float m = fmaxf(__uint_as_float(s_m[pl]), kFp8MinMax);
-            const float r = 448.0f / m;
-            if (l == 0) f.sx[(size_t)pj * nx + pi] = m / 448.0f;
-            float4 o;
-            node_values(pl, l, o);
-            uint8_t *row = s_q + pl * XS8;
-            const uint32_t c = pack4_e4m3(o.x * r, o.y * r, o.z * r, o.w * r);
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) m = fmaxf(m, __shfl_xor(m, off));
+        m = fmaxf(m, kFp8MinMax);
+        const float rs = 448.0f / m;
+        if (pin && j == 0) f.sx[(size_t)pj * nx + pi] = m / 448.0f;
+#pragma unroll
+        for (int q = 0; q < NI; ++q) {
+            const int l = j + q * G;
+            if (l > nf || !pin) continue;
+            float4 v;
+            if constexpr (KEEP) v = o[q];
+            else node_values(pl, l, v);
+            const uint32_t c = pack4_e4m3(v.x * rs, v.y * rs, v.z * rs, v.w * rs);
             if (l == nf) {
                 *reinterpret_cast<uint32_t *>(row + 4 * nf) = c;      // 4 nf is a multiple of 4
             } else {
-                row[2 * l] = (uint8_t)c;
-                row[2 * l + 1] = (uint8_t)(c >> 8);
-                row[2 * nf + 2 * l] = (uint8_t)(c >> 16);
-                row[2 * nf + 2 * l + 1] = (uint8_t)(c >> 24);
+                *reinterpret_cast<uint16_t *>(row + 2 * l) = (uint16_t)c;            // P v
+                *reinterpret_cast<uint16_t *>(row + 2 * nf + 2 * l) = (uint16_t)(c >> 16);   // D
             }
         }
         __syncthreads();
