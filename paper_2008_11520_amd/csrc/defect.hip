@@ -301,7 +301,7 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
     constexpr int CE = TP + 2;                  // coarse elements incl. halo
 
     constexpr int nf = (n + 1) * (n + 1), nin = 4 * nf + 4;
-    // XT = uint8_t: FP8 network input, assembled in FP32 and quantised per patch
+    // XT = uint8_t: FP8 network input, formed in FP32 and quantised per patch
     constexpr bool FP8 = std::is_same<XT, uint8_t>::value;
     typedef typename std::conditional<FP8, float, XT>::type ST;
     constexpr int XS8 = xstride_fp8(nin);        // FP8 row stride (bytes)
@@ -310,8 +310,8 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
     constexpr size_t kXBytes = FUSED ? sizeof(__bf16) * 64 * kFusedLDA
                                      : (FP8 ? (size_t)TP * TP * XS8 : sizeof(ST) * TP * TP * nin);
     __shared__ CoarseRec s_c[CE * CE];
-    // (u_prev - P v) / dt at nodes; once the element residuals are formed the
-    // same bytes hold the tile's network-input rows
+    // u_prev / dt at the nodes; once the element residuals are formed the same
+    // bytes hold the tile's network-input rows
     __shared__ __align__(16) unsigned char s_wx[kWBytes > kXBytes ? kWBytes : kXBytes];
     float2 *s_w = reinterpret_cast<float2 *>(s_wx);
     ST *s_x = reinterpret_cast<ST *>(s_wx);

@@ -274,8 +274,8 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
     // ---- FP64 share of each patch at each of its 4 corners c = (cx, cy):
     //      (1/dt) [ sum_k d_k sum_{a,b} A[mx_k][cx][a] A[my_k][cy][b] Dbar(a,b)
     //             + sum_c' (d0 M0 + d1 M1 + d2 M2)[c][c'] v_c' ].
-    //      One item per (patch, component, cx): the x pass T_m(b) = sum_a A[m][cx][a] Dbar(a,b),
-    //      then the y pass for both cy (the four items of a patch on
+    //      One item per (patch, component, cx): the x pass T_m(b) = sum_a A[m][cx][a] Dbar(a,b)
+    //      and the y pass for both cy (the four items of a patch on
     //      neighbouring lanes read neighbouring LDS words).
     const float *dbar1 = reinterpret_cast<const float *>(s_dbar);
     for (int it = tid; it < TP * TP * 4; it += kThreads) {
@@ -285,7 +285,9 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
         const size_t e = (size_t)pj * nx + pi;
         const double d0 = f.geo64[4 * e], d1 = f.geo64[4 * e + 1], d2 = f.geo64[4 * e + 2];
         const int bi = (pl % TP) * n, bj = (pl / TP) * n;
-        double T0[n + 1], T1[n + 1];
+        // x pass of node row b, then its terms of the y pass for both cy (the
+        // y sums run over b in order, as a pass over stored rows would)
+        double S[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
 #pragma unroll
         for (int b = 0; b <= n; ++b) {
             double s0 = 0.0, s1 = 0.0;
@@ -295,8 +297,13 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                 s0 += s_A[(0 * 2 + cx) * (n + 1) + a] * dv;
                 s1 += s_A[(1 * 2 + cx) * (n + 1) + a] * dv;
             }
-            T0[b] = s0;
-            T1[b] = s1;
+#pragma unroll
+            for (int cy = 0; cy < 2; ++cy) {
+                const double ay0 = s_A[(0 * 2 + cy) * (n + 1) + b], ay1 = s_A[(1 * 2 + cy) * (n + 1) + b];
+                S[cy][0] += ay0 * s0;
+                S[cy][1] += ay0 * s1;
+                S[cy][2] += ay1 * s0;
+            }
         }
         const int cb = (pl / TP) * (TP + 1) + (pl % TP);
         const float *v1 = reinterpret_cast<const float *>(s_v);
@@ -304,14 +311,7 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                               (double)v1[2 * (cb + TP + 1) + comp], (double)v1[2 * (cb + TP + 2) + comp]};
 #pragma unroll
         for (int cy = 0; cy < 2; ++cy) {
-            double S0 = 0.0, S1 = 0.0, S2 = 0.0;
-#pragma unroll
-            for (int b = 0; b <= n; ++b) {
-                const double ay0 = s_A[(0 * 2 + cy) * (n + 1) + b], ay1 = s_A[(1 * 2 + cy) * (n + 1) + b];
-                S0 += ay0 * T0[b];
-                S1 += ay0 * T1[b];
-                S2 += ay1 * T0[b];
-            }
+            const double S0 = S[cy][0], S1 = S[cy][1], S2 = S[cy][2];
             const int c = cx + 2 * cy;
             double acc = d0 * S0 + d1 * S1 + d2 * S2;
 #pragma unroll
@@ -327,12 +327,13 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
 
 // Single flow: one tile per block.  Batched: the blocks stride over the
 // table's tiles of all flows, so the grid need not match the batch.
-// Waves per SIMD the rhs aims at (what its LDS allows; register budget 512 / waves).
-template <int K>
-constexpr int rhs_waves() { return K == 2 ? 6 : 4; }
+// Waves per SIMD the rhs aims at (what its LDS allows; register budget 512 /
+// waves; the batched K = 3 instance needs more registers than 5 waves leave).
+template <int K, bool BATCHED>
+constexpr int rhs_waves() { return K == 2 ? 6 : (K == 3 && !BATCHED ? 5 : 4); }
 
 template <int K, int FROM_PATCHES, bool BATCHED>
-__global__ __launch_bounds__(kThreads, rhs_waves<K>()) void k_rhs(FlowArgs single, const BatchTable *__restrict__ bt, RhsTables tab)
+__global__ __launch_bounds__(kThreads, (rhs_waves<K, BATCHED>())) void k_rhs(FlowArgs single, const BatchTable *__restrict__ bt, RhsTables tab)
 {
     if (!BATCHED) {
         rhs_tile<K, FROM_PATCHES, false>(single, blockIdx.x, tab);
