@@ -77,32 +77,38 @@ template <> struct Op<1> {
 };
 
 
-template <int PREC, int H>
+// One 64-patch tile.  Wave w takes row tiles 2 (w & 1) and 2 (w & 1) + 1 and
+// half of the hidden (and MLP output) tiles, w >> 1, so that every weight
+// fragment it reads feeds two row tiles and the workgroup reads each weight
+// fragment twice.  HMC is the MLP hidden width rounded up to 64, 128 or 256
+// (0 without the hidden layer): it sizes the LDS.
+template <int PREC, int H, int HMC>
 __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net)
 {
     typedef Op<PREC> O;
     typedef typename O::T T;
     typedef typename O::Frag Frag;
     constexpr int KC = O::KC, KQ = O::KQ;
-    constexpr int HT = H / 16;                 // hidden-unit tiles
+    constexpr int HT = H / 16, HW = HT / 2;    // hidden-unit tiles, per wave
+    static_assert(HT % 2 == 0, "hidden tiles split over two wave pairs");
     constexpr int PAD = 16 / sizeof(T);        // 16-byte row padding
     constexpr int LDH = H + PAD;
-    constexpr int LDM = 256 + PAD;             // MLP hidden width <= 256
+    constexpr int LDM = HMC + PAD;
 
     // r*h (phase 2 operand) and the MLP hidden layer share one buffer: the
-    // former is dead once phase 2 is done.
+    // former is dead once phase 2 is done.  Rows are the tile's 64 patches.
     constexpr int LDB = LDH > LDM ? LDH : LDM;
-    __shared__ __align__(16) T sBuf[4][16 * LDB];
-    __shared__ __align__(16) T sHp[4][16 * LDH];
-    T *sR = sBuf[0], *sAm = sBuf[0];
+    __shared__ __align__(16) T sBuf[kNetRows * LDB];
+    __shared__ __align__(16) T sHp[kNetRows * LDH];
+    T *sR = sBuf, *sAm = sBuf;
 
     const int P = f.nx * f.ny;
     const int nin = net.nin, nout = net.nout, Hm = net.Hm, kc1 = net.kc1;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int li = lane & 15, lq = lane >> 4;
-    const int rbase = blk * kNetRows + wave * 16;   // first patch row of this wave
-    const int arow = rbase + li;                    // row this lane supplies A values for
-    const bool aok = arow < P;
+    const int rg = wave & 1, hg = wave >> 1;
+    const int r0 = 32 * rg;                         // first tile-local row of this wave
+    const int rbase = blk * kNetRows + r0;          // first patch row of this wave
 
     const Frag *B1 = reinterpret_cast<const Frag *>(net.B1);
     const Frag *B2 = reinterpret_cast<const Frag *>(net.B2);
@@ -110,115 +116,150 @@ __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net
     const Frag *B4 = reinterpret_cast<const Frag *>(net.B4);
 
     // ---- phase 1: [x | h] x [W_g | U_g]^T for g = z, r, h
-    f4 az[HT], ar[HT], ah[HT];
+    f4 az[HW][2], ar[HW][2], ah[HW][2];
 #pragma unroll
-    for (int t = 0; t < HT; ++t) az[t] = ar[t] = ah[t] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < HW; ++t)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) az[t][q] = ar[t][q] = ah[t][q] = f4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 0; kc < kc1; ++kc) {
         const int k0 = kc * KC + lq * KQ;
-        Frag a;
-        if (aok && k0 < nin) a = O::load_x(f.X, (size_t)arow * nin + k0);
-        else if (aok && k0 < nin + H) a = O::load_f32(f.h + (size_t)arow * H + (k0 - nin));
-        else {
+        Frag a[2];
 #pragma unroll
-            for (int e = 0; e < KQ; ++e) a[e] = O::cvt(0.f);
+        for (int q = 0; q < 2; ++q) {
+            const int arow = rbase + 16 * q + li;      // row this lane supplies operand values for
+            if (arow < P && k0 < nin) a[q] = O::load_x(f.X, (size_t)arow * nin + k0);
+            else if (arow < P && k0 < nin + H) a[q] = O::load_f32(f.h + (size_t)arow * H + (k0 - nin));
+            else {
+#pragma unroll
+                for (int e = 0; e < KQ; ++e) a[q][e] = O::cvt(0.f);
+            }
         }
 #pragma unroll
-        for (int t = 0; t < HT; ++t) {
-            az[t] = O::mma(az[t], a, B1[((0 * HT + t) * kc1 + kc) * 64 + lane]);
-            ar[t] = O::mma(ar[t], a, B1[((1 * HT + t) * kc1 + kc) * 64 + lane]);
-            ah[t] = O::mma(ah[t], a, B1[((2 * HT + t) * kc1 + kc) * 64 + lane]);
+        for (int tw = 0; tw < HW; ++tw) {
+            const int t = hg * HW + tw;
+            const Frag wz = B1[((0 * HT + t) * kc1 + kc) * 64 + lane];
+            const Frag wr = B1[((1 * HT + t) * kc1 + kc) * 64 + lane];
+            const Frag wh = B1[((2 * HT + t) * kc1 + kc) * 64 + lane];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                az[tw][q] = O::mma(az[tw][q], a[q], wz);
+                ar[tw][q] = O::mma(ar[tw][q], a[q], wr);
+                ah[tw][q] = O::mma(ah[tw][q], a[q], wh);
+            }
         }
     }
 
-    // ---- gates; r*h to LDS.  Lane holds rows rbase + 4 lq + e, column 16 t + li.
-    float hold[HT][4];
+    // ---- gates; r*h to LDS.  Lane holds rows 16 q + 4 lq + e (of the
+    //      wave's 32), column 16 t + li.
+    float hold[HW][2][4];
 #pragma unroll
-    for (int t = 0; t < HT; ++t)
+    for (int tw = 0; tw < HW; ++tw)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int row = rbase + 4 * lq + e, k = 16 * t + li;
-            const float h0 = row < P ? f.h[(size_t)row * H + k] : 0.f;
-            hold[t][e] = h0;
-            az[t][e] = sigmoid(az[t][e]);
-            const float r = sigmoid(ar[t][e]);
-            sR[wave * 16 * LDB + (4 * lq + e) * LDH + k] = O::cvt(r * h0);
-        }
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int lr = r0 + 16 * q + 4 * lq + e, row = blk * kNetRows + lr, k = 16 * (hg * HW + tw) + li;
+                const float h0 = row < P ? f.h[(size_t)row * H + k] : 0.f;
+                hold[tw][q][e] = h0;
+                az[tw][q][e] = sigmoid(az[tw][q][e]);
+                const float r = sigmoid(ar[tw][q][e]);
+                sR[lr * LDH + k] = O::cvt(r * h0);
+            }
     __syncthreads();
 
     // ---- phase 2: (r*h) x U_h^T; update h
-    f4 au[HT];
+    f4 au[HW][2];
 #pragma unroll
-    for (int t = 0; t < HT; ++t) au[t] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int tw = 0; tw < HW; ++tw)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) au[tw][q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kc = 0; kc < H / KC; ++kc) {
-        Frag a = *reinterpret_cast<const Frag *>(&sR[wave * 16 * LDB + li * LDH + kc * KC + lq * KQ]);
+        Frag a[2];
 #pragma unroll
-        for (int t = 0; t < HT; ++t) au[t] = O::mma(au[t], a, B2[(t * (H / KC) + kc) * 64 + lane]);
+        for (int q = 0; q < 2; ++q) a[q] = *reinterpret_cast<const Frag *>(&sR[(r0 + 16 * q + li) * LDH + kc * KC + lq * KQ]);
+#pragma unroll
+        for (int tw = 0; tw < HW; ++tw) {
+            const Frag w = B2[((hg * HW + tw) * (H / KC) + kc) * 64 + lane];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) au[tw][q] = O::mma(au[tw][q], a[q], w);
+        }
     }
 #pragma unroll
-    for (int t = 0; t < HT; ++t)
+    for (int tw = 0; tw < HW; ++tw)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int row = rbase + 4 * lq + e, k = 16 * t + li;
-            const float z = az[t][e];
-            const float hh = fast_tanh(ah[t][e] + au[t][e]);
-            const float hn = z * hold[t][e] + (1.0f - z) * hh;
-            if (row < P) f.h[(size_t)row * H + k] = hn;
-            sHp[wave][(4 * lq + e) * LDH + k] = O::cvt(hn);
-        }
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int lr = r0 + 16 * q + 4 * lq + e, row = blk * kNetRows + lr, k = 16 * (hg * HW + tw) + li;
+                const float z = az[tw][q][e];
+                const float hh = fast_tanh(ah[tw][q][e] + au[tw][q][e]);
+                const float hn = z * hold[tw][q][e] + (1.0f - z) * hh;
+                if (row < P) f.h[(size_t)row * H + k] = hn;
+                sHp[lr * LDH + k] = O::cvt(hn);
+            }
     __syncthreads();
 
-    // ---- MLP head
+    // ---- MLP head; the wave pair hg takes every other output tile
     const int ot_n = (nout + 15) / 16;
-    if (Hm > 0) {
-        for (int mt = 0; mt < Hm / 16; ++mt) {
-            f4 acc = {0.f, 0.f, 0.f, 0.f};
+    auto out_tile = [&](int ot, const T *src, int ld, int kcn, const Frag *Bw) {
+        f4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        for (int kc = 0; kc < kcn; ++kc) {
+            const Frag w = Bw[(ot * kcn + kc) * 64 + lane];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                acc[q] = O::mma(acc[q], *reinterpret_cast<const Frag *>(&src[(r0 + 16 * q + li) * ld + kc * KC + lq * KQ]), w);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = rbase + 16 * q + 4 * lq + e, o = 16 * ot + li;
+                if (row < P && o < nout) f.dpatch[(size_t)row * nout + o] = acc[q][e];
+            }
+    };
+    if constexpr (HMC > 0) {
+        for (int mt = hg; mt < Hm / 16; mt += 2) {
+            f4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
             for (int kc = 0; kc < H / KC; ++kc) {
-                Frag a = *reinterpret_cast<const Frag *>(&sHp[wave][li * LDH + kc * KC + lq * KQ]);
-                acc = O::mma(acc, a, B3[(mt * (H / KC) + kc) * 64 + lane]);
+                const Frag w = B3[(mt * (H / KC) + kc) * 64 + lane];
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    acc[q] = O::mma(acc[q], *reinterpret_cast<const Frag *>(&sHp[(r0 + 16 * q + li) * LDH + kc * KC + lq * KQ]), w);
             }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) sAm[wave * 16 * LDB + (4 * lq + e) * LDM + 16 * mt + li] = O::cvt(fmaxf(acc[e], 0.f));
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    sAm[(r0 + 16 * q + 4 * lq + e) * LDM + 16 * mt + li] = O::cvt(fmaxf(acc[q][e], 0.f));
         }
         __syncthreads();
-        const int kcm = Hm / KC;
-        for (int ot = 0; ot < ot_n; ++ot) {
-            f4 acc = {0.f, 0.f, 0.f, 0.f};
-            for (int kc = 0; kc < kcm; ++kc) {
-                Frag a = *reinterpret_cast<const Frag *>(&sAm[wave * 16 * LDB + li * LDM + kc * KC + lq * KQ]);
-                acc = O::mma(acc, a, B4[(ot * kcm + kc) * 64 + lane]);
-            }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int row = rbase + 4 * lq + e, o = 16 * ot + li;
-                if (row < P && o < nout) f.dpatch[(size_t)row * nout + o] = acc[e];
-            }
-        }
+        for (int ot = hg; ot < ot_n; ot += 2) out_tile(ot, sAm, LDM, Hm / KC, B4);
     } else {
-        for (int ot = 0; ot < ot_n; ++ot) {
-            f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kc = 0; kc < H / KC; ++kc) {
-                Frag a = *reinterpret_cast<const Frag *>(&sHp[wave][li * LDH + kc * KC + lq * KQ]);
-                acc = O::mma(acc, a, B3[(ot * (H / KC) + kc) * 64 + lane]);
-            }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int row = rbase + 4 * lq + e, o = 16 * ot + li;
-                if (row < P && o < nout) f.dpatch[(size_t)row * nout + o] = acc[e];
-            }
-        }
+        for (int ot = hg; ot < ot_n; ot += 2) out_tile(ot, sHp, LDH, H / KC, B3);
     }
+}
+
+// MLP hidden width class of the generic kernel (LDS sizing).
+static constexpr int hm_class(int Hm) { return Hm == 0 ? 0 : (Hm <= 64 ? 64 : (Hm <= 128 ? 128 : 256)); }
+
+// Waves per SIMD of the generic kernel: two workgroups per CU where the LDS
+// allows it.
+template <int PREC, int H, int HMC>
+constexpr int net_waves()
+{
+    constexpr int sz = PREC == 0 ? 4 : 2, pad = 16 / sz, ldh = H + pad, ldm = HMC + pad;
+    return kNetRows * ((ldh > ldm ? ldh : ldm) + ldh) * sz <= 80 * 1024 ? 2 : 1;
 }
 
 // Single flow: one tile per block.  Batched: the blocks stride over the
 // table's tiles of all flows, so the grid need not match the batch.
-template <int PREC, int H, bool BATCHED>
-__global__ __launch_bounds__(kThreads) void k_net(FlowArgs single, const BatchTable *__restrict__ bt, NetArgs net)
+template <int PREC, int H, int HMC, bool BATCHED>
+__global__ __launch_bounds__(kThreads, (net_waves<PREC, H, HMC>())) void k_net(FlowArgs single, const BatchTable *__restrict__ bt, NetArgs net)
 {
     if (!BATCHED) {
-        net_tile<PREC, H>(single, blockIdx.x, net);
+        net_tile<PREC, H, HMC>(single, blockIdx.x, net);
         return;
     }
     const int total = bt->prefix[kKindNet][bt->nflows];
@@ -226,7 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_net(FlowArgs single, const BatchTa
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         int blk = g;
         const FlowArgs &f = *batch_flow(bt, kKindNet, blk);
-        net_tile<PREC, H>(f, blk, net);
+        net_tile<PREC, H, HMC>(f, blk, net);
         __syncthreads();   // LDS is reused by the next tile
     }
 }
@@ -1236,12 +1277,23 @@ int net_blocks(const NetArgs &net, int row_tiles)
     return row_tiles;
 }
 
+template <int PREC, int H, int HMC>
+static void launch_net_m(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net, hipStream_t s)
+{
+    if (bt) hipLaunchKernelGGL((k_net<PREC, H, HMC, true>), dim3(nblocks), dim3(kThreads), 0, s, f, bt, net);
+    else hipLaunchKernelGGL((k_net<PREC, H, HMC, false>), dim3(nblocks), dim3(kThreads), 0, s, f, bt, net);
+}
+
 template <int PREC, int H>
 static hipError_t launch_net_t(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net,
                                hipStream_t s)
 {
-    if (bt) hipLaunchKernelGGL((k_net<PREC, H, true>), dim3(nblocks), dim3(kThreads), 0, s, f, bt, net);
-    else hipLaunchKernelGGL((k_net<PREC, H, false>), dim3(nblocks), dim3(kThreads), 0, s, f, bt, net);
+    switch (hm_class(net.Hm)) {
+    case 0: launch_net_m<PREC, H, 0>(f, bt, nblocks, net, s); break;
+    case 64: launch_net_m<PREC, H, 64>(f, bt, nblocks, net, s); break;
+    case 128: launch_net_m<PREC, H, 128>(f, bt, nblocks, net, s); break;
+    default: launch_net_m<PREC, H, 256>(f, bt, nblocks, net, s);
+    }
     return hipGetLastError();
 }
 
