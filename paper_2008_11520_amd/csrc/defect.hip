@@ -337,29 +337,31 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
         uq[i] = in ? reinterpret_cast<const float2 *>(f.uprev)[(size_t)J * (NX + 1) + I] : make_float2(0.f, 0.f);
     }
 
-    // 1. coarse-element records
+    // 1. coarse-element records.  Every record is formed from indices clamped
+    //    into the mesh, with no branch, so that all of its loads (corner v
+    //    and p, map coefficients) are issued before any is used; a record
+    //    outside the mesh then copies the nearest element's and is never read
+    //    (residuals and input rows are formed for elements inside the mesh).
     const float2 *v2 = reinterpret_cast<const float2 *>(f.v);
+    const bool has_p = f.p != nullptr;
+    const float *p1 = has_p ? f.p : reinterpret_cast<const float *>(f.v);   // read and discarded without p
     for (int t = tid; t < CE * CE; t += kThreads) {
-        const int ci = ci0 + t % CE, cj = cj0 + t / CE;
+        const int ci = min(max(ci0 + t % CE, 0), nx - 1), cj = min(max(cj0 + t / CE, 0), ny - 1);
+        const int c = cj * (nx + 1) + ci;
+        const float2 a = v2[c], b = v2[c + 1], cc = v2[c + nx + 1], d = v2[c + nx + 2];
+        const float *g = f.geo + 6 * ((size_t)cj * nx + ci);
+        const float g0 = g[0], g1 = g[1], g2 = g[2], g3 = g[3], g4 = g[4], g5 = g[5];
+        const float pa = p1[c], pb = p1[c + 1], pc = p1[c + nx + 1], pd = p1[c + nx + 2];
         CoarseRec r;
-        if (ci >= 0 && ci < nx && cj >= 0 && cj < ny) {
-            const int c = cj * (nx + 1) + ci;
-            const float2 a = v2[c], b = v2[c + 1], cc = v2[c + nx + 1], d = v2[c + nx + 2];
-            r.V0x = a.x; r.V1x = b.x - a.x; r.V2x = cc.x - a.x; r.V3x = d.x - b.x - cc.x + a.x;
-            r.V0y = a.y; r.V1y = b.y - a.y; r.V2y = cc.y - a.y; r.V3y = d.y - b.y - cc.y + a.y;
-            if (f.p) {
-                const float pa = f.p[c], pb = f.p[c + 1], pc = f.p[c + nx + 1], pd = f.p[c + nx + 2];
-                r.P0 = pa; r.P1 = pb - pa; r.P2 = pc - pa; r.P3 = pd - pb - pc + pa;
-            } else {
-                r.P0 = r.P1 = r.P2 = r.P3 = 0.f;
-            }
-            const float *g = f.geo + 6 * ((size_t)cj * nx + ci);
-            r.exx = g[0]; r.exy = g[1];
-            r.eyx = g[2]; r.eyy = g[3];
-            r.exyx = g[4]; r.exyy = g[5];
-        } else {
-            r = CoarseRec{};
-        }
+        r.V0x = a.x; r.V1x = b.x - a.x; r.V2x = cc.x - a.x; r.V3x = d.x - b.x - cc.x + a.x;
+        r.V0y = a.y; r.V1y = b.y - a.y; r.V2y = cc.y - a.y; r.V3y = d.y - b.y - cc.y + a.y;
+        r.P0 = has_p ? pa : 0.f;
+        r.P1 = has_p ? pb - pa : 0.f;
+        r.P2 = has_p ? pc - pa : 0.f;
+        r.P3 = has_p ? pd - pb - pc + pa : 0.f;
+        r.exx = g0; r.exy = g1;
+        r.eyx = g2; r.eyy = g3;
+        r.exyx = g4; r.exyy = g5;
         s_c[t] = r;
     }
 
@@ -625,13 +627,13 @@ template <int K, typename XT, bool BATCHED>
 __global__ __launch_bounds__(kThreads, (defect_waves<K, XT>())) void k_defect(FlowArgs single, const BatchTable *__restrict__ bt)
 {
     if (!BATCHED) {
-        defect_tile<K, XT, false>(single, blockIdx.x);
+        defect_tile<K, XT, false>(single, xcd_tile(blockIdx.x, gridDim.x));
         return;
     }
     const int total = bt->prefix[kKindDefect][bt->nflows];
 #pragma unroll 1
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        int blk = g;
+        int blk = xcd_tile(g, total);
         const FlowArgs &f = *batch_flow(bt, kKindDefect, blk);
         defect_tile<K, XT, true>(f, blk);
         __syncthreads();   // LDS is reused by the next tile
@@ -642,13 +644,13 @@ template <bool BATCHED, int HM>
 __global__ __launch_bounds__(kThreads, 4) void k_defect_net(FlowArgs single, const BatchTable *__restrict__ bt, NetArgs net)
 {
     if (!BATCHED) {
-        defect_tile<2, __bf16, false, true, HM>(single, blockIdx.x, &net);
+        defect_tile<2, __bf16, false, true, HM>(single, xcd_tile(blockIdx.x, gridDim.x), &net);
         return;
     }
     const int total = bt->prefix[kKindDefect][bt->nflows];
 #pragma unroll 1
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        int blk = g;
+        int blk = xcd_tile(g, total);
         const FlowArgs &f = *batch_flow(bt, kKindDefect, blk);
         defect_tile<2, __bf16, true, true, HM>(f, blk, &net);
         __syncthreads();   // LDS is reused by the next tile

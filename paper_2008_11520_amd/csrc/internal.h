@@ -99,6 +99,18 @@ hipError_t launch_rhs(const FlowArgs &f, const BatchTable *bt, int nblocks, int 
                       const RhsTables &tab, int from_patches, hipStream_t s);
 hipError_t launch_gather(const FlowArgs &f, const BatchTable *bt, int nblocks, hipStream_t s);
 
+// Workgroups are handed to the chip's eight XCDs in turn (workgroup b to XCD
+// b mod 8), and each XCD has its own L2.  Tile order for the kernels whose
+// tiles read their neighbours' edge data: XCD x takes a contiguous run of the n
+// tiles, so neighbouring tiles meet in one L2.  A bijection of [0, n), so any
+// other dispatch order only costs locality.
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    constexpr int X = 8;
+    const int q = n / X, r = n % X, x = b % X;
+    return x * q + min(x, r) + b / X;
+}
+
 // Find the flow and the flow-local block of a block of a batched launch.
 __device__ inline const FlowArgs *batch_flow(const BatchTable *bt, int kind, int &blk)
 {

@@ -52,24 +52,51 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
     float2 *const s_dbar = s_buf;
     __shared__ float2 s_v[(TP + 1) * (TP + 1)];
     __shared__ double s_A[4 * (n + 1)];
+    __shared__ double s_M[3 * 4 * 4];
+    __shared__ double2 s_g[2 * TP * TP];
 
     const int nx = f.nx, ny = f.ny, NX = nx * n, NY = ny * n;
     const int tiles_x = (nx + TP - 1) / TP;
     const int tx = blk % tiles_x, ty = blk / tiles_x;
     const int pi0 = tx * TP, pj0 = ty * TP;    // first patch of the tile
     const int I0 = pi0 * n, J0 = pj0 * n;      // first fine node
+    // Addresses are formed from the tile's base (uniform, in scalar
+    // registers) plus a 32-bit offset per thread.
+    const size_t pt0 = (size_t)pj0 * nx + pi0;  // the tile's first patch
+    const size_t nt0 = (size_t)J0 * (NX + 1) + I0;   // the tile's first node
+    float2 *const ut = reinterpret_cast<float2 *>(f.uprev) + nt0;
     // The step's defect has already read the first-step flag (stream order).
     if (FROM_PATCHES && blk == 0 && tid == 0) *f.first_flag = 0;
 
-    // ---- stage: moment table, coarse corner velocities, per-patch outputs.
-    //      The tables are read through pinned pointers: in the batched tile
-    //      loop their loads would otherwise be hoisted and held in registers.
+    // ---- stage: moment tables, coarse corner velocities, the patches' map
+    //      determinant coefficients, per-patch outputs.  Every load is issued
+    //      into registers before the first LDS store, so the tile waits for
+    //      one memory round trip instead of one per table.  The tables are
+    //      read through pinned pointers: in the batched tile loop their loads
+    //      would otherwise be hoisted and held in registers.
     const gptr<double> tabA = pinned<double>(tab.A), tabM = pinned<double>(tab.M);
-    for (int t = tid; t < 4 * (n + 1); t += kThreads) s_A[t] = tabA[t];
-    const float2 *v2 = reinterpret_cast<const float2 *>(f.v);
-    for (int t = tid; t < (TP + 1) * (TP + 1); t += kThreads) {
-        int ci = pi0 + t % (TP + 1), cj = pj0 + t / (TP + 1);
-        s_v[t] = (ci <= nx && cj <= ny) ? v2[(size_t)cj * (nx + 1) + ci] : make_float2(0.f, 0.f);
+    constexpr int NA = 4 * (n + 1), NM = 3 * 4 * 4, NV = (TP + 1) * (TP + 1), NG = 2 * TP * TP;
+    static_assert(NA + NM <= kThreads, "one table entry per thread");
+    constexpr int VIT = (NV + kThreads - 1) / kThreads, GIT = (NG + kThreads - 1) / kThreads;
+    // (the addresses are clamped into the arrays and the loads made
+    // unconditionally: a load under a condition is waited for at once)
+    const double tabA_r = tabA[min(tid, NA - 1)], tabM_r = tabM[min(max(tid - NA, 0), NM - 1)];
+    const float2 *vt = reinterpret_cast<const float2 *>(f.v) + (size_t)pj0 * (nx + 1) + pi0;
+    const double2 *gt = reinterpret_cast<const double2 *>(f.geo64) + 2 * pt0;
+    float2 v_r[VIT];
+    double2 g_r[GIT];
+#pragma unroll
+    for (int i = 0; i < VIT; ++i) {
+        const int t = min(tid + i * kThreads, NV - 1);
+        const int ci = min(t % (TP + 1), nx - pi0), cj = min(t / (TP + 1), ny - pj0);
+        v_r[i] = vt[cj * (nx + 1) + ci];
+    }
+#pragma unroll
+    for (int i = 0; i < GIT; ++i) {
+        // (d0, d1) and (d2, pad) of patch t / 2 of the tile
+        const int t = min(tid + i * kThreads, NG - 1), pl = t >> 1;
+        const int pa = min(pl % TP, nx - 1 - pi0), pb = min(pl / TP, ny - 1 - pj0);
+        g_r[i] = gt[2 * (pb * nx + pa) + (t & 1)];
     }
     if (FROM_PATCHES) {
         // per-patch outputs, 8 bytes at a time, into the staged (TP+2)^2-patch
@@ -84,7 +111,8 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
         constexpr int NR = 4 * TP * (n + 1) + 4;
         static_assert(NR <= kThreads, "one ring node per thread");
         float2 *sd2 = s_buf;
-        const float2 *dp2 = reinterpret_cast<const float2 *>(f.dpatch);
+        const float2 *dt2 = reinterpret_cast<const float2 *>(f.dpatch) + pt0 * nf;
+        const int prow = nx * nf;                  // nodes per patch row of the mesh
         const int npr = min(TP, nx - pi0), nrows = min(TP, ny - pj0);
         // With nx even and the tile full in x, every row starts on a 16-byte
         // boundary and holds an even number of nodes: 16 bytes per load.
@@ -94,21 +122,19 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
         float2 tmp[IT];
         float4 tmp4[IT4];
         if (wide) {
-            const float4 *dp4 = reinterpret_cast<const float4 *>(f.dpatch);
+            const float4 *dt4 = reinterpret_cast<const float4 *>(dt2);
 #pragma unroll
             for (int i = 0; i < IT4; ++i) {
                 const int t = tid + i * kThreads;
                 const int r = t / RW4, k = t - r * RW4;
-                tmp4[i] = (t < NS4 && r < nrows) ? dp4[((size_t)(pj0 + r) * nx + pi0) * nf / 2 + k]
-                                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+                tmp4[i] = (t < NS4 && r < nrows) ? dt4[r * (prow / 2) + k] : make_float4(0.f, 0.f, 0.f, 0.f);
             }
         } else {
 #pragma unroll
             for (int i = 0; i < IT; ++i) {
                 const int t = tid + i * kThreads;
                 const int r = t / RW, k = t - r * RW;
-                tmp[i] = (t < NS && r < nrows && k < npr * nf) ? dp2[((size_t)(pj0 + r) * nx + pi0) * nf + k]
-                                                              : make_float2(0.f, 0.f);
+                tmp[i] = (t < NS && r < nrows && k < npr * nf) ? dt2[r * prow + k] : make_float2(0.f, 0.f);
             }
         }
         float2 ring = make_float2(0.f, 0.f);
@@ -128,7 +154,7 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
             }
             const int gi = pi0 + qi, gj = pj0 + qj;
             if (gi >= 0 && gi < nx && gj >= 0 && gj < ny) {
-                ring = dp2[((size_t)gj * nx + gi) * nf + b * (n + 1) + a];
+                ring = dt2[(qj * nx + qi) * nf + b * (n + 1) + a];
                 rdst = ((qj + 1) * HP + qi + 1) * nf + b * (n + 1) + a;
             }
         }
@@ -153,6 +179,17 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
         }
         if (rdst >= 0) sd2[rdst] = ring;
     }
+    if (tid < NA) s_A[tid] = tabA_r;
+    else if (tid < NA + NM) s_M[tid - NA] = tabM_r;
+#pragma unroll
+    for (int i = 0; i < VIT; ++i) {
+        // corners beyond the mesh (tiles at its end) hold zeros
+        const int t = tid + i * kThreads;
+        if (t < NV) s_v[t] = (pi0 + t % (TP + 1) <= nx && pj0 + t / (TP + 1) <= ny) ? v_r[i] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < GIT; ++i)
+        if (tid + i * kThreads < NG) s_g[tid + i * kThreads] = g_r[i];
     __syncthreads();
 
     // ---- node pass: mean over the containing patches (row-major order, as
@@ -182,20 +219,20 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                 if (dirichlet_node<K>(f.dirichlet, I, J, NX, NY)) d = make_float2(0.f, 0.f);
                 const bool owned = (li < kRhsFine || I == NX) && (lj < kRhsFine || J == NY);
                 if (owned) {
-                    // P v at the node from the corners of its (left/lower) patch
+                    // P v at the node from the corners of its (left/lower) patch,
+                    // along the node row (as in the pass below)
                     const float xi = a * (1.0f / n), eta = b * (1.0f / n);
                     const int c = (pJ - pj0) * (TP + 1) + (pI - pi0);
                     const float2 v00 = s_v[c], v10 = s_v[c + 1], v01 = s_v[c + TP + 1], v11 = s_v[c + TP + 2];
-                    const float n00 = (1.f - xi) * (1.f - eta), n10 = xi * (1.f - eta), n01 = (1.f - xi) * eta,
-                                n11 = xi * eta;
-                    const float pvx = n00 * v00.x + n10 * v10.x + n01 * v01.x + n11 * v11.x;
-                    const float pvy = n00 * v00.y + n10 * v10.y + n01 * v01.y + n11 * v11.y;
-                    const size_t fi = (size_t)J * (NX + 1) + I;
-                    reinterpret_cast<float2 *>(f.uprev)[fi] = make_float2(pvx + d.x, pvy + d.y);
-                    if (f.dbar_out) reinterpret_cast<float2 *>(f.dbar_out)[fi] = d;
+                    const float lx = v00.x + (v01.x - v00.x) * eta, ly = v00.y + (v01.y - v00.y) * eta;
+                    const float rx = v10.x + (v11.x - v10.x) * eta, ry = v10.y + (v11.y - v10.y) * eta;
+                    const float pvx = lx + (rx - lx) * xi, pvy = ly + (ry - ly) * xi;
+                    const int fo = lj * (NX + 1) + li;
+                    ut[fo] = make_float2(pvx + d.x, pvy + d.y);
+                    if (f.dbar_out) (reinterpret_cast<float2 *>(f.dbar_out) + nt0)[fo] = d;
                 }
             } else {
-                d = reinterpret_cast<const float2 *>(f.dbar_in)[(size_t)J * (NX + 1) + I];
+                d = (reinterpret_cast<const float2 *>(f.dbar_in) + nt0)[lj * (NX + 1) + li];
             }
         }
         return d;
@@ -224,10 +261,16 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
             dpos[o] = (pb * n + b) * NO + pa * n;
             const int hb = (pb + 1) * HP + pa + 1;
             const bool low = b == 0 && pj > 0;
-            const int J = pj * n + b;
+            const bool mrow = (dir & 4u) && pj == 0 && b == 0, mcol = (dir & 1u) && pi == 0;
+            // P v along the node row: linear between the row's ends
             const float eta = b * (1.0f / n);
             const int c = pb * (TP + 1) + pa;
             const float2 v00 = s_v[c], v10 = s_v[c + 1], v01 = s_v[c + TP + 1], v11 = s_v[c + TP + 2];
+            const float lx = v00.x + (v01.x - v00.x) * eta, ly = v00.y + (v01.y - v00.y) * eta;
+            const float rx = v10.x + (v11.x - v10.x) * eta, ry = v10.y + (v11.y - v10.y) * eta;
+            const float dx = rx - lx, dy = ry - ly;
+            float2 *const urow = ut + (pb * n + b) * (NX + 1) + pa * n;
+            float2 *const drow = f.dbar_out ? reinterpret_cast<float2 *>(f.dbar_out) + (urow - reinterpret_cast<float2 *>(f.uprev)) : nullptr;
 #pragma unroll
             for (int a = 0; a < n; ++a) {
                 const bool lft = a == 0 && pi > 0;
@@ -238,16 +281,11 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                 { const float2 q = sd2[hb * nf + b * (n + 1) + a]; acc.x += q.x; acc.y += q.y; }
                 const float inv = (lft && low) ? 0.25f : ((lft || low) ? 0.5f : 1.0f);
                 float2 d = make_float2(acc.x * inv, acc.y * inv);
-                const int I = pi * n + a;
-                if (((dir & 1u) && I == 0) || ((dir & 4u) && J == 0)) d = make_float2(0.f, 0.f);
+                if (mrow || (a == 0 && mcol)) d = make_float2(0.f, 0.f);
                 const float xi = a * (1.0f / n);
-                const float n00 = (1.f - xi) * (1.f - eta), n10 = xi * (1.f - eta), n01 = (1.f - xi) * eta,
-                            n11 = xi * eta;
-                const float pvx = n00 * v00.x + n10 * v10.x + n01 * v01.x + n11 * v11.x;
-                const float pvy = n00 * v00.y + n10 * v10.y + n01 * v01.y + n11 * v11.y;
-                const size_t fi = (size_t)J * (NX + 1) + I;
-                reinterpret_cast<float2 *>(f.uprev)[fi] = make_float2(pvx + d.x, pvy + d.y);
-                if (f.dbar_out) reinterpret_cast<float2 *>(f.dbar_out)[fi] = d;
+                const float pvx = lx + dx * xi, pvy = ly + dy * xi;
+                urow[a] = make_float2(pvx + d.x, pvy + d.y);
+                if (drow) drow[a] = d;
                 dreg[o][a] = d;
             }
         }
@@ -278,12 +316,14 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
     //      and the y pass for both cy (the four items of a patch on
     //      neighbouring lanes read neighbouring LDS words).
     const float *dbar1 = reinterpret_cast<const float *>(s_dbar);
+    const size_t P = (size_t)nx * ny;
+    double *const pt = f.part + 2 * pt0;
     for (int it = tid; it < TP * TP * 4; it += kThreads) {
         const int cx = it & 1, comp = (it >> 1) & 1, pl = it >> 2;
         const int pi = pi0 + pl % TP, pj = pj0 + pl / TP;
         if (pi >= nx || pj >= ny) continue;
-        const size_t e = (size_t)pj * nx + pi;
-        const double d0 = f.geo64[4 * e], d1 = f.geo64[4 * e + 1], d2 = f.geo64[4 * e + 2];
+        const double2 g01 = s_g[2 * pl], g2x = s_g[2 * pl + 1];
+        const double d0 = g01.x, d1 = g01.y, d2 = g2x.x;
         const int bi = (pl % TP) * n, bj = (pl / TP) * n;
         // x pass of node row b, then its terms of the y pass for both cy (the
         // y sums run over b in order, as a pass over stored rows would)
@@ -305,6 +345,8 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                 S[cy][2] += ay1 * s0;
             }
         }
+        // this item's entry in corner plane cx (plane c = cx + 2 cy holds P pairs)
+        double *const pq = pt + 2 * (size_t)cx * P + 2 * ((pl / TP) * nx + pl % TP) + comp;
         const int cb = (pl / TP) * (TP + 1) + (pl % TP);
         const float *v1 = reinterpret_cast<const float *>(s_v);
         const double vq[4] = {(double)v1[2 * cb + comp], (double)v1[2 * (cb + 1) + comp],
@@ -316,11 +358,11 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
             double acc = d0 * S0 + d1 * S1 + d2 * S2;
 #pragma unroll
             for (int cc = 0; cc < 4; ++cc) {
-                const double w = d0 * tabM[(0 * 4 + c) * 4 + cc] + d1 * tabM[(1 * 4 + c) * 4 + cc] +
-                                 d2 * tabM[(2 * 4 + c) * 4 + cc];
+                const double w = d0 * s_M[(0 * 4 + c) * 4 + cc] + d1 * s_M[(1 * 4 + c) * 4 + cc] +
+                                 d2 * s_M[(2 * 4 + c) * 4 + cc];
                 acc += w * vq[cc];
             }
-            f.part[2 * ((size_t)c * nx * ny + e) + comp] = f.inv_dt64 * acc;
+            pq[4 * cy * P] = f.inv_dt64 * acc;
         }
     }
 }
@@ -336,13 +378,13 @@ template <int K, int FROM_PATCHES, bool BATCHED>
 __global__ __launch_bounds__(kThreads, (rhs_waves<K, BATCHED>())) void k_rhs(FlowArgs single, const BatchTable *__restrict__ bt, RhsTables tab)
 {
     if (!BATCHED) {
-        rhs_tile<K, FROM_PATCHES, false>(single, blockIdx.x, tab);
+        rhs_tile<K, FROM_PATCHES, false>(single, xcd_tile(blockIdx.x, gridDim.x), tab);
         return;
     }
     const int total = bt->prefix[kKindRhs][bt->nflows];
 #pragma unroll 1
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        int blk = g;
+        int blk = xcd_tile(g, total);
         const FlowArgs &f = *batch_flow(bt, kKindRhs, blk);
         rhs_tile<K, FROM_PATCHES, true>(f, blk, tab);
         __syncthreads();   // LDS is reused by the next tile
