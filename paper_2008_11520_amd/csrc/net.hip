@@ -1056,103 +1056,145 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_q8p(FlowArgs single, 
     }
 }
 
-// Persistent BF16 kernel for the shapes k_net_h64 does not cover (H = 128,
-// or K = 3), Hm = 0 or H.  Eight waves; wave w owns hidden tile w % HT for
-// 4 / (8 / HT) row tiles of each 64-patch tile, as in k_net_q8p.  The weights
-// (368 KB at K = 3, H = 128) do not fit in registers or LDS, so each wave
-// streams its hidden tile's fragments from L2 once per 64-patch tile; the
-// input and state rows are staged through LDS and prefetched one tile ahead.
+// Persistent BF16 kernel on 128-patch tiles for the shapes k_net_h64 does not
+// cover (H = 128, or K = 3), Hm = 0 or H.  Eight waves; wave w owns hidden
+// tile w % HT for the 8 / (8 / HT) row tiles of its row group, so each weight
+// fragment streamed from L2 (the weights, 368 KB at K = 3, H = 128, fit
+// neither in registers nor in LDS) feeds 8 (H = 128) or 4 (H = 64) row tiles
+// per gate.  The input rows of the tile fill LDS during the gate GEMM; r * h,
+// h' and the MLP hidden layer then reuse those bytes.  The FP32 state stays
+// in registers in the lane layout of the update.  The input rows are
+// prefetched one tile ahead; the state is loaded when the tile starts and
+// waited for only after the k-chunks that hold input alone.  A 128-patch tile
+// is a pair of 64-patch row tiles of the launch, each of which may belong to
+// another flow of a batch.
+constexpr int kWideRows = 128;
+
 template <int K, int H, int HM>
-__global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16p(FlowArgs single, const BatchTable *__restrict__ bt,
-                                                                NetArgs net, int ntiles)
+__global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single, const BatchTable *__restrict__ bt,
+                                                                NetArgs net, int ntiles64)
 {
     typedef Op<1> O;
     constexpr int n = 1 << K, nf = (n + 1) * (n + 1), nin = 4 * nf + 4, nout = 2 * nf;
     constexpr int KC = 32, KQ = 8, KC1 = (nin + H + KC - 1) / KC, HC = H / KC;
-    constexpr int HT = H / 16, WPH = 8 / HT, RTW = 4 / WPH;
+    constexpr int HT = H / 16, WPH = 8 / HT, RTW = (kWideRows / 16) / WPH;
     constexpr int OT = (nout + 15) / 16;
-    constexpr int LDA = KC1 * KC + 8, LDH = H + 8, LDS32 = H + 4;
+    constexpr int LDA = KC1 * KC + 8, LDH = H + 8;
     constexpr int PADK = KC1 * KC - nin - H;
+    constexpr int ABYTES = kWideRows * LDA * 2, HBYTES = kWideRows * LDH * 2;
+    constexpr int LDSB = ABYTES > 2 * HBYTES ? ABYTES : 2 * HBYTES;
     static_assert(HM == 0 || HM == H, "MLP hidden tiles follow the hidden tiles");
-    static_assert(nin % 8 == 0, "input rows in 16-byte pieces");
-    if (bt) ntiles = bt->prefix[kKindNet][bt->nflows];
+    static_assert(nin % 8 == 0 && PADK % 8 == 0, "rows in 16-byte pieces");
+    static_assert(kNetH64Threads == 512 && (H == 64 || H == 128), "eight waves over 4 or 8 hidden tiles");
+    if (bt) ntiles64 = bt->prefix[kKindNet][bt->nflows];
+    const int ntiles = (ntiles64 + 1) / 2;
 
-    __shared__ __align__(16) __bf16 sA[64 * LDA];        // [x | h | 0] rows (BF16)
-    __shared__ __align__(16) float sH[64 * LDS32];       // FP32 state rows
-    __shared__ __align__(16) __bf16 sR[64 * LDH];        // r*h
-    __shared__ __align__(16) __bf16 sHp[64 * LDH];       // h'
-    __shared__ __align__(16) __bf16 sAm[64 * LDH];       // MLP hidden layer
+    __shared__ __align__(16) unsigned char s_lds[LDSB];
+    __bf16 *const sA = reinterpret_cast<__bf16 *>(s_lds);             // [x | h | 0] rows, gate GEMM
+    __bf16 *const sR = reinterpret_cast<__bf16 *>(s_lds);             // r * h, after the gate GEMM
+    __bf16 *const sHp = reinterpret_cast<__bf16 *>(s_lds + HBYTES);   // h'
+    __bf16 *const sAm = sR;                                           // MLP hidden layer, after U_h (r * h)
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lq = lane >> 4;
     const int ht = wave % HT, rt0 = RTW * (wave / HT);
     const int ucol = 16 * ht + 4 * lq;
-    const bf8 *B1 = reinterpret_cast<const bf8 *>(net.B1);
-    const bf8 *B2 = reinterpret_cast<const bf8 *>(net.B2);
-    const bf8 *B3 = reinterpret_cast<const bf8 *>(net.B3);
-    const bf8 *B4 = reinterpret_cast<const bf8 *>(net.B4);
 
-    constexpr int XCH = 64 * nin / 8, HCH = 64 * H / 4;
+    // the two 64-row halves of a tile: input, state and output rows, row count
+    // (global address-space pointers: global, not flat, loads and stores;
+    // the single flow's fields copied out, since the lambdas below would
+    // otherwise reach the argument through a generic pointer)
+    typedef __attribute__((address_space(1))) float gfloat;
+    const void *const sX = single.X;
+    float *const sh = single.h, *const sdp = single.dpatch;
+    const int sP = single.nx * single.ny;
+    struct Half {
+        gptr<__bf16> X;
+        gfloat *h, *dp;
+        int nrows;
+    };
+    auto half_of = [&](int t64) -> Half {
+        Half r{nullptr, nullptr, nullptr, 0};
+        if (t64 >= ntiles64) return r;
+        int blk = t64;
+        // (fields read in two branches: a pointer that may point at either the
+        // kernel argument or the batch table would make them flat loads)
+        const void *X;
+        float *h, *dp;
+        int P;
+        if (bt) {
+            const FlowArgs &F = *batch_flow(bt, kKindNet, blk);
+            X = F.X; h = F.h; dp = F.dpatch; P = F.nx * F.ny;
+        } else {
+            X = sX; h = sh; dp = sdp; P = sP;
+        }
+        const int row0 = blk * 64;
+        r.X = (gptr<__bf16>)(reinterpret_cast<const __bf16 *>(X) + (size_t)row0 * nin);
+        r.h = (gfloat *)(h + (size_t)row0 * H);
+        r.dp = (gfloat *)(dp + (size_t)row0 * nout);
+        r.nrows = min(64, P - row0);
+        return r;
+    };
+
+    constexpr int XR = nin / 8, XCH = kWideRows * XR;
     constexpr int XPT = (XCH + kNetH64Threads - 1) / kNetH64Threads;
-    constexpr int HPT = (HCH + kNetH64Threads - 1) / kNetH64Threads;
+    constexpr int KX = nin / KC;        // k-chunks that hold input alone
     bf8 xr[XPT];
-    f4 hr[HPT];
-    auto load_tile = [&](int tile) {
-        int blk = tile;
-        const FlowArgs *fq = bt ? batch_flow(bt, kKindNet, blk) : &single;
-        const int P = fq->nx * fq->ny, row0 = blk * 64, nrows = min(64, P - row0);
-        const bf8 *xg = reinterpret_cast<const bf8 *>(reinterpret_cast<const __bf16 *>(fq->X) + (size_t)row0 * nin);
-        const f4 *hgv = reinterpret_cast<const f4 *>(fq->h + (size_t)row0 * H);
+    // (index math from tile_thread(): recomputed in each tile instead of
+    // hoisted out of the tile loop and held in registers)
+    auto load_x = [&](const Half &a, const Half &b) {
+        const int t0 = tile_thread();
 #pragma unroll
         for (int i = 0; i < XPT; ++i) {
-            const int c = tid + i * kNetH64Threads;
-            xr[i] = (c < XCH && c / (nin / 8) < nrows) ? xg[c] : bf8{};
-        }
-#pragma unroll
-        for (int i = 0; i < HPT; ++i) {
-            const int c = tid + i * kNetH64Threads;
-            hr[i] = (c < HCH && c / (H / 4) < nrows) ? hgv[c] : f4{0.f, 0.f, 0.f, 0.f};
+            const int c = t0 + i * kNetH64Threads;
+            const int r = c / XR, k = c - r * XR;
+            const Half &hh = r < 64 ? a : b;
+            const int rr = r & 63;
+            xr[i] = (c < XCH && rr < hh.nrows) ? *(gptr<bf8>)(hh.X + rr * nin + 8 * k) : bf8{};
         }
     };
-    if (PADK > 0)
-        for (int t = tid; t < 64 * PADK; t += kNetH64Threads) sA[(t / PADK) * LDA + nin + H + t % PADK] = (__bf16)0.f;
-    if (blockIdx.x < ntiles) load_tile(blockIdx.x);
+    if ((int)blockIdx.x < ntiles) load_x(half_of(2 * blockIdx.x), half_of(2 * blockIdx.x + 1));
 
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        int blk = tile;
-        const FlowArgs &ff = bt ? *batch_flow(bt, kKindNet, blk) : single;
-        const int P = ff.nx * ff.ny;
-        const int row0 = blk * 64;
-        const int nrows = min(64, P - row0);
-        float *hg = ff.h + (size_t)row0 * H;
-        float *dp = ff.dpatch + (size_t)row0 * nout;
+        const Half ha = half_of(2 * tile), hb = half_of(2 * tile + 1);
+        const gptr<bf8> B1 = pinned<bf8>(net.B1);
+        const gptr<bf8> B2 = pinned<bf8>(net.B2);
+        const gptr<bf8> B3 = pinned<bf8>(net.B3);
+        const gptr<bf8> B4 = pinned<bf8>(net.B4);
 
+        // this tile's state, in the lane layout of the update (rows
+        // 16 q + li of the wave's row tiles, units ucol .. ucol + 3)
+        f4 hold[RTW];
+#pragma unroll
+        for (int q = 0; q < RTW; ++q) {
+            const int r = 16 * (rt0 + q) + li;
+            const Half &hh = r < 64 ? ha : hb;
+            hold[q] = (r & 63) < hh.nrows ? *(const __attribute__((address_space(1))) f4 *)(hh.h + (r & 63) * H + ucol)
+                                          : f4{0.f, 0.f, 0.f, 0.f};
+        }
         __syncthreads();   // the previous tile's readers of LDS are done
+        const int t1 = tile_thread();
 #pragma unroll
         for (int i = 0; i < XPT; ++i) {
-            const int c = tid + i * kNetH64Threads;
-            if (c < XCH) *reinterpret_cast<bf8 *>(&sA[(c / (nin / 8)) * LDA + 8 * (c % (nin / 8))]) = xr[i];
-        }
-#pragma unroll
-        for (int i = 0; i < HPT; ++i) {
-            const int c = tid + i * kNetH64Threads;
-            if (c < HCH) {
-                const int r = c / (H / 4), k = 4 * (c % (H / 4));
-                *reinterpret_cast<f4 *>(&sH[r * LDS32 + k]) = hr[i];
-                bf4 hb;
-                hb[0] = (__bf16)hr[i].x; hb[1] = (__bf16)hr[i].y; hb[2] = (__bf16)hr[i].z; hb[3] = (__bf16)hr[i].w;
-                *reinterpret_cast<bf4 *>(&sA[r * LDA + nin + k]) = hb;
+            const int c = t1 + i * kNetH64Threads;
+            if (c < XCH) {
+                const int r = c / XR, k = c - r * XR;
+                *reinterpret_cast<bf8 *>(&sA[r * LDA + 8 * k]) = xr[i];
             }
         }
-        if (tile + (int)gridDim.x < ntiles) load_tile(tile + gridDim.x);
+        // zeros after [x | h]: the last k-chunk reads them (r * h and h'
+        // overwrite them later in the tile)
+        if (PADK > 0)
+            for (int t = t1; t < kWideRows * (PADK / 8); t += kNetH64Threads)
+                *reinterpret_cast<uint4 *>(&sA[(t / (PADK / 8)) * LDA + nin + H + 8 * (t % (PADK / 8))]) = make_uint4(0u, 0u, 0u, 0u);
         __syncthreads();
 
-        // ---- phase 1: weight fragments streamed chunk by chunk
+        // ---- gates: weight fragments streamed chunk by chunk; the chunks of
+        //      input alone first, then the state's BF16 copy joins the rows
         f4 az[RTW], ar[RTW], ah[RTW];
 #pragma unroll
         for (int q = 0; q < RTW; ++q) az[q] = ar[q] = ah[q] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 3
-        for (int kc = 0; kc < KC1; ++kc) {
+        auto chunk = [&](int kc) {
             const bf8 wz = B1[((0 * HT + ht) * KC1 + kc) * 64 + lane];
             const bf8 wr = B1[((1 * HT + ht) * KC1 + kc) * 64 + lane];
             const bf8 wh = B1[((2 * HT + ht) * KC1 + kc) * 64 + lane];
@@ -1163,12 +1205,22 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16p(FlowArgs single,
                 ar[q] = O::mma(ar[q], wr, a);
                 ah[q] = O::mma(ah[q], wh, a);
             }
+        };
+#pragma unroll 1
+        for (int kc = 0; kc < KX; ++kc) chunk(kc);
+#pragma unroll
+        for (int q = 0; q < RTW; ++q) {
+            bf4 hb4;
+            hb4[0] = (__bf16)hold[q].x; hb4[1] = (__bf16)hold[q].y; hb4[2] = (__bf16)hold[q].z; hb4[3] = (__bf16)hold[q].w;
+            *reinterpret_cast<bf4 *>(&sA[(16 * (rt0 + q) + li) * LDA + nin + ucol]) = hb4;
         }
-        f4 hold[RTW];
+        __syncthreads();
+#pragma unroll 1
+        for (int kc = KX; kc < KC1; ++kc) chunk(kc);
+        __syncthreads();   // every wave is done with the input rows (r * h reuses them)
 #pragma unroll
         for (int q = 0; q < RTW; ++q) {
             const int r = 16 * (rt0 + q) + li;
-            hold[q] = *reinterpret_cast<const f4 *>(&sH[r * LDS32 + ucol]);
             bf4 rh;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -1177,9 +1229,11 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16p(FlowArgs single,
             }
             *reinterpret_cast<bf4 *>(&sR[r * LDH + ucol]) = rh;
         }
+        // the next tile's input rows: in flight during U_h and the MLP
+        if (tile + (int)gridDim.x < ntiles) load_x(half_of(2 * (tile + gridDim.x)), half_of(2 * (tile + gridDim.x) + 1));
         __syncthreads();
 
-        // ---- phase 2: U_h (r*h); new state
+        // ---- U_h (r * h); new state
         bf8 w2[HC];
 #pragma unroll
         for (int kc = 0; kc < HC; ++kc) w2[kc] = B2[(ht * HC + kc) * 64 + lane];
@@ -1191,30 +1245,33 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16p(FlowArgs single,
             for (int kc = 0; kc < HC; ++kc)
                 au = O::mma(au, w2[kc], *reinterpret_cast<const bf8 *>(&sR[r * LDH + kc * KC + lq * KQ]));
             f4 hn;
-            bf4 hb;
+            bf4 hb4;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float z = az[q][e];
                 hn[e] = z * hold[q][e] + (1.0f - z) * fast_tanh(ah[q][e] + au[e]);
-                hb[e] = (__bf16)hn[e];
+                hb4[e] = (__bf16)hn[e];
             }
-            if (r < nrows) *reinterpret_cast<f4 *>(hg + (size_t)r * H + ucol) = hn;
-            *reinterpret_cast<bf4 *>(&sHp[r * LDH + ucol]) = hb;
+            const Half &hh = r < 64 ? ha : hb;
+            if ((r & 63) < hh.nrows) *(__attribute__((address_space(1))) f4 *)(hh.h + (r & 63) * H + ucol) = hn;
+            *reinterpret_cast<bf4 *>(&sHp[r * LDH + ucol]) = hb4;
         }
         __syncthreads();
 
         // ---- MLP head
         const __bf16 *src = sHp;
-        const bf8 *Wo = B3;
-        constexpr int CO = HC;          // HM == H or 0: both layers have H-wide inputs
+        gptr<bf8> Wo = B3;
         if constexpr (HM > 0) {
+            bf8 w3[HC];
+#pragma unroll
+            for (int kc = 0; kc < HC; ++kc) w3[kc] = B3[(ht * HC + kc) * 64 + lane];
 #pragma unroll
             for (int q = 0; q < RTW; ++q) {
                 const int r = 16 * (rt0 + q) + li;
                 f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int kc = 0; kc < HC; ++kc)
-                    acc = O::mma(acc, B3[(ht * HC + kc) * 64 + lane], *reinterpret_cast<const bf8 *>(&sHp[r * LDH + kc * KC + lq * KQ]));
+                    acc = O::mma(acc, w3[kc], *reinterpret_cast<const bf8 *>(&sHp[r * LDH + kc * KC + lq * KQ]));
                 bf4 m;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) m[e] = (__bf16)fmaxf(acc[e], 0.f);
@@ -1226,21 +1283,24 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16p(FlowArgs single,
         }
         for (int ot = ht; ot < OT; ot += HT) {
             const int oc = 16 * ot + 4 * lq;
-            bf8 wo[CO];
+            bf8 wo[HC];
 #pragma unroll
-            for (int kc = 0; kc < CO; ++kc) wo[kc] = Wo[(ot * CO + kc) * 64 + lane];
+            for (int kc = 0; kc < HC; ++kc) wo[kc] = Wo[(ot * HC + kc) * 64 + lane];
 #pragma unroll
             for (int q = 0; q < RTW; ++q) {
                 const int r = 16 * (rt0 + q) + li;
                 f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int kc = 0; kc < CO; ++kc)
+                for (int kc = 0; kc < HC; ++kc)
                     acc = O::mma(acc, wo[kc], *reinterpret_cast<const bf8 *>(&src[r * LDH + kc * KC + lq * KQ]));
                 // nout is even: the pairs (oc, oc+1), (oc+2, oc+3) are inside or outside together
-                if (r < nrows) {
-                    float *o = dp + (size_t)r * nout + oc;
-                    if (oc < nout) *reinterpret_cast<float2 *>(o) = make_float2(acc[0], acc[1]);
-                    if (oc + 2 < nout) *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[2], acc[3]);
+                const Half &hh = r < 64 ? ha : hb;
+                if ((r & 63) < hh.nrows) {
+                    gfloat *o = hh.dp + (r & 63) * nout + oc;
+                    typedef float v2 __attribute__((ext_vector_type(2)));
+                    typedef __attribute__((address_space(1))) v2 gv2;
+                    if (oc < nout) *(gv2 *)o = v2{acc[0], acc[1]};
+                    if (oc + 2 < nout) *(gv2 *)(o + 2) = v2{acc[2], acc[3]};
                 }
             }
         }
@@ -1255,11 +1315,11 @@ static bool use_q8p(const NetArgs &net)
 {
     return net.prec == 2 && (net.H == 64 || net.H == 128) && (net.Hm == 0 || net.Hm == net.H);
 }
-static bool use_b16p(const NetArgs &net)
+static bool use_b16w(const NetArgs &net)
 {
     return net.prec == 1 && !use_h64(net) && (net.H == 64 || net.H == 128) && (net.Hm == 0 || net.Hm == net.H);
 }
-static bool persistent(const NetArgs &net) { return use_h64(net) || use_q8p(net) || use_b16p(net); }
+static bool persistent(const NetArgs &net) { return use_h64(net) || use_q8p(net) || use_b16w(net); }
 
 bool net_needs_x(int prec, int K, int H, int Hm) { return !use_h64(prec, K, H, Hm); }
 
@@ -1305,20 +1365,21 @@ hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int ntiles, const
         else hipLaunchKernelGGL(k_net_h64<2>, dim3(nblocks), dim3(kNetH64Threads), 0, s, f, bt, net, ntiles);
         return hipGetLastError();
     }
-    if (use_b16p(net)) {
-        dim3 g(nblocks), b(kNetH64Threads);
-#define DNNMG_B16P(KK, HH, MM) hipLaunchKernelGGL((k_net_b16p<KK, HH, MM>), g, b, 0, s, f, bt, net, ntiles)
-#define DNNMG_B16P_H(KK)                                                                             \
-        if (net.H == 64) { if (net.Hm == 64) DNNMG_B16P(KK, 64, 64); else DNNMG_B16P(KK, 64, 0); }    \
-        else { if (net.Hm == 128) DNNMG_B16P(KK, 128, 128); else DNNMG_B16P(KK, 128, 0); }
+    if (use_b16w(net)) {
+        // 128-patch tiles: half as many blocks are enough
+        dim3 g(net_blocks(net, (ntiles + 1) / 2)), b(kNetH64Threads);
+#define DNNMG_B16W(KK, HH, MM) hipLaunchKernelGGL((k_net_b16w<KK, HH, MM>), g, b, 0, s, f, bt, net, ntiles)
+#define DNNMG_B16W_H(KK)                                                                             \
+        if (net.H == 64) { if (net.Hm == 64) DNNMG_B16W(KK, 64, 64); else DNNMG_B16W(KK, 64, 0); }    \
+        else { if (net.Hm == 128) DNNMG_B16W(KK, 128, 128); else DNNMG_B16W(KK, 128, 0); }
         switch (net.K) {
-        case 1: DNNMG_B16P_H(1) break;
-        case 2: DNNMG_B16P_H(2) break;
-        case 3: DNNMG_B16P_H(3) break;
+        case 1: DNNMG_B16W_H(1) break;
+        case 2: DNNMG_B16W_H(2) break;
+        case 3: DNNMG_B16W_H(3) break;
         default: return hipErrorInvalidValue;
         }
-#undef DNNMG_B16P_H
-#undef DNNMG_B16P
+#undef DNNMG_B16W_H
+#undef DNNMG_B16W
         return hipGetLastError();
     }
     if (use_q8p(net)) {
