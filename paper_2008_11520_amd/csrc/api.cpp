@@ -46,6 +46,10 @@ namespace {
 
 struct Sizes {
     int n, nf, nin, nout, P, Fn, Nc;
+    int upitch;   // nodes per row of the u_prev state: NX+1 rounded up to 16, so
+                  // that rows (and the defect/rhs tiles' 32-node runs) start on
+                  // 128-byte lines and tiles do not share lines of it
+    size_t Fu;    // nodes of the u_prev state, (NY+1) upitch
 };
 
 Sizes sizes_of(const dnnmg_config &c)
@@ -58,6 +62,8 @@ Sizes sizes_of(const dnnmg_config &c)
     s.P = c.nx * c.ny;
     s.Fn = (c.nx * s.n + 1) * (c.ny * s.n + 1);
     s.Nc = (c.nx + 1) * (c.ny + 1);
+    s.upitch = (c.nx * s.n + 1 + 15) / 16 * 16;
+    s.Fu = (size_t)s.upitch * (c.ny * s.n + 1);
     return s;
 }
 
@@ -105,7 +111,7 @@ Layout layout_of(const dnnmg_config &c)
     L.geo64 = take(sizeof(double) * 4 * s.P);
     L.feat = take(sizeof(float) * 4 * s.P);
     L.h = take(sizeof(float) * (size_t)s.P * c.H);
-    L.uprev = take(sizeof(float) * 2 * (size_t)s.Fn);
+    L.uprev = take(sizeof(float) * 2 * s.Fu);
     if (c.precision == DNNMG_FP8_E4M3) {
         L.X = take((size_t)s.P * xstride_fp8(s.nin));
         L.sx = take(sizeof(float) * (size_t)s.P);
@@ -455,6 +461,7 @@ FlowArgs flow_args(const dnnmg_ctx *c, const float *v, const float *p)
     f.feat = c->feat();
     f.h = c->h();
     f.uprev = c->uprev();
+    f.upitch = c->s.upitch;
     f.X = c->X();
     f.xfmt = c->cfg.precision;
     f.sx = c->sx();
@@ -507,7 +514,7 @@ int create_common(const dnnmg_config *cfg, const double *cxy, const float *weigh
     const Sizes &s = c->s;
     hipError_t e = hipMemcpyAsync(c->ws + c->L.cxy, cxy, sizeof(double) * 2 * s.Nc, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemsetAsync(c->h(), 0, sizeof(float) * (size_t)s.P * cfg->H, st);
-    if (e == hipSuccess) e = hipMemsetAsync(c->uprev(), 0, sizeof(float) * 2 * (size_t)s.Fn, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->uprev(), 0, sizeof(float) * 2 * s.Fu, st);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + c->L.bad, 0, sizeof(int), st);
     if (e == hipSuccess) e = hipMemsetAsync(c->first_flag(), 1, sizeof(int), st);
     if (e == hipSuccess)
@@ -733,8 +740,10 @@ extern "C" int dnnmg_get_state(dnnmg_ctx *ctx, float *h, float *u, void *stream)
     hipStream_t st = (hipStream_t)stream;
     if (h) HIP_OR_FAIL(hipMemcpyAsync(h, ctx->h(), sizeof(float) * (size_t)ctx->s.P * ctx->cfg.H,
                                       hipMemcpyDeviceToDevice, st));
-    if (u) HIP_OR_FAIL(hipMemcpyAsync(u, ctx->uprev(), sizeof(float) * 2 * (size_t)ctx->s.Fn,
-                                      hipMemcpyDeviceToDevice, st));
+    // (the state's rows are padded to upitch nodes; the caller's are NX+1)
+    const size_t row = sizeof(float) * 2 * (size_t)(ctx->cfg.nx * ctx->s.n + 1);
+    if (u) HIP_OR_FAIL(hipMemcpy2DAsync(u, row, ctx->uprev(), sizeof(float) * 2 * (size_t)ctx->s.upitch, row,
+                                        ctx->cfg.ny * ctx->s.n + 1, hipMemcpyDeviceToDevice, st));
     return DNNMG_OK;
 }
 
@@ -746,8 +755,9 @@ extern "C" int dnnmg_set_state(dnnmg_ctx *ctx, const float *h, const float *u, l
     hipStream_t st = (hipStream_t)stream;
     if (h) HIP_OR_FAIL(hipMemcpyAsync(ctx->h(), h, sizeof(float) * (size_t)ctx->s.P * ctx->cfg.H,
                                       hipMemcpyDeviceToDevice, st));
-    if (u) HIP_OR_FAIL(hipMemcpyAsync(ctx->uprev(), u, sizeof(float) * 2 * (size_t)ctx->s.Fn,
-                                      hipMemcpyDeviceToDevice, st));
+    const size_t row = sizeof(float) * 2 * (size_t)(ctx->cfg.nx * ctx->s.n + 1);
+    if (u) HIP_OR_FAIL(hipMemcpy2DAsync(ctx->uprev(), sizeof(float) * 2 * (size_t)ctx->s.upitch, u, row, row,
+                                        ctx->cfg.ny * ctx->s.n + 1, hipMemcpyDeviceToDevice, st));
     HIP_OR_FAIL(hipMemsetAsync(ctx->first_flag(), steps == 0 ? 1 : 0, sizeof(int), st));
     ctx->steps = steps;
     return DNNMG_OK;

@@ -334,7 +334,7 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
         const int t = tid + i * kThreads;
         const int I = I0 - 1 + t % NN, J = J0 - 1 + t / NN;
         const bool in = t < NN * NN && !first && I >= 0 && I <= NX && J >= 0 && J <= NY;
-        uq[i] = in ? reinterpret_cast<const float2 *>(f.uprev)[(size_t)J * (NX + 1) + I] : make_float2(0.f, 0.f);
+        uq[i] = in ? reinterpret_cast<const float2 *>(f.uprev)[(size_t)J * f.upitch + I] : make_float2(0.f, 0.f);
     }
 
     // 1. coarse-element records.  Every record is formed from indices clamped

@@ -27,7 +27,8 @@ struct FlowArgs {
     const float *feat;     // P x 4
     int *first_flag;       // device: nonzero before the first step (then u_prev := P v)
     float *h;              // P x H
-    float *uprev;          // Fn x 2
+    float *uprev;          // (NY+1) rows of upitch nodes x 2 (the first NX+1 nodes of a row used)
+    int upitch;            // nodes per u_prev row: NX+1 rounded up to 16 (128-byte rows)
     float *X;              // network input, the step writes it: P x nin FP32 or BF16, or for FP8
                            // P rows of xstride(nin) E4M3 codes (zero beyond nin)
     float *sx;             // FP8: per-patch scale of X

@@ -63,8 +63,9 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
     // Addresses are formed from the tile's base (uniform, in scalar
     // registers) plus a 32-bit offset per thread.
     const size_t pt0 = (size_t)pj0 * nx + pi0;  // the tile's first patch
-    const size_t nt0 = (size_t)J0 * (NX + 1) + I0;   // the tile's first node
-    float2 *const ut = reinterpret_cast<float2 *>(f.uprev) + nt0;
+    const size_t nt0 = (size_t)J0 * (NX + 1) + I0;   // the tile's first node (rows of NX+1 nodes)
+    const int up = f.upitch;                          // u_prev rows: upitch nodes
+    float2 *const ut = reinterpret_cast<float2 *>(f.uprev) + (size_t)J0 * up + I0;
     // The step's defect has already read the first-step flag (stream order).
     if (FROM_PATCHES && blk == 0 && tid == 0) *f.first_flag = 0;
 
@@ -227,9 +228,8 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                     const float lx = v00.x + (v01.x - v00.x) * eta, ly = v00.y + (v01.y - v00.y) * eta;
                     const float rx = v10.x + (v11.x - v10.x) * eta, ry = v10.y + (v11.y - v10.y) * eta;
                     const float pvx = lx + (rx - lx) * xi, pvy = ly + (ry - ly) * xi;
-                    const int fo = lj * (NX + 1) + li;
-                    ut[fo] = make_float2(pvx + d.x, pvy + d.y);
-                    if (f.dbar_out) (reinterpret_cast<float2 *>(f.dbar_out) + nt0)[fo] = d;
+                    ut[lj * up + li] = make_float2(pvx + d.x, pvy + d.y);
+                    if (f.dbar_out) (reinterpret_cast<float2 *>(f.dbar_out) + nt0)[lj * (NX + 1) + li] = d;
                 }
             } else {
                 d = (reinterpret_cast<const float2 *>(f.dbar_in) + nt0)[lj * (NX + 1) + li];
@@ -269,8 +269,9 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
             const float lx = v00.x + (v01.x - v00.x) * eta, ly = v00.y + (v01.y - v00.y) * eta;
             const float rx = v10.x + (v11.x - v10.x) * eta, ry = v10.y + (v11.y - v10.y) * eta;
             const float dx = rx - lx, dy = ry - ly;
-            float2 *const urow = ut + (pb * n + b) * (NX + 1) + pa * n;
-            float2 *const drow = f.dbar_out ? reinterpret_cast<float2 *>(f.dbar_out) + (urow - reinterpret_cast<float2 *>(f.uprev)) : nullptr;
+            float2 *const urow = ut + (pb * n + b) * up + pa * n;
+            float2 *const drow = f.dbar_out ? reinterpret_cast<float2 *>(f.dbar_out) + nt0 + (pb * n + b) * (NX + 1) + pa * n
+                                            : nullptr;
 #pragma unroll
             for (int a = 0; a < n; ++a) {
                 const bool lft = a == 0 && pi > 0;
