@@ -607,21 +607,53 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
     constexpr int HPT = (HCH + kNetH64Threads - 1) / kNetH64Threads;
     bf8 xrA[XPT], xrB[XPT];
     f4 hrA[HPT], hrB[HPT];
-    auto load_tile = [&](int tile, bf8 (&xr)[XPT], f4 (&hr)[HPT]) {
+    // A row tile's buffers.  The fields are read in two branches: a pointer
+    // that may point at either the kernel argument or the batch table would
+    // make them flat loads (and the lambdas below would reach the argument
+    // through a generic pointer).
+    typedef __attribute__((address_space(1))) float gfloat;
+    struct Rows {
+        gptr<bf8> X;
+        gfloat *h, *dp;
+        int nrows;
+    };
+    const void *const s_X = single.X;
+    float *const s_h = single.h, *const s_dp = single.dpatch;
+    const int s_P = single.nx * single.ny;
+    auto rows_of = [&](int tile) -> Rows {
         int blk = tile;
-        const FlowArgs *fq = bt ? batch_flow(bt, kKindNet, blk) : &single;
-        const int P = fq->nx * fq->ny, row0 = blk * 64, nrows = min(64, P - row0);
-        const bf8 *xg = reinterpret_cast<const bf8 *>(reinterpret_cast<const __bf16 *>(fq->X) + (size_t)row0 * nin);
-        const f4 *hgv = reinterpret_cast<const f4 *>(fq->h + (size_t)row0 * H);
+        const void *X;
+        float *h, *dp;
+        int P;
+        if (bt) {
+            const FlowArgs &F = *batch_flow(bt, kKindNet, blk);
+            X = F.X; h = F.h; dp = F.dpatch; P = F.nx * F.ny;
+        } else {
+            X = s_X; h = s_h; dp = s_dp; P = s_P;
+        }
+        const int row0 = blk * 64;
+        Rows r;
+        r.X = (gptr<bf8>)(reinterpret_cast<const __bf16 *>(X) + (size_t)row0 * nin);
+        r.h = (gfloat *)(h + (size_t)row0 * H);
+        r.dp = (gfloat *)(dp + (size_t)row0 * nout);
+        r.nrows = min(64, P - row0);
+        return r;
+    };
+    // (index math from tile_thread(): recomputed in each tile instead of
+    // hoisted out of the tile loop and held in registers)
+    typedef __attribute__((address_space(1))) const f4 gf4;
+    auto load_tile = [&](int tile, bf8 (&xr)[XPT], f4 (&hr)[HPT]) {
+        const Rows rw = rows_of(tile);
+        const int t0 = tile_thread();
 #pragma unroll
         for (int i = 0; i < XPT; ++i) {
-            const int c = tid + i * kNetH64Threads;
-            xr[i] = (c < XCH && c / (nin / 8) < nrows) ? xg[c] : bf8{};
+            const int c = t0 + i * kNetH64Threads;
+            xr[i] = (c < XCH && c / (nin / 8) < rw.nrows) ? rw.X[c] : bf8{};
         }
 #pragma unroll
         for (int i = 0; i < HPT; ++i) {
-            const int c = tid + i * kNetH64Threads;
-            hr[i] = (c < HCH && c / (H / 4) < nrows) ? hgv[c] : f4{0.f, 0.f, 0.f, 0.f};
+            const int c = t0 + i * kNetH64Threads;
+            hr[i] = (c < HCH && c / (H / 4) < rw.nrows) ? ((gf4 *)rw.h)[c] : f4{0.f, 0.f, 0.f, 0.f};
         }
     };
     // the k-padding columns of [x | h] stay zero for the whole launch
@@ -634,23 +666,21 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
     // one 64-patch tile: stage the prefetched registers, refill them with
     // tile `next`, compute
     auto process = [&](int tile, bf8 (&xr)[XPT], f4 (&hr)[HPT], int next) {
-        int blk = tile;
-        const FlowArgs ff = bt ? *batch_flow(bt, kKindNet, blk) : single;
-        const int P = ff.nx * ff.ny;
-        const int row0 = blk * 64;
-        const int nrows = min(64, P - row0);
-        float *hg = ff.h + (size_t)row0 * H;
-        float *dp = ff.dpatch + (size_t)row0 * nout;
+        const Rows rw = rows_of(tile);
+        const int nrows = rw.nrows;
+        gfloat *const hg = rw.h;
+        gfloat *const dp = rw.dp;
 
         __syncthreads();   // the previous tile's readers of LDS are done
+        const int t1 = tile_thread();
 #pragma unroll
         for (int i = 0; i < XPT; ++i) {
-            const int c = tid + i * kNetH64Threads;
+            const int c = t1 + i * kNetH64Threads;
             if (c < XCH) *reinterpret_cast<bf8 *>(&sA[(c / (nin / 8)) * LDA + 8 * (c % (nin / 8))]) = xr[i];
         }
 #pragma unroll
         for (int i = 0; i < HPT; ++i) {
-            const int c = tid + i * kNetH64Threads;
+            const int c = t1 + i * kNetH64Threads;
             if (c < HCH) {
                 const int r = c / (H / 4), k = 4 * (c % (H / 4));
                 *reinterpret_cast<f4 *>(&sH[r * LDS32 + k]) = hr[i];
@@ -713,7 +743,7 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
                 hn[e] = z * hold[q][e] + (1.0f - z) * fast_tanh(ah[q][e] + au[e]);
                 hb[e] = (__bf16)hn[e];
             }
-            if (r < nrows) *reinterpret_cast<f4 *>(hg + (size_t)r * H + ucol) = hn;
+            if (r < nrows) *(__attribute__((address_space(1))) f4 *)(hg + r * H + ucol) = hn;
             *reinterpret_cast<bf4 *>(&sHp[r * LDH + ucol]) = hb;
         }
         __syncthreads();
@@ -750,9 +780,11 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
                 }
                 // nout is even: the pairs (ucol, ucol+1), (ucol+2, ucol+3) are inside or outside together
                 if (r < nrows) {
-                    float *o = dp + (size_t)r * nout + ucol;
-                    if (ucol < nout) *reinterpret_cast<float2 *>(o) = make_float2(acc[0], acc[1]);
-                    if (ucol + 2 < nout) *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[2], acc[3]);
+                    typedef float v2 __attribute__((ext_vector_type(2)));
+                    typedef __attribute__((address_space(1))) v2 gv2;
+                    gfloat *o = dp + r * nout + ucol;
+                    if (ucol < nout) *(gv2 *)o = v2{acc[0], acc[1]};
+                    if (ucol + 2 < nout) *(gv2 *)(o + 2) = v2{acc[2], acc[3]};
                 }
             }
         }
@@ -820,39 +852,72 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_q8p(FlowArgs single, 
     for (int kc = 0; kc < HC; ++kc) w2[kc] = B2[(ht * HC + kc) * 64 + lane];
     for (int t = tid; t < W3N; t += kNetH64Threads) sW3[t] = B3[t];
     for (int t = tid; t < W4N; t += kNetH64Threads) sW4[t] = HM > 0 ? B4[t] : 0;
-    float s1z[4], s1r[4], s1h[4], s2u[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        s1z[e] = net.s1[ucol + e];
-        s1r[e] = net.s1[H + ucol + e];
-        s1h[e] = net.s1[2 * H + ucol + e];
-        s2u[e] = net.s2[ucol + e];
-    }
+    // per-unit weight scales: read where they are used (global, cached)
+    const gptr<float> S1 = pinned<float>(net.s1), S2 = pinned<float>(net.s2);
 
-    // next-tile prefetch into registers: network input codes, FP32 state, x scales
+    // A row tile's buffers.  The fields are read in two branches: a pointer
+    // that may point at either the kernel argument or the batch table would
+    // make them flat loads (and the lambdas below would reach the argument
+    // through a generic pointer).
+    typedef __attribute__((address_space(1))) float gfloat;
+    struct Rows {
+        gptr<uint8_t> X;
+        gptr<float> sx;
+        gfloat *h, *dp;
+        int nrows;
+    };
+    const void *const s_X = single.X;
+    const float *const s_sx = single.sx;
+    float *const s_h = single.h, *const s_dp = single.dpatch;
+    const int s_P = single.nx * single.ny;
+    auto rows_of = [&](int tile) -> Rows {
+        int blk = tile;
+        const void *X;
+        const float *sxp;
+        float *h, *dp;
+        int P;
+        if (bt) {
+            const FlowArgs &F = *batch_flow(bt, kKindNet, blk);
+            X = F.X; sxp = F.sx; h = F.h; dp = F.dpatch; P = F.nx * F.ny;
+        } else {
+            X = s_X; sxp = s_sx; h = s_h; dp = s_dp; P = s_P;
+        }
+        const int row0 = blk * 64;
+        Rows r;
+        r.X = (gptr<uint8_t>)(reinterpret_cast<const uint8_t *>(X) + (size_t)row0 * XS);
+        r.sx = (gptr<float>)(sxp + row0);
+        r.h = (gfloat *)(h + (size_t)row0 * H);
+        r.dp = (gfloat *)(dp + (size_t)row0 * nout);
+        r.nrows = min(64, P - row0);
+        return r;
+    };
+
+    // next-tile prefetch into registers: network input codes, FP32 state, x
+    // scales (index math from tile_thread(): recomputed in each tile instead
+    // of hoisted out of the tile loop and held in registers)
     constexpr int XCH = 64 * XS / 16, HCH = 64 * H / 4;
     constexpr int XPT = (XCH + kNetH64Threads - 1) / kNetH64Threads;
     constexpr int HPT = (HCH + kNetH64Threads - 1) / kNetH64Threads;
-    uint4 xr[XPT];
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(1))) const u4 gu4;
+    typedef __attribute__((address_space(1))) const f4 gf4;
+    u4 xr[XPT];
     f4 hr[HPT];
     float sxr = 1.0f;
     auto load_tile = [&](int tile) {
-        int blk = tile;
-        const FlowArgs *fq = bt ? batch_flow(bt, kKindNet, blk) : &single;
-        const int P = fq->nx * fq->ny, row0 = blk * 64, nrows = min(64, P - row0);
-        const uint4 *xg = reinterpret_cast<const uint4 *>(reinterpret_cast<const uint8_t *>(fq->X) + (size_t)row0 * XS);
-        const f4 *hgv = reinterpret_cast<const f4 *>(fq->h + (size_t)row0 * H);
+        const Rows rw = rows_of(tile);
+        const int t0 = tile_thread();
 #pragma unroll
         for (int i = 0; i < XPT; ++i) {
-            const int c = tid + i * kNetH64Threads;
-            xr[i] = (c < XCH && c / (XS / 16) < nrows) ? xg[c] : make_uint4(0u, 0u, 0u, 0u);
+            const int c = t0 + i * kNetH64Threads;
+            xr[i] = (c < XCH && c / (XS / 16) < rw.nrows) ? ((gu4 *)rw.X)[c] : u4{0u, 0u, 0u, 0u};
         }
 #pragma unroll
         for (int i = 0; i < HPT; ++i) {
-            const int c = tid + i * kNetH64Threads;
-            hr[i] = (c < HCH && c / (H / 4) < nrows) ? hgv[c] : f4{0.f, 0.f, 0.f, 0.f};
+            const int c = t0 + i * kNetH64Threads;
+            hr[i] = (c < HCH && c / (H / 4) < rw.nrows) ? ((gf4 *)rw.h)[c] : f4{0.f, 0.f, 0.f, 0.f};
         }
-        sxr = tid < nrows ? fq->sx[row0 + tid] : 1.0f;
+        sxr = t0 < rw.nrows ? rw.sx[t0] : 1.0f;
     };
     if (blockIdx.x < ntiles) load_tile(blockIdx.x);
 
@@ -871,26 +936,24 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_q8p(FlowArgs single, 
     };
 
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        int blk = tile;
-        const FlowArgs &ff = bt ? *batch_flow(bt, kKindNet, blk) : single;
-        const int P = ff.nx * ff.ny;
-        const int row0 = blk * 64;
-        const int nrows = min(64, P - row0);
-        float *hg = ff.h + (size_t)row0 * H;
-        float *dp = ff.dpatch + (size_t)row0 * nout;
+        const Rows rw = rows_of(tile);
+        const int nrows = rw.nrows;
+        gfloat *const hg = rw.h;
+        gfloat *const dp = rw.dp;
 
         __syncthreads();   // the previous tile's readers of LDS are done
+        const int t1 = tile_thread();
 #pragma unroll
         for (int i = 0; i < XPT; ++i) {
-            const int c = tid + i * kNetH64Threads;
-            if (c < XCH) *reinterpret_cast<uint4 *>(&sX[(c / (XS / 16)) * LDX + 16 * (c % (XS / 16))]) = xr[i];
+            const int c = t1 + i * kNetH64Threads;
+            if (c < XCH) *reinterpret_cast<u4 *>(&sX[(c / (XS / 16)) * LDX + 16 * (c % (XS / 16))]) = xr[i];
         }
         // the state: FP32 rows and their codes; the H / 4 consecutive threads
         // that hold one row's pieces reduce its maximum by shuffles
         static_assert(HCH % kNetH64Threads == 0 && (H / 4) <= 64, "whole rows per pass");
 #pragma unroll
         for (int i = 0; i < HPT; ++i) {
-            const int c = tid + i * kNetH64Threads;
+            const int c = t1 + i * kNetH64Threads;
             const int row = c / (H / 4), k = 4 * (c % (H / 4));
             *reinterpret_cast<f4 *>(&sH[row * LDS32 + k]) = hr[i];
             float m = fmaxf(fmaxf(fabsf(hr[i].x), fabsf(hr[i].y)), fmaxf(fabsf(hr[i].z), fabsf(hr[i].w)));
@@ -902,7 +965,7 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_q8p(FlowArgs single, 
             *reinterpret_cast<uint32_t *>(&sQ[row * LDQ + k]) =
                 pack4_e4m3(hr[i].x * r, hr[i].y * r, hr[i].z * r, hr[i].w * r);
         }
-        if (tid < 64) sSx[tid] = sxr;
+        if (t1 < 64) sSx[t1] = sxr;
         if (tile + (int)gridDim.x < ntiles) load_tile(tile + gridDim.x);
         __syncthreads();
 
@@ -942,9 +1005,9 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_q8p(FlowArgs single, 
                 float m = 0.0f;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    az[q][e] = sigmoid(az[q][e] * sh[q] * s1z[e]);
-                    ar[q][e] = sigmoid(ar[q][e] * sh[q] * s1r[e]) * hold[q][e];   // r*h
-                    ah[q][e] *= sx[q] * s1h[e];
+                    az[q][e] = sigmoid(az[q][e] * sh[q] * S1[ucol + e]);
+                    ar[q][e] = sigmoid(ar[q][e] * sh[q] * S1[H + ucol + e]) * hold[q][e];   // r*h
+                    ah[q][e] *= sx[q] * S1[2 * H + ucol + e];
                     m = fmaxf(m, fabsf(ar[q][e]));
                 }
                 wave_max(m, row);
@@ -972,11 +1035,11 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_q8p(FlowArgs single, 
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const float z = az[q][e];
-                    const float hn = z * hold[q][e] + (1.0f - z) * fast_tanh(ah[q][e] + au[e] * srh[q] * s2u[e]);
+                    const float hn = z * hold[q][e] + (1.0f - z) * fast_tanh(ah[q][e] + au[e] * srh[q] * S2[ucol + e]);
                     az[q][e] = hn;
                     m = fmaxf(m, fabsf(hn));
                 }
-                if (row < nrows) *reinterpret_cast<f4 *>(hg + (size_t)row * H + ucol) = az[q];
+                if (row < nrows) *(__attribute__((address_space(1))) f4 *)(hg + row * H + ucol) = az[q];
                 wave_max(m, row);
             }
             __syncthreads();
@@ -1046,9 +1109,11 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_q8p(FlowArgs single, 
                         acc = mma_fp8(acc, Wo[(ot * CO + kc) * 64 + lane], mma_fp8_operand(&src[row * LDQ + kc * KC + lq * KQ]));
                     // nout is even: the pairs (oc, oc+1), (oc+2, oc+3) are inside or outside together
                     if (row < nrows) {
-                        float *o = dp + (size_t)row * nout + oc;
-                        if (oc < nout) *reinterpret_cast<float2 *>(o) = make_float2(acc[0] * sin_[q] * so4[0], acc[1] * sin_[q] * so4[1]);
-                        if (oc + 2 < nout) *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[2] * sin_[q] * so4[2], acc[3] * sin_[q] * so4[3]);
+                        typedef float v2 __attribute__((ext_vector_type(2)));
+                        typedef __attribute__((address_space(1))) v2 gv2;
+                        gfloat *o = dp + row * nout + oc;
+                        if (oc < nout) *(gv2 *)o = v2{acc[0] * sin_[q] * so4[0], acc[1] * sin_[q] * so4[1]};
+                        if (oc + 2 < nout) *(gv2 *)(o + 2) = v2{acc[2] * sin_[q] * so4[2], acc[3] * sin_[q] * so4[3]};
                     }
                 }
             }
