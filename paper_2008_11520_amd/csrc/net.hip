@@ -49,6 +49,9 @@ template <> struct Op<0> {
     {
         return *reinterpret_cast<const f4 *>(reinterpret_cast<const float *>(X) + off);
     }
+    // The same through global address-space pointers.
+    __device__ static inline Frag load_f32(gptr<float> p) { return *(gptr<f4>)p; }
+    __device__ static inline Frag load_x(gptr<T> X, size_t off) { return *(gptr<f4>)(X + off); }
 };
 
 // BF16 operands: one 16x16x32 MFMA per 32-wide k-chunk.
@@ -74,6 +77,16 @@ template <> struct Op<1> {
     {
         return *reinterpret_cast<const bf8 *>(reinterpret_cast<const __bf16 *>(X) + off);
     }
+    // The same through global address-space pointers.
+    __device__ static inline Frag load_f32(gptr<float> p)
+    {
+        f4 u = *(gptr<f4>)p, w = *(gptr<f4>)(p + 4);
+        Frag r;
+        r[0] = (__bf16)u.x; r[1] = (__bf16)u.y; r[2] = (__bf16)u.z; r[3] = (__bf16)u.w;
+        r[4] = (__bf16)w.x; r[5] = (__bf16)w.y; r[6] = (__bf16)w.z; r[7] = (__bf16)w.w;
+        return r;
+    }
+    __device__ static inline Frag load_x(gptr<T> X, size_t off) { return *(gptr<bf8>)(X + off); }
 };
 
 
@@ -104,9 +117,18 @@ __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net
 
     const int P = f.nx * f.ny;
     const int nin = net.nin, nout = net.nout, Hm = net.Hm, kc1 = net.kc1;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // (tile_thread(): in the batched tile loop the index math is redone per
+    // tile instead of hoisted out of the loop and held in registers)
+    const int tid = tile_thread();
+    const int wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lq = lane >> 4;
     const int rg = wave & 1, hg = wave >> 1;
+    // the flow's buffers through global address-space pointers: global, not
+    // flat, memory instructions where the pointers come from the batch table
+    typedef __attribute__((address_space(1))) float gfloat;
+    const gptr<T> Xg = (gptr<T>)f.X;
+    gfloat *const hG = (gfloat *)f.h;
+    gfloat *const dG = (gfloat *)f.dpatch;
     const int r0 = 32 * rg;                         // first tile-local row of this wave
     const int rbase = blk * kNetRows + r0;          // first patch row of this wave
 
@@ -127,8 +149,8 @@ __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int arow = rbase + 16 * q + li;      // row this lane supplies operand values for
-            if (arow < P && k0 < nin) a[q] = O::load_x(f.X, (size_t)arow * nin + k0);
-            else if (arow < P && k0 < nin + H) a[q] = O::load_f32(f.h + (size_t)arow * H + (k0 - nin));
+            if (arow < P && k0 < nin) a[q] = O::load_x(Xg, (size_t)arow * nin + k0);
+            else if (arow < P && k0 < nin + H) a[q] = O::load_f32((gptr<float>)(hG + (size_t)arow * H + (k0 - nin)));
             else {
 #pragma unroll
                 for (int e = 0; e < KQ; ++e) a[q][e] = O::cvt(0.f);
@@ -159,7 +181,7 @@ __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int lr = r0 + 16 * q + 4 * lq + e, row = blk * kNetRows + lr, k = 16 * (hg * HW + tw) + li;
-                const float h0 = row < P ? f.h[(size_t)row * H + k] : 0.f;
+                const float h0 = row < P ? hG[(size_t)row * H + k] : 0.f;
                 hold[tw][q][e] = h0;
                 az[tw][q][e] = sigmoid(az[tw][q][e]);
                 const float r = sigmoid(ar[tw][q][e]);
@@ -195,7 +217,7 @@ __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net
                 const float z = az[tw][q][e];
                 const float hh = fast_tanh(ah[tw][q][e] + au[tw][q][e]);
                 const float hn = z * hold[tw][q][e] + (1.0f - z) * hh;
-                if (row < P) f.h[(size_t)row * H + k] = hn;
+                if (row < P) hG[(size_t)row * H + k] = hn;
                 sHp[lr * LDH + k] = O::cvt(hn);
             }
     __syncthreads();
@@ -215,7 +237,7 @@ __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = rbase + 16 * q + 4 * lq + e, o = 16 * ot + li;
-                if (row < P && o < nout) f.dpatch[(size_t)row * nout + o] = acc[q][e];
+                if (row < P && o < nout) dG[(size_t)row * nout + o] = acc[q][e];
             }
     };
     if constexpr (HMC > 0) {
