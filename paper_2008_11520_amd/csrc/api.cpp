@@ -790,7 +790,9 @@ extern "C" int dnnmg_batch_create(int max_flows, dnnmg_batch **out)
         delete b;
         return fail(DNNMG_EDEVICE, "cannot query the device's compute units");
     }
-    b->cap = 4 * ncu;
+    // eight blocks per CU: room for every batched kernel's resident
+    // workgroups (up to six per CU for the rhs), the rest wait their turn
+    b->cap = 8 * ncu;
     bool ok = hipMalloc((void **)&b->dev, sizeof(BatchTable)) == hipSuccess;
     for (int i = 0; ok && i < 2; ++i)
         ok = hipHostMalloc((void **)&b->host[i], sizeof(BatchTable), hipHostMallocDefault) == hipSuccess &&
