@@ -92,9 +92,13 @@ class Server:
         self.batch = Batch(max_flows)
 
     def warmup(self):
-        """One tick of the model's own one-patch context: captures the batch
-        graph (and loads the kernels) before any request is timed.  The shared
-        weights are not changed by a step."""
+        """Before any request is timed: one tick of the model's own one-patch
+        context (captures the batch graph, loads the kernels), then one small
+        request taken through admission, a tick beside the model's context and
+        retirement, so that the first use of every host and device path of a
+        request (context creation, the kernels that evaluate its field ring)
+        falls outside the measurement.  The shared weights are not changed by
+        a step."""
         import torch
         nc = self.model.s["Nc"]
         with torch.cuda.stream(self.stream):
@@ -104,6 +108,13 @@ class Server:
             self.batch.prepare([self.model], [v], [p], None, [b], stream=self.stream)
             self.batch.launch(graph=self.use_graph, stream=self.stream)
         self.stream.synchronize()
+        a = self.admit(dict(id=-1, nx=4, ny=2, steps=1, field_seed=0), 0.0)
+        with torch.cuda.stream(self.stream):
+            self.batch.prepare([self.model, a.ctx], [v, a.vring[0]], [p, a.pring[0]], None, [b, a.b_out],
+                               stream=self.stream)
+            self.batch.launch(graph=self.use_graph, stream=self.stream)
+        self.stream.synchronize()
+        self.retire(a)
 
     def flow_bytes(self, nx, ny):
         cfg = make_config(nx, ny, self.K, self.H, self.Hm, self.dt, self.nu, self.precision, synth.DIR_CHANNEL)
