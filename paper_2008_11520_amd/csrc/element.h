@@ -180,6 +180,13 @@ __host__ __device__ inline void strip_residual(const CoarseRec &r, int a, int b0
         //   = det w_c - v_x (det dv_c/dx + [c = x] det / dt) - v_y (det dv_c/dy + [c = y] det / dt)
         const float Bxx = Bx0x + Bx1x * xi + idt * A, Byx = By0x + By1x * xi;
         const float Bxy = Bx0y + Bx1y * xi, Byy = By0y + By1y * xi + idt * A;
+        // with v_c = a_c + vt_c eta and det d(v_c)/dx_k = B + C eta on this
+        // abscissa, v_x (det dv_c/dx + ...) + v_y (det dv_c/dy + ...) is a
+        // quadratic in eta: its coefficients once per xi, two FMAs per point
+        const float q0x = ax * Bxx + ay * Byx, q2x = vtx * Cxx2 + vty * Cyx;
+        const float q1x = ax * Cxx2 + vtx * Bxx + ay * Cyx + vty * Byx;
+        const float q0y = ax * Bxy + ay * Byy, q2y = vtx * Cxy + vty * Cyy2;
+        const float q1y = ax * Cxy + vtx * Bxy + ay * Cyy2 + vty * Byy;
         const float g11 = nu * (xt * xt + yt * yt);
         const float G0 = -(nexx * xt + nexy * yt), G1 = -(nexyx * xt + nexyy * yt);
         const float E0x = g11 * r.V1x + G0 * vtx, E1x = g11 * r.V3x + G1 * vtx;
@@ -208,13 +215,11 @@ __host__ __device__ inline void strip_residual(const CoarseRec &r, int a, int b0
                 const float det = A + d2 * eta;
                 const float inv = Rcp::f(det);
                 const float pq = ap + bp * eta;
-                const float vxq = ax + vtx * eta, vyq = ay + vty * eta;
-                const float dxx = Bxx + Cxx2 * eta, dxy = Byx + Cyx * eta;
-                const float dyx = Bxy + Cxy * eta, dyy = Byy + Cyy2 * eta;
+                const float cvx = q0x + (q1x + q2x * eta) * eta, cvy = q0y + (q1y + q2y * eta) * eta;
                 const float wxq = wxl + (wxu - wxl) * gj;
                 const float wyq = wyl + (wyu - wyl) * gj;
-                m[0][j] = det * wxq - (vxq * dxx + vyq * dxy);
-                m[1][j] = det * wyq - (vxq * dyx + vyq * dyy);
+                m[0][j] = det * wxq - cvx;
+                m[1][j] = det * wyq - cvy;
                 const float T1x = E0x + E1x * eta, T1y = E0y + E1y * eta;
                 const float T2x = F0x + (F1x + F2x * eta) * eta, T2y = F0y + (F1y + F2y * eta) * eta;
                 Qs[0][j] = pq * yt - inv * T1x;
