@@ -94,8 +94,6 @@ hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int nblocks, cons
                       hipStream_t s);
 // Blocks of the network launch (persistent kernels use fewer than row tiles).
 int net_blocks(const NetArgs &net, int row_tiles);
-hipError_t net_set_attributes(int prec, int H);
-size_t net_lds_bytes(const NetArgs &net);
 hipError_t launch_rhs(const FlowArgs &f, const BatchTable *bt, int nblocks, int K,
                       const RhsTables &tab, int from_patches, hipStream_t s);
 hipError_t launch_gather(const FlowArgs &f, const BatchTable *bt, int nblocks, hipStream_t s);

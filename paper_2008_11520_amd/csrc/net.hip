@@ -1408,7 +1408,6 @@ static bool use_b16w(const NetArgs &net)
 }
 static bool persistent(const NetArgs &net) { return use_h64(net) || use_q8p(net) || use_b16w(net); }
 
-bool net_needs_x(int prec, int K, int H, int Hm) { return !use_h64(prec, K, H, Hm); }
 
 int net_blocks(const NetArgs &net, int row_tiles)
 {
@@ -1511,7 +1510,5 @@ hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int ntiles, const
     return hipErrorInvalidValue;
 }
 
-hipError_t net_set_attributes(int, int) { return hipSuccess; }
-size_t net_lds_bytes(const NetArgs &) { return 0; }
 
 }  // namespace dnnmg
