@@ -326,11 +326,18 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
         const double2 g01 = s_g[2 * pl], g2x = s_g[2 * pl + 1];
         const double d0 = g01.x, d1 = g01.y, d2 = g2x.x;
         const int bi = (pl % TP) * n, bj = (pl / TP) * n;
-        // x pass of node row b, then its terms of the y pass for both cy (the
-        // y sums run over b in order, as a pass over stored rows would)
+        // x pass of node row b, then its terms of the y pass for both cy.  With
+        // 8 or more patches per tile row (K <= 2) the two patch rows one wave
+        // holds start their walk over the node rows one row apart, so that at
+        // each step their reads fall in different LDS banks (patch rows lie a
+        // multiple of 64 banks apart).  (At K = 3 the rotation's run-time row
+        // index cost more than the conflicts it removed.)
+        constexpr int RR = TP >= 8 ? 2 : 1;
+        const int rot = (pl / TP) % RR;
         double S[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
 #pragma unroll
-        for (int b = 0; b <= n; ++b) {
+        for (int b0 = 0; b0 <= n; ++b0) {
+            const int b = b0 + rot > n ? b0 + rot - (n + 1) : b0 + rot;
             double s0 = 0.0, s1 = 0.0;
 #pragma unroll
             for (int a = 0; a <= n; ++a) {
