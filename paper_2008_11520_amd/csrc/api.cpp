@@ -306,20 +306,28 @@ int build_weights(const dnnmg_config &c, const float *w, hipStream_t st, Weights
         }
         pack_matrix(buf, A, rows, cols, tiles, chunks, prec);
     };
+    // BF16: gate rows pre-multiplied by -log2(e) (z, r) and 2 log2(e) (the
+    // candidate's W_h and U_h), so that the kernels' exponentials are 2^x
+    const bool l2 = prec == DNNMG_BF16;
+    const float gs[3] = {l2 ? -kLog2e : 1.0f, l2 ? -kLog2e : 1.0f, l2 ? 2.0f * kLog2e : 1.0f};
     size_t off[4];
     off[0] = 0;
     for (int g = 0; g < 3; ++g) {   // [W_g | U_g], the U_h block is applied in phase 2
         std::vector<float> A((size_t)H * (xw + H), 0.0f);
         for (int j = 0; j < H; ++j) {
-            for (int k = 0; k < nin; ++k) A[(size_t)j * (xw + H) + k] = Wg[g][(size_t)j * nin + k];
+            for (int k = 0; k < nin; ++k) A[(size_t)j * (xw + H) + k] = gs[g] * Wg[g][(size_t)j * nin + k];
             if (g < 2)
-                for (int k = 0; k < H; ++k) A[(size_t)j * (xw + H) + xw + k] = Ug[g][(size_t)j * H + k];
+                for (int k = 0; k < H; ++k) A[(size_t)j * (xw + H) + xw + k] = gs[g] * Ug[g][(size_t)j * H + k];
         }
         pack(A, H, xw + H, HT, kc1, 0);
     }
     buf.resize(align256(buf.size()));
     off[1] = buf.size();
-    pack(std::vector<float>(Ug[2], Ug[2] + (size_t)H * H), H, H, HT, H / KC, 1);
+    {
+        std::vector<float> Uh(Ug[2], Ug[2] + (size_t)H * H);
+        for (float &x : Uh) x *= gs[2];
+        pack(Uh, H, H, HT, H / KC, 1);
+    }
     buf.resize(align256(buf.size()));
     off[2] = buf.size();
     if (Hm > 0) {

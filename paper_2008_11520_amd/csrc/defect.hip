@@ -217,8 +217,8 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
         bf4 rh;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            az[q][e] = sigmoid(az[q][e]);
-            rh[e] = (__bf16)(sigmoid(ar[q][e]) * hold[q][e]);
+            az[q][e] = sigmoid_l2(az[q][e]);
+            rh[e] = (__bf16)(sigmoid_l2(ar[q][e]) * hold[q][e]);
         }
         *reinterpret_cast<bf4 *>(&sR[r * LDH + ucol]) = rh;
     }
@@ -237,7 +237,7 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const float z = az[q][e];
-            hn[e] = z * hold[q][e] + (1.0f - z) * fast_tanh(ah[q][e] + au[e]);
+            hn[e] = z * hold[q][e] + (1.0f - z) * tanh_l2(ah[q][e] + au[e]);
             hb[e] = (__bf16)hn[e];
         }
         if (valid(r)) *reinterpret_cast<f4 *>(f.h + patch(r) * H + ucol) = hn;

@@ -14,6 +14,12 @@ typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 // state update h' = z h + (1 - z) tanh(.) needs.
 __device__ inline float sigmoid(float t) { return __builtin_amdgcn_rcpf(1.0f + __expf(-t)); }
 __device__ inline float fast_tanh(float t) { return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * t)); }
+// The same on pre-activations that the packed BF16 weights have already
+// multiplied by -log2(e) (the gates z and r, logistic) or by 2 log2(e) (the
+// candidate state, tanh): the exponential is then the hardware's 2^x, with no
+// scaling multiply.
+__device__ inline float sigmoid_l2(float t) { return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t)); }
+__device__ inline float tanh_l2(float t) { return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t)); }
 
 // The thread's index in its workgroup, opaque to the optimiser.  The batched
 // kernels loop over tiles; with the plain index the compiler hoists every

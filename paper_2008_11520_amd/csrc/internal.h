@@ -74,6 +74,9 @@ struct BatchTable {
 __host__ __device__ constexpr int xstride_fp8(int nin) { return (nin + 31) / 32 * 32; }
 // Smallest row maximum a scale is computed from (keeps 448 / m finite).
 constexpr float kFp8MinMax = 448.0f * 0x1p-64f;
+// BF16 gate weights are packed pre-multiplied by -log2(e) (z, r) and
+// 2 log2(e) (W_h, U_h): the kernels then form the GRU's exponentials as 2^x.
+constexpr float kLog2e = 1.44269504088896340736f;
 
 
 // Blocks each kernel kind needs for one flow.

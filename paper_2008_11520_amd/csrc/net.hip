@@ -183,8 +183,9 @@ __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net
                 const int lr = r0 + 16 * q + 4 * lq + e, row = blk * kNetRows + lr, k = 16 * (hg * HW + tw) + li;
                 const float h0 = row < P ? hG[(size_t)row * H + k] : 0.f;
                 hold[tw][q][e] = h0;
-                az[tw][q][e] = sigmoid(az[tw][q][e]);
-                const float r = sigmoid(ar[tw][q][e]);
+                // (BF16 weights come pre-multiplied for 2^x, see sigmoid_l2)
+                az[tw][q][e] = PREC == 1 ? sigmoid_l2(az[tw][q][e]) : sigmoid(az[tw][q][e]);
+                const float r = PREC == 1 ? sigmoid_l2(ar[tw][q][e]) : sigmoid(ar[tw][q][e]);
                 sR[lr * LDH + k] = O::cvt(r * h0);
             }
     __syncthreads();
@@ -215,7 +216,7 @@ __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net
             for (int e = 0; e < 4; ++e) {
                 const int lr = r0 + 16 * q + 4 * lq + e, row = blk * kNetRows + lr, k = 16 * (hg * HW + tw) + li;
                 const float z = az[tw][q][e];
-                const float hh = fast_tanh(ah[tw][q][e] + au[tw][q][e]);
+                const float hh = PREC == 1 ? tanh_l2(ah[tw][q][e] + au[tw][q][e]) : fast_tanh(ah[tw][q][e] + au[tw][q][e]);
                 const float hn = z * hold[tw][q][e] + (1.0f - z) * hh;
                 if (row < P) hG[(size_t)row * H + k] = hn;
                 sHp[lr * LDH + k] = O::cvt(hn);
@@ -740,8 +741,8 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
             bf4 rh;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                az[q][e] = sigmoid(az[q][e]);
-                rh[e] = (__bf16)(sigmoid(ar[q][e]) * hold[q][e]);
+                az[q][e] = sigmoid_l2(az[q][e]);
+                rh[e] = (__bf16)(sigmoid_l2(ar[q][e]) * hold[q][e]);
             }
             *reinterpret_cast<bf4 *>(&sR[r * LDH + ucol]) = rh;
         }
@@ -762,7 +763,7 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float z = az[q][e];
-                hn[e] = z * hold[q][e] + (1.0f - z) * fast_tanh(ah[q][e] + au[e]);
+                hn[e] = z * hold[q][e] + (1.0f - z) * tanh_l2(ah[q][e] + au[e]);
                 hb[e] = (__bf16)hn[e];
             }
             if (r < nrows) *(__attribute__((address_space(1))) f4 *)(hg + r * H + ucol) = hn;
@@ -1311,8 +1312,8 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
             bf4 rh;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                az[q][e] = sigmoid(az[q][e]);
-                rh[e] = (__bf16)(sigmoid(ar[q][e]) * hold[q][e]);
+                az[q][e] = sigmoid_l2(az[q][e]);
+                rh[e] = (__bf16)(sigmoid_l2(ar[q][e]) * hold[q][e]);
             }
             *reinterpret_cast<bf4 *>(&sR[r * LDH + ucol]) = rh;
         }
@@ -1336,7 +1337,7 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float z = az[q][e];
-                hn[e] = z * hold[q][e] + (1.0f - z) * fast_tanh(ah[q][e] + au[e]);
+                hn[e] = z * hold[q][e] + (1.0f - z) * tanh_l2(ah[q][e] + au[e]);
                 hb4[e] = (__bf16)hn[e];
             }
             const Half &hh = r < 64 ? ha : hb;
