@@ -237,7 +237,9 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const float z = az[q][e];
-            hn[e] = z * hold[q][e] + (1.0f - z) * tanh_l2(ah[q][e] + au[e]);
+            // h' = z h + (1 - z) c = c + z (h - c), c the candidate state
+            const float c = tanh_l2(ah[q][e] + au[e]);
+            hn[e] = c + z * (hold[q][e] - c);
             hb[e] = (__bf16)hn[e];
         }
         if (valid(r)) *reinterpret_cast<f4 *>(f.h + patch(r) * H + ucol) = hn;

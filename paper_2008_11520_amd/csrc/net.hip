@@ -217,7 +217,7 @@ __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net
                 const int lr = r0 + 16 * q + 4 * lq + e, row = blk * kNetRows + lr, k = 16 * (hg * HW + tw) + li;
                 const float z = az[tw][q][e];
                 const float hh = PREC == 1 ? tanh_l2(ah[tw][q][e] + au[tw][q][e]) : fast_tanh(ah[tw][q][e] + au[tw][q][e]);
-                const float hn = z * hold[tw][q][e] + (1.0f - z) * hh;
+                const float hn = hh + z * (hold[tw][q][e] - hh);   // z h + (1 - z) hh
                 if (row < P) hG[(size_t)row * H + k] = hn;
                 sHp[lr * LDH + k] = O::cvt(hn);
             }
@@ -446,7 +446,7 @@ __device__ __forceinline__ void net_tile_fp8(const FlowArgs &f, int blk, NetArgs
             const int row = rbase + 4 * lq + e, k = 16 * t + li;
             const float z = az[t][e];
             const float hh = fast_tanh(ah[t][e] + au[t][e] * srh[e] * net.s2[k]);
-            const float hn = z * hold[t][e] + (1.0f - z) * hh;
+            const float hn = hh + z * (hold[t][e] - hh);   // z h + (1 - z) hh
             if (row < P) f.h[(size_t)row * H + k] = hn;
             au[t][e] = hn;
             mp[e] = fmaxf(mp[e], fabsf(hn));
@@ -763,7 +763,9 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float z = az[q][e];
-                hn[e] = z * hold[q][e] + (1.0f - z) * tanh_l2(ah[q][e] + au[e]);
+                // h' = z h + (1 - z) c = c + z (h - c), c the candidate state
+                const float c = tanh_l2(ah[q][e] + au[e]);
+                hn[e] = c + z * (hold[q][e] - c);
                 hb[e] = (__bf16)hn[e];
             }
             if (r < nrows) *(__attribute__((address_space(1))) f4 *)(hg + r * H + ucol) = hn;
@@ -1058,7 +1060,8 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_q8p(FlowArgs single, 
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const float z = az[q][e];
-                    const float hn = z * hold[q][e] + (1.0f - z) * fast_tanh(ah[q][e] + au[e] * srh[q] * S2[ucol + e]);
+                    const float c = fast_tanh(ah[q][e] + au[e] * srh[q] * S2[ucol + e]);
+                    const float hn = c + z * (hold[q][e] - c);   // z h + (1 - z) c
                     az[q][e] = hn;
                     m = fmaxf(m, fabsf(hn));
                 }
@@ -1337,7 +1340,9 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float z = az[q][e];
-                hn[e] = z * hold[q][e] + (1.0f - z) * tanh_l2(ah[q][e] + au[e]);
+                // h' = z h + (1 - z) c = c + z (h - c), c the candidate state
+                const float c = tanh_l2(ah[q][e] + au[e]);
+                hn[e] = c + z * (hold[q][e] - c);
                 hb4[e] = (__bf16)hn[e];
             }
             const Half &hh = r < 64 ? ha : hb;
