@@ -1152,13 +1152,15 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_q8p(FlowArgs single, 
 // tile w % HT for the 8 / (8 / HT) row tiles of its row group, so each weight
 // fragment streamed from L2 (the weights, 368 KB at K = 3, H = 128, fit
 // neither in registers nor in LDS) feeds 8 (H = 128) or 4 (H = 64) row tiles
-// per gate.  The input rows of the tile fill LDS during the gate GEMM; r * h,
-// h' and the MLP hidden layer then reuse those bytes.  The FP32 state stays
-// in registers in the lane layout of the update.  The input rows are
-// prefetched one tile ahead; the state is loaded when the tile starts and
-// waited for only after the k-chunks that hold input alone.  A 128-patch tile
-// is a pair of 64-patch row tiles of the launch, each of which may belong to
-// another flow of a batch.
+// per gate.  LDS holds three regions: the tile's input rows (pitch nin, which
+// keeps the fragment reads free of bank conflicts), the gate rows' state part
+// [h | 0] (later r * h, then the MLP hidden layer) and h'.  The next tile's
+// input rows are copied from global memory straight into their region, and
+// its FP32 state into registers, while the current tile runs its output
+// products; the weights of those products are requested first, so the waits
+// for them never wait for the copy.  A 128-patch tile is a pair of
+// the launch's 64-patch row tiles, each of which may belong to another flow
+// of a batch.
 constexpr int kWideRows = 128;
 
 template <int K, int H, int HM>
@@ -1170,23 +1172,27 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
     constexpr int KC = 32, KQ = 8, KC1 = (nin + H + KC - 1) / KC, HC = H / KC;
     constexpr int HT = H / 16, WPH = 8 / HT, RTW = (kWideRows / 16) / WPH;
     constexpr int OT = (nout + 15) / 16;
-    constexpr int LDA = KC1 * KC + 8, LDH = H + 8;
-    constexpr int PADK = KC1 * KC - nin - H;
-    constexpr int ABYTES = kWideRows * LDA * 2, HBYTES = kWideRows * LDH * 2;
-    constexpr int LDSB = ABYTES > 2 * HBYTES ? ABYTES : 2 * HBYTES;
+    constexpr int LDG = KC1 * KC - nin, LDH = H + 8;
+    constexpr int XP = nin / 8;                       // 16-byte pieces per input row
+    constexpr int XBYTES = kWideRows * nin * 2;
+    constexpr int GBYTES = kWideRows * (LDG > LDH ? LDG : LDH) * 2;
+    constexpr int HBYTES = kWideRows * LDH * 2;
+    constexpr int KX = nin / KC;                      // k-chunks of input alone; chunk KX may straddle
     static_assert(HM == 0 || HM == H, "MLP hidden tiles follow the hidden tiles");
-    static_assert(nin % 8 == 0 && PADK % 8 == 0, "rows in 16-byte pieces");
+    static_assert(nin % 8 == 0 && LDG >= H && (LDG - H) % 8 == 0, "rows in 16-byte pieces");
     static_assert(kNetH64Threads == 512 && (H == 64 || H == 128), "eight waves over 4 or 8 hidden tiles");
+    static_assert(XBYTES + GBYTES + HBYTES <= 160 * 1024, "LDS of one CU");
     if (bt) ntiles64 = bt->prefix[kKindNet][bt->nflows];
     const int ntiles = (ntiles64 + 1) / 2;
 
-    __shared__ __align__(16) unsigned char s_lds[LDSB];
-    __bf16 *const sA = reinterpret_cast<__bf16 *>(s_lds);             // [x | h | 0] rows, gate GEMM
-    __bf16 *const sR = reinterpret_cast<__bf16 *>(s_lds);             // r * h, after the gate GEMM
-    __bf16 *const sHp = reinterpret_cast<__bf16 *>(s_lds + HBYTES);   // h'
-    __bf16 *const sAm = sR;                                           // MLP hidden layer, after U_h (r * h)
+    // (three arrays, not one: the compiler then knows that reads of sG and
+    // sHp cannot see the copy into sX and need not wait for it)
+    __shared__ __align__(16) __bf16 sX[XBYTES / 2];     // input rows
+    __shared__ __align__(16) __bf16 sG[GBYTES / 2];     // [h | 0], then r * h, then MLP hidden
+    __shared__ __align__(16) __bf16 sHp[HBYTES / 2];    // h'
 
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = lane & 15, lq = lane >> 4;
     const int ht = wave % HT, rt0 = RTW * (wave / HT);
     const int ucol = 16 * ht + 4 * lq;
@@ -1196,7 +1202,9 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
     // the single flow's fields copied out, since the lambdas below would
     // otherwise reach the argument through a generic pointer)
     typedef __attribute__((address_space(1))) float gfloat;
-    const void *const sX = single.X;
+    typedef __attribute__((address_space(1))) void gvoid;
+    typedef __attribute__((address_space(3))) void lvoid;
+    const void *const sXg = single.X;
     float *const sh = single.h, *const sdp = single.dpatch;
     const int sP = single.nx * single.ny;
     struct Half {
@@ -1217,7 +1225,7 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
             const FlowArgs &F = *batch_flow(bt, kKindNet, blk);
             X = F.X; h = F.h; dp = F.dpatch; P = F.nx * F.ny;
         } else {
-            X = sX; h = sh; dp = sdp; P = sP;
+            X = sXg; h = sh; dp = sdp; P = sP;
         }
         const int row0 = blk * 64;
         r.X = (gptr<__bf16>)(reinterpret_cast<const __bf16 *>(X) + (size_t)row0 * nin);
@@ -1227,88 +1235,108 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
         return r;
     };
 
-    constexpr int XR = nin / 8, XCH = kWideRows * XR;
-    constexpr int XPT = (XCH + kNetH64Threads - 1) / kNetH64Threads;
-    constexpr int KX = nin / KC;        // k-chunks that hold input alone
-    bf8 xr[XPT];
-    // (index math from tile_thread(): recomputed in each tile instead of
-    // hoisted out of the tile loop and held in registers)
-    auto load_x = [&](const Half &a, const Half &b) {
-        const int t0 = tile_thread();
+    // a tile's input rows, copied into sX without passing through registers:
+    // one wave load moves 64 consecutive 16-byte pieces (a half's rows are
+    // consecutive in global memory and in sX).  The loads are unconditional,
+    // so that the waits for later loads can count past them: pieces of rows
+    // past the flow's end are read from its last row (those rows' results
+    // are never stored), an empty half reads the other half's rows, and the
+    // waves with one load fewer repeat the last piece.  (Lane index from
+    // tile_thread(): the index math is recomputed in each tile instead of
+    // hoisted out of the tile loop into registers.)
+    auto fill_x = [&](const Half &a, const Half &b) {
+        const int l = tile_thread() & 63;
 #pragma unroll
-        for (int i = 0; i < XPT; ++i) {
-            const int c = t0 + i * kNetH64Threads;
-            const int r = c / XR, k = c - r * XR;
-            const Half &hh = r < 64 ? a : b;
-            const int rr = r & 63;
-            xr[i] = (c < XCH && rr < hh.nrows) ? *(gptr<bf8>)(hh.X + rr * nin + 8 * k) : bf8{};
+        for (int i = 0; i < (2 * XP + 7) / 8; ++i) {
+            const int j = min(wave + 8 * i, 2 * XP - 1);
+            const bool second = j >= XP;
+            const Half &hh = second && b.nrows > 0 ? b : a;
+            const int jj = second ? j - XP : j;
+            const int p = 64 * jj + l;
+            const int row = min(p / XP, hh.nrows - 1);
+            __builtin_amdgcn_global_load_lds((gvoid *)(hh.X + row * nin + 8 * (p - row * XP)),
+                                             (lvoid *)(sX + (second ? 64 * nin : 0) + 512 * jj), 16, 0, 0);
         }
     };
-    if ((int)blockIdx.x < ntiles) load_x(half_of(2 * blockIdx.x), half_of(2 * blockIdx.x + 1));
+    // a tile's FP32 state in the lane layout of the update (rows 16 q + li
+    // of the wave's row tiles, units ucol .. ucol + 3); unconditional loads
+    // as above (rows past the flow's end read its last row)
+    f4 hold[RTW];
+    auto load_hold = [&](const Half &a, const Half &b) {
+        const int l = tile_thread() & 15;
+#pragma unroll
+        for (int q = 0; q < RTW; ++q) {
+            const int r = 16 * (rt0 + q) + l;
+            const Half &hh = r >= 64 && b.nrows > 0 ? b : a;
+            const int row = min(r & 63, hh.nrows - 1);
+            hold[q] = *(const __attribute__((address_space(1))) f4 *)(hh.h + row * H + ucol);
+        }
+    };
+    if ((int)blockIdx.x < ntiles) {
+        const Half a = half_of(2 * blockIdx.x), b = half_of(2 * blockIdx.x + 1);
+        fill_x(a, b);
+        load_hold(a, b);
+    }
 
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const Half ha = half_of(2 * tile), hb = half_of(2 * tile + 1);
+        const bool more = tile + (int)gridDim.x < ntiles;
         const gptr<bf8> B1 = pinned<bf8>(net.B1);
         const gptr<bf8> B2 = pinned<bf8>(net.B2);
         const gptr<bf8> B3 = pinned<bf8>(net.B3);
         const gptr<bf8> B4 = pinned<bf8>(net.B4);
 
-        // this tile's state, in the lane layout of the update (rows
-        // 16 q + li of the wave's row tiles, units ucol .. ucol + 3)
-        f4 hold[RTW];
+        __syncthreads();   // the previous tile's readers of sG and sHp are done
+        // the state's BF16 copy and the zeros after it (the last k-chunk
+        // reads them)
 #pragma unroll
         for (int q = 0; q < RTW; ++q) {
             const int r = 16 * (rt0 + q) + li;
-            const Half &hh = r < 64 ? ha : hb;
-            hold[q] = (r & 63) < hh.nrows ? *(const __attribute__((address_space(1))) f4 *)(hh.h + (r & 63) * H + ucol)
-                                          : f4{0.f, 0.f, 0.f, 0.f};
+            bf4 hb4;
+            hb4[0] = (__bf16)hold[q].x; hb4[1] = (__bf16)hold[q].y; hb4[2] = (__bf16)hold[q].z; hb4[3] = (__bf16)hold[q].w;
+            *reinterpret_cast<bf4 *>(&sG[r * LDG + ucol]) = hb4;
         }
-        __syncthreads();   // the previous tile's readers of LDS are done
-        const int t1 = tile_thread();
-#pragma unroll
-        for (int i = 0; i < XPT; ++i) {
-            const int c = t1 + i * kNetH64Threads;
-            if (c < XCH) {
-                const int r = c / XR, k = c - r * XR;
-                *reinterpret_cast<bf8 *>(&sA[r * LDA + 8 * k]) = xr[i];
-            }
-        }
-        // zeros after [x | h]: the last k-chunk reads them (r * h and h'
-        // overwrite them later in the tile)
-        if (PADK > 0)
-            for (int t = t1; t < kWideRows * (PADK / 8); t += kNetH64Threads)
-                *reinterpret_cast<uint4 *>(&sA[(t / (PADK / 8)) * LDA + nin + H + 8 * (t % (PADK / 8))]) = make_uint4(0u, 0u, 0u, 0u);
+        if (LDG > H)
+            for (int t = tile_thread(); t < kWideRows * ((LDG - H) / 8); t += kNetH64Threads)
+                *reinterpret_cast<uint4 *>(&sG[(t / ((LDG - H) / 8)) * LDG + H + 8 * (t % ((LDG - H) / 8))]) = make_uint4(0u, 0u, 0u, 0u);
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's pieces of the input rows have landed in LDS
         __syncthreads();
 
-        // ---- gates: weight fragments streamed chunk by chunk; the chunks of
-        //      input alone first, then the state's BF16 copy joins the rows
+        // ---- gates: weight fragments streamed chunk by chunk
         f4 az[RTW], ar[RTW], ah[RTW];
 #pragma unroll
         for (int q = 0; q < RTW; ++q) az[q] = ar[q] = ah[q] = f4{0.f, 0.f, 0.f, 0.f};
-        auto chunk = [&](int kc) {
+        auto chunk = [&](int kc, const __bf16 *base, int pitch, int lrow) {
             const bf8 wz = B1[((0 * HT + ht) * KC1 + kc) * 64 + lane];
             const bf8 wr = B1[((1 * HT + ht) * KC1 + kc) * 64 + lane];
             const bf8 wh = B1[((2 * HT + ht) * KC1 + kc) * 64 + lane];
 #pragma unroll
             for (int q = 0; q < RTW; ++q) {
-                const bf8 a = *reinterpret_cast<const bf8 *>(&sA[(16 * (rt0 + q) + li) * LDA + kc * KC + lq * KQ]);
+                const bf8 a = *reinterpret_cast<const bf8 *>(&base[(16 * (rt0 + q) + lrow) * pitch]);
                 az[q] = O::mma(az[q], wz, a);
                 ar[q] = O::mma(ar[q], wr, a);
                 ah[q] = O::mma(ah[q], wh, a);
             }
         };
 #pragma unroll 1
-        for (int kc = 0; kc < KX; ++kc) chunk(kc);
-#pragma unroll
-        for (int q = 0; q < RTW; ++q) {
-            bf4 hb4;
-            hb4[0] = (__bf16)hold[q].x; hb4[1] = (__bf16)hold[q].y; hb4[2] = (__bf16)hold[q].z; hb4[3] = (__bf16)hold[q].w;
-            *reinterpret_cast<bf4 *>(&sA[(16 * (rt0 + q) + li) * LDA + nin + ucol]) = hb4;
+        for (int kc = 0; kc < KX; ++kc) chunk(kc, sX + kc * KC + lq * KQ, nin, li);
+        {
+            // chunk KX: a lane's 8 columns lie in the input or in the state
+            // part (lane indices from tile_thread(): the row addresses are
+            // recomputed in each tile, not held in registers across tiles)
+            const int tt = tile_thread() & 63;
+            const int k0 = KX * KC + (tt >> 4) * KQ;
+            const bool inx = k0 < nin;
+            chunk(KX, inx ? sX + k0 : sG + (k0 - nin), inx ? nin : LDG, tt & 15);
         }
-        __syncthreads();
 #pragma unroll 1
-        for (int kc = KX; kc < KC1; ++kc) chunk(kc);
-        __syncthreads();   // every wave is done with the input rows (r * h reuses them)
+        for (int kc = KX + 1; kc < KC1; ++kc) chunk(kc, sG + (kc * KC + lq * KQ - nin), LDG, li);
+        __syncthreads();   // every wave is done with sX and sG
+
+        bf8 w2[HC], w3[HC];
+#pragma unroll
+        for (int kc = 0; kc < HC; ++kc) w2[kc] = B2[(ht * HC + kc) * 64 + lane];
+
 #pragma unroll
         for (int q = 0; q < RTW; ++q) {
             const int r = 16 * (rt0 + q) + li;
@@ -1318,23 +1346,18 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
                 az[q][e] = sigmoid_l2(az[q][e]);
                 rh[e] = (__bf16)(sigmoid_l2(ar[q][e]) * hold[q][e]);
             }
-            *reinterpret_cast<bf4 *>(&sR[r * LDH + ucol]) = rh;
+            *reinterpret_cast<bf4 *>(&sG[r * LDH + ucol]) = rh;
         }
-        // the next tile's input rows: in flight during U_h and the MLP
-        if (tile + (int)gridDim.x < ntiles) load_x(half_of(2 * (tile + gridDim.x)), half_of(2 * (tile + gridDim.x) + 1));
         __syncthreads();
 
         // ---- U_h (r * h); new state
-        bf8 w2[HC];
-#pragma unroll
-        for (int kc = 0; kc < HC; ++kc) w2[kc] = B2[(ht * HC + kc) * 64 + lane];
 #pragma unroll
         for (int q = 0; q < RTW; ++q) {
             const int r = 16 * (rt0 + q) + li;
             f4 au = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kc = 0; kc < HC; ++kc)
-                au = O::mma(au, w2[kc], *reinterpret_cast<const bf8 *>(&sR[r * LDH + kc * KC + lq * KQ]));
+                au = O::mma(au, w2[kc], *reinterpret_cast<const bf8 *>(&sG[r * LDH + kc * KC + lq * KQ]));
             f4 hn;
             bf4 hb4;
 #pragma unroll
@@ -1349,15 +1372,26 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
             if ((r & 63) < hh.nrows) *(__attribute__((address_space(1))) f4 *)(hh.h + (r & 63) * H + ucol) = hn;
             *reinterpret_cast<bf4 *>(&sHp[r * LDH + ucol]) = hb4;
         }
+        // weights of the MLP hidden layer and of this wave's output tiles
+        // (ht, ht + HT, ...)
+        if constexpr (HM > 0) {
+#pragma unroll
+            for (int kc = 0; kc < HC; ++kc) w3[kc] = B3[(ht * HC + kc) * 64 + lane];
+        }
+        const gptr<bf8> Wo = HM > 0 ? B4 : B3;
+        constexpr int NOT = (OT + HT - 1) / HT;
+        bf8 wo[NOT][HC];
+#pragma unroll
+        for (int j = 0; j < NOT; ++j) {
+            const int ot = min(ht + j * HT, OT - 1);
+#pragma unroll
+            for (int kc = 0; kc < HC; ++kc) wo[j][kc] = Wo[(ot * HC + kc) * 64 + lane];
+        }
         __syncthreads();
 
         // ---- MLP head
         const __bf16 *src = sHp;
-        gptr<bf8> Wo = B3;
         if constexpr (HM > 0) {
-            bf8 w3[HC];
-#pragma unroll
-            for (int kc = 0; kc < HC; ++kc) w3[kc] = B3[(ht * HC + kc) * 64 + lane];
 #pragma unroll
             for (int q = 0; q < RTW; ++q) {
                 const int r = 16 * (rt0 + q) + li;
@@ -1368,28 +1402,42 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
                 bf4 m;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) m[e] = (__bf16)fmaxf(acc[e], 0.f);
-                *reinterpret_cast<bf4 *>(&sAm[r * LDH + ucol]) = m;
+                *reinterpret_cast<bf4 *>(&sG[r * LDH + ucol]) = m;
             }
             __syncthreads();
-            src = sAm;
-            Wo = B4;
+            src = sG;
         }
-        for (int ot = ht; ot < OT; ot += HT) {
-            const int oc = 16 * ot + 4 * lq;
-            bf8 wo[HC];
+        // the next tile's input rows and state, in flight during the output
+        // products.  Issued after the last barrier of the tile (a barrier
+        // would wait for the copy into LDS) and after the output weights
+        // have landed (while the copy is outstanding, any wait for a load
+        // waits for the copy too).
+        __builtin_amdgcn_s_waitcnt(0);
+        {
+            // (the last tile of the block loads itself again: no branch)
+            const int nt = more ? tile + (int)gridDim.x : tile;
+            const Half a = half_of(2 * nt), b = half_of(2 * nt + 1);
+            fill_x(a, b);
+            load_hold(a, b);
+        }
+        const int lo = tile_thread() & 15;   // (row addresses recomputed in each tile)
 #pragma unroll
-            for (int kc = 0; kc < HC; ++kc) wo[kc] = Wo[(ot * HC + kc) * 64 + lane];
+        for (int j = 0; j < NOT; ++j) {
+            const int ot = ht + j * HT;
+            if (ot >= OT) break;
+            const int oc = 16 * ot + 4 * lq;
 #pragma unroll
             for (int q = 0; q < RTW; ++q) {
                 const int r = 16 * (rt0 + q) + li;
                 f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int kc = 0; kc < HC; ++kc)
-                    acc = O::mma(acc, wo[kc], *reinterpret_cast<const bf8 *>(&src[r * LDH + kc * KC + lq * KQ]));
+                    acc = O::mma(acc, wo[j][kc], *reinterpret_cast<const bf8 *>(&src[r * LDH + kc * KC + lq * KQ]));
                 // nout is even: the pairs (oc, oc+1), (oc+2, oc+3) are inside or outside together
-                const Half &hh = r < 64 ? ha : hb;
-                if ((r & 63) < hh.nrows) {
-                    gfloat *o = hh.dp + (r & 63) * nout + oc;
+                const int ro = 16 * (rt0 + q) + lo;
+                const Half &hh = ro < 64 ? ha : hb;
+                if ((ro & 63) < hh.nrows) {
+                    gfloat *o = hh.dp + (ro & 63) * nout + oc;
                     typedef float v2 __attribute__((ext_vector_type(2)));
                     typedef __attribute__((address_space(1))) v2 gv2;
                     if (oc < nout) *(gv2 *)o = v2{acc[0], acc[1]};
@@ -1398,6 +1446,7 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
             }
         }
     }
+    __builtin_amdgcn_s_waitcnt(0);   // the last tile's repeated copy into LDS has landed
 }
 
 static int g_num_cus = 0;
