@@ -166,22 +166,21 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
     const gptr<bf8> B4 = pinned<bf8>(net.B4);
     // the tile's state in this lane's layout (rows 16 q + li, units ucol..+3):
     // one HBM read serves the MFMA operand (BF16, next to the network input)
-    // and the update
+    // and the update.  It is waited for only after the k-chunks that hold
+    // input alone.
     f4 hp[RT];
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
         const int r = 16 * q + li;
         hp[q] = valid(r) ? *reinterpret_cast<const f4 *>(f.h + patch(r) * H + ucol) : f4{0.f, 0.f, 0.f, 0.f};
     }
-#pragma unroll
-    for (int q = 0; q < RT; ++q) {
-        bf4 hb;
-        hb[0] = (__bf16)hp[q].x; hb[1] = (__bf16)hp[q].y; hb[2] = (__bf16)hp[q].z; hb[3] = (__bf16)hp[q].w;
-        *reinterpret_cast<bf4 *>(&sA[(16 * q + li) * LDA + nin + ucol]) = hb;
+    // zeros after [x | h]: the lanes of the last k-chunk that lie beyond it
+    // read these (the zero is formed from tile_thread(), so that it is not
+    // materialised once outside the batched tile loop and held there)
+    if (tid < 64) {
+        const unsigned z = (unsigned)tile_thread() >> 16;
+        *reinterpret_cast<uint4 *>(&sA[tid * LDA + nin + H]) = make_uint4(z, z, z, z);
     }
-    // zeros after [x | h]: the lanes of the last k-chunk that lie beyond it read these
-    if (tid < 64) *reinterpret_cast<uint4 *>(&sA[tid * LDA + nin + H]) = make_uint4(0u, 0u, 0u, 0u);
-    __syncthreads();
 
     // ---- phase 1: the three gates of this wave's hidden tile, four row tiles.
     //      Weight fragments are read chunk by chunk (L2-resident; other waves
@@ -202,9 +201,22 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
             ah[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, a, first ? z0 : ah[q], 0, 0, 0);
         }
     };
+    // the chunks of input alone (the input rows are complete: the defect
+    // phase ended with a barrier), then the state's BF16 copy joins the rows
+    constexpr int KX = nin / KC;
+    static_assert(KX >= 1 && KX < KC1 - 1, "input-only chunks, then chunks with the state");
     chunk(0, true, false);
-#pragma unroll 2
-    for (int kc = 1; kc < KC1 - 1; ++kc) chunk(kc, false, false);
+#pragma unroll
+    for (int kc = 1; kc < KX; ++kc) chunk(kc, false, false);
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        bf4 hb;
+        hb[0] = (__bf16)hp[q].x; hb[1] = (__bf16)hp[q].y; hb[2] = (__bf16)hp[q].z; hb[3] = (__bf16)hp[q].w;
+        *reinterpret_cast<bf4 *>(&sA[(16 * q + li) * LDA + nin + ucol]) = hb;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int kc = KX; kc < KC1 - 1; ++kc) chunk(kc, false, false);
     chunk(KC1 - 1, false, true);
     bf8 w2[2];
 #pragma unroll
