@@ -21,6 +21,7 @@
 #include "device.h"
 #include "fp8.h"
 #include "internal.h"
+#include "net_index.h"
 
 namespace dnnmg {
 
@@ -671,12 +672,12 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_h64(FlowArgs single, 
 #pragma unroll
         for (int i = 0; i < XPT; ++i) {
             const int c = t0 + i * kNetH64Threads;
-            xr[i] = (c < XCH && c / (nin / 8) < rw.nrows) ? rw.X[c] : bf8{};
+            xr[i] = tile_piece_in(c, nin / 8, rw.nrows) ? rw.X[c] : bf8{};
         }
 #pragma unroll
         for (int i = 0; i < HPT; ++i) {
             const int c = t0 + i * kNetH64Threads;
-            hr[i] = (c < HCH && c / (H / 4) < rw.nrows) ? ((gf4 *)rw.h)[c] : f4{0.f, 0.f, 0.f, 0.f};
+            hr[i] = tile_piece_in(c, H / 4, rw.nrows) ? ((gf4 *)rw.h)[c] : f4{0.f, 0.f, 0.f, 0.f};
         }
     };
     // the k-padding columns of [x | h] stay zero for the whole launch
@@ -935,12 +936,12 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_q8p(FlowArgs single, 
 #pragma unroll
         for (int i = 0; i < XPT; ++i) {
             const int c = t0 + i * kNetH64Threads;
-            xr[i] = (c < XCH && c / (XS / 16) < rw.nrows) ? ((gu4 *)rw.X)[c] : u4{0u, 0u, 0u, 0u};
+            xr[i] = tile_piece_in(c, XS / 16, rw.nrows) ? ((gu4 *)rw.X)[c] : u4{0u, 0u, 0u, 0u};
         }
 #pragma unroll
         for (int i = 0; i < HPT; ++i) {
             const int c = t0 + i * kNetH64Threads;
-            hr[i] = (c < HCH && c / (H / 4) < rw.nrows) ? ((gf4 *)rw.h)[c] : f4{0.f, 0.f, 0.f, 0.f};
+            hr[i] = tile_piece_in(c, H / 4, rw.nrows) ? ((gf4 *)rw.h)[c] : f4{0.f, 0.f, 0.f, 0.f};
         }
         sxr = t0 < rw.nrows ? rw.sx[t0] : 1.0f;
     };
@@ -1238,37 +1239,32 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
     // a tile's input rows, copied into sX without passing through registers:
     // one wave load moves 64 consecutive 16-byte pieces (a half's rows are
     // consecutive in global memory and in sX).  The loads are unconditional,
-    // so that the waits for later loads can count past them: pieces of rows
-    // past the flow's end are read from its last row (those rows' results
-    // are never stored), an empty half reads the other half's rows, and the
-    // waves with one load fewer repeat the last piece.  (Lane index from
+    // so that the waits for later loads can count past them; wide_x_piece
+    // keeps every read inside the half's rows (rows past a flow's end read
+    // its last row at the same column, an empty half reads the other half's
+    // rows; those rows' results are never stored).  (Lane index from
     // tile_thread(): the index math is recomputed in each tile instead of
     // hoisted out of the tile loop into registers.)
     auto fill_x = [&](const Half &a, const Half &b) {
         const int l = tile_thread() & 63;
 #pragma unroll
         for (int i = 0; i < (2 * XP + 7) / 8; ++i) {
-            const int j = min(wave + 8 * i, 2 * XP - 1);
-            const bool second = j >= XP;
-            const Half &hh = second && b.nrows > 0 ? b : a;
-            const int jj = second ? j - XP : j;
-            const int p = 64 * jj + l;
-            const int row = min(p / XP, hh.nrows - 1);
-            __builtin_amdgcn_global_load_lds((gvoid *)(hh.X + row * nin + 8 * (p - row * XP)),
-                                             (lvoid *)(sX + (second ? 64 * nin : 0) + 512 * jj), 16, 0, 0);
+            const WidePiece w = wide_x_piece(i, wave, l, XP, a.nrows, b.nrows);
+            const Half &hh = w.half ? b : a;
+            __builtin_amdgcn_global_load_lds((gvoid *)(hh.X + w.src), (lvoid *)(sX + w.dst), 16, 0, 0);
         }
     };
     // a tile's FP32 state in the lane layout of the update (rows 16 q + li
     // of the wave's row tiles, units ucol .. ucol + 3); unconditional loads
-    // as above (rows past the flow's end read its last row)
+    // as above (wide_h_row: rows past the flow's end read its last row)
     f4 hold[RTW];
     auto load_hold = [&](const Half &a, const Half &b) {
         const int l = tile_thread() & 15;
 #pragma unroll
         for (int q = 0; q < RTW; ++q) {
-            const int r = 16 * (rt0 + q) + l;
-            const Half &hh = r >= 64 && b.nrows > 0 ? b : a;
-            const int row = min(r & 63, hh.nrows - 1);
+            int half;
+            const int row = wide_h_row(16 * (rt0 + q) + l, a.nrows, b.nrows, half);
+            const Half &hh = half ? b : a;
             hold[q] = *(const __attribute__((address_space(1))) f4 *)(hh.h + row * H + ucol);
         }
     };
