@@ -30,6 +30,9 @@ def lib():
         L.orc_restrict.argtypes = [i, i, i, i, _D, _D]
         L.orc_dirichlet_mask.argtypes = [i, i, i, u, _U8]
         L.orc_defect.argtypes = [i, i, i, _D, _D, _D, _D, d, d, u, _D]
+        L.orc_defect_abs.argtypes = [i, i, i, _D, _D, _D, _D, d, d, _D]
+        L.orc_set_threads.argtypes = [i]
+        L.orc_get_threads.restype = i
         L.orc_mass_apply.argtypes = [i, i, i, _D, _D, _D]
         L.orc_features.argtypes = [i, i, _D, _D]
         L.orc_gather_input.argtypes = [i, i, i, _D, _D, _D, _D]
@@ -111,6 +114,26 @@ def defect(nx, ny, K, cxy, pv, pp, uprev, dt, nu, dirichlet):
     lib().orc_defect(nx, ny, K, _p(_f64(cxy)), _p(_f64(pv)), _p(_f64(pp)), _p(_f64(uprev)),
                      dt, nu, dirichlet, _p(D))
     return D
+
+
+def defect_abs(nx, ny, K, cxy, pv, pp, uprev, inv_dt, nu):
+    """Error scale of the defect (orc_defect_abs): the element terms and the
+    sums inside them in absolute value, assembled, unmasked.  inv_dt is the
+    1/dt of the evaluation being judged (0 if it leaves the mass term out)."""
+    s = sizes(nx, ny, K)
+    S = np.empty((s["Fn"], 2))
+    lib().orc_defect_abs(nx, ny, K, _p(_f64(cxy)), _p(_f64(pv)), _p(_f64(pp)), _p(_f64(uprev)),
+                         inv_dt, nu, _p(S))
+    return S
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().orc_get_threads())
 
 
 def mass_apply(nx, ny, K, cxy, u):

@@ -15,7 +15,13 @@
  * reset gate applied before U_h as printed in Eq. (gru)).
  *
  * Everything is plain loops in double precision, in the order the
- * definitions state; no blocking, fusion or reordering.
+ * definitions state; no blocking, fusion or reordering.  Loops whose
+ * iterations write disjoint outputs (per patch, per fine node) may run on
+ * several threads (OpenMP).  The element loops that add into shared nodes
+ * run their rows in two passes, even rows then odd rows, so no two threads
+ * add into one node and every node receives its contributions in an order
+ * that does not depend on the number of threads: results are the same bit
+ * for bit on 1 or many threads.
  *
  * Indexing (structured meshes):
  *   coarse node (i,j), 0<=i<=nx, 0<=j<=ny : index j*(nx+1)+i
@@ -27,6 +33,28 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the parallel loops (1 when built without OpenMP). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
+int orc_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ---------------------------------------------------------------- helpers */
 
@@ -99,6 +127,7 @@ void orc_fine_coords(int nx, int ny, int K, const double *cxy, double *fxy)
 void orc_prolong(int nx, int ny, int K, int ncomp, const double *coarse, double *fine)
 {
     int n = 1 << K;
+#pragma omp parallel for schedule(static)
     for (int J = 0; J <= ny * n; ++J)
         for (int I = 0; I <= nx * n; ++I) {
             int i, a, j, b;
@@ -124,7 +153,12 @@ void orc_restrict(int nx, int ny, int K, int ncomp, const double *fine, double *
 {
     int n = 1 << K;
     memset(coarse, 0, sizeof(double) * (size_t)ncomp * (nx + 1) * (ny + 1));
-    for (int J = 0; J <= ny * n; ++J)
+    /* a fine row J adds into the coarse rows j and j + 1 of its owner j:
+     * owners of one parity never share a coarse row */
+    for (int parity = 0; parity < 2; ++parity)
+#pragma omp parallel for schedule(static)
+    for (int jo = parity; jo < ny; jo += 2)
+    for (int J = jo * n; J <= (jo == ny - 1 ? ny * n : jo * n + n - 1); ++J)
         for (int I = 0; I <= nx * n; ++I) {
             int i, a, j, b;
             owner(I, n, nx, &i, &a);
@@ -174,7 +208,11 @@ void orc_defect(int nx, int ny, int K, const double *cxy, const double *v, const
     memset(D, 0, sizeof(double) * 2 * Fn);
     double g[2];
     gauss2(g);
-    for (int J = 0; J < NY; ++J)
+    /* element row J adds into node rows J and J + 1: rows of one parity
+     * never share a node */
+    for (int parity = 0; parity < 2; ++parity)
+#pragma omp parallel for schedule(static)
+    for (int J = parity; J < NY; J += 2)
         for (int I = 0; I < NX; ++I) {
             int node[4] = {fine_node(nx, n, I, J), fine_node(nx, n, I + 1, J),
                            fine_node(nx, n, I, J + 1), fine_node(nx, n, I + 1, J + 1)};
@@ -230,6 +268,93 @@ void orc_defect(int nx, int ny, int K, const double *cxy, const double *v, const
     free(mask);
 }
 
+/* -------------------------------------------- error scale of the defect */
+/* Not part of the step: a scale for judging a floating-point evaluation of
+ * orc_defect.  The same element loop, Gauss points and terms, each term in
+ * absolute value, and inside each term the sums that form it taken over
+ * absolute values: the element map and the velocity written as bilinear
+ * polynomials f00 + e_s s + e_t t + e_st s t in the reference coordinates
+ * (e_s = f10 - f00, e_t = f01 - f00, e_st = f11 - f10 - f01 + f00), so
+ * d/ds f = e_s + e_st t is bounded by |e_s| + |e_st| t, and so on; the
+ * interpolated v, u_prev and p from absolute nodal values; the mass term
+ * from |u_prev| + |v|.  No Dirichlet masking.
+ *
+ * An evaluation of D in working precision u that forms the same quantities
+ * (in any order, from edge vectors and nodal differences) differs from the
+ * exact D at a node by at most a modest multiple of u times this scale (the
+ * running-error bound of sums of products), however much the element terms
+ * cancel in the node sums.  inv_dt is the 1/dt of that evaluation: 0 for
+ * one that leaves the mass term out. */
+void orc_defect_abs(int nx, int ny, int K, const double *cxy, const double *v, const double *p,
+                    const double *uprev, double inv_dt, double nu, double *S)
+{
+    int n = 1 << K, NX = nx * n, NY = ny * n;
+    size_t Fn = (size_t)(NX + 1) * (NY + 1);
+    double *fxy = (double *)malloc(sizeof(double) * 2 * Fn);
+    orc_fine_coords(nx, ny, K, cxy, fxy);
+    memset(S, 0, sizeof(double) * 2 * Fn);
+    double g[2];
+    gauss2(g);
+    for (int parity = 0; parity < 2; ++parity)
+#pragma omp parallel for schedule(static)
+    for (int J = parity; J < NY; J += 2)
+        for (int I = 0; I < NX; ++I) {
+            int node[4] = {fine_node(nx, n, I, J), fine_node(nx, n, I + 1, J),
+                           fine_node(nx, n, I, J + 1), fine_node(nx, n, I + 1, J + 1)};
+            for (int qt = 0; qt < 2; ++qt)
+                for (int qs = 0; qs < 2; ++qs) {
+                    double N[4], dNs[4], dNt[4];
+                    q1_shape(g[qs], g[qt], N);
+                    q1_shape_ds(g[qs], g[qt], dNs, dNt);
+                    /* bilinear coefficients of the map (x, y) and of v */
+                    double ex[2], et[2], est[2];
+                    for (int d = 0; d < 2; ++d) {
+                        double f0 = fxy[2 * node[0] + d], f1 = fxy[2 * node[1] + d];
+                        double f2 = fxy[2 * node[2] + d], f3 = fxy[2 * node[3] + d];
+                        ex[d] = f1 - f0; et[d] = f2 - f0; est[d] = f3 - f1 - f2 + f0;
+                    }
+                    double s_ = g[qs], t_ = g[qt];
+                    double xs = ex[0] + est[0] * t_, xt = et[0] + est[0] * s_;
+                    double ys = ex[1] + est[1] * t_, yt = et[1] + est[1] * s_;
+                    double axs = fabs(ex[0]) + fabs(est[0]) * t_, axt = fabs(et[0]) + fabs(est[0]) * s_;
+                    double ays = fabs(ex[1]) + fabs(est[1]) * t_, ayt = fabs(et[1]) + fabs(est[1]) * s_;
+                    double det = fabs(xs * yt - xt * ys);
+                    double adx[4], ady[4];   /* |grad N| with the inverse Jacobian taken term by term */
+                    for (int k = 0; k < 4; ++k) {
+                        adx[k] = (ayt * fabs(dNs[k]) + ays * fabs(dNt[k])) / det;
+                        ady[k] = (axt * fabs(dNs[k]) + axs * fabs(dNt[k])) / det;
+                    }
+                    double av[2] = {0, 0}, au[2] = {0, 0}, ap = 0, ag[2][2];
+                    for (int k = 0; k < 4; ++k) {
+                        for (int c = 0; c < 2; ++c) {
+                            av[c] += N[k] * fabs(v[2 * node[k] + c]);
+                            au[c] += N[k] * fabs(uprev[2 * node[k] + c]);
+                        }
+                        ap += N[k] * fabs(p[node[k]]);
+                    }
+                    for (int c = 0; c < 2; ++c) {
+                        double v0 = v[2 * node[0] + c], v1 = v[2 * node[1] + c];
+                        double v2 = v[2 * node[2] + c], v3 = v[2 * node[3] + c];
+                        double as = fabs(v1 - v0) + fabs(v3 - v1 - v2 + v0) * t_;   /* |dv/ds| */
+                        double at = fabs(v2 - v0) + fabs(v3 - v1 - v2 + v0) * s_;   /* |dv/dt| */
+                        ag[c][0] = (ayt * as + ays * at) / det;
+                        ag[c][1] = (axt * as + axs * at) / det;
+                    }
+                    double wd = 0.25 * (axs * ayt + axt * ays);
+                    for (int a = 0; a < 4; ++a)
+                        for (int c = 0; c < 2; ++c) {
+                            double adphi = (c == 0) ? adx[a] : ady[a];
+                            double r = inv_dt * N[a] * (au[c] + av[c])
+                                     + N[a] * (av[0] * ag[c][0] + av[1] * ag[c][1])
+                                     + nu * (adx[a] * ag[c][0] + ady[a] * ag[c][1])
+                                     + ap * adphi;
+                            S[2 * node[a] + c] += wd * r;
+                        }
+                }
+        }
+    free(fxy);
+}
+
 /* ---------------------------------------------------- step 9: mass matrix */
 /* Mu = M_f u, the consistent fine-level mass matrix (same element loop and
  * quadrature as the defect) applied to a 2-component nodal field. */
@@ -242,7 +367,9 @@ void orc_mass_apply(int nx, int ny, int K, const double *cxy, const double *u, d
     memset(Mu, 0, sizeof(double) * 2 * Fn);
     double g[2];
     gauss2(g);
-    for (int J = 0; J < NY; ++J)
+    for (int parity = 0; parity < 2; ++parity)
+#pragma omp parallel for schedule(static)
+    for (int J = parity; J < NY; J += 2)
         for (int I = 0; I < NX; ++I) {
             int node[4] = {fine_node(nx, n, I, J), fine_node(nx, n, I + 1, J),
                            fine_node(nx, n, I, J + 1), fine_node(nx, n, I + 1, J + 1)};
@@ -300,6 +427,7 @@ void orc_gather_input(int nx, int ny, int K, const double *pv, const double *D,
                       const double *feat, double *X)
 {
     int n = 1 << K, nf = (n + 1) * (n + 1), nin = 4 * nf + 4;
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t e = (size_t)j * nx + i;
@@ -328,8 +456,11 @@ void orc_gru(int P, int nin, int H, const double *Wz, const double *Wr, const do
              const double *Uz, const double *Ur, const double *Uh,
              const double *X, const double *h, double *hout)
 {
+#pragma omp parallel
+    {
     double *z = (double *)malloc(sizeof(double) * H);
     double *rh = (double *)malloc(sizeof(double) * H);
+#pragma omp for schedule(static)
     for (int e = 0; e < P; ++e) {
         const double *x = X + (size_t)e * nin;
         const double *he = h + (size_t)e * H;
@@ -355,6 +486,7 @@ void orc_gru(int P, int nin, int H, const double *Wz, const double *Wr, const do
     }
     free(z);
     free(rh);
+    }
 }
 
 /* ---------------------------------------------------------- step 7: MLP */
@@ -362,7 +494,10 @@ void orc_gru(int P, int nin, int H, const double *Wz, const double *Wr, const do
 void orc_mlp(int P, int H, int Hm, int nout, const double *M1, const double *M2,
              const double *h, double *d)
 {
+#pragma omp parallel
+    {
     double *a = (double *)malloc(sizeof(double) * (Hm > 0 ? Hm : 1));
+#pragma omp for schedule(static)
     for (int e = 0; e < P; ++e) {
         const double *he = h + (size_t)e * H;
         double *de = d + (size_t)e * nout;
@@ -386,6 +521,7 @@ void orc_mlp(int P, int H, int Hm, int nout, const double *M1, const double *M2,
         }
     }
     free(a);
+    }
 }
 
 /* ------------------------------------- steps 6-7 with FP8 E4M3 operands */
@@ -510,8 +646,11 @@ void orc_gru_fp8(int P, int nin, int H, const double *Wz, const double *Wr, cons
         }
     }
     quant_matrix(H, H, Uh, qUh, sUh);
+#pragma omp parallel
+    {
     unsigned char *qx = (unsigned char *)malloc(nin), *qh = (unsigned char *)malloc(H), *qrh = (unsigned char *)malloc(H);
     double *z = (double *)malloc(sizeof(double) * H), *rh = (double *)malloc(sizeof(double) * H);
+#pragma omp for schedule(static)
     for (int e = 0; e < P; ++e) {
         const double *he = h + (size_t)e * H;
         float sx, sh, srh;
@@ -533,8 +672,10 @@ void orc_gru_fp8(int P, int nin, int H, const double *Wz, const double *Wr, cons
             hout[(size_t)e * H + k] = z[k] * he[k] + (1.0 - z[k]) * tanh(ah);
         }
     }
+    free(qx); free(qh); free(qrh); free(z); free(rh);
+    }
     for (int g = 0; g < 3; ++g) { free(qB[g]); free(sB[g]); }
-    free(qUh); free(sUh); free(row); free(qx); free(qh); free(qrh); free(z); free(rh);
+    free(qUh); free(sUh); free(row);
 }
 
 /* MLP with FP8 operands: each layer quantises its input per patch and its
@@ -547,8 +688,11 @@ void orc_mlp_fp8(int P, int H, int Hm, int nout, const double *M1, const double 
     float *s1 = (float *)malloc(sizeof(float) * n1), *s2 = (float *)malloc(sizeof(float) * nout);
     quant_matrix(n1, H, M1, q1, s1);
     if (Hm > 0) quant_matrix(nout, Hm, M2, q2, s2);
+#pragma omp parallel
+    {
     unsigned char *qh = (unsigned char *)malloc(H), *qa = (unsigned char *)malloc(Hm > 0 ? Hm : 1);
     double *a = (double *)malloc(sizeof(double) * (Hm > 0 ? Hm : 1));
+#pragma omp for schedule(static)
     for (int e = 0; e < P; ++e) {
         float sh, sa;
         double *de = d + (size_t)e * nout;
@@ -564,7 +708,9 @@ void orc_mlp_fp8(int P, int H, int Hm, int nout, const double *M1, const double 
             for (int o = 0; o < nout; ++o) de[o] = (double)s1[o] * (double)sh * qdot(H, qh, q1 + (size_t)o * H);
         }
     }
-    free(q1); free(q2); free(s1); free(s2); free(qh); free(qa); free(a);
+    free(qh); free(qa); free(a);
+    }
+    free(q1); free(q2); free(s1); free(s2);
 }
 
 /* ---------------------------------------------------- step 8: averaging */
@@ -577,6 +723,7 @@ void orc_average(int nx, int ny, int K, const double *dpatch, unsigned dir, doub
     size_t Fn = (size_t)(NX + 1) * (NY + 1);
     unsigned char *mask = (unsigned char *)malloc(Fn);
     orc_dirichlet_mask(nx, ny, K, dir, mask);
+#pragma omp parallel for schedule(static)
     for (int J = 0; J <= NY; ++J)
         for (int I = 0; I <= NX; ++I) {
             double s[2] = {0, 0};

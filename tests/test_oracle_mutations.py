@@ -32,6 +32,9 @@ MUTATIONS = {
     "average_fixed_divisor": ("s[0] / cnt", "s[0] / 4", 0),
     "input_component": ("x[2 * nf + 2 * l] = D[2 * f];", "x[2 * nf + 2 * l] = D[2 * f + 1];", 0),
     "aspect_inverted": ("f[2] = hx / hy;", "f[2] = hy / hx;", 0),
+    "features_hx_hy_swapped": ("f[0] = hx; f[1] = hy;", "f[0] = hy; f[1] = hx;", 0),
+    "features_hx_one_edge": ("hx = 0.5 * (hypot(c10[0] - c00[0], c10[1] - c00[1]) +",
+                             "hx = 0.5 * (hypot(c11[0] - c01[0], c11[1] - c01[1]) +", 0),
     "lumped_mass": ("Mu[2 * node[a] + c] += wd * N[a] * uq[c];", "Mu[2 * node[a] + c] += wd * 0.25 * uq[c];", 0),
     "mask_wrong_axis": ("((dir & 4u) && J == 0)", "((dir & 4u) && I == 0)", 0),
     "state_without_correction": ("uprev[f] = Pv[f] + Dbar[f];", "uprev[f] = Pv[f];", 0),

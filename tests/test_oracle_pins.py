@@ -499,6 +499,27 @@ def test_features_on_unit_square_and_general_quads():
             assert f[j * nx + i, 2] == f[j * nx + i, 0] / f[j * nx + i, 1]
 
 
+def test_features_hx_hy_on_rectangles_and_a_trapezoid():
+    """hx is the mean length of the two edges along the element's first
+    (x) direction, hy of the two along the second: on the 2.2 x 0.41 channel
+    at 256 x 64 they are the two different spacings, and on one trapezoid
+    (bottom edge 2, top edge 1, left edge 1, right edge sqrt 2) they are
+    1.5 and (1 + sqrt 2) / 2 -- a swap of the two, or a single edge, fails."""
+    nx, ny = 256, 64
+    f = oracle.features(nx, ny, rect(nx, ny, 2.2, 0.41))
+    assert np.allclose(f[:, 0], 2.2 / 256, rtol=1e-13, atol=0)
+    assert np.allclose(f[:, 1], 0.41 / 64, rtol=1e-13, atol=0)
+    assert np.allclose(f[:, 2], (2.2 / 256) / (0.41 / 64), rtol=1e-13, atol=0)
+    assert np.allclose(f[:, 3], 2.2 * 0.41 / (256 * 64), rtol=1e-12, atol=0)
+    # one trapezoid: c00 = (0, 0), c10 = (2, 0), c01 = (0, 1), c11 = (1, 1)
+    cxy = np.array([[0.0, 0.0], [2.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
+    hx, hy, aspect, area = oracle.features(1, 1, cxy)[0]
+    assert abs(hx - 1.5) < 1e-15
+    assert abs(hy - (1.0 + math.sqrt(2.0)) / 2) < 1e-15
+    assert abs(aspect - 1.5 / ((1.0 + math.sqrt(2.0)) / 2)) < 1e-15
+    assert abs(area - 1.5) < 1e-15          # (2 + 1) / 2 * height 1
+
+
 def test_step_carries_corrected_velocity_into_next_defect():
     """Alg. 2: the right-hand side of step n+1 is built from P v_n + d_n.
     On a uniform mesh, the step-2 defect minus the defect of the same fields
@@ -538,3 +559,65 @@ def test_zero_weights_give_zero_correction_and_state():
         ref = _coarse_mass_bruteforce(nx, ny, flow.cxy.reshape(-1, 2), v.astype(np.float64)) / flow.dt
         assert np.abs(out["bL"] - ref).max() <= 1e-13 * np.abs(ref).max()
     assert s["P"] == nx * ny
+
+
+def test_results_do_not_depend_on_the_thread_count():
+    """The oracle's parallel loops write disjoint outputs, and its element
+    loops add into nodes in a fixed order (even rows, then odd rows): a step
+    on 1 thread and on 4 threads agree bit for bit, FP64 and FP8 forms."""
+    nx, ny, K, H, Hm = 9, 7, 2, 16, 16
+    flow = synth.channel_flow(nx, ny, 3, 0.005, perturb_seed=2)
+    w = synth.xavier_weights(K, H, Hm, 5).astype(np.float64)
+    base = oracle.get_threads()
+    try:
+        runs = []
+        for threads in (1, 4):
+            oracle.set_threads(threads)
+            for fp8 in (False, True):
+                o = oracle.OracleFlow(nx, ny, K, H, Hm, flow.dt, 1e-3, flow.dirichlet, flow.cxy, w, fp8=fp8)
+                outs = [o.step(*flow.fields(n), want=("Pv", "D", "X", "dpatch", "Dbar", "bL")) for n in range(3)]
+                runs.append((threads, fp8, outs, o.h.copy(), o.uprev.copy()))
+        for a, b in zip(runs[:2], runs[2:]):
+            assert a[1] == b[1]
+            for sa, sb in zip(a[2], b[2]):
+                for k in sa:
+                    assert np.array_equal(sa[k], sb[k]), (a[1], k)
+            assert np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4])
+    finally:
+        oracle.set_threads(base)
+
+
+def test_defect_error_scale_bounds_the_defect_and_is_exact_without_cancellation():
+    """orc_defect_abs: (1) it bounds |D| node by node (each term and each sum
+    in it is replaced by one of absolute values, so the triangle inequality
+    gives S >= |D|) on a perturbed mesh with random fields; (2) with the mass
+    term alone and u_prev >= 0 on a rectilinear mesh nothing cancels, so
+    S = D = (1/dt) M u_prev; (3) pressure alone, p = c >= 0 constant, on a
+    uniform mesh: every Gauss point of each of the 4 elements around an
+    interior node contributes w |det| c |d phi / dx|, and the four points of
+    an element sum |dN/ds| to 2, so S_x = 4 * (1/4) * hx hy * c * 2 / hx =
+    2 c hy and S_y = 2 c hx."""
+    nx, ny, K = 6, 5, 1
+    n = 1 << K
+    s = oracle.sizes(nx, ny, K)
+    cxy = perturbed(nx, ny, 2.2, 0.41, seed=4)
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal((s["Fn"], 2))
+    p = rng.standard_normal(s["Fn"])
+    u = rng.standard_normal((s["Fn"], 2))
+    D = oracle.defect(nx, ny, K, cxy, v, p, u, 0.01, 1e-3, 0)
+    S = oracle.defect_abs(nx, ny, K, cxy, v, p, u, 1 / 0.01, 1e-3)
+    assert np.all(S >= np.abs(D) * (1 - 1e-14))
+    # (2) mass term alone on a rectilinear mesh
+    cr = rect(nx, ny, 2.2, 0.41)
+    up = np.abs(u)
+    D2 = oracle.defect(nx, ny, K, cr, 0 * v, 0 * p, up, 0.01, 1e-3, 0)
+    S2 = oracle.defect_abs(nx, ny, K, cr, 0 * v, 0 * p, up, 1 / 0.01, 1e-3)
+    assert np.allclose(S2, D2, rtol=1e-13, atol=0)
+    assert np.allclose(S2, oracle.mass_apply(nx, ny, K, cr, up) / 0.01, rtol=1e-13, atol=0)
+    # (3) pressure alone, constant c
+    c = 0.7
+    S3 = oracle.defect_abs(nx, ny, K, cr, 0 * v, c + 0 * p, 0 * u, 0.0, 1e-3).reshape(ny * n + 1, nx * n + 1, 2)
+    hx, hy = 2.2 / (nx * n), 0.41 / (ny * n)
+    assert np.allclose(S3[1:-1, 1:-1, 0], 2 * c * hy, rtol=1e-13, atol=0)
+    assert np.allclose(S3[1:-1, 1:-1, 1], 2 * c * hx, rtol=1e-13, atol=0)
