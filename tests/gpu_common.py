@@ -20,6 +20,62 @@ def rel_max(a, b):
     return float(np.abs(a - b).max() / (m if m > 0 else 1.0))
 
 
+# FP32 unit roundoff
+EPS32 = 2.0 ** -24
+# fine elements per side of a defect / rhs tile (tile-edge nodes are where
+# neighbouring tiles' halos and staged edge nodes meet)
+TILE_FINE = 32
+
+
+def node_errors(got, ref, nx, ny, K, dirichlet, name="Dbar"):
+    """Element-wise errors of a fine nodal field (Fn x 2): relative L2, max
+    abs error over max |oracle| for all nodes, for the nodes on defect/rhs
+    tile edges (fine index a multiple of 32), and the count of Dirichlet
+    nodes where the GPU value is not exactly zero."""
+    n = 1 << K
+    NX, NY = nx * n, ny * n
+    g = np.asarray(got, np.float64).reshape(NY + 1, NX + 1, 2)
+    r = np.asarray(ref, np.float64).reshape(NY + 1, NX + 1, 2)
+    mask = oracle.dirichlet_mask(nx, ny, K, dirichlet).reshape(NY + 1, NX + 1)
+    edge = (np.arange(NX + 1)[None, :] % TILE_FINE == 0) | (np.arange(NY + 1)[:, None] % TILE_FINE == 0)
+    m = np.abs(r).max()
+    m = m if m > 0 else 1.0
+    err = np.abs(g - r).max(axis=2)
+    sel = edge & ~mask
+    return {name: rel_l2(g, r), name + "_max": float(err.max() / m),
+            name + "_edge_max": float(err[sel].max() / m) if sel.any() else 0.0,
+            name + "_dirichlet_nonzero": int(np.count_nonzero(g[mask]))}
+
+
+def step_errors(got, ref, h_ref, nx, ny, K, dirichlet):
+    """Errors of one step's outputs: D-bar (element-wise, see node_errors),
+    the per-patch outputs and the state (relative L2 and max-relative), and
+    b_L (relative L2 and max-relative)."""
+    e = node_errors(got["Dbar"], ref["Dbar"], nx, ny, K, dirichlet)
+    for k, r in (("dpatch", ref.get("dpatch")), ("h", h_ref), ("bL", ref["bL"])):
+        if r is None:
+            continue
+        e[k] = rel_l2(got[k], r)
+        e[k + "_max"] = rel_max(got[k], r)
+    return e
+
+
+def merge_worst(worst, errs):
+    for k, v in errs.items():
+        worst[k] = max(worst.get(k, 0), v)
+    return worst
+
+
+def assert_step_errors(worst, tol, bl_tol):
+    """The bound applies to relative L2 and to max-relative alike; D-bar is
+    exactly zero at Dirichlet nodes."""
+    assert worst["Dbar_dirichlet_nonzero"] == 0, worst
+    for k in ("Dbar", "Dbar_max", "Dbar_edge_max", "dpatch", "dpatch_max", "h", "h_max"):
+        if k in worst:
+            assert worst[k] < tol, (k, worst)
+    assert worst["bL"] < bl_tol and worst["bL_max"] < bl_tol, worst
+
+
 def to_dev(a, dtype=None):
     import torch
     t = torch.from_numpy(np.ascontiguousarray(a))

@@ -1,9 +1,13 @@
 """GPU path (through the C ABI) against the FP64 oracle on the same seeded inputs.
 
-Tolerances (relative L2 over the whole output unless stated):
-  P v                  1e-6   FP32 bilinear interpolation of FP32 values
+Tolerances (relative L2 over the whole output, and max |error| over
+max |oracle|, unless stated):
+  P v                  1e-6 max-rel: FP32 bilinear interpolation of FP32 values
   D (defect)           derived per test: FP32 assembly; see test docstrings
-  d (correction)       1e-5 FP32 operands, 2e-2 BF16 operands
+  d (correction), per-patch output, state
+                       1e-5 FP32 operands, 2e-2 BF16 operands, on both norms;
+                       tile-edge nodes reported separately; exactly 0 at
+                       Dirichlet nodes
   b_L stage            1e-10 (FP64 right-hand side and restriction of given inputs)
   b_L end to end       1e-5 FP32 (bounded by the correction's error)
   zero weights         d == 0 bitwise; b_L to 1e-12
@@ -14,8 +18,8 @@ import pytest
 import oracle
 from paper_2008_11520_amd import synth
 
-from gpu_common import (GpuRunner, make_gpu_flow, make_oracle_flow, rel_l2, rel_max, to_dev, window,
-                        window_fields)
+from gpu_common import (EPS32, GpuRunner, assert_step_errors, make_gpu_flow, make_oracle_flow, merge_worst,
+                        node_errors, rel_l2, rel_max, step_errors, to_dev, window, window_fields)
 
 pytestmark = pytest.mark.gpu
 
@@ -82,18 +86,24 @@ def test_defect_with_given_previous_velocity(name):
                         u_prev.astype(np.float64).reshape(-1, 2), flow.dt, 1e-3, flow.dirichlet)
     got = D.cpu().numpy().reshape(-1, 2)
     err = rel_l2(got, ref)
-    print("defect rel-L2 error", name, err)
+    S = oracle.defect_abs(flow.nx, flow.ny, K, flow.cxy.reshape(-1, 2), pv, pp,
+                          u_prev.astype(np.float64).reshape(-1, 2), 1.0 / flow.dt, 1e-3)
+    ratio = np.abs(got - ref) / (EPS32 * S + 1e-300)
+    print("defect rel-L2 error", name, err, "max error / (eps32 * scale) %.2f" % ratio.max())
     assert err < 1e-5
+    assert ratio.max() <= 64.0
 
 
 @pytest.mark.parametrize("name", sorted(FLOWS))
 def test_defect_first_step_without_mass_term(name):
-    """Before the first step the previous velocity is P v itself, so only
-    convection, diffusion and pressure remain.  These node sums cancel
-    (a smooth field's residual is O(h^2) of its element terms), so the FP32
-    error relative to the result grows like eps32 / h: bound 1e-4 of the
-    result, plus 1e-6 of the size of the element terms (the mass term of the
-    same field against u_prev = 0) for fields whose exact defect vanishes."""
+    """Before the first step the previous velocity is P v itself, and the
+    kernel leaves the mass term out, so only convection, diffusion and
+    pressure remain.  Their element terms cancel in the node sums (a smooth
+    field's residual is O(h^2) of its element terms), so the error is judged
+    node by node against the running-error scale of those terms: the oracle's
+    defect_abs with the mass term off (every term, and every sum inside one,
+    in absolute value).  An FP32 evaluation of a few tens of operations per
+    term stays within 64 eps32 of that scale."""
     import torch
     flow, K, H, Hm = FLOWS[name]
     w = synth.xavier_weights(K, H, Hm, 1234)
@@ -106,12 +116,15 @@ def test_defect_first_step_without_mass_term(name):
     pv = oracle.prolong(flow.nx, flow.ny, K, v.astype(np.float64))
     pp = oracle.prolong(flow.nx, flow.ny, K, p.astype(np.float64))
     ref = oracle.defect(flow.nx, flow.ny, K, flow.cxy.reshape(-1, 2), pv, pp, pv, flow.dt, 1e-3, flow.dirichlet)
-    scale = oracle.defect(flow.nx, flow.ny, K, flow.cxy.reshape(-1, 2), pv, pp, 0 * pv, flow.dt, 1e-3,
-                          flow.dirichlet)
-    err = np.linalg.norm(D.cpu().numpy().reshape(-1, 2) - ref)
-    bound = 1e-4 * np.linalg.norm(ref) + 1e-6 * np.linalg.norm(scale)
-    print("defect (no mass term) error", name, err, "bound", bound, "rel", err / max(np.linalg.norm(ref), 1e-300))
-    assert err < bound
+    S = oracle.defect_abs(flow.nx, flow.ny, K, flow.cxy.reshape(-1, 2), pv, pp, pv, 0.0, 1e-3)
+    mask = oracle.dirichlet_mask(flow.nx, flow.ny, K, flow.dirichlet)
+    got = D.cpu().numpy().reshape(-1, 2)
+    err = np.abs(got - ref)
+    ratio = err / (EPS32 * S + 1e-300)
+    print("defect (no mass term)", name, "max error / (eps32 * scale) %.2f" % ratio.max(),
+          "rel-L2 %.2e" % rel_l2(got, ref))
+    assert np.all(got[mask] == 0.0)
+    assert ratio.max() <= 64.0
 
 
 @pytest.mark.parametrize("name", sorted(FLOWS))
@@ -127,13 +140,9 @@ def test_step_sequence_matches_oracle(name, prec, tol):
         v, p = flow.fields(n)
         got = g.step(v, p)
         ref = o.step(v, p, want=("Dbar", "bL", "dpatch"))
-        errs = dict(Dbar=rel_l2(got["Dbar"], ref["Dbar"]), dpatch=rel_l2(got["dpatch"], ref["dpatch"]),
-                    h=rel_l2(got["h"], o.h), bL=rel_l2(got["bL"], ref["bL"]))
-        for k, e in errs.items():
-            worst[k] = max(worst.get(k, 0.0), e)
+        merge_worst(worst, step_errors(got, ref, o.h, flow.nx, flow.ny, K, flow.dirichlet))
     print("step errors", name, prec, worst)
-    assert worst["Dbar"] < tol and worst["dpatch"] < tol and worst["h"] < tol
-    assert worst["bL"] < (1e-5 if prec == "fp32" else tol)
+    assert_step_errors(worst, tol, 1e-5 if prec == "fp32" else tol)
 
 
 @pytest.mark.parametrize("name", ["unit16_k1", "ragged13x7_k2_perturbed", "stretched5x3_k3"])
@@ -288,55 +297,77 @@ def test_batched_step_equals_single_steps_bitwise():
         batch.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 2e-2)])
-def test_channel_256x64_k2_full_size(prec, tol):
-    """The 256 x 64 channel (16384 patches), K=2, H=64, MLP 64-64-50: 3 steps."""
+def test_channel_256x64_k2_full_size_100_steps():
+    """The 256 x 64 channel (16384 patches), K=2, H=64, MLP 64-64-50, for
+    the 100 steps of its configuration, FP32 and BF16 operands side by side
+    against one FP64 oracle run: every step's correction, per-patch output,
+    state and restricted rhs within the bounds (no drift beyond them), the
+    worst error of every tenth step printed."""
     flow = synth.channel_flow(256, 64, 1, 0.005)
     K, H, Hm = 2, 64, 64
     w = synth.xavier_weights(K, H, Hm, 1234)
-    g = GpuRunner(make_gpu_flow(flow, K, H, Hm, 1e-3, w, prec))
+    runs = {prec: GpuRunner(make_gpu_flow(flow, K, H, Hm, 1e-3, w, prec)) for prec in ("fp32", "bf16")}
+    tols = {"fp32": (1e-5, 1e-5), "bf16": (2e-2, 2e-2)}
     o = make_oracle_flow(flow, K, H, Hm, 1e-3, w)
-    for n in range(3):
+    worst = {prec: {} for prec in runs}
+    for n in range(100):
         v, p = flow.fields(n)
-        got = g.step(v, p)
-        ref = o.step(v, p, want=("Dbar", "bL"))
-        e = dict(Dbar=rel_l2(got["Dbar"], ref["Dbar"]), h=rel_l2(got["h"], o.h), bL=rel_l2(got["bL"], ref["bL"]))
-        print("channel256x64", prec, n, e)
-        assert e["Dbar"] < tol and e["h"] < tol
+        ref = o.step(v, p, want=("Dbar", "bL", "dpatch"))
+        for prec, g in runs.items():
+            e = step_errors(g.step(v, p), ref, o.h, flow.nx, flow.ny, K, flow.dirichlet)
+            merge_worst(worst[prec], e)
+            assert_step_errors(e, *tols[prec])
+            if n % 10 == 9:
+                print("channel256x64 step %d %s Dbar %.2e (max %.2e) h %.2e (max %.2e) bL %.2e"
+                      % (n + 1, prec, e["Dbar"], e["Dbar_max"], e["h"], e["h_max"], e["bL"]), flush=True)
+    print("channel256x64 worst over 100 steps", worst)
 
 
-def test_channel_1024x256_perturbed_first_step_sampled_windows():
-    """Full size (262144 patches), the launch configuration the benchmark times:
-    the first step checked on windows the oracle computes in seconds (outputs
-    more than 3 patches from a window edge depend on window data only)."""
+def test_channel_1024x256_perturbed_steps_sampled_windows():
+    """Full size (262144 patches), the launch configuration the benchmark
+    times, for 5 steps, so the previous corrected velocity (mass term) and
+    the GRU state carried between steps run at full size: after every step,
+    windows the oracle steps alongside (the same 5 steps on the window's own
+    data) are compared away from their edges.  Each step moves the reach of
+    a window edge's missing neighbours inwards by about one patch (the
+    defect reads one fine element beyond a patch, the averaging its
+    neighbours' outputs), so the margin is steps + 2 patches; windows that
+    touch the domain's boundary keep it there.  Relative L2 and max-relative
+    of the correction and of b_L, per step."""
     flow = synth.channel_flow(1024, 256, 1, 0.005, perturb_seed=7)
     K, H, Hm = 2, 64, 64
     w = synth.xavier_weights(K, H, Hm, 1234)
     n = 1 << K
+    nsteps = 5
+    wins = ((0, 0, 24, 20), (500, 118, 24, 20), (1024 - 24, 256 - 20, 24, 20), (700, 0, 24, 20))
     for prec, tol in (("fp32", 1e-5), ("bf16", 2e-2)):
         g = GpuRunner(make_gpu_flow(flow, K, H, Hm, 1e-3, w, prec))
-        got = g.step(*flow.fields(0))
-        Dg = got["Dbar"].reshape(flow.ny * n + 1, flow.nx * n + 1, 2)
-        bg = got["bL"].reshape(flow.ny + 1, flow.nx + 1, 2)
-        m = 3
-        for (i0, j0) in ((0, 0), (500, 120), (1024 - 20, 256 - 16), (700, 0)):
-            i1, j1 = min(i0 + 20, 1024), min(j0 + 16, 256)
+        subs = []
+        for (i0, j0, wx, wy) in wins:
+            i1, j1 = min(i0 + wx, 1024), min(j0 + wy, 256)
             sub = window(flow, i0, i1, j0, j1)
-            o = make_oracle_flow(sub, K, H, Hm, 1e-3, w)
-            ref = o.step(*window_fields(flow, 0, i0, i1, j0, j1), want=("Dbar", "bL"))
-            Dr = ref["Dbar"].reshape(sub.ny * n + 1, sub.nx * n + 1, 2)
-            br = ref["bL"].reshape(sub.ny + 1, sub.nx + 1, 2)
-            # interior region of the window (or up to the true boundary)
-            a0 = 0 if i0 == 0 else m
-            a1 = sub.nx if i1 == flow.nx else sub.nx - m
-            c0 = 0 if j0 == 0 else m
-            c1 = sub.ny if j1 == flow.ny else sub.ny - m
-            eD = rel_l2(Dg[(j0 + c0) * n:(j0 + c1) * n + 1, (i0 + a0) * n:(i0 + a1) * n + 1],
-                        Dr[c0 * n:c1 * n + 1, a0 * n:a1 * n + 1])
-            eb = rel_l2(bg[j0 + c0 + 1:j0 + c1, i0 + a0 + 1:i0 + a1], br[c0 + 1:c1, a0 + 1:a1])
-            print("window", prec, (i0, j0), eD, eb)
-            assert eD < tol
-            assert eb < (1e-5 if prec == "fp32" else tol)
+            subs.append((i0, j0, i1, j1, sub, make_oracle_flow(sub, K, H, Hm, 1e-3, w)))
+        for step in range(nsteps):
+            got = g.step(*flow.fields(step))
+            Dg = got["Dbar"].reshape(flow.ny * n + 1, flow.nx * n + 1, 2)
+            bg = got["bL"].reshape(flow.ny + 1, flow.nx + 1, 2)
+            m = step + 2
+            for (i0, j0, i1, j1, sub, o) in subs:
+                ref = o.step(*window_fields(flow, step, i0, i1, j0, j1), want=("Dbar", "bL"))
+                Dr = ref["Dbar"].reshape(sub.ny * n + 1, sub.nx * n + 1, 2)
+                br = ref["bL"].reshape(sub.ny + 1, sub.nx + 1, 2)
+                # interior region of the window (or up to the true boundary)
+                a0 = 0 if i0 == 0 else m
+                a1 = sub.nx if i1 == flow.nx else sub.nx - m
+                c0 = 0 if j0 == 0 else m
+                c1 = sub.ny if j1 == flow.ny else sub.ny - m
+                dg = Dg[(j0 + c0) * n:(j0 + c1) * n + 1, (i0 + a0) * n:(i0 + a1) * n + 1]
+                dr = Dr[c0 * n:c1 * n + 1, a0 * n:a1 * n + 1]
+                bgw, brw = bg[j0 + c0 + 1:j0 + c1, i0 + a0 + 1:i0 + a1], br[c0 + 1:c1, a0 + 1:a1]
+                e = dict(Dbar=rel_l2(dg, dr), Dbar_max=rel_max(dg, dr), bL=rel_l2(bgw, brw), bL_max=rel_max(bgw, brw))
+                print("window", prec, "step", step, (i0, j0), {k: "%.2e" % x for k, x in e.items()}, flush=True)
+                assert e["Dbar"] < tol and e["Dbar_max"] < tol
+                assert max(e["bL"], e["bL_max"]) < (1e-5 if prec == "fp32" else tol)
 
 
 def test_channel_1024x256_zero_weights_full_size():
