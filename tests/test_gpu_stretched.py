@@ -5,7 +5,12 @@ captured launch in FP32, BF16 and FP8 E4M3.  Sampled flows are checked on
 windows the oracle computes in seconds (outputs more than 3 patches from a
 window edge depend on window data only): FP32 against the FP64 step (1e-5),
 BF16 against it (2e-2), FP8 against the oracle's FP8 form (2e-2, see
-test_gpu_fp8)."""
+test_gpu_fp8), each in relative L2 and in max |error| over max |oracle|.
+FP8's max-relative bound is 0.1: there the largest node errors come from
+single E4M3 code flips (the matrix cores' FP8 products carry ~1e-4 relative
+error, enough to move a value of the hidden layer across a rounding
+boundary), and one flip moves a patch's output by one code step of the
+flipped value, up to 2^-3 of it, times its output weights."""
 import numpy as np
 import pytest
 
@@ -69,7 +74,8 @@ def test_stretched_64_flows_k3_batched_sampled_windows(prec, tol):
         bgw, brw = bg[j0 + c0 + 1:j0 + c1, i0 + a0 + 1:i0 + a1], br[c0 + 1:c1, a0 + 1:a1]
         e = [rel_l2(dg, dr), rel_max(dg, dr), rel_l2(bgw, brw), rel_max(bgw, brw)]
         print("stretched", prec, fi, (i0, j0), "Dbar %.2e (max %.2e) bL %.2e (max %.2e)" % tuple(e))
-        assert max(e) < tol
+        max_tol = 0.1 if prec == "fp8" else tol
+        assert e[0] < tol and e[2] < tol and e[1] < max_tol and e[3] < max_tol
     batch.close()
     for c in ctxs:
         c.close()
