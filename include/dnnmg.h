@@ -75,6 +75,7 @@ enum { DNNMG_FP32 = 0, DNNMG_BF16 = 1, DNNMG_FP8_E4M3 = 2 };
  * the same arithmetic in the same order, so their results are bitwise equal. */
 enum { DNNMG_F_UNFUSED = 1 };
 
+
 /* Dirichlet sides (Eq. (boundary)); other sides are do-nothing outflow. */
 enum { DNNMG_DIR_XMIN = 1, DNNMG_DIR_XMAX = 2, DNNMG_DIR_YMIN = 4, DNNMG_DIR_YMAX = 8 };
 
@@ -197,6 +198,28 @@ int dnnmg_defect(dnnmg_ctx *ctx, const float *v_coarse_dev, const float *p_coars
  * correction: b_out = P^T (1/dt) M_f (P v + dbar), FP64.  dbar_dev Fn x 2. */
 int dnnmg_rhs_restrict(dnnmg_ctx *ctx, const float *v_coarse_dev, const float *dbar_dev,
                        double *b_out_dev, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * dnnmg_rhs_restrict without a context.  b_out = P^T (1/dt) M_f (P v + dbar)
+ * in FP64 for the structured nx x ny coarse mesh coarse_xy_dev (device,
+ * (ny+1)(nx+1) x 2 doubles, positively oriented elements: not checked here),
+ * with v_coarse_dev (ny+1)(nx+1) x 2 FP32, dbar_dev Fn x 2 FP32 and b_out_dev
+ * (ny+1)(nx+1) x 2 doubles, all device pointers owned by the caller.  The
+ * same kernels as dnnmg_rhs_restrict, and moment tables formed on the device
+ * by the same formula as at create, so the same result bit for bit.
+ * Allocates nothing: the kernels' scratch (map coefficients, FP64 corner
+ * partial sums, moment tables) is one static device array of
+ * dnnmg_noalloc_scratch_bytes() bytes (about 34 MiB) per GPU, held until the
+ * process ends, which limits nx * ny to DNNMG_NOALLOC_MAX_PATCHES
+ * (DNNMG_EINVAL beyond).  Every call on a GPU uses that GPU's one array:
+ * calls that overlap on one GPU (other streams, other threads) race; calls
+ * ordered on one stream do not.  Graph-capturable (kernel launches only). */
+enum { DNNMG_NOALLOC_MAX_PATCHES = 1 << 18 };
+size_t dnnmg_noalloc_scratch_bytes(void);
+int dnnmg_rhs_restrict_noalloc(int nx, int ny, int K, double dt, const double *coarse_xy_dev,
+                               const float *v_coarse_dev, const float *dbar_dev, double *b_out_dev,
+                               void *stream);
 
 /* Copy the state out (h: P x H FP32, uprev: Fn x 2 FP32; either may be NULL)
  * or in (then `steps` sets the step counter; 0 means "before the first step"). */

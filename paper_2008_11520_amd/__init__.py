@@ -28,7 +28,9 @@ SYMBOLS = [
     "dnnmg_batch_prepare", "dnnmg_batch_launch", "dnnmg_batch_captures", "dnnmg_step_batch", "dnnmg_destroy", "dnnmg_last_error", "dnnmg_prolong", "dnnmg_defect",
     "dnnmg_rhs_restrict", "dnnmg_get_state", "dnnmg_set_state", "dnnmg_patch_output",
     "dnnmg_step_count", "dnnmg_profile_enable", "dnnmg_profile_read", "dnnmg_quantize_e4m3",
+    "dnnmg_noalloc_scratch_bytes", "dnnmg_rhs_restrict_noalloc",
 ]
+DNNMG_NOALLOC_MAX_PATCHES = 1 << 18
 
 
 class DnnmgError(RuntimeError):
@@ -81,6 +83,8 @@ def lib():
     L.dnnmg_profile_enable.argtypes = [vp, i]
     L.dnnmg_quantize_e4m3.argtypes = [vp, i, i, vp, vp, vp]
     L.dnnmg_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    L.dnnmg_noalloc_scratch_bytes.argtypes = []; L.dnnmg_noalloc_scratch_bytes.restype = sz
+    L.dnnmg_rhs_restrict_noalloc.argtypes = [i, i, i, ctypes.c_double, vp, vp, vp, vp, vp]
     for name in SYMBOLS:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
     L.dnnmg_last_error.restype = ctypes.c_char_p
@@ -243,6 +247,23 @@ def quantize_e4m3(a, q_out, scale_out, stream=None):
     _check(lib().dnnmg_quantize_e4m3(_ptr(a, torch.float32, rows * cols, "a"), rows, cols,
                                      _ptr(q_out, torch.uint8, rows * cols, "q_out"),
                                      _ptr(scale_out, torch.float32, rows, "scale_out"), _stream(stream)))
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().dnnmg_noalloc_scratch_bytes())
+
+
+def rhs_restrict_noalloc(nx, ny, K, dt, coarse_xy, v, dbar, b_out, stream=None):
+    """dnnmg_rhs_restrict_noalloc: b_out = P^T (1/dt) M_f (P v + dbar) with no
+    context and no device allocation.  coarse_xy: device float64
+    ((ny+1)(nx+1) x 2), v: float32 coarse velocity, dbar: float32 fine
+    correction, b_out: float64 coarse output."""
+    import torch
+    s = sizes(nx, ny, K)
+    _check(lib().dnnmg_rhs_restrict_noalloc(nx, ny, K, dt, _ptr(coarse_xy, torch.float64, 2 * s["Nc"], "coarse_xy"),
+                                            _ptr(v, torch.float32, 2 * s["Nc"], "v"),
+                                            _ptr(dbar, torch.float32, 2 * s["Fn"], "dbar"),
+                                            _ptr(b_out, torch.float64, 2 * s["Nc"], "b_out"), _stream(stream)))
 
 
 class Batch:

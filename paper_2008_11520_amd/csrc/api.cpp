@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -415,41 +416,11 @@ void release_weights(Weights *w)
     }
 }
 
-// Exact moment tables on the reference square (see rhs.hip):
-//   int N_c phi_l m_k = A[mx_k][cx][a] A[my_k][cy][b]  (l = (a,b), c = (cx,cy)),
-//   M[k][c][c'] = int N_c N_c' m_k,  m = {1, xi, eta}.
-// Each factor is a 1D integral of a piecewise cubic, done with two Gauss points
-// per fine interval (exact).
 void moment_tables(int K, std::vector<double> &A1, std::vector<double> &M)
 {
-    const int n = 1 << K, nf = (n + 1) * (n + 1);
-    const double gp[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
-    auto L = [](int p, double x) { return p == 0 ? 1.0 - x : x; };
-    auto hat = [n](int a, double x) { double t = 1.0 - std::fabs(n * x - a); return t > 0.0 ? t : 0.0; };
-    // A[m][p][a] = int_0^1 L_p(x) hat_a(x) x^m dx ; C[m][p][q] = int_0^1 L_p L_q x^m dx
-    std::vector<double> A(2 * 2 * (n + 1), 0.0);
-    double C[2][2][2] = {};
-    for (int iv = 0; iv < n; ++iv)
-        for (int g = 0; g < 2; ++g) {
-            const double x = (iv + gp[g]) / n, w = 0.5 / n;
-            for (int m = 0; m < 2; ++m)
-                for (int p = 0; p < 2; ++p) {
-                    const double xm = m ? x : 1.0;
-                    for (int a = 0; a <= n; ++a) A[(m * 2 + p) * (n + 1) + a] += w * L(p, x) * hat(a, x) * xm;
-                    for (int q = 0; q < 2; ++q) C[m][p][q] += w * L(p, x) * L(q, x) * xm;
-                }
-        }
-    // G_k[c][l] = A[mx_k][cx][a] A[my_k][cy][b] factorises; the kernel uses A directly
-    (void)nf;
-    A1 = A;
-    M.assign(3 * 4 * 4, 0.0);
-    const int mx[3] = {0, 1, 0}, my[3] = {0, 0, 1};   // which direction carries xi / eta
-    for (int k = 0; k < 3; ++k)
-        for (int c = 0; c < 4; ++c) {
-            const int cx = c & 1, cy = c >> 1;
-            for (int cc = 0; cc < 4; ++cc)
-                M[(k * 4 + c) * 4 + cc] = C[mx[k]][cx][cc & 1] * C[my[k]][cy][cc >> 1];
-        }
+    A1.assign(moment_a_size(K), 0.0);
+    M.assign(kMomentMSize, 0.0);
+    fill_moment_tables(K, A1.data(), M.data());
 }
 
 FlowArgs flow_args(const dnnmg_ctx *c, const float *v, const float *p)
@@ -738,6 +709,87 @@ extern "C" int dnnmg_rhs_restrict(dnnmg_ctx *ctx, const float *v, const float *d
     hipStream_t st = (hipStream_t)stream;
     HIP_OR_FAIL(launch_rhs(f, nullptr, blocks_for(kKindRhs, g.nx, g.ny, g.K), g.K, ctx->tables(), 0, st));
     HIP_OR_FAIL(launch_gather(f, nullptr, blocks_for(kKindGather, g.nx, g.ny, g.K), st));
+    return DNNMG_OK;
+}
+
+// ------------------------------------------- allocation-free rhs + restriction
+// dnnmg_rhs_restrict without a context: the kernels' scratch (the patches'
+// map coefficients, the FP64 corner partial sums, the moment tables) lives in
+// one file-scope device array instead of a hipMalloc'd workspace.
+namespace {
+constexpr size_t cround(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t kStaticTabA = 0;                                              // moment table A (K <= 3)
+constexpr size_t kStaticTabM = kStaticTabA + cround(sizeof(double) * 4 * 9);  // moment table M
+constexpr size_t kStaticGeo = kStaticTabM + cround(sizeof(double) * kMomentMSize);
+constexpr size_t kStaticGeo64 = kStaticGeo + cround(sizeof(float) * 6 * DNNMG_NOALLOC_MAX_PATCHES);
+constexpr size_t kStaticFeat = kStaticGeo64 + cround(sizeof(double) * 4 * DNNMG_NOALLOC_MAX_PATCHES);
+constexpr size_t kStaticPart = kStaticFeat + cround(sizeof(float) * 4 * DNNMG_NOALLOC_MAX_PATCHES);
+constexpr size_t kStaticBad = kStaticPart + cround(sizeof(double) * 8 * DNNMG_NOALLOC_MAX_PATCHES);
+constexpr size_t kStaticBytes = kStaticBad + 256;
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_dev[kMaxDevices] = {};   // the array's device address, per device
+}  // namespace
+
+// (its name in host code is a host-side stand-in: host code uses only the
+// addresses hipGetSymbolAddress returns)
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+// The array's address on the current device, looked up once per device.
+static int static_scratch(unsigned char **out)
+{
+    int dev = 0;
+    HIP_OR_FAIL(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DNNMG_EDEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIP_OR_FAIL(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(DNNMG_EDEVICE, "hipGetSymbolAddress returned NULL");
+        g_scratch_dev[dev] = (unsigned char *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return DNNMG_OK;
+}
+
+extern "C" size_t dnnmg_noalloc_scratch_bytes(void) { return kStaticBytes; }
+
+extern "C" int dnnmg_rhs_restrict_noalloc(int nx, int ny, int K, double dt, const double *cxy, const float *v,
+                                          const float *dbar, double *b, void *stream)
+{
+    if (!cxy || !v || !dbar || !b) return fail(DNNMG_EINVAL, "coarse_xy, v, dbar and b_out must not be NULL");
+    if (nx < 1 || ny < 1) return fail(DNNMG_EINVAL, "nx, ny must be >= 1 (got %d, %d)", nx, ny);
+    if (K < 1 || K > 3) return fail(DNNMG_EINVAL, "K must be 1, 2 or 3 (got %d)", K);
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DNNMG_EINVAL, "dt must be > 0");
+    if ((long long)nx * ny > DNNMG_NOALLOC_MAX_PATCHES)
+        return fail(DNNMG_EINVAL, "%d x %d = %lld patches exceed the allocation-free limit of %d", nx, ny,
+                    (long long)nx * ny, DNNMG_NOALLOC_MAX_PATCHES);
+    unsigned char *sc = nullptr;
+    int rc = static_scratch(&sc);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    double *tabA = (double *)(sc + kStaticTabA), *tabM = (double *)(sc + kStaticTabM);
+    FlowArgs f{};
+    f.nx = nx;
+    f.ny = ny;
+    f.inv_dt = (float)(1.0 / dt);
+    f.inv_dt64 = 1.0 / dt;
+    f.v = v;
+    f.geo = (const float *)(sc + kStaticGeo);
+    f.geo64 = (const double *)(sc + kStaticGeo64);
+    f.feat = (const float *)(sc + kStaticFeat);
+    f.upitch = nx * (1 << K) + 1;
+    f.dbar_in = dbar;
+    f.part = (double *)(sc + kStaticPart);
+    f.bL = b;
+    // every scratch word the kernels read is written earlier in this call
+    // (geometry, tables, partial sums), so nothing needs clearing
+    HIP_OR_FAIL(launch_geometry(cxy, nx, ny, (float *)f.geo, (double *)f.geo64, (float *)f.feat,
+                                (int *)(sc + kStaticBad), st));
+    HIP_OR_FAIL(launch_moment_tables(K, tabA, tabM, st));
+    HIP_OR_FAIL(launch_rhs(f, nullptr, blocks_for(kKindRhs, nx, ny, K), K, RhsTables{tabA, tabM}, 0, st));
+    HIP_OR_FAIL(launch_gather(f, nullptr, blocks_for(kKindGather, nx, ny, K), st));
     return DNNMG_OK;
 }
 

@@ -58,6 +58,49 @@ struct RhsTables {
     const double *M;       // 3 x 4 x 4    : int N_c N_c' {1, xi, eta} on the reference square
 };
 
+// Exact moment tables on the reference square (see rhs.hip), host and
+// device (the allocation-free entry point forms them on the device):
+//   int N_c phi_l m_k = A[mx_k][cx][a] A[my_k][cy][b]  (l = (a,b), c = (cx,cy)),
+//   M[k][c][c'] = int N_c N_c' m_k,  m = {1, xi, eta}.
+// Each factor is a 1D integral of a piecewise cubic, done with two Gauss
+// points per fine interval (exact).  A: 2 x 2 x (n+1), M: 3 x 4 x 4.
+__host__ __device__ constexpr int moment_a_size(int K) { return 4 * ((1 << K) + 1); }
+constexpr int kMomentMSize = 3 * 4 * 4;
+__host__ __device__ inline void fill_moment_tables(int K, double *A, double *M)
+{
+#pragma clang fp contract(off)   // plain products and sums: host and device round alike
+    const int n = 1 << K;
+    const double r = 0.28867513459481288225;   // 1 / (2 sqrt 3)
+    const double gp[2] = {0.5 - r, 0.5 + r};
+    for (int i = 0; i < moment_a_size(K); ++i) A[i] = 0.0;
+    double C[2][2][2] = {};
+    for (int iv = 0; iv < n; ++iv)
+        for (int g = 0; g < 2; ++g) {
+            const double x = (iv + gp[g]) / n, w = 0.5 / n;
+            const double L[2] = {1.0 - x, x};
+            for (int m = 0; m < 2; ++m)
+                for (int p = 0; p < 2; ++p) {
+                    const double xm = m ? x : 1.0;
+                    for (int a = 0; a <= n; ++a) {
+                        double hat = 1.0 - fabs(n * x - a);
+                        hat = hat > 0.0 ? hat : 0.0;
+                        A[(m * 2 + p) * (n + 1) + a] += w * L[p] * hat * xm;
+                    }
+                    for (int q = 0; q < 2; ++q) C[m][p][q] += w * L[p] * L[q] * xm;
+                }
+        }
+    const int mx[3] = {0, 1, 0}, my[3] = {0, 0, 1};   // which direction carries xi / eta
+    for (int k = 0; k < 3; ++k)
+        for (int c = 0; c < 4; ++c) {
+            const int cx = c & 1, cy = c >> 1;
+            for (int cc = 0; cc < 4; ++cc)
+                M[(k * 4 + c) * 4 + cc] = C[mx[k]][cx][cc & 1] * C[my[k]][cy][cc >> 1];
+        }
+}
+// The same tables formed on the device (one thread), for callers without a
+// context.
+hipError_t launch_moment_tables(int K, double *A, double *M, hipStream_t s);
+
 // Device table for batched launches: per kernel kind, a block prefix over
 // flows, then the flows.
 enum { kKindDefect = 0, kKindNet = 1, kKindRhs = 2, kKindGather = 3, kKinds = 4 };

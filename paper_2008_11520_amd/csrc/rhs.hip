@@ -456,6 +456,18 @@ hipError_t launch_rhs(const FlowArgs &f, const BatchTable *bt, int nblocks, int 
     return hipGetLastError();
 }
 
+__global__ void k_moment_tables(int K, double *A, double *M)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) fill_moment_tables(K, A, M);
+}
+
+hipError_t launch_moment_tables(int K, double *A, double *M, hipStream_t s)
+{
+    if (K < 1 || K > 3) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_moment_tables, dim3(1), dim3(64), 0, s, K, A, M);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather(const FlowArgs &f, const BatchTable *bt, int nblocks, hipStream_t s)
 {
     if (bt) hipLaunchKernelGGL(k_gather<true>, dim3(nblocks), dim3(kThreads), 0, s, f, bt);

@@ -137,3 +137,21 @@ def test_unknown_flags_rejected_on_host():
     rc = L.dnnmg_create(ctypes.byref(c), cxy.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p),
                         w.size, None, ctypes.byref(out))
     assert rc == pam.DNNMG_EINVAL and b"flags" in L.dnnmg_last_error()
+
+
+def test_noalloc_entry_point_rejects_on_the_host():
+    """dnnmg_rhs_restrict_noalloc validates before touching the device: NULL
+    pointers, K, dt, and meshes beyond the static scratch's patch limit."""
+    L = pam.lib()
+    p = ctypes.c_void_p(256)    # never dereferenced: every case fails validation first
+    assert pam.noalloc_scratch_bytes() >= 64 * pam.DNNMG_NOALLOC_MAX_PATCHES
+    cases = [((4, 3, 2, 0.01, None, p, p, p), "NULL"),
+             ((4, 3, 4, 0.01, p, p, p, p), "K must be"),
+             ((4, 3, 2, 0.0, p, p, p, p), "dt"),
+             ((0, 3, 2, 0.01, p, p, p, p), "nx, ny"),
+             ((1024, 257, 2, 0.01, p, p, p, p), "allocation-free limit")]
+    for args, msg in cases:
+        rc = L.dnnmg_rhs_restrict_noalloc(*args, None)
+        assert rc == pam.DNNMG_EINVAL, args
+        assert msg in L.dnnmg_last_error().decode(), (args, L.dnnmg_last_error())
+
