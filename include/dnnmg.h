@@ -75,6 +75,16 @@ enum { DNNMG_FP32 = 0, DNNMG_BF16 = 1, DNNMG_FP8_E4M3 = 2 };
  * the same arithmetic in the same order, so their results are bitwise equal. */
 enum { DNNMG_F_UNFUSED = 1 };
 
+/* DNNMG_F_NANCHECK: the step's kernels also record whether any value of the
+ * averaged correction d (bit DNNMG_NONFINITE_CORRECTION) or of the restricted
+ * right-hand side b^L (bit DNNMG_NONFINITE_RHS, set by dnnmg_restrict_rhs and
+ * the batched gather) was NaN or infinite, in a device flag of the context
+ * that dnnmg_nonfinite reads.  Results are the same with or without it.
+ * The state h is not watched: with an MLP hidden layer, max(0, s) maps a NaN
+ * hidden value to zero (here and in the FP64 definition), so a non-finite
+ * state can leave the correction finite. */
+enum { DNNMG_F_NANCHECK = 2 };
+enum { DNNMG_NONFINITE_CORRECTION = 1, DNNMG_NONFINITE_RHS = 2 };
 
 /* Dirichlet sides (Eq. (boundary)); other sides are do-nothing outflow. */
 enum { DNNMG_DIR_XMIN = 1, DNNMG_DIR_XMAX = 2, DNNMG_DIR_YMIN = 4, DNNMG_DIR_YMAX = 8 };
@@ -89,7 +99,7 @@ typedef struct {
     double nu;           /* viscosity (>= 0)                                         */
     int precision;       /* DNNMG_FP32 / DNNMG_BF16 / DNNMG_FP8_E4M3                 */
     unsigned dirichlet;  /* DNNMG_DIR_* bits                                         */
-    unsigned flags;      /* 0, or DNNMG_F_UNFUSED                                    */
+    unsigned flags;      /* 0, or DNNMG_F_UNFUSED | DNNMG_F_NANCHECK                 */
 } dnnmg_config;
 
 /* Network sizes: N_in = 4 (n+1)^2 + 4 (prolongated velocity and defect at the
@@ -226,6 +236,16 @@ int dnnmg_rhs_restrict_noalloc(int nx, int ny, int K, double dt, const double *c
 int dnnmg_get_state(dnnmg_ctx *ctx, float *h_out_dev, float *uprev_out_dev, void *stream);
 int dnnmg_set_state(dnnmg_ctx *ctx, const float *h_in_dev, const float *uprev_in_dev,
                     long long steps, void *stream);
+
+/* Non-finite check (DNNMG_F_NANCHECK; failure detection: a flow whose
+ * correction or right-hand side has diverged is caught before the coarse
+ * solver consumes it or its state is stepped again):
+ * waits for the work enqueued on `stream` (a host synchronisation, so not for
+ * use under graph capture), then stores in *flags_out the DNNMG_NONFINITE_*
+ * bits recorded since the context was created or last cleared, and clears
+ * them if `clear` is nonzero.  DNNMG_ESTATE if the context was created
+ * without the flag; DNNMG_EINVAL for NULL arguments. */
+int dnnmg_nonfinite(dnnmg_ctx *ctx, int clear, int *flags_out, void *stream);
 
 /* Per-patch network output of the most recent step, before averaging:
  * d_out P x N_out FP32.  DNNMG_ESTATE before the first step. */

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(HERE, "libdnnmg.so")
 DNNMG_OK, DNNMG_EINVAL, DNNMG_ENOMEM, DNNMG_EDEVICE, DNNMG_ESTATE, DNNMG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 FP32, BF16, FP8_E4M3 = 0, 1, 2
 DNNMG_F_UNFUSED = 1
+DNNMG_F_NANCHECK = 2
+DNNMG_NONFINITE_CORRECTION, DNNMG_NONFINITE_RHS = 1, 2
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
 
 SYMBOLS = [
@@ -28,7 +30,7 @@ SYMBOLS = [
     "dnnmg_batch_prepare", "dnnmg_batch_launch", "dnnmg_batch_captures", "dnnmg_step_batch", "dnnmg_destroy", "dnnmg_last_error", "dnnmg_prolong", "dnnmg_defect",
     "dnnmg_rhs_restrict", "dnnmg_get_state", "dnnmg_set_state", "dnnmg_patch_output",
     "dnnmg_step_count", "dnnmg_profile_enable", "dnnmg_profile_read", "dnnmg_quantize_e4m3",
-    "dnnmg_noalloc_scratch_bytes", "dnnmg_rhs_restrict_noalloc",
+    "dnnmg_noalloc_scratch_bytes", "dnnmg_rhs_restrict_noalloc", "dnnmg_nonfinite",
 ]
 DNNMG_NOALLOC_MAX_PATCHES = 1 << 18
 
@@ -84,6 +86,7 @@ def lib():
     L.dnnmg_quantize_e4m3.argtypes = [vp, i, i, vp, vp, vp]
     L.dnnmg_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     L.dnnmg_noalloc_scratch_bytes.argtypes = []; L.dnnmg_noalloc_scratch_bytes.restype = sz
+    L.dnnmg_nonfinite.argtypes = [vp, i, ctypes.POINTER(ctypes.c_int), vp]
     L.dnnmg_rhs_restrict_noalloc.argtypes = [i, i, i, ctypes.c_double, vp, vp, vp, vp, vp]
     for name in SYMBOLS:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
@@ -212,6 +215,13 @@ class DnnMG:
         import torch
         _check(lib().dnnmg_patch_output(self.handle, _ptr(d_out, torch.float32, self.s["P"] * self.s["nout"],
                                                           "d_out"), _stream(stream)))
+
+    def nonfinite(self, clear=True, stream=None) -> int:
+        """dnnmg_nonfinite: DNNMG_NONFINITE_* bits recorded since the last clear
+        (waits for the stream's work)."""
+        out = ctypes.c_int(0)
+        _check(lib().dnnmg_nonfinite(self.handle, 1 if clear else 0, ctypes.byref(out), _stream(stream)))
+        return int(out.value)
 
     def profile_enable(self, max_steps: int):
         _check(lib().dnnmg_profile_enable(self.handle, max_steps))

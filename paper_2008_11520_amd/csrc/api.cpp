@@ -82,7 +82,8 @@ int check_config(const dnnmg_config *c)
     if (c->precision < DNNMG_FP32 || c->precision > DNNMG_FP8_E4M3)
         return fail(DNNMG_EINVAL, "precision %d unknown", c->precision);
     if (c->dirichlet > 15u) return fail(DNNMG_EINVAL, "dirichlet flags 0x%x out of range", c->dirichlet);
-    if ((c->flags & ~(unsigned)DNNMG_F_UNFUSED) != 0u) return fail(DNNMG_EINVAL, "unknown flags 0x%x", c->flags);
+    if ((c->flags & ~(unsigned)(DNNMG_F_UNFUSED | DNNMG_F_NANCHECK)) != 0u)
+        return fail(DNNMG_EINVAL, "unknown flags 0x%x", c->flags);
     if (c->H <= 0 || c->Hm < 0) return fail(DNNMG_EINVAL, "H must be > 0 and Hm >= 0");
     if (c->H != 32 && c->H != 64 && c->H != 128)
         return fail(DNNMG_EUNSUPPORTED, "H = %d has no kernels (32, 64, 128)", c->H);
@@ -99,7 +100,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Device layout of one context's workspace.
 struct Layout {
-    size_t geo, geo64, feat, h, uprev, X, sx, dpatch, part, part2, cxy, flag, bad, total;
+    size_t geo, geo64, feat, h, uprev, X, sx, dpatch, part, part2, cxy, flag, bad, nonfinite, total;
 };
 
 Layout layout_of(const dnnmg_config &c)
@@ -126,6 +127,7 @@ Layout layout_of(const dnnmg_config &c)
     L.cxy = take(sizeof(double) * 2 * (size_t)s.Nc);
     L.flag = take(sizeof(int));
     L.bad = take(sizeof(int));
+    L.nonfinite = take(sizeof(int));
     L.total = o;
     return L;
 }
@@ -446,6 +448,7 @@ FlowArgs flow_args(const dnnmg_ctx *c, const float *v, const float *p)
     f.sx = c->sx();
     f.dpatch = c->dpatch();
     f.part = c->part();
+    f.nonfinite = (c->cfg.flags & DNNMG_F_NANCHECK) ? (int *)(c->ws + c->L.nonfinite) : nullptr;
     return f;
 }
 
@@ -495,6 +498,7 @@ int create_common(const dnnmg_config *cfg, const double *cxy, const float *weigh
     if (e == hipSuccess) e = hipMemsetAsync(c->h(), 0, sizeof(float) * (size_t)s.P * cfg->H, st);
     if (e == hipSuccess) e = hipMemsetAsync(c->uprev(), 0, sizeof(float) * 2 * s.Fu, st);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + c->L.bad, 0, sizeof(int), st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + c->L.nonfinite, 0, sizeof(int), st);
     if (e == hipSuccess) e = hipMemsetAsync(c->first_flag(), 1, sizeof(int), st);
     if (e == hipSuccess)
         e = launch_geometry((const double *)(c->ws + c->L.cxy), cfg->nx, cfg->ny, c->geo(), c->geo64(), c->feat(),
@@ -820,6 +824,21 @@ extern "C" int dnnmg_set_state(dnnmg_ctx *ctx, const float *h, const float *u, l
                                         ctx->cfg.ny * ctx->s.n + 1, hipMemcpyDeviceToDevice, st));
     HIP_OR_FAIL(hipMemsetAsync(ctx->first_flag(), steps == 0 ? 1 : 0, sizeof(int), st));
     ctx->steps = steps;
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_nonfinite(dnnmg_ctx *ctx, int clear, int *flags_out, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!flags_out) return fail(DNNMG_EINVAL, "flags_out is NULL");
+    if (!(ctx->cfg.flags & DNNMG_F_NANCHECK)) return fail(DNNMG_ESTATE, "context created without DNNMG_F_NANCHECK");
+    hipStream_t st = (hipStream_t)stream;
+    int v = 0;
+    HIP_OR_FAIL(hipMemcpyAsync(&v, ctx->ws + ctx->L.nonfinite, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (clear) HIP_OR_FAIL(hipMemsetAsync(ctx->ws + ctx->L.nonfinite, 0, sizeof(int), st));
+    HIP_OR_FAIL(hipStreamSynchronize(st));
+    *flags_out = v;
     return DNNMG_OK;
 }
 

@@ -38,6 +38,7 @@ struct FlowArgs {
     float *D;              // stage only: Fn x 2 defect at the fine nodes
     const float *dbar_in;  // stage: given fine correction (rhs/restrict alone)
     double *bL;            // restricted rhs output (gather)
+    int *nonfinite;        // non-finite check (or nullptr): bit 0 correction, bit 1 restricted rhs
 };
 
 // Shared network description.

@@ -197,7 +197,9 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
     //      the mean is defined), Dirichlet mask, corrected velocity.
     const float2 *sd2 = s_buf;
     // Any tile node (li, lj); the patch offsets are those of the staged ring.
-    // Returns the node's averaged correction.
+    // Returns the node's averaged correction.  nonfin: this thread has
+    // averaged a correction that is not finite (the step's non-finite check).
+    bool nonfin = false;
     auto node = [&](int li, int lj) -> float2 {
         const int I = I0 + li, J = J0 + lj;
         float2 d = make_float2(0.f, 0.f);
@@ -218,6 +220,7 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                 const float inv = (lft && low) ? 0.25f : ((lft || low) ? 0.5f : 1.0f);
                 d = make_float2(acc.x * inv, acc.y * inv);
                 if (dirichlet_node<K>(f.dirichlet, I, J, NX, NY)) d = make_float2(0.f, 0.f);
+                nonfin |= !(__builtin_isfinite(d.x) && __builtin_isfinite(d.y));
                 const bool owned = (li < kRhsFine || I == NX) && (lj < kRhsFine || J == NY);
                 if (owned) {
                     // P v at the node from the corners of its (left/lower) patch,
@@ -283,6 +286,7 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                 const float inv = (lft && low) ? 0.25f : ((lft || low) ? 0.5f : 1.0f);
                 float2 d = make_float2(acc.x * inv, acc.y * inv);
                 if (mrow || (a == 0 && mcol)) d = make_float2(0.f, 0.f);
+                nonfin |= !(__builtin_isfinite(d.x) && __builtin_isfinite(d.y));
                 const float xi = a * (1.0f / n);
                 const float pvx = lx + dx * xi, pvy = ly + dy * xi;
                 urow[a] = make_float2(pvx + d.x, pvy + d.y);
@@ -307,6 +311,7 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                 for (int a = 0; a < n; ++a) s_dbar[dpos[o] + a] = dreg[o][a];
             }
         if (lpos >= 0) s_dbar[lpos] = dlast;
+        if (nonfin && f.nonfinite) atomicOr(f.nonfinite, 1);
     }
     __syncthreads();
 
@@ -416,6 +421,7 @@ __device__ __forceinline__ void gather_tile(const FlowArgs &f, int blk)
     if (i > 0 && j < ny) { const double2 q = pl[1 * P + (size_t)j * nx + i - 1]; bx += q.x; by += q.y; }
     if (i < nx && j < ny) { const double2 q = pl[(size_t)j * nx + i]; bx += q.x; by += q.y; }
     reinterpret_cast<double2 *>(f.bL)[t] = make_double2(bx, by);
+    if (f.nonfinite && !(__builtin_isfinite(bx) && __builtin_isfinite(by))) atomicOr(f.nonfinite, 2);
 }
 
 // Single flow: one tile per block.  Batched: the blocks stride over the
