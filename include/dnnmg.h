@@ -186,6 +186,34 @@ int dnnmg_step_batch(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int nflows,
 
 int dnnmg_destroy(dnnmg_ctx *ctx);
 
+/* ---------------------------------------------------------------------
+ * Device arena (serving form: flows admitted and retired while others run).
+ * One hipMalloc of `bytes` and a pinned staging ring of `staging_bytes` when
+ * the arena is made; contexts made in it take their workspace from it (first
+ * fit) and return it when destroyed, so dnnmg_create_in_arena and
+ * dnnmg_destroy of such a context neither allocate, free nor synchronise a
+ * stream (the coarse coordinates travel through the staging ring with an
+ * asynchronous copy; the mesh orientation is checked on the host).  A freed
+ * block is reused by later contexts, whose set-up is enqueued on their
+ * creation stream: on one stream it follows the destroyed context's work;
+ * across streams, wait for that work before destroying.  Not thread-safe.
+ * ------------------------------------------------------------------- */
+typedef struct dnnmg_arena dnnmg_arena;
+int dnnmg_arena_create(size_t bytes, size_t staging_bytes, dnnmg_arena **out);
+/* DNNMG_ESTATE while contexts still use the arena. */
+int dnnmg_arena_destroy(dnnmg_arena *arena);
+/* Bytes a context of this configuration takes from an arena (its weights
+ * are the model's); 0 if cfg is invalid. */
+size_t dnnmg_arena_block_bytes(const dnnmg_config *cfg);
+/* Bytes in use, and the largest free block. */
+int dnnmg_arena_usage(const dnnmg_arena *arena, size_t *used, size_t *largest_free);
+/* dnnmg_create_shared with the workspace taken from `arena`.  DNNMG_ENOMEM if
+ * no free block is large enough (nothing is changed); DNNMG_EINVAL for the
+ * cases of dnnmg_create_shared, and if the coordinates exceed the staging
+ * ring.  No host synchronisation. */
+int dnnmg_create_in_arena(dnnmg_arena *arena, const dnnmg_config *cfg, const double *coarse_xy_host,
+                          const dnnmg_ctx *model, void *stream, dnnmg_ctx **out);
+
 /* Last error message of the calling thread ("" if none). */
 const char *dnnmg_last_error(void);
 

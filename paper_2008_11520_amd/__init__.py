@@ -31,6 +31,8 @@ SYMBOLS = [
     "dnnmg_rhs_restrict", "dnnmg_get_state", "dnnmg_set_state", "dnnmg_patch_output",
     "dnnmg_step_count", "dnnmg_profile_enable", "dnnmg_profile_read", "dnnmg_quantize_e4m3",
     "dnnmg_noalloc_scratch_bytes", "dnnmg_rhs_restrict_noalloc", "dnnmg_nonfinite",
+    "dnnmg_arena_create", "dnnmg_arena_destroy", "dnnmg_arena_block_bytes", "dnnmg_arena_usage",
+    "dnnmg_create_in_arena",
 ]
 DNNMG_NOALLOC_MAX_PATCHES = 1 << 18
 
@@ -87,6 +89,11 @@ def lib():
     L.dnnmg_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     L.dnnmg_noalloc_scratch_bytes.argtypes = []; L.dnnmg_noalloc_scratch_bytes.restype = sz
     L.dnnmg_nonfinite.argtypes = [vp, i, ctypes.POINTER(ctypes.c_int), vp]
+    L.dnnmg_arena_create.argtypes = [sz, sz, ctypes.POINTER(vp)]
+    L.dnnmg_arena_destroy.argtypes = [vp]
+    L.dnnmg_arena_block_bytes.argtypes = [cp]; L.dnnmg_arena_block_bytes.restype = sz
+    L.dnnmg_arena_usage.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    L.dnnmg_create_in_arena.argtypes = [vp, cp, vp, vp, vp, ctypes.POINTER(vp)]
     L.dnnmg_rhs_restrict_noalloc.argtypes = [i, i, i, ctypes.c_double, vp, vp, vp, vp, vp]
     for name in SYMBOLS:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
@@ -144,7 +151,7 @@ class DnnMG:
     """One flow of the fine-level DNN-MG step (see include/dnnmg.h)."""
 
     def __init__(self, cfg: Config, coarse_xy: np.ndarray, weights: np.ndarray | None = None,
-                 share: "DnnMG | None" = None, stream=None):
+                 share: "DnnMG | None" = None, stream=None, arena: "Arena | None" = None):
         import torch
         self.cfg = cfg
         self.s = sizes(cfg.nx, cfg.ny, cfg.K)
@@ -152,7 +159,13 @@ class DnnMG:
         if self._cxy.size != 2 * self.s["Nc"]:
             raise ValueError("coarse_xy must hold %d values" % (2 * self.s["Nc"]))
         h = ctypes.c_void_p()
-        if share is None:
+        if arena is not None:
+            if share is None:
+                raise ValueError("a context in an arena shares a model's weights (share=...)")
+            _check(lib().dnnmg_create_in_arena(arena.handle, ctypes.byref(cfg),
+                                               self._cxy.ctypes.data_as(ctypes.c_void_p), share.handle,
+                                               _stream(stream), ctypes.byref(h)))
+        elif share is None:
             w = np.ascontiguousarray(weights, dtype=np.float32).reshape(-1)
             _check(lib().dnnmg_create(ctypes.byref(cfg), self._cxy.ctypes.data_as(ctypes.c_void_p),
                                       w.ctypes.data_as(ctypes.c_void_p), w.size, _stream(stream),
@@ -259,6 +272,38 @@ def quantize_e4m3(a, q_out, scale_out, stream=None):
                                      _ptr(scale_out, torch.float32, rows, "scale_out"), _stream(stream)))
 
 
+class Arena:
+    """Device arena for serving (dnnmg_arena_*): contexts made with
+    DnnMG(..., share=model, arena=arena) take their workspace from it."""
+
+    def __init__(self, nbytes: int, staging_bytes: int = 8 << 20):
+        h = ctypes.c_void_p()
+        _check(lib().dnnmg_arena_create(int(nbytes), int(staging_bytes), ctypes.byref(h)))
+        self.handle = h
+        self.nbytes = int(nbytes)
+
+    @staticmethod
+    def block_bytes(cfg: Config) -> int:
+        return int(lib().dnnmg_arena_block_bytes(ctypes.byref(cfg)))
+
+    def usage(self):
+        """(bytes in use, largest free block)."""
+        used, largest = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().dnnmg_arena_usage(self.handle, ctypes.byref(used), ctypes.byref(largest)))
+        return int(used.value), int(largest.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().dnnmg_arena_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def noalloc_scratch_bytes() -> int:
     return int(lib().dnnmg_noalloc_scratch_bytes())
 
@@ -311,6 +356,20 @@ class Batch:
     def prepare(self, flows, vs, ps=None, d_outs=None, b_outs=None, stream=None):
         nf, arr, va, pa, da, ba = self._arrays(flows, vs, ps, d_outs, b_outs)
         _check(lib().dnnmg_batch_prepare(self.handle, arr, nf, va, pa, da, ba, _stream(stream)))
+
+    def prepare_raw(self, n, handles, v_ptrs, p_ptrs=None, b_ptrs=None, stream=None):
+        """dnnmg_batch_prepare from arrays of n context handles and device
+        pointers (contiguous numpy uintp arrays, as the serving loop keeps
+        them; p_ptrs and b_ptrs may be None).  No per-flow checks here beyond
+        the library's own."""
+        def arr(a):
+            if a is None:
+                return None
+            if a.dtype != np.uintp or not a.flags.c_contiguous or a.size < n:
+                raise ValueError("pointer arrays must be contiguous uintp with >= n entries")
+            return ctypes.c_void_p(a.ctypes.data)
+        _check(lib().dnnmg_batch_prepare(self.handle, arr(handles), int(n), arr(v_ptrs), arr(p_ptrs), None,
+                                         arr(b_ptrs), _stream(stream)))
 
     def launch(self, graph=False, stream=None):
         _check(lib().dnnmg_batch_launch(self.handle, 1 if graph else 0, _stream(stream)))

@@ -11,10 +11,13 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
 
+#include "arena.h"
 #include "dnnmg.h"
 #include "internal.h"
 
@@ -221,6 +224,8 @@ struct Profile {
 };
 static void profile_release(Profile &pr);
 
+struct dnnmg_arena;
+
 struct dnnmg_ctx {
     dnnmg_config cfg;
     Profile prof;
@@ -230,6 +235,7 @@ struct dnnmg_ctx {
     Weights *w = nullptr;
     long long steps = 0;
     int device = 0;
+    dnnmg_arena *arena = nullptr;   // the workspace is a block of this arena (not hipMalloc'd)
 
     float *geo() const { return (float *)(ws + L.geo); }
     double *geo64() const { return (double *)(ws + L.geo64); }
@@ -520,6 +526,74 @@ int check_ctx(const dnnmg_ctx *c)
 
 }  // namespace
 
+// ------------------------------------------------------------------ arena
+// Device memory for serving: one hipMalloc when the arena is made; contexts
+// made in it take their workspace from it (first fit, 256-byte blocks) and
+// give it back when destroyed, so admitting and retiring flows neither
+// allocates, frees nor synchronises.  Coarse coordinates reach the device
+// through a pinned staging ring (asynchronous copies); a ring slot is reused
+// once the event recorded after its copy has completed.  The bookkeeping
+// (BlockList, StageRing) is host code in arena.h.
+struct dnnmg_arena {
+    unsigned char *base = nullptr;
+    BlockList blocks;
+    int live = 0;                           // contexts holding a block
+    unsigned char *stage = nullptr;         // pinned staging ring
+    StageRing ring;
+    std::deque<hipEvent_t> slot_events;     // one per live ring slot, oldest first
+    std::vector<hipEvent_t> events;         // idle events
+    int device = 0;
+};
+
+namespace {
+
+// Release the ring slots whose copies have completed (oldest first); with
+// wait, first block on the oldest one.
+int arena_reclaim(dnnmg_arena *a, bool wait)
+{
+    while (!a->slot_events.empty()) {
+        hipEvent_t ev = a->slot_events.front();
+        hipError_t e = wait ? hipEventSynchronize(ev) : hipEventQuery(ev);
+        if (e == hipErrorNotReady) return DNNMG_OK;
+        if (e != hipSuccess) return fail(DNNMG_EDEVICE, "staging event: %s", hipGetErrorString(e));
+        a->slot_events.pop_front();
+        a->events.push_back(ev);
+        a->ring.pop_oldest();
+        wait = false;
+    }
+    return DNNMG_OK;
+}
+
+// A staging slot of `bytes` and an idle event for it, waiting for the oldest
+// slots' copies only when the ring (or the event pool) is full.
+int arena_stage(dnnmg_arena *a, size_t bytes, size_t *off)
+{
+    if (arena_round(bytes) > a->ring.bytes)
+        return fail(DNNMG_EINVAL, "%zu coordinate bytes exceed the arena's staging ring", bytes);
+    int rc = arena_reclaim(a, false);
+    while (rc == DNNMG_OK && (a->events.empty() || !a->ring.place(bytes, off))) rc = arena_reclaim(a, true);
+    return rc;
+}
+
+// The check the geometry kernel makes, on the host: det J of the bilinear
+// map is positive at the four corners of every element.
+bool mesh_positively_oriented(const double *cxy, int nx, int ny)
+{
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const double *c00 = cxy + 2 * ((size_t)j * (nx + 1) + i), *c10 = c00 + 2;
+            const double *c01 = c00 + 2 * (nx + 1), *c11 = c01 + 2;
+            const double exx = c10[0] - c00[0], exy = c10[1] - c00[1];
+            const double eyx = c01[0] - c00[0], eyy = c01[1] - c00[1];
+            const double twx = c11[0] - c10[0] - c01[0] + c00[0], twy = c11[1] - c10[1] - c01[1] + c00[1];
+            const double d0 = exx * eyy - exy * eyx, d1 = exx * twy - exy * twx, d2 = twx * eyy - twy * eyx;
+            if (!(d0 > 0.0 && d0 + d1 > 0.0 && d0 + d2 > 0.0 && d0 + d1 + d2 > 0.0)) return false;
+        }
+    return true;
+}
+
+}  // namespace
+
 // ================================================================ ABI
 extern "C" size_t dnnmg_weight_count(const dnnmg_config *cfg)
 {
@@ -552,9 +626,135 @@ extern "C" int dnnmg_destroy(dnnmg_ctx *ctx)
     for (hipEvent_t e : ctx->prof.ev) (void)hipEventSynchronize(e);
     for (hipEvent_t e : ctx->prof.evg) (void)hipEventSynchronize(e);
     profile_release(ctx->prof);
-    (void)hipFree(ctx->ws);
+    if (ctx->arena) {
+        ctx->arena->blocks.give((size_t)(ctx->ws - ctx->arena->base), ctx->L.total);
+        ctx->arena->live--;
+    } else {
+        (void)hipFree(ctx->ws);
+    }
     release_weights(ctx->w);
     delete ctx;
+    return DNNMG_OK;
+}
+
+extern "C" size_t dnnmg_arena_block_bytes(const dnnmg_config *cfg)
+{
+    if (check_config(cfg) != DNNMG_OK) return 0;
+    return align256(layout_of(*cfg).total);
+}
+
+extern "C" int dnnmg_arena_create(size_t bytes, size_t staging_bytes, dnnmg_arena **out)
+{
+    if (!out) return fail(DNNMG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (bytes < 256 || staging_bytes < 256) return fail(DNNMG_EINVAL, "arena and staging sizes must be >= 256 bytes");
+    dnnmg_arena *a = new dnnmg_arena();
+    a->blocks.init(bytes);
+    a->ring.init(staging_bytes);
+    (void)hipGetDevice(&a->device);
+    bool ok = hipMalloc((void **)&a->base, a->blocks.bytes) == hipSuccess &&
+              hipHostMalloc((void **)&a->stage, a->ring.bytes, hipHostMallocDefault) == hipSuccess;
+    for (int i = 0; ok && i < 64; ++i) {
+        hipEvent_t e = nullptr;
+        ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+        if (ok) a->events.push_back(e);
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        if (a->base) (void)hipFree(a->base);
+        if (a->stage) (void)hipHostFree(a->stage);
+        for (hipEvent_t e : a->events) (void)hipEventDestroy(e);
+        delete a;
+        return fail(DNNMG_ENOMEM, "arena of %zu bytes (staging %zu) could not be allocated", bytes, staging_bytes);
+    }
+    *out = a;
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_arena_destroy(dnnmg_arena *a)
+{
+    if (!a) return fail(DNNMG_EINVAL, "arena is NULL");
+    if (a->live > 0) return fail(DNNMG_ESTATE, "%d contexts still use the arena", a->live);
+    while (!a->slot_events.empty()) {
+        int rc = arena_reclaim(a, true);
+        if (rc) return rc;
+    }
+    for (hipEvent_t e : a->events) (void)hipEventDestroy(e);
+    (void)hipFree(a->base);
+    (void)hipHostFree(a->stage);
+    delete a;
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_arena_usage(const dnnmg_arena *a, size_t *used, size_t *largest_free)
+{
+    if (!a || !used || !largest_free) return fail(DNNMG_EINVAL, "arena, used and largest_free must not be NULL");
+    *used = a->blocks.used;
+    *largest_free = a->blocks.largest();
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_create_in_arena(dnnmg_arena *a, const dnnmg_config *cfg, const double *cxy,
+                                     const dnnmg_ctx *model, void *stream, dnnmg_ctx **out)
+{
+    if (!out) return fail(DNNMG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!a) return fail(DNNMG_EINVAL, "arena is NULL");
+    if (!model) return fail(DNNMG_EINVAL, "model is NULL");
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    if (!cxy) return fail(DNNMG_EINVAL, "coarse_xy_host is NULL");
+    const Weights *w = model->w;
+    if (w->K != cfg->K || w->H != cfg->H || w->Hm != cfg->Hm || w->prec != cfg->precision)
+        return fail(DNNMG_EINVAL, "shared weights have another K/H/Hm/precision");
+    const size_t ncxy = 2 * (size_t)(cfg->nx + 1) * (cfg->ny + 1);
+    for (size_t i = 0; i < ncxy; ++i)
+        if (!std::isfinite(cxy[i])) return fail(DNNMG_EINVAL, "coarse_xy_host[%zu] is not finite", i);
+    if (!mesh_positively_oriented(cxy, cfg->nx, cfg->ny))
+        return fail(DNNMG_EINVAL, "coarse mesh has an element that is not positively oriented");
+    const Layout L = layout_of(*cfg);
+    size_t off = 0, soff = 0;
+    if (!a->blocks.take(L.total, &off))
+        return fail(DNNMG_ENOMEM, "arena has no free block of %zu bytes (%zu of %zu in use)", align256(L.total),
+                    a->blocks.used, a->blocks.bytes);
+    rc = arena_stage(a, sizeof(double) * ncxy, &soff);
+    if (rc) { a->blocks.give(off, L.total); return rc; }
+    hipStream_t st = (hipStream_t)stream;
+    dnnmg_ctx *c = new dnnmg_ctx();
+    c->cfg = *cfg;
+    c->s = sizes_of(*cfg);
+    c->L = L;
+    c->device = a->device;
+    c->arena = a;
+    c->ws = a->base + off;
+    c->w = model->w;
+    const Sizes &s = c->s;
+    std::memcpy(a->stage + soff, cxy, sizeof(double) * ncxy);
+    hipError_t e = hipMemcpyAsync(c->ws + L.cxy, a->stage + soff, sizeof(double) * ncxy, hipMemcpyHostToDevice, st);
+    hipEvent_t ev = a->events.back();
+    if (e == hipSuccess) e = hipEventRecord(ev, st);
+    if (e == hipSuccess) {
+        a->events.pop_back();
+        a->ring.push(soff, sizeof(double) * ncxy);
+        a->slot_events.push_back(ev);
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(c->h(), 0, sizeof(float) * (size_t)s.P * cfg->H, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->uprev(), 0, sizeof(float) * 2 * s.Fu, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.nonfinite, 0, sizeof(int), st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->first_flag(), 1, sizeof(int), st);
+    if (e == hipSuccess)
+        e = launch_geometry((const double *)(c->ws + L.cxy), cfg->nx, cfg->ny, c->geo(), c->geo64(), c->feat(),
+                            (int *)(c->ws + L.bad), st);
+    if (e != hipSuccess) {
+        // the enqueued work may still touch the block: wait for it before returning the block
+        (void)hipStreamSynchronize(st);
+        a->blocks.give(off, L.total);
+        delete c;
+        return fail(DNNMG_EDEVICE, "create in arena: %s", hipGetErrorString(e));
+    }
+    ++c->w->refs;
+    a->live++;
+    *out = c;
     return DNNMG_OK;
 }
 

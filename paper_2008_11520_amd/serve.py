@@ -8,24 +8,33 @@ that arrive while others run join at the next tick boundary and finished ones
 leave.  Each flow keeps its GRU state and corrected velocity resident on the
 device between ticks.
 
+The flows' state and workspace live in one device arena made when the server
+starts (dnnmg_arena_*): admitting a request carves its block and enqueues its
+set-up on the serving stream, retiring it returns the block; neither
+allocates, frees or waits for the stream, so the ticks already in flight keep
+the GPU busy while the host admits and retires.
+
 The coarse solve is not part of this build: each admitted request gets a ring
 of `ring` coarse (v, p) time levels evaluated on the device from its seeded
-Fourier field, and step n reads level n mod ring.
+Fourier field (calibrated on the device too, without a read-back), and step
+n reads level n mod ring.
 
 Per-step latency is the time from the moment a flow's step becomes eligible
 (its admission, or the completion of its previous step) to the completion of
 the tick that carries it.  Ticks are pipelined: while the GPU runs one, the
-host admits arrivals and issues the next, and a flow's buffers are released
-only after the tick with its last step has finished.
+host admits arrivals and issues the next, and a flow's block is returned only
+after the tick with its last step has finished.  The per-tick flow table is
+formed from numpy arrays of handles and device pointers, rebuilt only when
+the membership changes.
 """
 from __future__ import annotations
 
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 
-from . import DnnMG, Batch, make_config, workspace_bytes, synth
+from . import DnnMG, Arena, Batch, DnnmgError, DNNMG_ENOMEM, make_config, synth
 
 
 class Scheduler:
@@ -44,15 +53,23 @@ class Scheduler:
                              % (req.get("id"), self.cost(req), self.budget))
         self.queue.append(req)
 
-    def admissible(self):
-        """Pop and return the requests that can start now."""
+    def admissible(self, limit=None):
+        """Pop and return the requests that can start now (at most `limit`)."""
         out = []
-        while self.queue and self.running < self.max_flows and self.used + self.cost(self.queue[0]) <= self.budget:
+        while (self.queue and self.running < self.max_flows and self.used + self.cost(self.queue[0]) <= self.budget
+               and (limit is None or len(out) < limit)):
             r = self.queue.pop(0)
             self.used += self.cost(r)
             self.running += 1
             out.append(r)
         return out
+
+    def requeue(self, req):
+        """Undo the admission of req (its memory could not be placed yet):
+        it goes back to the head of the queue."""
+        self.used -= self.cost(req)
+        self.running -= 1
+        self.queue.insert(0, req)
 
     def release(self, req):
         self.used -= self.cost(req)
@@ -62,16 +79,12 @@ class Scheduler:
 @dataclass
 class Active:
     req: dict
+    idx: int                 # the request's row in the server's per-request arrays
     ctx: DnnMG
-    vring: object           # (ring, Nc*2) float32 device tensor
-    pring: object           # (ring, Nc) float32 device tensor
-    b_out: object           # (Nc*2,) float64 device tensor: restricted rhs of the last step
-    bytes: int
-    step: int = 0            # steps issued
-    completed: int = 0       # steps whose tick has finished
-    eligible: float = 0.0
+    vring: object            # (ring, Nc*2) float32 device tensor
+    pring: object            # (ring, Nc) float32 device tensor
+    b_out: object            # (Nc*2,) float64 device tensor: restricted rhs of the last step
     admitted: float = 0.0
-    latencies: list = field(default_factory=list)
 
 
 class Server:
@@ -88,7 +101,8 @@ class Server:
             self.model = DnnMG(make_config(1, 1, K, H, Hm, dt, nu, precision, 15),
                                synth.rect_mesh(1, 1), w, stream=self.stream)
         free, total = torch.cuda.mem_get_info()
-        self.hbm_budget = int(hbm_budget if hbm_budget is not None else 0.8 * free)
+        self.hbm_budget = int(hbm_budget if hbm_budget is not None else min(0.5 * free, 16 << 30))
+        self.arena = Arena(self.hbm_budget)
         self.batch = Batch(max_flows)
 
     def warmup(self):
@@ -108,7 +122,7 @@ class Server:
             self.batch.prepare([self.model], [v], [p], None, [b], stream=self.stream)
             self.batch.launch(graph=self.use_graph, stream=self.stream)
         self.stream.synchronize()
-        a = self.admit(dict(id=-1, nx=4, ny=2, steps=1, field_seed=0), 0.0)
+        a = self.admit(dict(id=-1, nx=4, ny=2, steps=1, field_seed=0), -1, 0.0)
         with torch.cuda.stream(self.stream):
             self.batch.prepare([self.model, a.ctx], [v, a.vring[0]], [p, a.pring[0]], None, [b, a.b_out],
                                stream=self.stream)
@@ -116,29 +130,36 @@ class Server:
         self.stream.synchronize()
         self.retire(a)
 
-    def flow_bytes(self, nx, ny):
-        cfg = make_config(nx, ny, self.K, self.H, self.Hm, self.dt, self.nu, self.precision, synth.DIR_CHANNEL)
-        nc = (nx + 1) * (ny + 1)
-        return workspace_bytes(cfg) + self.ring * nc * 12 + nc * 16
+    def config(self, nx, ny):
+        return make_config(nx, ny, self.K, self.H, self.Hm, self.dt, self.nu, self.precision, synth.DIR_CHANNEL)
 
-    def admit(self, req, now):
+    def flow_bytes(self, nx, ny):
+        """Arena bytes of one request's flow (state and workspace)."""
+        return Arena.block_bytes(self.config(nx, ny))
+
+    def admit(self, req, idx, now):
+        """The request's context in the arena and its field ring, enqueued on
+        the serving stream; None if the arena has no block for it yet."""
         import torch
         nx, ny = req["nx"], req["ny"]
-        flow = synth.Flow(nx, ny, synth.rect_mesh(nx, ny, synth.CHANNEL_LX, synth.CHANNEL_LY), synth.DIR_CHANNEL,
-                          self.dt, synth.FourierField(synth.CHANNEL_LX, synth.CHANNEL_LY, req["field_seed"]),
-                          inflow_max=1.5)
-        cfg = make_config(nx, ny, self.K, self.H, self.Hm, self.dt, self.nu, self.precision, synth.DIR_CHANNEL)
+        cxy = synth.rect_mesh(nx, ny, synth.CHANNEL_LX, synth.CHANNEL_LY)
+        ff = synth.FourierField(synth.CHANNEL_LX, synth.CHANNEL_LY, req["field_seed"])
         with torch.cuda.stream(self.stream):
-            ctx = DnnMG(cfg, flow.cxy, share=self.model, stream=self.stream)
-            xy = torch.from_numpy(flow.cxy.reshape(-1, 2)).cuda()
-            flow.fourier.calibrate_torch(xy)
-            v, p = flow.fourier.fields_torch(xy, [n * self.dt for n in range(self.ring)], inflow_max=1.5)
+            try:
+                ctx = DnnMG(self.config(nx, ny), cxy, share=self.model, stream=self.stream, arena=self.arena)
+            except DnnmgError as e:
+                if e.code == DNNMG_ENOMEM:
+                    return None
+                raise
+            xy = synth.rect_mesh_torch(nx, ny, synth.CHANNEL_LX, synth.CHANNEL_LY, "cuda")
+            times = self.dt * torch.arange(self.ring, dtype=torch.float64, device="cuda")
+            v, p = synth.fields_torch_calibrated(ff, xy, times, inflow_max=1.5, height=synth.CHANNEL_LY)
             vring = v.reshape(self.ring, -1).float().contiguous()
             pring = p.float().contiguous()
             b_out = torch.empty(2 * ctx.s["Nc"], dtype=torch.float64, device="cuda")
-        return Active(req, ctx, vring, pring, b_out, self.flow_bytes(nx, ny), eligible=now, admitted=now)
+        return Active(req, idx, ctx, vring, pring, b_out, admitted=now)
 
-    def retire(self, a, results=None):
+    def retire(self, a, results=None, steps=0):
         import torch
         if results is not None:
             h = torch.empty(a.ctx.s["P"] * self.H, dtype=torch.float32, device="cuda")
@@ -147,46 +168,72 @@ class Server:
                 a.ctx.get_state(h, u, stream=self.stream)
             self.stream.synchronize()
             results[a.req["id"]] = dict(h=h.cpu().numpy(), u=u.cpu().numpy(), bL=a.b_out.cpu().numpy(),
-                                        steps=a.step, queue_delay=a.req["admitted_at"] - a.req["queued_at"])
+                                        steps=steps, queue_delay=a.req["admitted_at"] - a.req["queued_at"])
         a.ctx.close()
 
-    def run(self, requests, time_scale=1.0, log_every=0.0, results=None, depth=2):
+    def run(self, requests, time_scale=1.0, log_every=0.0, results=None, depth=2, admit_burst=4):
         """Serve `requests` (dicts with id, arrival [s], nx, ny, steps,
         field_seed).  Arrival times are divided by time_scale (10 = ten times
         the offered rate).  Up to `depth` ticks are in flight: the host admits
         requests and prepares tick n+1 while the GPU runs tick n (stream order
-        keeps them apart).  Returns pooled statistics; with a dict `results`,
+        keeps them apart); while ticks are in flight at most `admit_burst`
+        requests are admitted between two ticks.  Returns pooled statistics; with a dict `results`,
         also each request's final state (h, corrected velocity) and last b_L."""
         import collections
         import torch
         self.warmup()
         pending = sorted((dict(r) for r in requests), key=lambda r: r["arrival"])
+        nreq = len(pending)
+        # per-request arrays (row = position in arrival order)
+        nsteps = np.array([r["steps"] for r in pending], dtype=np.int64)
+        npatch = np.array([r["nx"] * r["ny"] for r in pending], dtype=np.int64)
+        issued = np.zeros(nreq, dtype=np.int64)
+        completed = np.zeros(nreq, dtype=np.int64)
+        eligible = np.zeros(nreq)
+        for i, r in enumerate(pending):
+            r["_idx"] = i
         sched = Scheduler(self.hbm_budget, self.max_flows, lambda r: self.flow_bytes(r["nx"], r["ny"]))
-        active, done = [], []            # flows still issuing steps; finished flows
-        inflight = collections.deque()   # ticks on the GPU: (start event, end event, members)
+        active = []                      # flows still issuing steps, in table order
+        by_idx = {}                      # request row -> Active, until retired
+        table = None                     # (rows, handles, vbase, pbase, bptr, vstride, pstride) of `active`
+        inflight = collections.deque()   # ticks on the GPU: (start event, end event, member rows)
         spare = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                  for _ in range(depth + 1)]
-        stats = dict(ticks=0, conc=0, patch_steps=0, busy=0.0, max_conc=0)
+        stats = dict(ticks=0, conc=0, patch_steps=0, busy=0.0, max_conc=0, done=0)
+        latencies = []
+        qdelay = []
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
         last_log = 0.0
 
+        def build_table():
+            rows = np.array([a.idx for a in active], dtype=np.int64)
+            u = np.uintp
+            handles = np.array([a.ctx.handle.value for a in active], dtype=u)
+            vbase = np.array([a.vring.data_ptr() for a in active], dtype=u)
+            pbase = np.array([a.pring.data_ptr() for a in active], dtype=u)
+            bptr = np.array([a.b_out.data_ptr() for a in active], dtype=u)
+            vstride = np.array([a.vring.stride(0) * 4 for a in active], dtype=u)
+            pstride = np.array([a.pring.stride(0) * 4 for a in active], dtype=u)
+            return rows, handles, vbase, pbase, bptr, vstride, pstride
+
         def complete_oldest():
-            e0, e1, members = inflight.popleft()
+            e0, e1, rows = inflight.popleft()
             e1.synchronize()
             t_done = now()
             stats["busy"] += e0.elapsed_time(e1) / 1e3
             spare.append((e0, e1))
-            for a in members:
-                a.latencies.append(t_done - a.eligible)
-                a.eligible = t_done
-                a.completed += 1
-                stats["patch_steps"] += a.req["nx"] * a.req["ny"]
-                if a.completed >= a.req["steps"]:
-                    a.req["finished_at"] = t_done
-                    done.append(a)
-                    self.retire(a, results)
-                    sched.release(a.req)
+            latencies.append(t_done - eligible[rows])
+            eligible[rows] = t_done
+            completed[rows] += 1
+            stats["patch_steps"] += int(npatch[rows].sum())
+            for i in rows[completed[rows] >= nsteps[rows]]:
+                a = by_idx.pop(int(i))
+                a.req["finished_at"] = t_done
+                qdelay.append(a.req["admitted_at"] - a.req["queued_at"])
+                self.retire(a, results, steps=int(issued[i]))
+                sched.release(a.req)
+                stats["done"] += 1
             return t_done
 
         while pending or sched.queue or active or inflight:
@@ -195,48 +242,66 @@ class Server:
                 r = pending.pop(0)
                 r["queued_at"] = r["arrival"] / time_scale
                 sched.arrive(r)
-            for r in sched.admissible():
-                a = self.admit(r, now())
+            # admissions, a few at a time while ticks are in flight (each
+            # costs host time: its set-up and field ring are enqueued), so
+            # the active flows' next tick is not held back by a burst
+            admitted = False
+            cap = admit_burst if inflight else len(sched.queue)
+            for r in sched.admissible(limit=cap):
+                a = self.admit(r, r["_idx"], now())
+                if a is None:                 # the arena is fragmented: wait for a release
+                    sched.requeue(r)
+                    break
                 r["admitted_at"] = a.admitted
+                eligible[a.idx] = a.admitted
                 active.append(a)
+                by_idx[a.idx] = a
+                admitted = True
+            if admitted:
+                table = None
             stats["max_conc"] = max(stats["max_conc"], len(active))
             if active and len(inflight) < depth:
                 # issue one tick: every active flow advances one step
-                flows = [a.ctx for a in active]
-                vs = [a.vring[a.step % self.ring] for a in active]
-                ps = [a.pring[a.step % self.ring] for a in active]
+                if table is None:
+                    table = build_table()
+                rows, handles, vbase, pbase, bptr, vstride, pstride = table
+                lvl = (issued[rows] % self.ring).astype(np.uintp)
+                vptr = vbase + lvl * vstride
+                pptr = pbase + lvl * pstride
                 e0, e1 = spare.pop()
                 with torch.cuda.stream(self.stream):
-                    self.batch.prepare(flows, vs, ps, None, [a.b_out for a in active], stream=self.stream)
+                    self.batch.prepare_raw(len(rows), handles, vptr, pptr, bptr, stream=self.stream)
                     e0.record(self.stream)
                     self.batch.launch(graph=self.use_graph, stream=self.stream)
                     e1.record(self.stream)
-                inflight.append((e0, e1, list(active)))
+                inflight.append((e0, e1, rows))
                 stats["ticks"] += 1
-                stats["conc"] += len(active)
-                for a in active:
-                    a.step += 1
-                active = [a for a in active if a.step < a.req["steps"]]
+                stats["conc"] += len(rows)
+                issued[rows] += 1
+                if np.any(issued[rows] >= nsteps[rows]):
+                    active = [a for a in active if issued[a.idx] < nsteps[a.idx]]
+                    table = None
                 continue
             if inflight:
                 t_done = complete_oldest()
                 if log_every and t_done - last_log > log_every:
                     last_log = t_done
                     print("serve: t=%.1fs active=%d queued=%d done=%d" % (t_done, len(active), len(sched.queue),
-                                                                           len(done)), flush=True)
+                                                                           stats["done"]), flush=True)
             elif pending:
                 time.sleep(max(0.0, min(pending[0]["arrival"] / time_scale - now(), 0.01)))
         wall = now()
-        lat = np.concatenate([np.asarray(a.latencies) for a in done]) if done else np.zeros(0)
-        qdelay = np.array([a.req["admitted_at"] - a.req["queued_at"] for a in done])
+        lat = np.concatenate(latencies) if latencies else np.zeros(0)
+        qd = np.asarray(qdelay)
         ticks = stats["ticks"]
         return {
-            "requests": len(done),
+            "requests": stats["done"],
             "steps": int(lat.size),
             "ticks": ticks,
             "depth": depth,
             "wall_s": wall,
             "gpu_busy_s": stats["busy"],
+            "gpu_busy_frac": stats["busy"] / wall if wall > 0 else 0.0,
             "patch_steps": stats["patch_steps"],
             "patch_steps_per_s": stats["patch_steps"] / wall if wall > 0 else 0.0,
             "mean_concurrency": stats["conc"] / ticks if ticks else 0.0,
@@ -244,11 +309,12 @@ class Server:
             "p50_step_latency_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
             "p99_step_latency_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
             "max_step_latency_ms": float(lat.max() * 1e3) if lat.size else None,
-            "p50_queue_delay_ms": float(np.percentile(qdelay, 50) * 1e3) if qdelay.size else None,
-            "p99_queue_delay_ms": float(np.percentile(qdelay, 99) * 1e3) if qdelay.size else None,
+            "p50_queue_delay_ms": float(np.percentile(qd, 50) * 1e3) if qd.size else None,
+            "p99_queue_delay_ms": float(np.percentile(qd, 99) * 1e3) if qd.size else None,
             "graph": self.use_graph,
         }
 
     def close(self):
         self.batch.close()
+        self.arena.close()
         self.model.close()

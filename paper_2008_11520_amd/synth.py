@@ -66,6 +66,16 @@ def rect_mesh(nx: int, ny: int, lx: float = 1.0, ly: float = 1.0,
     return np.stack([X, Y], axis=-1)
 
 
+def rect_mesh_torch(nx: int, ny: int, lx: float, ly: float, device):
+    """rect_mesh formed on a torch device ((ny+1)(nx+1) x 2 float64), the
+    same values: no host-to-device copy."""
+    import torch
+    xs = lx * torch.arange(nx + 1, dtype=torch.float64, device=device) / nx
+    ys = ly * torch.arange(ny + 1, dtype=torch.float64, device=device) / ny
+    Y, X = torch.meshgrid(ys, xs, indexing="ij")
+    return torch.stack([X, Y], dim=-1).reshape(-1, 2)
+
+
 def perturb_interior(cxy: np.ndarray, frac: float, seed: int) -> np.ndarray:
     """Move every interior coarse node by U[-frac*h, frac*h] in each direction
     (h = local spacing per direction); boundary nodes stay put."""
@@ -171,22 +181,29 @@ class FourierField:
     # The same fields evaluated with torch on a device tensor of node
     # coordinates (N x 2, float64), for inputs made on the GPU.
     def _raw_torch(self, xy, times):
+        """Raw v and p at the nodes for every time, all modes at once (a few
+        kernels whatever the number of modes): (T x N) each."""
         import torch
-        x, y = xy[:, 0][None, :], xy[:, 1][None, :]
-        t = torch.as_tensor(times, dtype=xy.dtype, device=xy.device)[:, None]
-        vx = torch.zeros(t.shape[0], xy.shape[0], dtype=xy.dtype, device=xy.device)
-        vy = torch.zeros_like(vx)
-        p = torch.zeros_like(vx)
-        for m in range(self.nmodes):
-            kx, ky = self.k[m]
-            inv = 1.0 / math.hypot(kx, ky)
-            c = torch.cos(2 * math.pi * (kx * x / self.lx + ky * y / self.ly) + self.phi[m] + self.om[m] * t)
-            c = c * (inv * 2 * math.pi)
-            vx += c * (ky / self.ly)
-            vy -= c * (kx / self.lx)
-        for m in range(self.pmodes):
-            kx, ky = self.pk[m]
-            p += torch.sin(2 * math.pi * (kx * x / self.lx + ky * y / self.ly) + self.pphi[m] + self.pom[m] * t)
+        dev, dt_ = xy.device, xy.dtype
+        x, y = xy[:, 0][None, :, None], xy[:, 1][None, :, None]
+        t = torch.as_tensor(times, dtype=dt_, device=dev).reshape(-1, 1, 1)
+
+        # the field's constants in one array, copied once (from pinned memory
+        # to a device: asynchronously, without waiting for the stream)
+        M, Mp = self.nmodes, self.pmodes
+        host = np.concatenate([self.k[:, 0], self.k[:, 1], self.phi, self.om,
+                               2 * math.pi / np.hypot(self.k[:, 0], self.k[:, 1]),
+                               self.pk[:, 0], self.pk[:, 1], self.pphi, self.pom])
+        cst = torch.from_numpy(host).to(dt_)
+        if dev.type != "cpu":
+            cst = cst.pin_memory().to(dev, non_blocking=True)
+        kx, ky, phi, om, inv = (cst[i * M:(i + 1) * M] for i in range(5))
+        pkx, pky, pphi, pom = (cst[5 * M + i * Mp:5 * M + (i + 1) * Mp] for i in range(4))
+        th = 2 * math.pi * (kx * x / self.lx + ky * y / self.ly) + phi + om * t
+        c = torch.cos(th) * inv
+        vx = (c * (ky / self.ly)).sum(-1)
+        vy = -(c * (kx / self.lx)).sum(-1)
+        p = torch.sin(2 * math.pi * (pkx * x / self.lx + pky * y / self.ly) + pphi + pom * t).sum(-1)
         return vx, vy, p
 
     def calibrate_torch(self, xy) -> "FourierField":
@@ -207,6 +224,31 @@ class FourierField:
             prof = 4.0 * y * (height - y) / (height * height)
             vx, vy = vx * prof + inflow_max * prof, vy * prof
         return torch.stack([vx, vy], dim=-1), p
+
+
+def fields_torch_calibrated(ff: "FourierField", xy, times, inflow_max=0.0, height=0.41):
+    """ff.fields_torch with the calibration (max |v| and max |p| over the
+    nodes at t = 0) done on the device as well: no value is read back to the
+    host, so evaluating a flow's fields does not wait for the stream's other
+    work.  Same scaling rule as calibrate()."""
+    import torch
+    # (times formed on the device: a host list would be copied with a
+    # stream synchronisation)
+    if not torch.is_tensor(times):
+        times = torch.as_tensor(times, dtype=xy.dtype).to(xy.device, non_blocking=True)
+    vx0, vy0, p0 = ff._raw_torch(xy, torch.zeros(1, dtype=xy.dtype, device=xy.device))
+    m = torch_hypot_max(vx0, vy0)
+    pm = p0.abs().max()
+    one = torch.ones((), dtype=xy.dtype, device=xy.device)
+    vscale = torch.where(m > 0, ff.amplitude / torch.where(m > 0, m, one), one)
+    pscale = torch.where(pm > 0, ff.p_amplitude / torch.where(pm > 0, pm, one), one)
+    vx, vy, p = ff._raw_torch(xy, times)
+    vx, vy, p = vx * vscale, vy * vscale, p * pscale
+    if inflow_max > 0.0:
+        y = xy[:, 1][None, :]
+        prof = 4.0 * y * (height - y) / (height * height)
+        vx, vy = vx * prof + inflow_max * prof, vy * prof
+    return torch.stack([vx, vy], dim=-1), p
 
 
 def torch_hypot_max(vx, vy):

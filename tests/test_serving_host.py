@@ -68,3 +68,40 @@ def test_torch_fields_match_numpy_fields(inflow):
         vn, pn = flow.fields(n)
         np.testing.assert_allclose(v[n].numpy().astype(np.float32), vn, rtol=0, atol=2e-6)
         np.testing.assert_allclose(p[n].numpy().astype(np.float32), pn, rtol=0, atol=2e-6)
+
+
+@pytest.mark.parametrize("inflow", [0.0, 1.5])
+def test_device_calibrated_fields_match_numpy_fields(inflow):
+    """The serving loop's field evaluation with the calibration kept on the
+    device (no host read-back) gives the numpy fields."""
+    import torch
+    nx, ny = 12, 5
+    cxy = synth.rect_mesh(nx, ny, synth.CHANNEL_LX, synth.CHANNEL_LY)
+    ff = synth.FourierField(synth.CHANNEL_LX, synth.CHANNEL_LY, 7).calibrate(cxy)
+    flow = synth.Flow(nx, ny, cxy, synth.DIR_CHANNEL, 0.005, ff, inflow_max=inflow)
+    xy = torch.from_numpy(cxy.reshape(-1, 2).copy())
+    v, p = synth.fields_torch_calibrated(synth.FourierField(synth.CHANNEL_LX, synth.CHANNEL_LY, 7), xy,
+                                         [n * 0.005 for n in range(3)], inflow_max=inflow, height=synth.CHANNEL_LY)
+    for n in range(3):
+        vn, pn = flow.fields(n)
+        np.testing.assert_allclose(v[n].numpy().astype(np.float32), vn, rtol=0, atol=2e-6)
+        np.testing.assert_allclose(p[n].numpy().astype(np.float32), pn, rtol=0, atol=2e-6)
+
+
+def test_device_mesh_equals_numpy_mesh():
+    import torch
+    for nx, ny in ((32, 8), (512, 128), (3, 1)):
+        a = synth.rect_mesh(nx, ny, synth.CHANNEL_LX, synth.CHANNEL_LY).reshape(-1, 2)
+        b = synth.rect_mesh_torch(nx, ny, synth.CHANNEL_LX, synth.CHANNEL_LY, "cpu").numpy()
+        assert np.array_equal(a, b)
+
+
+def test_scheduler_admission_limit():
+    s = Scheduler(budget=100, max_flows=8, cost=lambda r: r["cost"])
+    for r in _reqs([10, 10, 10, 10]):
+        s.arrive(r)
+    assert [r["id"] for r in s.admissible(limit=2)] == [0, 1]
+    assert [r["id"] for r in s.admissible(limit=0)] == []
+    assert [r["id"] for r in s.admissible()] == [2, 3]
+    s.requeue(dict(id=3, cost=10))
+    assert s.used == 30 and s.running == 3 and [r["id"] for r in s.queue] == [3]
