@@ -119,96 +119,77 @@ def calibrate_copy(mib):
     print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 3}))
 
 
-def run_gpu(wl, precision, steps, warmup, flags=0):
+def make_flow_leg(wl, precision, flags=0, copies=1):
+    """A single-flow leg: `copies` contexts of the workload's flow and its
+    coarse fields of 16 distinct steps, resident on the device."""
     import torch
     import paper_2008_11520_amd as pam
     from paper_2008_11520_amd import synth
     flow = wl.flows[0]
     w = synth.xavier_weights(wl.K, wl.H, wl.Hm, wl.weight_seed)
     cfg = pam.make_config(flow.nx, flow.ny, wl.K, wl.H, wl.Hm, flow.dt, wl.nu, precision, flow.dirichlet, flags)
-    g = pam.DnnMG(cfg, flow.cxy, w)
-    s = g.s
-    total = warmup + steps
-    # distinct coarse fields per step, resident on the device
-    nfield = min(total, 16)
+    ctxs = [pam.DnnMG(cfg, flow.cxy, w) for _ in range(copies)]
+    s = ctxs[0].s
     vs, ps = [], []
-    for n in range(nfield):
+    for n in range(16):
         v, p = flow.fields(n)
         vs.append(torch.from_numpy(v.reshape(-1)).cuda())
         ps.append(torch.from_numpy(p).cuda())
-    b = torch.empty(2 * s["Nc"], dtype=torch.float64, device="cuda")
-    stream = torch.cuda.current_stream()
-    for n in range(warmup):
-        g.step(vs[n % nfield], ps[n % nfield])
-        g.restrict_rhs(b)
-    torch.cuda.synchronize()
-    # the timed steps: no events between the kernels (each event record puts a
-    # few microseconds of idle time on the stream)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for n in range(steps):
-        k = (warmup + n) % nfield
-        g.step(vs[k], ps[k])
-        g.restrict_rhs(b)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    # the same loop again with the library's per-stage HIP events on the launch
-    # stream: the kernels' own durations (roofline, stage breakdown)
-    nprof = min(steps, 50)
-    g.profile_enable(nprof)
-    for n in range(nprof):
-        k = (warmup + steps + n) % nfield
-        g.step(vs[k], ps[k])
-        g.restrict_rhs(b)
-    torch.cuda.synchronize()
-    stage_ms, stage_n = g.profile_read()
-    g.profile_enable(0)
-    ok = bool(torch.isfinite(b).all().item())
-    g.close()
-    return dict(ms_total=ms, wall_s=wall, P=s["P"], stage_ms=stage_ms, stage_n=stage_n, finite=ok,
+    bs = [torch.empty(2 * s["Nc"], dtype=torch.float64, device="cuda") for _ in ctxs]
+    return dict(precision=precision, flags=flags, ctxs=ctxs, vs=vs, ps=ps, bs=bs, P=s["P"], n=0,
                 fused=is_fused(wl, precision, flags))
 
 
-def run_gpu_rotated(wl, precision, steps, warmup, copies=2):
-    """The same step with `copies` independent contexts of the flow stepped in
-    turn: their state (h, u_prev, workspace) together exceeds the 256 MB
-    last-level cache, so no step finds its inputs left in it by the step
-    before.  Returns ms per step (event-free timed loop)."""
-    import torch
-    import paper_2008_11520_amd as pam
-    from paper_2008_11520_amd import synth
-    flow = wl.flows[0]
-    w = synth.xavier_weights(wl.K, wl.H, wl.Hm, wl.weight_seed)
-    cfg = pam.make_config(flow.nx, flow.ny, wl.K, wl.H, wl.Hm, flow.dt, wl.nu, precision, flow.dirichlet)
-    ctxs = [pam.DnnMG(cfg, flow.cxy, w) for _ in range(copies)]
-    nfield = 4
-    vs, ps = [], []
-    for n in range(nfield):
-        v, p = flow.fields(n)
-        vs.append(torch.from_numpy(v.reshape(-1)).cuda())
-        ps.append(torch.from_numpy(p).cuda())
-    bs = [torch.empty(2 * c.s["Nc"], dtype=torch.float64, device="cuda") for c in ctxs]
-    for n in range(warmup * copies):
-        c = n % copies
-        ctxs[c].step(vs[n % nfield], ps[n % nfield])
+def step_leg(leg, count):
+    """Enqueue `count` steps (+ restriction), the contexts in turn."""
+    ctxs, vs, ps, bs = leg["ctxs"], leg["vs"], leg["ps"], leg["bs"]
+    for _ in range(count):
+        k = leg["n"]
+        c = k % len(ctxs)
+        ctxs[c].step(vs[k % 16], ps[k % 16])
         ctxs[c].restrict_rhs(bs[c])
-    torch.cuda.synchronize()
+        leg["n"] = k + 1
+
+
+def time_leg(leg, steps, warmup):
+    """Enqueue warmup untimed steps, then `steps` steps bracketed by events
+    with no events between the kernels (an event record puts a few
+    microseconds of idle time on the stream).  Returns the two events; the
+    caller synchronises once after all legs, so the GPU never waits for the
+    host between legs."""
+    import torch
     stream = torch.cuda.current_stream()
+    step_leg(leg, warmup)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for n in range(steps):
-        c = n % copies
-        ctxs[c].step(vs[n % nfield], ps[n % nfield])
-        ctxs[c].restrict_rhs(bs[c])
+    step_leg(leg, steps)
     e1.record(stream)
+    return e0, e1
+
+
+def profile_leg(leg, nprof=50):
+    """The same steps with the library's per-stage HIP events on the launch
+    stream: the kernels' own durations (roofline, stage breakdown)."""
+    import torch
+    g = leg["ctxs"][0]
+    g.profile_enable(nprof)
+    for _ in range(nprof):
+        k = leg["n"]
+        g.step(leg["vs"][k % 16], leg["ps"][k % 16])
+        g.restrict_rhs(leg["bs"][0])
+        leg["n"] = k + 1
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    for c in ctxs:
+    stage_ms, stage_n = g.profile_read()
+    g.profile_enable(0)
+    return stage_ms, stage_n
+
+
+def close_leg(leg):
+    import torch
+    ok = all(bool(torch.isfinite(b).all().item()) for b in leg["bs"])
+    for c in leg["ctxs"]:
         c.close()
-    return ms
+    return ok
 
 
 def run_gpu_batch(wl, precision, steps, warmup):
@@ -314,6 +295,48 @@ def run_serving(time_scales, n_requests=256, rate=20.0, hbm_budget=None, use_gra
     return out
 
 
+def run_closed_loop(steps=5, fine_steps=2):
+    """The closed DNN-MG loop (coarse Newton solve on level L, then the fine
+    step on the GPU) against the same Newton solver run on level L+K (the
+    fine solve DNN-MG replaces), per time step, on two flows."""
+    import numpy as np
+    from paper_2008_11520_amd import loop, synth
+    cases = [("unit16x16_k1", synth.unit_square_flow(16, 16, 1, 0.01), 1, 32, 0, "fp32"),
+             ("channel64x16_k2", synth.channel_flow(64, 16, 1, 0.005), 2, 64, 64, "bf16")]
+    out = []
+    nu = 1e-3
+    for name, flow, K, H, Hm, prec in cases:
+        w = synth.xavier_weights(K, H, Hm, 1234)
+        fine = loop.GpuFineStep(flow, K, H, Hm, w, nu, prec)
+        loop.run(flow, nu, 1, fine=fine)                      # first use of the kernels and solver paths
+        fine.seconds = 0.0
+        t0 = time.perf_counter()
+        r = loop.run(flow, nu, steps, fine=fine)
+        wall = time.perf_counter() - t0
+        fine.close()
+        n = 1 << K
+        fflow = synth.Flow(flow.nx * n, flow.ny * n,
+                           synth.rect_mesh(flow.nx * n, flow.ny * n, flow.cxy[-1, -1, 0], flow.cxy[-1, -1, 1]),
+                           flow.dirichlet, flow.dt, flow.fourier, inflow_max=flow.inflow_max)
+        t0 = time.perf_counter()
+        f = loop.run(fflow, nu, fine_steps)
+        fine_wall = time.perf_counter() - t0
+        res = {"case": name, "K": K, "precision": prec, "steps": steps, "fine_steps": fine_steps,
+               "dnnmg_ms_per_step": wall / steps * 1e3,
+               "coarse_solve_ms_per_step": r["coarse_s"] / steps * 1e3,
+               "fine_step_ms_per_step": fine.seconds / steps * 1e3,
+               "fine_solve_ms_per_step": fine_wall / fine_steps * 1e3,
+               "fine_over_dnnmg": (fine_wall / fine_steps) / (wall / steps),
+               "coarse_unknowns": 3 * (flow.nx + 1) * (flow.ny + 1),
+               "fine_unknowns": 3 * (fflow.nx + 1) * (fflow.ny + 1),
+               "newton_steps": r["newton"], "fine_newton_steps": f["newton"]}
+        out.append(res)
+        print("bench: closed loop %s: DNN-MG %.1f ms/step (coarse %.1f, fine step %.2f), fine solve %.1f ms/step"
+              % (name, res["dnnmg_ms_per_step"], res["coarse_solve_ms_per_step"], res["fine_step_ms_per_step"],
+                 res["fine_solve_ms_per_step"]), file=sys.stderr, flush=True)
+    return out
+
+
 def roofline(wl, flow, P, main_r, precision):
     """Roofline of the dominant stage: per-launch algorithmic work over the
     stage's average launch time from the library's HIP events on the launch
@@ -374,13 +397,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    # (the first few tens of milliseconds of steps after the GPU has idled run
-    # up to ~12 % slower while its clocks ramp up: the default warm-up covers
-    # that, about 0.12 s of the single-flow step)
-    ap.add_argument("--warmup", type=int, default=1000)
+    # (after the GPU has idled, its clocks take ~0.1 s of work to come up:
+    # the single-flow legs run back to back after a two-context leg of at
+    # least 600 steps, and each leg also takes `warmup` untimed steps)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="channel1024x256_k2_perturbed")
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-closed-loop", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
     ap.add_argument("--serving", default="offered,all", metavar="LIST",
                     help="serving runs after the throughput legs: comma list of offered (20/s), x10, x100, "
@@ -407,26 +431,47 @@ def main():
 
     forms = {}
     batched = len(wl.flows) > 1
-    # the headline form is timed last: the legs before it bring the GPU's
-    # clocks up from idle (the first tens of milliseconds of work after an
-    # idle period run slower), as they are in a running simulation
-    for prec in ([p for p in ("fp32", "fp8", "bf16") if p != args.precision] + [args.precision]):
-        r = (run_gpu_batch if batched else run_gpu)(wl, prec, args.steps, args.warmup)
-        forms[prec] = r
-        print("bench: %s %.3f ms/step" % (prec, r["ms_total"] / args.steps), file=sys.stderr, flush=True)
-    if not batched and args.precision == "bf16":
-        # the same BF16 step with defect and network as separate launches
-        import paper_2008_11520_amd as pam
-        r = run_gpu(wl, "bf16", args.steps, args.warmup, flags=pam.DNNMG_F_UNFUSED)
-        forms["bf16_unfused"] = r
-        print("bench: bf16 unfused %.3f ms/step" % (r["ms_total"] / args.steps), file=sys.stderr, flush=True)
-
     rotated = None
-    if not batched:
-        ms_rot = run_gpu_rotated(wl, args.precision, args.steps, args.warmup)
-        rotated = {"contexts": 2, "ms_per_step": ms_rot,
-                   "patch_steps_per_s": forms[args.precision]["P"] / (ms_rot / 1e3)}
+    busy_before_ms = None
+    if batched:
+        for prec in ([p for p in ("fp32", "fp8", "bf16") if p != args.precision] + [args.precision]):
+            r = run_gpu_batch(wl, prec, args.steps, args.warmup)
+            forms[prec] = r
+            print("bench: %s %.3f ms/step" % (prec, r["ms_total"] / args.steps), file=sys.stderr, flush=True)
+    else:
+        import paper_2008_11520_amd as pam
+        # Every context and input is made first, so that the timed legs run
+        # back to back with the GPU busy: its clocks come up from idle over
+        # the first ~0.1 s of work and drop again after a fraction of a second
+        # without it.  The two-context (last-level-cache-rotated) leg runs
+        # first, for at least 600 steps; the headline form is timed last.
+        order = [p for p in ("fp32", "fp8", "bf16") if p != args.precision]
+        legs = {p: make_flow_leg(wl, p) for p in order}
+        if args.precision == "bf16":
+            legs["bf16_unfused"] = make_flow_leg(wl, "bf16", flags=pam.DNNMG_F_UNFUSED)
+            order.append("bf16_unfused")
+        legs[args.precision] = make_flow_leg(wl, args.precision)
+        order.append(args.precision)
+        rot = make_flow_leg(wl, args.precision, copies=2)
+        torch.cuda.synchronize()
+        rot_steps = max(args.steps, 600)
+        start = torch.cuda.Event(enable_timing=True)
+        start.record(torch.cuda.current_stream())
+        ev_rot = time_leg(rot, rot_steps, args.warmup)
+        ev = {name: time_leg(legs[name], args.steps, args.warmup) for name in order}
+        torch.cuda.synchronize()
+        ms_rot = ev_rot[0].elapsed_time(ev_rot[1]) / rot_steps
+        rotated = {"contexts": 2, "steps": rot_steps, "ms_per_step": ms_rot,
+                   "patch_steps_per_s": rot["P"] / (ms_rot / 1e3)}
         print("bench: %s, two contexts in turn %.3f ms/step" % (args.precision, ms_rot), file=sys.stderr, flush=True)
+        ms = {name: e0.elapsed_time(e1) for name, (e0, e1) in ev.items()}
+        busy_before_ms = start.elapsed_time(ev[args.precision][0])
+        for name in order:
+            stage_ms, stage_n = profile_leg(legs[name])
+            forms[name] = dict(ms_total=ms[name], P=legs[name]["P"], stage_ms=stage_ms, stage_n=stage_n,
+                               fused=legs[name]["fused"], finite=close_leg(legs[name]))
+            print("bench: %s %.3f ms/step" % (name, ms[name] / args.steps), file=sys.stderr, flush=True)
+        close_leg(rot)
 
     main_r = forms[args.precision]
     P = main_r["P"]
@@ -464,6 +509,7 @@ def main():
                      "frac": step_bytes / (ms_step / 1e3) / 1e9 / PEAK_HBM_GBS},
         "roofline": roof,
         "cache_rotated": rotated,
+        "gpu_busy_before_timed_ms": busy_before_ms,
         "finite": main_r["finite"],
     }
     scales = {"offered": 1.0, "x10": 10.0, "x100": 100.0, "all": 1e9}
@@ -474,6 +520,10 @@ def main():
         out["serving"] = {"workload": "256 requests, Poisson 20/s, channel meshes 32x8..512x128, 50-500 steps, "
                                       "K=2 H=64 bf16, hipGraph",
                           "runs": dict(zip(runs, res))}
+    if not args.no_closed_loop:
+        out["closed_loop"] = {"note": "coarse Newton solve (host, sparse LU) + fine step (GPU) per time step, "
+                                      "against the same Newton solver on level L+K",
+                              "runs": run_closed_loop()}
     if not args.no_cpu_baseline:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)

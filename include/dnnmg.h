@@ -207,6 +207,11 @@ int dnnmg_arena_destroy(dnnmg_arena *arena);
 size_t dnnmg_arena_block_bytes(const dnnmg_config *cfg);
 /* Bytes in use, and the largest free block. */
 int dnnmg_arena_usage(const dnnmg_arena *arena, size_t *used, size_t *largest_free);
+/* Copy `bytes` from host memory to device memory through the arena's pinned
+ * staging ring, asynchronously on `stream` (the host buffer may be reused at
+ * once; nothing waits for the stream unless the ring is full).  DNNMG_EINVAL
+ * if bytes exceed the ring. */
+int dnnmg_arena_upload(dnnmg_arena *arena, void *dst_dev, const void *src_host, size_t bytes, void *stream);
 /* dnnmg_create_shared with the workspace taken from `arena`.  DNNMG_ENOMEM if
  * no free block is large enough (nothing is changed); DNNMG_EINVAL for the
  * cases of dnnmg_create_shared, and if the coordinates exceed the staging

@@ -32,7 +32,7 @@ SYMBOLS = [
     "dnnmg_step_count", "dnnmg_profile_enable", "dnnmg_profile_read", "dnnmg_quantize_e4m3",
     "dnnmg_noalloc_scratch_bytes", "dnnmg_rhs_restrict_noalloc", "dnnmg_nonfinite",
     "dnnmg_arena_create", "dnnmg_arena_destroy", "dnnmg_arena_block_bytes", "dnnmg_arena_usage",
-    "dnnmg_create_in_arena",
+    "dnnmg_create_in_arena", "dnnmg_arena_upload",
 ]
 DNNMG_NOALLOC_MAX_PATCHES = 1 << 18
 
@@ -94,6 +94,7 @@ def lib():
     L.dnnmg_arena_block_bytes.argtypes = [cp]; L.dnnmg_arena_block_bytes.restype = sz
     L.dnnmg_arena_usage.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
     L.dnnmg_create_in_arena.argtypes = [vp, cp, vp, vp, vp, ctypes.POINTER(vp)]
+    L.dnnmg_arena_upload.argtypes = [vp, vp, vp, sz, vp]
     L.dnnmg_rhs_restrict_noalloc.argtypes = [i, i, i, ctypes.c_double, vp, vp, vp, vp, vp]
     for name in SYMBOLS:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
@@ -285,6 +286,15 @@ class Arena:
     @staticmethod
     def block_bytes(cfg: Config) -> int:
         return int(lib().dnnmg_arena_block_bytes(ctypes.byref(cfg)))
+
+    def upload(self, dst, src: np.ndarray, stream=None):
+        """dnnmg_arena_upload: host array src into the device tensor dst (same
+        number of bytes), asynchronously on the stream."""
+        src = np.ascontiguousarray(src)
+        if not dst.is_cuda or not dst.is_contiguous() or dst.numel() * dst.element_size() != src.nbytes:
+            raise ValueError("dst must be a contiguous device tensor of %d bytes" % src.nbytes)
+        _check(lib().dnnmg_arena_upload(self.handle, ctypes.c_void_p(dst.data_ptr()),
+                                        src.ctypes.data_as(ctypes.c_void_p), src.nbytes, _stream(stream)))
 
     def usage(self):
         """(bytes in use, largest free block)."""

@@ -694,6 +694,24 @@ extern "C" int dnnmg_arena_usage(const dnnmg_arena *a, size_t *used, size_t *lar
     return DNNMG_OK;
 }
 
+extern "C" int dnnmg_arena_upload(dnnmg_arena *a, void *dst_dev, const void *src_host, size_t bytes, void *stream)
+{
+    if (!a || !dst_dev || !src_host) return fail(DNNMG_EINVAL, "arena, dst and src must not be NULL");
+    if (bytes == 0) return DNNMG_OK;
+    size_t soff = 0;
+    int rc = arena_stage(a, bytes, &soff);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    std::memcpy(a->stage + soff, src_host, bytes);
+    HIP_OR_FAIL(hipMemcpyAsync(dst_dev, a->stage + soff, bytes, hipMemcpyHostToDevice, st));
+    hipEvent_t ev = a->events.back();
+    HIP_OR_FAIL(hipEventRecord(ev, st));
+    a->events.pop_back();
+    a->ring.push(soff, bytes);
+    a->slot_events.push_back(ev);
+    return DNNMG_OK;
+}
+
 extern "C" int dnnmg_create_in_arena(dnnmg_arena *a, const dnnmg_config *cfg, const double *cxy,
                                      const dnnmg_ctx *model, void *stream, dnnmg_ctx **out)
 {

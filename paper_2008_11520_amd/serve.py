@@ -153,7 +153,8 @@ class Server:
                 raise
             xy = synth.rect_mesh_torch(nx, ny, synth.CHANNEL_LX, synth.CHANNEL_LY, "cuda")
             times = self.dt * torch.arange(self.ring, dtype=torch.float64, device="cuda")
-            v, p = synth.fields_torch_calibrated(ff, xy, times, inflow_max=1.5, height=synth.CHANNEL_LY)
+            v, p = synth.fields_torch_calibrated(ff, xy, times, inflow_max=1.5, height=synth.CHANNEL_LY,
+                                                 upload=lambda dst, src: self.arena.upload(dst, src, self.stream))
             vring = v.reshape(self.ring, -1).float().contiguous()
             pring = p.float().contiguous()
             b_out = torch.empty(2 * ctx.s["Nc"], dtype=torch.float64, device="cuda")

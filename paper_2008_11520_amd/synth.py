@@ -194,9 +194,17 @@ class FourierField:
         host = np.concatenate([self.k[:, 0], self.k[:, 1], self.phi, self.om,
                                2 * math.pi / np.hypot(self.k[:, 0], self.k[:, 1]),
                                self.pk[:, 0], self.pk[:, 1], self.pphi, self.pom])
-        cst = torch.from_numpy(host).to(dt_)
-        if dev.type != "cpu":
-            cst = cst.pin_memory().to(dev, non_blocking=True)
+        up = getattr(self, "_upload", None)
+        if dev.type == "cpu":
+            cst = torch.from_numpy(host).to(dt_)
+        elif up is not None:
+            # (the caller's asynchronous host-to-device path, e.g. the serving
+            # arena's staging ring: no pinned allocation per field)
+            cst = torch.empty(host.size, dtype=torch.float64, device=dev)
+            up(cst, host)
+            cst = cst.to(dt_)
+        else:
+            cst = torch.from_numpy(host).to(dt_).pin_memory().to(dev, non_blocking=True)
         kx, ky, phi, om, inv = (cst[i * M:(i + 1) * M] for i in range(5))
         pkx, pky, pphi, pom = (cst[5 * M + i * Mp:5 * M + (i + 1) * Mp] for i in range(4))
         th = 2 * math.pi * (kx * x / self.lx + ky * y / self.ly) + phi + om * t
@@ -226,7 +234,7 @@ class FourierField:
         return torch.stack([vx, vy], dim=-1), p
 
 
-def fields_torch_calibrated(ff: "FourierField", xy, times, inflow_max=0.0, height=0.41):
+def fields_torch_calibrated(ff: "FourierField", xy, times, inflow_max=0.0, height=0.41, upload=None):
     """ff.fields_torch with the calibration (max |v| and max |p| over the
     nodes at t = 0) done on the device as well: no value is read back to the
     host, so evaluating a flow's fields does not wait for the stream's other
@@ -236,6 +244,7 @@ def fields_torch_calibrated(ff: "FourierField", xy, times, inflow_max=0.0, heigh
     # stream synchronisation)
     if not torch.is_tensor(times):
         times = torch.as_tensor(times, dtype=xy.dtype).to(xy.device, non_blocking=True)
+    ff._upload = upload
     vx0, vy0, p0 = ff._raw_torch(xy, torch.zeros(1, dtype=xy.dtype, device=xy.device))
     m = torch_hypot_max(vx0, vy0)
     pm = p0.abs().max()

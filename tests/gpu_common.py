@@ -143,3 +143,15 @@ def window_fields(flow, step, i0, i1, j0, j1):
     v = v.reshape(flow.ny + 1, flow.nx + 1, 2)[j0:j1 + 1, i0:i1 + 1].reshape(-1, 2)
     p = p.reshape(flow.ny + 1, flow.nx + 1)[j0:j1 + 1, i0:i1 + 1].reshape(-1)
     return np.ascontiguousarray(v), np.ascontiguousarray(p)
+
+
+class OracleFineStep:
+    """The oracle's fine step as the fine step of the closed DNN-MG loop
+    (paper_2008_11520_amd.loop.run): coarse v, p in, b_L out (FP64)."""
+
+    def __init__(self, flow, K, H, Hm, weights, nu, fp8=False):
+        self.o = oracle.OracleFlow(flow.nx, flow.ny, K, H, Hm, flow.dt, nu, flow.dirichlet, flow.cxy,
+                                   np.asarray(weights, dtype=np.float64), fp8=fp8)
+
+    def step(self, v, p):
+        return self.o.step(np.asarray(v, np.float64), np.asarray(p, np.float64), want=("bL",))["bL"]

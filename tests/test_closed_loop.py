@@ -1,0 +1,37 @@
+"""The closed DNN-MG loop (Alg. 2) on the host with the oracle's fine step:
+with zero network weights the correction vanishes and the restricted fine
+right-hand side equals the coarse one (P^T M_f P = M_L), so the loop must
+reproduce the plain coarse loop; with seeded weights the correction must
+change the coarse trajectory."""
+import numpy as np
+import pytest
+
+from paper_2008_11520_amd import loop, synth
+
+from gpu_common import OracleFineStep
+
+
+@pytest.mark.parametrize("case", ["unit16_k1", "channel24x8_k2"])
+def test_zero_weights_reproduce_the_coarse_loop(case):
+    if case == "unit16_k1":
+        flow, K, H, Hm = synth.unit_square_flow(16, 16, 1, 0.01), 1, 32, 0
+    else:
+        flow, K, H, Hm = synth.channel_flow(24, 8, 2, 0.005, perturb_seed=3), 2, 64, 64
+    nu = 1e-3
+    w = np.zeros_like(synth.xavier_weights(K, H, Hm, 1))
+    dnn = loop.run(flow, nu, 6, fine=OracleFineStep(flow, K, H, Hm, w, nu))
+    ref = loop.run(flow, nu, 6)
+    # the fine step takes the coarse fields in FP32: differences of that size
+    scale = np.abs(ref["v"]).max()
+    assert np.abs(dnn["v"] - ref["v"]).max() <= 1e-6 * scale
+    assert all(2 <= it <= 6 for it in dnn["newton"])
+
+
+def test_seeded_weights_change_the_trajectory():
+    flow, K, H, Hm = synth.unit_square_flow(16, 16, 1, 0.01), 1, 32, 0
+    nu = 1e-3
+    w = synth.xavier_weights(K, H, Hm, 1234)
+    dnn = loop.run(flow, nu, 4, fine=OracleFineStep(flow, K, H, Hm, w, nu))
+    ref = loop.run(flow, nu, 4)
+    assert np.abs(dnn["v"][0] - ref["v"][0]).max() == 0.0        # the first coarse solve has no fine input
+    assert np.abs(dnn["v"][-1] - ref["v"][-1]).max() > 1e-2 * np.abs(ref["v"]).max()

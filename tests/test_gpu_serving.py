@@ -107,8 +107,10 @@ def test_server_mix_equals_alone():
     velocity and last restricted rhs equal those of the same request served
     alone, bit for bit."""
     from paper_2008_11520_amd.serve import Server
+    # arrivals 0.1 ms apart and 20-36 steps each, so that requests overlap on
+    # the GPU and later ones queue behind the budget
     meshes = [(16, 4), (32, 8), (8, 2), (16, 4), (32, 8), (4, 1)]
-    reqs = [dict(id=i, arrival=0.002 * i, nx=nx, ny=ny, steps=3 + (i * 2) % 5, field_seed=500 + i)
+    reqs = [dict(id=i, arrival=1e-4 * i, nx=nx, ny=ny, steps=20 + 4 * ((i * 2) % 5), field_seed=500 + i)
             for i, (nx, ny) in enumerate(meshes)]
     probe = Server(max_flows=8, ring=4)
     budget = 2 * probe.flow_bytes(32, 8) + probe.flow_bytes(4, 1)
