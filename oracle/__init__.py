@@ -46,6 +46,12 @@ def lib():
         L.orc_step_prec.argtypes = [i, i, i, i, i, d, d, u, _D, _D, _D, _D, _D, _D, i, i,
                                     _D, _D, _D, _D, _D, _D]
         L.orc_step_prec.restype = i
+        L.orc_step_theta.argtypes = [i, i, i, i, i, d, d, d, u, _D, _D, _D, _D, _D, _D, i, i,
+                                     _D, _D, _D, _D, _D, _D]
+        L.orc_step_theta.restype = i
+        L.orc_transport_apply.argtypes = [i, i, i, _D, _D, d, _D]
+        L.orc_defect_theta.argtypes = [i, i, i, _D, _D, _D, _D, d, d, d, u, _D]
+        L.orc_rhs_restrict_theta.argtypes = [i, i, i, _D, _D, _D, d, d, d, _D]
         L.orc_e4m3_decode.argtypes = [u]
         L.orc_e4m3_decode.restype = d
         L.orc_e4m3_encode.argtypes = [ctypes.c_float]
@@ -125,6 +131,29 @@ def defect_abs(nx, ny, K, cxy, pv, pp, uprev, inv_dt, nu):
     lib().orc_defect_abs(nx, ny, K, _p(_f64(cxy)), _p(_f64(pv)), _p(_f64(pp)), _p(_f64(uprev)),
                          inv_dt, nu, _p(S))
     return S
+
+
+def transport_apply(nx, ny, K, cxy, w, nu):
+    """T(w) = C(w) w + nu K w at the fine nodes (unmasked)."""
+    s = sizes(nx, ny, K)
+    out = np.empty((s["Fn"], 2))
+    lib().orc_transport_apply(nx, ny, K, _p(_f64(cxy)), _p(_f64(w)), nu, _p(out))
+    return out
+
+
+def defect_theta(nx, ny, K, cxy, pv, pp, uprev, dt, nu, theta, dirichlet):
+    s = sizes(nx, ny, K)
+    D = np.empty((s["Fn"], 2))
+    lib().orc_defect_theta(nx, ny, K, _p(_f64(cxy)), _p(_f64(pv)), _p(_f64(pp)), _p(_f64(uprev)),
+                           dt, nu, theta, dirichlet, _p(D))
+    return D
+
+
+def rhs_restrict_theta(nx, ny, K, cxy, v, Dbar, dt, nu, theta):
+    s = sizes(nx, ny, K)
+    out = np.empty((s["Nc"], 2))
+    lib().orc_rhs_restrict_theta(nx, ny, K, _p(_f64(cxy)), _p(_f64(v)), _p(_f64(Dbar)), dt, nu, theta, _p(out))
+    return out
 
 
 def set_threads(n):
@@ -247,9 +276,10 @@ def rhs_restrict(nx, ny, K, cxy, v, Dbar, dt):
 class OracleFlow:
     """Stateful wrapper: h (P x H) and u_prev (Fn x 2) in float64."""
 
-    def __init__(self, nx, ny, K, H, Hm, dt, nu, dirichlet, cxy, weights, fp8=False):
+    def __init__(self, nx, ny, K, H, Hm, dt, nu, dirichlet, cxy, weights, fp8=False, theta=1.0):
         self.nx, self.ny, self.K, self.H, self.Hm = nx, ny, K, H, Hm
         self.fp8 = bool(fp8)
+        self.theta = float(theta)
         self.dt, self.nu, self.dirichlet = dt, nu, dirichlet
         self.cxy = _f64(cxy).reshape(-1, 2)
         self.w = _f64(weights).reshape(-1)
@@ -266,8 +296,8 @@ class OracleFlow:
                       dpatch=(s["P"], s["nout"]), Dbar=(s["Fn"], 2), bL=(s["Nc"], 2))
         for k in want:
             outs[k] = np.empty(shapes[k])
-        rc = lib().orc_step_prec(self.nx, self.ny, self.K, self.H, self.Hm, self.dt, self.nu,
-                                 self.dirichlet, _p(self.cxy), _p(self.w),
+        rc = lib().orc_step_theta(self.nx, self.ny, self.K, self.H, self.Hm, self.dt, self.nu, self.theta,
+                                  self.dirichlet, _p(self.cxy), _p(self.w),
                                  _p(_f64(v).reshape(-1, 2)), _p(_f64(p).reshape(-1)),
                                  _p(self.h), _p(self.uprev), 1 if self.nsteps == 0 else 0, int(self.fp8),
                                  *[_p(outs[k]) for k in ("Pv", "D", "X", "dpatch", "Dbar", "bL")])

@@ -768,8 +768,115 @@ void orc_rhs_restrict(int nx, int ny, int K, const double *cxy, const double *v,
     free(bf);
 }
 
+/* ------------------------------------- theta scheme (Crank-Nicolson: 1/2) */
+/* T(w) = C(w) w + nu K w: the convection and diffusion rows of the
+ * momentum operator applied to a fine nodal field w (2 per node), with the
+ * defect's element loop and quadrature, unmasked.  The time scheme of
+ * Eq. (4cranknicholson3) weights them by 1/2 at the new and the old time
+ * level; with a general weight theta (1 = implicit Euler, 1/2 = the paper's
+ * Crank-Nicolson) the step's two operators are
+ *   D = (1/dt) M (u_prev - v) - theta T(v) - (1 - theta) T(u_prev) + B^T p,
+ *   b = (1/dt) M u_corr - (1 - theta) T(u_corr)            (no body force). */
+void orc_transport_apply(int nx, int ny, int K, const double *cxy, const double *w, double nu, double *T)
+{
+    int n = 1 << K, NX = nx * n, NY = ny * n;
+    size_t Fn = (size_t)(NX + 1) * (NY + 1);
+    double *fxy = (double *)malloc(sizeof(double) * 2 * Fn);
+    orc_fine_coords(nx, ny, K, cxy, fxy);
+    memset(T, 0, sizeof(double) * 2 * Fn);
+    double g[2];
+    gauss2(g);
+    for (int parity = 0; parity < 2; ++parity)
+#pragma omp parallel for schedule(static)
+    for (int J = parity; J < NY; J += 2)
+        for (int I = 0; I < NX; ++I) {
+            int node[4] = {fine_node(nx, n, I, J), fine_node(nx, n, I + 1, J),
+                           fine_node(nx, n, I, J + 1), fine_node(nx, n, I + 1, J + 1)};
+            for (int qt = 0; qt < 2; ++qt)
+                for (int qs = 0; qs < 2; ++qs) {
+                    double N[4], dNs[4], dNt[4];
+                    q1_shape(g[qs], g[qt], N);
+                    q1_shape_ds(g[qs], g[qt], dNs, dNt);
+                    double xs = 0, xt = 0, ys = 0, yt = 0;
+                    for (int k = 0; k < 4; ++k) {
+                        xs += fxy[2 * node[k]] * dNs[k];
+                        xt += fxy[2 * node[k]] * dNt[k];
+                        ys += fxy[2 * node[k] + 1] * dNs[k];
+                        yt += fxy[2 * node[k] + 1] * dNt[k];
+                    }
+                    double det = xs * yt - xt * ys;
+                    double dNx[4], dNy[4];
+                    for (int k = 0; k < 4; ++k) {
+                        dNx[k] = (yt * dNs[k] - ys * dNt[k]) / det;
+                        dNy[k] = (-xt * dNs[k] + xs * dNt[k]) / det;
+                    }
+                    double wq[2] = {0, 0}, gw[2][2] = {{0, 0}, {0, 0}};
+                    for (int k = 0; k < 4; ++k)
+                        for (int c = 0; c < 2; ++c) {
+                            wq[c] += N[k] * w[2 * node[k] + c];
+                            gw[c][0] += w[2 * node[k] + c] * dNx[k];
+                            gw[c][1] += w[2 * node[k] + c] * dNy[k];
+                        }
+                    double wd = 0.25 * fabs(det);
+                    for (int a = 0; a < 4; ++a)
+                        for (int c = 0; c < 2; ++c) {
+                            double conv = wq[0] * gw[c][0] + wq[1] * gw[c][1];
+                            double r = N[a] * conv + nu * (dNx[a] * gw[c][0] + dNy[a] * gw[c][1]);
+                            T[2 * node[a] + c] += wd * r;
+                        }
+                }
+        }
+    free(fxy);
+}
+
+/* The defect of the theta scheme: the implicit-Euler defect (theta = 1)
+ * plus (1 - theta) (T(v) - T(u_prev)), masked at Dirichlet nodes. */
+void orc_defect_theta(int nx, int ny, int K, const double *cxy, const double *v, const double *p,
+                      const double *uprev, double dt, double nu, double theta, unsigned dir, double *D)
+{
+    int n = 1 << K;
+    size_t Fn = (size_t)(nx * n + 1) * (ny * n + 1);
+    orc_defect(nx, ny, K, cxy, v, p, uprev, dt, nu, dir, D);
+    if (theta == 1.0) return;
+    double *Tv = (double *)malloc(sizeof(double) * 2 * Fn);
+    double *Tu = (double *)malloc(sizeof(double) * 2 * Fn);
+    unsigned char *mask = (unsigned char *)malloc(Fn);
+    orc_transport_apply(nx, ny, K, cxy, v, nu, Tv);
+    orc_transport_apply(nx, ny, K, cxy, uprev, nu, Tu);
+    orc_dirichlet_mask(nx, ny, K, dir, mask);
+    for (size_t f = 0; f < Fn; ++f)
+        for (int c = 0; c < 2; ++c)
+            D[2 * f + c] = mask[f] ? 0.0 : D[2 * f + c] + (1.0 - theta) * (Tv[2 * f + c] - Tu[2 * f + c]);
+    free(Tv);
+    free(Tu);
+    free(mask);
+}
+
+/* b_L = R [(1/dt) M_f u_corr - (1 - theta) T(u_corr)], u_corr = P v + Dbar. */
+void orc_rhs_restrict_theta(int nx, int ny, int K, const double *cxy, const double *v, const double *Dbar,
+                            double dt, double nu, double theta, double *bL)
+{
+    orc_rhs_restrict(nx, ny, K, cxy, v, Dbar, dt, bL);
+    if (theta == 1.0) return;
+    int n = 1 << K;
+    size_t Fn = (size_t)(nx * n + 1) * (ny * n + 1), Nc = (size_t)(nx + 1) * (ny + 1);
+    double *u = (double *)malloc(sizeof(double) * 2 * Fn);
+    double *T = (double *)malloc(sizeof(double) * 2 * Fn);
+    double *RT = (double *)malloc(sizeof(double) * 2 * Nc);
+    orc_prolong(nx, ny, K, 2, v, u);
+    for (size_t f = 0; f < 2 * Fn; ++f) u[f] += Dbar[f];
+    orc_transport_apply(nx, ny, K, cxy, u, nu, T);
+    orc_restrict(nx, ny, K, 2, T, RT);
+    for (size_t c = 0; c < 2 * Nc; ++c) bL[c] -= (1.0 - theta) * RT[c];
+    free(u);
+    free(T);
+    free(RT);
+}
+
 /* ---------------------------------------------------------- the full step */
-/* One DNN-MG fine step (Alg. 2, lines 6-9) for given coarse v, p.
+/* One DNN-MG fine step (Alg. 2, lines 6-9) for given coarse v, p, with the
+ * time scheme's weight theta (1: implicit Euler; 1/2: Crank-Nicolson as in
+ * Eq. (4cranknicholson3); see orc_defect_theta, orc_rhs_restrict_theta).
  * weights: W_z, W_r, W_h (H x nin), U_z, U_r, U_h (H x H), then M1 (Hm x H)
  * and M2 (nout x Hm), or M (nout x H) when Hm == 0.
  * fp8 != 0 takes the network products with FP8 E4M3 operands
@@ -779,11 +886,11 @@ void orc_rhs_restrict(int nx, int ny, int K, const double *cxy, const double *v,
  * an earlier step exists yet), so the mass term of the defect vanishes.
  * Optional outputs (NULL to skip): Pv (Fn x 2), D (Fn x 2), X (P x nin),
  * dpatch (P x nout), Dbar (Fn x 2), bL ((nx+1)(ny+1) x 2). */
-int orc_step_prec(int nx, int ny, int K, int H, int Hm, double dt, double nu, unsigned dir,
-                  const double *cxy, const double *weights, const double *v, const double *p,
-                  double *h, double *uprev, int first, int fp8,
-                  double *Pv_out, double *D_out, double *X_out, double *dpatch_out,
-                  double *Dbar_out, double *bL_out)
+int orc_step_theta(int nx, int ny, int K, int H, int Hm, double dt, double nu, double theta, unsigned dir,
+                   const double *cxy, const double *weights, const double *v, const double *p,
+                   double *h, double *uprev, int first, int fp8,
+                   double *Pv_out, double *D_out, double *X_out, double *dpatch_out,
+                   double *Dbar_out, double *bL_out)
 {
     int n = 1 << K, nf = (n + 1) * (n + 1), nout = 2 * nf, nin = 4 * nf + 4;
     int P = nx * ny;
@@ -808,7 +915,7 @@ int orc_step_prec(int nx, int ny, int K, int H, int Hm, double dt, double nu, un
     orc_prolong(nx, ny, K, 2, v, Pv);
     orc_prolong(nx, ny, K, 1, p, Pp);
     if (first) memcpy(uprev, Pv, sizeof(double) * 2 * Fn);
-    orc_defect(nx, ny, K, cxy, Pv, Pp, uprev, dt, nu, dir, D);
+    orc_defect_theta(nx, ny, K, cxy, Pv, Pp, uprev, dt, nu, theta, dir, D);
     orc_features(nx, ny, cxy, feat);
     orc_gather_input(nx, ny, K, Pv, D, feat, X);
     if (fp8) {
@@ -819,7 +926,7 @@ int orc_step_prec(int nx, int ny, int K, int H, int Hm, double dt, double nu, un
         orc_mlp(P, H, Hm, nout, M1, M2, hn, dp);
     }
     orc_average(nx, ny, K, dp, dir, Dbar);
-    orc_rhs_restrict(nx, ny, K, cxy, v, Dbar, dt, bL);
+    orc_rhs_restrict_theta(nx, ny, K, cxy, v, Dbar, dt, nu, theta, bL);
 
     /* state update: h <- h', u_prev <- u_corr = P v + Dbar */
     memcpy(h, hn, sizeof(double) * (size_t)P * H);
@@ -833,6 +940,17 @@ int orc_step_prec(int nx, int ny, int K, int H, int Hm, double dt, double nu, un
     if (bL_out) memcpy(bL_out, bL, sizeof(double) * 2 * Nc);
     free(Pv); free(Pp); free(D); free(feat); free(X); free(hn); free(dp); free(Dbar); free(bL);
     return 0;
+}
+
+/* orc_step_theta with implicit Euler (theta = 1). */
+int orc_step_prec(int nx, int ny, int K, int H, int Hm, double dt, double nu, unsigned dir,
+                  const double *cxy, const double *weights, const double *v, const double *p,
+                  double *h, double *uprev, int first, int fp8,
+                  double *Pv_out, double *D_out, double *X_out, double *dpatch_out,
+                  double *Dbar_out, double *bL_out)
+{
+    return orc_step_theta(nx, ny, K, H, Hm, dt, nu, 1.0, dir, cxy, weights, v, p, h, uprev, first, fp8,
+                          Pv_out, D_out, X_out, dpatch_out, Dbar_out, bL_out);
 }
 
 /* orc_step_prec with FP64 network products. */

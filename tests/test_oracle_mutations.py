@@ -38,6 +38,14 @@ MUTATIONS = {
     "lumped_mass": ("Mu[2 * node[a] + c] += wd * N[a] * uq[c];", "Mu[2 * node[a] + c] += wd * 0.25 * uq[c];", 0),
     "mask_wrong_axis": ("((dir & 4u) && J == 0)", "((dir & 4u) && I == 0)", 0),
     "state_without_correction": ("uprev[f] = Pv[f] + Dbar[f];", "uprev[f] = Pv[f];", 0),
+    # theta scheme (Crank-Nicolson)
+    "theta_defect_sign": ("(1.0 - theta) * (Tv[2 * f + c] - Tu[2 * f + c])",
+                          "(1.0 - theta) * (Tu[2 * f + c] - Tv[2 * f + c])", 0),
+    "theta_defect_weight": ("(1.0 - theta) * (Tv[2 * f + c]", "theta * (Tv[2 * f + c]", 0),
+    "theta_rhs_sign": ("bL[c] -= (1.0 - theta) * RT[c];", "bL[c] += (1.0 - theta) * RT[c];", 0),
+    "transport_no_viscosity": ("double r = N[a] * conv + nu * (dNx[a]", "double r = N[a] * conv + 0.0 * (dNx[a]", 0),
+    "transport_convection_transposed": ("double conv = wq[0] * gw[c][0] + wq[1] * gw[c][1];",
+                                        "double conv = wq[0] * gw[0][c] + wq[1] * gw[1][c];", 0),
     # FP8 E4M3 operand form
     "e4m3_ties_away": ("rint((ldexp(a, -e) - 1.0) * 8.0)", "round((ldexp(a, -e) - 1.0) * 8.0)", 0),
     "e4m3_truncate": ("rint((ldexp(a, -e) - 1.0) * 8.0)", "floor((ldexp(a, -e) - 1.0) * 8.0)", 0),

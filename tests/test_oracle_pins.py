@@ -621,3 +621,76 @@ def test_defect_error_scale_bounds_the_defect_and_is_exact_without_cancellation(
     hx, hy = 2.2 / (nx * n), 0.41 / (ny * n)
     assert np.allclose(S3[1:-1, 1:-1, 0], 2 * c * hy, rtol=1e-13, atol=0)
     assert np.allclose(S3[1:-1, 1:-1, 1], 2 * c * hx, rtol=1e-13, atol=0)
+
+
+# ------------------------------------------------- theta scheme (Crank-Nicolson)
+def test_transport_operator_textbook_diffusion_and_exact_solution():
+    """T(w) = C(w) w + nu K w: (1) a shear field w = (g(y), 0) carries no
+    convection (its nodal values are constant along x), so on a uniform mesh
+    T(w) is nu times the textbook Q1 stiffness stencil; (2) for an exact
+    affine steady solution (v.grad v = -grad p, Delta v = 0) T(v) equals the
+    pressure term B^T p at interior nodes, on a perturbed mesh."""
+    nx, ny, K, lx, ly, nu = 5, 4, 1, 2.2, 0.41, 0.37
+    n = 1 << K
+    NX, NY = nx * n, ny * n
+    cxy = rect(nx, ny, lx, ly)
+    fxy = oracle.fine_coords(nx, ny, K, cxy)
+    g = np.sin(7.0 * fxy[:, 1]) + fxy[:, 1] ** 2
+    w = np.stack([g, 0 * g], axis=1)
+    T = oracle.transport_apply(nx, ny, K, cxy, w, nu).reshape(NY + 1, NX + 1, 2)
+    Ax, Mx = _stencil_1d(lx / NX)
+    Ay, My = _stencil_1d(ly / NY)
+    gc = g.reshape(NY + 1, NX + 1)
+    ref = nu * (_apply_tensor_stencil(gc, Ax, My, NX, NY) + _apply_tensor_stencil(gc, Mx, Ay, NX, NY))
+    assert np.abs(T[1:-1, 1:-1, 0] - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(T[1:-1, 1:-1, 1]).max() <= 1e-12 * np.abs(ref).max()
+    for kind in ("diag", "shear"):
+        cp = perturbed(6, 5, 2.0, 1.0)
+        v, p = _manufactured(kind, cp)
+        pv, pp = oracle.prolong(6, 5, 2, v), oracle.prolong(6, 5, 2, p)
+        Tv = oracle.transport_apply(6, 5, 2, cp, pv, 1e-3).reshape(21, 25, 2)
+        Bp = oracle.defect(6, 5, 2, cp, 0 * pv, pp, 0 * pv, 0.01, 1e-3, 0).reshape(21, 25, 2)
+        assert np.abs(Tv[1:-1, 1:-1] - Bp[1:-1, 1:-1]).max() <= 1e-12 * np.abs(Bp).max()
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5])
+def test_theta_defect_weights_old_and_new_levels(theta):
+    """With the exact steady solution as the previous velocity, a zero new
+    velocity and the exact pressure, the theta defect is
+    (1/dt) M u + theta B^T p at interior nodes (the old level's transport
+    term -(1 - theta) T(u) cancels that share of the pressure term); with
+    the exact solution at both levels it vanishes for every theta."""
+    nx, ny, K, dt = 6, 5, 2, 0.01
+    cp = perturbed(nx, ny, 2.0, 1.0)
+    v, p = _manufactured("diag", cp)
+    pv, pp = oracle.prolong(nx, ny, K, v), oracle.prolong(nx, ny, K, p)
+    D = oracle.defect_theta(nx, ny, K, cp, 0 * pv, pp, pv, dt, 1e-3, theta, synth.DIR_ALL).reshape(21, 25, 2)
+    Mu = oracle.mass_apply(nx, ny, K, cp, pv).reshape(21, 25, 2) / dt
+    Bp = oracle.defect(nx, ny, K, cp, 0 * pv, pp, 0 * pv, dt, 1e-3, 0).reshape(21, 25, 2)
+    ref = Mu + theta * Bp
+    assert np.abs(D[1:-1, 1:-1] - ref[1:-1, 1:-1]).max() <= 1e-12 * np.abs(ref).max()
+    assert np.all(D[0] == 0) and np.all(D[-1] == 0) and np.all(D[:, 0] == 0) and np.all(D[:, -1] == 0)
+    D0 = oracle.defect_theta(nx, ny, K, cp, pv, pp, pv, dt, 1e-3, theta, synth.DIR_ALL)
+    Dc = oracle.defect(nx, ny, K, cp, pv, 0 * pp, pv, dt, 0.0, synth.DIR_ALL)
+    assert np.linalg.norm(D0) <= 1e-12 * np.linalg.norm(Dc)
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 1.0])
+def test_theta_rhs_conserves_the_closed_form_sum(theta):
+    """Restriction keeps sums (partition of unity) and the test functions'
+    gradients sum to zero, so for a corrected velocity u the entries of
+    b_L sum to (1/dt) int u - (1 - theta) int (u.grad)u.  For the exact
+    affine solution (u.grad)u = -grad p is constant and both integrals are
+    closed forms over the domain [0, Lx] x [0, Ly] (perturbed interior)."""
+    nx, ny, K, dt, lx, ly = 6, 5, 2, 0.01, 2.0, 1.0
+    cp = perturbed(nx, ny, lx, ly)
+    al, be, de = 0.4, -0.7, 1.3
+    x, y = cp[..., 0].reshape(-1), cp[..., 1].reshape(-1)
+    v = np.stack([al + be * (x + y), de - be * (x + y)], -1)
+    s = oracle.sizes(nx, ny, K)
+    b = oracle.rhs_restrict_theta(nx, ny, K, cp, v, np.zeros((s["Fn"], 2)), dt, 1e-3, theta)
+    area = lx * ly
+    int_u = area * np.array([al + be * (lx + ly) / 2, de - be * (lx + ly) / 2])
+    grad_p = -be * (al + de) * np.array([1.0, -1.0])
+    ref = int_u / dt - (1.0 - theta) * (-grad_p * area)
+    assert np.allclose(b.sum(axis=0), ref, rtol=1e-12, atol=0)
