@@ -125,6 +125,67 @@ __host__ __device__ inline void element_residual(const CoarseRec &r, int a, int 
     element_sums<n>(my, Qys, Qyt, R + 1);
 }
 
+// The same element with the time scheme's weights (Crank-Nicolson at
+// theta = 1/2): the new level's convection and diffusion weighted by theta,
+// the old level's (the previous corrected velocity u, nodal values w0..w3 at
+// the corners 00, 10, 01, 11) by 1 - theta:
+//   m_c = det (u_c - v_c) / dt - theta v . (Cof grad_ref v_c) - (1 - theta) u . (Cof grad_ref u_c)
+//   Q_c = p Cof^T e_c - (nu / det) G (theta grad_ref v_c + (1 - theta) grad_ref u_c)
+// with grad_ref u from the element's bilinear nodal interpolant (n times its
+// fine-element derivatives, in the coarse reference coordinates).
+template <int K, typename Rcp>
+__host__ __device__ inline void element_residual_theta(const CoarseRec &r, int a, int b, float nu, float idt,
+                                                       float theta, float2 w0, float2 w1, float2 w2, float2 w3,
+                                                       float (&R)[8])
+{
+    constexpr int n = 1 << K;
+    constexpr float inv_n = 1.0f / n, g0 = kGauss0, g1 = kGauss1;
+    const float th_old = 1.0f - theta;
+    const float gs[2] = {g0, g1};
+    // the previous velocity's nodal values on this element
+    const float u00x = w0.x, u00y = w0.y, u10x = w1.x, u10y = w1.y;
+    const float u01x = w2.x, u01y = w2.y, u11x = w3.x, u11y = w3.y;
+    float mx[2][2], my[2][2], Qxs[2][2], Qxt[2][2], Qys[2][2], Qyt[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const float s = gs[i], t = gs[j];                 // fine-element coordinates
+            const float xi = (a + s) * inv_n, eta = (b + t) * inv_n;
+            const float xs = r.exx + r.exyx * eta, ys = r.exy + r.exyy * eta;
+            const float xt = r.eyx + r.exyx * xi, yt = r.eyy + r.exyy * xi;
+            const float det = xs * yt - xt * ys;
+            // new level: v, its coarse-reference gradient, p
+            const float vxq = (r.V0x + r.V1x * xi) + (r.V2x + r.V3x * xi) * eta;
+            const float vyq = (r.V0y + r.V1y * xi) + (r.V2y + r.V3y * xi) * eta;
+            const float vsx = r.V1x + r.V3x * eta, vsy = r.V1y + r.V3y * eta;
+            const float vtx = r.V2x + r.V3x * xi, vty = r.V2y + r.V3y * xi;
+            const float pq = (r.P0 + r.P1 * xi) + (r.P2 + r.P3 * xi) * eta;
+            // old level: u and its coarse-reference gradient
+            const float uxq = (1 - t) * (u00x + (u10x - u00x) * s) + t * (u01x + (u11x - u01x) * s);
+            const float uyq = (1 - t) * (u00y + (u10y - u00y) * s) + t * (u01y + (u11y - u01y) * s);
+            const float usx = n * ((u10x - u00x) * (1 - t) + (u11x - u01x) * t);
+            const float usy = n * ((u10y - u00y) * (1 - t) + (u11y - u01y) * t);
+            const float utx = n * ((u01x - u00x) * (1 - s) + (u11x - u10x) * s);
+            const float uty = n * ((u01y - u00y) * (1 - s) + (u11y - u10y) * s);
+            // Cof grad_ref of each component, both levels
+            const float dvxx = yt * vsx - ys * vtx, dvxy = -xt * vsx + xs * vtx;
+            const float dvyx = yt * vsy - ys * vty, dvyy = -xt * vsy + xs * vty;
+            const float duxx = yt * usx - ys * utx, duxy = -xt * usx + xs * utx;
+            const float duyx = yt * usy - ys * uty, duyy = -xt * usy + xs * uty;
+            mx[i][j] = det * idt * (uxq - vxq) - theta * (vxq * dvxx + vyq * dvxy) - th_old * (uxq * duxx + uyq * duxy);
+            my[i][j] = det * idt * (uyq - vyq) - theta * (vxq * dvyx + vyq * dvyy) - th_old * (uxq * duyx + uyq * duyy);
+            const float g11 = xt * xt + yt * yt, g22 = xs * xs + ys * ys, g12 = -(xs * xt + ys * yt);
+            const float inv = nu * Rcp::f(det);
+            const float gsx = theta * vsx + th_old * usx, gtx = theta * vtx + th_old * utx;
+            const float gsy = theta * vsy + th_old * usy, gty = theta * vty + th_old * uty;
+            Qxs[i][j] = pq * yt - inv * (g11 * gsx + g12 * gtx);
+            Qxt[i][j] = -pq * ys - inv * (g12 * gsx + g22 * gtx);
+            Qys[i][j] = -pq * xt - inv * (g11 * gsy + g12 * gty);
+            Qyt[i][j] = pq * xs - inv * (g12 * gsy + g22 * gty);
+        }
+    element_sums<n>(mx, Qxs, Qxt, R);
+    element_sums<n>(my, Qys, Qyt, R + 1);
+}
+
 // A vertical strip of SH fine elements of coarse element r: column a, rows
 // b0 .. b0 + SH - 1.  The same sums as element_residual, arranged so that the
 // work per Gauss point shrinks: on the coarse element

@@ -57,6 +57,51 @@ static double strip_vs_elements(std::mt19937 &g, int trials)
     return worst;
 }
 
+// element_residual_theta at theta = 1 against element_residual (the same
+// implicit-Euler sums, arranged differently), and at theta = 1/2 with the old
+// level equal to the new one (u = v at the nodes of a bilinear v, so both
+// levels' transport terms are the same and the weights must add up to one).
+template <int K>
+static double theta_form_vs_element_form(std::mt19937 &g, int trials)
+{
+    constexpr int n = 1 << K;
+    std::uniform_real_distribution<float> U(-1.f, 1.f);
+    double worst = 0;
+    for (int t = 0; t < trials; ++t) {
+        CoarseRec r;
+        float *v = &r.V0x;
+        for (int q = 0; q < 12; ++q) v[q] = U(g) * (q % 4 == 0 ? 2.f : 0.7f);
+        const float sc = std::pow(10.f, 2 * U(g));
+        r.exx = sc * (1.f + 0.3f * U(g)); r.exy = sc * 0.3f * U(g);
+        r.eyx = sc * 0.3f * U(g); r.eyy = sc * (1.f + 0.3f * U(g));
+        r.exyx = sc * 0.2f * U(g); r.exyy = sc * 0.2f * U(g);
+        const bool same = t % 2;   // u = v at the corners (bilinear v): theta = 1/2 must equal theta = 1
+        // (with u = v the mass term is left out: u - v would only hold the
+        // two evaluations' rounding, amplified by 1/dt)
+        const float nu = 1e-3f * (1 + 10 * (t % 3)), idt = same ? 0.f : 200.f;
+        const int a = t % n, b = (t / n) % n;
+        float2 u[4];
+        for (int c = 0; c < 4; ++c) {
+            const float xi = (a + (c & 1)) * (1.0f / n), eta = (b + (c >> 1)) * (1.0f / n);
+            if (same) {
+                u[c].x = (r.V0x + r.V1x * xi) + (r.V2x + r.V3x * xi) * eta;
+                u[c].y = (r.V0y + r.V1y * xi) + (r.V2y + r.V3y * xi) * eta;
+            } else {
+                u[c].x = 2 * U(g); u[c].y = 2 * U(g);
+            }
+        }
+        float Rt[8], Re[8];
+        element_residual_theta<K, HostOps>(r, a, b, nu, idt, same ? 0.5f : 1.0f, u[0], u[1], u[2], u[3], Rt);
+        float2 w[4];
+        for (int c = 0; c < 4; ++c) w[c] = {u[c].x * idt, u[c].y * idt};
+        element_residual<K, HostOps>(r, a, b, nu, idt, w[0], w[1], w[2], w[3], Re);
+        float mag = 0;
+        for (float x : Re) mag = std::fmax(mag, std::fabs(x));
+        for (int c = 0; c < 8; ++c) worst = std::fmax(worst, std::fabs(Rt[c] - Re[c]) / mag);
+    }
+    return worst;
+}
+
 template <int SH>
 static bool partition_ok(int K)
 {
@@ -98,7 +143,11 @@ int main()
     const double e1 = strip_vs_elements<1, 2>(g, 20000), e2 = strip_vs_elements<2, 4>(g, 20000),
                  e3 = strip_vs_elements<3, 4>(g, 20000);
     std::printf("strip vs elements, max relative difference: K=1 %.3g  K=2 %.3g  K=3 %.3g\n", e1, e2, e3);
+    const double t1 = theta_form_vs_element_form<1>(g, 20000), t2 = theta_form_vs_element_form<2>(g, 20000),
+                 t3 = theta_form_vs_element_form<3>(g, 20000);
+    std::printf("theta form (theta = 1, and theta = 1/2 with u = v) vs element form: K=1 %.3g  K=2 %.3g  K=3 %.3g\n",
+                t1, t2, t3);
     const bool p1 = partition_ok<2>(1), p2 = partition_ok<4>(2), p3 = partition_ok<4>(3);
     std::printf("tile partition: K=1 %s  K=2 %s  K=3 %s\n", p1 ? "ok" : "FAIL", p2 ? "ok" : "FAIL", p3 ? "ok" : "FAIL");
-    return (e1 < 1e-5 && e2 < 1e-5 && e3 < 1e-5 && p1 && p2 && p3) ? 0 : 1;
+    return (e1 < 1e-5 && e2 < 1e-5 && e3 < 1e-5 && t1 < 1e-5 && t2 < 1e-5 && t3 < 1e-5 && p1 && p2 && p3) ? 0 : 1;
 }
