@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp8": 5000.0}
 PEAK_FP32_VECTOR_TFLOPS = 157.3      # published: packed (two-wide) FP32 FMA on every lane
+PEAK_FP64_VECTOR_TFLOPS = 78.6       # published FP64 vector rate
 # the vector FP32 rate this build can reach: packed FP32 instructions are kept
 # out of the generated code, so one FMA per lane per cycle: 256 CUs x 4 SIMDs x
 # 16 lanes x 2 FLOP x 2.4 GHz (reported beside the published-peak fraction)
@@ -337,6 +338,19 @@ def run_closed_loop(steps=5, fine_steps=2):
     return out
 
 
+def cn_rhs_flop_per_patch(K):
+    """FP64 FLOP per patch of the Crank-Nicolson explicit term in the rhs
+    kernel (the transport of u = P v + d against the four coarse hats), as
+    the formula is written: per fine-element Gauss point, the map's Jacobian
+    and determinant (11), u and its reference gradient (38), the cofactor
+    gradients (12), u . grad u (6), nu / det (1), the coarse hats (12), and
+    per corner the cofactor gradient of the hat (6) and the weighted sums of
+    both components (16); 4 Gauss points on each of the n^2 fine elements."""
+    n = 1 << K
+    per_point = 11 + 38 + 12 + 6 + 1 + 12 + 4 * (6 + 16)
+    return 4 * n * n * per_point
+
+
 def roofline(wl, flow, P, main_r, precision):
     """Roofline of the dominant stage: per-launch algorithmic work over the
     stage's average launch time from the library's HIP events on the launch
@@ -450,6 +464,10 @@ def main():
         if args.precision == "bf16":
             legs["bf16_unfused"] = make_flow_leg(wl, "bf16", flags=pam.DNNMG_F_UNFUSED)
             order.append("bf16_unfused")
+        # the Crank-Nicolson scheme (separate launches; FP64 explicit term in the rhs)
+        cn = args.precision + "_crank_nicolson"
+        legs[cn] = make_flow_leg(wl, args.precision, flags=pam.DNNMG_F_CRANK_NICOLSON)
+        order.append(cn)
         legs[args.precision] = make_flow_leg(wl, args.precision)
         order.append(args.precision)
         rot = make_flow_leg(wl, args.precision, copies=2)
@@ -484,6 +502,16 @@ def main():
     if main_r["stage_ms"] is not None:
         roof = roofline(wl, flow, P, main_r, args.precision)
     step_bytes = per_patch_step_bytes(wl.K, wl.H) * P
+    cn_roof = None
+    cn_r = forms.get(args.precision + "_crank_nicolson")
+    if cn_r is not None and cn_r["stage_ms"] is not None:
+        # the rhs kernel of the Crank-Nicolson form: FP64 vector arithmetic
+        t_s = cn_r["stage_ms"][2] / max(cn_r["stage_n"][2], 1) / 1e3
+        fl = cn_rhs_flop_per_patch(wl.K)
+        cn_roof = {"kernel": "avg_rhs_fp64 with the explicit transport term", "bound": "alu",
+                   "achieved": fl * P / t_s / 1e12, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                   "frac": fl * P / t_s / 1e12 / PEAK_FP64_VECTOR_TFLOPS, "algorithmic_per_patch": fl,
+                   "avg_launch_us": t_s * 1e6, "units_per_launch": P}
     out = {
         "metric": "patch-steps/sec of fine DNN-MG step (BF16 vs FP32); serving p50/p99 step latency",
         "value": value,
@@ -508,6 +536,7 @@ def main():
                      "achieved_GBs": step_bytes / (ms_step / 1e3) / 1e9,
                      "frac": step_bytes / (ms_step / 1e3) / 1e9 / PEAK_HBM_GBS},
         "roofline": roof,
+        "crank_nicolson_rhs_roofline": cn_roof,
         "cache_rotated": rotated,
         "gpu_busy_before_timed_ms": busy_before_ms,
         "finite": main_r["finite"],

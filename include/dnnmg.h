@@ -86,6 +86,20 @@ enum { DNNMG_F_UNFUSED = 1 };
 enum { DNNMG_F_NANCHECK = 2 };
 enum { DNNMG_NONFINITE_CORRECTION = 1, DNNMG_NONFINITE_RHS = 2 };
 
+/* DNNMG_F_CRANK_NICOLSON: the Crank-Nicolson time scheme of
+ * Eq. (4cranknicholson3) (no body force) instead of implicit Euler.  With
+ * T(w) = C(w) w + nu K w the convection and diffusion rows, the step's defect
+ * becomes
+ *   D = (1/dt) M (u_prev - P v) - (1/2) T(P v) - (1/2) T(u_prev) + B^T P p
+ * and its right-hand side
+ *   b^L = R [ (1/dt) M u_corr - (1/2) T(u_corr) ],  u_corr = P v + d,
+ * the explicit term formed in FP64 like the mass term.  On the first step
+ * u_prev = P v (as with implicit Euler).  Such contexts always run the
+ * separate-launch form, step alone (dnnmg_step_batch rejects them) and use
+ * the same weights and state layout; dnnmg_defect and dnnmg_rhs_restrict
+ * follow the context's scheme, dnnmg_rhs_restrict_noalloc is implicit Euler. */
+enum { DNNMG_F_CRANK_NICOLSON = 4 };
+
 /* Dirichlet sides (Eq. (boundary)); other sides are do-nothing outflow. */
 enum { DNNMG_DIR_XMIN = 1, DNNMG_DIR_XMAX = 2, DNNMG_DIR_YMIN = 4, DNNMG_DIR_YMAX = 8 };
 
@@ -99,7 +113,8 @@ typedef struct {
     double nu;           /* viscosity (>= 0)                                         */
     int precision;       /* DNNMG_FP32 / DNNMG_BF16 / DNNMG_FP8_E4M3                 */
     unsigned dirichlet;  /* DNNMG_DIR_* bits                                         */
-    unsigned flags;      /* 0, or DNNMG_F_UNFUSED | DNNMG_F_NANCHECK                 */
+    unsigned flags;      /* 0, or DNNMG_F_UNFUSED | DNNMG_F_NANCHECK |
+                            DNNMG_F_CRANK_NICOLSON                                   */
 } dnnmg_config;
 
 /* Network sizes: N_in = 4 (n+1)^2 + 4 (prolongated velocity and defect at the

@@ -21,6 +21,7 @@ DNNMG_OK, DNNMG_EINVAL, DNNMG_ENOMEM, DNNMG_EDEVICE, DNNMG_ESTATE, DNNMG_EUNSUPP
 FP32, BF16, FP8_E4M3 = 0, 1, 2
 DNNMG_F_UNFUSED = 1
 DNNMG_F_NANCHECK = 2
+DNNMG_F_CRANK_NICOLSON = 4
 DNNMG_NONFINITE_CORRECTION, DNNMG_NONFINITE_RHS = 1, 2
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
 

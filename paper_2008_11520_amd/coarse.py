@@ -7,10 +7,13 @@ side b_L of the previous step (line 9).  Here, as in the fine step:
 
 * Q1 velocity and Q1 pressure on a structured quadrilateral mesh (possibly
   perturbed; bilinear element maps), 2 x 2 Gauss quadrature;
-* implicit Euler:  (1/dt) M v + C(v) v + nu K v - B^T p = b_L  (momentum rows
-  at nodes without a Dirichlet condition; v = v_D at the others), where the
-  matrices are those of the defect (Eq. (nonlinearshort) read for implicit
-  Euler);
+* the theta scheme:  (1/dt) M v + theta (C(v) v + nu K v) - B^T p = b_L
+  (momentum rows at nodes without a Dirichlet condition; v = v_D at the
+  others), theta = 1 implicit Euler (Eq. (nonlinearshort) read for implicit
+  Euler), theta = 1/2 Crank-Nicolson (Eq. (4cranknicholson3), no body force);
+  the matrices are those of the fine defect.  The explicit part of the
+  theta scheme, -(1 - theta) (C(u) u + nu K u) of the previous velocity u,
+  belongs to the right-hand side (rhs_of);
 * continuity with local projection stabilisation (Sec. 3.1), in its
   two-level form for equal-order Q1:
   (div v, xi) + sum_P alpha_P (grad p - k_P(grad p), grad xi - k_P(grad xi)) = 0,
@@ -40,17 +43,19 @@ _G = (0.5 - 0.5 / math.sqrt(3.0), 0.5 + 0.5 / math.sqrt(3.0))
 
 
 class CoarseNS:
-    """Implicit-Euler Q1/Q1 Navier-Stokes on one structured mesh level.
+    """Q1/Q1 Navier-Stokes with the theta scheme on one structured mesh level.
 
     cxy: (ny+1, nx+1, 2) node coordinates (node (i, j) at index j (nx+1) + i);
-    dirichlet: DNNMG_DIR_* side bits (others are do-nothing outflow)."""
+    dirichlet: DNNMG_DIR_* side bits (others are do-nothing outflow);
+    theta: 1 implicit Euler, 1/2 Crank-Nicolson."""
 
-    def __init__(self, cxy, dt, nu, dirichlet, alpha0=0.1):
+    def __init__(self, cxy, dt, nu, dirichlet, alpha0=0.1, theta=1.0):
         cxy = np.asarray(cxy, dtype=np.float64)
         self.ny, self.nx = cxy.shape[0] - 1, cxy.shape[1] - 1
         nx, ny = self.nx, self.ny
         self.N = (nx + 1) * (ny + 1)
         self.dt, self.nu, self.alpha0 = float(dt), float(nu), float(alpha0)
+        self.theta = float(theta)
         xy = cxy.reshape(-1, 2)
         i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
         n00 = (j * (nx + 1) + i).reshape(-1)
@@ -135,7 +140,7 @@ class CoarseNS:
         """Momentum (2N) and continuity (N) residual of A(v, p) - b, with the
         Dirichlet rows v - v_D and, when pinned, p_0."""
         C, _ = self._convection(v)
-        A = self.M / self.dt + C + self.nu * self.K
+        A = self.M / self.dt + self.theta * (C + self.nu * self.K)
         r = np.empty(3 * self.N)
         r[:self.N] = A @ v[:, 0] - self.Gx @ p - b[:, 0]
         r[self.N:2 * self.N] = A @ v[:, 1] - self.Gy @ p - b[:, 1]
@@ -149,9 +154,10 @@ class CoarseNS:
 
     def jacobian(self, v):
         C, D = self._convection(v)
-        A = self.M / self.dt + C + self.nu * self.K
-        J = sp.bmat([[A + D[0, 0], D[0, 1], -self.Gx],
-                     [D[1, 0], A + D[1, 1], -self.Gy],
+        th = self.theta
+        A = self.M / self.dt + th * (C + self.nu * self.K)
+        J = sp.bmat([[A + th * D[0, 0], th * D[0, 1], -self.Gx],
+                     [th * D[1, 0], A + th * D[1, 1], -self.Gy],
                      [self.Gx.T, self.Gy.T, self.S]], format="lil")
         rows = np.concatenate([np.flatnonzero(self.dmask), self.N + np.flatnonzero(self.dmask)])
         if self.pin_pressure:
@@ -191,3 +197,19 @@ class CoarseNS:
         this level (the step without a network correction)."""
         u = np.asarray(u, dtype=np.float64).reshape(self.N, 2)
         return np.stack([self.M @ u[:, 0], self.M @ u[:, 1]], axis=1) / self.dt
+
+    def transport(self, u):
+        """T(u) = C(u) u + nu K u on this level (N x 2)."""
+        u = np.asarray(u, dtype=np.float64).reshape(self.N, 2)
+        C, _ = self._convection(u)
+        A = C + self.nu * self.K
+        return np.stack([A @ u[:, 0], A @ u[:, 1]], axis=1)
+
+    def rhs_of(self, u):
+        """The theta scheme's right-hand side of a previous velocity u on this
+        level, (1/dt) M u - (1 - theta) T(u) (the step without a network
+        correction)."""
+        b = self.mass_rhs(u)
+        if self.theta != 1.0:
+            b = b - (1.0 - self.theta) * self.transport(u)
+        return b

@@ -85,7 +85,7 @@ int check_config(const dnnmg_config *c)
     if (c->precision < DNNMG_FP32 || c->precision > DNNMG_FP8_E4M3)
         return fail(DNNMG_EINVAL, "precision %d unknown", c->precision);
     if (c->dirichlet > 15u) return fail(DNNMG_EINVAL, "dirichlet flags 0x%x out of range", c->dirichlet);
-    if ((c->flags & ~(unsigned)(DNNMG_F_UNFUSED | DNNMG_F_NANCHECK)) != 0u)
+    if ((c->flags & ~(unsigned)(DNNMG_F_UNFUSED | DNNMG_F_NANCHECK | DNNMG_F_CRANK_NICOLSON)) != 0u)
         return fail(DNNMG_EINVAL, "unknown flags 0x%x", c->flags);
     if (c->H <= 0 || c->Hm < 0) return fail(DNNMG_EINVAL, "H must be > 0 and Hm >= 0");
     if (c->H != 32 && c->H != 64 && c->H != 128)
@@ -103,7 +103,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Device layout of one context's workspace.
 struct Layout {
-    size_t geo, geo64, feat, h, uprev, X, sx, dpatch, part, part2, cxy, flag, bad, nonfinite, total;
+    size_t geo, geo64, map64, feat, h, uprev, X, sx, dpatch, part, part2, cxy, flag, bad, nonfinite, total;
 };
 
 Layout layout_of(const dnnmg_config &c)
@@ -114,6 +114,7 @@ Layout layout_of(const dnnmg_config &c)
     auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
     L.geo = take(sizeof(float) * 6 * s.P);
     L.geo64 = take(sizeof(double) * 4 * s.P);
+    L.map64 = take((c.flags & DNNMG_F_CRANK_NICOLSON) ? sizeof(double) * 8 * s.P : 0);
     L.feat = take(sizeof(float) * 4 * s.P);
     L.h = take(sizeof(float) * (size_t)s.P * c.H);
     L.uprev = take(sizeof(float) * 2 * s.Fu);
@@ -239,6 +240,7 @@ struct dnnmg_ctx {
 
     float *geo() const { return (float *)(ws + L.geo); }
     double *geo64() const { return (double *)(ws + L.geo64); }
+    double *map64() const { return (cfg.flags & DNNMG_F_CRANK_NICOLSON) ? (double *)(ws + L.map64) : nullptr; }
     float *feat() const { return (float *)(ws + L.feat); }
     float *h() const { return (float *)(ws + L.h); }
     float *uprev() const { return (float *)(ws + L.uprev); }
@@ -455,6 +457,11 @@ FlowArgs flow_args(const dnnmg_ctx *c, const float *v, const float *p)
     f.dpatch = c->dpatch();
     f.part = c->part();
     f.nonfinite = (c->cfg.flags & DNNMG_F_NANCHECK) ? (int *)(c->ws + c->L.nonfinite) : nullptr;
+    if (c->cfg.flags & DNNMG_F_CRANK_NICOLSON) {
+        f.theta = 0.5f;
+        f.nu64 = c->cfg.nu;
+        f.map64 = c->map64();
+    }
     return f;
 }
 
@@ -507,8 +514,8 @@ int create_common(const dnnmg_config *cfg, const double *cxy, const float *weigh
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + c->L.nonfinite, 0, sizeof(int), st);
     if (e == hipSuccess) e = hipMemsetAsync(c->first_flag(), 1, sizeof(int), st);
     if (e == hipSuccess)
-        e = launch_geometry((const double *)(c->ws + c->L.cxy), cfg->nx, cfg->ny, c->geo(), c->geo64(), c->feat(),
-                            (int *)(c->ws + c->L.bad), st);
+        e = launch_geometry((const double *)(c->ws + c->L.cxy), cfg->nx, cfg->ny, c->geo(), c->geo64(), c->map64(),
+                            c->feat(), (int *)(c->ws + c->L.bad), st);
     int bad = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&bad, c->ws + c->L.bad, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -761,8 +768,8 @@ extern "C" int dnnmg_create_in_arena(dnnmg_arena *a, const dnnmg_config *cfg, co
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.nonfinite, 0, sizeof(int), st);
     if (e == hipSuccess) e = hipMemsetAsync(c->first_flag(), 1, sizeof(int), st);
     if (e == hipSuccess)
-        e = launch_geometry((const double *)(c->ws + L.cxy), cfg->nx, cfg->ny, c->geo(), c->geo64(), c->feat(),
-                            (int *)(c->ws + L.bad), st);
+        e = launch_geometry((const double *)(c->ws + L.cxy), cfg->nx, cfg->ny, c->geo(), c->geo64(), c->map64(),
+                            c->feat(), (int *)(c->ws + L.bad), st);
     if (e != hipSuccess) {
         // the enqueued work may still touch the block: wait for it before returning the block
         (void)hipStreamSynchronize(st);
@@ -784,7 +791,7 @@ static int enqueue_step(dnnmg_ctx *c, const FlowArgs &f, hipStream_t st)
     Profile &pr = c->prof;
     hipEvent_t *ev = (pr.max_steps > 0 && pr.steps < pr.max_steps) ? &pr.ev[4 * pr.steps] : nullptr;
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[0], st));
-    if (fused_step(c->w->net) && !(g.flags & DNNMG_F_UNFUSED)) {
+    if (fused_step(c->w->net) && !(g.flags & (DNNMG_F_UNFUSED | DNNMG_F_CRANK_NICOLSON))) {
         // defect, network input, GRU and MLP in one launch (stage 1 then times nothing)
         HIP_OR_FAIL(launch_defect_net(f, nullptr, blocks_for(kKindDefect, g.nx, g.ny, g.K), c->w->net, st));
         if (ev) HIP_OR_FAIL(hipEventRecord(ev[1], st));
@@ -1007,7 +1014,7 @@ extern "C" int dnnmg_rhs_restrict_noalloc(int nx, int ny, int K, double dt, cons
     f.bL = b;
     // every scratch word the kernels read is written earlier in this call
     // (geometry, tables, partial sums), so nothing needs clearing
-    HIP_OR_FAIL(launch_geometry(cxy, nx, ny, (float *)f.geo, (double *)f.geo64, (float *)f.feat,
+    HIP_OR_FAIL(launch_geometry(cxy, nx, ny, (float *)f.geo, (double *)f.geo64, nullptr, (float *)f.feat,
                                 (int *)(sc + kStaticBad), st));
     HIP_OR_FAIL(launch_moment_tables(K, tabA, tabM, st));
     HIP_OR_FAIL(launch_rhs(f, nullptr, blocks_for(kKindRhs, nx, ny, K), K, RhsTables{tabA, tabM}, 0, st));
@@ -1142,6 +1149,8 @@ extern "C" int dnnmg_batch_prepare(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int n
         if (!v[i]) return fail(DNNMG_EINVAL, "v[%d] is NULL", i);
         if (b_out && !b_out[i]) return fail(DNNMG_EINVAL, "b_out[%d] is NULL", i);
         if (ctxs[i]->w != w) return fail(DNNMG_EINVAL, "ctxs[%d] does not share the weights of ctxs[0]", i);
+        if (ctxs[i]->cfg.flags & DNNMG_F_CRANK_NICOLSON)
+            return fail(DNNMG_EINVAL, "ctxs[%d] uses DNNMG_F_CRANK_NICOLSON: such flows step alone (dnnmg_step)", i);
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(DNNMG_EINVAL, "ctxs[%d] repeats ctxs[%d]", i, j);
     }

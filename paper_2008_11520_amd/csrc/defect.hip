@@ -26,12 +26,14 @@ namespace dnnmg {
 
 // ---------------------------------------------------------------- geometry
 // Per coarse element: FP32 map vectors for the defect, FP64 coefficients of
-// det J = d0 + d1 xi + d2 eta for the right-hand side, and the four patch
+// det J = d0 + d1 xi + d2 eta for the right-hand side, optionally the FP64
+// map vectors themselves (the Crank-Nicolson rhs), and the four patch
 // features hx, hy, hx/hy, area.  *bad is set if an element is not positively
 // oriented (det J <= 0 at a corner).
 __global__ __launch_bounds__(kThreads) void k_geometry(const double *__restrict__ cxy, int nx, int ny,
                                                        float *__restrict__ geo, double *__restrict__ geo64,
-                                                       float *__restrict__ feat, int *__restrict__ bad)
+                                                       double *__restrict__ map64, float *__restrict__ feat,
+                                                       int *__restrict__ bad)
 {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nx * ny) return;
@@ -52,6 +54,10 @@ __global__ __launch_bounds__(kThreads) void k_geometry(const double *__restrict_
     double d2 = twx * eyy - twy * eyx;       // exy x ey
     double *g64 = geo64 + 4 * (size_t)e;
     g64[0] = d0; g64[1] = d1; g64[2] = d2; g64[3] = 0.0;
+    if (map64) {
+        double *m = map64 + 8 * (size_t)e;
+        m[0] = exx; m[1] = exy_; m[2] = eyx; m[3] = eyy; m[4] = twx; m[5] = twy; m[6] = 0.0; m[7] = 0.0;
+    }
     if (!(d0 > 0.0 && d0 + d1 > 0.0 && d0 + d2 > 0.0 && d0 + d1 + d2 > 0.0)) *bad = 1;
     double hx = 0.5 * (hypot(exx, exy_) + hypot(c11[0] - c01[0], c11[1] - c01[1]));
     double hy = 0.5 * (hypot(eyx, eyy) + hypot(c11[0] - c10[0], c11[1] - c10[1]));
@@ -61,12 +67,12 @@ __global__ __launch_bounds__(kThreads) void k_geometry(const double *__restrict_
     f[0] = (float)hx; f[1] = (float)hy; f[2] = (float)(hx / hy); f[3] = (float)(0.5 * fabs(ax * by - ay * bx));
 }
 
-hipError_t launch_geometry(const double *cxy, int nx, int ny, float *geo, double *geo64, float *feat,
-                           int *bad, hipStream_t s)
+hipError_t launch_geometry(const double *cxy, int nx, int ny, float *geo, double *geo64, double *map64,
+                           float *feat, int *bad, hipStream_t s)
 {
     int P = nx * ny;
     hipLaunchKernelGGL(k_geometry, dim3((P + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
-                       cxy, nx, ny, geo, geo64, feat, bad);
+                       cxy, nx, ny, geo, geo64, map64, feat, bad);
     return hipGetLastError();
 }
 
@@ -304,9 +310,16 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
 
 // FUSED (K = 2, BF16 input): the network input stays in LDS and the tile's
 // GRU and MLP run right after (gru_fused); HM is the MLP hidden width.
-template <int K, typename XT, bool OPAQUE_TID, bool FUSED = false, int HM = 0>
+// CN: the theta scheme (Crank-Nicolson at f.theta = 1/2): after the first
+// step the elements take element_residual_theta, with the previous corrected
+// velocity itself (not divided by dt) at the nodes.  On the first step the
+// previous velocity is P v, the two transport levels coincide and the mass
+// term vanishes, so the implicit-Euler elements with 1/dt = 0 give the same
+// defect.
+template <int K, typename XT, bool OPAQUE_TID, bool FUSED = false, int HM = 0, bool CN = false>
 __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const NetArgs *net = nullptr)
 {
+    static_assert(!(CN && FUSED), "the theta scheme runs unfused");
     const int tid = OPAQUE_TID ? tile_thread() : (int)threadIdx.x;
     constexpr int n = 1 << K;
     constexpr float inv_n = 1.0f / n;
@@ -381,13 +394,16 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
 
     // 2. u_prev / dt on the tile's nodes + halo (zero before the first step:
     //    u_prev is then P v, so the element code, which subtracts v / dt at
-    //    each Gauss point, takes 1/dt as 0); clear the node accumulators
+    //    each Gauss point, takes 1/dt as 0); clear the node accumulators.
+    //    The theta scheme keeps u_prev itself.
     const float idt = first ? 0.0f : inv_dt;
+    const bool theta_elems = CN && !first;
 #pragma unroll
     for (int i = 0; i < NIT; ++i) {
         const int t = tid + i * kThreads;
         if (t >= NN * NN) break;
-        s_w[t] = make_float2(uq[i].x * idt, uq[i].y * idt);
+        const float sw = CN ? 1.0f : idt;
+        s_w[t] = make_float2(uq[i].x * sw, uq[i].y * sw);
         s_acc[t] = make_float2(0.f, 0.f);
     }
     __syncthreads();
@@ -416,7 +432,24 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
             const int n0 = (sr * SH + 1) * NN + ec + 1;
             sn0[s] = n0;
             const CoarseRec &r = s_c[((eJ >> K) - cj0) * CE + ((eI >> K) - ci0)];
-            strip_residual<K, SH, HwRcp>(r, eI & (n - 1), eJ & (n - 1), nu, idt, s_w + n0, NN, S[s]);
+            if (theta_elems) {
+                // element by element up the strip: corners 00, 10 on node row k, 01, 11 on row k + 1
+                const float2 *w = s_w + n0;
+#pragma unroll
+                for (int k = 0; k < SH; ++k) {
+                    float R[8];
+                    element_residual_theta<K, HwRcp>(r, eI & (n - 1), (eJ & (n - 1)) + k, nu, inv_dt, f.theta,
+                                                     w[k * NN], w[k * NN + 1], w[(k + 1) * NN],
+                                                     w[(k + 1) * NN + 1], R);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        S[s][k][c] = k ? S[s][k][c] + R[c] : R[c];
+                        S[s][k + 1][c] = R[4 + c];
+                    }
+                }
+            } else {
+                strip_residual<K, SH, HwRcp>(r, eI & (n - 1), eJ & (n - 1), nu, idt, s_w + n0, NN, S[s]);
+            }
         }
     }
     // halo ring, one element per thread (halo_of)
@@ -431,8 +464,12 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
             const int n0 = (me + 1) * NN + le + 1;
             hn0 = n0;
             const CoarseRec &r = s_c[((eJ >> K) - cj0) * CE + ((eI >> K) - ci0)];
-            element_residual<K, HwRcp>(r, eI & (n - 1), eJ & (n - 1), nu, idt, s_w[n0], s_w[n0 + 1], s_w[n0 + NN],
-                                       s_w[n0 + NN + 1], Rh);
+            if (theta_elems)
+                element_residual_theta<K, HwRcp>(r, eI & (n - 1), eJ & (n - 1), nu, inv_dt, f.theta, s_w[n0],
+                                                 s_w[n0 + 1], s_w[n0 + NN], s_w[n0 + NN + 1], Rh);
+            else
+                element_residual<K, HwRcp>(r, eI & (n - 1), eJ & (n - 1), nu, idt, s_w[n0], s_w[n0 + 1],
+                                           s_w[n0 + NN], s_w[n0 + NN + 1], Rh);
         }
     }
 
@@ -654,6 +691,13 @@ __global__ __launch_bounds__(kThreads, (defect_waves<K, XT>())) void k_defect(Fl
     }
 }
 
+// The theta scheme (Crank-Nicolson), single flow.
+template <int K, typename XT>
+__global__ __launch_bounds__(kThreads, (defect_waves<K, XT>())) void k_defect_cn(FlowArgs single)
+{
+    defect_tile<K, XT, false, false, 0, true>(single, xcd_tile(blockIdx.x, gridDim.x));
+}
+
 template <bool BATCHED, int HM>
 __global__ __launch_bounds__(kThreads, 4) void k_defect_net(FlowArgs single, const BatchTable *__restrict__ bt, NetArgs net)
 {
@@ -675,7 +719,7 @@ bool fused_step(const NetArgs &net) { return net.prec == 1 && net.K == 2 && net.
 
 hipError_t launch_defect_net(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net, hipStream_t s)
 {
-    if (!fused_step(net)) return hipErrorInvalidValue;
+    if (!fused_step(net) || f.theta != 1.0f) return hipErrorInvalidValue;
     dim3 g(nblocks), b(kThreads);
     if (net.Hm == 64) {
         if (bt) hipLaunchKernelGGL((k_defect_net<true, 64>), g, b, 0, s, f, bt, net);
@@ -690,8 +734,11 @@ hipError_t launch_defect_net(const FlowArgs &f, const BatchTable *bt, int nblock
 hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, int xfmt, hipStream_t s)
 {
     dim3 g(nblocks), b(kThreads);
+    const bool cn = f.theta != 1.0f;
+    if (cn && bt) return hipErrorInvalidValue;
 #define DNNMG_DEFECT_LAUNCH(KK, XT)                                                           \
     if (bt) hipLaunchKernelGGL((k_defect<KK, XT, true>), g, b, 0, s, f, bt);                   \
+    else if (cn) hipLaunchKernelGGL((k_defect_cn<KK, XT>), g, b, 0, s, f);                     \
     else hipLaunchKernelGGL((k_defect<KK, XT, false>), g, b, 0, s, f, bt);
 #define DNNMG_DEFECT_CASE(KK)                                                                 \
     case KK:                                                                                  \

@@ -39,6 +39,11 @@ struct FlowArgs {
     const float *dbar_in;  // stage: given fine correction (rhs/restrict alone)
     double *bL;            // restricted rhs output (gather)
     int *nonfinite;        // non-finite check (or nullptr): bit 0 correction, bit 1 restricted rhs
+    // time scheme: theta = 1 implicit Euler, 1/2 Crank-Nicolson (then map64
+    // holds the coarse maps in FP64 and nu64 the viscosity for the rhs)
+    float theta = 1.0f;
+    double nu64 = 0.0;
+    const double *map64 = nullptr;   // per coarse element: ex, ey, exy (x, y each), 2 pad
 };
 
 // Shared network description.
@@ -127,9 +132,12 @@ constexpr float kLog2e = 1.44269504088896340736f;
 int blocks_for(int kind, int nx, int ny, int K);
 
 // Launchers (return hipError_t of the launch).
-hipError_t launch_geometry(const double *cxy, int nx, int ny, float *geo, double *geo64,
+// map64 (or nullptr): the FP64 map vectors the Crank-Nicolson rhs needs.
+hipError_t launch_geometry(const double *cxy, int nx, int ny, float *geo, double *geo64, double *map64,
                            float *feat, int *bad, hipStream_t s);
 hipError_t launch_prolong(const FlowArgs &f, int K, float *pv, float *pp, hipStream_t s);
+// f.theta != 1 (Crank-Nicolson) takes the theta-weighted element residuals;
+// single flow only (bt must be null then).
 hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, int xfmt, hipStream_t s);
 // Defect + GRU + MLP in one launch (K = 2, BF16 operands, H = 64, Hm 0 or 64):
 // the network input never leaves LDS.  fused_step tells whether it applies.
@@ -141,6 +149,7 @@ hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int nblocks, cons
                       hipStream_t s);
 // Blocks of the network launch (persistent kernels use fewer than row tiles).
 int net_blocks(const NetArgs &net, int row_tiles);
+// f.theta != 1 adds the explicit transport term -(1 - theta) R T(u) (single flow).
 hipError_t launch_rhs(const FlowArgs &f, const BatchTable *bt, int nblocks, int K,
                       const RhsTables &tab, int from_patches, hipStream_t s);
 hipError_t launch_gather(const FlowArgs &f, const BatchTable *bt, int nblocks, hipStream_t s);

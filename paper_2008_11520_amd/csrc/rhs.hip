@@ -32,10 +32,110 @@ __device__ inline bool dirichlet_node(unsigned dir, int I, int J, int NX, int NY
     return ((dir & 1u) && I == 0) || ((dir & 2u) && I == NX) || ((dir & 4u) && J == 0) || ((dir & 8u) && J == NY);
 }
 
+// The explicit transport term of the theta scheme at the four corners c of
+// each patch E, in FP64:
+//   T_c = int_E N_c (u . grad u) + nu grad N_c . grad u  dx,  u = P v + d,
+// N_c the coarse hat: since the fine Q1 space holds the coarse one, the
+// restriction R = P^T of the fine rows T(u) is this integral of the coarse
+// hats, taken with the fine elements' 2 x 2 Gauss rule (u is bilinear on each
+// fine element, the map F bilinear on E).  Per Gauss point (xi, eta) in E's
+// reference square, with Cof = det J^{-T} and w = 1 / (4 n^2):
+//   w [ N_c (u_x (Cof grad_ref u)_x + u_y (Cof grad_ref u)_y)
+//       + (nu / det) (Cof grad_ref N_c) . (Cof grad_ref u) ].
+// One item per (patch, fine element row); the rows of a patch sit on
+// neighbouring lanes and are summed with a fixed butterfly.
+template <int K>
+__device__ __forceinline__ void transport_corners(const FlowArgs &f, int tid, int pi0, int pj0, const float2 *s_v,
+                                                  const float2 *s_dbar, double *s_T)
+{
+    constexpr int n = 1 << K;
+    constexpr int TP = kRhsFine / n, NO = kRhsFine + 1;
+    constexpr int NI = TP * TP * n;
+    static_assert(kThreads % n == 0, "a patch's rows on neighbouring lanes of one wave");
+    constexpr double inv_n = 1.0 / n, wq = 0.25 / (n * n);
+    constexpr double g0 = 0.21132486540518711775, g1 = 0.78867513459481288225;
+    const double nu = f.nu64;
+    const int nx = f.nx, ny = f.ny;
+    for (int it0 = 0; it0 < NI; it0 += kThreads) {
+        const int it = it0 + tid;
+        const int b = it % n, pl = it / n;
+        const int pa = pl % TP, pb = pl / TP;
+        double acc[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+        if (it < NI && pi0 + pa < nx && pj0 + pb < ny) {
+            const double *m = f.map64 + 8 * ((size_t)(pj0 + pb) * nx + pi0 + pa);
+            const double exx = m[0], exy = m[1], eyx = m[2], eyy = m[3], twx = m[4], twy = m[5];
+            const int c = pb * (TP + 1) + pa;
+            const float2 v00 = s_v[c], v10 = s_v[c + 1], v01 = s_v[c + TP + 1], v11 = s_v[c + TP + 2];
+            // u = P v + d at fine node (a, bb) of the patch, FP64
+            auto unode = [&](int a, int bb, double &ux, double &uy) {
+                const double xi = a * inv_n, eta = bb * inv_n;
+                const double n00 = (1.0 - xi) * (1.0 - eta), n10 = xi * (1.0 - eta), n01 = (1.0 - xi) * eta,
+                             n11 = xi * eta;
+                const float2 d = s_dbar[(pb * n + bb) * NO + pa * n + a];
+                ux = n00 * v00.x + n10 * v10.x + n01 * v01.x + n11 * v11.x + (double)d.x;
+                uy = n00 * v00.y + n10 * v10.y + n01 * v01.y + n11 * v11.y + (double)d.y;
+            };
+            double u0x, u0y, u2x, u2y;     // left column of the current element: rows b, b + 1
+            unode(0, b, u0x, u0y);
+            unode(0, b + 1, u2x, u2y);
+#pragma unroll 1
+            for (int a = 0; a < n; ++a) {
+                double u1x, u1y, u3x, u3y;
+                unode(a + 1, b, u1x, u1y);
+                unode(a + 1, b + 1, u3x, u3y);
+#pragma unroll 1
+                for (int q = 0; q < 4; ++q) {
+                        const double s = (q & 1) ? g1 : g0, t = (q >> 1) ? g1 : g0;
+                        const double xi = (a + s) * inv_n, eta = (b + t) * inv_n;
+                        const double xs = exx + twx * eta, ys = exy + twy * eta;
+                        const double xt = eyx + twx * xi, yt = eyy + twy * xi;
+                        const double det = xs * yt - xt * ys;
+                        const double ux = (1.0 - t) * (u0x + (u1x - u0x) * s) + t * (u2x + (u3x - u2x) * s);
+                        const double uy = (1.0 - t) * (u0y + (u1y - u0y) * s) + t * (u2y + (u3y - u2y) * s);
+                        // coarse-reference derivatives (n times the fine element's)
+                        const double usx = n * ((u1x - u0x) * (1.0 - t) + (u3x - u2x) * t);
+                        const double usy = n * ((u1y - u0y) * (1.0 - t) + (u3y - u2y) * t);
+                        const double utx = n * ((u2x - u0x) * (1.0 - s) + (u3x - u1x) * s);
+                        const double uty = n * ((u2y - u0y) * (1.0 - s) + (u3y - u1y) * s);
+                        // Cof grad_ref of each component
+                        const double gxx = yt * usx - ys * utx, gxy = -xt * usx + xs * utx;
+                        const double gyx = yt * usy - ys * uty, gyy = -xt * usy + xs * uty;
+                        const double cvx = ux * gxx + uy * gxy, cvy = ux * gyx + uy * gyy;
+                        const double nud = nu / det;
+                        const double N[4] = {(1.0 - xi) * (1.0 - eta), xi * (1.0 - eta), (1.0 - xi) * eta, xi * eta};
+                        const double Ns[4] = {-(1.0 - eta), 1.0 - eta, -eta, eta};
+                        const double Nt[4] = {-(1.0 - xi), -xi, 1.0 - xi, xi};
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const double hx = yt * Ns[k] - ys * Nt[k], hy = -xt * Ns[k] + xs * Nt[k];
+                            acc[k][0] += wq * (N[k] * cvx + nud * (hx * gxx + hy * gxy));
+                            acc[k][1] += wq * (N[k] * cvy + nud * (hx * gyx + hy * gyy));
+                        }
+                    }
+                u0x = u1x; u0y = u1y; u2x = u3x; u2y = u3y;
+            }
+        }
+        // sum over the patch's n rows (lanes it - b .. it - b + n - 1)
+#pragma unroll
+        for (int off = 1; off < n; off <<= 1)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) acc[k][c] += __shfl_xor(acc[k][c], off);
+        if (it < NI && b == 0)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                s_T[8 * pl + 2 * k] = acc[k][0];
+                s_T[8 * pl + 2 * k + 1] = acc[k][1];
+            }
+    }
+}
+
 // One workgroup per tile of kRhsFine x kRhsFine fine elements (TP x TP patches).
 // from_patches = 1: average f.dpatch and store the corrected velocity (the
 // step); 0: take the correction from f.dbar_in (stage, state untouched).
-template <int K, int FROM_PATCHES, bool OPAQUE_TID>
+// CN: the theta scheme's rhs, (1/dt) M u - (1 - theta) T(u), restricted.
+template <int K, int FROM_PATCHES, bool OPAQUE_TID, bool CN = false>
 __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables tab)
 {
     const int tid = OPAQUE_TID ? tile_thread() : (int)threadIdx.x;
@@ -54,6 +154,7 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
     __shared__ double s_A[4 * (n + 1)];
     __shared__ double s_M[3 * 4 * 4];
     __shared__ double2 s_g[2 * TP * TP];
+    __shared__ double s_T[CN ? 8 * TP * TP : 1];
 
     const int nx = f.nx, ny = f.ny, NX = nx * n, NY = ny * n;
     const int tiles_x = (nx + TP - 1) / TP;
@@ -314,6 +415,11 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
         if (nonfin && f.nonfinite) atomicOr(f.nonfinite, 1);
     }
     __syncthreads();
+    if constexpr (CN) {
+        transport_corners<K>(f, tid, pi0, pj0, s_v, s_dbar, s_T);
+        __syncthreads();
+    }
+    const double th_old = CN ? 1.0 - (double)f.theta : 0.0;
 
     // ---- FP64 share of each patch at each of its 4 corners c = (cx, cy):
     //      (1/dt) [ sum_k d_k sum_{a,b} A[mx_k][cx][a] A[my_k][cy][b] Dbar(a,b)
@@ -375,7 +481,9 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                                  d2 * s_M[(2 * 4 + c) * 4 + cc];
                 acc += w * vq[cc];
             }
-            pq[4 * cy * P] = f.inv_dt64 * acc;
+            double b = f.inv_dt64 * acc;
+            if constexpr (CN) b -= th_old * s_T[8 * pl + 2 * c + comp];
+            pq[4 * cy * P] = b;
         }
     }
 }
@@ -386,6 +494,13 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
 // waves; the batched K = 3 instance needs more registers than 5 waves leave).
 template <int K, bool BATCHED>
 constexpr int rhs_waves() { return K == 2 ? 6 : (K == 3 && !BATCHED ? 5 : 4); }
+
+// The theta scheme (Crank-Nicolson), single flow.
+template <int K, int FROM_PATCHES>
+__global__ __launch_bounds__(kThreads, 3) void k_rhs_cn(FlowArgs single, RhsTables tab)
+{
+    rhs_tile<K, FROM_PATCHES, false, true>(single, xcd_tile(blockIdx.x, gridDim.x), tab);
+}
 
 template <int K, int FROM_PATCHES, bool BATCHED>
 __global__ __launch_bounds__(kThreads, (rhs_waves<K, BATCHED>())) void k_rhs(FlowArgs single, const BatchTable *__restrict__ bt, RhsTables tab)
@@ -445,10 +560,14 @@ hipError_t launch_rhs(const FlowArgs &f, const BatchTable *bt, int nblocks, int 
                       int from_patches, hipStream_t s)
 {
     if (bt && !from_patches) return hipErrorInvalidValue;   // batched launches are whole steps
+    const bool cn = f.theta != 1.0f;
+    if (cn && (bt || !f.map64)) return hipErrorInvalidValue;
     dim3 g(nblocks), b(kThreads);
 #define DNNMG_RHS_CASE(KK)                                                                \
     case KK:                                                                              \
-        if (bt) hipLaunchKernelGGL((k_rhs<KK, 1, true>), g, b, 0, s, f, bt, tab);         \
+        if (cn && from_patches) hipLaunchKernelGGL((k_rhs_cn<KK, 1>), g, b, 0, s, f, tab); \
+        else if (cn) hipLaunchKernelGGL((k_rhs_cn<KK, 0>), g, b, 0, s, f, tab);           \
+        else if (bt) hipLaunchKernelGGL((k_rhs<KK, 1, true>), g, b, 0, s, f, bt, tab);    \
         else if (from_patches) hipLaunchKernelGGL((k_rhs<KK, 1, false>), g, b, 0, s, f, bt, tab); \
         else hipLaunchKernelGGL((k_rhs<KK, 0, false>), g, b, 0, s, f, bt, tab);           \
         break;

@@ -6,7 +6,8 @@ Per time step n:
   lines 6-9: the fine step on level L+K (prolongation, defect, GRU + MLP
              correction, right-hand side of the corrected velocity, its
              restriction), whose b_L is the next coarse right-hand side.
-The first coarse solve takes b = (1/dt) M_L v_0 (no fine step before it).
+The first coarse solve takes the coarse right-hand side of v_0,
+(1/dt) M_L v_0 - (1 - theta) T_L(v_0) (no fine step before it).
 Dirichlet values at step n are the flow's boundary values at t_n.
 
 The fine step is an object with step(v, p) -> b_L (coarse (N, 2) arrays,
@@ -26,10 +27,13 @@ class GpuFineStep:
     """dnnmg_step + dnnmg_restrict_rhs on the device: the coarse fields go
     to the device as FP32, b_L comes back as FP64."""
 
-    def __init__(self, flow, K, H, Hm, weights, nu, precision="fp32"):
+    def __init__(self, flow, K, H, Hm, weights, nu, precision="fp32", theta=1.0):
         import torch
-        from . import DnnMG, make_config
-        self.g = DnnMG(make_config(flow.nx, flow.ny, K, H, Hm, flow.dt, nu, precision, flow.dirichlet),
+        from . import DNNMG_F_CRANK_NICOLSON, DnnMG, make_config
+        if theta not in (1.0, 0.5):
+            raise ValueError("theta must be 1 (implicit Euler) or 1/2 (Crank-Nicolson)")
+        flags = DNNMG_F_CRANK_NICOLSON if theta == 0.5 else 0
+        self.g = DnnMG(make_config(flow.nx, flow.ny, K, H, Hm, flow.dt, nu, precision, flow.dirichlet, flags),
                        flow.cxy, weights)
         nc = (flow.nx + 1) * (flow.ny + 1)
         self.v = torch.empty(2 * nc, dtype=torch.float32, device="cuda")
@@ -59,15 +63,17 @@ def boundary_values(flow, n):
     return v.astype(np.float64)
 
 
-def run(flow, nu, steps, fine=None, coarse=None):
-    """Run `steps` DNN-MG time steps of `flow` (a synth.Flow).  fine=None
-    runs the coarse solver alone (b = (1/dt) M_L v_{n-1}: plain coarse
-    multigrid in the paper's comparison).  Returns the coarse velocities and
-    pressures per step, the Newton step counts and the coarse-solve time."""
-    ns = coarse if coarse is not None else CoarseNS(flow.cxy, flow.dt, nu, flow.dirichlet)
+def run(flow, nu, steps, fine=None, coarse=None, theta=1.0):
+    """Run `steps` DNN-MG time steps of `flow` (a synth.Flow) with the time
+    scheme's weight theta (1 implicit Euler, 1/2 Crank-Nicolson; the fine
+    step must use the same).  fine=None runs the coarse solver alone (b the
+    coarse right-hand side of v_{n-1}: plain coarse multigrid in the paper's
+    comparison).  Returns the coarse velocities and pressures per step, the
+    Newton step counts and the coarse-solve time."""
+    ns = coarse if coarse is not None else CoarseNS(flow.cxy, flow.dt, nu, flow.dirichlet, theta=theta)
     v = boundary_values(flow, 0)
     p = np.zeros(ns.N)
-    b = ns.mass_rhs(v)
+    b = ns.rhs_of(v)
     vs, ps, newton = [], [], []
     t_coarse = 0.0
     for n in range(1, steps + 1):
@@ -79,5 +85,5 @@ def run(flow, nu, steps, fine=None, coarse=None):
         newton.append(it)
         # the fine step's coarse inputs are FP32 (the library's boundary)
         vf, pf = v.astype(np.float32), p.astype(np.float32)
-        b = fine.step(vf, pf) if fine is not None else ns.mass_rhs(v)
+        b = fine.step(vf, pf) if fine is not None else ns.rhs_of(v)
     return dict(v=np.array(vs), p=np.array(ps), newton=newton, coarse_s=t_coarse)

@@ -84,15 +84,15 @@ def to_dev(a, dtype=None):
     return t.cuda()
 
 
-def make_gpu_flow(flow, K, H, Hm, nu, weights, precision="fp32", share=None):
+def make_gpu_flow(flow, K, H, Hm, nu, weights, precision="fp32", share=None, flags=0):
     import paper_2008_11520_amd as pam
-    cfg = pam.make_config(flow.nx, flow.ny, K, H, Hm, flow.dt, nu, precision, flow.dirichlet)
+    cfg = pam.make_config(flow.nx, flow.ny, K, H, Hm, flow.dt, nu, precision, flow.dirichlet, flags)
     return pam.DnnMG(cfg, flow.cxy, None if share is not None else weights, share=share)
 
 
-def make_oracle_flow(flow, K, H, Hm, nu, weights):
+def make_oracle_flow(flow, K, H, Hm, nu, weights, theta=1.0):
     return oracle.OracleFlow(flow.nx, flow.ny, K, H, Hm, flow.dt, nu, flow.dirichlet,
-                             flow.cxy, weights.astype(np.float64))
+                             flow.cxy, weights.astype(np.float64), theta=theta)
 
 
 class GpuRunner:
@@ -149,9 +149,9 @@ class OracleFineStep:
     """The oracle's fine step as the fine step of the closed DNN-MG loop
     (paper_2008_11520_amd.loop.run): coarse v, p in, b_L out (FP64)."""
 
-    def __init__(self, flow, K, H, Hm, weights, nu, fp8=False):
+    def __init__(self, flow, K, H, Hm, weights, nu, fp8=False, theta=1.0):
         self.o = oracle.OracleFlow(flow.nx, flow.ny, K, H, Hm, flow.dt, nu, flow.dirichlet, flow.cxy,
-                                   np.asarray(weights, dtype=np.float64), fp8=fp8)
+                                   np.asarray(weights, dtype=np.float64), fp8=fp8, theta=theta)
 
     def step(self, v, p):
         return self.o.step(np.asarray(v, np.float64), np.asarray(p, np.float64), want=("bL",))["bL"]

@@ -129,7 +129,7 @@ def test_fp8_config_sizes_and_quantiser_validation():
 
 def test_unknown_flags_rejected_on_host():
     L = pam.lib()
-    c = cfg(flags=4)
+    c = cfg(flags=8)
     s = pam.sizes(4, 3, 2)
     cxy = np.zeros(2 * s["Nc"])
     w = np.zeros(pam.weight_count(c), dtype=np.float32)
@@ -156,12 +156,22 @@ def test_noalloc_entry_point_rejects_on_the_host():
         assert msg in L.dnnmg_last_error().decode(), (args, L.dnnmg_last_error())
 
 
+def test_crank_nicolson_flag_is_known_and_holds_fp64_maps():
+    """DNNMG_F_CRANK_NICOLSON is a valid flag; its workspace adds the FP64
+    map vectors (64 bytes per patch, 256-byte aligned)."""
+    base = pam.workspace_bytes(cfg())
+    cn = pam.workspace_bytes(cfg(flags=pam.DNNMG_F_CRANK_NICOLSON))
+    P = 4 * 3
+    assert cn - base == (64 * P + 255) // 256 * 256
+    assert pam.workspace_bytes(cfg(flags=pam.DNNMG_F_CRANK_NICOLSON | pam.DNNMG_F_NANCHECK)) == cn
+
+
 def test_nancheck_flag_validation():
     """DNNMG_F_NANCHECK is a known flag (the configuration is valid); unknown
     flag bits are not; dnnmg_nonfinite rejects NULL arguments on the host."""
     assert pam.workspace_bytes(cfg(flags=pam.DNNMG_F_NANCHECK)) > pam.workspace_bytes(cfg()) - 1
     assert pam.workspace_bytes(cfg(flags=pam.DNNMG_F_NANCHECK | pam.DNNMG_F_UNFUSED)) > 0
-    assert pam.workspace_bytes(cfg(flags=4)) == 0
+    assert pam.workspace_bytes(cfg(flags=8)) == 0
     L = pam.lib()
     out = ctypes.c_int(7)
     assert L.dnnmg_nonfinite(None, 1, ctypes.byref(out), None) == pam.DNNMG_EINVAL

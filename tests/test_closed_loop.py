@@ -35,3 +35,24 @@ def test_seeded_weights_change_the_trajectory():
     ref = loop.run(flow, nu, 4)
     assert np.abs(dnn["v"][0] - ref["v"][0]).max() == 0.0        # the first coarse solve has no fine input
     assert np.abs(dnn["v"][-1] - ref["v"][-1]).max() > 1e-2 * np.abs(ref["v"]).max()
+
+
+@pytest.mark.parametrize("case", ["unit16_k1", "channel24x8_k2_rect"])
+def test_crank_nicolson_zero_weights_reproduce_the_coarse_loop(case):
+    """Crank-Nicolson: with zero weights b_L = R [(1/dt) M_f P v - (1/2) T_f(P v)].
+    On affine meshes the fine 2 x 2 Gauss rule integrates the coarse hats'
+    mass, convection and diffusion terms exactly (polynomials of degree <= 3
+    per variable), as the coarse rule does, so R T_f(P v) = T_L(v) and the loop
+    reproduces the coarse Crank-Nicolson loop."""
+    if case == "unit16_k1":
+        flow, K, H, Hm = synth.unit_square_flow(16, 16, 1, 0.01), 1, 32, 0
+    else:
+        flow, K, H, Hm = synth.channel_flow(24, 8, 2, 0.005), 2, 64, 64
+    nu = 1e-3
+    w = np.zeros_like(synth.xavier_weights(K, H, Hm, 1))
+    dnn = loop.run(flow, nu, 5, fine=OracleFineStep(flow, K, H, Hm, w, nu, theta=0.5), theta=0.5)
+    ref = loop.run(flow, nu, 5, theta=0.5)
+    ie = loop.run(flow, nu, 5)
+    scale = np.abs(ref["v"]).max()
+    assert np.abs(dnn["v"] - ref["v"]).max() <= 1e-6 * scale
+    assert np.abs(ie["v"][-1] - ref["v"][-1]).max() > 1e-4 * scale    # the scheme matters
