@@ -52,6 +52,17 @@ def lib():
         L.orc_transport_apply.argtypes = [i, i, i, _D, _D, d, _D]
         L.orc_defect_theta.argtypes = [i, i, i, _D, _D, _D, _D, d, d, d, u, _D]
         L.orc_rhs_restrict_theta.argtypes = [i, i, i, _D, _D, _D, d, d, d, _D]
+        L.orc_step_form.argtypes = [i, i, i, i, i, d, d, d, u, i, i, _D, _D, _D, _D, _D, _D, i, i,
+                                    _D, _D, _D, _D, _D, _D]
+        L.orc_step_form.restype = i
+        L.orc_continuity_rows.argtypes = [i, i, i, _D, _D, _D]
+        L.orc_paper_geometry.argtypes = [i, i, _D, _D]
+        L.orc_peclet.argtypes = [i, i, _D, _D, d, _D]
+        L.orc_gather_input_paper.argtypes = [i, i, i, _D, _D, _D, _D, _D, _D]
+        L.orc_gru_form.argtypes = [i, i, i, _D, _D, _D, _D, _D, _D, _D, _D, i, _D]
+        L.orc_conv_head.argtypes = [i, i, i, _D, _D, _D, _D, _D, _D]
+        L.orc_paper_weight_count.argtypes = [i, i]
+        L.orc_paper_weight_count.restype = ctypes.c_long
         L.orc_e4m3_decode.argtypes = [u]
         L.orc_e4m3_decode.restype = d
         L.orc_e4m3_encode.argtypes = [ctypes.c_float]
@@ -273,17 +284,72 @@ def rhs_restrict(nx, ny, K, cxy, v, Dbar, dt):
     return out
 
 
-class OracleFlow:
-    """Stateful wrapper: h (P x H) and u_prev (Fn x 2) in float64."""
+def continuity_rows(nx, ny, K, cxy, pv):
+    """-(div Pv, xi_a) at the fine nodes (unmasked)."""
+    s = sizes(nx, ny, K)
+    out = np.empty(s["Fn"])
+    lib().orc_continuity_rows(nx, ny, K, _p(_f64(cxy)), _p(_f64(pv)), _p(out))
+    return out
 
-    def __init__(self, nx, ny, K, H, Hm, dt, nu, dirichlet, cxy, weights, fp8=False, theta=1.0):
+
+def paper_geometry(nx, ny, cxy):
+    out = np.empty((nx * ny, 12))
+    lib().orc_paper_geometry(nx, ny, _p(_f64(cxy)), _p(out))
+    return out
+
+
+def peclet(nx, ny, cxy, v, nu):
+    out = np.empty((nx * ny, 4))
+    lib().orc_peclet(nx, ny, _p(_f64(cxy)), _p(_f64(v)), nu, _p(out))
+    return out
+
+
+def gather_input_paper(nx, ny, K, D, Rp, v, Pe, G):
+    s = sizes(nx, ny, K)
+    out = np.empty((s["P"], 3 * s["nf"] + 24))
+    lib().orc_gather_input_paper(nx, ny, K, _p(_f64(D)), _p(_f64(Rp)), _p(_f64(v)), _p(_f64(Pe)), _p(_f64(G)),
+                                 _p(out))
+    return out
+
+
+def gru_form(X, h, Wz, Wr, Wh, Uz, Ur, Uh, reset_after):
+    X, h = _f64(X), _f64(h)
+    P, nin = X.shape
+    H = h.shape[1]
+    out = np.empty((P, H))
+    lib().orc_gru_form(P, nin, H, *[_p(_f64(w)) for w in (Wz, Wr, Wh, Uz, Ur, Uh)], _p(X), _p(h),
+                       int(reset_after), _p(out))
+    return out
+
+
+def conv_head(K, h, M, WV, WS, wf):
+    h = _f64(h)
+    P, H = h.shape
+    out = np.empty((P, 2 * (2 ** K + 1) ** 2))
+    lib().orc_conv_head(P, K, H, _p(_f64(M)), _p(_f64(WV)), _p(_f64(WS)), _p(_f64(wf)), _p(h), _p(out))
+    return out
+
+
+def paper_weight_count(K, H):
+    return int(lib().orc_paper_weight_count(K, H))
+
+
+class OracleFlow:
+    """Stateful wrapper: h (P x H) and u_prev (Fn x 2) in float64.
+    form 0: the workloads' network; 1: the paper's (orc_step_form)."""
+
+    def __init__(self, nx, ny, K, H, Hm, dt, nu, dirichlet, cxy, weights, fp8=False, theta=1.0, form=0,
+                 reset_after=False):
         self.nx, self.ny, self.K, self.H, self.Hm = nx, ny, K, H, Hm
         self.fp8 = bool(fp8)
         self.theta = float(theta)
+        self.form, self.reset_after = int(form), int(bool(reset_after))
         self.dt, self.nu, self.dirichlet = dt, nu, dirichlet
         self.cxy = _f64(cxy).reshape(-1, 2)
         self.w = _f64(weights).reshape(-1)
         s = sizes(nx, ny, K)
+        if self.form:
+            s["nin"] = 3 * s["nf"] + 24
         self.s = s
         self.h = np.zeros((s["P"], H))
         self.uprev = np.zeros((s["Fn"], 2))
@@ -296,8 +362,8 @@ class OracleFlow:
                       dpatch=(s["P"], s["nout"]), Dbar=(s["Fn"], 2), bL=(s["Nc"], 2))
         for k in want:
             outs[k] = np.empty(shapes[k])
-        rc = lib().orc_step_theta(self.nx, self.ny, self.K, self.H, self.Hm, self.dt, self.nu, self.theta,
-                                  self.dirichlet, _p(self.cxy), _p(self.w),
+        rc = lib().orc_step_form(self.nx, self.ny, self.K, self.H, self.Hm, self.dt, self.nu, self.theta,
+                                 self.dirichlet, self.form, self.reset_after, _p(self.cxy), _p(self.w),
                                  _p(_f64(v).reshape(-1, 2)), _p(_f64(p).reshape(-1)),
                                  _p(self.h), _p(self.uprev), 1 if self.nsteps == 0 else 0, int(self.fp8),
                                  *[_p(outs[k]) for k in ("Pv", "D", "X", "dpatch", "Dbar", "bL")])

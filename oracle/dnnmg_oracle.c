@@ -873,57 +873,356 @@ void orc_rhs_restrict_theta(int nx, int ny, int K, const double *cxy, const doub
     free(RT);
 }
 
+/* ----------------------------------- the paper's network form (Sec. 4.2) */
+/* The inputs and the head of the network as the paper describes them, in
+ * place of the workloads' [P v, D, hx, hy, aspect, area] and MLP:
+ *   inputs (3 nf + 24 per patch; 51 at K = 1, 99 at K = 2): the residual of
+ *   the prolongated solution at the patch's fine nodes, momentum rows (the
+ *   defect D, x, y interleaved) then continuity rows; the coarse velocity at
+ *   the four corners; a Peclet number per corner; twelve geometry values;
+ *   head: a fully connected layer H -> nout, two convolutional blocks on its
+ *   output and a final length-1 convolution. */
+
+/* Continuity rows of the residual of the prolongated velocity: the
+ * divergence part -(div Pv, xi_a), assembled like the defect over the fine
+ * elements with 2x2 Gauss points on their own bilinear maps.  The pressure
+ * stabilisation of the continuity equation is not part of this input
+ * (reading), and no row is masked (the pressure has no Dirichlet values). */
+void orc_continuity_rows(int nx, int ny, int K, const double *cxy, const double *v, double *Rp)
+{
+    int n = 1 << K, NX = nx * n, NY = ny * n;
+    size_t Fn = (size_t)(NX + 1) * (NY + 1);
+    double *fxy = (double *)malloc(sizeof(double) * 2 * Fn);
+    orc_fine_coords(nx, ny, K, cxy, fxy);
+    memset(Rp, 0, sizeof(double) * Fn);
+    double g[2];
+    gauss2(g);
+    for (int parity = 0; parity < 2; ++parity)
+#pragma omp parallel for schedule(static)
+    for (int J = parity; J < NY; J += 2)
+        for (int I = 0; I < NX; ++I) {
+            int node[4] = {fine_node(nx, n, I, J), fine_node(nx, n, I + 1, J),
+                           fine_node(nx, n, I, J + 1), fine_node(nx, n, I + 1, J + 1)};
+            for (int qt = 0; qt < 2; ++qt)
+                for (int qs = 0; qs < 2; ++qs) {
+                    double N[4], dNs[4], dNt[4];
+                    q1_shape(g[qs], g[qt], N);
+                    q1_shape_ds(g[qs], g[qt], dNs, dNt);
+                    double xs = 0, xt = 0, ys = 0, yt = 0;
+                    for (int k = 0; k < 4; ++k) {
+                        xs += fxy[2 * node[k]] * dNs[k];
+                        xt += fxy[2 * node[k]] * dNt[k];
+                        ys += fxy[2 * node[k] + 1] * dNs[k];
+                        yt += fxy[2 * node[k] + 1] * dNt[k];
+                    }
+                    double det = xs * yt - xt * ys;
+                    double div = 0.0;
+                    for (int k = 0; k < 4; ++k)
+                        div += v[2 * node[k]] * (yt * dNs[k] - ys * dNt[k]) / det +
+                               v[2 * node[k] + 1] * (-xt * dNs[k] + xs * dNt[k]) / det;
+                    double wd = 0.25 * fabs(det);
+                    for (int a = 0; a < 4; ++a) Rp[node[a]] -= wd * div * N[a];
+                }
+        }
+    free(fxy);
+}
+
+/* Twelve geometry values per patch (its coarse element with corners
+ * c00, c10, c11, c01 counter-clockwise):
+ *   edge lengths  h = (|c10 - c00|, |c11 - c10|, |c11 - c01|, |c01 - c00|)
+ *                     (bottom, right, top, left);
+ *   aspect ratios (h0 / h1, h2 / h3, h0 / h2, h1 / h3): two pairs of
+ *                     neighbouring edges, then the two pairs of opposite ones;
+ *   angles        the interior angles at c00, c10, c11, c01 (radians).
+ * (The paper names these three groups of four; the order and the pairing
+ * are a reading.) */
+static double corner_angle(const double *o, const double *a, const double *b)
+{
+    double ux = a[0] - o[0], uy = a[1] - o[1], wx = b[0] - o[0], wy = b[1] - o[1];
+    return atan2(fabs(ux * wy - uy * wx), ux * wx + uy * wy);
+}
+
+void orc_paper_geometry(int nx, int ny, const double *cxy, double *G)
+{
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const double *c00 = cxy + 2 * coarse_node(nx, i, j);
+            const double *c10 = cxy + 2 * coarse_node(nx, i + 1, j);
+            const double *c01 = cxy + 2 * coarse_node(nx, i, j + 1);
+            const double *c11 = cxy + 2 * coarse_node(nx, i + 1, j + 1);
+            double h0 = hypot(c10[0] - c00[0], c10[1] - c00[1]);
+            double h1 = hypot(c11[0] - c10[0], c11[1] - c10[1]);
+            double h2 = hypot(c11[0] - c01[0], c11[1] - c01[1]);
+            double h3 = hypot(c01[0] - c00[0], c01[1] - c00[1]);
+            double *o = G + 12 * (size_t)(j * nx + i);
+            o[0] = h0; o[1] = h1; o[2] = h2; o[3] = h3;
+            o[4] = h0 / h1; o[5] = h2 / h3; o[6] = h0 / h2; o[7] = h1 / h3;
+            o[8] = corner_angle(c00, c10, c01);
+            o[9] = corner_angle(c10, c11, c00);
+            o[10] = corner_angle(c11, c01, c10);
+            o[11] = corner_angle(c01, c00, c11);
+        }
+}
+
+/* Peclet numbers Pe = q |v| / nu at the four corners of each patch (order
+ * 00, 10, 01, 11), q the patch size, read as the square root of the coarse
+ * element's area; v the coarse velocity (Euclidean norm). */
+void orc_peclet(int nx, int ny, const double *cxy, const double *v, double nu, double *Pe)
+{
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            int c[4] = {coarse_node(nx, i, j), coarse_node(nx, i + 1, j), coarse_node(nx, i, j + 1),
+                        coarse_node(nx, i + 1, j + 1)};
+            const double *c00 = cxy + 2 * c[0], *c10 = cxy + 2 * c[1], *c01 = cxy + 2 * c[2], *c11 = cxy + 2 * c[3];
+            double d1x = c11[0] - c00[0], d1y = c11[1] - c00[1];
+            double d2x = c01[0] - c10[0], d2y = c01[1] - c10[1];
+            double q = sqrt(0.5 * fabs(d1x * d2y - d1y * d2x));
+            for (int k = 0; k < 4; ++k)
+                Pe[4 * (size_t)(j * nx + i) + k] = q * hypot(v[2 * c[k]], v[2 * c[k] + 1]) / nu;
+        }
+}
+
+/* x_e = [D at the patch nodes (x, y interleaved, x fastest), the continuity
+ * rows at the same nodes, v at the corners 00, 10, 01, 11 (x, y), Pe at the
+ * corners, the twelve geometry values]: 3 nf + 24 values. */
+void orc_gather_input_paper(int nx, int ny, int K, const double *D, const double *Rp, const double *v,
+                            const double *Pe, const double *G, double *X)
+{
+    int n = 1 << K, nf = (n + 1) * (n + 1), nin = 3 * nf + 24;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t e = (size_t)j * nx + i;
+            double *x = X + e * nin;
+            for (int b = 0; b <= n; ++b)
+                for (int a = 0; a <= n; ++a) {
+                    int l = b * (n + 1) + a;
+                    int f = fine_node(nx, n, i * n + a, j * n + b);
+                    x[2 * l] = D[2 * f];
+                    x[2 * l + 1] = D[2 * f + 1];
+                    x[2 * nf + l] = Rp[f];
+                }
+            int c[4] = {coarse_node(nx, i, j), coarse_node(nx, i + 1, j), coarse_node(nx, i, j + 1),
+                        coarse_node(nx, i + 1, j + 1)};
+            for (int k = 0; k < 4; ++k) {
+                x[3 * nf + 2 * k] = v[2 * c[k]];
+                x[3 * nf + 2 * k + 1] = v[2 * c[k] + 1];
+                x[3 * nf + 8 + k] = Pe[4 * e + k];
+            }
+            for (int k = 0; k < 12; ++k) x[3 * nf + 12 + k] = G[12 * e + k];
+        }
+}
+
+/* The GRU of Eq. (gru) (reset_after = 0: the reset gate multiplies h before
+ * U_h, as printed) or with the reset gate applied after U_h,
+ *   h' = z*h + (1-z)*tanh(W_h x + r * (U_h h))   (reset_after = 1),
+ * the form of the common library GRU cell the paper's implementation used. */
+void orc_gru_form(int P, int nin, int H, const double *Wz, const double *Wr, const double *Wh,
+                  const double *Uz, const double *Ur, const double *Uh,
+                  const double *X, const double *h, int reset_after, double *hout)
+{
+    if (!reset_after) {
+        orc_gru(P, nin, H, Wz, Wr, Wh, Uz, Ur, Uh, X, h, hout);
+        return;
+    }
+#pragma omp parallel
+    {
+    double *z = (double *)malloc(sizeof(double) * H);
+    double *r = (double *)malloc(sizeof(double) * H);
+#pragma omp for schedule(static)
+    for (int e = 0; e < P; ++e) {
+        const double *x = X + (size_t)e * nin;
+        const double *he = h + (size_t)e * H;
+        for (int k = 0; k < H; ++k) {
+            double az = 0.0, ar = 0.0;
+            for (int i = 0; i < nin; ++i) {
+                az += Wz[(size_t)k * nin + i] * x[i];
+                ar += Wr[(size_t)k * nin + i] * x[i];
+            }
+            for (int m = 0; m < H; ++m) {
+                az += Uz[(size_t)k * H + m] * he[m];
+                ar += Ur[(size_t)k * H + m] * he[m];
+            }
+            z[k] = logistic(az);
+            r[k] = logistic(ar);
+        }
+        for (int k = 0; k < H; ++k) {
+            double wx = 0.0, uh = 0.0;
+            for (int i = 0; i < nin; ++i) wx += Wh[(size_t)k * nin + i] * x[i];
+            for (int m = 0; m < H; ++m) uh += Uh[(size_t)k * H + m] * he[m];
+            hout[(size_t)e * H + k] = z[k] * he[k] + (1.0 - z[k]) * tanh(wx + r[k] * uh);
+        }
+    }
+    free(z);
+    free(r);
+    }
+}
+
+/* A convolutional block: a convolution with 4 filters of 3 x 3 taps (zero
+ * padding 1, stride 1) from one channel to 4, then the transposed
+ * convolution with the same weights from 4 channels back to one (the
+ * block's second layer is the first one transposed; 36 weights).  The
+ * image is rows x cols, row-major; W[f][dr][dc] for offsets dr, dc in -1..1. */
+static void conv_block(int rows, int cols, const double *W, const double *in, double *out)
+{
+    double *z = (double *)malloc(sizeof(double) * 4 * rows * cols);
+    for (int f = 0; f < 4; ++f)
+        for (int r = 0; r < rows; ++r)
+            for (int c = 0; c < cols; ++c) {
+                double s = 0.0;
+                for (int dr = -1; dr <= 1; ++dr)
+                    for (int dc = -1; dc <= 1; ++dc) {
+                        int rr = r + dr, cc = c + dc;
+                        if (rr >= 0 && rr < rows && cc >= 0 && cc < cols)
+                            s += W[9 * f + 3 * (dr + 1) + (dc + 1)] * in[rr * cols + cc];
+                    }
+                z[(f * rows + r) * cols + c] = s;
+            }
+    /* the adjoint: out[r][c] = sum_f sum_{dr,dc} W[f][dr][dc] z_f[r - dr][c - dc] */
+    for (int r = 0; r < rows; ++r)
+        for (int c = 0; c < cols; ++c) {
+            double s = 0.0;
+            for (int f = 0; f < 4; ++f)
+                for (int dr = -1; dr <= 1; ++dr)
+                    for (int dc = -1; dc <= 1; ++dc) {
+                        int rr = r - dr, cc = c - dc;
+                        if (rr >= 0 && rr < rows && cc >= 0 && cc < cols)
+                            s += W[9 * f + 3 * (dr + 1) + (dc + 1)] * z[(f * rows + rr) * cols + cc];
+                    }
+            out[r * cols + c] = s;
+        }
+    free(z);
+}
+
+/* The paper's head on the GRU state h' (no biases, no activations stated):
+ *   y = M h'                                       (fully connected, nout x H)
+ *   a = V(y): the vertex block, on y as a 2 x nf image (component rows,
+ *             patch nodes in the input's order as columns): its 3 x 3
+ *             taps join the two components of a node and of the nodes
+ *             beside it in that order;
+ *   b = S(y): the spatial block, on each component as an (n+1) x (n+1)
+ *             image of the patch's nodes;
+ *   d = wf * (a + b)                               (the final length-1
+ *             convolution: the two blocks' single filters summed, each
+ *             output entry weighted; nout weights).
+ * (Reading of the architecture figure and the parameter counts: the 90
+ * parameters beside the GRU and the dense layer are 36 + 36 + 18 at K = 1.) */
+void orc_conv_head(int P, int K, int H, const double *M, const double *WV, const double *WS, const double *wf,
+                   const double *h, double *d)
+{
+    int n = 1 << K, nf = (n + 1) * (n + 1), nout = 2 * nf;
+#pragma omp parallel
+    {
+    double *y = (double *)malloc(sizeof(double) * nout);
+    double *a = (double *)malloc(sizeof(double) * nout);
+    double *comp = (double *)malloc(sizeof(double) * nf);
+    double *bc = (double *)malloc(sizeof(double) * nf);
+    double *img = (double *)malloc(sizeof(double) * nout);
+#pragma omp for schedule(static)
+    for (int e = 0; e < P; ++e) {
+        const double *he = h + (size_t)e * H;
+        for (int o = 0; o < nout; ++o) {
+            double s = 0.0;
+            for (int m = 0; m < H; ++m) s += M[(size_t)o * H + m] * he[m];
+            y[o] = s;
+        }
+        /* vertex block: image row c = component, column l = node */
+        for (int c = 0; c < 2; ++c)
+            for (int l = 0; l < nf; ++l) img[c * nf + l] = y[2 * l + c];
+        conv_block(2, nf, WV, img, a);
+        double *de = d + (size_t)e * nout;
+        for (int c = 0; c < 2; ++c)
+            for (int l = 0; l < nf; ++l) de[2 * l + c] = a[c * nf + l];
+        /* spatial block, per component */
+        for (int c = 0; c < 2; ++c) {
+            for (int l = 0; l < nf; ++l) comp[l] = y[2 * l + c];
+            conv_block(n + 1, n + 1, WS, comp, bc);
+            for (int l = 0; l < nf; ++l) de[2 * l + c] += bc[l];
+        }
+        for (int o = 0; o < nout; ++o) de[o] *= wf[o];
+    }
+    free(y); free(a); free(comp); free(bc); free(img);
+    }
+}
+
+/* Weights of the paper's form: W_z, W_r, W_h (H x (3 nf + 24)), U_z, U_r,
+ * U_h (H x H), M (nout x H), the vertex block's 36, the spatial block's 36,
+ * the final layer's nout. */
+long orc_paper_weight_count(int K, int H)
+{
+    int n = 1 << K, nf = (n + 1) * (n + 1), nin = 3 * nf + 24, nout = 2 * nf;
+    return 3L * H * (nin + H) + (long)nout * H + 36 + 36 + nout;
+}
+
 /* ---------------------------------------------------------- the full step */
 /* One DNN-MG fine step (Alg. 2, lines 6-9) for given coarse v, p, with the
  * time scheme's weight theta (1: implicit Euler; 1/2: Crank-Nicolson as in
  * Eq. (4cranknicholson3); see orc_defect_theta, orc_rhs_restrict_theta).
- * weights: W_z, W_r, W_h (H x nin), U_z, U_r, U_h (H x H), then M1 (Hm x H)
- * and M2 (nout x Hm), or M (nout x H) when Hm == 0.
- * fp8 != 0 takes the network products with FP8 E4M3 operands
- * (orc_gru_fp8, orc_mlp_fp8).
+ * form 0: the workloads' network, inputs [P v, D, hx, hy, aspect, area] and
+ *   weights W_z, W_r, W_h (H x nin), U_z, U_r, U_h (H x H), then M1 (Hm x H)
+ *   and M2 (nout x Hm), or M (nout x H) when Hm == 0;
+ * form 1: the paper's network (inputs of orc_gather_input_paper, head of
+ *   orc_conv_head; weights as orc_paper_weight_count lists; Hm unused).
+ * reset_after selects the GRU form (orc_gru_form).
+ * fp8 != 0 takes the network products with FP8 E4M3 operands (form 0 with
+ * reset_after = 0 only: orc_gru_fp8, orc_mlp_fp8).
  * State in/out: h (P x H), uprev (Fn x 2).  When first != 0 the previous
  * corrected velocity is taken as P v of this step (no right-hand side from
  * an earlier step exists yet), so the mass term of the defect vanishes.
  * Optional outputs (NULL to skip): Pv (Fn x 2), D (Fn x 2), X (P x nin),
- * dpatch (P x nout), Dbar (Fn x 2), bL ((nx+1)(ny+1) x 2). */
-int orc_step_theta(int nx, int ny, int K, int H, int Hm, double dt, double nu, double theta, unsigned dir,
-                   const double *cxy, const double *weights, const double *v, const double *p,
-                   double *h, double *uprev, int first, int fp8,
-                   double *Pv_out, double *D_out, double *X_out, double *dpatch_out,
-                   double *Dbar_out, double *bL_out)
+ * dpatch (P x nout), Dbar (Fn x 2), bL ((nx+1)(ny+1) x 2).
+ * Returns 0, -1 for an unsupported combination, -2 when out of memory. */
+int orc_step_form(int nx, int ny, int K, int H, int Hm, double dt, double nu, double theta, unsigned dir,
+                  int form, int reset_after, const double *cxy, const double *weights, const double *v,
+                  const double *p, double *h, double *uprev, int first, int fp8,
+                  double *Pv_out, double *D_out, double *X_out, double *dpatch_out,
+                  double *Dbar_out, double *bL_out)
 {
-    int n = 1 << K, nf = (n + 1) * (n + 1), nout = 2 * nf, nin = 4 * nf + 4;
+    int n = 1 << K, nf = (n + 1) * (n + 1), nout = 2 * nf;
+    int nin = form ? 3 * nf + 24 : 4 * nf + 4;
     int P = nx * ny;
+    if (fp8 && (form || reset_after)) return -1;
     size_t Fn = (size_t)(nx * n + 1) * (ny * n + 1);
     size_t Nc = (size_t)(nx + 1) * (ny + 1);
     const double *Wz = weights, *Wr = Wz + (size_t)H * nin, *Wh = Wr + (size_t)H * nin;
     const double *Uz = Wh + (size_t)H * nin, *Ur = Uz + (size_t)H * H, *Uh = Ur + (size_t)H * H;
     const double *M1 = Uh + (size_t)H * H;
-    const double *M2 = Hm > 0 ? M1 + (size_t)Hm * H : NULL;
+    const double *M2 = (!form && Hm > 0) ? M1 + (size_t)Hm * H : NULL;
+    const double *WV = M1 + (size_t)nout * H, *WS = WV + 36, *wf = WS + 36;   /* form 1 */
 
     double *Pv = (double *)malloc(sizeof(double) * 2 * Fn);
     double *Pp = (double *)malloc(sizeof(double) * Fn);
     double *D = (double *)malloc(sizeof(double) * 2 * Fn);
-    double *feat = (double *)malloc(sizeof(double) * 4 * P);
+    double *feat = (double *)malloc(sizeof(double) * 12 * P);
     double *X = (double *)malloc(sizeof(double) * (size_t)P * nin);
     double *hn = (double *)malloc(sizeof(double) * (size_t)P * H);
     double *dp = (double *)malloc(sizeof(double) * (size_t)P * nout);
     double *Dbar = (double *)malloc(sizeof(double) * 2 * Fn);
     double *bL = (double *)malloc(sizeof(double) * 2 * Nc);
-    if (!Pv || !Pp || !D || !feat || !X || !hn || !dp || !Dbar || !bL) return -2;
+    double *Rp = form ? (double *)malloc(sizeof(double) * Fn) : NULL;
+    double *Pe = form ? (double *)malloc(sizeof(double) * 4 * P) : NULL;
+    if (!Pv || !Pp || !D || !feat || !X || !hn || !dp || !Dbar || !bL || (form && (!Rp || !Pe))) return -2;
 
     orc_prolong(nx, ny, K, 2, v, Pv);
     orc_prolong(nx, ny, K, 1, p, Pp);
     if (first) memcpy(uprev, Pv, sizeof(double) * 2 * Fn);
     orc_defect_theta(nx, ny, K, cxy, Pv, Pp, uprev, dt, nu, theta, dir, D);
-    orc_features(nx, ny, cxy, feat);
-    orc_gather_input(nx, ny, K, Pv, D, feat, X);
+    if (form) {
+        orc_continuity_rows(nx, ny, K, cxy, Pv, Rp);
+        orc_peclet(nx, ny, cxy, v, nu, Pe);
+        orc_paper_geometry(nx, ny, cxy, feat);
+        orc_gather_input_paper(nx, ny, K, D, Rp, v, Pe, feat, X);
+    } else {
+        orc_features(nx, ny, cxy, feat);
+        orc_gather_input(nx, ny, K, Pv, D, feat, X);
+    }
     if (fp8) {
         orc_gru_fp8(P, nin, H, Wz, Wr, Wh, Uz, Ur, Uh, X, h, hn);
         orc_mlp_fp8(P, H, Hm, nout, M1, M2, hn, dp);
     } else {
-        orc_gru(P, nin, H, Wz, Wr, Wh, Uz, Ur, Uh, X, h, hn);
-        orc_mlp(P, H, Hm, nout, M1, M2, hn, dp);
+        orc_gru_form(P, nin, H, Wz, Wr, Wh, Uz, Ur, Uh, X, h, reset_after, hn);
+        if (form) orc_conv_head(P, K, H, M1, WV, WS, wf, hn, dp);
+        else orc_mlp(P, H, Hm, nout, M1, M2, hn, dp);
     }
     orc_average(nx, ny, K, dp, dir, Dbar);
     orc_rhs_restrict_theta(nx, ny, K, cxy, v, Dbar, dt, nu, theta, bL);
@@ -939,7 +1238,19 @@ int orc_step_theta(int nx, int ny, int K, int H, int Hm, double dt, double nu, d
     if (Dbar_out) memcpy(Dbar_out, Dbar, sizeof(double) * 2 * Fn);
     if (bL_out) memcpy(bL_out, bL, sizeof(double) * 2 * Nc);
     free(Pv); free(Pp); free(D); free(feat); free(X); free(hn); free(dp); free(Dbar); free(bL);
+    free(Rp); free(Pe);
     return 0;
+}
+
+/* orc_step_form with the workloads' network (form 0, reset gate as printed). */
+int orc_step_theta(int nx, int ny, int K, int H, int Hm, double dt, double nu, double theta, unsigned dir,
+                   const double *cxy, const double *weights, const double *v, const double *p,
+                   double *h, double *uprev, int first, int fp8,
+                   double *Pv_out, double *D_out, double *X_out, double *dpatch_out,
+                   double *Dbar_out, double *bL_out)
+{
+    return orc_step_form(nx, ny, K, H, Hm, dt, nu, theta, dir, 0, 0, cxy, weights, v, p, h, uprev, first, fp8,
+                         Pv_out, D_out, X_out, dpatch_out, Dbar_out, bL_out);
 }
 
 /* orc_step_theta with implicit Euler (theta = 1). */

@@ -1,7 +1,8 @@
 /* Host driver for an AddressSanitizer + UndefinedBehaviorSanitizer build of
  * the FP64 oracle (oracle/dnnmg_oracle.c, linked in): every exported
  * function on small meshes of every K, with and without the MLP hidden
- * layer, in the FP64 and FP8 network forms, for three steps each.  Exits 0
+ * layer, in the FP64 and FP8 network forms, for three steps each, and
+ * the paper's network form (both GRU forms) with Crank-Nicolson.  Exits 0
  * if the sanitizers report nothing (they abort on the first report). */
 #include <math.h>
 #include <stdio.h>
@@ -16,6 +17,12 @@ void orc_defect_abs(int nx, int ny, int K, const double *cxy, const double *v, c
                     const double *uprev, double inv_dt, double nu, double *S);
 void orc_qgemm(int M, int N, int Kd, const double *A, const double *B, double *out);
 void orc_features(int nx, int ny, const double *cxy, double *feat);
+int orc_step_form(int nx, int ny, int K, int H, int Hm, double dt, double nu, double theta, unsigned dir,
+                  int form, int reset_after, const double *cxy, const double *weights, const double *v,
+                  const double *p, double *h, double *uprev, int first, int fp8,
+                  double *Pv_out, double *D_out, double *X_out, double *dpatch_out,
+                  double *Dbar_out, double *bL_out);
+long orc_paper_weight_count(int K, int H);
 
 static double urand(unsigned long long *s)
 {
@@ -65,10 +72,35 @@ int main(void)
             free(h);
             free(up);
         }
+        {
+            /* the paper's network form, Crank-Nicolson, both GRU forms */
+            const long npw = orc_paper_weight_count(K, H);
+            const int pin = 3 * nf + 24;
+            double *pw = malloc(sizeof(double) * npw), *pX = malloc(sizeof(double) * (size_t)P * pin);
+            for (long k = 0; k < npw; ++k) pw[k] = 0.3 * urand(&seed);
+            for (int ra = 0; ra < 2; ++ra) {
+                double *h = calloc((size_t)P * H, sizeof(double)), *up = calloc(2 * (size_t)Fn, sizeof(double));
+                for (int step = 0; step < 3; ++step) {
+                    for (int c = 0; c < Nc; ++c) {
+                        v[2 * c] = urand(&seed); v[2 * c + 1] = urand(&seed); p[c] = 0.1 * urand(&seed);
+                    }
+                    if (orc_step_form(nx, ny, K, H, 0, 0.01, 1e-3, 0.5, 13u, 1, ra, cxy, pw, v, p, h, up, step == 0, 0,
+                                      Pv, D, pX, dp, Db, bL) != 0) {
+                        fprintf(stderr, "paper-form step failed\n");
+                        return 1;
+                    }
+                }
+                free(h);
+                free(up);
+            }
+            free(pw);
+            free(pX);
+        }
         double *out = malloc(sizeof(double) * 2 * 3);
         orc_qgemm(1, 3, nin, X, w, out);   /* one row of X (P >= 1), three of W_z (H >= 8) */
         free(out);
-        printf("shape %dx%d K=%d H=%d Hm=%d: 3 steps FP64 and FP8, error scale, quantised product\n", nx, ny, K, H, Hm);
+        printf("shape %dx%d K=%d H=%d Hm=%d: 3 steps FP64 and FP8, paper form (Crank-Nicolson), error scale, "
+               "quantised product\n", nx, ny, K, H, Hm);
         free(cxy); free(w); free(v); free(p); free(Pv); free(D); free(X); free(dp); free(Db); free(bL);
         free(S); free(feat);
     }

@@ -46,6 +46,19 @@ MUTATIONS = {
     "transport_no_viscosity": ("double r = N[a] * conv + nu * (dNx[a]", "double r = N[a] * conv + 0.0 * (dNx[a]", 0),
     "transport_convection_transposed": ("double conv = wq[0] * gw[c][0] + wq[1] * gw[c][1];",
                                         "double conv = wq[0] * gw[0][c] + wq[1] * gw[1][c];", 0),
+    # the paper's network form
+    "continuity_sign": ("Rp[node[a]] -= wd * div * N[a];", "Rp[node[a]] += wd * div * N[a];", 0),
+    "continuity_dy_for_vx": ("div += v[2 * node[k]] * (yt * dNs[k] - ys * dNt[k]) / det +",
+                             "div += v[2 * node[k]] * (-xt * dNs[k] + xs * dNt[k]) / det +", 0),
+    "paper_aspect_pairing": ("o[4] = h0 / h1; o[5] = h2 / h3;", "o[4] = h0 / h3; o[5] = h2 / h1;", 0),
+    "paper_angle_corner": ("o[9] = corner_angle(c10, c11, c00);", "o[9] = corner_angle(c11, c10, c01);", 0),
+    "peclet_area_not_size": ("double q = sqrt(0.5 * fabs(d1x * d2y - d1y * d2x));",
+                             "double q = 0.5 * fabs(d1x * d2y - d1y * d2x);", 0),
+    "paper_input_rp_node": ("x[2 * nf + l] = Rp[f];", "x[2 * nf + l] = Rp[f > 0 ? f - 1 : f];", 0),
+    "gru_reset_after_before": ("tanh(wx + r[k] * uh)", "tanh(wx + uh)", 0),
+    "conv_adjoint_direction": ("int rr = r - dr, cc = c - dc;", "int rr = r + dr, cc = c + dc;", 0),
+    "vertex_block_transposed": ("conv_block(2, nf, WV, img, a);", "conv_block(nf, 2, WV, img, a);", 0),
+    "conv_head_no_output_weights": ("for (int o = 0; o < nout; ++o) de[o] *= wf[o];", "(void)wf;", 0),
     # FP8 E4M3 operand form
     "e4m3_ties_away": ("rint((ldexp(a, -e) - 1.0) * 8.0)", "round((ldexp(a, -e) - 1.0) * 8.0)", 0),
     "e4m3_truncate": ("rint((ldexp(a, -e) - 1.0) * 8.0)", "floor((ldexp(a, -e) - 1.0) * 8.0)", 0),
@@ -78,6 +91,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     env = dict(os.environ, DNNMG_ORACLE_LIB=str(mlib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_fp8_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_fp8_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_paper_net_pins.py")],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, "pins did not catch mutation %s:\n%s" % (name, r.stdout[-2000:])
