@@ -120,15 +120,19 @@ def calibrate_copy(mib):
     print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 3}))
 
 
-def make_flow_leg(wl, precision, flags=0, copies=1):
+def make_flow_leg(wl, precision, flags=0, copies=1, H=None):
     """A single-flow leg: `copies` contexts of the workload's flow and its
-    coarse fields of 16 distinct steps, resident on the device."""
+    coarse fields of 16 distinct steps, resident on the device.  With
+    DNNMG_F_PAPER_NET in flags: the paper's network (hidden size H, no MLP)."""
     import torch
     import paper_2008_11520_amd as pam
     from paper_2008_11520_amd import synth
     flow = wl.flows[0]
-    w = synth.xavier_weights(wl.K, wl.H, wl.Hm, wl.weight_seed)
-    cfg = pam.make_config(flow.nx, flow.ny, wl.K, wl.H, wl.Hm, flow.dt, wl.nu, precision, flow.dirichlet, flags)
+    paper = bool(flags & pam.DNNMG_F_PAPER_NET)
+    H = wl.H if H is None else H
+    Hm = 0 if paper else wl.Hm
+    w = synth.paper_net_weights(wl.K, H, wl.weight_seed) if paper else synth.xavier_weights(wl.K, H, Hm, wl.weight_seed)
+    cfg = pam.make_config(flow.nx, flow.ny, wl.K, H, Hm, flow.dt, wl.nu, precision, flow.dirichlet, flags)
     ctxs = [pam.DnnMG(cfg, flow.cxy, w) for _ in range(copies)]
     s = ctxs[0].s
     vs, ps = [], []
@@ -468,6 +472,13 @@ def main():
         cn = args.precision + "_crank_nicolson"
         legs[cn] = make_flow_leg(wl, args.precision, flags=pam.DNNMG_F_CRANK_NICOLSON)
         order.append(cn)
+        # the paper's network (inputs with continuity rows, Peclet numbers and
+        # twelve geometry values; dense + convolutional head), N_GRU = 96 at
+        # K = 2 as in the paper's two-level network
+        if args.precision != "fp8":
+            pn = args.precision + "_paper_net_h96"
+            legs[pn] = make_flow_leg(wl, args.precision, flags=pam.DNNMG_F_PAPER_NET, H=96)
+            order.append(pn)
         legs[args.precision] = make_flow_leg(wl, args.precision)
         order.append(args.precision)
         rot = make_flow_leg(wl, args.precision, copies=2)

@@ -100,13 +100,42 @@ enum { DNNMG_NONFINITE_CORRECTION = 1, DNNMG_NONFINITE_RHS = 2 };
  * follow the context's scheme, dnnmg_rhs_restrict_noalloc is implicit Euler. */
 enum { DNNMG_F_CRANK_NICOLSON = 4 };
 
+/* DNNMG_F_PAPER_NET: the network of the paper (Sec. 4.2, the architecture
+ * figure, Sec. 5.2) instead of the workloads' MLP form.
+ * Inputs per patch, 3 nf + 24 values (51 at K = 1, 99 at K = 2), nf = (n+1)^2:
+ *   the residual of the prolongated solution at the patch's fine nodes,
+ *   momentum rows (the defect D, x and y interleaved, x-fastest node order),
+ *   then continuity rows -(div P v, xi) (without the pressure
+ *   stabilisation); the coarse velocity at the corners 00, 10, 01, 11 (x, y);
+ *   a Peclet number q |v| / nu per corner, q the square root of the patch
+ *   area; twelve geometry values: edge lengths (bottom, right, top, left),
+ *   ratios h0/h1, h2/h3, h0/h2, h1/h3, interior angles at 00, 10, 11, 01.
+ * Head: y = M h' (nout x H), then two convolutional blocks of 4 filters with
+ *   3 x 3 taps, each a convolution and its transpose with the same weights
+ *   (zero padding 1): the vertex block on y as a 2 x nf image (component,
+ *   node), the spatial block on each component's (n+1) x (n+1) node grid;
+ *   the output is wf * (vertex + spatial), one weight per output entry.
+ * Weights (float, in this order): W_z, W_r, W_h (H x (3 nf + 24) each),
+ *   U_z, U_r, U_h (H x H), M (nout x H), the vertex block's 36 (filter,
+ *   row offset -1..1, column offset -1..1), the spatial block's 36, wf (nout):
+ *   8634 values at K = 1, H = 32.  The head is linear, so the library folds
+ *   it into one nout x H matrix at create time (in FP64).
+ * Requires Hm = 0, nu > 0 and FP32 or BF16 operands; such contexts step
+ * alone (dnnmg_step_batch rejects them) and run the separate-launch form. */
+enum { DNNMG_F_PAPER_NET = 8 };
+
+/* DNNMG_F_GRU_RESET_AFTER: the GRU candidate tanh(W_h x + r * (U_h h)) (the
+ * reset gate applied after U_h, as common library GRU cells do) instead of
+ * tanh(W_h x + U_h (r * h)) of Eq. (gru).  FP32 or BF16 operands. */
+enum { DNNMG_F_GRU_RESET_AFTER = 16 };
+
 /* Dirichlet sides (Eq. (boundary)); other sides are do-nothing outflow. */
 enum { DNNMG_DIR_XMIN = 1, DNNMG_DIR_XMAX = 2, DNNMG_DIR_YMIN = 4, DNNMG_DIR_YMAX = 8 };
 
 typedef struct {
     int nx, ny;          /* coarse elements per direction, >= 1; patches = nx*ny    */
     int K;               /* levels bridged, 1..3; n = 2^K                           */
-    int H;               /* GRU hidden size: 32, 64 or 128                          */
+    int H;               /* GRU hidden size: 32, 64, 96 (FP32, BF16) or 128          */
     int Hm;              /* MLP hidden width: 0 (single linear H -> N_out), or a
                             multiple of 32 up to 256                                 */
     double dt;           /* time step (> 0)                                          */
@@ -114,7 +143,8 @@ typedef struct {
     int precision;       /* DNNMG_FP32 / DNNMG_BF16 / DNNMG_FP8_E4M3                 */
     unsigned dirichlet;  /* DNNMG_DIR_* bits                                         */
     unsigned flags;      /* 0, or DNNMG_F_UNFUSED | DNNMG_F_NANCHECK |
-                            DNNMG_F_CRANK_NICOLSON                                   */
+                            DNNMG_F_CRANK_NICOLSON | DNNMG_F_PAPER_NET |
+                            DNNMG_F_GRU_RESET_AFTER                                  */
 } dnnmg_config;
 
 /* Network sizes: N_in = 4 (n+1)^2 + 4 (prolongated velocity and defect at the

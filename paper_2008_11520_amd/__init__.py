@@ -22,6 +22,8 @@ FP32, BF16, FP8_E4M3 = 0, 1, 2
 DNNMG_F_UNFUSED = 1
 DNNMG_F_NANCHECK = 2
 DNNMG_F_CRANK_NICOLSON = 4
+DNNMG_F_PAPER_NET = 8
+DNNMG_F_GRU_RESET_AFTER = 16
 DNNMG_NONFINITE_CORRECTION, DNNMG_NONFINITE_RHS = 1, 2
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
 
@@ -157,6 +159,8 @@ class DnnMG:
         import torch
         self.cfg = cfg
         self.s = sizes(cfg.nx, cfg.ny, cfg.K)
+        if cfg.flags & DNNMG_F_PAPER_NET:
+            self.s["nin"] = (3 * self.s["nf"] + 24 + 7) // 8 * 8     # rows padded to 8 values
         self._cxy = np.ascontiguousarray(coarse_xy, dtype=np.float64).reshape(-1)
         if self._cxy.size != 2 * self.s["Nc"]:
             raise ValueError("coarse_xy must hold %d values" % (2 * self.s["Nc"]))

@@ -50,6 +50,7 @@ namespace {
 
 struct Sizes {
     int n, nf, nin, nout, P, Fn, Nc;
+    int nin_true;  // inputs per patch: 4 nf + 4, or 3 nf + 24 in the paper's form (nin pads it to 8)
     int upitch;   // nodes per row of the u_prev state: NX+1 rounded up to 16, so
                   // that rows (and the defect/rhs tiles' 32-node runs) start on
                   // 128-byte lines and tiles do not share lines of it
@@ -61,7 +62,9 @@ Sizes sizes_of(const dnnmg_config &c)
     Sizes s;
     s.n = 1 << c.K;
     s.nf = (s.n + 1) * (s.n + 1);
-    s.nin = 4 * s.nf + 4;
+    const bool paper = (c.flags & DNNMG_F_PAPER_NET) != 0u;
+    s.nin_true = paper ? 3 * s.nf + 24 : 4 * s.nf + 4;
+    s.nin = paper ? (s.nin_true + 7) / 8 * 8 : s.nin_true;
     s.nout = 2 * s.nf;
     s.P = c.nx * c.ny;
     s.Fn = (c.nx * s.n + 1) * (c.ny * s.n + 1);
@@ -70,6 +73,10 @@ Sizes sizes_of(const dnnmg_config &c)
     s.Fu = (size_t)s.upitch * (c.ny * s.n + 1);
     return s;
 }
+
+// Configuration flags that change the network (weights are shared only
+// between contexts that agree on them).
+constexpr unsigned kNetFlags = DNNMG_F_PAPER_NET | DNNMG_F_GRU_RESET_AFTER;
 
 int kchunk(int prec) { return prec == DNNMG_FP32 ? 16 : 32; }
 int kquad(int prec) { return prec == DNNMG_FP32 ? 4 : 8; }
@@ -85,11 +92,20 @@ int check_config(const dnnmg_config *c)
     if (c->precision < DNNMG_FP32 || c->precision > DNNMG_FP8_E4M3)
         return fail(DNNMG_EINVAL, "precision %d unknown", c->precision);
     if (c->dirichlet > 15u) return fail(DNNMG_EINVAL, "dirichlet flags 0x%x out of range", c->dirichlet);
-    if ((c->flags & ~(unsigned)(DNNMG_F_UNFUSED | DNNMG_F_NANCHECK | DNNMG_F_CRANK_NICOLSON)) != 0u)
+    if ((c->flags & ~(unsigned)(DNNMG_F_UNFUSED | DNNMG_F_NANCHECK | DNNMG_F_CRANK_NICOLSON | DNNMG_F_PAPER_NET |
+                                DNNMG_F_GRU_RESET_AFTER)) != 0u)
         return fail(DNNMG_EINVAL, "unknown flags 0x%x", c->flags);
+    if ((c->flags & (DNNMG_F_PAPER_NET | DNNMG_F_GRU_RESET_AFTER)) && c->precision == DNNMG_FP8_E4M3)
+        return fail(DNNMG_EUNSUPPORTED, "DNNMG_F_PAPER_NET and DNNMG_F_GRU_RESET_AFTER run FP32 or BF16 operands");
+    if ((c->flags & DNNMG_F_PAPER_NET) && c->Hm != 0)
+        return fail(DNNMG_EINVAL, "the paper's network has no MLP hidden layer (Hm must be 0)");
+    if ((c->flags & DNNMG_F_PAPER_NET) && !(c->nu > 0.0))
+        return fail(DNNMG_EINVAL, "the paper's network input (Peclet numbers) needs nu > 0");
     if (c->H <= 0 || c->Hm < 0) return fail(DNNMG_EINVAL, "H must be > 0 and Hm >= 0");
-    if (c->H != 32 && c->H != 64 && c->H != 128)
-        return fail(DNNMG_EUNSUPPORTED, "H = %d has no kernels (32, 64, 128)", c->H);
+    if (c->H != 32 && c->H != 64 && c->H != 96 && c->H != 128)
+        return fail(DNNMG_EUNSUPPORTED, "H = %d has no kernels (32, 64, 96, 128)", c->H);
+    if (c->H == 96 && c->precision == DNNMG_FP8_E4M3)
+        return fail(DNNMG_EUNSUPPORTED, "H = 96 runs FP32 or BF16 operands");
     if (c->Hm != 0 && (c->Hm % 32 != 0 || c->Hm > 256))
         return fail(DNNMG_EUNSUPPORTED, "Hm = %d unsupported (0 or a multiple of 32 up to 256)", c->Hm);
     const double n = double(1 << c->K);
@@ -103,7 +119,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Device layout of one context's workspace.
 struct Layout {
-    size_t geo, geo64, map64, feat, h, uprev, X, sx, dpatch, part, part2, cxy, flag, bad, nonfinite, total;
+    size_t geo, geo64, map64, geo12, feat, h, uprev, X, sx, dpatch, part, part2, cxy, flag, bad, nonfinite, total;
 };
 
 Layout layout_of(const dnnmg_config &c)
@@ -115,6 +131,7 @@ Layout layout_of(const dnnmg_config &c)
     L.geo = take(sizeof(float) * 6 * s.P);
     L.geo64 = take(sizeof(double) * 4 * s.P);
     L.map64 = take((c.flags & DNNMG_F_CRANK_NICOLSON) ? sizeof(double) * 8 * s.P : 0);
+    L.geo12 = take((c.flags & DNNMG_F_PAPER_NET) ? sizeof(float) * 12 * s.P : 0);
     L.feat = take(sizeof(float) * 4 * s.P);
     L.h = take(sizeof(float) * (size_t)s.P * c.H);
     L.uprev = take(sizeof(float) * 2 * s.Fu);
@@ -212,6 +229,7 @@ struct Weights {
     void *dev = nullptr;
     size_t bytes = 0;
     int K = 0, H = 0, Hm = 0, prec = 0;
+    unsigned netflags = 0;   // the configuration flags that shape the network (kNetFlags)
     NetArgs net{};
     RhsTables tab{};       // moment tables (depend on K only), inside dev
 };
@@ -241,6 +259,7 @@ struct dnnmg_ctx {
     float *geo() const { return (float *)(ws + L.geo); }
     double *geo64() const { return (double *)(ws + L.geo64); }
     double *map64() const { return (cfg.flags & DNNMG_F_CRANK_NICOLSON) ? (double *)(ws + L.map64) : nullptr; }
+    float *geo12() const { return (cfg.flags & DNNMG_F_PAPER_NET) ? (float *)(ws + L.geo12) : nullptr; }
     float *feat() const { return (float *)(ws + L.feat); }
     float *h() const { return (float *)(ws + L.h); }
     float *uprev() const { return (float *)(ws + L.uprev); }
@@ -283,6 +302,8 @@ namespace {
 size_t weight_count(const dnnmg_config &c)
 {
     Sizes s = sizes_of(c);
+    if (c.flags & DNNMG_F_PAPER_NET)   // GRU, FC, two convolutional blocks of 36, the last layer
+        return 3 * (size_t)c.H * (s.nin_true + c.H) + (size_t)s.nout * c.H + 36 + 36 + s.nout;
     size_t n = 3 * (size_t)c.H * s.nin + 3 * (size_t)c.H * c.H;
     n += c.Hm > 0 ? (size_t)c.Hm * c.H + (size_t)s.nout * c.Hm : (size_t)s.nout * c.H;
     return n;
@@ -290,9 +311,83 @@ size_t weight_count(const dnnmg_config &c)
 
 void moment_tables(int K, std::vector<double> &A1, std::vector<double> &M);
 
+// B = sum_f C_f^T C_f for a block of 4 filters of 3 x 3 taps (W[f][dr][dc],
+// offsets -1..1) on a rows x cols image (row-major, zero padding): C_f is the
+// convolution, its transpose the block's second layer.  Dense, FP64.
+std::vector<double> conv_block_matrix(int rows, int cols, const float *W)
+{
+    const int m = rows * cols;
+    std::vector<double> C((size_t)m * m), B((size_t)m * m, 0.0);
+    for (int f = 0; f < 4; ++f) {
+        std::fill(C.begin(), C.end(), 0.0);
+        for (int r = 0; r < rows; ++r)
+            for (int c = 0; c < cols; ++c)
+                for (int dr = -1; dr <= 1; ++dr)
+                    for (int dc = -1; dc <= 1; ++dc) {
+                        const int rr = r + dr, cc = c + dc;
+                        if (rr < 0 || rr >= rows || cc < 0 || cc >= cols) continue;
+                        C[(size_t)(r * cols + c) * m + rr * cols + cc] += W[9 * f + 3 * (dr + 1) + (dc + 1)];
+                    }
+        for (int i = 0; i < m; ++i)
+            for (int k = 0; k < m; ++k) {
+                const double cki = C[(size_t)k * m + i];
+                if (cki == 0.0) continue;
+                for (int j = 0; j < m; ++j) B[(size_t)i * m + j] += cki * C[(size_t)k * m + j];
+            }
+    }
+    return B;
+}
+
+// The paper's network weights (W_g: H x nin_true, U_g, M: nout x H, the
+// vertex and spatial convolution blocks, the last layer's nout weights) in
+// the standard layout: W_g padded with zero columns to nin, and the head,
+// which is linear (a dense layer, two blocks W^T W, the weighted sum), folded
+// into one nout x H matrix  diag(wf) (B_vertex + B_spatial) M  in FP64.  The
+// vertex block acts on the 2 x nf image (component, node), the spatial block
+// on each component's (n+1) x (n+1) node grid.
+std::vector<float> fold_paper_weights(const dnnmg_config &c, const float *w)
+{
+    const Sizes s = sizes_of(c);
+    const int H = c.H, nt = s.nin_true, nin = s.nin, nout = s.nout, nf = s.nf, n1 = s.n + 1;
+    std::vector<float> out((size_t)3 * H * nin + 3 * (size_t)H * H + (size_t)nout * H, 0.0f);
+    for (int g = 0; g < 3; ++g)
+        for (int j = 0; j < H; ++j)
+            for (int k = 0; k < nt; ++k)
+                out[((size_t)g * H + j) * nin + k] = w[((size_t)g * H + j) * nt + k];
+    const float *U = w + 3 * (size_t)H * nt;
+    std::copy(U, U + 3 * (size_t)H * H, out.begin() + 3 * (size_t)H * nin);
+    const float *M = U + 3 * (size_t)H * H, *WV = M + (size_t)nout * H, *WS = WV + 36, *wf = WS + 36;
+    // block operators on the output vector y (entry 2 l + comp)
+    std::vector<double> B((size_t)nout * nout, 0.0);
+    const std::vector<double> BV = conv_block_matrix(2, nf, WV);   // image index comp * nf + l
+    for (int ci = 0; ci < 2; ++ci)
+        for (int li = 0; li < nf; ++li)
+            for (int cj = 0; cj < 2; ++cj)
+                for (int lj = 0; lj < nf; ++lj)
+                    B[(size_t)(2 * li + ci) * nout + 2 * lj + cj] += BV[(size_t)(ci * nf + li) * 2 * nf + cj * nf + lj];
+    const std::vector<double> BS = conv_block_matrix(n1, n1, WS);  // image index l
+    for (int comp = 0; comp < 2; ++comp)
+        for (int li = 0; li < nf; ++li)
+            for (int lj = 0; lj < nf; ++lj)
+                B[(size_t)(2 * li + comp) * nout + 2 * lj + comp] += BS[(size_t)li * nf + lj];
+    float *Mf = out.data() + 3 * (size_t)H * nin + 3 * (size_t)H * H;
+    for (int o = 0; o < nout; ++o)
+        for (int m = 0; m < H; ++m) {
+            double acc = 0.0;
+            for (int i = 0; i < nout; ++i) acc += B[(size_t)o * nout + i] * (double)M[(size_t)i * H + m];
+            Mf[(size_t)o * H + m] = (float)((double)wf[o] * acc);
+        }
+    return out;
+}
+
 // Pack host FP32 weights into the four fragment arrays the network kernel reads.
 int build_weights(const dnnmg_config &c, const float *w, hipStream_t st, Weights **out)
 {
+    std::vector<float> folded;
+    if (c.flags & DNNMG_F_PAPER_NET) {
+        folded = fold_paper_weights(c, w);
+        w = folded.data();
+    }
     Sizes s = sizes_of(c);
     const int H = c.H, Hm = c.Hm, prec = c.precision, KC = kchunk(prec);
     const int nin = s.nin, nout = s.nout, HT = H / 16;
@@ -385,9 +480,12 @@ int build_weights(const dnnmg_config &c, const float *w, hipStream_t st, Weights
         return fail(DNNMG_EDEVICE, "weight upload: %s", hipGetErrorString(e));
     }
     W->K = c.K; W->H = H; W->Hm = Hm; W->prec = prec;
+    W->netflags = c.flags & kNetFlags;
     unsigned char *d = (unsigned char *)W->dev;
     W->net = NetArgs{c.K, H, Hm, nin, nout, prec, kc1, d + off[0], d + off[1], d + off[2], d + off[3],
                      nullptr, nullptr, nullptr, nullptr};
+    W->net.xform = (c.flags & DNNMG_F_PAPER_NET) ? 1 : 0;
+    W->net.reset_after = (c.flags & DNNMG_F_GRU_RESET_AFTER) ? 1 : 0;
     if (fp8) {
         W->net.s1 = (const float *)(d + offS[0]);
         W->net.s2 = (const float *)(d + offS[1]);
@@ -457,6 +555,10 @@ FlowArgs flow_args(const dnnmg_ctx *c, const float *v, const float *p)
     f.dpatch = c->dpatch();
     f.part = c->part();
     f.nonfinite = (c->cfg.flags & DNNMG_F_NANCHECK) ? (int *)(c->ws + c->L.nonfinite) : nullptr;
+    if (c->cfg.flags & DNNMG_F_PAPER_NET) {
+        f.xform = 1;
+        f.geo12 = c->geo12();
+    }
     if (c->cfg.flags & DNNMG_F_CRANK_NICOLSON) {
         f.theta = 0.5f;
         f.nu64 = c->cfg.nu;
@@ -479,8 +581,9 @@ int create_common(const dnnmg_config *cfg, const double *cxy, const float *weigh
         if (!weights) return fail(DNNMG_EINVAL, "weights_host is NULL");
         if (nw != weight_count(*cfg))
             return fail(DNNMG_EINVAL, "n_weights = %zu, expected %zu", nw, weight_count(*cfg));
-    } else if (shared->K != cfg->K || shared->H != cfg->H || shared->Hm != cfg->Hm || shared->prec != cfg->precision) {
-        return fail(DNNMG_EINVAL, "shared weights have another K/H/Hm/precision");
+    } else if (shared->K != cfg->K || shared->H != cfg->H || shared->Hm != cfg->Hm || shared->prec != cfg->precision ||
+               shared->netflags != (cfg->flags & kNetFlags)) {
+        return fail(DNNMG_EINVAL, "shared weights have another K/H/Hm/precision/network form");
     }
     hipStream_t st = (hipStream_t)stream;
     dnnmg_ctx *c = new dnnmg_ctx();
@@ -515,7 +618,7 @@ int create_common(const dnnmg_config *cfg, const double *cxy, const float *weigh
     if (e == hipSuccess) e = hipMemsetAsync(c->first_flag(), 1, sizeof(int), st);
     if (e == hipSuccess)
         e = launch_geometry((const double *)(c->ws + c->L.cxy), cfg->nx, cfg->ny, c->geo(), c->geo64(), c->map64(),
-                            c->feat(), (int *)(c->ws + c->L.bad), st);
+                            c->feat(), c->geo12(), (int *)(c->ws + c->L.bad), st);
     int bad = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&bad, c->ws + c->L.bad, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -730,8 +833,9 @@ extern "C" int dnnmg_create_in_arena(dnnmg_arena *a, const dnnmg_config *cfg, co
     if (rc) return rc;
     if (!cxy) return fail(DNNMG_EINVAL, "coarse_xy_host is NULL");
     const Weights *w = model->w;
-    if (w->K != cfg->K || w->H != cfg->H || w->Hm != cfg->Hm || w->prec != cfg->precision)
-        return fail(DNNMG_EINVAL, "shared weights have another K/H/Hm/precision");
+    if (w->K != cfg->K || w->H != cfg->H || w->Hm != cfg->Hm || w->prec != cfg->precision ||
+        w->netflags != (cfg->flags & kNetFlags))
+        return fail(DNNMG_EINVAL, "shared weights have another K/H/Hm/precision/network form");
     const size_t ncxy = 2 * (size_t)(cfg->nx + 1) * (cfg->ny + 1);
     for (size_t i = 0; i < ncxy; ++i)
         if (!std::isfinite(cxy[i])) return fail(DNNMG_EINVAL, "coarse_xy_host[%zu] is not finite", i);
@@ -769,7 +873,7 @@ extern "C" int dnnmg_create_in_arena(dnnmg_arena *a, const dnnmg_config *cfg, co
     if (e == hipSuccess) e = hipMemsetAsync(c->first_flag(), 1, sizeof(int), st);
     if (e == hipSuccess)
         e = launch_geometry((const double *)(c->ws + L.cxy), cfg->nx, cfg->ny, c->geo(), c->geo64(), c->map64(),
-                            c->feat(), (int *)(c->ws + L.bad), st);
+                            c->feat(), c->geo12(), (int *)(c->ws + L.bad), st);
     if (e != hipSuccess) {
         // the enqueued work may still touch the block: wait for it before returning the block
         (void)hipStreamSynchronize(st);
@@ -1014,7 +1118,7 @@ extern "C" int dnnmg_rhs_restrict_noalloc(int nx, int ny, int K, double dt, cons
     f.bL = b;
     // every scratch word the kernels read is written earlier in this call
     // (geometry, tables, partial sums), so nothing needs clearing
-    HIP_OR_FAIL(launch_geometry(cxy, nx, ny, (float *)f.geo, (double *)f.geo64, nullptr, (float *)f.feat,
+    HIP_OR_FAIL(launch_geometry(cxy, nx, ny, (float *)f.geo, (double *)f.geo64, nullptr, (float *)f.feat, nullptr,
                                 (int *)(sc + kStaticBad), st));
     HIP_OR_FAIL(launch_moment_tables(K, tabA, tabM, st));
     HIP_OR_FAIL(launch_rhs(f, nullptr, blocks_for(kKindRhs, nx, ny, K), K, RhsTables{tabA, tabM}, 0, st));
@@ -1149,8 +1253,9 @@ extern "C" int dnnmg_batch_prepare(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int n
         if (!v[i]) return fail(DNNMG_EINVAL, "v[%d] is NULL", i);
         if (b_out && !b_out[i]) return fail(DNNMG_EINVAL, "b_out[%d] is NULL", i);
         if (ctxs[i]->w != w) return fail(DNNMG_EINVAL, "ctxs[%d] does not share the weights of ctxs[0]", i);
-        if (ctxs[i]->cfg.flags & DNNMG_F_CRANK_NICOLSON)
-            return fail(DNNMG_EINVAL, "ctxs[%d] uses DNNMG_F_CRANK_NICOLSON: such flows step alone (dnnmg_step)", i);
+        if (ctxs[i]->cfg.flags & (DNNMG_F_CRANK_NICOLSON | DNNMG_F_PAPER_NET))
+            return fail(DNNMG_EINVAL, "ctxs[%d] uses DNNMG_F_CRANK_NICOLSON or DNNMG_F_PAPER_NET: such flows step "
+                                      "alone (dnnmg_step)", i);
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(DNNMG_EINVAL, "ctxs[%d] repeats ctxs[%d]", i, j);
     }

@@ -27,13 +27,20 @@ namespace dnnmg {
 // ---------------------------------------------------------------- geometry
 // Per coarse element: FP32 map vectors for the defect, FP64 coefficients of
 // det J = d0 + d1 xi + d2 eta for the right-hand side, optionally the FP64
-// map vectors themselves (the Crank-Nicolson rhs), and the four patch
-// features hx, hy, hx/hy, area.  *bad is set if an element is not positively
-// oriented (det J <= 0 at a corner).
+// map vectors themselves (the Crank-Nicolson rhs), the four patch features
+// hx, hy, hx/hy, area, and optionally the paper's twelve geometry inputs
+// (edge lengths bottom, right, top, left; ratios h0/h1, h2/h3, h0/h2, h1/h3;
+// interior angles at the corners 00, 10, 11, 01).  *bad is set if an element
+// is not positively oriented (det J <= 0 at a corner).
+__device__ inline double corner_angle64(double ux, double uy, double wx, double wy)
+{
+    return atan2(fabs(ux * wy - uy * wx), ux * wx + uy * wy);
+}
+
 __global__ __launch_bounds__(kThreads) void k_geometry(const double *__restrict__ cxy, int nx, int ny,
                                                        float *__restrict__ geo, double *__restrict__ geo64,
                                                        double *__restrict__ map64, float *__restrict__ feat,
-                                                       int *__restrict__ bad)
+                                                       float *__restrict__ geo12, int *__restrict__ bad)
 {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nx * ny) return;
@@ -65,14 +72,26 @@ __global__ __launch_bounds__(kThreads) void k_geometry(const double *__restrict_
     double bx = c01[0] - c10[0], by = c01[1] - c10[1];
     float *f = feat + 4 * (size_t)e;
     f[0] = (float)hx; f[1] = (float)hy; f[2] = (float)(hx / hy); f[3] = (float)(0.5 * fabs(ax * by - ay * bx));
+    if (geo12) {
+        const double rx = c11[0] - c10[0], ry = c11[1] - c10[1];   // right edge, 10 -> 11
+        const double tx = c11[0] - c01[0], ty = c11[1] - c01[1];   // top edge, 01 -> 11
+        const double h0 = hypot(exx, exy_), h1 = hypot(rx, ry), h2 = hypot(tx, ty), h3 = hypot(eyx, eyy);
+        float *o = geo12 + 12 * (size_t)e;
+        o[0] = (float)h0; o[1] = (float)h1; o[2] = (float)h2; o[3] = (float)h3;
+        o[4] = (float)(h0 / h1); o[5] = (float)(h2 / h3); o[6] = (float)(h0 / h2); o[7] = (float)(h1 / h3);
+        o[8] = (float)corner_angle64(exx, exy_, eyx, eyy);          // at 00: to 10 and to 01
+        o[9] = (float)corner_angle64(rx, ry, -exx, -exy_);          // at 10: to 11 and to 00
+        o[10] = (float)corner_angle64(-tx, -ty, -rx, -ry);          // at 11: to 01 and to 10
+        o[11] = (float)corner_angle64(-eyx, -eyy, tx, ty);          // at 01: to 00 and to 11
+    }
 }
 
 hipError_t launch_geometry(const double *cxy, int nx, int ny, float *geo, double *geo64, double *map64,
-                           float *feat, int *bad, hipStream_t s)
+                           float *feat, float *geo12, int *bad, hipStream_t s)
 {
     int P = nx * ny;
     hipLaunchKernelGGL(k_geometry, dim3((P + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
-                       cxy, nx, ny, geo, geo64, map64, feat, bad);
+                       cxy, nx, ny, geo, geo64, map64, feat, geo12, bad);
     return hipGetLastError();
 }
 
@@ -316,10 +335,15 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
 // previous velocity is P v, the two transport levels coincide and the mass
 // term vanishes, so the implicit-Euler elements with 1/dt = 0 give the same
 // defect.
-template <int K, typename XT, bool OPAQUE_TID, bool FUSED = false, int HM = 0, bool CN = false>
+// PAPER: the network input of the paper's form (Sec. 4.2): the residual at
+// the patch nodes, momentum rows (D) then continuity rows, the corner
+// velocities, Peclet numbers and twelve geometry values, padded with zeros to
+// a multiple of 8 values.
+template <int K, typename XT, bool OPAQUE_TID, bool FUSED = false, int HM = 0, bool CN = false, bool PAPER = false>
 __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const NetArgs *net = nullptr)
 {
     static_assert(!(CN && FUSED), "the theta scheme runs unfused");
+    static_assert(!(PAPER && (FUSED || std::is_same<XT, uint8_t>::value)), "paper inputs: unfused, FP32 or BF16");
     const int tid = OPAQUE_TID ? tile_thread() : (int)threadIdx.x;
     constexpr int n = 1 << K;
     constexpr float inv_n = 1.0f / n;
@@ -327,7 +351,7 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
     constexpr int NN = kTileFine + 3;           // nodes of those elements
     constexpr int CE = TP + 2;                  // coarse elements incl. halo
 
-    constexpr int nf = (n + 1) * (n + 1), nin = 4 * nf + 4;
+    constexpr int nf = (n + 1) * (n + 1), nin = PAPER ? (3 * nf + 24 + 7) / 8 * 8 : 4 * nf + 4;
     // XT = uint8_t: FP8 network input, formed in FP32 and quantised per patch
     constexpr bool FP8 = std::is_same<XT, uint8_t>::value;
     typedef typename std::conditional<FP8, float, XT>::type ST;
@@ -617,6 +641,70 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
                 *reinterpret_cast<b2 *>(o) = v;
             }
         };
+        if constexpr (PAPER) {
+            // continuity row of fine node (I, J): -(div P v, xi) over its (up to
+            // four) fine elements.  On a coarse element det J div(P v) is affine
+            // in the reference coordinates, c0 + c1 xi + c2 eta (the xi eta
+            // terms cancel), so each element's integral against the node's hat
+            // is exact in closed form: (h^2 / 4) (c0 + c1 xb + c2 eb), h = 1/n,
+            // (xb, eb) the element's corner shifted by h/3 (far side 2h/3)
+            // towards the node.
+            auto cont_row = [&](int I, int J) -> float {
+                float acc = 0.0f;
+#pragma unroll
+                for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+                    for (int di = 0; di < 2; ++di) {
+                        const int eI = I - 1 + di, eJ = J - 1 + dj;
+                        if (eI < 0 || eI >= NX || eJ < 0 || eJ >= NY) continue;
+                        const CoarseRec &r = s_c[((eJ >> K) - cj0) * CE + ((eI >> K) - ci0)];
+                        const float c0 = r.eyy * r.V1x - r.exy * r.V2x - r.eyx * r.V1y + r.exx * r.V2y;
+                        const float c1 = r.exyy * r.V1x - r.exy * r.V3x - r.exyx * r.V1y + r.exx * r.V3y;
+                        const float c2 = r.eyy * r.V3x - r.exyy * r.V2x - r.eyx * r.V3y + r.exyx * r.V2y;
+                        const float xb = ((eI & (n - 1)) + (2 - di) * (1.0f / 3.0f)) * inv_n;
+                        const float eb = ((eJ & (n - 1)) + (2 - dj) * (1.0f / 3.0f)) * inv_n;
+                        acc += c0 + c1 * xb + c2 * eb;
+                    }
+                return -0.25f * inv_n * inv_n * acc;
+            };
+            const float inv_nu = 1.0f / f.nu;
+            const float2 *vg = reinterpret_cast<const float2 *>(f.v);
+            for (int t = tid; t < PP * (n + 2); t += kThreads) {
+                const bool extra = t >= PP * (n + 1);
+                const int pl = extra ? t - PP * (n + 1) : t / (n + 1), b = extra ? n + 1 : t - pl * (n + 1);
+                const int pa = pl % TP, pb = pl / TP, pi = tx * TP + pa, pj = ty * TP + pb;
+                if (pi >= nx || pj >= ny) continue;
+                ST *o = s_x + pl * LDX;
+                if (extra) {
+                    // corner velocities and Peclet numbers (corners 00, 10, 01, 11),
+                    // the twelve geometry values, zeros to the padded width
+                    const size_t e = (size_t)pj * nx + pi;
+                    const int c = pj * (nx + 1) + pi;
+                    const float2 cv[4] = {vg[c], vg[c + 1], vg[c + nx + 1], vg[c + nx + 2]};
+                    const float q = sqrtf(f.feat[4 * e + 3]) * inv_nu;
+                    ST *x = o + 3 * nf;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        x[2 * k] = (ST)cv[k].x;
+                        x[2 * k + 1] = (ST)cv[k].y;
+                        x[8 + k] = (ST)(q * sqrtf(cv[k].x * cv[k].x + cv[k].y * cv[k].y));
+                    }
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) x[12 + k] = (ST)f.geo12[12 * e + k];
+                    for (int k = 3 * nf + 24; k < nin; ++k) o[k] = (ST)0.0f;
+                    continue;
+                }
+                const float2 *d = &s_acc[(pb * n + b + 1) * NN + pa * n + 1];
+                const int J = pj * n + b;
+#pragma unroll
+                for (int a = 0; a <= n; ++a) {
+                    const int l = b * (n + 1) + a;
+                    const float2 dd = d[a];
+                    store2(o + 2 * l, dd.x, dd.y);
+                    o[2 * nf + l] = (ST)cont_row(pi * n + a, J);
+                }
+            }
+        } else
         // (items of one patch on consecutive lanes: their LDS rows interleave
         // across the banks, where one row per lane would stride LDX apart)
         for (int t = tid; t < PP * (n + 2); t += kThreads) {
@@ -691,11 +779,18 @@ __global__ __launch_bounds__(kThreads, (defect_waves<K, XT>())) void k_defect(Fl
     }
 }
 
-// The theta scheme (Crank-Nicolson), single flow.
-template <int K, typename XT>
-__global__ __launch_bounds__(kThreads, (defect_waves<K, XT>())) void k_defect_cn(FlowArgs single)
+// The theta scheme (Crank-Nicolson) and/or the paper's network input, single flow.
+// (at K = 1 the paper's wider input rows leave LDS for one workgroup fewer)
+template <int K, typename XT, bool PAPER>
+constexpr int defect_form_waves()
 {
-    defect_tile<K, XT, false, false, 0, true>(single, xcd_tile(blockIdx.x, gridDim.x));
+    return PAPER && K == 1 ? defect_waves<K, XT>() - 1 : defect_waves<K, XT>();
+}
+
+template <int K, typename XT, bool CN, bool PAPER>
+__global__ __launch_bounds__(kThreads, (defect_form_waves<K, XT, PAPER>())) void k_defect_form(FlowArgs single)
+{
+    defect_tile<K, XT, false, false, 0, CN, PAPER>(single, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 template <bool BATCHED, int HM>
@@ -715,7 +810,11 @@ __global__ __launch_bounds__(kThreads, 4) void k_defect_net(FlowArgs single, con
     }
 }
 
-bool fused_step(const NetArgs &net) { return net.prec == 1 && net.K == 2 && net.H == 64 && (net.Hm == 0 || net.Hm == 64); }
+bool fused_step(const NetArgs &net)
+{
+    return net.prec == 1 && net.K == 2 && net.H == 64 && (net.Hm == 0 || net.Hm == 64) && net.xform == 0 &&
+           !net.reset_after;
+}
 
 hipError_t launch_defect_net(const FlowArgs &f, const BatchTable *bt, int nblocks, const NetArgs &net, hipStream_t s)
 {
@@ -734,15 +833,21 @@ hipError_t launch_defect_net(const FlowArgs &f, const BatchTable *bt, int nblock
 hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, int K, int xfmt, hipStream_t s)
 {
     dim3 g(nblocks), b(kThreads);
-    const bool cn = f.theta != 1.0f;
-    if (cn && bt) return hipErrorInvalidValue;
+    const bool cn = f.theta != 1.0f, paper = f.xform != 0;
+    if ((cn || paper) && bt) return hipErrorInvalidValue;
+    if (paper && (xfmt == 2 || !f.geo12)) return hipErrorInvalidValue;
 #define DNNMG_DEFECT_LAUNCH(KK, XT)                                                           \
     if (bt) hipLaunchKernelGGL((k_defect<KK, XT, true>), g, b, 0, s, f, bt);                   \
-    else if (cn) hipLaunchKernelGGL((k_defect_cn<KK, XT>), g, b, 0, s, f);                     \
+    else if (cn) hipLaunchKernelGGL((k_defect_form<KK, XT, true, false>), g, b, 0, s, f);      \
     else hipLaunchKernelGGL((k_defect<KK, XT, false>), g, b, 0, s, f, bt);
+#define DNNMG_DEFECT_PAPER(KK, XT)                                                            \
+    if (cn) hipLaunchKernelGGL((k_defect_form<KK, XT, true, true>), g, b, 0, s, f);            \
+    else hipLaunchKernelGGL((k_defect_form<KK, XT, false, true>), g, b, 0, s, f);
 #define DNNMG_DEFECT_CASE(KK)                                                                 \
     case KK:                                                                                  \
-        if (xfmt == 1) { DNNMG_DEFECT_LAUNCH(KK, __bf16) }                                    \
+        if (paper && xfmt == 1) { DNNMG_DEFECT_PAPER(KK, __bf16) }                            \
+        else if (paper) { DNNMG_DEFECT_PAPER(KK, float) }                                     \
+        else if (xfmt == 1) { DNNMG_DEFECT_LAUNCH(KK, __bf16) }                               \
         else if (xfmt == 2) { DNNMG_DEFECT_LAUNCH(KK, uint8_t) }                              \
         else { DNNMG_DEFECT_LAUNCH(KK, float) }                                               \
         break;
@@ -753,6 +858,7 @@ hipError_t launch_defect(const FlowArgs &f, const BatchTable *bt, int nblocks, i
     default: return hipErrorInvalidValue;
     }
 #undef DNNMG_DEFECT_CASE
+#undef DNNMG_DEFECT_PAPER
 #undef DNNMG_DEFECT_LAUNCH
     return hipGetLastError();
 }

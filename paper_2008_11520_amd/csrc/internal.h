@@ -41,6 +41,8 @@ struct FlowArgs {
     int *nonfinite;        // non-finite check (or nullptr): bit 0 correction, bit 1 restricted rhs
     // time scheme: theta = 1 implicit Euler, 1/2 Crank-Nicolson (then map64
     // holds the coarse maps in FP64 and nu64 the viscosity for the rhs)
+    int xform = 0;                   // network input form (NetArgs::xform)
+    const float *geo12 = nullptr;    // xform 1: per patch the twelve geometry inputs
     float theta = 1.0f;
     double nu64 = 0.0;
     const double *map64 = nullptr;   // per coarse element: ex, ey, exy (x, y each), 2 pad
@@ -55,6 +57,8 @@ struct NetArgs {
     const void *B3;        // M1 (or M when Hm == 0)
     const void *B4;        // M2
     const float *s1, *s2, *s3, *s4;  // FP8: per-output-row weight scales
+    int xform = 0;         // network input: 0 [P v, D, 4 features]; 1 the paper's (3 nf + 24, padded to nin)
+    int reset_after = 0;   // GRU candidate tanh(W_h x + r * (U_h h)) instead of U_h (r * h)
 };
 
 // Moment tables for the FP64 right-hand side (exact integrals on the
@@ -132,9 +136,10 @@ constexpr float kLog2e = 1.44269504088896340736f;
 int blocks_for(int kind, int nx, int ny, int K);
 
 // Launchers (return hipError_t of the launch).
-// map64 (or nullptr): the FP64 map vectors the Crank-Nicolson rhs needs.
+// map64 (or nullptr): the FP64 map vectors the Crank-Nicolson rhs needs;
+// geo12 (or nullptr): the paper-form network's twelve geometry inputs.
 hipError_t launch_geometry(const double *cxy, int nx, int ny, float *geo, double *geo64, double *map64,
-                           float *feat, int *bad, hipStream_t s);
+                           float *feat, float *geo12, int *bad, hipStream_t s);
 hipError_t launch_prolong(const FlowArgs &f, int K, float *pv, float *pp, hipStream_t s);
 // f.theta != 1 (Crank-Nicolson) takes the theta-weighted element residuals;
 // single flow only (bt must be null then).

@@ -118,6 +118,7 @@ __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net
 
     const int P = f.nx * f.ny;
     const int nin = net.nin, nout = net.nout, Hm = net.Hm, kc1 = net.kc1;
+    const bool reset_after = net.reset_after != 0;
     // (tile_thread(): in the batched tile loop the index math is redone per
     // tile instead of hoisted out of the loop and held in registers)
     const int tid = tile_thread();
@@ -187,11 +188,13 @@ __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net
                 // (BF16 weights come pre-multiplied for 2^x, see sigmoid_l2)
                 az[tw][q][e] = PREC == 1 ? sigmoid_l2(az[tw][q][e]) : sigmoid(az[tw][q][e]);
                 const float r = PREC == 1 ? sigmoid_l2(ar[tw][q][e]) : sigmoid(ar[tw][q][e]);
-                sR[lr * LDH + k] = O::cvt(r * h0);
+                // reset after U_h: phase 2 takes h itself, r stays for the candidate
+                ar[tw][q][e] = r;
+                sR[lr * LDH + k] = O::cvt(reset_after ? h0 : r * h0);
             }
     __syncthreads();
 
-    // ---- phase 2: (r*h) x U_h^T; update h
+    // ---- phase 2: (r*h) x U_h^T (or h x U_h^T, then times r); update h
     f4 au[HW][2];
 #pragma unroll
     for (int tw = 0; tw < HW; ++tw)
@@ -217,7 +220,8 @@ __device__ __forceinline__ void net_tile(const FlowArgs &f, int blk, NetArgs net
             for (int e = 0; e < 4; ++e) {
                 const int lr = r0 + 16 * q + 4 * lq + e, row = blk * kNetRows + lr, k = 16 * (hg * HW + tw) + li;
                 const float z = az[tw][q][e];
-                const float hh = PREC == 1 ? tanh_l2(ah[tw][q][e] + au[tw][q][e]) : fast_tanh(ah[tw][q][e] + au[tw][q][e]);
+                const float u = reset_after ? ar[tw][q][e] * au[tw][q][e] : au[tw][q][e];
+                const float hh = PREC == 1 ? tanh_l2(ah[tw][q][e] + u) : fast_tanh(ah[tw][q][e] + u);
                 const float hn = hh + z * (hold[tw][q][e] - hh);   // z h + (1 - z) hh
                 if (row < P) hG[(size_t)row * H + k] = hn;
                 sHp[lr * LDH + k] = O::cvt(hn);
@@ -1447,15 +1451,23 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
 
 static int g_num_cus = 0;
 
+// The persistent kernels take rows of the standard width 4 nf + 4 and the
+// GRU as printed; other forms run the generic kernels.
+static bool standard_rows(const NetArgs &net)
+{
+    const int n = 1 << net.K;
+    return net.nin == 4 * (n + 1) * (n + 1) + 4 && !net.reset_after;
+}
 static bool use_h64(int prec, int K, int H, int Hm) { return prec == 1 && H == 64 && K <= 2 && (Hm == 0 || Hm == 64); }
-static bool use_h64(const NetArgs &net) { return use_h64(net.prec, net.K, net.H, net.Hm); }
+static bool use_h64(const NetArgs &net) { return standard_rows(net) && use_h64(net.prec, net.K, net.H, net.Hm); }
 static bool use_q8p(const NetArgs &net)
 {
-    return net.prec == 2 && (net.H == 64 || net.H == 128) && (net.Hm == 0 || net.Hm == net.H);
+    return standard_rows(net) && net.prec == 2 && (net.H == 64 || net.H == 128) && (net.Hm == 0 || net.Hm == net.H);
 }
 static bool use_b16w(const NetArgs &net)
 {
-    return net.prec == 1 && !use_h64(net) && (net.H == 64 || net.H == 128) && (net.Hm == 0 || net.Hm == net.H);
+    return standard_rows(net) && net.prec == 1 && !use_h64(net) && (net.H == 64 || net.H == 128) &&
+           (net.Hm == 0 || net.Hm == net.H);
 }
 static bool persistent(const NetArgs &net) { return use_h64(net) || use_q8p(net) || use_b16w(net); }
 
@@ -1552,10 +1564,12 @@ hipError_t launch_net(const FlowArgs &f, const BatchTable *bt, int ntiles, const
     if (net.prec == 0) {
         if (net.H == 32) return launch_net_t<0, 32>(f, bt, nblocks, net, s);
         if (net.H == 64) return launch_net_t<0, 64>(f, bt, nblocks, net, s);
+        if (net.H == 96) return launch_net_t<0, 96>(f, bt, nblocks, net, s);
         if (net.H == 128) return launch_net_t<0, 128>(f, bt, nblocks, net, s);
     } else if (net.prec == 1) {
         if (net.H == 32) return launch_net_t<1, 32>(f, bt, nblocks, net, s);
         if (net.H == 64) return launch_net_t<1, 64>(f, bt, nblocks, net, s);
+        if (net.H == 96) return launch_net_t<1, 96>(f, bt, nblocks, net, s);
         if (net.H == 128) return launch_net_t<1, 128>(f, bt, nblocks, net, s);
     }
     return hipErrorInvalidValue;

@@ -347,6 +347,24 @@ def xavier_weights(K: int, H: int, Hm: int, seed: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
+def paper_net_weights(K: int, H: int, seed: int) -> np.ndarray:
+    """Seeded weights of the paper's network form (DNNMG_F_PAPER_NET): the
+    GRU over 3 nf + 24 inputs and the dense layer Xavier-uniform, the two
+    convolutional blocks' 36 weights each uniform in +-1/3, the last
+    layer's nout weights uniform in [0.5, 1.5]."""
+    n = 1 << K
+    nf = (n + 1) * (n + 1)
+    nin, nout = 3 * nf + 24, 2 * nf
+    rng = SplitMix64(seed)
+    parts = []
+    for (o, i) in [(H, nin)] * 3 + [(H, H)] * 3 + [(nout, H)]:
+        a = math.sqrt(6.0 / (i + o))
+        parts.append(rng.uniform(o * i, -a, a))
+    parts.append(rng.uniform(72, -1.0 / 3.0, 1.0 / 3.0))
+    parts.append(rng.uniform(nout, 0.5, 1.5))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def split_weights(w: np.ndarray, K: int, H: int, Hm: int):
     """Views of the packed weight vector as the individual matrices."""
     _, _, shapes = net_shapes(K, H, Hm)

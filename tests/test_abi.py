@@ -129,7 +129,7 @@ def test_fp8_config_sizes_and_quantiser_validation():
 
 def test_unknown_flags_rejected_on_host():
     L = pam.lib()
-    c = cfg(flags=8)
+    c = cfg(flags=32)
     s = pam.sizes(4, 3, 2)
     cxy = np.zeros(2 * s["Nc"])
     w = np.zeros(pam.weight_count(c), dtype=np.float32)
@@ -166,12 +166,30 @@ def test_crank_nicolson_flag_is_known_and_holds_fp64_maps():
     assert pam.workspace_bytes(cfg(flags=pam.DNNMG_F_CRANK_NICOLSON | pam.DNNMG_F_NANCHECK)) == cn
 
 
+def test_paper_net_weight_counts_and_validation():
+    """DNNMG_F_PAPER_NET: the weight vector of the paper's form (8634 values
+    at K = 1, H = 32: Sec. 5.2); Hm must be 0, nu > 0, FP32/BF16 only; H = 96
+    (the paper's K = 2 network) runs FP32 and BF16; the GRU flag is known."""
+    P = pam.DNNMG_F_PAPER_NET
+    assert pam.weight_count(cfg(K=1, H=32, Hm=0, flags=P)) == 8634
+    assert pam.weight_count(cfg(K=2, H=96, Hm=0, flags=P)) == 60960 + 36 + 36 + 50
+    assert pam.workspace_bytes(cfg(K=1, H=32, Hm=0, flags=P)) > 0
+    assert pam.workspace_bytes(cfg(K=2, H=96, Hm=0, flags=P, precision=1)) > 0
+    assert pam.workspace_bytes(cfg(K=2, H=64, Hm=64, flags=P)) == 0
+    assert pam.workspace_bytes(cfg(K=2, H=64, Hm=0, flags=P, precision=2)) == 0
+    assert pam.workspace_bytes(cfg(K=2, H=64, Hm=0, flags=P, nu=0.0)) == 0
+    assert pam.workspace_bytes(cfg(H=96, Hm=0)) > 0
+    assert pam.workspace_bytes(cfg(H=96, Hm=0, precision=2)) == 0
+    assert pam.workspace_bytes(cfg(flags=pam.DNNMG_F_GRU_RESET_AFTER)) > 0
+    assert pam.workspace_bytes(cfg(flags=pam.DNNMG_F_GRU_RESET_AFTER, precision=2)) == 0
+
+
 def test_nancheck_flag_validation():
     """DNNMG_F_NANCHECK is a known flag (the configuration is valid); unknown
     flag bits are not; dnnmg_nonfinite rejects NULL arguments on the host."""
     assert pam.workspace_bytes(cfg(flags=pam.DNNMG_F_NANCHECK)) > pam.workspace_bytes(cfg()) - 1
     assert pam.workspace_bytes(cfg(flags=pam.DNNMG_F_NANCHECK | pam.DNNMG_F_UNFUSED)) > 0
-    assert pam.workspace_bytes(cfg(flags=8)) == 0
+    assert pam.workspace_bytes(cfg(flags=32)) == 0
     L = pam.lib()
     out = ctypes.c_int(7)
     assert L.dnnmg_nonfinite(None, 1, ctypes.byref(out), None) == pam.DNNMG_EINVAL
