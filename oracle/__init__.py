@@ -63,6 +63,20 @@ def lib():
         L.orc_conv_head.argtypes = [i, i, i, _D, _D, _D, _D, _D, _D]
         L.orc_paper_weight_count.argtypes = [i, i]
         L.orc_paper_weight_count.restype = ctypes.c_long
+        _I = ctypes.POINTER(ctypes.c_int)
+        L.orc_umesh_count.argtypes = [i, i, _I, i, _I, _I]
+        L.orc_umesh_refine.argtypes = [i, i, _D, _I, i, i, _I, _D, _D, _I]
+        L.orc_u_prolong.argtypes = [i, i, _I, _I, i, i, _D, _D]
+        L.orc_u_restrict.argtypes = [i, i, i, _I, _I, i, i, _D, _D]
+        L.orc_u_mask.argtypes = [i, i, _I, _I, i, i, _I, _U8]
+        L.orc_u_defect.argtypes = [i, i, _I, _D, i, _D, _D, _D, d, d, _U8, _D]
+        L.orc_u_mass_apply.argtypes = [i, i, _I, _D, i, _D, _D]
+        L.orc_u_features.argtypes = [i, _D, _I, _D]
+        L.orc_u_average.argtypes = [i, i, _I, i, _D, _U8, _D]
+        L.orc_u_rhs_restrict.argtypes = [i, i, i, _I, _I, _D, i, _D, _D, d, _D]
+        L.orc_u_step.argtypes = [i, i, _D, _I, i, i, i, d, d, _I, _D, i, _U8, _D, _D, _D, _D, _D, i,
+                                 _D, _D, _D, _D, _D, _D]
+        L.orc_u_step.restype = i
         L.orc_e4m3_decode.argtypes = [u]
         L.orc_e4m3_decode.restype = d
         L.orc_e4m3_encode.argtypes = [ctypes.c_float]
@@ -367,6 +381,121 @@ class OracleFlow:
                                  _p(_f64(v).reshape(-1, 2)), _p(_f64(p).reshape(-1)),
                                  _p(self.h), _p(self.uprev), 1 if self.nsteps == 0 else 0, int(self.fp8),
                                  *[_p(outs[k]) for k in ("Pv", "D", "X", "dpatch", "Dbar", "bL")])
+        if rc != 0:
+            raise MemoryError("oracle step failed: %d" % rc)
+        self.nsteps += 1
+        return {k: outs[k] for k in want}
+
+
+# ----------------------------------------------------- unstructured meshes
+def _pi(a):
+    if a is None:
+        return None
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _i32(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a.reshape(shape) if shape is not None else a
+
+
+class UFine:
+    """The refined fine mesh of an unstructured coarse mesh (orc_umesh_refine):
+    fine node coordinates fxy (Fn x 2), patch maps pmap (ne x nf), the
+    Dirichlet mask, and the wrappers of the mesh's operators."""
+
+    def __init__(self, mesh, K):
+        self.mesh, self.K = mesh, K
+        self.xy = _f64(mesh.xy).reshape(-1, 2)
+        self.elems = _i32(mesh.elems, (-1, 4))
+        self.nc, self.ne = self.xy.shape[0], self.elems.shape[0]
+        n = 1 << K
+        self.nf = (n + 1) ** 2
+        E, Fn = ctypes.c_int(), ctypes.c_int()
+        lib().orc_umesh_count(self.nc, self.ne, _pi(self.elems), K, ctypes.byref(E), ctypes.byref(Fn))
+        self.E, self.Fn = E.value, Fn.value
+        self.curved = _i32(mesh.curved, (-1, 3)) if len(mesh.curved) else np.zeros((0, 3), np.int32)
+        self.circles = _f64(mesh.circles).reshape(-1, 3) if len(mesh.circles) else np.zeros((0, 3))
+        self.fxy = np.empty((self.Fn, 2))
+        self.pmap = np.empty((self.ne, self.nf), dtype=np.int32)
+        lib().orc_umesh_refine(self.nc, self.ne, _p(self.xy), _pi(self.elems), K, self.curved.shape[0],
+                               _pi(self.curved), _p(self.circles) if self.circles.size else None,
+                               _p(self.fxy), _pi(self.pmap))
+        dirs = _i32(mesh.dirichlet_edges, (-1, 2)) if len(mesh.dirichlet_edges) else np.zeros((0, 2), np.int32)
+        m = np.empty(self.Fn, dtype=np.uint8)
+        lib().orc_u_mask(self.ne, K, _pi(self.elems), _pi(self.pmap), self.Fn, dirs.shape[0], _pi(dirs),
+                         m.ctypes.data_as(_U8))
+        self.mask_u8 = m
+        self.mask = m.astype(bool)
+
+    def prolong(self, coarse):
+        c = _f64(coarse)
+        ncomp = 1 if c.ndim == 1 else c.shape[-1]
+        out = np.empty((self.Fn, ncomp) if ncomp > 1 else (self.Fn,))
+        lib().orc_u_prolong(self.ne, self.K, _pi(self.elems), _pi(self.pmap), self.Fn, ncomp, _p(c), _p(out))
+        return out
+
+    def restrict(self, fine):
+        f = _f64(fine)
+        ncomp = 1 if f.ndim == 1 else f.shape[-1]
+        out = np.empty((self.nc, ncomp) if ncomp > 1 else (self.nc,))
+        lib().orc_u_restrict(self.nc, self.ne, self.K, _pi(self.elems), _pi(self.pmap), self.Fn, ncomp, _p(f),
+                             _p(out))
+        return out
+
+    def defect(self, pv, pp, uprev, dt, nu):
+        D = np.empty((self.Fn, 2))
+        lib().orc_u_defect(self.ne, self.K, _pi(self.pmap), _p(self.fxy), self.Fn, _p(_f64(pv)), _p(_f64(pp)),
+                           _p(_f64(uprev)), dt, nu, self.mask_u8.ctypes.data_as(_U8), _p(D))
+        return D
+
+    def mass_apply(self, u):
+        out = np.empty((self.Fn, 2))
+        lib().orc_u_mass_apply(self.ne, self.K, _pi(self.pmap), _p(self.fxy), self.Fn, _p(_f64(u)), _p(out))
+        return out
+
+    def features(self):
+        out = np.empty((self.ne, 4))
+        lib().orc_u_features(self.ne, _p(self.xy), _pi(self.elems), _p(out))
+        return out
+
+    def average(self, dpatch):
+        out = np.empty((self.Fn, 2))
+        lib().orc_u_average(self.ne, self.K, _pi(self.pmap), self.Fn, _p(_f64(dpatch)),
+                            self.mask_u8.ctypes.data_as(_U8), _p(out))
+        return out
+
+    def rhs_restrict(self, v, Dbar, dt):
+        out = np.empty((self.nc, 2))
+        lib().orc_u_rhs_restrict(self.nc, self.ne, self.K, _pi(self.elems), _pi(self.pmap), _p(self.fxy), self.Fn,
+                                 _p(_f64(v)), _p(_f64(Dbar)), dt, _p(out))
+        return out
+
+
+class OracleUFlow:
+    """Stateful fine step on an unstructured mesh (orc_u_step): h (ne x H) and
+    u_prev (Fn x 2) in float64."""
+
+    def __init__(self, mesh, K, H, Hm, dt, nu, weights):
+        self.f = UFine(mesh, K)
+        self.K, self.H, self.Hm, self.dt, self.nu = K, H, Hm, dt, nu
+        self.w = _f64(weights).reshape(-1)
+        self.h = np.zeros((self.f.ne, H))
+        self.uprev = np.zeros((self.f.Fn, 2))
+        self.nsteps = 0
+
+    def step(self, v, p, want=("Dbar", "bL")):
+        f = self.f
+        nf = f.nf
+        shapes = dict(Pv=(f.Fn, 2), D=(f.Fn, 2), X=(f.ne, 4 * nf + 4), dpatch=(f.ne, 2 * nf), Dbar=(f.Fn, 2),
+                      bL=(f.nc, 2))
+        outs = {k: (np.empty(shapes[k]) if k in want else None) for k in shapes}
+        rc = lib().orc_u_step(f.nc, f.ne, _p(f.xy), _pi(f.elems), self.K, self.H, self.Hm, self.dt, self.nu,
+                              _pi(f.pmap), _p(f.fxy), f.Fn, f.mask_u8.ctypes.data_as(_U8), _p(self.w),
+                              _p(_f64(v).reshape(-1, 2)), _p(_f64(p).reshape(-1)), _p(self.h), _p(self.uprev),
+                              1 if self.nsteps == 0 else 0,
+                              *[_p(outs[k]) for k in ("Pv", "D", "X", "dpatch", "Dbar", "bL")])
         if rc != 0:
             raise MemoryError("oracle step failed: %d" % rc)
         self.nsteps += 1

@@ -1154,6 +1154,447 @@ long orc_paper_weight_count(int K, int H)
     return 3L * H * (nin + H) + (long)nout * H + 36 + 36 + nout;
 }
 
+/* ------------------------------------------ unstructured quadrilateral meshes */
+/* A coarse mesh of quadrilaterals given by node coordinates and, per element,
+ * its four nodes v0, v1, v2, v3 counter-clockwise (reference corners (0,0),
+ * (1,0), (1,1), (0,1)); edges may lie on circles (isoparametric refinement).
+ * Each element is refined into n x n fine elements, n = 2^K (one patch per
+ * coarse element).  Fine nodes are numbered
+ *   0 .. Nc-1                  the coarse nodes;
+ *   Nc + k (n-1) + (t-1)       the n-1 inner nodes of coarse edge k, t = 1..n-1
+ *                              counted from the edge's lower-numbered node;
+ *                              edges numbered in order of first appearance over
+ *                              the elements, local edges in the order
+ *                              (v0,v1), (v1,v2), (v3,v2), (v0,v3);
+ *   Nc + E (n-1) + e (n-1)^2 + (b-1)(n-1) + (a-1)
+ *                              the inner nodes (a, b) of element e.
+ * pmap[e nf + b (n+1) + a] is the fine node at reference point (a/n, b/n) of
+ * element e (patch-local order as in the structured form). */
+
+/* Edges: an open-addressing table of node pairs (lo, hi) -> edge index. */
+typedef struct { int *key; int cap; } edge_table;
+
+static int edge_find_or_add(edge_table *t, int a, int b, int *next)
+{
+    int lo = a < b ? a : b, hi = a < b ? b : a;
+    unsigned long long h = ((unsigned long long)(unsigned)lo * 2654435761ULL) ^ ((unsigned long long)(unsigned)hi * 40503ULL);
+    int i = (int)(h % (unsigned long long)t->cap);
+    for (;;) {
+        if (t->key[3 * i] < 0) {
+            t->key[3 * i] = lo; t->key[3 * i + 1] = hi; t->key[3 * i + 2] = (*next)++;
+            return t->key[3 * i + 2];
+        }
+        if (t->key[3 * i] == lo && t->key[3 * i + 1] == hi) return t->key[3 * i + 2];
+        i = (i + 1) % t->cap;
+    }
+}
+
+/* Edge index of each element's four local edges (ne x 4); returns E. */
+static int umesh_edges(int ne, const int *elems, int *eidx)
+{
+    edge_table t;
+    t.cap = 8 * ne + 16;
+    t.key = (int *)malloc(sizeof(int) * 3 * t.cap);
+    for (int i = 0; i < 3 * t.cap; ++i) t.key[i] = -1;
+    int next = 0;
+    for (int e = 0; e < ne; ++e) {
+        const int *v = elems + 4 * e;
+        const int ends[4][2] = {{v[0], v[1]}, {v[1], v[2]}, {v[3], v[2]}, {v[0], v[3]}};
+        for (int k = 0; k < 4; ++k) eidx[4 * e + k] = edge_find_or_add(&t, ends[k][0], ends[k][1], &next);
+    }
+    free(t.key);
+    return next;
+}
+
+/* Number of edges and of fine nodes. */
+int orc_umesh_count(int nc, int ne, const int *elems, int K, int *n_edges, int *n_fine)
+{
+    int n = 1 << K;
+    int *eidx = (int *)malloc(sizeof(int) * 4 * ne);
+    int E = umesh_edges(ne, elems, eidx);
+    free(eidx);
+    *n_edges = E;
+    *n_fine = nc + E * (n - 1) + ne * (n - 1) * (n - 1);
+    return 0;
+}
+
+/* The curve of an element edge from node a to node b at parameter s in
+ * [0, 1]: the straight segment, or the circular arc between them (angle
+ * linear in s) when the edge is listed as curved. */
+static int curve_of(int a, int b, int ncurved, const int *curved)
+{
+    for (int k = 0; k < ncurved; ++k)
+        if ((curved[3 * k] == a && curved[3 * k + 1] == b) || (curved[3 * k] == b && curved[3 * k + 1] == a))
+            return curved[3 * k + 2];
+    return -1;
+}
+
+static void edge_point(const double *xy, int a, int b, double s, int circ, const double *circles, double *out)
+{
+    const double *A = xy + 2 * a, *B = xy + 2 * b;
+    if (circ < 0) {
+        out[0] = (1.0 - s) * A[0] + s * B[0];
+        out[1] = (1.0 - s) * A[1] + s * B[1];
+        return;
+    }
+    const double cx = circles[3 * circ], cy = circles[3 * circ + 1], r = circles[3 * circ + 2];
+    double ta = atan2(A[1] - cy, A[0] - cx), tb = atan2(B[1] - cy, B[0] - cx);
+    double d = tb - ta;
+    const double pi = 3.14159265358979323846;
+    while (d > pi) d -= 2.0 * pi;
+    while (d < -pi) d += 2.0 * pi;
+    out[0] = cx + r * cos(ta + s * d);
+    out[1] = cy + r * sin(ta + s * d);
+}
+
+/* Fine node coordinates (Fn x 2) and the patch maps (ne x nf).  Edge nodes
+ * sit on the edge's curve at parameter t/n from its lower-numbered node;
+ * inner nodes at F_e(a/n, b/n), F_e the transfinite (Gordon-Hall) map of the
+ * element's four edge curves (the bilinear map when all four are straight). */
+int orc_umesh_refine(int nc, int ne, const double *xy, const int *elems, int K, int ncurved, const int *curved,
+                     const double *circles, double *fxy, int *pmap)
+{
+    int n = 1 << K, nf = (n + 1) * (n + 1);
+    int *eidx = (int *)malloc(sizeof(int) * 4 * ne);
+    int E = umesh_edges(ne, elems, eidx);
+    int base_in = nc + E * (n - 1);
+    for (int i = 0; i < nc; ++i) { fxy[2 * i] = xy[2 * i]; fxy[2 * i + 1] = xy[2 * i + 1]; }
+    for (int e = 0; e < ne; ++e) {
+        const int *v = elems + 4 * e;
+        const int ends[4][2] = {{v[0], v[1]}, {v[1], v[2]}, {v[3], v[2]}, {v[0], v[3]}};
+        int circ[4];
+        for (int k = 0; k < 4; ++k) circ[k] = curve_of(ends[k][0], ends[k][1], ncurved, curved);
+        for (int b = 0; b <= n; ++b)
+            for (int a = 0; a <= n; ++a) {
+                int l = b * (n + 1) + a, f;
+                double xi = (double)a / n, eta = (double)b / n;
+                int edge = -1, along = 0;            /* local edge and the index along it from its first end */
+                if (b == 0 && a > 0 && a < n) { edge = 0; along = a; }
+                else if (a == n && b > 0 && b < n) { edge = 1; along = b; }
+                else if (b == n && a > 0 && a < n) { edge = 2; along = a; }
+                else if (a == 0 && b > 0 && b < n) { edge = 3; along = b; }
+                if (a == 0 && b == 0) f = v[0];
+                else if (a == n && b == 0) f = v[1];
+                else if (a == n && b == n) f = v[2];
+                else if (a == 0 && b == n) f = v[3];
+                else if (edge >= 0) {
+                    int p = ends[edge][0], q = ends[edge][1];
+                    int t = p < q ? along : n - along;          /* from the lower-numbered node */
+                    f = nc + eidx[4 * e + edge] * (n - 1) + (t - 1);
+                    int lo = p < q ? p : q, hi = p < q ? q : p;
+                    edge_point(xy, lo, hi, (double)t / n, circ[edge], circles, fxy + 2 * f);
+                } else {
+                    f = base_in + e * (n - 1) * (n - 1) + (b - 1) * (n - 1) + (a - 1);
+                    /* transfinite map: edge curves blended, minus the bilinear corner part */
+                    double Bp[2], Tp[2], Lp[2], Rp[2];
+                    edge_point(xy, v[0], v[1], xi, circ[0], circles, Bp);
+                    edge_point(xy, v[3], v[2], xi, circ[2], circles, Tp);
+                    edge_point(xy, v[0], v[3], eta, circ[3], circles, Lp);
+                    edge_point(xy, v[1], v[2], eta, circ[1], circles, Rp);
+                    for (int c = 0; c < 2; ++c) {
+                        double bil = (1 - xi) * (1 - eta) * xy[2 * v[0] + c] + xi * (1 - eta) * xy[2 * v[1] + c] +
+                                     xi * eta * xy[2 * v[2] + c] + (1 - xi) * eta * xy[2 * v[3] + c];
+                        fxy[2 * f + c] = (1 - eta) * Bp[c] + eta * Tp[c] + (1 - xi) * Lp[c] + xi * Rp[c] - bil;
+                    }
+                }
+                pmap[(size_t)e * nf + l] = f;
+            }
+    }
+    free(eidx);
+    return 0;
+}
+
+/* P: fine node f takes the bilinear interpolation (in reference
+ * coordinates) of the corner values of the first element containing it. */
+static void umesh_first(int ne, int K, const int *pmap, int Fn, int *first)
+{
+    int nf = ((1 << K) + 1) * ((1 << K) + 1);
+    for (int f = 0; f < Fn; ++f) first[f] = -1;
+    for (int e = 0; e < ne; ++e)
+        for (int l = 0; l < nf; ++l)
+            if (first[pmap[(size_t)e * nf + l]] < 0) first[pmap[(size_t)e * nf + l]] = e * nf + l;
+}
+
+static void umesh_hats(int K, int l, double N[4])   /* corner order v0, v1, v2, v3 */
+{
+    int n = 1 << K, a = l % (n + 1), b = l / (n + 1);
+    double s = (double)a / n, t = (double)b / n;
+    N[0] = (1 - s) * (1 - t); N[1] = s * (1 - t); N[2] = s * t; N[3] = (1 - s) * t;
+}
+
+void orc_u_prolong(int ne, int K, const int *elems, const int *pmap, int Fn, int ncomp, const double *coarse,
+                   double *fine)
+{
+    int nf = ((1 << K) + 1) * ((1 << K) + 1);
+    int *first = (int *)malloc(sizeof(int) * Fn);
+    umesh_first(ne, K, pmap, Fn, first);
+    for (int f = 0; f < Fn; ++f) {
+        int e = first[f] / nf, l = first[f] % nf;
+        double N[4];
+        umesh_hats(K, l, N);
+        for (int c = 0; c < ncomp; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 4; ++k) s += N[k] * coarse[ncomp * elems[4 * e + k] + c];
+            fine[ncomp * f + c] = s;
+        }
+    }
+    free(first);
+}
+
+/* R = P^T. */
+void orc_u_restrict(int nc, int ne, int K, const int *elems, const int *pmap, int Fn, int ncomp, const double *fine,
+                    double *coarse)
+{
+    int nf = ((1 << K) + 1) * ((1 << K) + 1);
+    int *first = (int *)malloc(sizeof(int) * Fn);
+    umesh_first(ne, K, pmap, Fn, first);
+    memset(coarse, 0, sizeof(double) * ncomp * nc);
+    for (int f = 0; f < Fn; ++f) {
+        int e = first[f] / nf, l = first[f] % nf;
+        double N[4];
+        umesh_hats(K, l, N);
+        for (int k = 0; k < 4; ++k)
+            for (int c = 0; c < ncomp; ++c) coarse[ncomp * elems[4 * e + k] + c] += N[k] * fine[ncomp * f + c];
+    }
+    free(first);
+}
+
+/* Dirichlet mask: fine nodes on the listed coarse edges (node pairs), ends
+ * included. */
+void orc_u_mask(int ne, int K, const int *elems, const int *pmap, int Fn, int ndir, const int *dir_edges,
+                unsigned char *mask)
+{
+    int n = 1 << K, nf = (n + 1) * (n + 1);
+    memset(mask, 0, Fn);
+    for (int e = 0; e < ne; ++e) {
+        const int *v = elems + 4 * e;
+        const int ends[4][2] = {{v[0], v[1]}, {v[1], v[2]}, {v[3], v[2]}, {v[0], v[3]}};
+        for (int k = 0; k < 4; ++k) {
+            int on = 0;
+            for (int d = 0; d < ndir; ++d)
+                if ((dir_edges[2 * d] == ends[k][0] && dir_edges[2 * d + 1] == ends[k][1]) ||
+                    (dir_edges[2 * d] == ends[k][1] && dir_edges[2 * d + 1] == ends[k][0])) on = 1;
+            if (!on) continue;
+            for (int t = 0; t <= n; ++t) {
+                int a = k == 0 || k == 2 ? t : (k == 1 ? n : 0);
+                int b = k == 1 || k == 3 ? t : (k == 2 ? n : 0);
+                mask[pmap[(size_t)e * nf + b * (n + 1) + a]] = 1;
+            }
+        }
+    }
+}
+
+/* The fine elements of the refined mesh: element (e, a, b) has the fine
+ * nodes of patch-local (a,b), (a+1,b), (a,b+1), (a+1,b+1) (corner order 00,
+ * 10, 01, 11 of q1_shape). */
+static void ufine_nodes(int K, const int *pmap, int e, int a, int b, int node[4])
+{
+    int n = 1 << K, nf = (n + 1) * (n + 1);
+    const int *pm = pmap + (size_t)e * nf;
+    node[0] = pm[b * (n + 1) + a]; node[1] = pm[b * (n + 1) + a + 1];
+    node[2] = pm[(b + 1) * (n + 1) + a]; node[3] = pm[(b + 1) * (n + 1) + a + 1];
+}
+
+/* The defect of orc_defect on the refined unstructured mesh (same element
+ * terms and quadrature on every fine element), masked. */
+void orc_u_defect(int ne, int K, const int *pmap, const double *fxy, int Fn, const double *v, const double *p,
+                  const double *uprev, double dt, double nu, const unsigned char *mask, double *D)
+{
+    int n = 1 << K;
+    memset(D, 0, sizeof(double) * 2 * Fn);
+    double g[2];
+    gauss2(g);
+    for (int e = 0; e < ne; ++e)
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) {
+                int node[4];
+                ufine_nodes(K, pmap, e, a, b, node);
+                for (int qt = 0; qt < 2; ++qt)
+                    for (int qs = 0; qs < 2; ++qs) {
+                        double N[4], dNs[4], dNt[4];
+                        q1_shape(g[qs], g[qt], N);
+                        q1_shape_ds(g[qs], g[qt], dNs, dNt);
+                        double xs = 0, xt = 0, ys = 0, yt = 0;
+                        for (int k = 0; k < 4; ++k) {
+                            xs += fxy[2 * node[k]] * dNs[k];
+                            xt += fxy[2 * node[k]] * dNt[k];
+                            ys += fxy[2 * node[k] + 1] * dNs[k];
+                            yt += fxy[2 * node[k] + 1] * dNt[k];
+                        }
+                        double det = xs * yt - xt * ys;
+                        double dNx[4], dNy[4];
+                        for (int k = 0; k < 4; ++k) {
+                            dNx[k] = (yt * dNs[k] - ys * dNt[k]) / det;
+                            dNy[k] = (-xt * dNs[k] + xs * dNt[k]) / det;
+                        }
+                        double vq[2] = {0, 0}, uq[2] = {0, 0}, pq = 0, gv[2][2] = {{0, 0}, {0, 0}};
+                        for (int k = 0; k < 4; ++k) {
+                            for (int c = 0; c < 2; ++c) {
+                                vq[c] += N[k] * v[2 * node[k] + c];
+                                uq[c] += N[k] * uprev[2 * node[k] + c];
+                                gv[c][0] += v[2 * node[k] + c] * dNx[k];
+                                gv[c][1] += v[2 * node[k] + c] * dNy[k];
+                            }
+                            pq += N[k] * p[node[k]];
+                        }
+                        double wd = 0.25 * fabs(det);
+                        for (int k = 0; k < 4; ++k)
+                            for (int c = 0; c < 2; ++c) {
+                                double conv = vq[0] * gv[c][0] + vq[1] * gv[c][1];
+                                double dphi = c == 0 ? dNx[k] : dNy[k];
+                                D[2 * node[k] + c] += wd * ((1.0 / dt) * N[k] * (uq[c] - vq[c]) - N[k] * conv -
+                                                            nu * (dNx[k] * gv[c][0] + dNy[k] * gv[c][1]) + pq * dphi);
+                            }
+                    }
+            }
+    for (int f = 0; f < Fn; ++f)
+        if (mask[f]) { D[2 * f] = 0.0; D[2 * f + 1] = 0.0; }
+}
+
+/* M_f u on the refined unstructured mesh. */
+void orc_u_mass_apply(int ne, int K, const int *pmap, const double *fxy, int Fn, const double *u, double *Mu)
+{
+    int n = 1 << K;
+    memset(Mu, 0, sizeof(double) * 2 * Fn);
+    double g[2];
+    gauss2(g);
+    for (int e = 0; e < ne; ++e)
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) {
+                int node[4];
+                ufine_nodes(K, pmap, e, a, b, node);
+                for (int qt = 0; qt < 2; ++qt)
+                    for (int qs = 0; qs < 2; ++qs) {
+                        double N[4], dNs[4], dNt[4];
+                        q1_shape(g[qs], g[qt], N);
+                        q1_shape_ds(g[qs], g[qt], dNs, dNt);
+                        double xs = 0, xt = 0, ys = 0, yt = 0;
+                        for (int k = 0; k < 4; ++k) {
+                            xs += fxy[2 * node[k]] * dNs[k];
+                            xt += fxy[2 * node[k]] * dNt[k];
+                            ys += fxy[2 * node[k] + 1] * dNs[k];
+                            yt += fxy[2 * node[k] + 1] * dNt[k];
+                        }
+                        double wd = 0.25 * fabs(xs * yt - xt * ys), uq[2] = {0, 0};
+                        for (int k = 0; k < 4; ++k)
+                            for (int c = 0; c < 2; ++c) uq[c] += N[k] * u[2 * node[k] + c];
+                        for (int k = 0; k < 4; ++k)
+                            for (int c = 0; c < 2; ++c) Mu[2 * node[k] + c] += wd * N[k] * uq[c];
+                    }
+            }
+}
+
+/* Patch features of orc_features from each element's four corners (v0..v3
+ * counter-clockwise): hx the mean of the edges (v0,v1), (v3,v2), hy of
+ * (v0,v3), (v1,v2), their ratio, and the area of the straight quadrilateral. */
+void orc_u_features(int ne, const double *xy, const int *elems, double *feat)
+{
+    for (int e = 0; e < ne; ++e) {
+        const double *c0 = xy + 2 * elems[4 * e], *c1 = xy + 2 * elems[4 * e + 1];
+        const double *c2 = xy + 2 * elems[4 * e + 2], *c3 = xy + 2 * elems[4 * e + 3];
+        double hx = 0.5 * (hypot(c1[0] - c0[0], c1[1] - c0[1]) + hypot(c2[0] - c3[0], c2[1] - c3[1]));
+        double hy = 0.5 * (hypot(c3[0] - c0[0], c3[1] - c0[1]) + hypot(c2[0] - c1[0], c2[1] - c1[1]));
+        double d1x = c2[0] - c0[0], d1y = c2[1] - c0[1], d2x = c3[0] - c1[0], d2y = c3[1] - c1[1];
+        double *f = feat + 4 * (size_t)e;
+        f[0] = hx; f[1] = hy; f[2] = hx / hy; f[3] = 0.5 * fabs(d1x * d2y - d1y * d2x);
+    }
+}
+
+/* Network input rows as orc_gather_input, through the patch maps. */
+void orc_u_gather_input(int ne, int K, const int *pmap, const double *pv, const double *D, const double *feat,
+                        double *X)
+{
+    int n = 1 << K, nf = (n + 1) * (n + 1), nin = 4 * nf + 4;
+    for (int e = 0; e < ne; ++e) {
+        double *x = X + (size_t)e * nin;
+        for (int l = 0; l < nf; ++l) {
+            int f = pmap[(size_t)e * nf + l];
+            x[2 * l] = pv[2 * f]; x[2 * l + 1] = pv[2 * f + 1];
+            x[2 * nf + 2 * l] = D[2 * f]; x[2 * nf + 2 * l + 1] = D[2 * f + 1];
+        }
+        for (int k = 0; k < 4; ++k) x[4 * nf + k] = feat[4 * (size_t)e + k];
+    }
+}
+
+/* Duplicate averaging: the mean of the outputs of every patch that holds
+ * the fine node (summed in patch order), zero at masked nodes. */
+void orc_u_average(int ne, int K, const int *pmap, int Fn, const double *dpatch, const unsigned char *mask,
+                   double *Dbar)
+{
+    int nf = ((1 << K) + 1) * ((1 << K) + 1);
+    int *cnt = (int *)calloc(Fn, sizeof(int));
+    memset(Dbar, 0, sizeof(double) * 2 * Fn);
+    for (int e = 0; e < ne; ++e)
+        for (int l = 0; l < nf; ++l) {
+            int f = pmap[(size_t)e * nf + l];
+            Dbar[2 * f] += dpatch[((size_t)e * nf + l) * 2];
+            Dbar[2 * f + 1] += dpatch[((size_t)e * nf + l) * 2 + 1];
+            cnt[f]++;
+        }
+    for (int f = 0; f < Fn; ++f) {
+        if (mask[f] || cnt[f] == 0) { Dbar[2 * f] = 0.0; Dbar[2 * f + 1] = 0.0; continue; }
+        Dbar[2 * f] /= cnt[f];
+        Dbar[2 * f + 1] /= cnt[f];
+    }
+    free(cnt);
+}
+
+/* b_L = R (1/dt) M_f (P v + Dbar) on the unstructured mesh. */
+void orc_u_rhs_restrict(int nc, int ne, int K, const int *elems, const int *pmap, const double *fxy, int Fn,
+                        const double *v, const double *Dbar, double dt, double *bL)
+{
+    double *u = (double *)malloc(sizeof(double) * 2 * Fn), *Mu = (double *)malloc(sizeof(double) * 2 * Fn);
+    orc_u_prolong(ne, K, elems, pmap, Fn, 2, v, u);
+    for (int f = 0; f < 2 * Fn; ++f) u[f] += Dbar[f];
+    orc_u_mass_apply(ne, K, pmap, fxy, Fn, u, Mu);
+    for (int f = 0; f < 2 * Fn; ++f) Mu[f] /= dt;
+    orc_u_restrict(nc, ne, K, elems, pmap, Fn, 2, Mu, bL);
+    free(u);
+    free(Mu);
+}
+
+/* One fine step (Alg. 2, lines 6-9; implicit Euler, the workloads' network)
+ * on the refined unstructured mesh: orc_step with the mesh's own prolongation,
+ * defect, patch inputs, averaging and rhs.  State h (ne x H), uprev (Fn x 2);
+ * optional outputs as orc_step (D, X, dpatch, Dbar over the fine nodes,
+ * bL over the coarse nodes). */
+int orc_u_step(int nc, int ne, const double *xy, const int *elems, int K, int H, int Hm, double dt, double nu,
+               const int *pmap, const double *fxy, int Fn, const unsigned char *mask, const double *weights,
+               const double *v, const double *p, double *h, double *uprev, int first,
+               double *Pv_out, double *D_out, double *X_out, double *dpatch_out, double *Dbar_out, double *bL_out)
+{
+    int n = 1 << K, nf = (n + 1) * (n + 1), nout = 2 * nf, nin = 4 * nf + 4, P = ne;
+    const double *Wz = weights, *Wr = Wz + (size_t)H * nin, *Wh = Wr + (size_t)H * nin;
+    const double *Uz = Wh + (size_t)H * nin, *Ur = Uz + (size_t)H * H, *Uh = Ur + (size_t)H * H;
+    const double *M1 = Uh + (size_t)H * H, *M2 = Hm > 0 ? M1 + (size_t)Hm * H : NULL;
+    double *Pv = (double *)malloc(sizeof(double) * 2 * Fn), *Pp = (double *)malloc(sizeof(double) * Fn);
+    double *D = (double *)malloc(sizeof(double) * 2 * Fn), *feat = (double *)malloc(sizeof(double) * 4 * P);
+    double *X = (double *)malloc(sizeof(double) * (size_t)P * nin), *hn = (double *)malloc(sizeof(double) * (size_t)P * H);
+    double *dp = (double *)malloc(sizeof(double) * (size_t)P * nout), *Dbar = (double *)malloc(sizeof(double) * 2 * Fn);
+    double *bL = (double *)malloc(sizeof(double) * 2 * nc);
+    if (!Pv || !Pp || !D || !feat || !X || !hn || !dp || !Dbar || !bL) return -2;
+    orc_u_prolong(ne, K, elems, pmap, Fn, 2, v, Pv);
+    orc_u_prolong(ne, K, elems, pmap, Fn, 1, p, Pp);
+    if (first) memcpy(uprev, Pv, sizeof(double) * 2 * Fn);
+    orc_u_defect(ne, K, pmap, fxy, Fn, Pv, Pp, uprev, dt, nu, mask, D);
+    orc_u_features(ne, xy, elems, feat);
+    orc_u_gather_input(ne, K, pmap, Pv, D, feat, X);
+    orc_gru(P, nin, H, Wz, Wr, Wh, Uz, Ur, Uh, X, h, hn);
+    orc_mlp(P, H, Hm, nout, M1, M2, hn, dp);
+    orc_u_average(ne, K, pmap, Fn, dp, mask, Dbar);
+    orc_u_rhs_restrict(nc, ne, K, elems, pmap, fxy, Fn, v, Dbar, dt, bL);
+    memcpy(h, hn, sizeof(double) * (size_t)P * H);
+    for (int f = 0; f < 2 * Fn; ++f) uprev[f] = Pv[f] + Dbar[f];
+    if (Pv_out) memcpy(Pv_out, Pv, sizeof(double) * 2 * Fn);
+    if (D_out) memcpy(D_out, D, sizeof(double) * 2 * Fn);
+    if (X_out) memcpy(X_out, X, sizeof(double) * (size_t)P * nin);
+    if (dpatch_out) memcpy(dpatch_out, dp, sizeof(double) * (size_t)P * nout);
+    if (Dbar_out) memcpy(Dbar_out, Dbar, sizeof(double) * 2 * Fn);
+    if (bL_out) memcpy(bL_out, bL, sizeof(double) * 2 * nc);
+    free(Pv); free(Pp); free(D); free(feat); free(X); free(hn); free(dp); free(Dbar); free(bL);
+    return 0;
+}
+
 /* ---------------------------------------------------------- the full step */
 /* One DNN-MG fine step (Alg. 2, lines 6-9) for given coarse v, p, with the
  * time scheme's weight theta (1: implicit Euler; 1/2: Crank-Nicolson as in

@@ -427,3 +427,193 @@ def serving_requests(n: int = 256, rate: float = 20.0, seed: int = 11,
         reqs.append(dict(id=r, arrival=float(arrivals[r]), nx=nx, ny=ny,
                          steps=int(steps[r]), field_seed=1000 + r))
     return reqs
+
+
+# --------------------------------------------------------------------------
+# Unstructured quadrilateral meshes (explicit connectivity, curved edges).
+# --------------------------------------------------------------------------
+
+@dataclass
+class UMesh:
+    """A coarse quadrilateral mesh: node coordinates (Nc x 2), elements
+    (P x 4 node indices v0, v1, v2, v3 counter-clockwise), Dirichlet edges
+    (node pairs), circles (cx, cy, r) and curved edges (node a, node b,
+    circle index)."""
+    xy: np.ndarray
+    elems: np.ndarray
+    dirichlet_edges: np.ndarray
+    circles: np.ndarray
+    curved: np.ndarray
+
+
+@dataclass
+class UFlow:
+    """A synthetic flow on an unstructured mesh: the coarse fields per step."""
+    mesh: UMesh
+    dt: float
+    fourier: FourierField
+    inflow_max: float = 0.0
+    height: float = CHANNEL_LY
+    hole: tuple = None        # (cx, cy, r): velocity damped to zero on this circle
+
+    def fields(self, step: int):
+        xy = self.mesh.xy
+        t = step * self.dt
+        v = self.fourier.velocity(xy, t)
+        if self.inflow_max > 0.0:
+            prof = channel_profile(xy[:, 1], self.height)
+            v = v * prof[:, None]
+            v[:, 0] += self.inflow_max * prof
+        if self.hole is not None:
+            cx, cy, r = self.hole
+            d = np.hypot(xy[:, 0] - cx, xy[:, 1] - cy)
+            s = np.clip((d - r) / r, 0.0, 1.0)
+            v = v * (s * s * (3.0 - 2.0 * s))[:, None]
+        p = self.fourier.pressure(xy, t)
+        return v.astype(np.float32), p.astype(np.float32)
+
+
+def _signed_area(xy, e):
+    p = xy[e]
+    return 0.5 * float(np.sum(p[:, 0] * np.roll(p[:, 1], -1) - np.roll(p[:, 0], -1) * p[:, 1]))
+
+
+class _NodeSet:
+    """Nodes merged by their coordinates (rounded to 1e-12 of the domain)."""
+
+    def __init__(self, scale):
+        self.q = 1e-12 * scale
+        self.idx, self.pts = {}, []
+
+    def add(self, x, y):
+        key = (round(x / self.q), round(y / self.q))
+        i = self.idx.get(key)
+        if i is None:
+            i = len(self.pts)
+            self.idx[key] = i
+            self.pts.append((x, y))
+        return i
+
+
+def cylinder_channel_umesh(m=8, length=CHANNEL_LX, height=CHANNEL_LY, center=(0.2, 0.2), radius=0.05,
+                           half_box=0.1):
+    """The channel [0, length] x [0, height] around a circular obstacle: an
+    O-grid ring of 4 m x mr elements between the circle and a square box
+    (half side half_box), and eight structured blocks outside the box, the
+    box side cut into m elements; about uniform element size 2 half_box / m.
+    Vertices where the ring meets the blocks' corners have five elements.
+    Curved edges: the ring's edges on the circle.  Dirichlet edges: the
+    inflow side x = 0, the walls y = 0, y = height and the circle; the
+    outflow x = length is do-nothing."""
+    cx, cy = center
+    hs = 2.0 * half_box / m
+    x0, x1 = cx - half_box, cx + half_box
+    y0, y1 = cy - half_box, cy + half_box
+    nodes = _NodeSet(max(length, height))
+    elems, curved, dirichlet = [], [], []
+
+    def add_quad(a, b, c, d, xy_tmp):
+        e = [a, b, c, d]
+        if _signed_area(xy_tmp, e) < 0:
+            e = [a, d, c, b]
+        elems.append(e)
+
+    # square box perimeter, counter-clockwise from (x0, y0)
+    per = []
+    for k in range(m):
+        per.append((x0 + (x1 - x0) * k / m, y0))
+    for k in range(m):
+        per.append((x1, y0 + (y1 - y0) * k / m))
+    for k in range(m):
+        per.append((x1 - (x1 - x0) * k / m, y1))
+    for k in range(m):
+        per.append((x0, y1 - (y1 - y0) * k / m))
+    mr = max(1, int(round((half_box - radius) / hs)))
+    ring = np.empty((4 * m, mr + 1), dtype=np.int64)
+    for i, (qx, qy) in enumerate(per):
+        d = math.hypot(qx - cx, qy - cy)
+        px, py = cx + radius * (qx - cx) / d, cy + radius * (qy - cy) / d
+        for j in range(mr + 1):
+            s = j / mr
+            ring[i, j] = nodes.add(px + s * (qx - px), py + s * (qy - py)) if j < mr else nodes.add(qx, qy)
+    # blocks outside the box
+    xb = [(0.0, x0), (x0, x1), (x1, length)]
+    yb = [(0.0, y0), (y0, y1), (y1, height)]
+    blocks = []
+    for bj, (ya, yb_) in enumerate(yb):
+        for bi, (xa, xb_) in enumerate(xb):
+            if bi == 1 and bj == 1:
+                continue
+            nxb = m if bi == 1 else max(1, int(round((xb_ - xa) / hs)))
+            nyb = m if bj == 1 else max(1, int(round((yb_ - ya) / hs)))
+            ids = np.empty((nyb + 1, nxb + 1), dtype=np.int64)
+            for j in range(nyb + 1):
+                for i in range(nxb + 1):
+                    ids[j, i] = nodes.add(xa + (xb_ - xa) * i / nxb, ya + (yb_ - ya) * j / nyb)
+            blocks.append(ids)
+    xy = np.array(nodes.pts, dtype=np.float64)
+    for i in range(4 * m):
+        i2 = (i + 1) % (4 * m)
+        for j in range(mr):
+            add_quad(ring[i, j], ring[i2, j], ring[i2, j + 1], ring[i, j + 1], xy)
+        curved.append((ring[i, 0], ring[i2, 0], 0))
+        dirichlet.append((ring[i, 0], ring[i2, 0]))
+    for ids in blocks:
+        nyb, nxb = ids.shape[0] - 1, ids.shape[1] - 1
+        for j in range(nyb):
+            for i in range(nxb):
+                add_quad(ids[j, i], ids[j, i + 1], ids[j + 1, i + 1], ids[j + 1, i], xy)
+        for j in range(nyb):
+            for i in (0, nxb):
+                a, b = ids[j, i], ids[j + 1, i]
+                if abs(xy[a, 0]) < 1e-12 and abs(xy[b, 0]) < 1e-12:
+                    dirichlet.append((a, b))
+        for i in range(nxb):
+            for j in (0, nyb):
+                a, b = ids[j, i], ids[j, i + 1]
+                if (abs(xy[a, 1]) < 1e-12 and abs(xy[b, 1]) < 1e-12) or \
+                   (abs(xy[a, 1] - height) < 1e-12 and abs(xy[b, 1] - height) < 1e-12):
+                    dirichlet.append((a, b))
+    return UMesh(xy, np.array(elems, dtype=np.int32), np.array(dirichlet, dtype=np.int32),
+                 np.array([[cx, cy, radius]], dtype=np.float64), np.array(curved, dtype=np.int32))
+
+
+def cylinder_channel_flow(m=8, field_seed=1, dt=0.005, inflow_max=1.5) -> UFlow:
+    mesh = cylinder_channel_umesh(m)
+    ff = FourierField(CHANNEL_LX, CHANNEL_LY, field_seed).calibrate(mesh.xy)
+    c = mesh.circles[0]
+    return UFlow(mesh, dt, ff, inflow_max=inflow_max, hole=(c[0], c[1], c[2]))
+
+
+def structured_as_umesh(cxy, dirichlet, order_seed=None, rotate_seed=None, renumber_seed=None):
+    """A structured mesh (ny+1, nx+1, 2) as an unstructured one.  Element e of
+    the structured mesh (row-major) becomes element order[e] with its corners
+    c00, c10, c11, c01 cyclically shifted by rot[e] places; coarse node c
+    becomes node perm[c].  Returns (UMesh, order, rot, perm); None seeds leave
+    that part unchanged (identity)."""
+    ny, nx = cxy.shape[0] - 1, cxy.shape[1] - 1
+    nc, P = (nx + 1) * (ny + 1), nx * ny
+    perm = np.arange(nc) if renumber_seed is None else np.random.default_rng(renumber_seed).permutation(nc)
+    order = np.arange(P) if order_seed is None else np.random.default_rng(order_seed).permutation(P)
+    rot = np.zeros(P, dtype=np.int64) if rotate_seed is None else np.random.default_rng(rotate_seed).integers(0, 4, P)
+    xy = np.empty((nc, 2))
+    xy[perm] = cxy.reshape(-1, 2)
+    elems = np.empty((P, 4), dtype=np.int32)
+    for j in range(ny):
+        for i in range(nx):
+            e = j * nx + i
+            c = [j * (nx + 1) + i, j * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i]
+            c = [perm[k] for k in c]
+            r = rot[e]
+            elems[order[e]] = c[r:] + c[:r]
+    dirs = []
+    for j in range(ny + 1):
+        for i in range(nx + 1):
+            a = j * (nx + 1) + i
+            if i < nx and ((j == 0 and dirichlet & DIR_YMIN) or (j == ny and dirichlet & DIR_YMAX)):
+                dirs.append((perm[a], perm[a + 1]))
+            if j < ny and ((i == 0 and dirichlet & DIR_XMIN) or (i == nx and dirichlet & DIR_XMAX)):
+                dirs.append((perm[a], perm[a + nx + 1]))
+    mesh = UMesh(xy, elems, np.array(dirs, dtype=np.int32).reshape(-1, 2), np.zeros((0, 3)),
+                 np.zeros((0, 3), dtype=np.int32))
+    return mesh, order, rot, perm

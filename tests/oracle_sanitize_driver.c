@@ -23,6 +23,15 @@ int orc_step_form(int nx, int ny, int K, int H, int Hm, double dt, double nu, do
                   double *Pv_out, double *D_out, double *X_out, double *dpatch_out,
                   double *Dbar_out, double *bL_out);
 long orc_paper_weight_count(int K, int H);
+int orc_umesh_count(int nc, int ne, const int *elems, int K, int *n_edges, int *n_fine);
+int orc_umesh_refine(int nc, int ne, const double *xy, const int *elems, int K, int ncurved, const int *curved,
+                     const double *circles, double *fxy, int *pmap);
+void orc_u_mask(int ne, int K, const int *elems, const int *pmap, int Fn, int ndir, const int *dir_edges,
+                unsigned char *mask);
+int orc_u_step(int nc, int ne, const double *xy, const int *elems, int K, int H, int Hm, double dt, double nu,
+               const int *pmap, const double *fxy, int Fn, const unsigned char *mask, const double *weights,
+               const double *v, const double *p, double *h, double *uprev, int first,
+               double *Pv_out, double *D_out, double *X_out, double *dpatch_out, double *Dbar_out, double *bL_out);
 
 static double urand(unsigned long long *s)
 {
@@ -103,6 +112,38 @@ int main(void)
                "quantised product\n", nx, ny, K, H, Hm);
         free(cxy); free(w); free(v); free(p); free(Pv); free(D); free(X); free(dp); free(Db); free(bL);
         free(S); free(feat);
+    }
+    {
+        /* an unstructured mesh: 2 x 1 elements, the bottom-left edge on a circle */
+        const double xy[12] = {0, 0, 1, 0, 2, 0, 0, 1, 1, 1, 2, 1};
+        const int el[8] = {0, 1, 4, 3, 1, 2, 5, 4};
+        const int curved[3] = {0, 1, 0}, dirs[4] = {0, 1, 0, 3};
+        const double circ[3] = {0.5, 1.0, 1.1180339887498949};
+        for (int K = 1; K <= 3; ++K) {
+            const int n = 1 << K, nf = (n + 1) * (n + 1), nin = 4 * nf + 4, nout = 2 * nf, H = 8;
+            int E, Fn;
+            orc_umesh_count(6, 2, el, K, &E, &Fn);
+            double *fxy = malloc(sizeof(double) * 2 * Fn), *up = calloc(2 * (size_t)Fn, sizeof(double));
+            int *pmap = malloc(sizeof(int) * 2 * nf);
+            unsigned char *mask = malloc(Fn);
+            orc_umesh_refine(6, 2, xy, el, K, 1, curved, circ, fxy, pmap);
+            orc_u_mask(2, K, el, pmap, Fn, 2, dirs, mask);
+            const size_t nw = 3 * (size_t)H * nin + 3 * (size_t)H * H + (size_t)nout * H;
+            double *w = malloc(sizeof(double) * nw), *h = calloc(2 * (size_t)H, sizeof(double));
+            for (size_t k = 0; k < nw; ++k) w[k] = 0.3 * urand(&seed);
+            double v[12], p[6], bL[12];
+            double *Db = malloc(sizeof(double) * 2 * Fn);
+            for (int step = 0; step < 3; ++step) {
+                for (int c = 0; c < 6; ++c) { v[2 * c] = urand(&seed); v[2 * c + 1] = urand(&seed); p[c] = urand(&seed); }
+                if (orc_u_step(6, 2, xy, el, K, H, 0, 0.01, 1e-3, pmap, fxy, Fn, mask, w, v, p, h, up, step == 0,
+                               NULL, NULL, NULL, NULL, Db, bL) != 0) {
+                    fprintf(stderr, "unstructured step failed\n");
+                    return 1;
+                }
+            }
+            free(fxy); free(up); free(pmap); free(mask); free(w); free(h); free(Db);
+        }
+        printf("unstructured 2-element mesh with a curved edge, K = 1..3: 3 steps\n");
     }
     return 0;
 }

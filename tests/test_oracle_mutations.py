@@ -59,6 +59,19 @@ MUTATIONS = {
     "conv_adjoint_direction": ("int rr = r - dr, cc = c - dc;", "int rr = r + dr, cc = c + dc;", 0),
     "vertex_block_transposed": ("conv_block(2, nf, WV, img, a);", "conv_block(nf, 2, WV, img, a);", 0),
     "conv_head_no_output_weights": ("for (int o = 0; o < nout; ++o) de[o] *= wf[o];", "(void)wf;", 0),
+    # unstructured meshes
+    "umesh_edge_from_own_end": ("int t = p < q ? along : n - along;", "int t = along;", 0),
+    "umesh_no_transfinite_blend": ("fxy[2 * f + c] = (1 - eta) * Bp[c] + eta * Tp[c] + (1 - xi) * Lp[c] + xi * Rp[c] - bil;",
+                                   "fxy[2 * f + c] = bil;", 0),
+    "umesh_arc_as_chord": ("out[0] = cx + r * cos(ta + s * d);\n    out[1] = cy + r * sin(ta + s * d);",
+                           "out[0] = (1.0 - s) * A[0] + s * B[0];\n    out[1] = (1.0 - s) * A[1] + s * B[1];", 0),
+    "u_average_fixed_divisor": ("Dbar[2 * f] /= cnt[f];", "Dbar[2 * f] /= 4;", 0),
+    "u_restrict_corner_order": ("coarse[ncomp * elems[4 * e + k] + c] += N[k] * fine[ncomp * f + c];",
+                                "coarse[ncomp * elems[4 * e + k] + c] += N[3 - k] * fine[ncomp * f + c];", 0),
+    "u_features_hx_edges": ("double hx = 0.5 * (hypot(c1[0] - c0[0], c1[1] - c0[1]) + hypot(c2[0] - c3[0], c2[1] - c3[1]));",
+                            "double hx = 0.5 * (hypot(c1[0] - c0[0], c1[1] - c0[1]) + hypot(c2[0] - c1[0], c2[1] - c1[1]));", 0),
+    "u_mask_without_ends": ("            for (int t = 0; t <= n; ++t) {\n                int a = k == 0 || k == 2",
+                            "            for (int t = 1; t < n; ++t) {\n                int a = k == 0 || k == 2", 0),
     # FP8 E4M3 operand form
     "e4m3_ties_away": ("rint((ldexp(a, -e) - 1.0) * 8.0)", "round((ldexp(a, -e) - 1.0) * 8.0)", 0),
     "e4m3_truncate": ("rint((ldexp(a, -e) - 1.0) * 8.0)", "floor((ldexp(a, -e) - 1.0) * 8.0)", 0),
@@ -92,6 +105,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_fp8_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_paper_net_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_paper_net_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_umesh_pins.py")],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, "pins did not catch mutation %s:\n%s" % (name, r.stdout[-2000:])
