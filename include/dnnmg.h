@@ -231,6 +231,65 @@ int dnnmg_step_batch(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int nflows,
 
 int dnnmg_destroy(dnnmg_ctx *ctx);
 
+/* ------------------------------------------------ unstructured meshes
+ * A coarse mesh of quadrilaterals with explicit connectivity (the paper's
+ * meshes, Sec. 3.1 and the obstacle geometries of the numerical examples):
+ * node coordinates, four nodes per element counter-clockwise (v0, v1, v2, v3
+ * at the reference corners (0,0), (1,0), (1,1), (0,1)), the boundary edges
+ * with Dirichlet values (node pairs; other boundary edges are do-nothing
+ * outflow), circles (cx, cy, r) and the edges lying on them (node a, node b,
+ * circle index; both nodes on the circle).  All arrays are host memory owned
+ * by the caller.  Elements next to each other must be oriented alike; every
+ * fine element must be positively oriented.
+ * Refinement: each element into n x n fine elements (one patch per element).
+ * Fine nodes on a curved edge lie on its arc (angle linear along the edge);
+ * element interiors follow the transfinite (Gordon-Hall) map of the four edge
+ * curves, so the fine mesh is the isoparametric refinement.  Fine node
+ * numbering (d_fine_dev, the u_prev state):
+ *   0 .. Nc-1                    the coarse nodes;
+ *   Nc + k (n-1) + t - 1         the inner nodes of edge k, t = 1 .. n-1 from
+ *                                its lower-numbered node; edges numbered in
+ *                                order of first appearance over the elements,
+ *                                local edges (v0,v1), (v1,v2), (v3,v2), (v0,v3);
+ *   Nc + E (n-1) + e (n-1)^2 + (b-1)(n-1) + a - 1
+ *                                the inner node (a, b) of element e.
+ * The step is the structured one's (Alg. 2, lines 6-9; implicit Euler, the
+ * workloads' network) with the mesh's own operators: P v at a fine node is the
+ * bilinear interpolation, in the reference coordinates of the first element
+ * that holds it, of that element's corner values; the defect and the mass
+ * matrix are assembled over the fine elements (2 x 2 Gauss points on each
+ * fine element's own bilinear map); duplicate predictions are averaged over
+ * every patch that holds a node; R = P^T.  Patch-local node order and the
+ * network input are those of the structured form, the features taken from
+ * each element's four corners (hx the mean of edges (v0,v1), (v3,v2); hy of
+ * (v0,v3), (v1,v2); hx / hy; the straight quadrilateral's area). */
+typedef struct {
+    int n_nodes, n_elems;
+    const double *xy;              /* n_nodes x 2                                */
+    const int *elems;              /* n_elems x 4                                */
+    int n_dirichlet;
+    const int *dirichlet_edges;    /* n_dirichlet x 2 (or NULL when 0)           */
+    int n_circles;
+    const double *circles;         /* n_circles x 3 (or NULL when 0)             */
+    int n_curved;
+    const int *curved_edges;       /* n_curved x 3 (or NULL when 0)              */
+} dnnmg_umesh;
+
+/* Edge and fine node counts of `mesh` refined K times (host only; validates
+ * the mesh: DNNMG_EINVAL with the reason in dnnmg_last_error). */
+int dnnmg_umesh_counts(const dnnmg_umesh *mesh, int K, int *n_edges, int *n_fine_nodes);
+
+/* A flow on an unstructured mesh.  cfg supplies K, H, Hm, dt, nu, precision
+ * (FP32 or BF16) and flags (DNNMG_F_NANCHECK, DNNMG_F_GRU_RESET_AFTER);
+ * cfg->nx, ny and dirichlet are not used.  Weights as dnnmg_create.  The
+ * context then takes dnnmg_step (v: n_nodes x 2, p: n_nodes, d: Fn x 2),
+ * dnnmg_restrict_rhs (b: n_nodes x 2), dnnmg_prolong, dnnmg_defect,
+ * dnnmg_rhs_restrict (fine arrays in the numbering above), dnnmg_get_state /
+ * dnnmg_set_state (u_prev Fn x 2), dnnmg_patch_output, dnnmg_nonfinite and
+ * the profiling calls; it steps alone (dnnmg_step_batch rejects it). */
+int dnnmg_create_umesh(const dnnmg_config *cfg, const dnnmg_umesh *mesh, const float *weights_host,
+                       size_t n_weights, void *stream, dnnmg_ctx **out);
+
 /* ---------------------------------------------------------------------
  * Device arena (serving form: flows admitted and retired while others run).
  * One hipMalloc of `bytes` and a pinned staging ring of `staging_bytes` when

@@ -35,7 +35,7 @@ SYMBOLS = [
     "dnnmg_step_count", "dnnmg_profile_enable", "dnnmg_profile_read", "dnnmg_quantize_e4m3",
     "dnnmg_noalloc_scratch_bytes", "dnnmg_rhs_restrict_noalloc", "dnnmg_nonfinite",
     "dnnmg_arena_create", "dnnmg_arena_destroy", "dnnmg_arena_block_bytes", "dnnmg_arena_usage",
-    "dnnmg_create_in_arena", "dnnmg_arena_upload",
+    "dnnmg_create_in_arena", "dnnmg_arena_upload", "dnnmg_umesh_counts", "dnnmg_create_umesh",
 ]
 DNNMG_NOALLOC_MAX_PATCHES = 1 << 18
 
@@ -85,6 +85,8 @@ def lib():
     L.dnnmg_rhs_restrict.argtypes = [vp, vp, vp, vp, vp]
     L.dnnmg_get_state.argtypes = [vp, vp, vp, vp]
     L.dnnmg_set_state.argtypes = [vp, vp, vp, ctypes.c_longlong, vp]
+    L.dnnmg_umesh_counts.argtypes = [ctypes.POINTER(UMeshC), i, ctypes.POINTER(i), ctypes.POINTER(i)]
+    L.dnnmg_create_umesh.argtypes = [cp, ctypes.POINTER(UMeshC), vp, sz, vp, ctypes.POINTER(vp)]
     L.dnnmg_patch_output.argtypes = [vp, vp, vp]
     L.dnnmg_step_count.argtypes = [vp]; L.dnnmg_step_count.restype = ctypes.c_longlong
     L.dnnmg_profile_enable.argtypes = [vp, i]
@@ -334,6 +336,58 @@ def rhs_restrict_noalloc(nx, ny, K, dt, coarse_xy, v, dbar, b_out, stream=None):
                                             _ptr(v, torch.float32, 2 * s["Nc"], "v"),
                                             _ptr(dbar, torch.float32, 2 * s["Fn"], "dbar"),
                                             _ptr(b_out, torch.float64, 2 * s["Nc"], "b_out"), _stream(stream)))
+
+
+class UMeshC(ctypes.Structure):
+    """dnnmg_umesh (include/dnnmg.h)."""
+    _fields_ = [("n_nodes", ctypes.c_int), ("n_elems", ctypes.c_int), ("xy", ctypes.c_void_p),
+                ("elems", ctypes.c_void_p), ("n_dirichlet", ctypes.c_int), ("dirichlet_edges", ctypes.c_void_p),
+                ("n_circles", ctypes.c_int), ("circles", ctypes.c_void_p), ("n_curved", ctypes.c_int),
+                ("curved_edges", ctypes.c_void_p)]
+
+
+def _umesh_c(mesh):
+    """(UMeshC, the arrays it points into) for a mesh with fields xy, elems,
+    dirichlet_edges, circles, curved (numpy-like)."""
+    keep = dict(xy=np.ascontiguousarray(mesh.xy, dtype=np.float64).reshape(-1, 2),
+                elems=np.ascontiguousarray(mesh.elems, dtype=np.int32).reshape(-1, 4),
+                dirs=np.ascontiguousarray(mesh.dirichlet_edges, dtype=np.int32).reshape(-1, 2),
+                circ=np.ascontiguousarray(mesh.circles, dtype=np.float64).reshape(-1, 3),
+                curved=np.ascontiguousarray(mesh.curved, dtype=np.int32).reshape(-1, 3))
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a.size else None
+    c = UMeshC(keep["xy"].shape[0], keep["elems"].shape[0], ptr(keep["xy"]), ptr(keep["elems"]),
+               keep["dirs"].shape[0], ptr(keep["dirs"]), keep["circ"].shape[0], ptr(keep["circ"]),
+               keep["curved"].shape[0], ptr(keep["curved"]))
+    return c, keep
+
+
+def umesh_counts(mesh, K):
+    """dnnmg_umesh_counts: (edges, fine nodes) of the mesh refined K times."""
+    c, _keep = _umesh_c(mesh)
+    E, Fn = ctypes.c_int(), ctypes.c_int()
+    _check(lib().dnnmg_umesh_counts(ctypes.byref(c), K, ctypes.byref(E), ctypes.byref(Fn)))
+    return E.value, Fn.value
+
+
+class UDnnMG(DnnMG):
+    """One flow on an unstructured mesh (dnnmg_create_umesh): the same calls
+    as DnnMG with fine arrays in the mesh's fine numbering."""
+
+    def __init__(self, K, H, Hm, dt, nu, mesh, weights, precision=FP32, flags=0, stream=None):
+        import torch
+        c, keep = _umesh_c(mesh)
+        ne, nc = keep["elems"].shape[0], keep["xy"].shape[0]
+        self.cfg = make_config(ne, 1, K, H, Hm, dt, nu, precision, 0, flags)
+        E, Fn = umesh_counts(mesh, K)
+        n = 1 << K
+        nf = (n + 1) ** 2
+        self.s = dict(n=n, nf=nf, nin=4 * nf + 4, nout=2 * nf, P=ne, Fn=Fn, Nc=nc, E=E)
+        w = np.ascontiguousarray(weights, dtype=np.float32).reshape(-1)
+        h = ctypes.c_void_p()
+        _check(lib().dnnmg_create_umesh(ctypes.byref(self.cfg), ctypes.byref(c), w.ctypes.data_as(ctypes.c_void_p),
+                                        w.size, _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.device = torch.cuda.current_device()
 
 
 class Batch:

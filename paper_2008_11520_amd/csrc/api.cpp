@@ -20,6 +20,7 @@
 #include "arena.h"
 #include "dnnmg.h"
 #include "internal.h"
+#include "umesh_build.h"
 
 using namespace dnnmg;
 
@@ -245,6 +246,19 @@ static void profile_release(Profile &pr);
 
 struct dnnmg_arena;
 
+// The refined unstructured mesh on the device (contexts made by
+// dnnmg_create_umesh): one allocation holding the gather lists, patch maps,
+// fine coordinates and the per-fine-node buffers.
+struct UMeshDev {
+    int nc = 0, ne = 0, E = 0, Fn = 0;
+    unsigned char *dev = nullptr;
+    int *corners = nullptr, *pmap = nullptr, *node_ptr = nullptr, *node_occ = nullptr;
+    int *cnode_ptr = nullptr, *cnode_occ = nullptr;
+    double *rel = nullptr;
+    float *feat = nullptr, *uprev = nullptr, *dloc = nullptr, *D = nullptr;
+    unsigned char *mask = nullptr;
+};
+
 struct dnnmg_ctx {
     dnnmg_config cfg;
     Profile prof;
@@ -255,6 +269,7 @@ struct dnnmg_ctx {
     long long steps = 0;
     int device = 0;
     dnnmg_arena *arena = nullptr;   // the workspace is a block of this arena (not hipMalloc'd)
+    UMeshDev *um = nullptr;         // unstructured mesh (dnnmg_create_umesh), else structured
 
     float *geo() const { return (float *)(ws + L.geo); }
     double *geo64() const { return (double *)(ws + L.geo64); }
@@ -634,6 +649,56 @@ int check_ctx(const dnnmg_ctx *c)
     return DNNMG_OK;
 }
 
+// ----------------------------------------------------- unstructured meshes
+UArgs uargs(const dnnmg_ctx *c, const float *v, const float *p)
+{
+    const UMeshDev &m = *c->um;
+    UArgs u{};
+    u.K = c->cfg.K;
+    u.P = m.ne;
+    u.Fn = m.Fn;
+    u.Nc = m.nc;
+    u.nin = c->s.nin;
+    u.xfmt = c->cfg.precision;
+    u.inv_dt = (float)(1.0 / c->cfg.dt);
+    u.nu = (float)c->cfg.nu;
+    u.inv_dt64 = 1.0 / c->cfg.dt;
+    u.v = v;
+    u.p = p;
+    u.corners = m.corners;
+    u.pmap = m.pmap;
+    u.rel = m.rel;
+    u.feat = m.feat;
+    u.mask = m.mask;
+    u.node_ptr = m.node_ptr;
+    u.node_occ = m.node_occ;
+    u.cnode_ptr = m.cnode_ptr;
+    u.cnode_occ = m.cnode_occ;
+    u.first_flag = c->first_flag();
+    u.uprev = m.uprev;
+    u.dloc = m.dloc;
+    u.D = m.D;
+    u.X = c->X();
+    u.dpatch = c->dpatch();
+    u.part = c->part();
+    u.nonfinite = (c->cfg.flags & DNNMG_F_NANCHECK) ? (int *)(c->ws + c->L.nonfinite) : nullptr;
+    return u;
+}
+
+// The network launch of an unstructured context: its patches as one row of
+// ne elements.
+FlowArgs unet_args(const dnnmg_ctx *c)
+{
+    FlowArgs f{};
+    f.nx = c->um->ne;
+    f.ny = 1;
+    f.h = c->h();
+    f.X = c->X();
+    f.xfmt = c->cfg.precision;
+    f.dpatch = c->dpatch();
+    return f;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ arena
@@ -730,12 +795,120 @@ extern "C" int dnnmg_create_shared(const dnnmg_config *cfg, const double *coarse
     return create_common(cfg, coarse_xy_host, nullptr, 0, model->w, stream, out);
 }
 
+extern "C" int dnnmg_umesh_counts(const dnnmg_umesh *mesh, int K, int *n_edges, int *n_fine_nodes)
+{
+    if (!mesh || !n_edges || !n_fine_nodes || !mesh->xy || !mesh->elems)
+        return fail(DNNMG_EINVAL, "mesh, its xy and elems, n_edges and n_fine_nodes must not be NULL");
+    UMeshHost m;
+    const std::string err = build_umesh(mesh->n_nodes, mesh->n_elems, mesh->xy, mesh->elems, mesh->n_dirichlet,
+                                        mesh->dirichlet_edges, mesh->n_circles, mesh->circles, mesh->n_curved,
+                                        mesh->curved_edges, K, m);
+    if (!err.empty()) return fail(DNNMG_EINVAL, "mesh: %s", err.c_str());
+    *n_edges = m.E;
+    *n_fine_nodes = m.Fn;
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_create_umesh(const dnnmg_config *cfg, const dnnmg_umesh *mesh, const float *weights,
+                                  size_t nw, void *stream, dnnmg_ctx **out)
+{
+    if (!out) return fail(DNNMG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfg || !mesh || !mesh->xy || !mesh->elems) return fail(DNNMG_EINVAL, "cfg, mesh, its xy and elems must not be NULL");
+    if ((mesh->n_dirichlet > 0 && !mesh->dirichlet_edges) || (mesh->n_circles > 0 && !mesh->circles) ||
+        (mesh->n_curved > 0 && !mesh->curved_edges))
+        return fail(DNNMG_EINVAL, "a mesh list with entries has a NULL pointer");
+    dnnmg_config g = *cfg;
+    g.nx = std::max(mesh->n_elems, 1);   // the patches as one row (sizes, network launch)
+    g.ny = 1;
+    g.dirichlet = 0;
+    int rc = check_config(&g);
+    if (rc) return rc;
+    if (g.flags & ~(unsigned)(DNNMG_F_NANCHECK | DNNMG_F_UNFUSED | DNNMG_F_GRU_RESET_AFTER))
+        return fail(DNNMG_EUNSUPPORTED, "unstructured meshes take DNNMG_F_NANCHECK and DNNMG_F_GRU_RESET_AFTER only");
+    if (g.precision == DNNMG_FP8_E4M3) return fail(DNNMG_EUNSUPPORTED, "unstructured meshes run FP32 or BF16 operands");
+    if (!weights) return fail(DNNMG_EINVAL, "weights_host is NULL");
+    if (nw != weight_count(g)) return fail(DNNMG_EINVAL, "n_weights = %zu, expected %zu", nw, weight_count(g));
+    UMeshHost m;
+    const std::string err = build_umesh(mesh->n_nodes, mesh->n_elems, mesh->xy, mesh->elems, mesh->n_dirichlet,
+                                        mesh->dirichlet_edges, mesh->n_circles, mesh->circles, mesh->n_curved,
+                                        mesh->curved_edges, g.K, m);
+    if (!err.empty()) return fail(DNNMG_EINVAL, "mesh: %s", err.c_str());
+
+    hipStream_t st = (hipStream_t)stream;
+    dnnmg_ctx *c = new dnnmg_ctx();
+    c->cfg = g;
+    c->s = sizes_of(g);
+    c->s.Fn = m.Fn;
+    c->s.Nc = m.nc;
+    c->L = layout_of(g);
+    (void)hipGetDevice(&c->device);
+    UMeshDev *d = new UMeshDev();
+    d->nc = m.nc; d->ne = m.ne; d->E = m.E; d->Fn = m.Fn;
+    c->um = d;
+    // one device block for the mesh: offsets of the arrays, 256-byte aligned
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t r = off; off += align256(bytes); return r; };
+    const size_t o_corn = take(sizeof(int) * m.corners.size()), o_pmap = take(sizeof(int) * m.pmap.size());
+    const size_t o_nptr = take(sizeof(int) * m.node_ptr.size()), o_nocc = take(sizeof(int) * m.node_occ.size());
+    const size_t o_cptr = take(sizeof(int) * m.cnode_ptr.size()), o_cocc = take(sizeof(int) * m.cnode_occ.size());
+    const size_t o_rel = take(sizeof(double) * m.rel.size()), o_feat = take(sizeof(float) * m.feat.size());
+    const size_t o_mask = take(m.mask.size()), o_up = take(sizeof(float) * 2 * (size_t)m.Fn);
+    const size_t o_dloc = take(sizeof(float) * 2 * (size_t)m.ne * m.nf), o_D = take(sizeof(float) * 2 * (size_t)m.Fn);
+    auto bail = [&](int code) {
+        (void)hipFree(c->ws);
+        (void)hipFree(d->dev);
+        if (c->w) release_weights(c->w);
+        delete d;
+        delete c;
+        return code;
+    };
+    if (hipMalloc((void **)&c->ws, c->L.total) != hipSuccess || hipMalloc((void **)&d->dev, off) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(DNNMG_ENOMEM, "hipMalloc of %zu + %zu bytes failed", c->L.total, off));
+    }
+    d->corners = (int *)(d->dev + o_corn); d->pmap = (int *)(d->dev + o_pmap);
+    d->node_ptr = (int *)(d->dev + o_nptr); d->node_occ = (int *)(d->dev + o_nocc);
+    d->cnode_ptr = (int *)(d->dev + o_cptr); d->cnode_occ = (int *)(d->dev + o_cocc);
+    d->rel = (double *)(d->dev + o_rel); d->feat = (float *)(d->dev + o_feat);
+    d->mask = d->dev + o_mask; d->uprev = (float *)(d->dev + o_up);
+    d->dloc = (float *)(d->dev + o_dloc); d->D = (float *)(d->dev + o_D);
+    rc = build_weights(g, weights, st, &c->w);
+    if (rc) { c->w = nullptr; return bail(rc); }
+    hipError_t e = hipSuccess;
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    up(d->corners, m.corners.data(), sizeof(int) * m.corners.size());
+    up(d->pmap, m.pmap.data(), sizeof(int) * m.pmap.size());
+    up(d->node_ptr, m.node_ptr.data(), sizeof(int) * m.node_ptr.size());
+    up(d->node_occ, m.node_occ.data(), sizeof(int) * m.node_occ.size());
+    up(d->cnode_ptr, m.cnode_ptr.data(), sizeof(int) * m.cnode_ptr.size());
+    up(d->cnode_occ, m.cnode_occ.data(), sizeof(int) * m.cnode_occ.size());
+    up(d->rel, m.rel.data(), sizeof(double) * m.rel.size());
+    up(d->feat, m.feat.data(), sizeof(float) * m.feat.size());
+    up(d->mask, m.mask.data(), m.mask.size());
+    if (e == hipSuccess) e = hipMemsetAsync(d->uprev, 0, sizeof(float) * 2 * (size_t)m.Fn, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->h(), 0, sizeof(float) * (size_t)m.ne * g.H, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + c->L.nonfinite, 0, sizeof(int), st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->first_flag(), 1, sizeof(int), st);
+    // the host vectors are the copies' sources: wait before they go
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bail(fail(DNNMG_EDEVICE, "create_umesh: %s", hipGetErrorString(e)));
+    *out = c;
+    return DNNMG_OK;
+}
+
 extern "C" int dnnmg_destroy(dnnmg_ctx *ctx)
 {
     if (!ctx) return fail(DNNMG_EINVAL, "ctx is NULL");
     for (hipEvent_t e : ctx->prof.ev) (void)hipEventSynchronize(e);
     for (hipEvent_t e : ctx->prof.evg) (void)hipEventSynchronize(e);
     profile_release(ctx->prof);
+    if (ctx->um) {
+        (void)hipFree(ctx->um->dev);
+        delete ctx->um;
+    }
     if (ctx->arena) {
         ctx->arena->blocks.give((size_t)(ctx->ws - ctx->arena->base), ctx->L.total);
         ctx->arena->live--;
@@ -889,6 +1062,26 @@ extern "C" int dnnmg_create_in_arena(dnnmg_arena *a, const dnnmg_config *cfg, co
 
 extern "C" long long dnnmg_step_count(const dnnmg_ctx *ctx) { return ctx ? ctx->steps : -1; }
 
+static int enqueue_ustep(dnnmg_ctx *c, const UArgs &u, hipStream_t st)
+{
+    const dnnmg_config &g = c->cfg;
+    Profile &pr = c->prof;
+    hipEvent_t *ev = (pr.max_steps > 0 && pr.steps < pr.max_steps) ? &pr.ev[4 * pr.steps] : nullptr;
+    if (ev) HIP_OR_FAIL(hipEventRecord(ev[0], st));
+    HIP_OR_FAIL(launch_udefect(u, c->um->D, st));
+    HIP_OR_FAIL(launch_uinput(u, st));
+    if (ev) HIP_OR_FAIL(hipEventRecord(ev[1], st));
+    HIP_OR_FAIL(launch_net(unet_args(c), nullptr, blocks_for(kKindNet, c->um->ne, 1, g.K), c->w->net, st));
+    if (ev) HIP_OR_FAIL(hipEventRecord(ev[2], st));
+    HIP_OR_FAIL(launch_uaverage(u, st));            // D now holds the averaged correction
+    HIP_OR_FAIL(launch_urhs(u, c->um->D, st));
+    if (ev) {
+        HIP_OR_FAIL(hipEventRecord(ev[3], st));
+        pr.steps++;
+    }
+    return DNNMG_OK;
+}
+
 static int enqueue_step(dnnmg_ctx *c, const FlowArgs &f, hipStream_t st)
 {
     const dnnmg_config &g = c->cfg;
@@ -978,6 +1171,14 @@ extern "C" int dnnmg_step(dnnmg_ctx *ctx, const float *v, const float *p, float 
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!v) return fail(DNNMG_EINVAL, "v_coarse_dev is NULL");
+    if (ctx->um) {
+        UArgs u = uargs(ctx, v, p);
+        u.dbar_out = d_fine;
+        rc = enqueue_ustep(ctx, u, (hipStream_t)stream);
+        if (rc) return rc;
+        ctx->steps++;
+        return DNNMG_OK;
+    }
     FlowArgs f = flow_args(ctx, v, p);
     f.dbar_out = d_fine;
     rc = enqueue_step(ctx, f, (hipStream_t)stream);
@@ -997,8 +1198,14 @@ extern "C" int dnnmg_restrict_rhs(dnnmg_ctx *ctx, double *b, void *stream)
     Profile &pr = ctx->prof;
     hipEvent_t *ev = (pr.max_steps > 0 && pr.gathers < pr.max_steps) ? &pr.evg[2 * pr.gathers] : nullptr;
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[0], (hipStream_t)stream));
-    HIP_OR_FAIL(launch_gather(f, nullptr, blocks_for(kKindGather, ctx->cfg.nx, ctx->cfg.ny, ctx->cfg.K),
-                              (hipStream_t)stream));
+    if (ctx->um) {
+        UArgs u = uargs(ctx, nullptr, nullptr);
+        u.bL = b;
+        HIP_OR_FAIL(launch_ugather(u, (hipStream_t)stream));
+    } else {
+        HIP_OR_FAIL(launch_gather(f, nullptr, blocks_for(kKindGather, ctx->cfg.nx, ctx->cfg.ny, ctx->cfg.K),
+                                  (hipStream_t)stream));
+    }
     if (ev) {
         HIP_OR_FAIL(hipEventRecord(ev[1], (hipStream_t)stream));
         pr.gathers++;
@@ -1011,6 +1218,13 @@ extern "C" int dnnmg_prolong(dnnmg_ctx *ctx, const float *v, const float *p, flo
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!v) return fail(DNNMG_EINVAL, "v_coarse_dev is NULL");
+    if (ctx->um) {
+        UArgs u = uargs(ctx, v, p);
+        u.pv_out = pv;
+        u.pp_out = pp;
+        HIP_OR_FAIL(launch_uprolong(u, (hipStream_t)stream));
+        return DNNMG_OK;
+    }
     FlowArgs f = flow_args(ctx, v, p);
     HIP_OR_FAIL(launch_prolong(f, ctx->cfg.K, pv, pp, (hipStream_t)stream));
     return DNNMG_OK;
@@ -1021,6 +1235,10 @@ extern "C" int dnnmg_defect(dnnmg_ctx *ctx, const float *v, const float *p, floa
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!v || !D) return fail(DNNMG_EINVAL, "v_coarse_dev and D_out_dev must not be NULL");
+    if (ctx->um) {
+        HIP_OR_FAIL(launch_udefect(uargs(ctx, v, p), D, (hipStream_t)stream));
+        return DNNMG_OK;
+    }
     FlowArgs f = flow_args(ctx, v, p);
     f.D = D;
     f.X = nullptr;   // the stage leaves the network input alone
@@ -1034,6 +1252,14 @@ extern "C" int dnnmg_rhs_restrict(dnnmg_ctx *ctx, const float *v, const float *d
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!v || !dbar || !b) return fail(DNNMG_EINVAL, "v, dbar and b_out must not be NULL");
+    if (ctx->um) {
+        UArgs u = uargs(ctx, v, nullptr);
+        u.part = (double *)(ctx->ws + ctx->L.part2);
+        u.bL = b;
+        HIP_OR_FAIL(launch_urhs(u, dbar, (hipStream_t)stream));
+        HIP_OR_FAIL(launch_ugather(u, (hipStream_t)stream));
+        return DNNMG_OK;
+    }
     FlowArgs f = flow_args(ctx, v, nullptr);
     f.dbar_in = dbar;
     f.part = (double *)(ctx->ws + ctx->L.part2);   // keeps the step's own partial sums intact
@@ -1133,6 +1359,11 @@ extern "C" int dnnmg_get_state(dnnmg_ctx *ctx, float *h, float *u, void *stream)
     hipStream_t st = (hipStream_t)stream;
     if (h) HIP_OR_FAIL(hipMemcpyAsync(h, ctx->h(), sizeof(float) * (size_t)ctx->s.P * ctx->cfg.H,
                                       hipMemcpyDeviceToDevice, st));
+    if (ctx->um) {
+        if (u) HIP_OR_FAIL(hipMemcpyAsync(u, ctx->um->uprev, sizeof(float) * 2 * (size_t)ctx->um->Fn,
+                                          hipMemcpyDeviceToDevice, st));
+        return DNNMG_OK;
+    }
     // (the state's rows are padded to upitch nodes; the caller's are NX+1)
     const size_t row = sizeof(float) * 2 * (size_t)(ctx->cfg.nx * ctx->s.n + 1);
     if (u) HIP_OR_FAIL(hipMemcpy2DAsync(u, row, ctx->uprev(), sizeof(float) * 2 * (size_t)ctx->s.upitch, row,
@@ -1148,9 +1379,14 @@ extern "C" int dnnmg_set_state(dnnmg_ctx *ctx, const float *h, const float *u, l
     hipStream_t st = (hipStream_t)stream;
     if (h) HIP_OR_FAIL(hipMemcpyAsync(ctx->h(), h, sizeof(float) * (size_t)ctx->s.P * ctx->cfg.H,
                                       hipMemcpyDeviceToDevice, st));
-    const size_t row = sizeof(float) * 2 * (size_t)(ctx->cfg.nx * ctx->s.n + 1);
-    if (u) HIP_OR_FAIL(hipMemcpy2DAsync(ctx->uprev(), sizeof(float) * 2 * (size_t)ctx->s.upitch, u, row, row,
-                                        ctx->cfg.ny * ctx->s.n + 1, hipMemcpyDeviceToDevice, st));
+    if (ctx->um) {
+        if (u) HIP_OR_FAIL(hipMemcpyAsync(ctx->um->uprev, u, sizeof(float) * 2 * (size_t)ctx->um->Fn,
+                                          hipMemcpyDeviceToDevice, st));
+    } else {
+        const size_t row = sizeof(float) * 2 * (size_t)(ctx->cfg.nx * ctx->s.n + 1);
+        if (u) HIP_OR_FAIL(hipMemcpy2DAsync(ctx->uprev(), sizeof(float) * 2 * (size_t)ctx->s.upitch, u, row, row,
+                                            ctx->cfg.ny * ctx->s.n + 1, hipMemcpyDeviceToDevice, st));
+    }
     HIP_OR_FAIL(hipMemsetAsync(ctx->first_flag(), steps == 0 ? 1 : 0, sizeof(int), st));
     ctx->steps = steps;
     return DNNMG_OK;
@@ -1253,6 +1489,7 @@ extern "C" int dnnmg_batch_prepare(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int n
         if (!v[i]) return fail(DNNMG_EINVAL, "v[%d] is NULL", i);
         if (b_out && !b_out[i]) return fail(DNNMG_EINVAL, "b_out[%d] is NULL", i);
         if (ctxs[i]->w != w) return fail(DNNMG_EINVAL, "ctxs[%d] does not share the weights of ctxs[0]", i);
+        if (ctxs[i]->um) return fail(DNNMG_EINVAL, "ctxs[%d] is an unstructured-mesh context: it steps alone", i);
         if (ctxs[i]->cfg.flags & (DNNMG_F_CRANK_NICOLSON | DNNMG_F_PAPER_NET))
             return fail(DNNMG_EINVAL, "ctxs[%d] uses DNNMG_F_CRANK_NICOLSON or DNNMG_F_PAPER_NET: such flows step "
                                       "alone (dnnmg_step)", i);

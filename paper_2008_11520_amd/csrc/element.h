@@ -319,6 +319,53 @@ __host__ __device__ inline void strip_residual(const CoarseRec &r, int a, int b0
     }
 }
 
+// One fine element of an unstructured mesh with its own bilinear map: node
+// coordinates x, y (corners 00, 10, 01, 11, relative to any origin), nodal
+// velocity v, pressure p and u_prev / dt (w), idt = 1/dt; the same terms as
+// element_residual with every derivative in the element's own reference
+// coordinates:
+//   m_c = det (w_c - idt v_c) - v . (Cof grad_ref v_c)
+//   Q_c = p Cof^T e_c - (nu / det) G grad_ref v_c
+//   R[2 a + c] = 1/4 sum_q [ N_a m_c + grad_ref N_a . Q_c ].
+template <typename Rcp>
+__host__ __device__ inline void quad_residual(const float (&x)[4], const float (&y)[4], const float (&vx)[4],
+                                              const float (&vy)[4], const float (&pn)[4], const float (&wx)[4],
+                                              const float (&wy)[4], float nu, float idt, float (&R)[8])
+{
+    constexpr float g0 = kGauss0, g1 = kGauss1;
+    for (int k = 0; k < 8; ++k) R[k] = 0.0f;
+    for (int q = 0; q < 4; ++q) {
+        const float s = (q & 1) ? g1 : g0, t = (q >> 1) ? g1 : g0;
+        const float N[4] = {(1.0f - s) * (1.0f - t), s * (1.0f - t), (1.0f - s) * t, s * t};
+        const float Ns[4] = {-(1.0f - t), 1.0f - t, -t, t};
+        const float Nt[4] = {-(1.0f - s), -s, 1.0f - s, s};
+        float xs = 0.f, xt = 0.f, ys = 0.f, yt = 0.f, v0 = 0.f, v1 = 0.f, pq = 0.f, w0 = 0.f, w1 = 0.f;
+        float vs0 = 0.f, vt0 = 0.f, vs1 = 0.f, vt1 = 0.f;
+        for (int k = 0; k < 4; ++k) {
+            xs += x[k] * Ns[k]; xt += x[k] * Nt[k];
+            ys += y[k] * Ns[k]; yt += y[k] * Nt[k];
+            v0 += N[k] * vx[k]; v1 += N[k] * vy[k];
+            pq += N[k] * pn[k];
+            w0 += N[k] * wx[k]; w1 += N[k] * wy[k];
+            vs0 += vx[k] * Ns[k]; vt0 += vx[k] * Nt[k];
+            vs1 += vy[k] * Ns[k]; vt1 += vy[k] * Nt[k];
+        }
+        const float det = xs * yt - xt * ys;
+        const float dxx = yt * vs0 - ys * vt0, dxy = -xt * vs0 + xs * vt0;   // det grad v_x
+        const float dyx = yt * vs1 - ys * vt1, dyy = -xt * vs1 + xs * vt1;   // det grad v_y
+        const float m0 = det * (w0 - idt * v0) - (v0 * dxx + v1 * dxy);
+        const float m1 = det * (w1 - idt * v1) - (v0 * dyx + v1 * dyy);
+        const float inv = nu * Rcp::f(det);
+        const float g11 = xt * xt + yt * yt, g22 = xs * xs + ys * ys, g12 = -(xs * xt + ys * yt);
+        const float Qs0 = pq * yt - inv * (g11 * vs0 + g12 * vt0), Qt0 = -pq * ys - inv * (g12 * vs0 + g22 * vt0);
+        const float Qs1 = -pq * xt - inv * (g11 * vs1 + g12 * vt1), Qt1 = pq * xs - inv * (g12 * vs1 + g22 * vt1);
+        for (int a = 0; a < 4; ++a) {
+            R[2 * a] += 0.25f * (N[a] * m0 + Ns[a] * Qs0 + Nt[a] * Qt0);
+            R[2 * a + 1] += 0.25f * (N[a] * m1 + Ns[a] * Qs1 + Nt[a] * Qt1);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- tile partition
 // A defect tile owns kT x kT fine elements (kT = 32) and computes the ring of
 // halo elements around them as well (tile-local element coordinates -1 .. kT).

@@ -132,6 +132,45 @@ constexpr float kFp8MinMax = 448.0f * 0x1p-64f;
 constexpr float kLog2e = 1.44269504088896340736f;
 
 
+// Arguments of the unstructured-mesh step (umesh.hip).  Patch e is coarse
+// element e (corners v0..v3 counter-clockwise, reference corners (0,0),
+// (1,0), (1,1), (0,1)); its (n+1)^2 fine nodes, patch-local l = b (n+1) + a,
+// are fine nodes pmap[e nf + l] at fine coordinates rel[...] relative to v0.
+// node_ptr/node_occ: for each fine node the (patch nf + l) that hold it, in
+// patch order; cnode_ptr/cnode_occ: for each coarse node the (patch 4 + corner).
+struct UArgs {
+    int K, P, Fn, Nc, nin, xfmt;
+    float inv_dt, nu;
+    double inv_dt64;
+    const float *v, *p;              // coarse fields (Nc x 2, Nc)
+    const int *corners;              // P x 4
+    const int *pmap;                 // P x nf
+    const double *rel;               // P x nf x 2
+    const float *feat;               // P x 4
+    const unsigned char *mask;       // Fn: Dirichlet nodes
+    const int *node_ptr, *node_occ;  // Fn + 1, P nf
+    const int *cnode_ptr, *cnode_occ;// Nc + 1, 4 P
+    int *first_flag;                 // nonzero before the first step (then u_prev := P v)
+    float *uprev;                    // Fn x 2
+    float *dloc;                     // P x nf x 2: each patch's element contributions to its nodes
+    float *D;                        // Fn x 2: the assembled defect, then (step) the averaged correction
+    void *X;                         // P x nin network input (FP32 or BF16)
+    const float *dpatch;             // P x nout
+    double *part;                    // P x 4 x 2: the patches' rhs shares at their corners
+    double *bL;                      // Nc x 2
+    float *dbar_out;                 // optional Fn x 2
+    const float *dbar_in;            // stage: given correction
+    float *pv_out, *pp_out;          // prolongation stage
+    int *nonfinite;                  // non-finite check (or nullptr)
+};
+
+hipError_t launch_udefect(const UArgs &u, float *D_out, hipStream_t s);          // defect at the fine nodes
+hipError_t launch_uinput(const UArgs &u, hipStream_t s);                         // network input rows
+hipError_t launch_uaverage(const UArgs &u, hipStream_t s);                       // averaging, state, correction
+hipError_t launch_urhs(const UArgs &u, const float *dbar, hipStream_t s);       // FP64 rhs shares per patch
+hipError_t launch_ugather(const UArgs &u, hipStream_t s);                        // b_L at the coarse nodes
+hipError_t launch_uprolong(const UArgs &u, hipStream_t s);                       // P v, P p at the fine nodes
+
 // Blocks each kernel kind needs for one flow.
 int blocks_for(int kind, int nx, int ny, int K);
 

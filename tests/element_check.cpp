@@ -2,7 +2,9 @@
 // (paper_2008_11520_amd/csrc/element.h):
 //   1. strip_residual equals the sum of element_residual over the strip's
 //      elements (random coarse elements: skewed, stretched, 1e-2 .. 1e2 in size);
-//   2. the tile partition (strip_of, halo_of) covers the tile's 32 x 32
+//   2. element_residual_theta and quad_residual (unstructured meshes) against
+//      element_residual on the same element;
+//   3. the tile partition (strip_of, halo_of) covers the tile's 32 x 32
 //      elements and its halo ring exactly once, and within each of the four
 //      assembly rounds no node receives two contributions.
 // Prints one line per check and exits non-zero on a failure.
@@ -102,6 +104,48 @@ static double theta_form_vs_element_form(std::mt19937 &g, int trials)
     return worst;
 }
 
+// quad_residual (an unstructured mesh's fine element with its own bilinear
+// map and nodal values) against element_residual on the same fine element of
+// a coarse element: node coordinates from the coarse map, nodal v and p from
+// the coarse bilinear fields, random nodal u_prev / dt.
+template <int K>
+static double quad_vs_element(std::mt19937 &g, int trials)
+{
+    constexpr int n = 1 << K;
+    std::uniform_real_distribution<float> U(-1.f, 1.f);
+    double worst = 0;
+    for (int t = 0; t < trials; ++t) {
+        CoarseRec r;
+        float *v = &r.V0x;
+        for (int q = 0; q < 12; ++q) v[q] = U(g) * (q % 4 == 0 ? 2.f : 0.7f);
+        const float sc = std::pow(10.f, 2 * U(g));
+        r.exx = sc * (1.f + 0.3f * U(g)); r.exy = sc * 0.3f * U(g);
+        r.eyx = sc * 0.3f * U(g); r.eyy = sc * (1.f + 0.3f * U(g));
+        r.exyx = sc * 0.2f * U(g); r.exyy = sc * 0.2f * U(g);
+        const float nu = 1e-3f * (1 + 10 * (t % 3)), idt = (t % 4 == 0) ? 0.f : 200.f;
+        const int a = t % n, b = (t / n) % n;
+        float x[4], y[4], vx[4], vy[4], pn[4], wx[4], wy[4];
+        float2 w[4];
+        for (int c = 0; c < 4; ++c) {
+            const float xi = (a + (c & 1)) * (1.0f / n), eta = (b + (c >> 1)) * (1.0f / n);
+            x[c] = r.exx * xi + r.eyx * eta + r.exyx * xi * eta;
+            y[c] = r.exy * xi + r.eyy * eta + r.exyy * xi * eta;
+            vx[c] = (r.V0x + r.V1x * xi) + (r.V2x + r.V3x * xi) * eta;
+            vy[c] = (r.V0y + r.V1y * xi) + (r.V2y + r.V3y * xi) * eta;
+            pn[c] = (r.P0 + r.P1 * xi) + (r.P2 + r.P3 * xi) * eta;
+            w[c] = {U(g) * 300, U(g) * 300};
+            wx[c] = w[c].x; wy[c] = w[c].y;
+        }
+        float Rq[8], Re[8];
+        quad_residual<HostOps>(x, y, vx, vy, pn, wx, wy, nu, idt, Rq);
+        element_residual<K, HostOps>(r, a, b, nu, idt, w[0], w[1], w[2], w[3], Re);
+        float mag = 0;
+        for (float z : Re) mag = std::fmax(mag, std::fabs(z));
+        for (int c = 0; c < 8; ++c) worst = std::fmax(worst, std::fabs(Rq[c] - Re[c]) / mag);
+    }
+    return worst;
+}
+
 template <int SH>
 static bool partition_ok(int K)
 {
@@ -147,7 +191,11 @@ int main()
                  t3 = theta_form_vs_element_form<3>(g, 20000);
     std::printf("theta form (theta = 1, and theta = 1/2 with u = v) vs element form: K=1 %.3g  K=2 %.3g  K=3 %.3g\n",
                 t1, t2, t3);
+    const double q1 = quad_vs_element<1>(g, 20000), q2 = quad_vs_element<2>(g, 20000),
+                 q3 = quad_vs_element<3>(g, 20000);
+    std::printf("unstructured fine element vs element form: K=1 %.3g  K=2 %.3g  K=3 %.3g\n", q1, q2, q3);
     const bool p1 = partition_ok<2>(1), p2 = partition_ok<4>(2), p3 = partition_ok<4>(3);
     std::printf("tile partition: K=1 %s  K=2 %s  K=3 %s\n", p1 ? "ok" : "FAIL", p2 ? "ok" : "FAIL", p3 ? "ok" : "FAIL");
-    return (e1 < 1e-5 && e2 < 1e-5 && e3 < 1e-5 && t1 < 1e-5 && t2 < 1e-5 && t3 < 1e-5 && p1 && p2 && p3) ? 0 : 1;
+    return (e1 < 1e-5 && e2 < 1e-5 && e3 < 1e-5 && t1 < 1e-5 && t2 < 1e-5 && t3 < 1e-5 && q1 < 1e-5 && q2 < 1e-5 &&
+            q3 < 1e-5 && p1 && p2 && p3) ? 0 : 1;
 }
