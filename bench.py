@@ -239,6 +239,51 @@ def run_gpu_batch(wl, precision, steps, warmup):
     return dict(ms_total=ms, wall_s=wall, P=P, stage_ms=None, stage_n=None, finite=ok)
 
 
+def run_umesh_leg(precision, steps, warmup, m=110, K=2, H=64, Hm=64):
+    """The step on an unstructured mesh: the channel around a circular
+    obstacle (O-grid ring with curved edges, five-element vertices), m
+    elements per box side (m = 110: 272 470 patches, about the channel
+    workload's 262 144), K = 2, H = 64, MLP 64-64-50.  Timed like the
+    single-flow legs; per-stage HIP events for the stage breakdown."""
+    import torch
+    import paper_2008_11520_amd as pam
+    from paper_2008_11520_amd import synth
+    flow = synth.cylinder_channel_flow(m)
+    w = synth.xavier_weights(K, H, Hm, 1234)
+    g = pam.UDnnMG(K, H, Hm, flow.dt, 1e-3, flow.mesh, w, precision)
+    vs, ps = [], []
+    for n in range(8):
+        v, p = flow.fields(n)
+        vs.append(torch.from_numpy(v.reshape(-1)).cuda())
+        ps.append(torch.from_numpy(p).cuda())
+    b = torch.empty(2 * g.s["Nc"], dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    for n in range(warmup):
+        g.step(vs[n % 8], ps[n % 8])
+        g.restrict_rhs(b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for n in range(steps):
+        g.step(vs[n % 8], ps[n % 8])
+        g.restrict_rhs(b)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    g.profile_enable(50)
+    for n in range(50):
+        g.step(vs[n % 8], ps[n % 8])
+        g.restrict_rhs(b)
+    torch.cuda.synchronize()
+    stage_ms, stage_n = g.profile_read()
+    ok = bool(torch.isfinite(b).all().item())
+    P = g.s["P"]
+    g.close()
+    return {"workload": "cylinder channel, unstructured: %d elements (%d nodes, %d fine nodes), K=%d H=%d Hm=%d %s"
+                        % (P, g.s["Nc"], g.s["Fn"], K, H, Hm, precision),
+            "patches": P, "ms_per_step": ms, "patch_steps_per_s": P / (ms / 1e3),
+            "stage_us": {STAGES[k]: stage_ms[k] / max(stage_n[k], 1) * 1e3 for k in range(4)}, "finite": ok}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -423,6 +468,7 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-closed-loop", action="store_true")
+    ap.add_argument("--no-umesh", action="store_true", help="skip the unstructured-mesh leg")
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
     ap.add_argument("--serving", default="offered,all", metavar="LIST",
                     help="serving runs after the throughput legs: comma list of offered (20/s), x10, x100, "
@@ -560,6 +606,10 @@ def main():
         out["serving"] = {"workload": "256 requests, Poisson 20/s, channel meshes 32x8..512x128, 50-500 steps, "
                                       "K=2 H=64 bf16, hipGraph",
                           "runs": dict(zip(runs, res))}
+    if not batched and args.precision != "fp8" and not args.no_umesh:
+        print("bench: unstructured mesh leg", file=sys.stderr, flush=True)
+        out["unstructured"] = run_umesh_leg(args.precision, args.steps, args.warmup)
+        print("bench: unstructured %.3f ms/step" % out["unstructured"]["ms_per_step"], file=sys.stderr, flush=True)
     if not args.no_closed_loop:
         out["closed_loop"] = {"note": "coarse Newton solve (host, sparse LU) + fine step (GPU) per time step, "
                                       "against the same Newton solver on level L+K",

@@ -145,7 +145,9 @@ struct UArgs {
     const float *v, *p;              // coarse fields (Nc x 2, Nc)
     const int *corners;              // P x 4
     const int *pmap;                 // P x nf
-    const double *rel;               // P x nf x 2
+    const float *rel;                // P x nf x 2 (FP32: fine coordinates relative to v0)
+    const double *W;                 // P x 4 x nf: hat-weighted mass rows of the patch
+    const double *M4;                // P x 4 x 4: the same applied to P v (corner values)
     const float *feat;               // P x 4
     const unsigned char *mask;       // Fn: Dirichlet nodes
     const int *node_ptr, *node_occ;  // Fn + 1, P nf

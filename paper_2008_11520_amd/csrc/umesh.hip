@@ -12,9 +12,9 @@
 //   (network)  the structured path's kernels on the rows;
 //   k_uaverage one thread per fine node: the mean of the patches' outputs,
 //              masked; the corrected velocity P v + d is the next u_prev;
-//   k_urhs     one thread per patch, FP64: its fine elements' mass products
-//              (1/dt) M (P v + d), weighted by the coarse hats at the nodes,
-//              give the patch's share of b^L at its four corners (R = P^T);
+//   k_urhs     FP64: each patch's share of b^L = R (1/dt) M (P v + d) at its
+//              corners from its hat-weighted mass rows (formed at create from
+//              the fine elements' 2 x 2 Gauss points; R = P^T);
 //   k_ugather  one thread per coarse node: the shares summed in patch order.
 // Sums over shared nodes are gathers in a fixed order: no atomics, bitwise
 // deterministic.  P v at a fine node is the bilinear interpolation, in the
@@ -64,13 +64,13 @@ __global__ __launch_bounds__(kThreads) void k_udefect(UArgs u)
         const int first = *u.first_flag;
         const float idt = first ? 0.0f : u.inv_dt;
         float x[4], y[4], vx[4], vy[4], pn[4], wx[4], wy[4];
-        const double2 *rel = reinterpret_cast<const double2 *>(u.rel) + (size_t)e * nf;
+        const float2 *rel = reinterpret_cast<const float2 *>(u.rel) + (size_t)e * nf;
         const float2 *up = reinterpret_cast<const float2 *>(u.uprev);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const double2 r = rel[ls[k]];
-            x[k] = (float)r.x;
-            y[k] = (float)r.y;
+            const float2 r = rel[ls[k]];
+            x[k] = r.x;
+            y[k] = r.y;
             float N[4];
             corner_hats(n, ls[k], N);
             vx[k] = N[0] * cv[0].x + N[1] * cv[1].x + N[2] * cv[2].x + N[3] * cv[3].x;
@@ -255,81 +255,60 @@ hipError_t launch_uprolong(const UArgs &u, hipStream_t s)
 }
 
 // -------------------------------------------------------- FP64 rhs shares
-// One thread per patch.  For each fine element and Gauss point: det and the
-// corrected velocity (P v from the corner values in FP64, plus d) at the
-// point; node k of the element receives w det N_k u, which the coarse hats
-// at that node carry to the patch's corners.
+// The patch's share of R (1/dt) M_f u at each corner c, u = P v + d, from its
+// hat-weighted mass rows formed at create (static geometry, FP64):
+//   sum_k M4[c][k] v_k + sum_l W[c][l] d_l.
+// A workgroup takes PPB patches; thread (patch, l) reads d at node l and the
+// four rows' entries l (consecutive lanes, consecutive addresses) and leaves
+// the eight products in LDS; thread (patch, corner, component) then sums them
+// over l in order.
 template <int K>
 __global__ __launch_bounds__(kThreads) void k_urhs(UArgs u, const float *dbar)
 {
-    constexpr int n = 1 << K, nf = (n + 1) * (n + 1);
-    const int e = blockIdx.x * kThreads + threadIdx.x;
-    if (e >= u.P) return;
-    constexpr double g0 = 0.21132486540518711775, g1 = 0.78867513459481288225;
-    const int *cn = u.corners + 4 * (size_t)e;
-    const float2 *v2 = reinterpret_cast<const float2 *>(u.v);
-    double cvx[4], cvy[4];
+    constexpr int n = 1 << K, nf = (n + 1) * (n + 1), PPB = kThreads / nf;
+    __shared__ double s_pr[PPB * nf * 8];
+    const int tid = threadIdx.x, pb = tid / nf, l = tid - pb * nf;
+    const int e = blockIdx.x * PPB + pb;
+    if (pb < PPB && e < u.P) {
+        const float2 d = reinterpret_cast<const float2 *>(dbar)[u.pmap[(size_t)e * nf + l]];
+        const double *Wp = u.W + (size_t)e * 4 * nf + l;
+        double *o = s_pr + (pb * nf + l) * 8;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float2 c = v2[cn[k]];
-        cvx[k] = c.x;
-        cvy[k] = c.y;
-    }
-    const double2 *rel = reinterpret_cast<const double2 *>(u.rel) + (size_t)e * nf;
-    const int *pm = u.pmap + (size_t)e * nf;
-    const float2 *db = reinterpret_cast<const float2 *>(dbar);
-    double b[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-#pragma unroll 1
-    for (int el = 0; el < n * n; ++el) {
-        const int a = el % n, bb = el / n, l00 = bb * (n + 1) + a;
-        const int ls[4] = {l00, l00 + 1, l00 + n + 1, l00 + n + 2};
-        double x[4], y[4], ux[4], uy[4], H[4][4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const double2 r = rel[ls[k]];
-            x[k] = r.x;
-            y[k] = r.y;
-            corner_hats(n, ls[k], H[k]);
-            const float2 d = db[pm[ls[k]]];
-            ux[k] = H[k][0] * cvx[0] + H[k][1] * cvx[1] + H[k][2] * cvx[2] + H[k][3] * cvx[3] + (double)d.x;
-            uy[k] = H[k][0] * cvy[0] + H[k][1] * cvy[1] + H[k][2] * cvy[2] + H[k][3] * cvy[3] + (double)d.y;
-        }
-#pragma unroll 1
-        for (int q = 0; q < 4; ++q) {
-            const double s = (q & 1) ? g1 : g0, t = (q >> 1) ? g1 : g0;
-            const double N[4] = {(1 - s) * (1 - t), s * (1 - t), (1 - s) * t, s * t};
-            const double Ns[4] = {-(1 - t), 1 - t, -t, t}, Nt[4] = {-(1 - s), -s, 1 - s, s};
-            double xs = 0, xt = 0, ys = 0, yt = 0, uqx = 0, uqy = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                xs += x[k] * Ns[k]; xt += x[k] * Nt[k];
-                ys += y[k] * Ns[k]; yt += y[k] * Nt[k];
-                uqx += N[k] * ux[k]; uqy += N[k] * uy[k];
-            }
-            const double wd = 0.25 * fabs(xs * yt - xt * ys);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const double mx = wd * N[k] * uqx, my = wd * N[k] * uqy;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    b[c][0] += H[k][c] * mx;
-                    b[c][1] += H[k][c] * my;
-                }
-            }
+        for (int c = 0; c < 4; ++c) {
+            const double w = Wp[c * nf];
+            o[2 * c] = w * (double)d.x;
+            o[2 * c + 1] = w * (double)d.y;
         }
     }
-    double2 *out = reinterpret_cast<double2 *>(u.part) + 4 * (size_t)e;
+    __syncthreads();
+    if (tid >= PPB * 8) return;
+    const int q = tid >> 3, j = tid & 7, c = j >> 1, comp = j & 1;
+    const int eq = blockIdx.x * PPB + q;
+    if (eq >= u.P) return;
+    const int *cn = u.corners + 4 * (size_t)eq;
+    const float *v1 = u.v;
+    const double *M = u.M4 + 16 * (size_t)eq + 4 * c;
+    double acc = 0.0;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) out[c] = make_double2(u.inv_dt64 * b[c][0], u.inv_dt64 * b[c][1]);
+    for (int k = 0; k < 4; ++k) acc += M[k] * (double)v1[2 * cn[k] + comp];
+    const double *pr = s_pr + q * nf * 8 + j;
+    for (int i = 0; i < nf; ++i) acc += pr[8 * i];
+    u.part[8 * (size_t)eq + j] = u.inv_dt64 * acc;
 }
 
 hipError_t launch_urhs(const UArgs &u, const float *dbar, hipStream_t s)
 {
-    dim3 g((u.P + kThreads - 1) / kThreads), b(kThreads);
     switch (u.K) {
-    case 1: hipLaunchKernelGGL(k_urhs<1>, g, b, 0, s, u, dbar); break;
-    case 2: hipLaunchKernelGGL(k_urhs<2>, g, b, 0, s, u, dbar); break;
-    case 3: hipLaunchKernelGGL(k_urhs<3>, g, b, 0, s, u, dbar); break;
+#define DNNMG_URHS(KK)                                                                                \
+    case KK: {                                                                                        \
+        constexpr int ppb = kThreads / (((1 << KK) + 1) * ((1 << KK) + 1));                          \
+        hipLaunchKernelGGL(k_urhs<KK>, dim3((u.P + ppb - 1) / ppb), dim3(kThreads), 0, s, u, dbar); \
+        break;                                                                                        \
+    }
+        DNNMG_URHS(1)
+        DNNMG_URHS(2)
+        DNNMG_URHS(3)
+#undef DNNMG_URHS
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

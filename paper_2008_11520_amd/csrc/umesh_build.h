@@ -20,10 +20,16 @@ struct UMeshHost {
     std::vector<int> pmap;              // ne x nf
     std::vector<double> fxy;            // Fn x 2
     std::vector<double> rel;            // ne x nf x 2, relative to the patch's corner v0
+    std::vector<float> rel32;           // the same in FP32 (the defect's element maps)
     std::vector<unsigned char> mask;    // Fn
     std::vector<int> node_ptr, node_occ;    // Fn + 1, ne nf (patch nf + l, patch order)
     std::vector<int> cnode_ptr, cnode_occ;  // nc + 1, 4 ne (patch 4 + corner)
     std::vector<float> feat;            // ne x 4: hx, hy, hx / hy, area
+    // the patch's mass products weighted by its coarse hats (static geometry):
+    // its share of R M_f u at corner c is sum_l W[c][l] u_l, and for u = P v
+    // inside the patch sum_k M4[c][k] v_k
+    std::vector<double> W;              // ne x 4 x nf
+    std::vector<double> M4;             // ne x 4 x 4
 };
 
 namespace umesh_detail {
@@ -186,6 +192,7 @@ inline std::string build_umesh(int nc, int ne, const double *xy, const int *elem
                 }
             }
     }
+    m.rel32.assign(m.rel.begin(), m.rel.end());
     // Dirichlet mask
     m.mask.assign((size_t)m.Fn, 0);
     std::unordered_map<uint64_t, int> dir;
@@ -225,6 +232,48 @@ inline std::string build_umesh(int nc, int ne, const double *xy, const int *elem
         std::vector<int> at(m.cnode_ptr.begin(), m.cnode_ptr.end() - 1);
         for (int e = 0; e < ne; ++e)
             for (int k = 0; k < 4; ++k) m.cnode_occ[at[elems[4 * e + k]]++] = 4 * e + k;
+    }
+    // hat-weighted mass rows: 2 x 2 Gauss points on every fine element's own
+    // bilinear map; W[c][l_j] += sum_q w |det| N_j(q) sum_k H_c(l_k) N_k(q),
+    // H_c(l) the coarse hat of corner c at patch-local node l
+    m.W.assign((size_t)ne * 4 * nf, 0.0);
+    m.M4.assign((size_t)ne * 16, 0.0);
+    {
+        const double g[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+        auto hat = [&](int c, int l) {
+            const double s = (double)(l % (n + 1)) / n, t = (double)(l / (n + 1)) / n;
+            return c == 0 ? (1 - s) * (1 - t) : c == 1 ? s * (1 - t) : c == 2 ? s * t : (1 - s) * t;
+        };
+        for (int e = 0; e < ne; ++e) {
+            double *We = &m.W[(size_t)e * 4 * nf];
+            for (int b = 0; b < n; ++b)
+                for (int a = 0; a < n; ++a) {
+                    const int l00 = b * (n + 1) + a, ls[4] = {l00, l00 + 1, l00 + n + 1, l00 + n + 2};
+                    for (int q = 0; q < 4; ++q) {
+                        const double s = g[q & 1], t = g[q >> 1];
+                        const double N[4] = {(1 - s) * (1 - t), s * (1 - t), (1 - s) * t, s * t};
+                        const double Ns[4] = {-(1 - t), 1 - t, -t, t}, Nt[4] = {-(1 - s), -s, 1 - s, s};
+                        double xs = 0, xt = 0, ys = 0, yt = 0;
+                        for (int k = 0; k < 4; ++k) {
+                            const double *r = &m.rel[((size_t)e * nf + ls[k]) * 2];
+                            xs += r[0] * Ns[k]; xt += r[0] * Nt[k];
+                            ys += r[1] * Ns[k]; yt += r[1] * Nt[k];
+                        }
+                        const double wd = 0.25 * std::fabs(xs * yt - xt * ys);
+                        for (int c = 0; c < 4; ++c) {
+                            double hq = 0.0;
+                            for (int k = 0; k < 4; ++k) hq += hat(c, ls[k]) * N[k];
+                            for (int j = 0; j < 4; ++j) We[(size_t)c * nf + ls[j]] += wd * N[j] * hq;
+                        }
+                    }
+                }
+            for (int c = 0; c < 4; ++c)
+                for (int k = 0; k < 4; ++k) {
+                    double acc = 0.0;
+                    for (int l = 0; l < nf; ++l) acc += We[(size_t)c * nf + l] * hat(k, l);
+                    m.M4[(size_t)e * 16 + 4 * c + k] = acc;
+                }
+        }
     }
     // patch features from the straight corners
     m.feat.assign(4 * (size_t)ne, 0.0f);
