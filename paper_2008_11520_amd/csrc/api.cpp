@@ -1075,7 +1075,7 @@ static int enqueue_ustep(dnnmg_ctx *c, const UArgs &u, hipStream_t st)
     Profile &pr = c->prof;
     hipEvent_t *ev = (pr.max_steps > 0 && pr.steps < pr.max_steps) ? &pr.ev[4 * pr.steps] : nullptr;
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[0], st));
-    HIP_OR_FAIL(launch_udefect(u, c->um->D, st));
+    HIP_OR_FAIL(launch_udefect(u, nullptr, st));     // contributions; the input rows sum them per node
     HIP_OR_FAIL(launch_uinput(u, st));
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[1], st));
     HIP_OR_FAIL(launch_net(unet_args(c), nullptr, blocks_for(kKindNet, c->um->ne, 1, g.K), c->w->net, st));

@@ -166,7 +166,7 @@ struct UArgs {
     int *nonfinite;                  // non-finite check (or nullptr)
 };
 
-hipError_t launch_udefect(const UArgs &u, float *D_out, hipStream_t s);          // defect at the fine nodes
+hipError_t launch_udefect(const UArgs &u, float *D_out, hipStream_t s);          // contributions, and D_out (if given)
 hipError_t launch_uinput(const UArgs &u, hipStream_t s);                         // network input rows
 hipError_t launch_uaverage(const UArgs &u, hipStream_t s);                       // averaging, state, correction
 hipError_t launch_urhs(const UArgs &u, const float *dbar, hipStream_t s);       // FP64 rhs shares per patch

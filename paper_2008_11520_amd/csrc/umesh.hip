@@ -8,7 +8,8 @@
 //              rounds (elements of one colour share no node);
 //   k_unode    one thread per fine node: the patches' contributions summed in
 //              patch order (node_occ), zero at Dirichlet nodes;
-//   k_uinput   the network input rows [P v, D, hx, hy, aspect, area];
+//   k_uinput   the network input rows [P v, D, hx, hy, aspect, area], D
+//              summed from the contributions as k_unode sums them;
 //   (network)  the structured path's kernels on the rows;
 //   k_uaverage one thread per fine node: the mean of the patches' outputs,
 //              masked; the corrected velocity P v + d is the next u_prev;
@@ -117,12 +118,14 @@ __global__ __launch_bounds__(kThreads) void k_unode(UArgs u, float *D)
     reinterpret_cast<float2 *>(D)[f] = s;
 }
 
+// D == nullptr: the element contributions only (the step: the network input
+// sums them per node itself); else also the defect at the fine nodes.
 template <int K>
 static void launch_udefect_k(const UArgs &u, float *D, hipStream_t s)
 {
     constexpr int n = 1 << K, PPB = kThreads / (n * n);
     hipLaunchKernelGGL(k_udefect<K>, dim3((u.P + PPB - 1) / PPB), dim3(kThreads), 0, s, u);
-    hipLaunchKernelGGL(k_unode, dim3((u.Fn + kThreads - 1) / kThreads), dim3(kThreads), 0, s, u, D);
+    if (D) hipLaunchKernelGGL(k_unode, dim3((u.Fn + kThreads - 1) / kThreads), dim3(kThreads), 0, s, u, D);
 }
 
 hipError_t launch_udefect(const UArgs &u, float *D, hipStream_t s)
@@ -137,8 +140,25 @@ hipError_t launch_udefect(const UArgs &u, float *D, hipStream_t s)
 }
 
 // ------------------------------------------------------- network input rows
-// One thread per (patch, local node) writes P v and D at the node; one per
-// patch writes its four features.
+// One thread per (patch, local node) writes P v and D at the node (pairs as
+// one store); one per patch writes its four features.  D comes from the
+// patches' element contributions directly: the node's contributions summed
+// over its gather list in patch order, as k_unode sums them (the same value
+// bit for bit), zero at Dirichlet nodes.
+template <typename XT>
+__device__ inline void store_pair(XT *o, float a, float b)
+{
+    if constexpr (sizeof(XT) == 4) {
+        *reinterpret_cast<float2 *>(o) = make_float2(a, b);
+    } else {
+        typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+        b2 v;
+        v[0] = (__bf16)a;
+        v[1] = (__bf16)b;
+        *reinterpret_cast<b2 *>(o) = v;
+    }
+}
+
 template <int K, typename XT>
 __global__ __launch_bounds__(kThreads) void k_uinput(UArgs u)
 {
@@ -149,7 +169,8 @@ __global__ __launch_bounds__(kThreads) void k_uinput(UArgs u)
     XT *x = reinterpret_cast<XT *>(u.X) + (size_t)e * u.nin;
     if (l == nf) {
         const float4 ft = reinterpret_cast<const float4 *>(u.feat)[e];
-        x[4 * nf] = (XT)ft.x; x[4 * nf + 1] = (XT)ft.y; x[4 * nf + 2] = (XT)ft.z; x[4 * nf + 3] = (XT)ft.w;
+        store_pair(x + 4 * nf, ft.x, ft.y);
+        store_pair(x + 4 * nf + 2, ft.z, ft.w);
         return;
     }
     const int *cn = u.corners + 4 * (size_t)e;
@@ -157,11 +178,25 @@ __global__ __launch_bounds__(kThreads) void k_uinput(UArgs u)
     float N[4];
     corner_hats(n, l, N);
     const float2 c0 = v2[cn[0]], c1 = v2[cn[1]], c2 = v2[cn[2]], c3 = v2[cn[3]];
-    const float2 d = reinterpret_cast<const float2 *>(u.D)[u.pmap[(size_t)e * nf + l]];
-    x[2 * l] = (XT)(N[0] * c0.x + N[1] * c1.x + N[2] * c2.x + N[3] * c3.x);
-    x[2 * l + 1] = (XT)(N[0] * c0.y + N[1] * c1.y + N[2] * c2.y + N[3] * c3.y);
-    x[2 * nf + 2 * l] = (XT)d.x;
-    x[2 * nf + 2 * l + 1] = (XT)d.y;
+    const float2 *dl = reinterpret_cast<const float2 *>(u.dloc);
+    const int a = l % (n + 1), b = l / (n + 1);
+    float2 d;
+    if (a > 0 && a < n && b > 0 && b < n) {
+        // a node inside the patch: this patch alone holds it, no Dirichlet side
+        d = dl[(size_t)e * nf + l];
+    } else {
+        const int f = u.pmap[(size_t)e * nf + l];
+        d = make_float2(0.f, 0.f);
+        for (int k = u.node_ptr[f]; k < u.node_ptr[f + 1]; ++k) {
+            const float2 q = dl[u.node_occ[k]];
+            d.x += q.x;
+            d.y += q.y;
+        }
+        if (u.mask[f]) d = make_float2(0.f, 0.f);
+    }
+    store_pair(x + 2 * l, N[0] * c0.x + N[1] * c1.x + N[2] * c2.x + N[3] * c3.x,
+               N[0] * c0.y + N[1] * c1.y + N[2] * c2.y + N[3] * c3.y);
+    store_pair(x + 2 * nf + 2 * l, d.x, d.y);
 }
 
 hipError_t launch_uinput(const UArgs &u, hipStream_t s)
