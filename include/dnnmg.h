@@ -70,10 +70,17 @@ enum { DNNMG_FP32 = 0, DNNMG_BF16 = 1, DNNMG_FP8_E4M3 = 2 };
 
 /* Configuration flags.  DNNMG_F_UNFUSED: where the library would run the
  * defect, the network input, the GRU and the MLP as one launch (K = 2, BF16
- * operands, H = 64, Hm 0 or 64; the network input then stays on chip), run
- * them as separate launches through an HBM buffer instead.  Both forms do
- * the same arithmetic in the same order, so their results are bitwise equal. */
+ * operands, H = 64, Hm 0 or 64; the network input then stays on chip, and
+ * the launch also averages the duplicate outputs at every fine node inside
+ * its tile, so the per-patch outputs stay on chip too), run them as separate
+ * launches through HBM buffers instead.  Both forms do the same arithmetic in
+ * the same order, so their results are bitwise equal. */
 enum { DNNMG_F_UNFUSED = 1 };
+
+/* DNNMG_F_PATCH_OUTPUTS: the one-launch step also stores the per-patch
+ * network outputs for dnnmg_patch_output (the other forms always store them:
+ * their averaging reads them back).  Results are the same with or without it. */
+enum { DNNMG_F_PATCH_OUTPUTS = 32 };
 
 /* DNNMG_F_NANCHECK: the step's kernels also record whether any value of the
  * averaged correction d (bit DNNMG_NONFINITE_CORRECTION) or of the restricted
@@ -144,7 +151,7 @@ typedef struct {
     unsigned dirichlet;  /* DNNMG_DIR_* bits                                         */
     unsigned flags;      /* 0, or DNNMG_F_UNFUSED | DNNMG_F_NANCHECK |
                             DNNMG_F_CRANK_NICOLSON | DNNMG_F_PAPER_NET |
-                            DNNMG_F_GRU_RESET_AFTER                                  */
+                            DNNMG_F_GRU_RESET_AFTER | DNNMG_F_PATCH_OUTPUTS          */
 } dnnmg_config;
 
 /* Network sizes: N_in = 4 (n+1)^2 + 4 (prolongated velocity and defect at the
@@ -189,7 +196,9 @@ int dnnmg_step(dnnmg_ctx *ctx, const float *v_coarse_dev, const float *p_coarse_
 
 /* Restricted right-hand side of the most recent step (Alg. 2, line 9):
  * b_coarse_dev: device, (ny+1)(nx+1) x 2 doubles,
- *   b^L = P^T (1/dt) M_f (P v + d), accumulated in FP64.
+ *   b^L = P^T (1/dt) M_f (P v + d), accumulated in FP64 from the stored FP32
+ *   corrected velocity P v + d (the state the next step reads; implicit
+ *   Euler), or from P v and d (Crank-Nicolson).
  * DNNMG_ESTATE before the first step.  May be called more than once. */
 int dnnmg_restrict_rhs(dnnmg_ctx *ctx, double *b_coarse_dev, void *stream);
 
@@ -385,7 +394,8 @@ int dnnmg_set_state(dnnmg_ctx *ctx, const float *h_in_dev, const float *uprev_in
 int dnnmg_nonfinite(dnnmg_ctx *ctx, int clear, int *flags_out, void *stream);
 
 /* Per-patch network output of the most recent step, before averaging:
- * d_out P x N_out FP32.  DNNMG_ESTATE before the first step. */
+ * d_out P x N_out FP32.  DNNMG_ESTATE before the first step, and after a
+ * one-launch step of a context created without DNNMG_F_PATCH_OUTPUTS. */
 int dnnmg_patch_output(dnnmg_ctx *ctx, float *d_out_dev, void *stream);
 
 long long dnnmg_step_count(const dnnmg_ctx *ctx);

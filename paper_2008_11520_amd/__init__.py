@@ -24,6 +24,7 @@ DNNMG_F_NANCHECK = 2
 DNNMG_F_CRANK_NICOLSON = 4
 DNNMG_F_PAPER_NET = 8
 DNNMG_F_GRU_RESET_AFTER = 16
+DNNMG_F_PATCH_OUTPUTS = 32
 DNNMG_NONFINITE_CORRECTION, DNNMG_NONFINITE_RHS = 1, 2
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
 

@@ -19,6 +19,7 @@
 
 #include "arena.h"
 #include "dnnmg.h"
+#include "frame.h"
 #include "internal.h"
 #include "umesh_build.h"
 
@@ -94,7 +95,7 @@ int check_config(const dnnmg_config *c)
         return fail(DNNMG_EINVAL, "precision %d unknown", c->precision);
     if (c->dirichlet > 15u) return fail(DNNMG_EINVAL, "dirichlet flags 0x%x out of range", c->dirichlet);
     if ((c->flags & ~(unsigned)(DNNMG_F_UNFUSED | DNNMG_F_NANCHECK | DNNMG_F_CRANK_NICOLSON | DNNMG_F_PAPER_NET |
-                                DNNMG_F_GRU_RESET_AFTER)) != 0u)
+                                DNNMG_F_GRU_RESET_AFTER | DNNMG_F_PATCH_OUTPUTS)) != 0u)
         return fail(DNNMG_EINVAL, "unknown flags 0x%x", c->flags);
     if ((c->flags & (DNNMG_F_PAPER_NET | DNNMG_F_GRU_RESET_AFTER)) && c->precision == DNNMG_FP8_E4M3)
         return fail(DNNMG_EUNSUPPORTED, "DNNMG_F_PAPER_NET and DNNMG_F_GRU_RESET_AFTER run FP32 or BF16 operands");
@@ -120,10 +121,21 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Device layout of one context's workspace.
 struct Layout {
-    size_t geo, geo64, map64, geo12, feat, h, uprev, X, sx, dpatch, part, part2, cxy, flag, bad, nonfinite, total;
+    size_t geo, geo64, map64, geo12, feat, h, uprev, X, sx, dpatch, frame, part, part2, cxy, flag, bad, nonfinite,
+        total;
+    size_t frame_bytes;
 };
 
-Layout layout_of(const dnnmg_config &c)
+// Whether a structured context's single-flow step runs as one launch
+// (defect, network input, GRU and MLP; then the duplicate averaging of the
+// tile's inner nodes too, and the tile frame goes to the rhs kernel).
+bool one_launch(const dnnmg_config &c)
+{
+    return c.K == 2 && c.H == 64 && (c.Hm == 0 || c.Hm == 64) && c.precision == DNNMG_BF16 &&
+           !(c.flags & (DNNMG_F_UNFUSED | DNNMG_F_CRANK_NICOLSON | DNNMG_F_PAPER_NET | DNNMG_F_GRU_RESET_AFTER));
+}
+
+Layout layout_of(const dnnmg_config &c, bool structured = true)
 {
     Sizes s = sizes_of(c);
     Layout L;
@@ -144,6 +156,12 @@ Layout layout_of(const dnnmg_config &c)
         L.sx = L.X;
     }
     L.dpatch = take(sizeof(float) * (size_t)s.P * s.nout);
+    {
+        typedef TileFrame<2> FR;
+        const size_t tiles = (size_t)((c.nx + FR::TP - 1) / FR::TP) * ((c.ny + FR::TP - 1) / FR::TP);
+        L.frame_bytes = structured && one_launch(c) ? sizeof(float) * 2 * FR::SIZE * tiles : 0;
+        L.frame = take(L.frame_bytes);
+    }
     L.part = take(sizeof(double) * 8 * (size_t)s.P);
     L.part2 = take(sizeof(double) * 8 * (size_t)s.P);
     L.cxy = take(sizeof(double) * 2 * (size_t)s.Nc);
@@ -268,6 +286,7 @@ struct dnnmg_ctx {
     unsigned char *ws = nullptr;
     Weights *w = nullptr;
     long long steps = 0;
+    bool dpatch_kept = true;        // the last step stored its per-patch outputs
     int device = 0;
     dnnmg_arena *arena = nullptr;   // the workspace is a block of this arena (not hipMalloc'd)
     UMeshDev *um = nullptr;         // unstructured mesh (dnnmg_create_umesh), else structured
@@ -282,6 +301,7 @@ struct dnnmg_ctx {
     float *X() const { return (float *)(ws + L.X); }
     float *sx() const { return cfg.precision == DNNMG_FP8_E4M3 ? (float *)(ws + L.sx) : nullptr; }
     float *dpatch() const { return (float *)(ws + L.dpatch); }
+    float *frame() const { return L.frame_bytes ? (float *)(ws + L.frame) : nullptr; }
     double *part() const { return (double *)(ws + L.part); }
     int *first_flag() const { return (int *)(ws + L.flag); }
     RhsTables tables() const { return w->tab; }
@@ -827,8 +847,9 @@ extern "C" int dnnmg_create_umesh(const dnnmg_config *cfg, const dnnmg_umesh *me
     g.dirichlet = 0;
     int rc = check_config(&g);
     if (rc) return rc;
-    if (g.flags & ~(unsigned)(DNNMG_F_NANCHECK | DNNMG_F_UNFUSED | DNNMG_F_GRU_RESET_AFTER))
-        return fail(DNNMG_EUNSUPPORTED, "unstructured meshes take DNNMG_F_NANCHECK and DNNMG_F_GRU_RESET_AFTER only");
+    if (g.flags & ~(unsigned)(DNNMG_F_NANCHECK | DNNMG_F_UNFUSED | DNNMG_F_GRU_RESET_AFTER | DNNMG_F_PATCH_OUTPUTS))
+        return fail(DNNMG_EUNSUPPORTED,
+                    "unstructured meshes take DNNMG_F_NANCHECK, DNNMG_F_GRU_RESET_AFTER and DNNMG_F_PATCH_OUTPUTS only");
     if (g.precision == DNNMG_FP8_E4M3) return fail(DNNMG_EUNSUPPORTED, "unstructured meshes run FP32 or BF16 operands");
     if (!weights) return fail(DNNMG_EINVAL, "weights_host is NULL");
     if (nw != weight_count(g)) return fail(DNNMG_EINVAL, "n_weights = %zu, expected %zu", nw, weight_count(g));
@@ -844,7 +865,7 @@ extern "C" int dnnmg_create_umesh(const dnnmg_config *cfg, const dnnmg_umesh *me
     c->s = sizes_of(g);
     c->s.Fn = m.Fn;
     c->s.Nc = m.nc;
-    c->L = layout_of(g);
+    c->L = layout_of(g, false);
     (void)hipGetDevice(&c->device);
     UMeshDev *d = new UMeshDev();
     d->nc = m.nc; d->ne = m.ne; d->E = m.E; d->Fn = m.Fn;
@@ -1095,9 +1116,14 @@ static int enqueue_step(dnnmg_ctx *c, const FlowArgs &f, hipStream_t st)
     Profile &pr = c->prof;
     hipEvent_t *ev = (pr.max_steps > 0 && pr.steps < pr.max_steps) ? &pr.ev[4 * pr.steps] : nullptr;
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[0], st));
+    FlowArgs fs = f;
     if (fused_step(c->w->net) && !(g.flags & (DNNMG_F_UNFUSED | DNNMG_F_CRANK_NICOLSON))) {
-        // defect, network input, GRU and MLP in one launch (stage 1 then times nothing)
-        HIP_OR_FAIL(launch_defect_net(f, nullptr, blocks_for(kKindDefect, g.nx, g.ny, g.K), c->w->net, st));
+        // defect, network input, GRU, MLP and the averaging inside the tiles in
+        // one launch (stage 1 then times nothing); the rhs completes the frame
+        if (!c->frame()) return fail(DNNMG_EINVAL, "internal: one-launch step without a tile frame");
+        fs.frame = c->frame();
+        fs.keep_dpatch = (g.flags & DNNMG_F_PATCH_OUTPUTS) ? 1 : 0;
+        HIP_OR_FAIL(launch_defect_net(fs, nullptr, blocks_for(kKindDefect, g.nx, g.ny, g.K), c->w->net, st));
         if (ev) HIP_OR_FAIL(hipEventRecord(ev[1], st));
     } else {
         HIP_OR_FAIL(launch_defect(f, nullptr, blocks_for(kKindDefect, g.nx, g.ny, g.K), g.K, f.xfmt, st));
@@ -1105,7 +1131,8 @@ static int enqueue_step(dnnmg_ctx *c, const FlowArgs &f, hipStream_t st)
         HIP_OR_FAIL(launch_net(f, nullptr, blocks_for(kKindNet, g.nx, g.ny, g.K), c->w->net, st));
     }
     if (ev) HIP_OR_FAIL(hipEventRecord(ev[2], st));
-    HIP_OR_FAIL(launch_rhs(f, nullptr, blocks_for(kKindRhs, g.nx, g.ny, g.K), g.K, c->tables(), 1, st));
+    HIP_OR_FAIL(launch_rhs(fs, nullptr, blocks_for(kKindRhs, g.nx, g.ny, g.K), g.K, c->tables(), 1, st));
+    c->dpatch_kept = !fs.frame || fs.keep_dpatch;
     if (ev) {
         HIP_OR_FAIL(hipEventRecord(ev[3], st));
         pr.steps++;
@@ -1420,6 +1447,9 @@ extern "C" int dnnmg_patch_output(dnnmg_ctx *ctx, float *d, void *stream)
     if (rc) return rc;
     if (!d) return fail(DNNMG_EINVAL, "d_out_dev is NULL");
     if (ctx->steps == 0) return fail(DNNMG_ESTATE, "no step has been taken yet");
+    if (!ctx->dpatch_kept)
+        return fail(DNNMG_ESTATE, "the last step kept no per-patch outputs (one-launch step: create the context "
+                                  "with DNNMG_F_PATCH_OUTPUTS)");
     HIP_OR_FAIL(hipMemcpyAsync(d, ctx->dpatch(), sizeof(float) * (size_t)ctx->s.P * ctx->s.nout,
                                hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return DNNMG_OK;

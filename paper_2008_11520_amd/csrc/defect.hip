@@ -19,6 +19,7 @@
 
 #include "device.h"
 #include "element.h"
+#include "frame.h"
 #include "fp8.h"
 #include "internal.h"
 
@@ -172,9 +173,10 @@ int blocks_for(int kind, int nx, int ny, int K)
 constexpr int kFusedLDA = 104 + 64 + 16;       // [x | h | 8 zeros] rows (168 + 8 values), padded so that 16 rows of a fragment read fall in distinct LDS banks
 constexpr int kFusedLDH = 64 + 8;
 
-template <int HM>
+template <int HM, bool FRAME>
 __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int tid, const NetArgs &net,
-                                          __bf16 *sA, __bf16 *sR, __bf16 *sHp, __bf16 *sAm)
+                                          __bf16 *sA, __bf16 *sR, __bf16 *sHp, __bf16 *sAm, float *s_of,
+                                          float2 *s_vc)
 {
     constexpr int nin = 104, nout = 50, H = 64, KC = 32, KQ = 8, KC1 = 6, TP = 8, RT = 4, HT = 4;
     constexpr int LDA = kFusedLDA, LDH = kFusedLDH;
@@ -198,6 +200,16 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
     for (int q = 0; q < RT; ++q) {
         const int r = 16 * q + li;
         hp[q] = valid(r) ? *reinterpret_cast<const f4 *>(f.h + patch(r) * H + ucol) : f4{0.f, 0.f, 0.f, 0.f};
+    }
+    // corner velocities of the tile's patches, for the averaging after the
+    // network when the outputs stay in LDS (f.frame); loaded on every launch,
+    // clamped into the mesh, and stored once the input-only chunks are issued
+    constexpr int SVF = TP + 1;
+    float2 vc = make_float2(0.f, 0.f);
+    if constexpr (FRAME) {
+        const int t = min(tid, SVF * SVF - 1);
+        const int ci = min(t % SVF, nx - tx * TP), cj = min(t / SVF, ny - ty * TP);
+        vc = reinterpret_cast<const float2 *>(f.v)[(size_t)(ty * TP + cj) * (nx + 1) + tx * TP + ci];
     }
     // zeros after [x | h]: the lanes of the last k-chunk that lie beyond it
     // read these (the zero is formed from tile_thread(), so that it is not
@@ -239,6 +251,7 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
         hb[0] = (__bf16)hp[q].x; hb[1] = (__bf16)hp[q].y; hb[2] = (__bf16)hp[q].z; hb[3] = (__bf16)hp[q].w;
         *reinterpret_cast<bf4 *>(&sA[(16 * q + li) * LDA + nin + ucol]) = hb;
     }
+    if (FRAME && f.frame && tid < SVF * SVF) s_vc[tid] = vc;
     __syncthreads();
 #pragma unroll 1
     for (int kc = KX; kc < KC1 - 1; ++kc) chunk(kc, false, false);
@@ -311,20 +324,139 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
 #pragma unroll
         for (int kc = 0; kc < 2; ++kc) wo[kc] = B3[(ht * 2 + kc) * 64 + lane];
     }
+    f4 acc[RT];
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
         const int r = 16 * q + li;
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc[q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kc = 0; kc < 2; ++kc)
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wo[kc], *reinterpret_cast<const bf8 *>(&src[r * LDH + kc * KC + lq * KQ]), acc, 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wo[kc], *reinterpret_cast<const bf8 *>(&src[r * LDH + kc * KC + lq * KQ]), acc[q], 0, 0, 0);
+    }
+    // outputs to LDS (rows of nout floats) for the averaging in the tile
+    // (f.frame), and/or to the per-patch outputs.  Without the MLP hidden
+    // layer the products above read h' from the bytes the LDS rows take.
+    const bool frame = FRAME && f.frame != nullptr;
+    if constexpr (HM == 0) {
+        if (frame) __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        const int r = 16 * q + li;
         // nout is even: the pairs (ucol, ucol+1), (ucol+2, ucol+3) are inside or outside together
-        if (valid(r)) {
+        if (frame) {
+            float *o = s_of + r * nout + ucol;
+            if (ucol < nout) *reinterpret_cast<float2 *>(o) = make_float2(acc[q][0], acc[q][1]);
+            if (ucol + 2 < nout) *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[q][2], acc[q][3]);
+        }
+        if ((!frame || f.keep_dpatch) && valid(r)) {
             float *o = f.dpatch + patch(r) * nout + ucol;
-            if (ucol < nout) *reinterpret_cast<float2 *>(o) = make_float2(acc[0], acc[1]);
-            if (ucol + 2 < nout) *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[2], acc[3]);
+            if (ucol < nout) *reinterpret_cast<float2 *>(o) = make_float2(acc[q][0], acc[q][1]);
+            if (ucol + 2 < nout) *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[q][2], acc[q][3]);
         }
     }
+}
+
+// Duplicate averaging (Sec. 4.2) inside the one-launch step, with the tile's
+// outputs in LDS (rows of 2 nf floats, s_o) and its patches' corner
+// velocities (s_vc, (TP+1)^2): every node inside the tile's boundary lines has
+// all its patches here.  Deep nodes get the corrected velocity P v + d in the
+// state (and d in the caller's output); inner frame nodes hand over d, the
+// tile's sides hand over their outputs (frame.h) for the rhs kernel to
+// complete.  The sums, the mask and P v + d are formed as the rhs kernel forms
+// them, so the state and outputs match the separate-launch step bit for bit.
+__device__ __forceinline__ void fused_average(const FlowArgs &f, int tx, int ty, int tid, const float2 *s_o,
+                                              const float2 *s_vc)
+{
+    constexpr int K = 2, n = 1 << K, nf = (n + 1) * (n + 1), TP = kTileFine / n, SVF = TP + 1;
+    constexpr float inv_n = 1.0f / n;
+    typedef TileFrame<K> FR;
+    static_assert(TP * TP * n == kThreads && FR::TP == TP, "one node row of one patch per thread");
+    const int nx = f.nx, ny = f.ny, NX = nx * n, NY = ny * n;
+    const int pi0 = tx * TP, pj0 = ty * TP, I0 = pi0 * n, J0 = pj0 * n;
+    const int tiles_x = (nx + TP - 1) / TP;
+    const int up = f.upitch;
+    const unsigned dir = f.dirichlet;
+    float2 *const fr = reinterpret_cast<float2 *>(f.frame) + (size_t)(ty * tiles_x + tx) * FR::SIZE;
+    float2 *const ut = reinterpret_cast<float2 *>(f.uprev) + (size_t)J0 * up + I0;
+    float2 *const dout = f.dbar_out ? reinterpret_cast<float2 *>(f.dbar_out) + (size_t)J0 * (NX + 1) + I0 : nullptr;
+    bool nonfin = false;
+    // the sides' outputs
+    for (int s = tid; s < 4 * FR::SIDE; s += kThreads) {
+        int pa, pb, a, b;
+        FR::side_source(s, pa, pb, a, b);
+        if (pi0 + pa < nx && pj0 + pb < ny) fr[s] = s_o[(pb * TP + pa) * nf + b * (n + 1) + a];
+    }
+    // a completed node: inner frame nodes hand over d, deep nodes store u
+    auto finish = [&](int li, int lj, float2 d, float px, float py) {
+        if (frame_kind(li, lj) == kFrameInner) {
+            fr[FR::inner_slot(li, lj)] = d;
+        } else {
+            ut[lj * up + li] = make_float2(px + d.x, py + d.y);
+            if (dout) dout[lj * (NX + 1) + li] = d;
+        }
+    };
+    // the nodes (a, b), a, b < n, of the tile's patches, one node row of one
+    // patch per thread (such a node is masked only on the sides I = 0 and
+    // J = 0, which are boundary lines)
+    {
+        const int pl = tid % (TP * TP), b = tid / (TP * TP);
+        const int pa = pl % TP, pb = pl / TP, pi = pi0 + pa, pj = pj0 + pb;
+        const int lj = pb * n + b;
+        if (pi < nx && pj < ny && lj > 0) {
+            const bool low = b == 0 && pj > 0;
+            const int c = pb * SVF + pa;
+            const float2 v00 = s_vc[c], v10 = s_vc[c + 1], v01 = s_vc[c + SVF], v11 = s_vc[c + SVF + 1];
+            const PvRow row = pv_row(v00.x, v00.y, v10.x, v10.y, v01.x, v01.y, v11.x, v11.y, b * inv_n);
+#pragma unroll
+            for (int a = 0; a < n; ++a) {
+                const int li = pa * n + a;
+                if (li == 0) continue;
+                const bool lft = a == 0 && pi > 0;
+                float2 acc = make_float2(0.f, 0.f);
+                if (lft && low) { const float2 q = s_o[(pl - TP - 1) * nf + n * (n + 1) + n]; acc.x += q.x; acc.y += q.y; }
+                if (low) { const float2 q = s_o[(pl - TP) * nf + n * (n + 1) + a]; acc.x += q.x; acc.y += q.y; }
+                if (lft) { const float2 q = s_o[(pl - 1) * nf + b * (n + 1) + n]; acc.x += q.x; acc.y += q.y; }
+                { const float2 q = s_o[pl * nf + b * (n + 1) + a]; acc.x += q.x; acc.y += q.y; }
+                const float inv = (lft && low) ? 0.25f : ((lft || low) ? 0.5f : 1.0f);
+                const float2 d = make_float2(acc.x * inv, acc.y * inv);
+                nonfin |= !(__builtin_isfinite(d.x) && __builtin_isfinite(d.y));
+                float px, py;
+                pv_at(row, a * inv_n, px, py);
+                finish(li, lj, d, px, py);
+            }
+        }
+    }
+    // the mesh end inside a ragged tile: its last node column li = le and row
+    // lj = me (on a full tile these are boundary lines)
+    const int le = min(TP, nx - pi0) * n, me = min(TP, ny - pj0) * n;
+    if (tid < le + me + 1) {
+        const int li = tid <= me ? le : tid - me - 1, lj = tid <= me ? tid : me;
+        if (frame_kind(li, lj) != kFrameEdge) {
+            const int I = I0 + li, J = J0 + lj;
+            const int pI = min(I >> K, nx - 1), pJ = min(J >> K, ny - 1);
+            const int a = I - pI * n, b = J - pJ * n;
+            const bool lft = a == 0 && pI > 0, low = b == 0 && pJ > 0;
+            const int hb = (pJ - pj0) * TP + (pI - pi0);
+            float2 acc = make_float2(0.f, 0.f);
+            if (lft && low) { const float2 q = s_o[(hb - TP - 1) * nf + n * (n + 1) + n]; acc.x += q.x; acc.y += q.y; }
+            if (low) { const float2 q = s_o[(hb - TP) * nf + n * (n + 1) + a]; acc.x += q.x; acc.y += q.y; }
+            if (lft) { const float2 q = s_o[(hb - 1) * nf + b * (n + 1) + n]; acc.x += q.x; acc.y += q.y; }
+            { const float2 q = s_o[hb * nf + b * (n + 1) + a]; acc.x += q.x; acc.y += q.y; }
+            const float inv = (lft && low) ? 0.25f : ((lft || low) ? 0.5f : 1.0f);
+            float2 d = make_float2(acc.x * inv, acc.y * inv);
+            if (((dir & 1u) && I == 0) || ((dir & 2u) && I == NX) || ((dir & 4u) && J == 0) || ((dir & 8u) && J == NY))
+                d = make_float2(0.f, 0.f);
+            nonfin |= !(__builtin_isfinite(d.x) && __builtin_isfinite(d.y));
+            const int c = (pJ - pj0) * SVF + (pI - pi0);
+            const float2 v00 = s_vc[c], v10 = s_vc[c + 1], v01 = s_vc[c + SVF], v11 = s_vc[c + SVF + 1];
+            const PvRow row = pv_row(v00.x, v00.y, v10.x, v10.y, v01.x, v01.y, v11.x, v11.y, b * inv_n);
+            float px, py;
+            pv_at(row, a * inv_n, px, py);
+            finish(li, lj, d, px, py);
+        }
+    }
+    if (nonfin && f.nonfinite) atomicOr(f.nonfinite, 1);
 }
 
 // FUSED (K = 2, BF16 input): the network input stays in LDS and the tile's
@@ -737,7 +869,17 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
             // the network input rows stay in LDS; r*h, h' reuse them after phase
             // 1 and the MLP hidden layer reuses the node accumulators
             __bf16 *sA = reinterpret_cast<__bf16 *>(s_wx);
-            gru_fused<HM>(f, tx, ty, tid, *net, sA, sA, sA + 64 * kFusedLDH, reinterpret_cast<__bf16 *>(s_acc));
+            // (the outputs' LDS rows take the input rows' bytes; the corner
+            // velocities the coarse records')
+            float2 *const s_vc = reinterpret_cast<float2 *>(s_c);
+            // (batched launches store the per-patch outputs: no frame code)
+            constexpr bool FRAME = !OPAQUE_TID;
+            gru_fused<HM, FRAME>(f, tx, ty, tid, *net, sA, sA, sA + 64 * kFusedLDH,
+                                 reinterpret_cast<__bf16 *>(s_acc), reinterpret_cast<float *>(s_wx), s_vc);
+            if (FRAME && f.frame) {
+                __syncthreads();
+                fused_average(f, tx, ty, tid, reinterpret_cast<const float2 *>(s_wx), s_vc);
+            }
             return;
         }
         constexpr int CPR = TP * nin * sizeof(XT) / 16;   // 16-byte pieces per tile row of patches

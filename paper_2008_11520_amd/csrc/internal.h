@@ -46,6 +46,11 @@ struct FlowArgs {
     float theta = 1.0f;
     double nu64 = 0.0;
     const double *map64 = nullptr;   // per coarse element: ex, ey, exy (x, y each), 2 pad
+    // one-launch K = 2 step (single flow): the tile frame it hands to the rhs
+    // (frame.h; nullptr: it stores the per-patch outputs instead), and
+    // whether it also stores them (keep_dpatch)
+    float *frame = nullptr;
+    int keep_dpatch = 1;
 };
 
 // Shared network description.

@@ -22,6 +22,7 @@
 // definition up to FP64 rounding.  A second kernel sums the four patch
 // contributions at each coarse node in a fixed order (no atomics).
 #include "device.h"
+#include "frame.h"
 #include "internal.h"
 
 namespace dnnmg {
@@ -64,8 +65,9 @@ __device__ __forceinline__ void transport_corners(const FlowArgs &f, int tid, in
         if (it < NI && pi0 + pa < nx && pj0 + pb < ny) {
             const double *m = f.map64 + 8 * ((size_t)(pj0 + pb) * nx + pi0 + pa);
             const double exx = m[0], exy = m[1], eyx = m[2], eyy = m[3], twx = m[4], twy = m[5];
-            const int c = pb * (TP + 1) + pa;
-            const float2 v00 = s_v[c], v10 = s_v[c + 1], v01 = s_v[c + TP + 1], v11 = s_v[c + TP + 2];
+            constexpr int SV = TP + 2;     // the rhs tile's corner layout
+            const int c = pb * SV + pa;
+            const float2 v00 = s_v[c], v10 = s_v[c + 1], v01 = s_v[c + SV], v11 = s_v[c + SV + 1];
             // u = P v + d at fine node (a, bb) of the patch, FP64
             auto unode = [&](int a, int bb, double &ux, double &uy) {
                 const double xi = a * inv_n, eta = bb * inv_n;
@@ -132,25 +134,38 @@ __device__ __forceinline__ void transport_corners(const FlowArgs &f, int tid, in
 }
 
 // One workgroup per tile of kRhsFine x kRhsFine fine elements (TP x TP patches).
-// from_patches = 1: average f.dpatch and store the corrected velocity (the
-// step); 0: take the correction from f.dbar_in (stage, state untouched).
+// FROM_PATCHES = 1: average f.dpatch and store the corrected velocity (the
+// step); 2: the same step after the one-launch K = 2 kernel, which has
+// averaged every node inside the tile's boundary lines already (frame.h):
+// the deep nodes' corrected velocity is read from the state, the frame
+// completed here; 0: take the correction from f.dbar_in (stage, state
+// untouched).
 // CN: the theta scheme's rhs, (1/dt) M u - (1 - theta) T(u), restricted.
+// The implicit-Euler step (UB) sums the stored corrected velocity u = P v + d
+// against the hat moments: P v is bilinear on the patch, so its fine
+// interpolant is itself, and R (1/dt) M u needs no separate coarse term.
+// The stage and the theta scheme keep d and the coarse mass term of P v.
 template <int K, int FROM_PATCHES, bool OPAQUE_TID, bool CN = false>
 __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables tab)
 {
+    static_assert(FROM_PATCHES != 2 || (K == 2 && !CN && !OPAQUE_TID), "tile frame: the one-launch K = 2 step");
+    constexpr bool UB = FROM_PATCHES != 0 && !CN;
     const int tid = OPAQUE_TID ? tile_thread() : (int)threadIdx.x;
     constexpr int n = 1 << K;
     constexpr int nf = (n + 1) * (n + 1);
     constexpr int TP = kRhsFine / n;          // patches per tile and direction
     constexpr int HP = TP + 2;                // with a ring of neighbour patches
     constexpr int NO = kRhsFine + 1;          // tile nodes per direction
+    constexpr int SV = TP + 2;                // corner velocities: the tile's patches and the next column and row
+    constexpr float inv_n = 1.0f / n;
+    static_assert(kRhsFine == kFrameLine, "one tile shape for the frame");
 
     // the staged per-patch outputs (step) and, once the node pass has read
-    // them, the averaged correction at the tile's nodes share one buffer
-    constexpr int kStaged = FROM_PATCHES ? HP * HP * nf : 0;
+    // them, the averaged correction (or u) at the tile's nodes share one buffer
+    constexpr int kStaged = FROM_PATCHES == 1 ? HP * HP * nf : 0;
     __shared__ float2 s_buf[kStaged > NO * NO ? kStaged : NO * NO];
     float2 *const s_dbar = s_buf;
-    __shared__ float2 s_v[(TP + 1) * (TP + 1)];
+    __shared__ float2 s_v[SV * SV];
     __shared__ double s_A[4 * (n + 1)];
     __shared__ double s_M[3 * 4 * 4];
     __shared__ double2 s_g[2 * TP * TP];
@@ -170,14 +185,25 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
     // The step's defect has already read the first-step flag (stream order).
     if (FROM_PATCHES && blk == 0 && tid == 0) *f.first_flag = 0;
 
+    // P v at tile node (li, lj) from the corners of the patch that owns it
+    // (the left/lower one: that patch may lie in the next tile column or row)
+    auto pv_of = [&](int li, int lj, float &px, float &py) {
+        const int I = I0 + li, J = J0 + lj;
+        const int pI = min(I >> K, nx - 1), pJ = min(J >> K, ny - 1);
+        const int c = (pJ - pj0) * SV + (pI - pi0);
+        const float2 v00 = s_v[c], v10 = s_v[c + 1], v01 = s_v[c + SV], v11 = s_v[c + SV + 1];
+        const PvRow r = pv_row(v00.x, v00.y, v10.x, v10.y, v01.x, v01.y, v11.x, v11.y, (J - pJ * n) * inv_n);
+        pv_at(r, (I - pI * n) * inv_n, px, py);
+    };
+
     // ---- stage: moment tables, coarse corner velocities, the patches' map
-    //      determinant coefficients, per-patch outputs.  Every load is issued
-    //      into registers before the first LDS store, so the tile waits for
-    //      one memory round trip instead of one per table.  The tables are
-    //      read through pinned pointers: in the batched tile loop their loads
-    //      would otherwise be hoisted and held in registers.
+    //      determinant coefficients, per-patch outputs (or the tile frame).
+    //      Every load is issued into registers before the first LDS store, so
+    //      the tile waits for one memory round trip instead of one per table.
+    //      The tables are read through pinned pointers: in the batched tile
+    //      loop their loads would otherwise be hoisted and held in registers.
     const gptr<double> tabA = pinned<double>(tab.A), tabM = pinned<double>(tab.M);
-    constexpr int NA = 4 * (n + 1), NM = 3 * 4 * 4, NV = (TP + 1) * (TP + 1), NG = 2 * TP * TP;
+    constexpr int NA = 4 * (n + 1), NM = 3 * 4 * 4, NV = SV * SV, NG = 2 * TP * TP;
     static_assert(NA + NM <= kThreads, "one table entry per thread");
     constexpr int VIT = (NV + kThreads - 1) / kThreads, GIT = (NG + kThreads - 1) / kThreads;
     // (the addresses are clamped into the arrays and the loads made
@@ -190,7 +216,7 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
 #pragma unroll
     for (int i = 0; i < VIT; ++i) {
         const int t = min(tid + i * kThreads, NV - 1);
-        const int ci = min(t % (TP + 1), nx - pi0), cj = min(t / (TP + 1), ny - pj0);
+        const int ci = min(t % SV, nx - pi0), cj = min(t / SV, ny - pj0);
         v_r[i] = vt[cj * (nx + 1) + ci];
     }
 #pragma unroll
@@ -200,7 +226,47 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
         const int pa = min(pl % TP, nx - 1 - pi0), pb = min(pl / TP, ny - 1 - pj0);
         g_r[i] = gt[2 * (pb * nx + pa) + (t & 1)];
     }
-    if (FROM_PATCHES) {
+    // tile frame (FROM_PATCHES = 2): the deep nodes' u (li, lj in 2 .. kRhsFine - 2),
+    // the inner nodes' averaged d (threads < INNER) and, on the threads from
+    // kThreads - EDGES on, the outputs of every patch at one boundary-line node
+    typedef TileFrame<K> FR;
+    constexpr int DN = kRhsFine - 3, ND = DN * DN;
+    constexpr int DIT = FROM_PATCHES == 2 ? (ND + kThreads - 1) / kThreads : 1;
+    static_assert(FROM_PATCHES != 2 || FR::INNER <= kThreads - FR::EDGES, "inner and edge nodes on separate threads");
+    float2 du[DIT];
+    float2 fin = make_float2(0.f, 0.f);
+    float2 fq[4];
+    if constexpr (FROM_PATCHES == 2) {
+        const float2 *fr = reinterpret_cast<const float2 *>(f.frame);
+#pragma unroll
+        for (int i = 0; i < DIT; ++i) {
+            // (a tile holds at least one patch: NX - I0, NY - J0 >= n >= 2)
+            const int t = min(tid + i * kThreads, ND - 1);
+            const int li = min(2 + t % DN, NX - I0), lj = min(2 + t / DN, NY - J0);
+            du[i] = ut[lj * up + li];
+        }
+        if (tid < FR::INNER) fin = fr[(size_t)blk * FR::SIZE + 4 * FR::SIDE + tid];
+        if (tid >= kThreads - FR::EDGES) {
+            int li, lj;
+            FR::edge_pos(tid - (kThreads - FR::EDGES), li, lj);
+            const int I = I0 + li, J = J0 + lj;
+            long o[4] = {0, 0, 0, 0};
+            if (I <= NX && J <= NY) {
+                // the node's patches in row-major order: lower left, lower,
+                // left, own (own: the left/lower-owner patch of the node)
+                const int pI = min(I >> K, nx - 1), pJ = min(J >> K, ny - 1);
+                const int a = I - pI * n, b = J - pJ * n;
+                const bool lft = a == 0 && pI > 0, low = b == 0 && pJ > 0;
+                o[3] = FR::contrib(nx, pI, pJ, a, b);
+                o[0] = lft && low ? FR::contrib(nx, pI - 1, pJ - 1, n, n) : o[3];
+                o[1] = low ? FR::contrib(nx, pI, pJ - 1, a, n) : o[3];
+                o[2] = lft ? FR::contrib(nx, pI - 1, pJ, n, b) : o[3];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) fq[q] = fr[o[q] < 0 ? 0 : o[q]];
+        }
+    }
+    if constexpr (FROM_PATCHES == 1) {
         // per-patch outputs, 8 bytes at a time, into the staged (TP+2)^2-patch
         // layout: the tile's own patches whole (each tile row of TP patches is
         // one contiguous run of TP nf nodes), and of the ring of neighbours only
@@ -287,25 +353,35 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
     for (int i = 0; i < VIT; ++i) {
         // corners beyond the mesh (tiles at its end) hold zeros
         const int t = tid + i * kThreads;
-        if (t < NV) s_v[t] = (pi0 + t % (TP + 1) <= nx && pj0 + t / (TP + 1) <= ny) ? v_r[i] : make_float2(0.f, 0.f);
+        if (t < NV) s_v[t] = (pi0 + t % SV <= nx && pj0 + t / SV <= ny) ? v_r[i] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int i = 0; i < GIT; ++i)
         if (tid + i * kThreads < NG) s_g[tid + i * kThreads] = g_r[i];
+    if constexpr (FROM_PATCHES == 2) {
+#pragma unroll
+        for (int i = 0; i < DIT; ++i) {
+            const int t = tid + i * kThreads;
+            const int li = 2 + t % DN, lj = 2 + t / DN;
+            if (t < ND && I0 + li <= NX && J0 + lj <= NY) s_dbar[lj * NO + li] = du[i];
+        }
+    }
     __syncthreads();
 
     // ---- node pass: mean over the containing patches (row-major order, as
     //      the mean is defined), Dirichlet mask, corrected velocity.
     const float2 *sd2 = s_buf;
     // Any tile node (li, lj); the patch offsets are those of the staged ring.
-    // Returns the node's averaged correction.  nonfin: this thread has
-    // averaged a correction that is not finite (the step's non-finite check).
+    // Returns the node's averaged correction and sets u to the corrected
+    // velocity (the step).  nonfin: this thread has averaged a correction
+    // that is not finite (the step's non-finite check).
     bool nonfin = false;
-    auto node = [&](int li, int lj) -> float2 {
+    auto node = [&](int li, int lj, float2 &u) -> float2 {
         const int I = I0 + li, J = J0 + lj;
         float2 d = make_float2(0.f, 0.f);
+        u = d;
         if (I <= NX && J <= NY) {
-            if (FROM_PATCHES) {
+            if (FROM_PATCHES == 1) {
                 // the node's own (left/lower-owner) patch, plus the patches to the
                 // left, below and diagonal when the node lies on their edges;
                 // summed in row-major patch order
@@ -322,30 +398,70 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                 d = make_float2(acc.x * inv, acc.y * inv);
                 if (dirichlet_node<K>(f.dirichlet, I, J, NX, NY)) d = make_float2(0.f, 0.f);
                 nonfin |= !(__builtin_isfinite(d.x) && __builtin_isfinite(d.y));
+                float px, py;
+                pv_of(li, lj, px, py);
+                u = make_float2(px + d.x, py + d.y);
                 const bool owned = (li < kRhsFine || I == NX) && (lj < kRhsFine || J == NY);
                 if (owned) {
-                    // P v at the node from the corners of its (left/lower) patch,
-                    // along the node row (as in the pass below)
-                    const float xi = a * (1.0f / n), eta = b * (1.0f / n);
-                    const int c = (pJ - pj0) * (TP + 1) + (pI - pi0);
-                    const float2 v00 = s_v[c], v10 = s_v[c + 1], v01 = s_v[c + TP + 1], v11 = s_v[c + TP + 2];
-                    const float lx = v00.x + (v01.x - v00.x) * eta, ly = v00.y + (v01.y - v00.y) * eta;
-                    const float rx = v10.x + (v11.x - v10.x) * eta, ry = v10.y + (v11.y - v10.y) * eta;
-                    const float pvx = lx + (rx - lx) * xi, pvy = ly + (ry - ly) * xi;
-                    ut[lj * up + li] = make_float2(pvx + d.x, pvy + d.y);
+                    ut[lj * up + li] = u;
                     if (f.dbar_out) (reinterpret_cast<float2 *>(f.dbar_out) + nt0)[lj * (NX + 1) + li] = d;
                 }
-            } else {
+            } else if (FROM_PATCHES == 0) {
                 d = (reinterpret_cast<const float2 *>(f.dbar_in) + nt0)[lj * (NX + 1) + li];
             }
         }
         return d;
     };
-    if (!FROM_PATCHES) {
-        for (int t = tid; t < NO * NO; t += kThreads) s_dbar[t] = node(t % NO, t / NO);
+    if constexpr (FROM_PATCHES == 0) {
+        float2 u;
+        for (int t = tid; t < NO * NO; t += kThreads) s_dbar[t] = node(t % NO, t / NO, u);
+    } else if constexpr (FROM_PATCHES == 2) {
+        // the frame: inner nodes take the averaged d handed over, edge nodes
+        // average their patches' outputs; both store u = P v + d where they own
+        // the node and put u where the FP64 pass reads it (the deep nodes' u
+        // is there already)
+        float2 *const dout = f.dbar_out ? reinterpret_cast<float2 *>(f.dbar_out) + nt0 : nullptr;
+        if (tid < FR::INNER) {
+            int li, lj;
+            FR::inner_pos(tid, li, lj);
+            if (I0 + li <= NX && J0 + lj <= NY) {
+                float px, py;
+                pv_of(li, lj, px, py);
+                const float2 u = make_float2(px + fin.x, py + fin.y);
+                ut[lj * up + li] = u;
+                if (dout) dout[lj * (NX + 1) + li] = fin;
+                s_dbar[lj * NO + li] = u;
+            }
+        } else if (tid >= kThreads - FR::EDGES) {
+            int li, lj;
+            FR::edge_pos(tid - (kThreads - FR::EDGES), li, lj);
+            const int I = I0 + li, J = J0 + lj;
+            if (I <= NX && J <= NY) {
+                const int pI = min(I >> K, nx - 1), pJ = min(J >> K, ny - 1);
+                const bool lft = I - pI * n == 0 && pI > 0, low = J - pJ * n == 0 && pJ > 0;
+                float2 acc = make_float2(0.f, 0.f);
+                if (lft && low) { acc.x += fq[0].x; acc.y += fq[0].y; }
+                if (low) { acc.x += fq[1].x; acc.y += fq[1].y; }
+                if (lft) { acc.x += fq[2].x; acc.y += fq[2].y; }
+                acc.x += fq[3].x; acc.y += fq[3].y;
+                const float inv = (lft && low) ? 0.25f : ((lft || low) ? 0.5f : 1.0f);
+                float2 d = make_float2(acc.x * inv, acc.y * inv);
+                if (dirichlet_node<K>(f.dirichlet, I, J, NX, NY)) d = make_float2(0.f, 0.f);
+                nonfin |= !(__builtin_isfinite(d.x) && __builtin_isfinite(d.y));
+                float px, py;
+                pv_of(li, lj, px, py);
+                const float2 u = make_float2(px + d.x, py + d.y);
+                if ((li < kRhsFine || I == NX) && (lj < kRhsFine || J == NY)) {
+                    ut[lj * up + li] = u;
+                    if (dout) dout[lj * (NX + 1) + li] = d;
+                }
+                s_dbar[lj * NO + li] = u;
+            }
+        }
+        if (nonfin && f.nonfinite) atomicOr(f.nonfinite, 1);
     } else {
-        // the corrections are kept in registers until every thread is done
-        // reading the staged outputs, then written over them
+        // the corrections (or u) are kept in registers until every thread is
+        // done reading the staged outputs, then written over them
         constexpr int OIT = (TP * TP * n + kThreads - 1) / kThreads;
         float2 dreg[OIT][n];
         int dpos[OIT];
@@ -366,13 +482,10 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
             const int hb = (pb + 1) * HP + pa + 1;
             const bool low = b == 0 && pj > 0;
             const bool mrow = (dir & 4u) && pj == 0 && b == 0, mcol = (dir & 1u) && pi == 0;
-            // P v along the node row: linear between the row's ends
-            const float eta = b * (1.0f / n);
-            const int c = pb * (TP + 1) + pa;
-            const float2 v00 = s_v[c], v10 = s_v[c + 1], v01 = s_v[c + TP + 1], v11 = s_v[c + TP + 2];
-            const float lx = v00.x + (v01.x - v00.x) * eta, ly = v00.y + (v01.y - v00.y) * eta;
-            const float rx = v10.x + (v11.x - v10.x) * eta, ry = v10.y + (v11.y - v10.y) * eta;
-            const float dx = rx - lx, dy = ry - ly;
+            // P v along the node row (the patch owns these nodes)
+            const int c = pb * SV + pa;
+            const float2 v00 = s_v[c], v10 = s_v[c + 1], v01 = s_v[c + SV], v11 = s_v[c + SV + 1];
+            const PvRow row = pv_row(v00.x, v00.y, v10.x, v10.y, v01.x, v01.y, v11.x, v11.y, b * inv_n);
             float2 *const urow = ut + (pb * n + b) * up + pa * n;
             float2 *const drow = f.dbar_out ? reinterpret_cast<float2 *>(f.dbar_out) + nt0 + (pb * n + b) * (NX + 1) + pa * n
                                             : nullptr;
@@ -388,11 +501,12 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
                 float2 d = make_float2(acc.x * inv, acc.y * inv);
                 if (mrow || (a == 0 && mcol)) d = make_float2(0.f, 0.f);
                 nonfin |= !(__builtin_isfinite(d.x) && __builtin_isfinite(d.y));
-                const float xi = a * (1.0f / n);
-                const float pvx = lx + dx * xi, pvy = ly + dy * xi;
-                urow[a] = make_float2(pvx + d.x, pvy + d.y);
+                float px, py;
+                pv_at(row, a * inv_n, px, py);
+                const float2 u = make_float2(px + d.x, py + d.y);
+                urow[a] = u;
                 if (drow) drow[a] = d;
-                dreg[o][a] = d;
+                dreg[o][a] = UB ? u : d;
             }
         }
         // the rest: the last node column and row of the tile's patches (the
@@ -401,7 +515,9 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
         static_assert(2 * kRhsFine + 1 <= kThreads, "one last-row/column node per thread");
         if (tid < le + me + 1) {
             const int li = tid <= me ? le : tid - me - 1, lj = tid <= me ? tid : me;
-            dlast = node(li, lj);
+            float2 u;
+            const float2 d = node(li, lj, u);
+            dlast = UB ? u : d;
             lpos = lj * NO + li;
         }
         __syncthreads();
@@ -422,9 +538,10 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
     const double th_old = CN ? 1.0 - (double)f.theta : 0.0;
 
     // ---- FP64 share of each patch at each of its 4 corners c = (cx, cy):
-    //      (1/dt) [ sum_k d_k sum_{a,b} A[mx_k][cx][a] A[my_k][cy][b] Dbar(a,b)
-    //             + sum_c' (d0 M0 + d1 M1 + d2 M2)[c][c'] v_c' ].
-    //      One item per (patch, component, cx): the x pass T_m(b) = sum_a A[m][cx][a] Dbar(a,b)
+    //      (1/dt) sum_k d_k sum_{a,b} A[mx_k][cx][a] A[my_k][cy][b] w(a,b),
+    //      w = u (the step), or w = Dbar plus the coarse term
+    //      (1/dt) sum_c' (d0 M0 + d1 M1 + d2 M2)[c][c'] v_c' (stage, theta scheme).
+    //      One item per (patch, component, cx): the x pass T_m(b) = sum_a A[m][cx][a] w(a,b)
     //      and the y pass for both cy (the four items of a patch on
     //      neighbouring lanes read neighbouring LDS words).
     const float *dbar1 = reinterpret_cast<const float *>(s_dbar);
@@ -466,20 +583,22 @@ __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables t
         }
         // this item's entry in corner plane cx (plane c = cx + 2 cy holds P pairs)
         double *const pq = pt + 2 * (size_t)cx * P + 2 * ((pl / TP) * nx + pl % TP) + comp;
-        const int cb = (pl / TP) * (TP + 1) + (pl % TP);
+        const int cb = (pl / TP) * SV + (pl % TP);
         const float *v1 = reinterpret_cast<const float *>(s_v);
-        const double vq[4] = {(double)v1[2 * cb + comp], (double)v1[2 * (cb + 1) + comp],
-                              (double)v1[2 * (cb + TP + 1) + comp], (double)v1[2 * (cb + TP + 2) + comp]};
 #pragma unroll
         for (int cy = 0; cy < 2; ++cy) {
             const double S0 = S[cy][0], S1 = S[cy][1], S2 = S[cy][2];
             const int c = cx + 2 * cy;
             double acc = d0 * S0 + d1 * S1 + d2 * S2;
+            if constexpr (!UB) {
+                const double vq[4] = {(double)v1[2 * cb + comp], (double)v1[2 * (cb + 1) + comp],
+                                      (double)v1[2 * (cb + SV) + comp], (double)v1[2 * (cb + SV + 1) + comp]};
 #pragma unroll
-            for (int cc = 0; cc < 4; ++cc) {
-                const double w = d0 * s_M[(0 * 4 + c) * 4 + cc] + d1 * s_M[(1 * 4 + c) * 4 + cc] +
-                                 d2 * s_M[(2 * 4 + c) * 4 + cc];
-                acc += w * vq[cc];
+                for (int cc = 0; cc < 4; ++cc) {
+                    const double w = d0 * s_M[(0 * 4 + c) * 4 + cc] + d1 * s_M[(1 * 4 + c) * 4 + cc] +
+                                     d2 * s_M[(2 * 4 + c) * 4 + cc];
+                    acc += w * vq[cc];
+                }
             }
             double b = f.inv_dt64 * acc;
             if constexpr (CN) b -= th_old * s_T[8 * pl + 2 * c + comp];
@@ -505,17 +624,17 @@ __global__ __launch_bounds__(kThreads, 3) void k_rhs_cn(FlowArgs single, RhsTabl
 template <int K, int FROM_PATCHES, bool BATCHED>
 __global__ __launch_bounds__(kThreads, (rhs_waves<K, BATCHED>())) void k_rhs(FlowArgs single, const BatchTable *__restrict__ bt, RhsTables tab)
 {
-    if (!BATCHED) {
+    if constexpr (!BATCHED) {
         rhs_tile<K, FROM_PATCHES, false>(single, xcd_tile(blockIdx.x, gridDim.x), tab);
-        return;
-    }
-    const int total = bt->prefix[kKindRhs][bt->nflows];
+    } else {
+        const int total = bt->prefix[kKindRhs][bt->nflows];
 #pragma unroll 1
-    for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        int blk = xcd_tile(g, total);
-        const FlowArgs &f = *batch_flow(bt, kKindRhs, blk);
-        rhs_tile<K, FROM_PATCHES, true>(f, blk, tab);
-        __syncthreads();   // LDS is reused by the next tile
+        for (int g = blockIdx.x; g < total; g += gridDim.x) {
+            int blk = xcd_tile(g, total);
+            const FlowArgs &f = *batch_flow(bt, kKindRhs, blk);
+            rhs_tile<K, FROM_PATCHES, true>(f, blk, tab);
+            __syncthreads();   // LDS is reused by the next tile
+        }
     }
 }
 
@@ -563,6 +682,12 @@ hipError_t launch_rhs(const FlowArgs &f, const BatchTable *bt, int nblocks, int 
     const bool cn = f.theta != 1.0f;
     if (cn && (bt || !f.map64)) return hipErrorInvalidValue;
     dim3 g(nblocks), b(kThreads);
+    if (from_patches && f.frame) {
+        // after the one-launch K = 2 step, single flow
+        if (K != 2 || bt || cn) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_rhs<2, 2, false>), g, b, 0, s, f, bt, tab);
+        return hipGetLastError();
+    }
 #define DNNMG_RHS_CASE(KK)                                                                \
     case KK:                                                                              \
         if (cn && from_patches) hipLaunchKernelGGL((k_rhs_cn<KK, 1>), g, b, 0, s, f, tab); \

@@ -84,8 +84,12 @@ def to_dev(a, dtype=None):
     return t.cuda()
 
 
-def make_gpu_flow(flow, K, H, Hm, nu, weights, precision="fp32", share=None, flags=0):
+def make_gpu_flow(flow, K, H, Hm, nu, weights, precision="fp32", share=None, flags=None):
+    """A GPU flow; by default it keeps its per-patch outputs (DNNMG_F_PATCH_OUTPUTS),
+    so that the tests can compare them."""
     import paper_2008_11520_amd as pam
+    if flags is None:
+        flags = pam.DNNMG_F_PATCH_OUTPUTS
     cfg = pam.make_config(flow.nx, flow.ny, K, H, Hm, flow.dt, nu, precision, flow.dirichlet, flags)
     return pam.DnnMG(cfg, flow.cxy, None if share is not None else weights, share=share)
 
@@ -109,17 +113,26 @@ class GpuRunner:
 
     def step(self, v, p):
         import torch
+        import paper_2008_11520_amd as pam
         vd, pd = to_dev(v.reshape(-1)), to_dev(p.reshape(-1))
         self.g.step(vd, pd, self.dbar)
         self.g.restrict_rhs(self.bL)
         self.g.get_state(self.h, None)
-        self.g.patch_output(self.dp)
+        try:
+            self.g.patch_output(self.dp)
+            kept = True
+        except pam.DnnmgError as e:
+            # a one-launch step without DNNMG_F_PATCH_OUTPUTS keeps none
+            assert e.code == pam.DNNMG_ESTATE, e
+            kept = False
         torch.cuda.synchronize()
         s = self.g.s
-        return dict(Dbar=self.dbar.cpu().numpy().reshape(s["Fn"], 2).copy(),
-                    bL=self.bL.cpu().numpy().reshape(s["Nc"], 2).copy(),
-                    h=self.h.cpu().numpy().reshape(s["P"], -1).copy(),
-                    dpatch=self.dp.cpu().numpy().reshape(s["P"], s["nout"]).copy())
+        out = dict(Dbar=self.dbar.cpu().numpy().reshape(s["Fn"], 2).copy(),
+                   bL=self.bL.cpu().numpy().reshape(s["Nc"], 2).copy(),
+                   h=self.h.cpu().numpy().reshape(s["P"], -1).copy())
+        if kept:
+            out["dpatch"] = self.dp.cpu().numpy().reshape(s["P"], s["nout"]).copy()
+        return out
 
 
 def window(flow, i0, i1, j0, j1):

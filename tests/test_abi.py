@@ -129,7 +129,7 @@ def test_fp8_config_sizes_and_quantiser_validation():
 
 def test_unknown_flags_rejected_on_host():
     L = pam.lib()
-    c = cfg(flags=32)
+    c = cfg(flags=64)
     s = pam.sizes(4, 3, 2)
     cxy = np.zeros(2 * s["Nc"])
     w = np.zeros(pam.weight_count(c), dtype=np.float32)
@@ -189,8 +189,21 @@ def test_nancheck_flag_validation():
     flag bits are not; dnnmg_nonfinite rejects NULL arguments on the host."""
     assert pam.workspace_bytes(cfg(flags=pam.DNNMG_F_NANCHECK)) > pam.workspace_bytes(cfg()) - 1
     assert pam.workspace_bytes(cfg(flags=pam.DNNMG_F_NANCHECK | pam.DNNMG_F_UNFUSED)) > 0
-    assert pam.workspace_bytes(cfg(flags=32)) == 0
+    assert pam.workspace_bytes(cfg(flags=64)) == 0
     L = pam.lib()
     out = ctypes.c_int(7)
     assert L.dnnmg_nonfinite(None, 1, ctypes.byref(out), None) == pam.DNNMG_EINVAL
     assert out.value == 7
+
+
+def test_patch_outputs_flag_and_tile_frame_workspace():
+    """DNNMG_F_PATCH_OUTPUTS is a known flag that changes no buffer; the
+    one-launch form (K=2, H=64, BF16) holds a tile frame of 280 (x, y) pairs
+    per 8 x 8-patch tile (ragged tiles counted whole), the other forms none."""
+    one = cfg(nx=20, ny=19, precision=1)
+    assert pam.workspace_bytes(cfg(nx=20, ny=19, precision=1, flags=pam.DNNMG_F_PATCH_OUTPUTS)) == \
+        pam.workspace_bytes(one)
+    frame = 3 * 3 * 280 * 8
+    unfused = pam.workspace_bytes(cfg(nx=20, ny=19, precision=1, flags=pam.DNNMG_F_UNFUSED))
+    assert pam.workspace_bytes(one) - unfused >= frame
+    assert pam.workspace_bytes(one) - unfused < frame + 512
