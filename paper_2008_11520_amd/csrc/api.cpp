@@ -114,6 +114,10 @@ int check_config(const dnnmg_config *c)
     const double fn = (c->nx * n + 1.0) * (c->ny * n + 1.0);
     if (fn > 2.0e9 || double(c->nx) * c->ny * (4.0 * (n + 1) * (n + 1) + 4) > 4.0e9)
         return fail(DNNMG_EINVAL, "mesh too large for one context");
+    // a tile's rows of the state (35 rows of the padded fine row) are
+    // addressed with 32-bit offsets
+    if ((c->nx * n + 16.0) * 36.0 > 2.0e9)
+        return fail(DNNMG_EINVAL, "mesh too wide for one context (nx * 2^K must stay below 5.5e7)");
     return DNNMG_OK;
 }
 

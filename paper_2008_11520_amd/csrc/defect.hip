@@ -185,8 +185,19 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
     const int nx = f.nx, ny = f.ny;
     const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lq = lane >> 4;
     const int ht = wave, ucol = 16 * ht + 4 * lq;
-    auto patch = [&](int r) { return (size_t)(ty * TP + r / TP) * nx + tx * TP + r % TP; };
     auto valid = [&](int r) { return tx * TP + r % TP < nx && ty * TP + r / TP < ny; };
+    // This lane's rows 16 q + li are patches (2 q + li / 8, li % 8) of the
+    // tile: their state and outputs are addressed from the tile's first patch
+    // (a uniform 64-bit base) with 32-bit lane offsets, formed once and
+    // stepped by 2 q patch rows (no 64-bit index products per access).
+    // (batched launches, FRAME false, keep the plain index form: at their
+    // register limit the lane offset held across the network spills)
+    const size_t p00 = (size_t)(ty * TP) * nx + tx * TP;
+    const unsigned roff = ((li >> 3) ? (unsigned)nx : 0u) + (unsigned)(li & 7);
+    auto patch = [&](int r) { return (size_t)(ty * TP + r / TP) * nx + tx * TP + r % TP; };
+    auto hrow = [&](int q) {
+        return FRAME ? f.h + p00 * H + (roff + 2u * q * (unsigned)nx) * H + ucol : f.h + patch(16 * q + li) * H + ucol;
+    };
     const gptr<bf8> B1 = pinned<bf8>(net.B1);
     const gptr<bf8> B2 = pinned<bf8>(net.B2);
     const gptr<bf8> B3 = pinned<bf8>(net.B3);
@@ -199,7 +210,7 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
         const int r = 16 * q + li;
-        hp[q] = valid(r) ? *reinterpret_cast<const f4 *>(f.h + patch(r) * H + ucol) : f4{0.f, 0.f, 0.f, 0.f};
+        hp[q] = valid(r) ? *reinterpret_cast<const f4 *>(hrow(q)) : f4{0.f, 0.f, 0.f, 0.f};
     }
     // corner velocities of the tile's patches, for the averaging after the
     // network when the outputs stay in LDS (f.frame); loaded on every launch,
@@ -292,7 +303,7 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
             hn[e] = c + z * (hold[q][e] - c);
             hb[e] = (__bf16)hn[e];
         }
-        if (valid(r)) *reinterpret_cast<f4 *>(f.h + patch(r) * H + ucol) = hn;
+        if (valid(r)) *reinterpret_cast<f4 *>(hrow(q)) = hn;
         *reinterpret_cast<bf4 *>(&sHp[r * LDH + ucol]) = hb;
     }
     __syncthreads();
@@ -350,7 +361,8 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
             if (ucol + 2 < nout) *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[q][2], acc[q][3]);
         }
         if ((!frame || f.keep_dpatch) && valid(r)) {
-            float *o = f.dpatch + patch(r) * nout + ucol;
+            float *o = FRAME ? f.dpatch + p00 * nout + (roff + 2u * q * (unsigned)nx) * nout + ucol
+                             : f.dpatch + patch(r) * nout + ucol;
             if (ucol < nout) *reinterpret_cast<float2 *>(o) = make_float2(acc[q][0], acc[q][1]);
             if (ucol + 2 < nout) *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[q][2], acc[q][3]);
         }
@@ -510,14 +522,41 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
 
     // 0. the previous corrected velocity on the tile's nodes + halo: issue the
     //    loads now, use them after the coarse records are formed
+    //    (node t of the halo grid is row t / NN, column t % NN; thread tid
+    //    takes t = tid + i kThreads, stepped by kThreads = DR rows + DC
+    //    columns, with a 32-bit offset from the grid's first node)
     constexpr int NIT = (NN * NN + kThreads - 1) / kThreads;
+    constexpr int DR = kThreads / NN, DC = kThreads % NN;
     float2 uq[NIT];
+    if constexpr (OPAQUE_TID) {
+        // (batched: the index form that keeps fewer registers live)
 #pragma unroll
-    for (int i = 0; i < NIT; ++i) {            // issue every load first
-        const int t = tid + i * kThreads;
-        const int I = I0 - 1 + t % NN, J = J0 - 1 + t / NN;
-        const bool in = t < NN * NN && !first && I >= 0 && I <= NX && J >= 0 && J <= NY;
-        uq[i] = in ? reinterpret_cast<const float2 *>(f.uprev)[(size_t)J * f.upitch + I] : make_float2(0.f, 0.f);
+        for (int i = 0; i < NIT; ++i) {
+            const int t = tid + i * kThreads;
+            const int I = I0 - 1 + t % NN, J = J0 - 1 + t / NN;
+            const bool in = t < NN * NN && !first && I >= 0 && I <= NX && J >= 0 && J <= NY;
+            uq[i] = in ? reinterpret_cast<const float2 *>(f.uprev)[(size_t)J * f.upitch + I] : make_float2(0.f, 0.f);
+        }
+    } else {
+        const int up = f.upitch;
+        const float2 *const ub = reinterpret_cast<const float2 *>(f.uprev) + ((ptrdiff_t)(J0 - 1) * up + (I0 - 1));
+        int row = tid / NN, col = tid - row * NN;
+        unsigned off = (unsigned)row * (unsigned)up + (unsigned)col;
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {            // issue every load first
+            const int t = tid + i * kThreads;
+            const int I = I0 - 1 + col, J = J0 - 1 + row;
+            const bool in = t < NN * NN && !first && I >= 0 && I <= NX && J >= 0 && J <= NY;
+            uq[i] = in ? ub[off] : make_float2(0.f, 0.f);
+            row += DR;
+            col += DC;
+            off += (unsigned)(DR * up + DC);
+            if (col >= NN) {
+                col -= NN;
+                ++row;
+                off += (unsigned)(up - NN);
+            }
+        }
     }
 
     // 1. coarse-element records.  Every record is formed from indices clamped
@@ -530,9 +569,12 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
     const float *p1 = has_p ? f.p : reinterpret_cast<const float *>(f.v);   // read and discarded without p
     for (int t = tid; t < CE * CE; t += kThreads) {
         const int ci = min(max(ci0 + t % CE, 0), nx - 1), cj = min(max(cj0 + t / CE, 0), ny - 1);
-        const int c = cj * (nx + 1) + ci;
+        // (single flow: 32-bit offsets, 6 P and the corner count fit; the
+        // batched form keeps the index form it was tuned with)
+        const unsigned cjn = (unsigned)cj * (unsigned)nx;
+        const unsigned c = OPAQUE_TID ? (unsigned)(cj * (nx + 1) + ci) : cjn + (unsigned)(cj + ci);
         const float2 a = v2[c], b = v2[c + 1], cc = v2[c + nx + 1], d = v2[c + nx + 2];
-        const float *g = f.geo + 6 * ((size_t)cj * nx + ci);
+        const float *g = OPAQUE_TID ? f.geo + 6 * ((size_t)cj * nx + ci) : f.geo + 6u * (cjn + (unsigned)ci);
         const float g0 = g[0], g1 = g[1], g2 = g[2], g3 = g[3], g4 = g[4], g5 = g[5];
         const float pa = p1[c], pb = p1[c + 1], pc = p1[c + nx + 1], pd = p1[c + nx + 2];
         CoarseRec r;
