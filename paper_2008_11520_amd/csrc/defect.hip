@@ -377,8 +377,12 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
 // tile's sides hand over their outputs (frame.h) for the rhs kernel to
 // complete.  The sums, the mask and P v + d are formed as the rhs kernel forms
 // them, so the state and outputs match the separate-launch step bit for bit.
+// The completed values are staged as a tile image in LDS (s_img, (kTileFine
+// + 1)^2 nodes: u at deep nodes, d at inner ones) and then stored row by row
+// with 16-byte stores: stored node by node straight from the sums, the 8-byte
+// values of one store instruction would lie 32 bytes apart.
 __device__ __forceinline__ void fused_average(const FlowArgs &f, int tx, int ty, int tid, const float2 *s_o,
-                                              const float2 *s_vc)
+                                              const float2 *s_vc, float2 *s_img)
 {
     constexpr int K = 2, n = 1 << K, nf = (n + 1) * (n + 1), TP = kTileFine / n, SVF = TP + 1;
     constexpr float inv_n = 1.0f / n;
@@ -393,49 +397,75 @@ __device__ __forceinline__ void fused_average(const FlowArgs &f, int tx, int ty,
     float2 *const ut = reinterpret_cast<float2 *>(f.uprev) + (size_t)J0 * up + I0;
     float2 *const dout = f.dbar_out ? reinterpret_cast<float2 *>(f.dbar_out) + (size_t)J0 * (NX + 1) + I0 : nullptr;
     bool nonfin = false;
-    // the sides' outputs
-    for (int s = tid; s < 4 * FR::SIDE; s += kThreads) {
-        int pa, pb, a, b;
-        FR::side_source(s, pa, pb, a, b);
-        if (pi0 + pa < nx && pj0 + pb < ny) fr[s] = s_o[(pb * TP + pa) * nf + b * (n + 1) + a];
+    // the sides' outputs: wave w copies side w (slots w SIDE + lane)
+    static_assert(kThreads == 4 * 64 && FR::SIDE <= 64, "one side per wave");
+    {
+        const int w = tid >> 6, l = tid & 63;
+        if (l < FR::SIDE) {
+            int pa, pb, a, b;
+            FR::side_pos(w, l, pa, pb, a, b);
+            if (pi0 + pa < nx && pj0 + pb < ny) fr[w * FR::SIDE + l] = s_o[(pb * TP + pa) * nf + b * (n + 1) + a];
+        }
     }
     // a completed node: inner frame nodes hand over d, deep nodes store u
+    constexpr int NO = kTileFine + 1;
     auto finish = [&](int li, int lj, float2 d, float px, float py) {
         if (frame_kind(li, lj) == kFrameInner) {
-            fr[FR::inner_slot(li, lj)] = d;
+            s_img[lj * NO + li] = d;
         } else {
-            ut[lj * up + li] = make_float2(px + d.x, py + d.y);
+            s_img[lj * NO + li] = make_float2(px + d.x, py + d.y);
             if (dout) dout[lj * (NX + 1) + li] = d;
         }
     };
     // the nodes (a, b), a, b < n, of the tile's patches, one node row of one
-    // patch per thread (such a node is masked only on the sides I = 0 and
-    // J = 0, which are boundary lines)
+    // patch per thread.  With li, lj >= 1 such a node has the patch to its
+    // left exactly when a = 0 and the one below exactly when b = 0, both in
+    // the tile, and no mask (masks lie on the sides I = 0, J = 0, which are
+    // boundary lines).  Absent patches are read from the own patch and
+    // replaced by +0 (a running sum from +0 is never -0, so adding +0 leaves
+    // its bits as skipping the patch would): the sums, in row-major patch
+    // order, are those of the rhs kernel.
+    const bool chk = f.nonfinite != nullptr;
     {
         const int pl = tid % (TP * TP), b = tid / (TP * TP);
         const int pa = pl % TP, pb = pl / TP, pi = pi0 + pa, pj = pj0 + pb;
         const int lj = pb * n + b;
         if (pi < nx && pj < ny && lj > 0) {
-            const bool low = b == 0 && pj > 0;
+            const bool low = b == 0;
+            const bool rin = lj == 1 || lj == kTileFine - 1;
             const int c = pb * SVF + pa;
             const float2 v00 = s_vc[c], v10 = s_vc[c + 1], v01 = s_vc[c + SVF], v11 = s_vc[c + SVF + 1];
             const PvRow row = pv_row(v00.x, v00.y, v10.x, v10.y, v01.x, v01.y, v11.x, v11.y, b * inv_n);
+            const float2 *const qo = s_o + pl * nf + b * (n + 1);              // own node row
+            const float2 *const ql = s_o + (low ? pl - TP : pl) * nf + n * (n + 1);   // top row of the patch below
+            const float2 z = make_float2(0.f, 0.f);
 #pragma unroll
             for (int a = 0; a < n; ++a) {
                 const int li = pa * n + a;
-                if (li == 0) continue;
-                const bool lft = a == 0 && pi > 0;
-                float2 acc = make_float2(0.f, 0.f);
-                if (lft && low) { const float2 q = s_o[(pl - TP - 1) * nf + n * (n + 1) + n]; acc.x += q.x; acc.y += q.y; }
-                if (low) { const float2 q = s_o[(pl - TP) * nf + n * (n + 1) + a]; acc.x += q.x; acc.y += q.y; }
-                if (lft) { const float2 q = s_o[(pl - 1) * nf + b * (n + 1) + n]; acc.x += q.x; acc.y += q.y; }
-                { const float2 q = s_o[pl * nf + b * (n + 1) + a]; acc.x += q.x; acc.y += q.y; }
-                const float inv = (lft && low) ? 0.25f : ((lft || low) ? 0.5f : 1.0f);
+                if (a == 0 && pa == 0) continue;                               // li = 0: boundary line
+                float2 acc = z;
+                if (a == 0) {
+                    const float2 qd = low ? s_o[(pl - TP - 1) * nf + n * (n + 1) + n] : z;
+                    acc.x += qd.x; acc.y += qd.y;
+                }
+                {
+                    const float2 q = ql[a];
+                    const float2 qb = low ? q : z;
+                    acc.x += qb.x; acc.y += qb.y;
+                }
+                if (a == 0) {
+                    const float2 q = s_o[(pl - 1) * nf + b * (n + 1) + n];
+                    acc.x += q.x; acc.y += q.y;
+                }
+                acc.x += qo[a].x; acc.y += qo[a].y;
+                const float inv = a == 0 ? (low ? 0.25f : 0.5f) : (low ? 0.5f : 1.0f);
                 const float2 d = make_float2(acc.x * inv, acc.y * inv);
-                nonfin |= !(__builtin_isfinite(d.x) && __builtin_isfinite(d.y));
+                if (chk) nonfin |= !(__builtin_isfinite(d.x) && __builtin_isfinite(d.y));
                 float px, py;
                 pv_at(row, a * inv_n, px, py);
-                finish(li, lj, d, px, py);
+                const bool inner = rin || (a == 1 && pa == 0) || (a == n - 1 && pa == TP - 1);
+                s_img[lj * NO + li] = inner ? d : make_float2(px + d.x, py + d.y);
+                if (dout && !inner) dout[lj * (NX + 1) + li] = d;
             }
         }
     }
@@ -459,7 +489,7 @@ __device__ __forceinline__ void fused_average(const FlowArgs &f, int tx, int ty,
             float2 d = make_float2(acc.x * inv, acc.y * inv);
             if (((dir & 1u) && I == 0) || ((dir & 2u) && I == NX) || ((dir & 4u) && J == 0) || ((dir & 8u) && J == NY))
                 d = make_float2(0.f, 0.f);
-            nonfin |= !(__builtin_isfinite(d.x) && __builtin_isfinite(d.y));
+            if (chk) nonfin |= !(__builtin_isfinite(d.x) && __builtin_isfinite(d.y));
             const int c = (pJ - pj0) * SVF + (pI - pi0);
             const float2 v00 = s_vc[c], v10 = s_vc[c + 1], v01 = s_vc[c + SVF], v11 = s_vc[c + SVF + 1];
             const PvRow row = pv_row(v00.x, v00.y, v10.x, v10.y, v01.x, v01.y, v11.x, v11.y, b * inv_n);
@@ -469,6 +499,32 @@ __device__ __forceinline__ void fused_average(const FlowArgs &f, int tx, int ty,
         }
     }
     if (nonfin && f.nonfinite) atomicOr(f.nonfinite, 1);
+    __syncthreads();
+    // the deep rows lj = 2 .. kTileFine - 2 of the state, nodes li = 2 ..
+    // kTileFine - 2 in pairs (16 bytes, aligned: state rows start on 128-byte
+    // lines and li = 2 is 16 bytes in), the last one alone; nodes beyond the
+    // mesh are not stored
+    constexpr int DL = kTileFine - 3, PR = (DL + 1) / 2;   // deep nodes per row, stores per row
+    static_assert(DL % 2 == 1, "pairs, then one node");
+    const int lim = NX - I0, ljm = NY - J0;                // last tile node inside the mesh
+    for (int t = tid; t < DL * PR; t += kThreads) {
+        const int lj = 2 + t / PR, c = t - (t / PR) * PR, li = 2 + 2 * c;
+        if (lj > ljm || li > lim) continue;
+        const float2 a = s_img[lj * NO + li];
+        float2 *const q = ut + lj * up + li;
+        if (c < PR - 1 && li + 1 <= lim) {
+            const float2 b = s_img[lj * NO + li + 1];
+            *reinterpret_cast<float4 *>(q) = make_float4(a.x, a.y, b.x, b.y);
+        } else {
+            *q = a;
+        }
+    }
+    // the inner frame nodes' d, in slot order
+    if (tid < FR::INNER) {
+        int li, lj;
+        FR::inner_pos(tid, li, lj);
+        if (li <= lim && lj <= ljm) fr[4 * FR::SIDE + tid] = s_img[lj * NO + li];
+    }
 }
 
 // FUSED (K = 2, BF16 input): the network input stays in LDS and the tile's
@@ -911,16 +967,18 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
             // the network input rows stay in LDS; r*h, h' reuse them after phase
             // 1 and the MLP hidden layer reuses the node accumulators
             __bf16 *sA = reinterpret_cast<__bf16 *>(s_wx);
-            // (the outputs' LDS rows take the input rows' bytes; the corner
-            // velocities the coarse records')
+            // (the outputs' LDS rows take the input rows' bytes, the corner
+            // velocities the coarse records', the averaged tile image the node
+            // accumulators')
             float2 *const s_vc = reinterpret_cast<float2 *>(s_c);
+            static_assert(NN * NN >= (kTileFine + 1) * (kTileFine + 1), "tile image in the node accumulators");
             // (batched launches store the per-patch outputs: no frame code)
             constexpr bool FRAME = !OPAQUE_TID;
             gru_fused<HM, FRAME>(f, tx, ty, tid, *net, sA, sA, sA + 64 * kFusedLDH,
                                  reinterpret_cast<__bf16 *>(s_acc), reinterpret_cast<float *>(s_wx), s_vc);
             if (FRAME && f.frame) {
                 __syncthreads();
-                fused_average(f, tx, ty, tid, reinterpret_cast<const float2 *>(s_wx), s_vc);
+                fused_average(f, tx, ty, tid, reinterpret_cast<const float2 *>(s_wx), s_vc, s_acc);
             }
             return;
         }

@@ -94,16 +94,21 @@ struct TileFrame {
         if (b == n && pb == TP - 1) return 3 * SIDE + pa * (n + 1) + a;
         return -1;
     }
-    // Side of slot s < 4 SIDE: tile patch (pa, pb) and node (a, b) it holds.
+    // Entry k < SIDE of side `side` (0 L, 1 R, 2 B, 3 T): tile patch (pa, pb)
+    // and node (a, b) it holds.
+    DNNMG_HD static void side_pos(int side, int k, int &pa, int &pb, int &a, int &b)
+    {
+        const int p = k / (n + 1), m = k - p * (n + 1);
+        pa = side == 0 ? 0 : (side == 1 ? TP - 1 : p);
+        pb = side < 2 ? p : (side == 2 ? 0 : TP - 1);
+        a = side == 0 ? 0 : (side == 1 ? n : m);
+        b = side < 2 ? m : (side == 2 ? 0 : n);
+    }
+    // The same for slot s < 4 SIDE.
     DNNMG_HD static void side_source(int s, int &pa, int &pb, int &a, int &b)
     {
-        const int side = s / SIDE, k = s - side * SIDE, p = k / (n + 1), m = k - p * (n + 1);
-        switch (side) {
-        case 0: pa = 0; pb = p; a = 0; b = m; break;
-        case 1: pa = TP - 1; pb = p; a = n; b = m; break;
-        case 2: pa = p; pb = 0; a = m; b = 0; break;
-        default: pa = p; pb = TP - 1; a = m; b = n;
-        }
+        const int side = s / SIDE;
+        side_pos(side, s - side * SIDE, pa, pb, a, b);
     }
     // Offset (in slots) in the flow's frame array of mesh patch (gi, gj)'s
     // output at node (a, b), a node on its tile's sides; -1 if it is not.
