@@ -277,7 +277,8 @@ struct UMeshDev {
     int *corners = nullptr, *pmap = nullptr, *node_ptr = nullptr, *node_occ = nullptr;
     int *cnode_ptr = nullptr, *cnode_occ = nullptr;
     float *rel = nullptr;
-    double *W = nullptr, *M4 = nullptr;
+    double *dgeo = nullptr, *W = nullptr, *M4 = nullptr;
+    int *cidx = nullptr;
     float *feat = nullptr, *uprev = nullptr, *dloc = nullptr, *D = nullptr;
     unsigned char *mask = nullptr;
 };
@@ -693,8 +694,11 @@ UArgs uargs(const dnnmg_ctx *c, const float *v, const float *p)
     u.corners = m.corners;
     u.pmap = m.pmap;
     u.rel = m.rel;
+    u.dgeo = m.dgeo;
+    u.cidx = m.cidx;
     u.W = m.W;
     u.M4 = m.M4;
+    u.tab = c->tables();
     u.feat = m.feat;
     u.mask = m.mask;
     u.node_ptr = m.node_ptr;
@@ -882,6 +886,7 @@ extern "C" int dnnmg_create_umesh(const dnnmg_config *cfg, const dnnmg_umesh *me
     const size_t o_cptr = take(sizeof(int) * m.cnode_ptr.size()), o_cocc = take(sizeof(int) * m.cnode_occ.size());
     const size_t o_rel = take(sizeof(float) * m.rel32.size()), o_feat = take(sizeof(float) * m.feat.size());
     const size_t o_W = take(sizeof(double) * m.W.size()), o_M4 = take(sizeof(double) * m.M4.size());
+    const size_t o_dgeo = take(sizeof(double) * m.dgeo.size()), o_cidx = take(sizeof(int) * m.cidx.size());
     const size_t o_mask = take(m.mask.size()), o_up = take(sizeof(float) * 2 * (size_t)m.Fn);
     const size_t o_dloc = take(sizeof(float) * 2 * (size_t)m.ne * m.nf), o_D = take(sizeof(float) * 2 * (size_t)m.Fn);
     auto bail = [&](int code) {
@@ -901,6 +906,7 @@ extern "C" int dnnmg_create_umesh(const dnnmg_config *cfg, const dnnmg_umesh *me
     d->cnode_ptr = (int *)(d->dev + o_cptr); d->cnode_occ = (int *)(d->dev + o_cocc);
     d->rel = (float *)(d->dev + o_rel); d->feat = (float *)(d->dev + o_feat);
     d->W = (double *)(d->dev + o_W); d->M4 = (double *)(d->dev + o_M4);
+    d->dgeo = (double *)(d->dev + o_dgeo); d->cidx = (int *)(d->dev + o_cidx);
     d->mask = d->dev + o_mask; d->uprev = (float *)(d->dev + o_up);
     d->dloc = (float *)(d->dev + o_dloc); d->D = (float *)(d->dev + o_D);
     rc = build_weights(g, weights, st, &c->w);
@@ -919,6 +925,8 @@ extern "C" int dnnmg_create_umesh(const dnnmg_config *cfg, const dnnmg_umesh *me
     up(d->feat, m.feat.data(), sizeof(float) * m.feat.size());
     up(d->W, m.W.data(), sizeof(double) * m.W.size());
     up(d->M4, m.M4.data(), sizeof(double) * m.M4.size());
+    up(d->dgeo, m.dgeo.data(), sizeof(double) * m.dgeo.size());
+    up(d->cidx, m.cidx.data(), sizeof(int) * m.cidx.size());
     up(d->mask, m.mask.data(), m.mask.size());
     if (e == hipSuccess) e = hipMemsetAsync(d->uprev, 0, sizeof(float) * 2 * (size_t)m.Fn, st);
     if (e == hipSuccess) e = hipMemsetAsync(c->h(), 0, sizeof(float) * (size_t)m.ne * g.H, st);

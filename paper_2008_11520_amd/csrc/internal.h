@@ -151,8 +151,11 @@ struct UArgs {
     const int *corners;              // P x 4
     const int *pmap;                 // P x nf
     const float *rel;                // P x nf x 2 (FP32: fine coordinates relative to v0)
-    const double *W;                 // P x 4 x nf: hat-weighted mass rows of the patch
-    const double *M4;                // P x 4 x 4: the same applied to P v (corner values)
+    const double *dgeo;              // P x 4: d0, d1, d2 of det J (straight patches: exact moments)
+    const int *cidx;                 // P: row of W and M4 of a patch with a curved edge, or -1
+    const double *W;                 // rows x 4 x nf: hat-weighted mass rows (curved patches)
+    const double *M4;                // rows x 4 x 4: the same applied to P v (corner values)
+    RhsTables tab;                   // the moment tables (straight patches)
     const float *feat;               // P x 4
     const unsigned char *mask;       // Fn: Dirichlet nodes
     const int *node_ptr, *node_occ;  // Fn + 1, P nf

@@ -14,8 +14,11 @@
 //   k_uaverage one thread per fine node: the mean of the patches' outputs,
 //              masked; the corrected velocity P v + d is the next u_prev;
 //   k_urhs     FP64: each patch's share of b^L = R (1/dt) M (P v + d) at its
-//              corners from its hat-weighted mass rows (formed at create from
-//              the fine elements' 2 x 2 Gauss points; R = P^T);
+//              corners: on a patch with straight edges (the bilinear image of
+//              the reference square) from exact moments of det J, as on
+//              structured meshes; on one with a curved edge from its
+//              hat-weighted mass rows (formed at create from the fine
+//              elements' 2 x 2 Gauss points); R = P^T;
 //   k_ugather  one thread per coarse node: the shares summed in patch order.
 // Sums over shared nodes are gathers in a fixed order: no atomics, bitwise
 // deterministic.  P v at a fine node is the bilinear interpolation, in the
@@ -297,38 +300,125 @@ hipError_t launch_uprolong(const UArgs &u, hipStream_t s)
 // four rows' entries l (consecutive lanes, consecutive addresses) and leaves
 // the eight products in LDS; thread (patch, corner, component) then sums them
 // over l in order.
+// One thread per patch.  Straight edges: with u the nodal values (a, b) of
+// the patch, the share at structured corner (cx, cy) is
+//   d0 S0 + d1 S1 + d2 S2,  S_k = sum_b A[my_k][cy][b] sum_a A[mx_k][cx][a] u(a, b)
+// ((mx, my) = (0, 0), (1, 0), (0, 1)), formed node row by node row as in the
+// structured rhs; the coarse term of P v from the moment tables M likewise.
+// (one wave per block: the patches are few for the chip, so small blocks
+// spread them over every CU; for K <= 2 all of a patch's map entries and then
+// all its corrections are loaded before any arithmetic: two memory round
+// trips per patch instead of two per node row)
+constexpr int kURhsThreads = 64;
+
 template <int K>
-__global__ __launch_bounds__(kThreads) void k_urhs(UArgs u, const float *dbar)
+__global__ __launch_bounds__(kURhsThreads) void k_urhs(UArgs u, const float *dbar)
 {
-    constexpr int n = 1 << K, nf = (n + 1) * (n + 1), PPB = kThreads / nf;
-    __shared__ double s_pr[PPB * nf * 8];
-    const int tid = threadIdx.x, pb = tid / nf, l = tid - pb * nf;
-    const int e = blockIdx.x * PPB + pb;
-    if (pb < PPB && e < u.P) {
-        const float2 d = reinterpret_cast<const float2 *>(dbar)[u.pmap[(size_t)e * nf + l]];
-        const double *Wp = u.W + (size_t)e * 4 * nf + l;
-        double *o = s_pr + (pb * nf + l) * 8;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const double w = Wp[c * nf];
-            o[2 * c] = w * (double)d.x;
-            o[2 * c + 1] = w * (double)d.y;
-        }
+    constexpr int n = 1 << K, nf = (n + 1) * (n + 1);
+    constexpr int NA = 4 * (n + 1), NM = 48;
+    constexpr bool ALL = K <= 2;
+    __shared__ double s_A[NA], s_M[NM];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < NA + NM; t += kURhsThreads) {
+        if (t < NA) s_A[t] = u.tab.A[t];
+        else s_M[t - NA] = u.tab.M[t - NA];
     }
     __syncthreads();
-    if (tid >= PPB * 8) return;
-    const int q = tid >> 3, j = tid & 7, c = j >> 1, comp = j & 1;
-    const int eq = blockIdx.x * PPB + q;
-    if (eq >= u.P) return;
-    const int *cn = u.corners + 4 * (size_t)eq;
-    const float *v1 = u.v;
-    const double *M = u.M4 + 16 * (size_t)eq + 4 * c;
-    double acc = 0.0;
+    const int e = blockIdx.x * kURhsThreads + tid;
+    if (e >= u.P) return;
+    const int *pm = u.pmap + (size_t)e * nf;
+    const float2 *d2 = reinterpret_cast<const float2 *>(dbar);
+    float2 wall[ALL ? nf : 1];
+    if constexpr (ALL) {
+        int f[nf];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc += M[k] * (double)v1[2 * cn[k] + comp];
-    const double *pr = s_pr + q * nf * 8 + j;
-    for (int i = 0; i < nf; ++i) acc += pr[8 * i];
-    u.part[8 * (size_t)eq + j] = u.inv_dt64 * acc;
+        for (int l = 0; l < nf; ++l) f[l] = pm[l];
+#pragma unroll
+        for (int l = 0; l < nf; ++l) wall[l] = d2[f[l]];
+    }
+    const int *cn = u.corners + 4 * (size_t)e;
+    const float2 *v2 = reinterpret_cast<const float2 *>(u.v);
+    float2 cv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cv[k] = v2[cn[k]];
+    const int ci = u.cidx[e];
+    double out[4][2];     // [corner (00, 10, 11, 01)][component]
+    if (ci < 0) {
+        const double *g = u.dgeo + 4 * (size_t)e;
+        const double g0 = g[0], g1 = g[1], g2 = g[2];
+        // S[cs][k][comp], cs the structured corner cx + 2 cy
+        double S[4][3][2];
+#pragma unroll
+        for (int cs = 0; cs < 4; ++cs)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) S[cs][k][0] = S[cs][k][1] = 0.0;
+#pragma unroll
+        for (int b = 0; b <= n; ++b) {
+            float2 w[n + 1];
+#pragma unroll
+            for (int a = 0; a <= n; ++a) w[a] = ALL ? wall[(b * (n + 1) + a) % (ALL ? nf : 1)] : d2[pm[b * (n + 1) + a]];
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                double s0x = 0.0, s0y = 0.0, s1x = 0.0, s1y = 0.0;
+#pragma unroll
+                for (int a = 0; a <= n; ++a) {
+                    const double a0 = s_A[(0 * 2 + cx) * (n + 1) + a], a1 = s_A[(1 * 2 + cx) * (n + 1) + a];
+                    s0x += a0 * (double)w[a].x; s0y += a0 * (double)w[a].y;
+                    s1x += a1 * (double)w[a].x; s1y += a1 * (double)w[a].y;
+                }
+#pragma unroll
+                for (int cy = 0; cy < 2; ++cy) {
+                    const double y0 = s_A[(0 * 2 + cy) * (n + 1) + b], y1 = s_A[(1 * 2 + cy) * (n + 1) + b];
+                    double (&T)[3][2] = S[cx + 2 * cy];
+                    T[0][0] += y0 * s0x; T[0][1] += y0 * s0y;
+                    T[1][0] += y0 * s1x; T[1][1] += y0 * s1y;
+                    T[2][0] += y1 * s0x; T[2][1] += y1 * s0y;
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int cs = c ^ (c >> 1);
+#pragma unroll
+            for (int comp = 0; comp < 2; ++comp) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int ks = k ^ (k >> 1);
+                    const double m = g0 * s_M[(0 * 4 + cs) * 4 + ks] + g1 * s_M[(1 * 4 + cs) * 4 + ks] +
+                                     g2 * s_M[(2 * 4 + cs) * 4 + ks];
+                    acc += m * (double)(comp ? cv[k].y : cv[k].x);
+                }
+                out[c][comp] = acc + g0 * S[cs][0][comp] + g1 * S[cs][1][comp] + g2 * S[cs][2][comp];
+            }
+        }
+    } else {
+        // a curved edge: the stored rows
+        const double *W = u.W + (size_t)ci * 4 * nf, *M = u.M4 + 16 * (size_t)ci;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double ax = 0.0, ay = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                ax += M[4 * c + k] * (double)cv[k].x;
+                ay += M[4 * c + k] * (double)cv[k].y;
+            }
+            out[c][0] = ax;
+            out[c][1] = ay;
+        }
+        for (int l = 0; l < nf; ++l) {
+            const float2 w = ALL ? wall[l % (ALL ? nf : 1)] : d2[pm[l]];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double r = W[c * nf + l];
+                out[c][0] += r * (double)w.x;
+                out[c][1] += r * (double)w.y;
+            }
+        }
+    }
+    double2 *o = reinterpret_cast<double2 *>(u.part + 8 * (size_t)e);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) o[c] = make_double2(u.inv_dt64 * out[c][0], u.inv_dt64 * out[c][1]);
 }
 
 hipError_t launch_urhs(const UArgs &u, const float *dbar, hipStream_t s)
@@ -336,8 +426,8 @@ hipError_t launch_urhs(const UArgs &u, const float *dbar, hipStream_t s)
     switch (u.K) {
 #define DNNMG_URHS(KK)                                                                                \
     case KK: {                                                                                        \
-        constexpr int ppb = kThreads / (((1 << KK) + 1) * ((1 << KK) + 1));                          \
-        hipLaunchKernelGGL(k_urhs<KK>, dim3((u.P + ppb - 1) / ppb), dim3(kThreads), 0, s, u, dbar); \
+        hipLaunchKernelGGL(k_urhs<KK>, dim3((u.P + kURhsThreads - 1) / kURhsThreads), dim3(kURhsThreads), 0, s, \
+                           u, dbar);                                                                  \
         break;                                                                                        \
     }
         DNNMG_URHS(1)

@@ -25,11 +25,18 @@ struct UMeshHost {
     std::vector<int> node_ptr, node_occ;    // Fn + 1, ne nf (patch nf + l, patch order)
     std::vector<int> cnode_ptr, cnode_occ;  // nc + 1, 4 ne (patch 4 + corner)
     std::vector<float> feat;            // ne x 4: hx, hy, hx / hy, area
-    // the patch's mass products weighted by its coarse hats (static geometry):
-    // its share of R M_f u at corner c is sum_l W[c][l] u_l, and for u = P v
-    // inside the patch sum_k M4[c][k] v_k
-    std::vector<double> W;              // ne x 4 x nf
-    std::vector<double> M4;             // ne x 4 x 4
+    // A patch with straight edges is the bilinear image of the reference
+    // square, its fine elements those of the uniform sub-squares: its mass
+    // products against the coarse hats are exact moments of det J = d0 + d1 s
+    // + d2 t (the structured rhs tables).  dgeo: d0, d1, d2 (and 0) per patch.
+    std::vector<double> dgeo;           // ne x 4
+    // A patch with a curved edge keeps its mass products weighted by its
+    // coarse hats (static geometry): its share of R M_f u at corner c is
+    // sum_l W[c][l] u_l, and for u = P v inside the patch sum_k M4[c][k] v_k.
+    // cidx: the patch's row of W and M4, or -1 (straight edges).
+    std::vector<int> cidx;              // ne
+    std::vector<double> W;              // (patches with a curved edge) x 4 x nf
+    std::vector<double> M4;             // (patches with a curved edge) x 4 x 4
 };
 
 namespace umesh_detail {
@@ -236,8 +243,25 @@ inline std::string build_umesh(int nc, int ne, const double *xy, const int *elem
     // hat-weighted mass rows: 2 x 2 Gauss points on every fine element's own
     // bilinear map; W[c][l_j] += sum_q w |det| N_j(q) sum_k H_c(l_k) N_k(q),
     // H_c(l) the coarse hat of corner c at patch-local node l
-    m.W.assign((size_t)ne * 4 * nf, 0.0);
-    m.M4.assign((size_t)ne * 16, 0.0);
+    m.dgeo.assign(4 * (size_t)ne, 0.0);
+    m.cidx.assign((size_t)ne, -1);
+    int ncp = 0;
+    for (int e = 0; e < ne; ++e) {
+        const int *v = elems + 4 * e;
+        const double *x0 = xy + 2 * v[0], *x1 = xy + 2 * v[1], *x2 = xy + 2 * v[2], *x3 = xy + 2 * v[3];
+        const double exx = x1[0] - x0[0], exy = x1[1] - x0[1], eyx = x3[0] - x0[0], eyy = x3[1] - x0[1];
+        const double fx = x2[0] - x1[0] - x3[0] + x0[0], fy = x2[1] - x1[1] - x3[1] + x0[1];
+        double *g = &m.dgeo[4 * (size_t)e];
+        g[0] = exx * eyy - eyx * exy;
+        g[1] = exx * fy - fx * exy;
+        g[2] = fx * eyy - eyx * fy;
+        const int ends[4][2] = {{v[0], v[1]}, {v[1], v[2]}, {v[3], v[2]}, {v[0], v[3]}};
+        bool curved = false;
+        for (int k = 0; k < 4; ++k) curved = curved || curve_of(ends[k][0], ends[k][1]) >= 0;
+        if (curved) m.cidx[e] = ncp++;
+    }
+    m.W.assign((size_t)ncp * 4 * nf, 0.0);
+    m.M4.assign((size_t)ncp * 16, 0.0);
     {
         const double g[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
         auto hat = [&](int c, int l) {
@@ -245,7 +269,8 @@ inline std::string build_umesh(int nc, int ne, const double *xy, const int *elem
             return c == 0 ? (1 - s) * (1 - t) : c == 1 ? s * (1 - t) : c == 2 ? s * t : (1 - s) * t;
         };
         for (int e = 0; e < ne; ++e) {
-            double *We = &m.W[(size_t)e * 4 * nf];
+            if (m.cidx[e] < 0) continue;
+            double *We = &m.W[(size_t)m.cidx[e] * 4 * nf];
             for (int b = 0; b < n; ++b)
                 for (int a = 0; a < n; ++a) {
                     const int l00 = b * (n + 1) + a, ls[4] = {l00, l00 + 1, l00 + n + 1, l00 + n + 2};
@@ -271,7 +296,7 @@ inline std::string build_umesh(int nc, int ne, const double *xy, const int *elem
                 for (int k = 0; k < 4; ++k) {
                     double acc = 0.0;
                     for (int l = 0; l < nf; ++l) acc += We[(size_t)c * nf + l] * hat(k, l);
-                    m.M4[(size_t)e * 16 + 4 * c + k] = acc;
+                    m.M4[(size_t)m.cidx[e] * 16 + 4 * c + k] = acc;
                 }
         }
     }
