@@ -1306,10 +1306,16 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
         f4 az[RTW], ar[RTW], ah[RTW];
 #pragma unroll
         for (int q = 0; q < RTW; ++q) az[q] = ar[q] = ah[q] = f4{0.f, 0.f, 0.f, 0.f};
+        // (each chunk requests the next chunk's fragments before its products,
+        // so the products never wait for the chunk's own)
+        bf8 wz = B1[((0 * HT + ht) * KC1 + 0) * 64 + lane];
+        bf8 wr = B1[((1 * HT + ht) * KC1 + 0) * 64 + lane];
+        bf8 wh = B1[((2 * HT + ht) * KC1 + 0) * 64 + lane];
         auto chunk = [&](int kc, const __bf16 *base, int pitch, int lrow) {
-            const bf8 wz = B1[((0 * HT + ht) * KC1 + kc) * 64 + lane];
-            const bf8 wr = B1[((1 * HT + ht) * KC1 + kc) * 64 + lane];
-            const bf8 wh = B1[((2 * HT + ht) * KC1 + kc) * 64 + lane];
+            const int kn = min(kc + 1, KC1 - 1);
+            const bf8 nz = B1[((0 * HT + ht) * KC1 + kn) * 64 + lane];
+            const bf8 nr = B1[((1 * HT + ht) * KC1 + kn) * 64 + lane];
+            const bf8 nh = B1[((2 * HT + ht) * KC1 + kn) * 64 + lane];
 #pragma unroll
             for (int q = 0; q < RTW; ++q) {
                 const bf8 a = *reinterpret_cast<const bf8 *>(&base[(16 * (rt0 + q) + lrow) * pitch]);
@@ -1317,6 +1323,9 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
                 ar[q] = O::mma(ar[q], wr, a);
                 ah[q] = O::mma(ah[q], wh, a);
             }
+            wz = nz;
+            wr = nr;
+            wh = nh;
         };
 #pragma unroll 1
         for (int kc = 0; kc < KX; ++kc) chunk(kc, sX + kc * KC + lq * KQ, nin, li);
