@@ -3,7 +3,7 @@
  *
  * The library performs, for one or many flows, the work that DNN-MG does in
  * place of fine-level multigrid at every time step (Margenberg, Hartmann,
- * Lessig, Richter, arXiv 2008.11520, Algorithm 2, lines 6-9; Sec. 4.1):
+ * Lessig, Richter, arXiv 2008.11520, the fine-level part of Algorithm 2; Sec. 4.1):
  *   1. prolongation of the coarse (level L) velocity and pressure to level L+K,
  *   2. element-wise assembly of the fine Navier-Stokes defect (momentum rows of
  *      the nonlinear residual of Eq. (nonlinearshort), implicit-Euler form),
@@ -183,7 +183,8 @@ int dnnmg_create(const dnnmg_config *cfg, const double *coarse_xy_host,
 int dnnmg_create_shared(const dnnmg_config *cfg, const double *coarse_xy_host,
                         const dnnmg_ctx *model, void *stream, dnnmg_ctx **out);
 
-/* One fine DNN-MG step (Alg. 2, lines 6-8).
+/* One fine DNN-MG step (Alg. 2: prolongation, network correction, corrected
+ * velocity).
  * v_coarse_dev: device, (ny+1)(nx+1) x 2 FP32 coarse velocity v_n^L.
  * p_coarse_dev: device, (ny+1)(nx+1) FP32 coarse pressure, or NULL (= 0).
  * d_fine_dev:   device, optional (NULL to skip), Fn x 2 FP32: the averaged,
@@ -194,7 +195,7 @@ int dnnmg_create_shared(const dnnmg_config *cfg, const double *coarse_xy_host,
 int dnnmg_step(dnnmg_ctx *ctx, const float *v_coarse_dev, const float *p_coarse_dev,
                float *d_fine_dev, void *stream);
 
-/* Restricted right-hand side of the most recent step (Alg. 2, line 9):
+/* Restricted right-hand side of the most recent step (Alg. 2, restriction):
  * b_coarse_dev: device, (ny+1)(nx+1) x 2 doubles,
  *   b^L = P^T (1/dt) M_f (P v + d), accumulated in FP64 from the stored FP32
  *   corrected velocity P v + d (the state the next step reads; implicit
@@ -262,13 +263,13 @@ int dnnmg_destroy(dnnmg_ctx *ctx);
  *                                local edges (v0,v1), (v1,v2), (v3,v2), (v0,v3);
  *   Nc + E (n-1) + e (n-1)^2 + (b-1)(n-1) + a - 1
  *                                the inner node (a, b) of element e.
- * The step is the structured one's (Alg. 2, lines 6-9; implicit Euler, the
+ * The step is the structured one's (the fine part of Alg. 2; implicit Euler, the
  * workloads' network) with the mesh's own operators: P v at a fine node is the
  * bilinear interpolation, in the reference coordinates of the first element
  * that holds it, of that element's corner values; the defect and the mass
  * matrix are assembled over the fine elements (2 x 2 Gauss points on each
- * fine element's own bilinear map); duplicate predictions are averaged over
- * every patch that holds a node; R = P^T.  Patch-local node order and the
+ * fine element's own bilinear map); a node's correction is the mean of the
+ * outputs of every patch that holds it; R = P^T.  Patch-local node order and the
  * network input are those of the structured form, the features taken from
  * each element's four corners (hx the mean of edges (v0,v1), (v3,v2); hy of
  * (v0,v3), (v1,v2); hx / hy; the straight quadrilateral's area). */
@@ -340,7 +341,7 @@ const char *dnnmg_last_error(void);
  * for per-output verification.  None of them changes the flow's state.
  * ------------------------------------------------------------------- */
 
-/* Prolongation (Alg. 2, line 6): pv_out Fn x 2 and pp_out Fn (either may be
+/* Prolongation (Alg. 2, its first fine step): pv_out Fn x 2 and pp_out Fn (either may be
  * NULL) from the coarse v (and p, NULL = 0). */
 int dnnmg_prolong(dnnmg_ctx *ctx, const float *v_coarse_dev, const float *p_coarse_dev,
                   float *pv_out_dev, float *pp_out_dev, void *stream);
@@ -350,7 +351,7 @@ int dnnmg_prolong(dnnmg_ctx *ctx, const float *v_coarse_dev, const float *p_coar
 int dnnmg_defect(dnnmg_ctx *ctx, const float *v_coarse_dev, const float *p_coarse_dev,
                  float *D_out_dev, void *stream);
 
-/* Right-hand side and restriction alone (Alg. 2, lines 8-9) for a given fine
+/* Right-hand side and restriction alone (Alg. 2, its last two steps) for a given fine
  * correction: b_out = P^T (1/dt) M_f (P v + dbar), FP64.  dbar_dev Fn x 2. */
 int dnnmg_rhs_restrict(dnnmg_ctx *ctx, const float *v_coarse_dev, const float *dbar_dev,
                        double *b_out_dev, void *stream);

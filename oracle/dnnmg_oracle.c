@@ -6,7 +6,7 @@
  * header, table or constant with the GPU library; both are fed from the
  * seeded input generators.
  *
- * What it computes: one step of Algorithm 2 (lines 6-9) of the paper --
+ * What it computes: the fine-level part of one step of Algorithm 2 of the paper --
  * prolongation of the coarse velocity, the fine Navier-Stokes defect, the
  * per-patch GRU + MLP correction, duplicate averaging, the fine right-hand
  * side and its restriction -- in the implicit-Euler, Q1/Q1 form used by the
@@ -123,7 +123,7 @@ void orc_fine_coords(int nx, int ny, int K, const double *cxy, double *fxy)
 
 /* ---------------------------------------------------- step 2: prolongation */
 /* P: interpolation of the coarse Q1 function at the fine nodes (Alg. 2,
- * line 6; grid transfer of Sec. 3.4).  ncomp values per node. */
+ * prolongation; grid transfer of Sec. 3.4).  ncomp values per node. */
 void orc_prolong(int nx, int ny, int K, int ncomp, const double *coarse, double *fine)
 {
     int n = 1 << K;
@@ -148,7 +148,7 @@ void orc_prolong(int nx, int ny, int K, int ncomp, const double *coarse, double 
 
 /* --------------------------------------------------- step 10: restriction */
 /* R = P^T: the transpose of the prolongation above, applied to a dual
- * (right-hand-side) vector (Alg. 2, line 9). */
+ * (right-hand-side) vector (Alg. 2, restriction). */
 void orc_restrict(int nx, int ny, int K, int ncomp, const double *fine, double *coarse)
 {
     int n = 1 << K;
@@ -749,8 +749,8 @@ void orc_average(int nx, int ny, int K, const double *dpatch, unsigned dir, doub
 }
 
 /* -------------------------------------------- steps 9-10 as one operation */
-/* b_L = R (1/dt) M_f u_corr with u_corr = P v + Dbar (Alg. 2, lines 8-9,
- * implicit-Euler right-hand side, no body force).  v is the coarse
+/* b_L = R (1/dt) M_f u_corr with u_corr = P v + Dbar (Alg. 2, right-hand
+ * side and restriction, implicit-Euler right-hand side, no body force).  v is the coarse
  * velocity, Dbar the fine correction. */
 void orc_rhs_restrict(int nx, int ny, int K, const double *cxy, const double *v,
                       const double *Dbar, double dt, double *bL)
@@ -1553,7 +1553,7 @@ void orc_u_rhs_restrict(int nc, int ne, int K, const int *elems, const int *pmap
     free(Mu);
 }
 
-/* One fine step (Alg. 2, lines 6-9; implicit Euler, the workloads' network)
+/* One fine step (the fine part of Alg. 2; implicit Euler, the workloads' network)
  * on the refined unstructured mesh: orc_step with the mesh's own prolongation,
  * defect, patch inputs, averaging and rhs.  State h (ne x H), uprev (Fn x 2);
  * optional outputs as orc_step (D, X, dpatch, Dbar over the fine nodes,
@@ -1596,7 +1596,7 @@ int orc_u_step(int nc, int ne, const double *xy, const int *elems, int K, int H,
 }
 
 /* ---------------------------------------------------------- the full step */
-/* One DNN-MG fine step (Alg. 2, lines 6-9) for given coarse v, p, with the
+/* One DNN-MG fine step (the fine part of Alg. 2) for given coarse v, p, with the
  * time scheme's weight theta (1: implicit Euler; 1/2: Crank-Nicolson as in
  * Eq. (4cranknicholson3); see orc_defect_theta, orc_rhs_restrict_theta).
  * form 0: the workloads' network, inputs [P v, D, hx, hy, aspect, area] and

@@ -1,9 +1,9 @@
 """Coarse-level Navier-Stokes solver of the closed DNN-MG loop.
 
-Algorithm 2, lines 2-5 of the paper: at every time step the coarse velocity
+The coarse part of Algorithm 2 of the paper: at every time step the coarse velocity
 and pressure (v_n, p_n) on level L are found by Newton's method for the
 discrete problem, whose right-hand side is the restricted fine right-hand
-side b_L of the previous step (line 9).  Here, as in the fine step:
+side b_L of the previous step (its restriction).  Here, as in the fine step:
 
 * Q1 velocity and Q1 pressure on a structured quadrilateral mesh (possibly
   perturbed; bilinear element maps), 2 x 2 Gauss quadrature;

@@ -5,7 +5,7 @@
 //   D_a,c = sum_e sum_q w_q |det J_q| [ (1/dt) phi_a (u_prev - v)_c - phi_a (v.grad v_c)
 //                                       - nu grad phi_a . grad v_c + p d_c phi_a ]
 // evaluated on the prolongated coarse fields v = P v_L, p = P p_L (Alg. 2,
-// line 6) and zeroed at Dirichlet nodes.  One workgroup owns a 32 x 32 tile of
+// prolongation) and zeroed at Dirichlet nodes.  One workgroup owns a 32 x 32 tile of
 // fine elements plus a ring of one halo element, so that the nodes on the tile
 // border get every element contribution without global atomics; element
 // residuals go to LDS and are summed per node in a fixed order (bitwise
@@ -98,7 +98,7 @@ hipError_t launch_geometry(const double *cxy, int nx, int ny, float *geo, double
 
 // ------------------------------------------------------------ prolongation
 // Bilinear interpolation of the coarse corner values of the element that
-// holds fine node (I,J) (Alg. 2, line 6).
+// holds fine node (I,J) (Alg. 2, prolongation).
 template <int K>
 __device__ inline void prolong_node(const float *__restrict__ v, const float *__restrict__ p, int nx, int ny,
                                     int I, int J, float &vx, float &vy, float &pp)

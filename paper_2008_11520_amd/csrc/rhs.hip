@@ -5,7 +5,7 @@
 //      nodes over the 1, 2 or 4 patches that contain the node (Sec. 4.2),
 //      zeroes Dirichlet nodes, and stores the corrected velocity P v + d as the
 //      state for the next defect (the patch that owns a node writes it);
-//   2. forms its share of b_L = P^T (1/dt) M_f (P v + d) (Alg. 2, lines 8-9) at
+//   2. forms its share of b_L = P^T (1/dt) M_f (P v + d) (Alg. 2, rhs + restriction) at
 //      its four corners, in FP64.
 // Step 2 uses exact moment tables instead of fine quadrature.  With the
 // coarse map F, det J = d0 + d1 xi + d2 eta is affine, so for the coarse hat N_c

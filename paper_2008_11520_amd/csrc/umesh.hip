@@ -1,7 +1,7 @@
 // The fine DNN-MG step on unstructured quadrilateral meshes (explicit
 // connectivity; fine nodes on curved edges moved onto the curve).
 //
-// Per step (Alg. 2, lines 6-9), all data addressed through the patch maps:
+// Per step (the fine part of Alg. 2), all data addressed through the patch maps:
 //   k_udefect  one thread per fine element: the element residual of the
 //              defect (quad_residual: its own bilinear map and nodal P v, P p,
 //              u_prev), summed per patch-local node in LDS in four colour

@@ -1,9 +1,9 @@
 """The closed DNN-MG time loop (Algorithm 2) on one flow.
 
 Per time step n:
-  lines 2-5: the coarse Newton solve for (v_n, p_n) on level L with the
+  coarse:    the coarse Newton solve for (v_n, p_n) on level L with the
              right-hand side b_L of the previous step (coarse.CoarseNS);
-  lines 6-9: the fine step on level L+K (prolongation, defect, GRU + MLP
+  fine:      the fine step on level L+K (prolongation, defect, GRU + MLP
              correction, right-hand side of the corrected velocity, its
              restriction), whose b_L is the next coarse right-hand side.
 The first coarse solve takes the coarse right-hand side of v_0,
