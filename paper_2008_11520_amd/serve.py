@@ -81,8 +81,8 @@ class Active:
     req: dict
     idx: int                 # the request's row in the server's per-request arrays
     ctx: DnnMG
-    vring: object            # (ring, Nc*2) float32 device tensor
-    pring: object            # (ring, Nc) float32 device tensor
+    vring: object            # (ring, Nc*2) float32 device view (its row stride spans the flow's ring group)
+    pring: object            # (ring, Nc) float32 device view (likewise)
     b_out: object            # (Nc*2,) float64 device tensor: restricted rhs of the last step
     admitted: float = 0.0
 
@@ -137,28 +137,64 @@ class Server:
         """Arena bytes of one request's flow (state and workspace)."""
         return Arena.block_bytes(self.config(nx, ny))
 
-    def admit(self, req, idx, now):
-        """The request's context in the arena and its field ring, enqueued on
-        the serving stream; None if the arena has no block for it yet."""
+    # nodes of one group evaluation of the field rings (its FP64 temporaries
+    # take about 0.5 KB per node)
+    RING_GROUP_NODES = 1 << 18
+
+    def admit_group(self, reqs, now):
+        """Contexts in the arena for reqs, in order, and their field rings,
+        all enqueued on the serving stream.  Returns (admitted Active list,
+        the requests from the first one the arena has no block for yet)."""
         import torch
-        nx, ny = req["nx"], req["ny"]
-        cxy = synth.rect_mesh(nx, ny, synth.CHANNEL_LX, synth.CHANNEL_LY)
-        ff = synth.FourierField(synth.CHANNEL_LX, synth.CHANNEL_LY, req["field_seed"])
+        made = []
         with torch.cuda.stream(self.stream):
-            try:
-                ctx = DnnMG(self.config(nx, ny), cxy, share=self.model, stream=self.stream, arena=self.arena)
-            except DnnmgError as e:
-                if e.code == DNNMG_ENOMEM:
-                    return None
-                raise
-            xy = synth.rect_mesh_torch(nx, ny, synth.CHANNEL_LX, synth.CHANNEL_LY, "cuda")
-            times = self.dt * torch.arange(self.ring, dtype=torch.float64, device="cuda")
-            v, p = synth.fields_torch_calibrated(ff, xy, times, inflow_max=1.5, height=synth.CHANNEL_LY,
-                                                 upload=lambda dst, src: self.arena.upload(dst, src, self.stream))
-            vring = v.reshape(self.ring, -1).float().contiguous()
-            pring = p.float().contiguous()
-            b_out = torch.empty(2 * ctx.s["Nc"], dtype=torch.float64, device="cuda")
-        return Active(req, idx, ctx, vring, pring, b_out, admitted=now)
+            for i, r in enumerate(reqs):
+                cxy = synth.rect_mesh(r["nx"], r["ny"], synth.CHANNEL_LX, synth.CHANNEL_LY)
+                try:
+                    ctx = DnnMG(self.config(r["nx"], r["ny"]), cxy, share=self.model, stream=self.stream,
+                                arena=self.arena)
+                except DnnmgError as e:
+                    if e.code == DNNMG_ENOMEM:
+                        return self._rings(made, now), list(reqs[i:])
+                    raise
+                made.append((r, ctx))
+            return self._rings(made, now), []
+
+    def _rings(self, made, now):
+        """Field rings of (request, context) pairs, evaluated in groups of at
+        most RING_GROUP_NODES nodes (a flow's values do not depend on its
+        group), as Active records."""
+        import torch
+        out = []
+        times = self.dt * np.arange(self.ring, dtype=np.float64)
+        i = 0
+        while i < len(made):
+            j, nodes = i, 0
+            while j < len(made) and (j == i or nodes + made[j][1].s["Nc"] <= self.RING_GROUP_NODES):
+                nodes += made[j][1].s["Nc"]
+                j += 1
+            grp = made[i:j]
+            ffs = [synth.FourierField(synth.CHANNEL_LX, synth.CHANNEL_LY, r["field_seed"]) for r, _ in grp]
+            v, p, offs = synth.channel_rings_torch(
+                ffs, [(r["nx"], r["ny"]) for r, _ in grp], times, synth.CHANNEL_LX, synth.CHANNEL_LY, 1.5,
+                synth.CHANNEL_LY, "cuda", upload=lambda dst, src: self.arena.upload(dst, src, self.stream))
+            v32, p32 = v.float(), p.float()       # ring x nodes (x 2), the group's flows in order
+            for k, (r, ctx) in enumerate(grp):
+                a, n = int(offs[k]), int(offs[k + 1] - offs[k])
+                # views of the group's FP32 arrays: level l of the flow is a
+                # contiguous run at vring[l], the row stride spans the group
+                vring = v32[:, a:a + n].reshape(self.ring, 2 * n)
+                pring = p32[:, a:a + n]
+                b_out = torch.empty(2 * ctx.s["Nc"], dtype=torch.float64, device="cuda")
+                out.append(Active(r, r.get("_idx", -1), ctx, vring, pring, b_out, admitted=now))
+            i = j
+        return out
+
+    def admit(self, req, idx, now):
+        """admit_group for one request; None if the arena has no block for it
+        yet."""
+        acts, rest = self.admit_group([dict(req, _idx=idx)], now)
+        return acts[0] if acts else None
 
     def retire(self, a, results=None, steps=0):
         import torch
@@ -246,19 +282,16 @@ class Server:
             # admissions, a few at a time while ticks are in flight (each
             # costs host time: its set-up and field ring are enqueued), so
             # the active flows' next tick is not held back by a burst
-            admitted = False
             cap = admit_burst if inflight else len(sched.queue)
-            for r in sched.admissible(limit=cap):
-                a = self.admit(r, r["_idx"], now())
-                if a is None:                 # the arena is fragmented: wait for a release
-                    sched.requeue(r)
-                    break
-                r["admitted_at"] = a.admitted
+            acts, unplaced = self.admit_group(sched.admissible(limit=cap), now())
+            for r in reversed(unplaced):      # the arena is fragmented: wait for a release
+                sched.requeue(r)
+            for a in acts:
+                a.req["admitted_at"] = a.admitted
                 eligible[a.idx] = a.admitted
                 active.append(a)
                 by_idx[a.idx] = a
-                admitted = True
-            if admitted:
+            if acts:
                 table = None
             stats["max_conc"] = max(stats["max_conc"], len(active))
             if active and len(inflight) < depth:

@@ -35,6 +35,19 @@ class SplitMix64:
         self.state = np.uint64(seed & 0xFFFFFFFFFFFFFFFF)
 
     def next_u64(self, n: int) -> np.ndarray:
+        if n <= 16:
+            # the same values from Python integers (a few draws cost less
+            # this way than through numpy's small-array calls)
+            mask = (1 << 64) - 1
+            s0, g = int(self.state), int(_GAMMA)
+            out = []
+            for k in range(1, n + 1):
+                z = (s0 + k * g) & mask
+                z = ((z ^ (z >> 30)) * int(_M1)) & mask
+                z = ((z ^ (z >> 27)) * int(_M2)) & mask
+                out.append(z ^ (z >> 31))
+            self.state = np.uint64((s0 + n * g) & mask)
+            return np.array(out, dtype=np.uint64)
         with np.errstate(over="ignore"):
             k = np.arange(1, n + 1, dtype=np.uint64)
             z = self.state + k * _GAMMA
@@ -262,6 +275,86 @@ def fields_torch_calibrated(ff: "FourierField", xy, times, inflow_max=0.0, heigh
 
 def torch_hypot_max(vx, vy):
     return (vx * vx + vy * vy).sqrt().max()
+
+
+def channel_rings_torch(ffs, meshes, times, lx, ly, inflow_max, height, device, upload=None):
+    """fields_torch_calibrated for a group of flows on rect_mesh(nx, ny, lx,
+    ly) meshes, evaluated together (a few tens of kernels for the group
+    instead of per flow).  ffs: FourierField per flow (same nmodes, pmodes);
+    meshes: (nx, ny) per flow.  Returns v (T x N x 2), p (T x N), FP64, the
+    flows' nodes one after another, and the F + 1 node offsets (flow f holds
+    nodes offs[f] .. offs[f+1]-1).  Every node value is formed by element-wise
+    operations only, the modes summed one after another, and the calibration
+    maxima are per flow, so a flow's values do not depend on which flows share
+    its group."""
+    import torch
+    F = len(ffs)
+    M, Mp = ffs[0].nmodes, ffs[0].pmodes
+    if any(f.nmodes != M or f.pmodes != Mp for f in ffs):
+        raise ValueError("all flows of a group need the same mode counts")
+    counts = np.array([(nx + 1) * (ny + 1) for nx, ny in meshes], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(counts)])
+    N = int(offs[-1])
+    times = np.asarray(times, dtype=np.float64).reshape(-1)
+    T = times.size
+    # one host array, one copy: per flow nx, ny, nx + 1, first node, the two
+    # amplitudes and the field constants; then the times (t = 0 first, for
+    # the calibration) and the node counts
+    c0 = 6
+    per = np.empty((F, c0 + 5 * M + 4 * Mp), dtype=np.float64)
+    for f, (ff, (nx, ny)) in enumerate(zip(ffs, meshes)):
+        per[f, :c0] = (nx, ny, nx + 1, offs[f], ff.amplitude, ff.p_amplitude)
+        per[f, c0:] = np.concatenate([ff.k[:, 0], ff.k[:, 1], ff.phi, ff.om,
+                                      2 * math.pi / np.hypot(ff.k[:, 0], ff.k[:, 1]),
+                                      ff.pk[:, 0], ff.pk[:, 1], ff.pphi, ff.pom])
+    host = np.concatenate([per.reshape(-1), [0.0], times, counts.astype(np.float64)])
+    if torch.device(device).type == "cpu":
+        buf = torch.from_numpy(host.copy())
+    elif upload is not None:
+        buf = torch.empty(host.size, dtype=torch.float64, device=device)
+        upload(buf, host)
+    else:
+        buf = torch.from_numpy(host).pin_memory().to(device, non_blocking=True)
+    dev = buf.device
+    per_t = buf[:per.size].reshape(per.shape)
+    t = buf[per.size:per.size + 1 + T].reshape(-1, 1)
+    cnt = buf[per.size + 1 + T:].to(torch.int64)
+    fid = torch.repeat_interleave(torch.arange(F, device=dev), cnt, output_size=N)
+    g = per_t.t()[:, fid]                            # the node's flow constants, one row per constant
+    local = torch.arange(N, device=dev) - g[3].to(torch.int64)
+    nx1 = g[2].to(torch.int64)
+    # rect_mesh_torch's arithmetic: (l * index) / n
+    x = lx * (local % nx1).double() / g[0]
+    y = ly * torch.div(local, nx1, rounding_mode="floor").double() / g[1]
+    kx = lambda m: g[c0 + m]
+    ky = lambda m: g[c0 + M + m]
+    phi = lambda m: g[c0 + 2 * M + m]
+    om = lambda m: g[c0 + 3 * M + m]
+    inv = lambda m: g[c0 + 4 * M + m]
+    pc = c0 + 5 * M
+    vx = torch.zeros(T + 1, N, dtype=torch.float64, device=dev)
+    vy = torch.zeros_like(vx)
+    p = torch.zeros_like(vx)
+    for m in range(M):
+        th = 2 * math.pi * (kx(m) * x / lx + ky(m) * y / ly) + phi(m) + om(m) * t
+        c = torch.cos(th) * inv(m)
+        vx += c * (ky(m) / ly)
+        vy -= c * (kx(m) / lx)
+    for m in range(Mp):
+        th = 2 * math.pi * (g[pc + m] * x / lx + g[pc + Mp + m] * y / ly) + g[pc + 2 * Mp + m] + g[pc + 3 * Mp + m] * t
+        p += torch.sin(th)
+    # calibration at t = 0: maxima over each flow's run of nodes (exact in
+    # any order)
+    mv = torch.segment_reduce((vx[0] * vx[0] + vy[0] * vy[0]).sqrt(), "max", lengths=cnt)
+    mp = torch.segment_reduce(p[0].abs(), "max", lengths=cnt)
+    one = torch.ones((), dtype=torch.float64, device=dev)
+    vscale = torch.where(mv > 0, per_t[:, 4] / torch.where(mv > 0, mv, one), one)[fid]
+    pscale = torch.where(mp > 0, per_t[:, 5] / torch.where(mp > 0, mp, one), one)[fid]
+    vx, vy, p = vx[1:] * vscale, vy[1:] * vscale, p[1:] * pscale
+    if inflow_max > 0.0:
+        prof = 4.0 * y * (height - y) / (height * height)
+        vx, vy = vx * prof + inflow_max * prof, vy * prof
+    return torch.stack([vx, vy], dim=-1), p, offs
 
 
 CHANNEL_LX, CHANNEL_LY = 2.2, 0.41

@@ -88,6 +88,34 @@ def test_device_calibrated_fields_match_numpy_fields(inflow):
         np.testing.assert_allclose(p[n].numpy().astype(np.float32), pn, rtol=0, atol=2e-6)
 
 
+@pytest.mark.parametrize("inflow", [0.0, 1.5])
+def test_grouped_field_rings_match_numpy_fields(inflow):
+    """The serving loop's field rings, evaluated for a group of flows at once,
+    give each flow's numpy fields, and a flow's values are those it gets when
+    evaluated alone."""
+    import torch
+    meshes = [(12, 5), (4, 1), (9, 3)]
+    seeds = [7, 8, 9]
+    times = [n * 0.005 for n in range(3)]
+    mk = lambda: [synth.FourierField(synth.CHANNEL_LX, synth.CHANNEL_LY, s) for s in seeds]
+    v, p, offs = synth.channel_rings_torch(mk(), meshes, times, synth.CHANNEL_LX, synth.CHANNEL_LY, inflow,
+                                           synth.CHANNEL_LY, "cpu")
+    assert v.shape == (3, offs[-1], 2) and p.shape == (3, offs[-1])
+    for f, ((nx, ny), s) in enumerate(zip(meshes, seeds)):
+        cxy = synth.rect_mesh(nx, ny, synth.CHANNEL_LX, synth.CHANNEL_LY)
+        ff = synth.FourierField(synth.CHANNEL_LX, synth.CHANNEL_LY, s).calibrate(cxy)
+        flow = synth.Flow(nx, ny, cxy, synth.DIR_CHANNEL, 0.005, ff, inflow_max=inflow)
+        a, b = offs[f], offs[f + 1]
+        v1, p1, o1 = synth.channel_rings_torch(mk()[f:f + 1], meshes[f:f + 1], times, synth.CHANNEL_LX,
+                                               synth.CHANNEL_LY, inflow, synth.CHANNEL_LY, "cpu")
+        np.testing.assert_allclose(v[:, a:b].numpy(), v1.numpy(), rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(p[:, a:b].numpy(), p1.numpy(), rtol=1e-14, atol=1e-15)
+        for n in range(3):
+            vn, pn = flow.fields(n)
+            np.testing.assert_allclose(v[n, a:b].numpy().astype(np.float32), vn, rtol=0, atol=2e-6)
+            np.testing.assert_allclose(p[n, a:b].numpy().astype(np.float32), pn, rtol=0, atol=2e-6)
+
+
 def test_device_mesh_equals_numpy_mesh():
     import torch
     for nx, ny in ((32, 8), (512, 128), (3, 1)):
