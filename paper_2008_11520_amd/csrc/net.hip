@@ -1160,13 +1160,22 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_q8p(FlowArgs single, 
 // per gate.  LDS holds three regions: the tile's input rows (pitch nin, which
 // keeps the fragment reads free of bank conflicts), the gate rows' state part
 // [h | 0] (later r * h, then the MLP hidden layer) and h'.  The next tile's
-// input rows are copied from global memory straight into their region, and
-// its FP32 state into registers, while the current tile runs its output
-// products; the weights of those products are requested first, so the waits
-// for them never wait for the copy.  A 128-patch tile is a pair of
+// input rows are copied from global memory straight into their region as
+// soon as the gate products are done with it, and its FP32 state into
+// registers once the update has read the current one, while the current tile
+// runs its state update, MLP and output products; the weights of those
+// products are requested first, so the waits for them never wait for the
+// copy.  A 128-patch tile is a pair of
 // the launch's 64-patch row tiles, each of which may belong to another flow
 // of a batch.
 constexpr int kWideRows = 128;
+
+// Workgroup barrier for LDS data only: this wave's LDS accesses complete,
+// then s_barrier.  Unlike __syncthreads() it does not wait for the wave's
+// outstanding global loads, so a copy into LDS (global_load_lds) of another
+// region can stay in flight across it.  (The memory clobber keeps the
+// compiler from moving memory accesses across it.)
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 template <int K, int H, int HM>
 __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single, const BatchTable *__restrict__ bt,
@@ -1306,13 +1315,16 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
         f4 az[RTW], ar[RTW], ah[RTW];
 #pragma unroll
         for (int q = 0; q < RTW; ++q) az[q] = ar[q] = ah[q] = f4{0.f, 0.f, 0.f, 0.f};
-        // (each chunk requests the next chunk's fragments before its products,
-        // so the products never wait for the chunk's own)
+        // (each chunk requests the fragments of the chunk two ahead before its
+        // products, so the products never wait for the chunk's own)
         bf8 wz = B1[((0 * HT + ht) * KC1 + 0) * 64 + lane];
         bf8 wr = B1[((1 * HT + ht) * KC1 + 0) * 64 + lane];
         bf8 wh = B1[((2 * HT + ht) * KC1 + 0) * 64 + lane];
+        bf8 vz = B1[((0 * HT + ht) * KC1 + 1) * 64 + lane];
+        bf8 vr = B1[((1 * HT + ht) * KC1 + 1) * 64 + lane];
+        bf8 vh = B1[((2 * HT + ht) * KC1 + 1) * 64 + lane];
         auto chunk = [&](int kc, const __bf16 *base, int pitch, int lrow) {
-            const int kn = min(kc + 1, KC1 - 1);
+            const int kn = min(kc + 2, KC1 - 1);
             const bf8 nz = B1[((0 * HT + ht) * KC1 + kn) * 64 + lane];
             const bf8 nr = B1[((1 * HT + ht) * KC1 + kn) * 64 + lane];
             const bf8 nh = B1[((2 * HT + ht) * KC1 + kn) * 64 + lane];
@@ -1323,9 +1335,12 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
                 ar[q] = O::mma(ar[q], wr, a);
                 ah[q] = O::mma(ah[q], wh, a);
             }
-            wz = nz;
-            wr = nr;
-            wh = nh;
+            wz = vz;
+            wr = vr;
+            wh = vh;
+            vz = nz;
+            vr = nr;
+            vh = nh;
         };
 #pragma unroll 1
         for (int kc = 0; kc < KX; ++kc) chunk(kc, sX + kc * KC + lq * KQ, nin, li);
@@ -1342,10 +1357,25 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
         for (int kc = KX + 1; kc < KC1; ++kc) chunk(kc, sG + (kc * KC + lq * KQ - nin), LDG, li);
         __syncthreads();   // every wave is done with sX and sG
 
+        // the weights of U_h, of the MLP hidden layer and of this wave's
+        // output tiles (ht, ht + HT, ...), requested before the copy below so
+        // that the waits for them do not wait for the copy
         bf8 w2[HC], w3[HC];
 #pragma unroll
         for (int kc = 0; kc < HC; ++kc) w2[kc] = B2[(ht * HC + kc) * 64 + lane];
-
+        if constexpr (HM > 0) {
+#pragma unroll
+            for (int kc = 0; kc < HC; ++kc) w3[kc] = B3[(ht * HC + kc) * 64 + lane];
+        }
+        const gptr<bf8> Wo = HM > 0 ? B4 : B3;
+        constexpr int NOT = (OT + HT - 1) / HT;
+        bf8 wo[NOT][HC];
+#pragma unroll
+        for (int j = 0; j < NOT; ++j) {
+            const int ot = min(ht + j * HT, OT - 1);
+#pragma unroll
+            for (int kc = 0; kc < HC; ++kc) wo[j][kc] = Wo[(ot * HC + kc) * 64 + lane];
+        }
 #pragma unroll
         for (int q = 0; q < RTW; ++q) {
             const int r = 16 * (rt0 + q) + li;
@@ -1357,7 +1387,17 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
             }
             *reinterpret_cast<bf4 *>(&sG[r * LDH + ucol]) = rh;
         }
-        __syncthreads();
+        // the next tile's input rows, copied into sX (free from here on) while
+        // this tile runs its state update, MLP and output products.  The
+        // weights above land first: while a copy into LDS is outstanding, a
+        // wait for any load waits for the copy too.  The barriers until the
+        // tile's end are lds_barrier(), which do not wait for the copy.  (The
+        // last tile of the block copies itself again: no branch.)
+        __builtin_amdgcn_s_waitcnt(0);
+        const int nt = more ? tile + (int)gridDim.x : tile;
+        const Half na = half_of(2 * nt), nb = half_of(2 * nt + 1);
+        fill_x(na, nb);
+        lds_barrier();
 
         // ---- U_h (r * h); new state
 #pragma unroll
@@ -1381,22 +1421,9 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
             if ((r & 63) < hh.nrows) *(__attribute__((address_space(1))) f4 *)(hh.h + (r & 63) * H + ucol) = hn;
             *reinterpret_cast<bf4 *>(&sHp[r * LDH + ucol]) = hb4;
         }
-        // weights of the MLP hidden layer and of this wave's output tiles
-        // (ht, ht + HT, ...)
-        if constexpr (HM > 0) {
-#pragma unroll
-            for (int kc = 0; kc < HC; ++kc) w3[kc] = B3[(ht * HC + kc) * 64 + lane];
-        }
-        const gptr<bf8> Wo = HM > 0 ? B4 : B3;
-        constexpr int NOT = (OT + HT - 1) / HT;
-        bf8 wo[NOT][HC];
-#pragma unroll
-        for (int j = 0; j < NOT; ++j) {
-            const int ot = min(ht + j * HT, OT - 1);
-#pragma unroll
-            for (int kc = 0; kc < HC; ++kc) wo[j][kc] = Wo[(ot * HC + kc) * 64 + lane];
-        }
-        __syncthreads();
+        // the next tile's state (this tile's is no longer read)
+        load_hold(na, nb);
+        lds_barrier();
 
         // ---- MLP head
         const __bf16 *src = sHp;
@@ -1413,21 +1440,8 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
                 for (int e = 0; e < 4; ++e) m[e] = (__bf16)fmaxf(acc[e], 0.f);
                 *reinterpret_cast<bf4 *>(&sG[r * LDH + ucol]) = m;
             }
-            __syncthreads();
+            lds_barrier();
             src = sG;
-        }
-        // the next tile's input rows and state, in flight during the output
-        // products.  Issued after the last barrier of the tile (a barrier
-        // would wait for the copy into LDS) and after the output weights
-        // have landed (while the copy is outstanding, any wait for a load
-        // waits for the copy too).
-        __builtin_amdgcn_s_waitcnt(0);
-        {
-            // (the last tile of the block loads itself again: no branch)
-            const int nt = more ? tile + (int)gridDim.x : tile;
-            const Half a = half_of(2 * nt), b = half_of(2 * nt + 1);
-            fill_x(a, b);
-            load_hold(a, b);
         }
         const int lo = tile_thread() & 15;   // (row addresses recomputed in each tile)
 #pragma unroll
