@@ -1169,6 +1169,7 @@ __global__ __launch_bounds__(kNetH64Threads, 2) void k_net_q8p(FlowArgs single, 
 // the launch's 64-patch row tiles, each of which may belong to another flow
 // of a batch.
 constexpr int kWideRows = 128;
+constexpr int kCPolNT = 2;   // cache-policy operand of a global load: non-temporal
 
 // Workgroup barrier for LDS data only: this wave's LDS accesses complete,
 // then s_barrier.  Unlike __syncthreads() it does not wait for the wave's
@@ -1264,7 +1265,9 @@ __global__ __launch_bounds__(kNetH64Threads, 1) void k_net_b16w(FlowArgs single,
         for (int i = 0; i < (2 * XP + 7) / 8; ++i) {
             const WidePiece w = wide_x_piece(i, wave, l, XP, a.nrows, b.nrows);
             const Half &hh = w.half ? b : a;
-            __builtin_amdgcn_global_load_lds((gvoid *)(hh.X + w.src), (lvoid *)(sX + w.dst), 16, 0, 0);
+            // (non-temporal: the rows are read once, and the weights that
+            // every tile reads stay in L2 instead)
+            __builtin_amdgcn_global_load_lds((gvoid *)(hh.X + w.src), (lvoid *)(sX + w.dst), 16, 0, kCPolNT);
         }
     };
     // a tile's FP32 state in the lane layout of the update (rows 16 q + li
