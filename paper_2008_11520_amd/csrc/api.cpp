@@ -322,17 +322,22 @@ struct dnnmg_batch {
     // what the last prepare uploaded
     bool prepared = false;
     int nflows = 0, K = 0, xfmt = 0, gather = 0;
+    int frame = 0;                              // the one-launch tiles hand over in their tile frames
     int totals[kKinds] = {0, 0, 0, 0};
     NetArgs net{};
     RhsTables tab{};
     int cap = 0;                                // grid of every batched launch in a graph
+    // grid of the one-tile-per-block launches (the one-launch tiles and the
+    // rhs after them) in the captured graph: at least their tiles, grown
+    // (and the graph captured again) when a membership has more
+    int tile_grid = 0;
     // captured launch sequence.  Every per-flow argument and the tile counts
     // are read from `dev` at run time, so a graph stays valid while K, the X
     // type, the gather and the shared weight set are unchanged, whichever
     // flows fill the table.
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int graph_K = -1, graph_xfmt = -1, graph_gather = -1;
+    int graph_K = -1, graph_xfmt = -1, graph_gather = -1, graph_frame = -1;
     NetArgs graph_net{};
     RhsTables graph_tab{};
     int captures = 0;
@@ -1546,6 +1551,10 @@ extern "C" int dnnmg_batch_prepare(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int n
             if (ctxs[j] == ctxs[i]) return fail(DNNMG_EINVAL, "ctxs[%d] repeats ctxs[%d]", i, j);
     }
     hipStream_t st = (hipStream_t)stream;
+    // the one-launch tiles average inside the tile and hand the rest over in
+    // the tile frame when every flow has one (as in dnnmg_step)
+    bool frame = fused_step(w->net);
+    for (int i = 0; i < nflows && frame; ++i) frame = ctxs[i]->frame() != nullptr;
     const int slot = b->slot;
     if (b->used[slot]) HIP_OR_FAIL(hipEventSynchronize(b->ev[slot]));
     BatchTable *t = b->host[slot];
@@ -1557,6 +1566,9 @@ extern "C" int dnnmg_batch_prepare(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int n
         FlowArgs f = flow_args(ctxs[i], v[i], p ? p[i] : nullptr);
         f.dbar_out = d_out ? d_out[i] : nullptr;
         f.bL = b_out ? b_out[i] : nullptr;
+        f.frame = frame ? ctxs[i]->frame() : nullptr;
+        f.keep_dpatch = !frame || (g.flags & DNNMG_F_PATCH_OUTPUTS) ? 1 : 0;
+        ctxs[i]->dpatch_kept = f.keep_dpatch != 0;
         t->flows[i] = f;
     }
     const size_t bytes = offsetof(BatchTable, flows) + sizeof(FlowArgs) * nflows;
@@ -1569,6 +1581,7 @@ extern "C" int dnnmg_batch_prepare(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int n
     b->K = ctxs[0]->cfg.K;
     b->xfmt = ctxs[0]->cfg.precision;
     b->gather = b_out != nullptr;
+    b->frame = frame ? 1 : 0;
     b->net = w->net;
     b->tab = ctxs[0]->tables();
     for (int k = 0; k < kKinds; ++k) b->totals[k] = t->prefix[k][nflows];
@@ -1584,13 +1597,16 @@ static int batch_enqueue(dnnmg_batch *b, bool graph, hipStream_t st)
     FlowArgs dummy{};
     int grid[kKinds];
     for (int k = 0; k < kKinds; ++k) grid[k] = graph ? b->cap : std::min(b->totals[k], b->cap);
+    // the one-launch tiles and the rhs of the tile frame take one tile per block
+    auto tiles = [&](int k) { return graph ? b->tile_grid : b->totals[k]; };
     if (fused_step(b->net)) {
-        HIP_OR_FAIL(launch_defect_net(dummy, b->dev, grid[kKindDefect], b->net, st));
+        HIP_OR_FAIL(launch_defect_net(dummy, b->dev, tiles(kKindDefect), b->net, st));
     } else {
         HIP_OR_FAIL(launch_defect(dummy, b->dev, grid[kKindDefect], b->K, b->xfmt, st));
         HIP_OR_FAIL(launch_net(dummy, b->dev, grid[kKindNet], b->net, st));
     }
-    HIP_OR_FAIL(launch_rhs(dummy, b->dev, grid[kKindRhs], b->K, b->tab, 1, st));
+    if (b->frame) HIP_OR_FAIL(launch_rhs(dummy, b->dev, tiles(kKindRhs), b->K, b->tab, 2, st));
+    else HIP_OR_FAIL(launch_rhs(dummy, b->dev, grid[kKindRhs], b->K, b->tab, 1, st));
     if (b->gather) HIP_OR_FAIL(launch_gather(dummy, b->dev, grid[kKindGather], st));
     return DNNMG_OK;
 }
@@ -1602,11 +1618,15 @@ extern "C" int dnnmg_batch_launch(dnnmg_batch *b, int use_graph, void *stream)
     hipStream_t st = (hipStream_t)stream;
     if (!use_graph) return batch_enqueue(b, false, st);
     if (!st) return fail(DNNMG_EINVAL, "graph launches need a non-default stream");
+    // (only the one-launch batches have one-tile-per-block launches)
+    const int tiles = fused_step(b->net) ? std::max(b->totals[kKindDefect], b->totals[kKindRhs]) : 0;
     const bool same = b->exec && b->graph_K == b->K && b->graph_xfmt == b->xfmt &&
-                      b->graph_gather == b->gather && same_net(b->graph_net, b->net) &&
+                      b->graph_gather == b->gather && b->graph_frame == b->frame && tiles <= b->tile_grid &&
+                      same_net(b->graph_net, b->net) &&
                       b->graph_tab.A == b->tab.A && b->graph_tab.M == b->tab.M;
     if (!same) {
         batch_drop_graph(b);
+        if (tiles > b->tile_grid) b->tile_grid = std::max(b->cap, 2 * tiles);
         HIP_OR_FAIL(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         int rc = batch_enqueue(b, true, st);
         hipGraph_t g = nullptr;
@@ -1619,6 +1639,7 @@ extern "C" int dnnmg_batch_launch(dnnmg_batch *b, int use_graph, void *stream)
         b->graph_K = b->K;
         b->graph_xfmt = b->xfmt;
         b->graph_gather = b->gather;
+        b->graph_frame = b->frame;
         b->graph_net = b->net;
         b->graph_tab = b->tab;
         b->captures++;

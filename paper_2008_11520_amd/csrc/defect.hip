@@ -1035,6 +1035,9 @@ __global__ __launch_bounds__(kThreads, (defect_form_waves<K, XT, PAPER>())) void
     defect_tile<K, XT, false, false, 0, CN, PAPER>(single, xcd_tile(blockIdx.x, gridDim.x));
 }
 
+// Batched: one tile per block as in a single flow (the grid covers the
+// table's tiles; blocks past them return), so the tiles take the single-flow
+// code, the tile frame included, with the flow's arguments from the table.
 template <bool BATCHED, int HM>
 __global__ __launch_bounds__(kThreads, 4) void k_defect_net(FlowArgs single, const BatchTable *__restrict__ bt, NetArgs net)
 {
@@ -1043,13 +1046,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_defect_net(FlowArgs single, con
         return;
     }
     const int total = bt->prefix[kKindDefect][bt->nflows];
-#pragma unroll 1
-    for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        int blk = xcd_tile(g, total);
-        const FlowArgs &f = *batch_flow(bt, kKindDefect, blk);
-        defect_tile<2, __bf16, true, true, HM>(f, blk, &net);
-        __syncthreads();   // LDS is reused by the next tile
-    }
+    if ((int)blockIdx.x >= total) return;
+    int blk = xcd_tile(blockIdx.x, total);
+    const FlowArgs &f = *batch_flow(bt, kKindDefect, blk);
+    defect_tile<2, __bf16, false, true, HM>(f, blk, &net);
 }
 
 bool fused_step(const NetArgs &net)

@@ -148,7 +148,7 @@ __device__ __forceinline__ void transport_corners(const FlowArgs &f, int tid, in
 template <int K, int FROM_PATCHES, bool OPAQUE_TID, bool CN = false>
 __device__ __forceinline__ void rhs_tile(const FlowArgs &f, int blk, RhsTables tab)
 {
-    static_assert(FROM_PATCHES != 2 || (K == 2 && !CN && !OPAQUE_TID), "tile frame: the one-launch K = 2 step");
+    static_assert(FROM_PATCHES != 2 || (K == 2 && !CN && !OPAQUE_TID), "tile frame: the one-launch K = 2 step, one tile per block");
     constexpr bool UB = FROM_PATCHES != 0 && !CN;
     const int tid = OPAQUE_TID ? tile_thread() : (int)threadIdx.x;
     constexpr int n = 1 << K;
@@ -626,6 +626,13 @@ __global__ __launch_bounds__(kThreads, (rhs_waves<K, BATCHED>())) void k_rhs(Flo
 {
     if constexpr (!BATCHED) {
         rhs_tile<K, FROM_PATCHES, false>(single, xcd_tile(blockIdx.x, gridDim.x), tab);
+    } else if constexpr (FROM_PATCHES == 2) {
+        // after the batched one-launch tiles: one tile per block, as they run
+        const int total = bt->prefix[kKindRhs][bt->nflows];
+        if ((int)blockIdx.x >= total) return;
+        int blk = xcd_tile(blockIdx.x, total);
+        const FlowArgs &f = *batch_flow(bt, kKindRhs, blk);
+        rhs_tile<K, 2, false>(f, blk, tab);
     } else {
         const int total = bt->prefix[kKindRhs][bt->nflows];
 #pragma unroll 1
@@ -682,10 +689,13 @@ hipError_t launch_rhs(const FlowArgs &f, const BatchTable *bt, int nblocks, int 
     const bool cn = f.theta != 1.0f;
     if (cn && (bt || !f.map64)) return hipErrorInvalidValue;
     dim3 g(nblocks), b(kThreads);
-    if (from_patches && f.frame) {
-        // after the one-launch K = 2 step, single flow
-        if (K != 2 || bt || cn) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_rhs<2, 2, false>), g, b, 0, s, f, bt, tab);
+    if (from_patches == 2 || (from_patches && f.frame)) {
+        // after the one-launch K = 2 step: a single flow (f.frame), or a batch
+        // whose flows all have their tile frame (from_patches = 2; one tile
+        // per block, nblocks at least the table's tiles)
+        if (K != 2 || cn || (!bt && !f.frame)) return hipErrorInvalidValue;
+        if (bt) hipLaunchKernelGGL((k_rhs<2, 2, true>), g, b, 0, s, f, bt, tab);
+        else hipLaunchKernelGGL((k_rhs<2, 2, false>), g, b, 0, s, f, bt, tab);
         return hipGetLastError();
     }
 #define DNNMG_RHS_CASE(KK)                                                                \
