@@ -223,12 +223,16 @@ int dnnmg_batch_prepare(dnnmg_batch *b, dnnmg_ctx *const *ctxs, int nflows,
 
 /* Launch the prepared step: one launch per kernel stage over all flows.  With
  * use_graph != 0 the launch sequence is captured into a hipGraph and replayed.
- * Its kernels run a fixed grid that strides over the tiles listed in the
- * device table, reading every per-flow argument and the tile counts at run
- * time, so one capture serves every membership: the graph is captured again
- * only when K, the precision, whether b_out is given, or the weight set
- * changes.  stream must then be a non-default stream.  Results equal dnnmg_step on each
- * context, bit for bit.  DNNMG_ESTATE if nothing was prepared. */
+ * Its kernels read every per-flow argument and the tile counts from the device
+ * table at run time: most stride over the listed tiles from a fixed grid; the
+ * one-launch tiles (K = 2, BF16, H = 64) and the rhs after them take one tile
+ * per block from a grid captured with room to spare (blocks past the tiles
+ * return).  So one capture serves many memberships: the graph is captured
+ * again when K, the precision, whether b_out is given, the weight set, or
+ * whether every flow has the one-launch step's tile frame changes, or when a
+ * membership has more one-launch tiles than the captured grid.  stream must
+ * then be a non-default stream.  Results equal dnnmg_step on each context, bit
+ * for bit.  DNNMG_ESTATE if nothing was prepared. */
 int dnnmg_batch_launch(dnnmg_batch *b, int use_graph, void *stream);
 
 /* Number of graph captures this batch object has made (-1 for NULL). */
