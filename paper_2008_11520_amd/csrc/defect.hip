@@ -190,8 +190,8 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
     // tile: their state and outputs are addressed from the tile's first patch
     // (a uniform 64-bit base) with 32-bit lane offsets, formed once and
     // stepped by 2 q patch rows (no 64-bit index products per access).
-    // (batched launches, FRAME false, keep the plain index form: at their
-    // register limit the lane offset held across the network spills)
+    // (FRAME false keeps the plain index form, which holds fewer registers
+    // across the network)
     const size_t p00 = (size_t)(ty * TP) * nx + tx * TP;
     const unsigned roff = ((li >> 3) ? (unsigned)nx : 0u) + (unsigned)(li & 7);
     auto patch = [&](int r) { return (size_t)(ty * TP + r / TP) * nx + tx * TP + r % TP; };
@@ -224,7 +224,7 @@ __device__ __forceinline__ void gru_fused(const FlowArgs &f, int tx, int ty, int
     }
     // zeros after [x | h]: the lanes of the last k-chunk that lie beyond it
     // read these (the zero is formed from tile_thread(), so that it is not
-    // materialised once outside the batched tile loop and held there)
+    // materialised once and held in a register)
     if (tid < 64) {
         const unsigned z = (unsigned)tile_thread() >> 16;
         *reinterpret_cast<uint4 *>(&sA[tid * LDA + nin + H]) = make_uint4(z, z, z, z);
@@ -972,7 +972,9 @@ __device__ __forceinline__ void defect_tile(const FlowArgs &f, int blk, const Ne
             // accumulators')
             float2 *const s_vc = reinterpret_cast<float2 *>(s_c);
             static_assert(NN * NN >= (kTileFine + 1) * (kTileFine + 1), "tile image in the node accumulators");
-            // (batched launches store the per-patch outputs: no frame code)
+            // (the one-launch tiles run one per block, single-flow and batched
+            // alike, so the frame code is always there; a flow without a tile
+            // frame stores the per-patch outputs)
             constexpr bool FRAME = !OPAQUE_TID;
             gru_fused<HM, FRAME>(f, tx, ty, tid, *net, sA, sA, sA + 64 * kFusedLDH,
                                  reinterpret_cast<__bf16 *>(s_acc), reinterpret_cast<float *>(s_wx), s_vc);
