@@ -358,6 +358,50 @@ def test_batched_step_equals_single_steps_bitwise():
         batch.close()
 
 
+def test_batched_tile_frames_and_mixed_flags_bitwise():
+    """The batched BF16 K=2 step with every flow's tile frame (flags 0: the
+    per-patch outputs stay on chip), and with a mix in which one flow has no
+    frame (DNNMG_F_UNFUSED: the whole batch stores and averages the per-patch
+    outputs), equals the flows' own steps bit for bit; the per-patch outputs
+    are refused exactly where the batched step kept them in the tiles."""
+    import torch
+    import paper_2008_11520_amd as pam
+    K, H, Hm = 2, 64, 64
+    w = synth.xavier_weights(K, H, Hm, 1234)
+    flows = [synth.channel_flow(13, 7, 3, 0.005, perturb_seed=5), synth.channel_flow(32, 8, 4, 0.005),
+             synth.channel_flow(5, 3, 9, 0.005)]
+    for flags in ([0, 0, 0], [0, pam.DNNMG_F_UNFUSED, pam.DNNMG_F_PATCH_OUTPUTS]):
+        single = [GpuRunner(make_gpu_flow(f, K, H, Hm, 1e-3, w, "bf16", flags=fl)) for f, fl in zip(flows, flags)]
+        model = make_gpu_flow(flows[0], K, H, Hm, 1e-3, w, "bf16")
+        batched = [make_gpu_flow(f, K, H, Hm, 1e-3, w, "bf16", share=model, flags=fl) for f, fl in zip(flows, flags)]
+        runners = [GpuRunner(b) for b in batched]
+        batch = pam.Batch(8)
+        for n in range(3):
+            fields = [f.fields(n) for f in flows]
+            ref = [r.step(v, p) for r, (v, p) in zip(single, fields)]
+            vs = [to_dev(v.reshape(-1)) for v, _ in fields]
+            ps = [to_dev(p) for _, p in fields]
+            batch.step(batched, vs, ps, [r.dbar for r in runners])
+            for r, b, rf in zip(runners, batched, ref):
+                b.restrict_rhs(r.bL)
+                b.get_state(r.h, None)
+                torch.cuda.synchronize()
+                assert np.array_equal(r.dbar.cpu().numpy().reshape(-1, 2), rf["Dbar"]), (flags, n)
+                assert np.array_equal(r.bL.cpu().numpy().reshape(-1, 2), rf["bL"]), (flags, n)
+                assert np.array_equal(r.h.cpu().numpy().reshape(b.s["P"], -1), rf["h"]), (flags, n)
+        frames = not any(fl & pam.DNNMG_F_UNFUSED for fl in flags)
+        for b, fl in zip(batched, flags):
+            d = torch.empty(b.s["P"] * b.s["nout"], dtype=torch.float32, device="cuda")
+            if frames and not fl & pam.DNNMG_F_PATCH_OUTPUTS:
+                with pytest.raises(pam.DnnmgError) as e:
+                    b.patch_output(d)
+                assert e.value.code == pam.DNNMG_ESTATE
+            else:
+                b.patch_output(d)
+        torch.cuda.synchronize()
+        batch.close()
+
+
 def test_channel_256x64_k2_full_size_100_steps():
     """The 256 x 64 channel (16384 patches), K=2, H=64, MLP 64-64-50, for
     the 100 steps of its configuration, FP32 and BF16 operands side by side
