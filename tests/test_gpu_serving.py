@@ -82,6 +82,50 @@ def test_batch_graph_replays_equal_eager_and_single(prec):
         S["batch"].close()
 
 
+def test_graph_grows_with_the_membership():
+    """The one-launch tiles run one per block from the graph's captured grid
+    (at least 8 blocks per CU, twice the tiles it was captured for): a
+    membership with more tiles than that captures the graph again, a smaller
+    one replays it (its extra blocks return); every tick equals the eager
+    launch, bit for bit."""
+    import torch
+    import paper_2008_11520_amd as pam
+    w = synth.xavier_weights(K, H, Hm, 1234)
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    big_nx = 8 * (2 * ncu + 8)                     # (2 ncu + 8) tiles of 8 x 8 patches per row, 4 rows: > 8 per CU
+    flows = [synth.channel_flow(13, 7, 3, 0.005, perturb_seed=5), synth.channel_flow(big_nx, 32, 4, 0.005)]
+    schedule = [[0], [0, 1], [0], [1, 0]]
+    st = torch.cuda.Stream()
+    sets = {}
+    for mode in ("eager", "graph"):
+        model = make_gpu_flow(flows[0], K, H, Hm, 1e-3, w, "bf16")
+        ctxs = [make_gpu_flow(f, K, H, Hm, 1e-3, w, "bf16", share=model) for f in flows]
+        sets[mode] = dict(model=model, ctxs=ctxs, runners=[GpuRunner(c) for c in ctxs], batch=pam.Batch(4))
+    nstep = [0] * len(flows)
+    for tick, members in enumerate(schedule):
+        fields = {i: flows[i].fields(nstep[i]) for i in members}
+        got = {}
+        for mode, S in sets.items():
+            with torch.cuda.stream(st):
+                vs = [to_dev(fields[i][0].reshape(-1)) for i in members]
+                ps = [to_dev(fields[i][1]) for i in members]
+                S["batch"].prepare([S["ctxs"][i] for i in members], vs, ps,
+                                   [S["runners"][i].dbar for i in members],
+                                   [S["runners"][i].bL for i in members], stream=st)
+                S["batch"].launch(graph=(mode == "graph"), stream=st)
+            st.synchronize()
+            got[mode] = {i: (S["runners"][i].dbar.cpu().numpy().copy(), S["runners"][i].bL.cpu().numpy().copy())
+                         for i in members}
+        for i in members:
+            assert np.array_equal(got["graph"][i][0], got["eager"][i][0]), (tick, i)
+            assert np.array_equal(got["graph"][i][1], got["eager"][i][1]), (tick, i)
+            nstep[i] += 1
+    assert sets["eager"]["batch"].captures == 0
+    assert sets["graph"]["batch"].captures == 2
+    for S in sets.values():
+        S["batch"].close()
+
+
 def test_graph_launch_rejects_default_stream():
     import torch
     import paper_2008_11520_amd as pam
