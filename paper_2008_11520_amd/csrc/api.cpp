@@ -1606,7 +1606,7 @@ static int batch_enqueue(dnnmg_batch *b, bool graph, hipStream_t st)
         HIP_OR_FAIL(launch_net(dummy, b->dev, grid[kKindNet], b->net, st));
     }
     if (b->frame) HIP_OR_FAIL(launch_rhs(dummy, b->dev, tiles(kKindRhs), b->K, b->tab, 2, st));
-    else HIP_OR_FAIL(launch_rhs(dummy, b->dev, grid[kKindRhs], b->K, b->tab, 1, st));
+    else HIP_OR_FAIL(launch_rhs(dummy, b->dev, b->K == 3 ? tiles(kKindRhs) : grid[kKindRhs], b->K, b->tab, 1, st));
     if (b->gather) HIP_OR_FAIL(launch_gather(dummy, b->dev, grid[kKindGather], st));
     return DNNMG_OK;
 }
@@ -1619,7 +1619,8 @@ extern "C" int dnnmg_batch_launch(dnnmg_batch *b, int use_graph, void *stream)
     if (!use_graph) return batch_enqueue(b, false, st);
     if (!st) return fail(DNNMG_EINVAL, "graph launches need a non-default stream");
     // (only the one-launch batches have one-tile-per-block launches)
-    const int tiles = fused_step(b->net) ? std::max(b->totals[kKindDefect], b->totals[kKindRhs]) : 0;
+    const int tiles = fused_step(b->net) ? std::max(b->totals[kKindDefect], b->totals[kKindRhs])
+                                         : (b->K == 3 ? b->totals[kKindRhs] : 0);
     const bool same = b->exec && b->graph_K == b->K && b->graph_xfmt == b->xfmt &&
                       b->graph_gather == b->gather && b->graph_frame == b->frame && tiles <= b->tile_grid &&
                       same_net(b->graph_net, b->net) &&

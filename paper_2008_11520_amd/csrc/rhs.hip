@@ -626,13 +626,14 @@ __global__ __launch_bounds__(kThreads, (rhs_waves<K, BATCHED>())) void k_rhs(Flo
 {
     if constexpr (!BATCHED) {
         rhs_tile<K, FROM_PATCHES, false>(single, xcd_tile(blockIdx.x, gridDim.x), tab);
-    } else if constexpr (FROM_PATCHES == 2) {
-        // after the batched one-launch tiles: one tile per block, as they run
+    } else if constexpr (FROM_PATCHES == 2 || K == 3) {
+        // after the batched one-launch tiles, and at K = 3: one tile per
+        // block, with the single-flow tile code
         const int total = bt->prefix[kKindRhs][bt->nflows];
         if ((int)blockIdx.x >= total) return;
         int blk = xcd_tile(blockIdx.x, total);
         const FlowArgs &f = *batch_flow(bt, kKindRhs, blk);
-        rhs_tile<K, 2, false>(f, blk, tab);
+        rhs_tile<K, FROM_PATCHES, false>(f, blk, tab);
     } else {
         const int total = bt->prefix[kKindRhs][bt->nflows];
 #pragma unroll 1
