@@ -475,6 +475,44 @@ def test_channel_1024x256_perturbed_steps_sampled_windows():
                 assert max(e["bL"], e["bL_max"]) < (1e-5 if prec == "fp32" else tol)
 
 
+def test_channel_1024x256_perturbed_200_steps_whole_field():
+    """Full size (262144 patches) for the 200 steps of the configuration,
+    whole fields against one FP64 oracle run: the BF16 step in the launch
+    configuration the benchmark times (one launch, no per-patch outputs
+    kept) and the FP32 step side by side.  Every step: the correction and
+    b_L, relative L2 and max-relative; every twentieth step and the last,
+    also the tile-edge and Dirichlet checks of the correction and the state
+    h.  The GRU state and the previous corrected velocity are carried over
+    all 200 steps, so this measures the drift at full length."""
+    flow = synth.channel_flow(1024, 256, 1, 0.005, perturb_seed=7)
+    K, H, Hm = 2, 64, 64
+    w = synth.xavier_weights(K, H, Hm, 1234)
+    runs = {prec: GpuRunner(make_gpu_flow(flow, K, H, Hm, 1e-3, w, prec, flags=0)) for prec in ("fp32", "bf16")}
+    tols = {"fp32": 1e-5, "bf16": 2e-2}
+    o = make_oracle_flow(flow, K, H, Hm, 1e-3, w)
+    worst = {prec: {} for prec in runs}
+    nsteps = 200
+    for n in range(nsteps):
+        v, p = flow.fields(n)
+        ref = o.step(v, p, want=("Dbar", "bL"))
+        full = n % 20 == 19 or n == nsteps - 1
+        for prec, g in runs.items():
+            got = g.step(v, p)
+            if full:
+                e = step_errors(got, ref, o.h, flow.nx, flow.ny, K, flow.dirichlet)
+            else:
+                e = dict(Dbar=rel_l2(got["Dbar"], ref["Dbar"]), Dbar_max=rel_max(got["Dbar"], ref["Dbar"]),
+                         bL=rel_l2(got["bL"], ref["bL"]), bL_max=rel_max(got["bL"], ref["bL"]),
+                         Dbar_dirichlet_nonzero=0)
+            merge_worst(worst[prec], e)
+            assert_step_errors(e, tols[prec], tols[prec])
+            if full:
+                print("channel1024x256 step %d %s Dbar %.2e (max %.2e, edge %.2e) h %.2e (max %.2e) bL %.2e (max %.2e)"
+                      % (n + 1, prec, e["Dbar"], e["Dbar_max"], e["Dbar_edge_max"], e["h"], e["h_max"],
+                         e["bL"], e["bL_max"]), flush=True)
+    print("channel1024x256 worst over %d steps" % nsteps, worst)
+
+
 def test_channel_1024x256_zero_weights_full_size():
     flow = synth.channel_flow(1024, 256, 1, 0.005, perturb_seed=7)
     K, H, Hm = 2, 64, 64
