@@ -10,7 +10,9 @@ FP8's max-relative bound is 0.1: there the largest node errors come from
 single E4M3 code flips (the matrix cores' FP8 products carry ~1e-4 relative
 error, enough to move a value of the hidden layer across a rounding
 boundary), and one flip moves a patch's output by one code step of the
-flipped value, up to 2^-3 of it, times its output weights."""
+flipped value, up to 2^-3 of it, times its output weights.  The BF16 step
+is also run for the configuration's 100 steps and checked on the whole
+field of two flows."""
 import numpy as np
 import pytest
 
@@ -76,6 +78,75 @@ def test_stretched_64_flows_k3_batched_sampled_windows(prec, tol):
         print("stretched", prec, fi, (i0, j0), "Dbar %.2e (max %.2e) bL %.2e (max %.2e)" % tuple(e))
         max_tol = 0.1 if prec == "fp8" else tol
         assert e[0] < tol and e[2] < tol and e[1] < max_tol and e[3] < max_tol
+    batch.close()
+    for c in ctxs:
+        c.close()
+    model.close()
+
+
+def test_stretched_64_flows_k3_bf16_100_steps_whole_field():
+    """The 100 steps of the stretched workload: all 64 flows stepped
+    together by replaying the captured batched launch, every flow with its
+    own field sequence (copied into the launch's input buffers, then the
+    step described and the captured graph replayed), BF16 operands as the
+    benchmark times them.  Two flows, the shortest and the longest domain
+    (the extremes of the stretch factor), are checked on
+    the whole field against an FP64 oracle run of their own: every step the
+    correction and b_L, relative L2 and max-relative; every twentieth step
+    also the tile-edge and Dirichlet checks and the GRU state.  The state and
+    the previous corrected velocity are carried over all 100 steps."""
+    import torch
+    import paper_2008_11520_amd as pam
+    from gpu_common import assert_step_errors, merge_worst, step_errors
+    wl = synth.workload("stretched64x128x128_k3")
+    K, H, Hm = wl.K, wl.H, wl.Hm
+    w = synth.xavier_weights(K, H, Hm, wl.weight_seed)
+    model = make_gpu_flow(wl.flows[0], K, H, Hm, wl.nu, w, "bf16", flags=0)
+    ctxs = [make_gpu_flow(f, K, H, Hm, wl.nu, w, "bf16", share=model, flags=0) for f in wl.flows]
+    s = ctxs[0].s
+    dbar = [torch.empty(2 * s["Fn"], dtype=torch.float32, device="cuda") for _ in ctxs]
+    bL = [torch.empty(2 * s["Nc"], dtype=torch.float64, device="cuda") for _ in ctxs]
+    hs = torch.empty(s["P"] * H, dtype=torch.float32, device="cuda")
+    vs = [torch.empty(2 * s["Nc"], dtype=torch.float32, device="cuda") for _ in ctxs]
+    ps = [torch.empty(s["Nc"], dtype=torch.float32, device="cuda") for _ in ctxs]
+    lengths = [float(np.max(f.cxy[..., 0])) for f in wl.flows]
+    checked = (int(np.argmin(lengths)), int(np.argmax(lengths)))
+    orc = {fi: make_oracle_flow(wl.flows[fi], K, H, Hm, wl.nu, w) for fi in checked}
+    batch = pam.Batch(64)
+    st = torch.cuda.Stream()
+    worst = {}
+    nsteps = 100
+    for n in range(nsteps):
+        fields = [f.fields(n) for f in wl.flows]
+        with torch.cuda.stream(st):
+            for (v, p), vd, pd in zip(fields, vs, ps):
+                vd.copy_(torch.from_numpy(np.ascontiguousarray(v.reshape(-1), dtype=np.float32)))
+                pd.copy_(torch.from_numpy(np.ascontiguousarray(p.reshape(-1), dtype=np.float32)))
+            batch.prepare(ctxs, vs, ps, dbar, bL, stream=st)
+            batch.launch(graph=True, stream=st)
+        st.synchronize()
+        full = n % 20 == 19 or n == nsteps - 1
+        for fi in checked:
+            flow = wl.flows[fi]
+            ref = orc[fi].step(*fields[fi], want=("Dbar", "bL"))
+            got = dict(Dbar=dbar[fi].cpu().numpy().reshape(-1, 2), bL=bL[fi].cpu().numpy().reshape(-1, 2))
+            if full:
+                with torch.cuda.stream(st):
+                    ctxs[fi].get_state(hs, None, stream=st)
+                st.synchronize()
+                got["h"] = hs.cpu().numpy().reshape(s["P"], H)
+                e = step_errors(got, ref, orc[fi].h, flow.nx, flow.ny, K, flow.dirichlet)
+                print("stretched flow %d step %d Dbar %.2e (max %.2e, edge %.2e) h %.2e (max %.2e) bL %.2e (max %.2e)"
+                      % (fi, n + 1, e["Dbar"], e["Dbar_max"], e["Dbar_edge_max"], e["h"], e["h_max"],
+                         e["bL"], e["bL_max"]), flush=True)
+            else:
+                e = dict(Dbar=rel_l2(got["Dbar"], ref["Dbar"]), Dbar_max=rel_max(got["Dbar"], ref["Dbar"]),
+                         bL=rel_l2(got["bL"], ref["bL"]), bL_max=rel_max(got["bL"], ref["bL"]),
+                         Dbar_dirichlet_nonzero=0)
+            merge_worst(worst, e)
+            assert_step_errors(e, 2e-2, 2e-2)
+    print("stretched worst over %d steps" % nsteps, worst)
+    assert batch.captures == 1
     batch.close()
     for c in ctxs:
         c.close()
