@@ -3,8 +3,10 @@ the oracle source (on the CPU) makes the pin suite fail.
 
 Each mutation is (original text, replacement, which occurrence).  The
 mutated copy is compiled into a temporary library and the pins are run
-against it in a subprocess through DNNMG_ORACLE_LIB.
+against it in a subprocess through DNNMG_ORACLE_LIB; the mutants run in
+parallel, once per module.
 """
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -92,20 +94,46 @@ def _mutate(text, old, new, occ):
     return text[:idx] + new + text[idx + len(old):]
 
 
+def _run_mutant(name, workdir):
+    """Compile the mutant and run the pin suites against it; returns the
+    pytest exit status and the tail of its output, or the exception."""
+    try:
+        old, new, occ = MUTATIONS[name]
+        os.makedirs(workdir, exist_ok=True)
+        msrc = os.path.join(workdir, "mutant.c")
+        with open(msrc, "w") as fh:
+            fh.write(_mutate(open(SRC).read(), old, new, occ))
+        mlib = os.path.join(workdir, "libmutant.so")
+        subprocess.check_call(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-o", mlib, msrc, "-lm"])
+        env = dict(os.environ, DNNMG_ORACLE_LIB=mlib, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                            os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_fp8_pins.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_paper_net_pins.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_umesh_pins.py")],
+                           env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+        return r.returncode, r.stdout[-2000:]
+    except Exception as e:  # reported by the mutant's own test
+        return e
+
+
+@pytest.fixture(scope="module")
+def mutant_results(tmp_path_factory):
+    """Every mutant compiled and run once, in parallel (each is an
+    independent compile and pytest process)."""
+    base = tmp_path_factory.mktemp("mutants")
+    workers = max(1, min(8, os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        futs = {name: ex.submit(_run_mutant, name, str(base / name)) for name in sorted(MUTATIONS)}
+        return {name: f.result() for name, f in futs.items()}
+
+
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
-def test_pins_catch_planted_mistake(name, tmp_path):
+def test_pins_catch_planted_mistake(name, mutant_results):
     old, new, occ = MUTATIONS[name]
-    src = open(SRC).read()
-    assert src.count(old) > occ, "mutation anchor missing: %s" % name
-    msrc = tmp_path / "mutant.c"
-    msrc.write_text(_mutate(src, old, new, occ))
-    mlib = tmp_path / "libmutant.so"
-    subprocess.check_call(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-o", str(mlib), str(msrc), "-lm"])
-    env = dict(os.environ, DNNMG_ORACLE_LIB=str(mlib))
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_fp8_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_paper_net_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_umesh_pins.py")],
-                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=300)
-    assert r.returncode != 0, "pins did not catch mutation %s:\n%s" % (name, r.stdout[-2000:])
+    assert open(SRC).read().count(old) > occ, "mutation anchor missing: %s" % name
+    res = mutant_results[name]
+    if isinstance(res, Exception):
+        raise res
+    code, out = res
+    assert code != 0, "pins did not catch mutation %s:\n%s" % (name, out)
